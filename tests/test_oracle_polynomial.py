@@ -1,0 +1,74 @@
+"""Pins of the oracle's residual polynomial and delta search (Sec. 4, Tables 1, 2, 4, Thm 4.1)."""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import load_golden
+from oracle import polynomial as P
+
+RECT1 = (-1.0, 2.8, 0.65)   # Tables 1 and 2
+RECT4 = (-1.0, 0.75 * 2.25**2 - 0.25, 0.9)  # Table 4 (see tests/golden/table4_params.txt)
+
+
+def test_table1_on_the_papers_grid():
+    for q, dstar, nu, nuq in load_golden("table1_rates.txt"):
+        q = int(q)
+        d, v, z0 = P.optimise_delta(1j, *RECT1, q, grid_step=1.0 / 16)
+        assert z0 == pytest.approx(0.9 + 1j)
+        assert abs(d - dstar) <= 0.0005 + 1e-12       # printed to 3 decimals
+        assert abs(v - nu) <= 0.003
+        assert abs(v ** (1.0 / q) - nuq) <= 0.003
+
+
+def test_table1_continuous_search_is_no_worse():
+    for q, dstar, nu, _ in load_golden("table1_rates.txt"):
+        d, v, _ = P.optimise_delta(1j, *RECT1, int(q))
+        assert v <= nu + 0.003
+        assert d > 0   # sign(delta) = sign(Im z)
+
+
+def test_table2_estimated_matvecs():
+    rows = load_golden("table2_matvecs.txt")
+    for row in rows:
+        q = int(row[0])
+        for z, paper in zip([1j, 0.5j, 0.25j, 0.125j], row[1:]):
+            _, nu, _ = P.optimise_delta(z, *RECT1, q)
+            est = P.estimated_matvecs(nu, q, 100.0)
+            # within one fixed-point step (q products) or 1 %
+            assert abs(est - paper) <= max(q, 0.01 * paper), (q, z, est, paper)
+
+
+def test_table4_parameters():
+    for _, imz, q, delta, mvs in load_golden("table4_params.txt"):
+        q = int(q)
+        z = 1j * (0.8 / 3 if abs(imz - 0.27) < 1e-9 else imz)
+        d, nu, _ = P.optimise_delta(z, *RECT4, q)
+        assert abs(d - delta) <= 0.02
+        assert abs(P.estimated_matvecs(nu, q, 5.0) - mvs) <= q
+
+
+@pytest.mark.parametrize("z,rect", [(1j, RECT1), (0.3j, RECT1), (0.5j, (-1.0, 29.4, 1.0)),
+                                    (-1.5j, (-1.0, 29.4, 1.0)), (-0.9j, (-0.5, 6.0, 0.4))])
+def test_thm41_closed_form_at_q1(z, rect):
+    pstar, value = P.richardson_closed_form(z, *rect)
+    d, nu, z0 = P.optimise_delta(z, *rect, 1, per_side=20000)
+    assert abs(nu - value) < 1e-4
+    # the q = 1 polynomial is R(lambda) = 1 - (lambda - z) p with p = i delta / p~(z)
+    p = 1j * d / P.ptilde(z, z0, d, 1)
+    assert abs(p - pstar) < 2e-3 * abs(pstar)
+
+
+def test_ptilde_tends_to_exponential():
+    lam = np.array([0.3 - 0.2j, -1.0, 2.0 - 0.5j])
+    z0, delta = 0.7 + 0.4j, 0.35
+    exact = np.exp(-1j * delta * (lam - z0))
+    assert np.abs(P.ptilde(lam, z0, delta, 30) - exact).max() < 1e-14
+    # q = 2 by hand
+    x = -1j * delta * (lam - z0)
+    assert np.allclose(P.ptilde(lam, z0, delta, 2), 1 + x + x * x / 2, atol=1e-15)
+
+
+def test_choose_q_prefers_smallest_rate_per_matvec():
+    q, d, nu = P.choose_q(1j, *RECT1, qmax=5, grid_step=1.0 / 16)
+    assert q == 2  # Table 1: nu^(1/q) = 0.733 is the smallest
