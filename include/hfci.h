@@ -1,0 +1,213 @@
+/*
+ * hfci.h -- C ABI of libhfci, an MI355X (gfx950) solver for the 3D Helmholtz
+ * equation by contour integration and polynomial preconditioning
+ * (Liu, Xi, Saad, de Hoop, arXiv 1811.12378).
+ *
+ * Problem (Sec. 1.1, eq. helmholtz-op / eq. lin-sys):
+ *     (-Laplace_h - omega^2 / c(x)^2) u = f
+ * on an nx*ny*nz grid of interior nodes with spacing h, homogeneous Dirichlet
+ * ghosts, 7-point second-order differences.
+ *
+ * Internally the operator is normalised as in Sec. 7.1 (eq. stiff-mass):
+ *     A = S - M - i D,   S = (s/h^2) * (7-point stencil),  s = c_min^2/omega^2,
+ *     M = diag(kappa), kappa_i = c_min^2 / c_i^2 <= 1,
+ *     D = diag(rho2 * (d_i/L)^2)  (absorbing layer of L cells, d_i = depth into it),
+ * so the physical system is A u = s f.  The damping carries a minus sign so that
+ * A = A1 - i A2 with A2 >= 0 as Lemma 3.1 requires.
+ *
+ * Memory / layout conventions (all entry points):
+ *   * Grid vectors are caller-owned DEVICE buffers, x fastest then y then z:
+ *     element (x, y, z) at index x + nx*(y + ny*z).  Complex values are
+ *     interleaved (re, im): complex128 (hfci_c128) or complex64 (two floats),
+ *     identical to torch.complex128 / torch.complex64 storage.
+ *   * Batches of vectors are contiguous: vector k starts at k*n elements,
+ *     n = nx*ny*nz.
+ *   * Handles are library-owned and released by the matching *_destroy.
+ *     Operators and contours may be destroyed before or after their context,
+ *     but no call other than *_destroy may use them once the context is gone.
+ *   * All device work is issued on the context's stream.  Every entry point
+ *     returns after its work has completed on that stream (it synchronises).
+ *   * On a negative status the outputs are unspecified and hfci_last_error()
+ *     holds a message (thread-local).  HFCI_W_NOCONV (> 0) still writes the
+ *     best iterate.
+ */
+#ifndef HFCI_H
+#define HFCI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } hfci_c128;
+
+typedef enum {
+  HFCI_OK = 0,
+  HFCI_W_NOCONV = 1,      /* iteration cap reached before the tolerance    */
+  HFCI_E_ARG = -1,        /* invalid argument (sizes, null pointers, enum) */
+  HFCI_E_HIP = -2,        /* HIP runtime error (message has the HIP text)  */
+  HFCI_E_OOM = -3,        /* device allocation failed                      */
+  HFCI_E_CONTOUR = -4,    /* contour violates Sec. 6.2's invariants, or the
+                             delta search found no contraction (nu >= 1)   */
+  HFCI_E_NUMERIC = -5,    /* NaN/Inf met in a reduction                    */
+  HFCI_E_STATE = -6       /* handle mismatch (e.g. contour of another op)  */
+} hfci_status;
+
+enum { HFCI_F32 = 32, HFCI_F64 = 64 };
+enum { HFCI_PRECOND_NONE = 0, HFCI_PRECOND_FCI = 1 };
+
+typedef struct hfci_ctx hfci_ctx;
+typedef struct hfci_op hfci_op;
+typedef struct hfci_contour hfci_contour;
+
+/* Options of the FCI preconditioner and the FGMRES wrapper (Sec. 2, Alg. 1). */
+typedef struct {
+  size_t size;          /* = sizeof(hfci_solve_opts); set by hfci_default_opts   */
+  int precision;        /* HFCI_F64 or HFCI_F32: arithmetic of the shifted-system
+                           sweeps and the quadrature combine.  The Arnoldi
+                           process, Givens least squares and true residuals are
+                           always FP64.                         default HFCI_F64 */
+  int restart;          /* m of FGMRES(m), 1..64                    default 30  */
+  int max_it;           /* cap on FGMRES iterations (all cycles)    default 500 */
+  double tol;           /* target ||f - A u|| / ||f|| (2-norm)      default 1e-6 */
+  int fp_steps;         /* > 0: exactly this many fixed-point steps per pole
+                           (lockstep mode); 0: adaptive stopping     default 0  */
+  double fp_reduce;     /* adaptive: stop a pole when ||r|| <= ||f|| / fp_reduce
+                           (Table 4 uses 5)                          default 5  */
+  int fp_max_steps;     /* adaptive: cap on steps per pole           default 200 */
+  int k_in;             /* Alg. 1 step 4: GMRES steps on the remainder (0 = off) */
+  int precond;          /* HFCI_PRECOND_FCI (default) or HFCI_PRECOND_NONE       */
+  int pole_batch;       /* poles advanced together per launch (x every RHS);
+                           0 = all J                                              */
+  int verbose;          /* 1: one line per FGMRES cycle on stderr               */
+} hfci_solve_opts;
+
+/* Counters of one call. */
+typedef struct {
+  size_t size;              /* = sizeof(hfci_stats), set by the caller          */
+  int its;                  /* FGMRES iterations (max over right-hand sides)     */
+  int restarts;             /* FGMRES cycles                                     */
+  long long matvecs;        /* stencil applications, all systems and precisions */
+  long long fp_steps;       /* fixed-point steps summed over (pole, RHS) systems */
+  double final_relres;      /* max over RHS of the true FP64 relative residual  */
+  double time_fci_ms;       /* device time in the preconditioner                 */
+  double time_arnoldi_ms;   /* device time in matvec/CGS2/update                 */
+  double time_total_ms;     /* wall time of the call                             */
+} hfci_stats;
+
+/* Per-kernel timing collected by hfci_ctx_profile (device time from HIP events
+ * recorded on the context's stream around each launch of the class). */
+typedef struct {
+  long long launches;   /* launches timed                                       */
+  double total_ms;      /* summed device time                                   */
+  double alg_bytes;     /* summed algorithmic HBM bytes (reads + writes each
+                           launch must move: every active system's vectors once,
+                           shared kappa and right-hand sides once per launch)   */
+} hfci_kernel_prof;
+
+enum {
+  HFCI_PROF_FP_STAGE = 0,  /* Horner stages 2..q of the fixed-point step         */
+  HFCI_PROF_FP_FIRST = 1,  /* first stage (also forms the shifted residual)      */
+  HFCI_PROF_APPLY = 2,     /* hfci_apply                                         */
+  HFCI_PROF_N = 3
+};
+
+/* Fill *o with the defaults listed above. */
+void hfci_default_opts(hfci_solve_opts* o);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* hfci_last_error(void);
+
+/* Library version string. */
+const char* hfci_version(void);
+
+/* ---- context -------------------------------------------------------------
+ * device: HIP device ordinal.  stream: a hipStream_t to issue work on, or NULL
+ * for the library's own stream.  The context owns the workspace memory. */
+hfci_status hfci_ctx_create(int device, void* stream, hfci_ctx** out);
+void hfci_ctx_destroy(hfci_ctx* ctx);
+
+/* Start (enable = 1, counters reset) or stop (0) kernel timing on the context. */
+hfci_status hfci_ctx_profile(hfci_ctx* ctx, int enable);
+/* Copy the counters into out[HFCI_PROF_N] (HOST array). */
+hfci_status hfci_ctx_profile_read(const hfci_ctx* ctx, hfci_kernel_prof* out);
+
+/* ---- operator (Sec. 1.1; Sec. 7.1 eq. stiff-mass) --------------------------
+ * c: DEVICE float64 array of nx*ny*nz wavespeeds (> 0), x fastest; read once,
+ *    not retained.  h: grid spacing.  omega: angular frequency (> 0).
+ * damp_cells (L >= 0) and damp_rho2 (>= 0): absorbing layer D_i = rho2 (d_i/L)^2.
+ * Errors: HFCI_E_ARG for non-positive sizes/h/omega or a non-positive c. */
+hfci_status hfci_op_create(hfci_ctx* ctx, int nx, int ny, int nz, double h,
+                           const double* c, double omega, int damp_cells,
+                           double damp_rho2, hfci_op** out);
+void hfci_op_destroy(hfci_op* op);
+
+/* Scalars of the normalised operator, written to host array out[7]:
+ *   s = c_min^2/omega^2, s/h^2, b1, b2, rho2, kappa_min, kappa_max,
+ * where [b1, b2] x [-rho2, 0] is the spectrum rectangle of Lemma 3.1 (Weyl
+ * bounds of S - M with the exact extreme Dirichlet Laplacian eigenvalues). */
+hfci_status hfci_op_info(const hfci_op* op, double* out7);
+
+/* y_k = (A - shift I) x_k for k < nvec (normalised A).  prec: HFCI_F64
+ * (complex128 x, y) or HFCI_F32 (complex64).  x and y are DEVICE buffers of
+ * nvec*n complex values and must not overlap. */
+hfci_status hfci_apply(const hfci_op* op, hfci_c128 shift, int prec, int nvec,
+                       const void* x, void* y);
+
+/* ---- contour and per-pole parameters (Sec. 6.1-6.2, Sec. 4.2) -------------
+ * J poles on the shifted-centre ellipse of eq. quad-points with radius
+ * r = (rho2/2 + eps)/sin(pi/J) (eq. quad-radius), weights
+ * sigma_j = (r cos theta_j + i t r sin theta_j)/J (eq. ellipse), and per pole
+ * z0_j = (b1+b2)/2 + i Im z_j and delta_j minimising eq. fix-pt-conv for the
+ * exponential-Taylor polynomial of degree q (eq. exp-taylor).
+ * z, sigma (HOST arrays of J, or NULL) override the computed poles/weights;
+ * delta (HOST array of J, or NULL) overrides the delta search.
+ * Errors: HFCI_E_ARG (J < 1, q < 1 or > 16, t <= 0, eps <= 0);
+ * HFCI_E_CONTOUR (a pole with Re z > 0 or Im z in (-eps-rho2, eps) when
+ * computed, or nu >= 1). */
+hfci_status hfci_contour_create(const hfci_op* op, int J, double t, double eps, int q,
+                                const hfci_c128* z, const hfci_c128* sigma,
+                                const double* delta, hfci_contour** out);
+void hfci_contour_destroy(hfci_contour* c);
+
+/* Copy the contour's parameters into HOST arrays of length J (any may be NULL):
+ * poles z, weights sigma, delta, Taylor centres z0, and the rate nu of each. */
+hfci_status hfci_contour_get(const hfci_contour* c, hfci_c128* z, hfci_c128* sigma,
+                             double* delta, hfci_c128* z0, double* nu);
+
+/* ---- shifted solves (Sec. 4.2, eq. fix-pt-exp) -----------------------------
+ * For every pole j < J and right-hand side k < nrhs, iterates eq. fix-pt-exp
+ * for (A - z_j I) y = f_k from y = 0, either exactly `steps` steps (steps > 0)
+ * or until ||f_k - (A - z_j) y|| <= ||f_k|| / reduce (at most max_steps).
+ * f: DEVICE, nrhs vectors.  y: DEVICE, J*nrhs vectors, system (j, k) at index
+ * j*nrhs + k.  prec: HFCI_F64 / HFCI_F32 for f and y.
+ * steps_taken: HOST int array of J*nrhs (or NULL). */
+hfci_status hfci_shifted_solve(const hfci_op* op, const hfci_contour* c, int prec,
+                               int nrhs, const void* f, void* y, int steps,
+                               double reduce, int max_steps, int* steps_taken);
+
+/* ---- FCI preconditioner (Algorithm 1) --------------------------------------
+ * out_k = v + d_k w_k with w_k = sum_j sigma_j/z_j y_jk (steps 1-2),
+ * d_k = (A w_k)^H f_k / (A w_k)^H (A w_k) (step 3), v from opts->k_in GMRES
+ * steps on A v = f_k - d_k A w_k (step 4).  f, out: DEVICE, nrhs vectors of
+ * complex128 (the FCI sweeps run in opts->precision).  stats may be NULL. */
+hfci_status hfci_fci_apply(const hfci_op* op, const hfci_contour* c,
+                           const hfci_solve_opts* opts, int nrhs,
+                           const hfci_c128* f, hfci_c128* out, hfci_stats* stats);
+
+/* ---- solve (Sec. 2: FCI inside flexible GMRES) ----------------------------
+ * Solves (-Laplace_h - omega^2/c^2) u_k = f_k for k < nrhs with FGMRES(m),
+ * classical Gram-Schmidt applied twice, Givens rotations and true-residual
+ * restarts, all FP64, preconditioned by FCI.  f: DEVICE complex128 (physical
+ * right-hand sides); u: DEVICE complex128, in: initial guess, out: solution.
+ * Returns HFCI_W_NOCONV if max_it was reached first (u holds the last iterate). */
+hfci_status hfci_solve(const hfci_op* op, const hfci_contour* c,
+                       const hfci_solve_opts* opts, int nrhs,
+                       const hfci_c128* f, hfci_c128* u, hfci_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HFCI_H */

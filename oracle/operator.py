@@ -140,3 +140,31 @@ def spectrum_rectangle(shape, kappa, damp, s_h2: float):
     b2 = smax - float(np.min(kappa))
     rho2 = float(np.max(damp)) if np.size(damp) else 0.0
     return b1, b2, rho2
+
+
+def apply_at(x: np.ndarray, kappa: np.ndarray, damp_cells: int, damp_rho2: float, s_h2: float,
+             shift: complex, points) -> np.ndarray:
+    """(A - shift I) x evaluated only at the given (z, y, x) nodes, term by term.
+
+    For sampled checks on grids too large for the full oracle: each value is
+    the 7-point formula written out with zero ghosts, and D from its definition.
+    """
+    nz, ny, nx = x.shape
+    out = np.empty(len(points), dtype=np.complex128)
+
+    def val(k, j, i):
+        if 0 <= k < nz and 0 <= j < ny and 0 <= i < nx:
+            return complex(x[k, j, i])
+        return 0.0
+
+    def depth(i, n):
+        return max(0, damp_cells - min(i, n - 1 - i))
+
+    for t, (k, j, i) in enumerate(points):
+        nb = (val(k - 1, j, i) + val(k + 1, j, i) + val(k, j - 1, i) + val(k, j + 1, i)
+              + val(k, j, i - 1) + val(k, j, i + 1))
+        d = max(depth(k, nz), depth(j, ny), depth(i, nx)) if damp_cells > 0 else 0
+        dmp = damp_rho2 * (d / damp_cells) ** 2 if damp_cells > 0 else 0.0
+        xc = val(k, j, i)
+        out[t] = s_h2 * (6.0 * xc - nb) - (float(kappa[k, j, i]) + 1j * dmp) * xc - shift * xc
+    return out

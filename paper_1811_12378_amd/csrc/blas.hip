@@ -1,0 +1,370 @@
+// BLAS-1 kernels and deterministic reductions for FGMRES and the FCI combine (gfx950).
+//
+// Reductions are two-pass and order-fixed: a grid of blas_blocks(n) blocks writes one
+// partial per block (wavefront shuffle tree, then 4 waves through LDS), and a second
+// kernel sums the partials of each component in a fixed order.  No floating-point
+// atomics, so FP64 results are bit-reproducible run to run.
+#include "kernels.h"
+
+namespace hfci {
+namespace {
+
+constexpr int NT = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Sum over the block of NV values per thread; results valid in thread 0 (v[k]).
+template <int NV>
+__device__ __forceinline__ void block_sum_n(double (&v)[NV], double* sh) {
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double s = wave_sum(v[k]);
+    if (lane == 0) sh[wid * NV + k] = s;
+  }
+  __syncthreads();
+  if (t == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = sh[k] + sh[NV + k] + sh[2 * NV + k] + sh[3 * NV + k];
+  }
+}
+
+__global__ __launch_bounds__(NT) void reduce_kernel(const double* __restrict__ partial, int nblk,
+                                                    double* __restrict__ out) {
+  __shared__ double sh[4];
+  const double* row = partial + (size_t)blockIdx.x * nblk;
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < nblk; i += NT) v[0] += row[i];
+  block_sum_n<1>(v, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = v[0];
+}
+
+template <int NVMAX>
+__global__ __launch_bounds__(NT) void multidot_kernel(const double2* __restrict__ V, int nv, size_t n,
+                                                      size_t vstride, const double2* __restrict__ w,
+                                                      double* __restrict__ partial) {
+  __shared__ double sh[4 * 2 * NVMAX];
+  double acc[2 * NVMAX];
+#pragma unroll
+  for (int k = 0; k < 2 * NVMAX; ++k) acc[k] = 0.0;
+  const size_t stride = (size_t)gridDim.x * NT;
+  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < n; p += stride) {
+    const double2 wv = w[p];
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i) {
+      if (i < nv) {
+        const double2 v = V[(size_t)i * vstride + p];
+        acc[2 * i] += v.x * wv.x + v.y * wv.y;      // Re conj(v) w
+        acc[2 * i + 1] += v.x * wv.y - v.y * wv.x;  // Im conj(v) w
+      }
+    }
+  }
+  block_sum_n<2 * NVMAX>(acc, sh);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 2 * nv; ++k) partial[(size_t)k * gridDim.x + blockIdx.x] = acc[k];
+  }
+}
+
+__global__ __launch_bounds__(NT) void multiaxpy_kernel(double2* __restrict__ w, const double2* __restrict__ V,
+                                                       int nv, size_t n, size_t vstride,
+                                                       const double* __restrict__ h,
+                                                       double sign) {
+  __shared__ double hs[2 * 64];
+  if (threadIdx.x < 2 * nv) hs[threadIdx.x] = sign * h[threadIdx.x];
+  __syncthreads();
+  const size_t stride = (size_t)gridDim.x * NT;
+  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < n; p += stride) {
+    double2 acc = w[p];
+    for (int i = 0; i < nv; ++i) {
+      const double2 v = V[(size_t)i * vstride + p];
+      const double hr = hs[2 * i], hi = hs[2 * i + 1];
+      acc.x += hr * v.x - hi * v.y;
+      acc.y += hr * v.y + hi * v.x;
+    }
+    w[p] = acc;
+  }
+}
+
+template <typename T2>
+__global__ __launch_bounds__(NT) void norm2_kernel(const T2* __restrict__ x, size_t n,
+                                                   double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double v[1] = {0.0};
+  const size_t stride = (size_t)gridDim.x * NT;
+  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < n; p += stride) {
+    const T2 a = x[p];
+    v[0] += (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+  }
+  block_sum_n<1>(v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
+}
+
+__global__ void scale_inv_kernel(double2* __restrict__ v, const double2* __restrict__ w, size_t n,
+                                 const double* __restrict__ nrm2) {
+  const double s = 1.0 / sqrt(nrm2[0]);
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    const double2 a = w[p];
+    v[p] = make_double2(a.x * s, a.y * s);
+  }
+}
+
+__global__ void fill_zero_kernel(uint4* __restrict__ p, size_t n16) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    p[i] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void fill_zero_tail(unsigned char* __restrict__ p, size_t nb) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) p[i] = 0;
+}
+
+__global__ void copy_scaled64_kernel(double2* __restrict__ d, const double2* __restrict__ s, size_t n,
+                                     double a) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    const double2 v = s[p];
+    d[p] = make_double2(a * v.x, a * v.y);
+  }
+}
+
+__global__ void cvt64to32_kernel(float2* __restrict__ d, const double2* __restrict__ s, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    const double2 v = s[p];
+    d[p] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+__global__ void cvt32to64_kernel(double2* __restrict__ d, const float2* __restrict__ s, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    const float2 v = s[p];
+    d[p] = make_double2((double)v.x, (double)v.y);
+  }
+}
+
+template <typename T2> struct ScalOf;
+template <> struct ScalOf<float2> { using t = float; };
+template <> struct ScalOf<double2> { using t = double; };
+
+template <typename T2>
+__global__ void combine_kernel(T2* __restrict__ w, const T2* __restrict__ y, const double* __restrict__ coef,
+                               int npole, int nrhs, size_t n, int accumulate) {
+  using T = typename ScalOf<T2>::t;
+  const int r = blockIdx.y;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    double ar = 0.0, ai = 0.0;
+    if (accumulate) {
+      const T2 o = w[(size_t)r * n + p];
+      ar = o.x;
+      ai = o.y;
+    }
+    for (int j = 0; j < npole; ++j) {
+      const T2 v = y[((size_t)j * nrhs + r) * n + p];
+      const double cr = coef[2 * j], ci = coef[2 * j + 1];
+      ar += cr * (double)v.x - ci * (double)v.y;
+      ai += cr * (double)v.y + ci * (double)v.x;
+    }
+    T2 o;
+    o.x = (T)ar;
+    o.y = (T)ai;
+    w[(size_t)r * n + p] = o;
+  }
+}
+
+template <typename T2>
+__global__ void scale_out_kernel(double2* __restrict__ out, const T2* __restrict__ w,
+                                 const double* __restrict__ d, size_t n) {
+  const int r = blockIdx.y;
+  const double dr = d[2 * r], di = d[2 * r + 1];
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    const T2 v = w[(size_t)r * n + p];
+    const double vr = v.x, vi = v.y;
+    out[(size_t)r * n + p] = make_double2(dr * vr - di * vi, dr * vi + di * vr);
+  }
+}
+
+// One block per system: sum its residual partials, then decide whether the
+// fixed-point iteration continues (stopping rule of Table 4, or a fixed count).
+__global__ __launch_bounds__(NT) void fp_check_kernel(const double* __restrict__ partial, int nblk,
+                                                      int sys0, int nrhs, const double* __restrict__ fnorm2,
+                                                      int fixed_steps, double inv_reduce2, int max_steps,
+                                                      int* __restrict__ active, int* __restrict__ steps,
+                                                      double* __restrict__ rnorm2) {
+  __shared__ double sh[4];
+  const int s = blockIdx.x;
+  if (active[s] == 0) return;  // converged earlier: its partial was not written
+  const double* row = partial + (size_t)s * nblk;
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < nblk; i += NT) v[0] += row[i];
+  block_sum_n<1>(v, sh);
+  if (threadIdx.x == 0) {
+    const double r2 = v[0];
+    rnorm2[s] = r2;
+    const int r = (sys0 + s) % nrhs;
+    int act;
+    if (fixed_steps > 0)
+      act = steps[s] < fixed_steps;
+    else
+      act = (r2 > fnorm2[r] * inv_reduce2) && (steps[s] < max_steps);
+    if (!(r2 == r2) || r2 > 1e300) act = 0;  // NaN / overflow: stop, reported by the host
+    active[s] = act;
+    if (act) steps[s] += 1;
+  }
+}
+
+__global__ void dfinish_kernel(const double* __restrict__ sums, int nrhs, double* __restrict__ d) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrhs) {
+    const double nr = sums[3 * r], ni = sums[3 * r + 1], den = sums[3 * r + 2];
+    d[2 * r] = den > 0 ? nr / den : 0.0;
+    d[2 * r + 1] = den > 0 ? ni / den : 0.0;
+  }
+}
+
+template <typename T2>
+__global__ void copy_active_kernel(T2* __restrict__ d, const T2* __restrict__ s, const int* __restrict__ active,
+                                   size_t n) {
+  const int sys = blockIdx.y;
+  if (!active[sys]) return;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride)
+    d[(size_t)sys * n + p] = s[(size_t)sys * n + p];
+}
+
+__global__ void set_int_kernel(int* p, int v, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+unsigned ew_blocks(size_t n) {
+  size_t b = (n + NT - 1) / NT;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+int blas_blocks(size_t n) {
+  size_t b = (n + 4 * NT - 1) / (4 * NT);
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+void launch_reduce(hipStream_t st, const double* partial, int nblk, int ncomp, double* out) {
+  if (ncomp <= 0) return;
+  hipLaunchKernelGGL(reduce_kernel, dim3(ncomp), dim3(NT), 0, st, partial, nblk, out);
+}
+
+void launch_multidot(hipStream_t st, const double2* V, int nv, size_t n, size_t vstride, const double2* w,
+                     double* partial) {
+  const int nb = blas_blocks(n);
+  if (nv > 32) {  // groups of 32 vectors; partial rows stay ordered by vector index
+    for (int i0 = 0; i0 < nv; i0 += 32)
+      launch_multidot(st, V + (size_t)i0 * vstride, nv - i0 < 32 ? nv - i0 : 32, n, vstride, w,
+                      partial + (size_t)2 * i0 * nb);
+    return;
+  }
+  if (nv <= 8)
+    hipLaunchKernelGGL(multidot_kernel<8>, dim3(nb), dim3(NT), 0, st, V, nv, n, vstride, w, partial);
+  else if (nv <= 16)
+    hipLaunchKernelGGL(multidot_kernel<16>, dim3(nb), dim3(NT), 0, st, V, nv, n, vstride, w, partial);
+  else
+    hipLaunchKernelGGL(multidot_kernel<32>, dim3(nb), dim3(NT), 0, st, V, nv, n, vstride, w, partial);
+}
+
+void launch_multiaxpy(hipStream_t st, double2* w, const double2* V, int nv, size_t n, size_t vstride,
+                      const double* h, double sign) {
+  if (nv > 32) {
+    for (int i0 = 0; i0 < nv; i0 += 32)
+      launch_multiaxpy(st, w, V + (size_t)i0 * vstride, nv - i0 < 32 ? nv - i0 : 32, n, vstride, h + 2 * i0, sign);
+    return;
+  }
+  hipLaunchKernelGGL(multiaxpy_kernel, dim3(blas_blocks(n)), dim3(NT), 0, st, w, V, nv, n, vstride, h, sign);
+}
+
+void launch_norm2_partial(hipStream_t st, const void* x, bool f32, size_t n, double* partial) {
+  if (f32)
+    hipLaunchKernelGGL(norm2_kernel<float2>, dim3(blas_blocks(n)), dim3(NT), 0, st, (const float2*)x, n, partial);
+  else
+    hipLaunchKernelGGL(norm2_kernel<double2>, dim3(blas_blocks(n)), dim3(NT), 0, st, (const double2*)x, n, partial);
+}
+
+void launch_scale_inv(hipStream_t st, double2* v, const double2* w, size_t n, const double* nrm2) {
+  hipLaunchKernelGGL(scale_inv_kernel, dim3(ew_blocks(n)), dim3(NT), 0, st, v, w, n, nrm2);
+}
+
+void launch_fill_zero(hipStream_t st, void* p, size_t bytes) {
+  const size_t n16 = bytes / 16;
+  if (n16) hipLaunchKernelGGL(fill_zero_kernel, dim3(ew_blocks(n16)), dim3(NT), 0, st, (uint4*)p, n16);
+  const size_t tail = bytes - n16 * 16;
+  if (tail)
+    hipLaunchKernelGGL(fill_zero_tail, dim3(1), dim3(64), 0, st, (unsigned char*)p + n16 * 16, tail);
+}
+
+void launch_copy_scaled64(hipStream_t st, double2* dst, const double2* src, size_t n, double s) {
+  hipLaunchKernelGGL(copy_scaled64_kernel, dim3(ew_blocks(n)), dim3(NT), 0, st, dst, src, n, s);
+}
+
+void launch_convert_64_to_32(hipStream_t st, float2* dst, const double2* src, size_t n) {
+  hipLaunchKernelGGL(cvt64to32_kernel, dim3(ew_blocks(n)), dim3(NT), 0, st, dst, src, n);
+}
+
+void launch_convert_32_to_64(hipStream_t st, double2* dst, const float2* src, size_t n) {
+  hipLaunchKernelGGL(cvt32to64_kernel, dim3(ew_blocks(n)), dim3(NT), 0, st, dst, src, n);
+}
+
+template <typename T2>
+void launch_combine(hipStream_t st, T2* w, const T2* y, const double* coef, int npole, int nrhs, size_t n,
+                    bool accumulate) {
+  const unsigned bx = ew_blocks(n) / (nrhs > 8 ? 8 : (unsigned)nrhs) + 1;
+  hipLaunchKernelGGL(combine_kernel<T2>, dim3(bx, nrhs), dim3(NT), 0, st, w, y, coef, npole, nrhs, n,
+                     accumulate ? 1 : 0);
+}
+
+template <typename T2>
+void launch_scale_out(hipStream_t st, double2* out, const T2* w, const double* d, int nrhs, size_t n) {
+  const unsigned bx = ew_blocks(n) / (nrhs > 8 ? 8 : (unsigned)nrhs) + 1;
+  hipLaunchKernelGGL(scale_out_kernel<T2>, dim3(bx, nrhs), dim3(NT), 0, st, out, w, d, n);
+}
+
+void launch_fp_check(hipStream_t st, const double* partial, int nblk, int nsys, int sys0, int nrhs,
+                     const double* fnorm2, int fixed_steps, double reduce, int max_steps, int* active,
+                     int* steps, double* rnorm2) {
+  hipLaunchKernelGGL(fp_check_kernel, dim3(nsys), dim3(NT), 0, st, partial, nblk, sys0, nrhs, fnorm2,
+                     fixed_steps, 1.0 / (reduce * reduce), max_steps, active, steps, rnorm2);
+}
+
+void launch_dfinish(hipStream_t st, const double* sums, int nrhs, double* d) {
+  hipLaunchKernelGGL(dfinish_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, sums, nrhs, d);
+}
+
+void launch_set_int(hipStream_t st, int* p, int v, int count) {
+  if (count > 0) hipLaunchKernelGGL(set_int_kernel, dim3((count + 255) / 256), dim3(256), 0, st, p, v, count);
+}
+
+void launch_copy_active_f(hipStream_t st, float2* d, const float2* s, const int* a, int nsys, size_t n) {
+  hipLaunchKernelGGL(copy_active_kernel<float2>, dim3(ew_blocks(n) / 4 + 1, nsys), dim3(NT), 0, st, d, s, a, n);
+}
+
+void launch_copy_active_d(hipStream_t st, double2* d, const double2* s, const int* a, int nsys, size_t n) {
+  hipLaunchKernelGGL(copy_active_kernel<double2>, dim3(ew_blocks(n) / 4 + 1, nsys), dim3(NT), 0, st, d, s, a, n);
+}
+
+template void launch_combine<float2>(hipStream_t, float2*, const float2*, const double*, int, int, size_t, bool);
+template void launch_combine<double2>(hipStream_t, double2*, const double2*, const double*, int, int, size_t,
+                                      bool);
+template void launch_scale_out<float2>(hipStream_t, double2*, const float2*, const double*, int, size_t);
+template void launch_scale_out<double2>(hipStream_t, double2*, const double2*, const double*, int, size_t);
+
+}  // namespace hfci

@@ -1,0 +1,521 @@
+// extern "C" entry points of libhfci: argument checks, handle management, error text.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace hfci {
+
+namespace {
+thread_local std::string g_err;
+constexpr size_t kPinnedInts = 65536;
+constexpr size_t kPinnedDbls = 65536;
+}  // namespace
+
+void throw_hip(hipError_t e, const char* what, const char* file, int line) {
+  const char* base = std::strrchr(file, '/');
+  std::string msg = std::string(hipGetErrorString(e)) + " in " + what + " (" + (base ? base + 1 : file) + ":" +
+                    std::to_string(line) + ")";
+  throw Error(e == hipErrorOutOfMemory ? HFCI_E_OOM : HFCI_E_HIP, msg);
+}
+
+void* Workspace::get(const std::string& tag, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  Buf& b = bufs_[tag];
+  if (b.bytes >= bytes) return b.p;
+  if (b.p) {
+    HFCI_HIP(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(HFCI_E_OOM, "device allocation of " + std::to_string(bytes) + " bytes for '" + tag + "' failed");
+  }
+  b.p = p;
+  b.bytes = bytes;
+  return p;
+}
+
+void Workspace::release_all() {
+  for (auto& kv : bufs_)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  bufs_.clear();
+}
+
+hipEvent_t Profiler::take() {
+  if (!free_.empty()) {
+    hipEvent_t e = free_.back();
+    free_.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HFCI_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void Profiler::begin(hipStream_t s) {
+  open_ = take();
+  HFCI_HIP(hipEventRecord(open_, s));
+}
+
+void Profiler::end(hipStream_t s, int cls, double bytes) {
+  hipEvent_t b = take();
+  HFCI_HIP(hipEventRecord(b, s));
+  pending_.push_back(Pending{cls, open_, b, bytes});
+  open_ = nullptr;
+}
+
+void Profiler::harvest() {
+  for (const Pending& p : pending_) {
+    float ms = 0.f;
+    HFCI_HIP(hipEventSynchronize(p.b));
+    HFCI_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    acc[p.cls].launches += 1;
+    acc[p.cls].ms += ms;
+    acc[p.cls].bytes += p.bytes;
+    free_.push_back(p.a);
+    free_.push_back(p.b);
+  }
+  pending_.clear();
+}
+
+void Profiler::reset() {
+  for (auto& a : acc) a = Acc{};
+}
+
+void Profiler::release() {
+  for (const Pending& p : pending_) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  pending_.clear();
+  for (hipEvent_t e : free_) (void)hipEventDestroy(e);
+  free_.clear();
+}
+
+static hfci_status fail(const Error& e) {
+  g_err = e.what();
+  return e.st;
+}
+
+#define HFCI_API_BEGIN try {
+#define HFCI_API_END                                  \
+  }                                                   \
+  catch (const Error& e) {                            \
+    return fail(e);                                   \
+  }                                                   \
+  catch (const std::exception& e) {                   \
+    g_err = e.what();                                 \
+    return HFCI_E_HIP;                                \
+  }
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    HFCI_HIP(hipGetDevice(&prev));
+    if (prev != dev) HFCI_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+static void check_opts(const hfci_solve_opts* o) {
+  HFCI_REQUIRE(o != nullptr, "opts is NULL");
+  HFCI_REQUIRE(o->size == sizeof(hfci_solve_opts), "opts->size mismatch (call hfci_default_opts)");
+  HFCI_REQUIRE(o->precision == HFCI_F32 || o->precision == HFCI_F64, "precision must be 32 or 64");
+  HFCI_REQUIRE(o->restart >= 1 && o->restart <= 64, "restart must be in [1, 64]");
+  HFCI_REQUIRE(o->max_it >= 1, "max_it must be >= 1");
+  HFCI_REQUIRE(o->tol >= 0.0, "tol must be >= 0");
+  HFCI_REQUIRE(o->fp_steps >= 0, "fp_steps must be >= 0");
+  HFCI_REQUIRE(o->fp_steps > 0 || (o->fp_reduce > 1.0 && o->fp_max_steps >= 1),
+               "adaptive stopping needs fp_reduce > 1 and fp_max_steps >= 1");
+  HFCI_REQUIRE(o->k_in == 0, "k_in > 0 (Alg. 1 step 4) is not supported by this build");
+  HFCI_REQUIRE(o->precond == HFCI_PRECOND_FCI || o->precond == HFCI_PRECOND_NONE, "unknown precond");
+  HFCI_REQUIRE(o->pole_batch >= 0, "pole_batch must be >= 0");
+}
+
+}  // namespace hfci
+
+using namespace hfci;
+
+struct hfci_ctx : public hfci::Ctx {};
+struct hfci_op : public hfci::Op {};
+struct hfci_contour : public hfci::Contour {};
+
+extern "C" {
+
+void hfci_default_opts(hfci_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->size = sizeof(hfci_solve_opts);
+  o->precision = HFCI_F64;
+  o->restart = 30;
+  o->max_it = 500;
+  o->tol = 1e-6;
+  o->fp_steps = 0;
+  o->fp_reduce = 5.0;
+  o->fp_max_steps = 200;
+  o->k_in = 0;
+  o->precond = HFCI_PRECOND_FCI;
+  o->pole_batch = 0;
+  o->verbose = 0;
+}
+
+const char* hfci_last_error(void) { return g_err.c_str(); }
+
+const char* hfci_version(void) { return "hfci 0.1 (gfx950)"; }
+
+hfci_status hfci_ctx_create(int device, void* stream, hfci_ctx** out) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(out != nullptr, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  HFCI_HIP(hipGetDeviceCount(&ndev));
+  HFCI_REQUIRE(device >= 0 && device < ndev, "device ordinal out of range");
+  DeviceGuard dg(device);
+  hfci_ctx* c = new hfci_ctx();
+  c->device = device;
+  try {
+    if (stream) {
+      c->stream = (hipStream_t)stream;
+    } else {
+      HFCI_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+    HFCI_HIP(hipHostMalloc((void**)&c->pinned_int, kPinnedInts * sizeof(int), hipHostMallocDefault));
+    HFCI_HIP(hipHostMalloc((void**)&c->pinned_dbl, kPinnedDbls * sizeof(double), hipHostMallocDefault));
+  } catch (...) {
+    if (c->pinned_int) (void)hipHostFree(c->pinned_int);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    throw;
+  }
+  *out = c;
+  return HFCI_OK;
+  HFCI_API_END
+}
+
+void hfci_ctx_destroy(hfci_ctx* c) {
+  if (!c) return;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  c->prof.release();
+  c->ws.release_all();
+  if (c->pinned_int) (void)hipHostFree(c->pinned_int);
+  if (c->pinned_dbl) (void)hipHostFree(c->pinned_dbl);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  if (prev >= 0) (void)hipSetDevice(prev);
+  delete c;
+}
+
+hfci_status hfci_ctx_profile(hfci_ctx* ctx, int enable) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(ctx, "NULL context");
+  DeviceGuard dg(ctx->device);
+  HFCI_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->prof.harvest();
+  if (enable) ctx->prof.reset();
+  ctx->prof.on = enable != 0;
+  return HFCI_OK;
+  HFCI_API_END
+}
+
+hfci_status hfci_ctx_profile_read(const hfci_ctx* ctx, hfci_kernel_prof* out) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(ctx && out, "NULL argument");
+  for (int k = 0; k < HFCI_PROF_N; ++k)
+    out[k] = hfci_kernel_prof{ctx->prof.acc[k].launches, ctx->prof.acc[k].ms, ctx->prof.acc[k].bytes};
+  return HFCI_OK;
+  HFCI_API_END
+}
+
+hfci_status hfci_op_create(hfci_ctx* ctx, int nx, int ny, int nz, double h, const double* c, double omega,
+                           int damp_cells, double damp_rho2, hfci_op** out) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(ctx && out && c, "NULL argument");
+  *out = nullptr;
+  HFCI_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1, "grid sizes must be >= 1");
+  HFCI_REQUIRE((double)nx * ny * nz < 4.0e9, "grid too large");
+  HFCI_REQUIRE(h > 0 && std::isfinite(h) && omega > 0 && std::isfinite(omega), "h and omega must be > 0");
+  HFCI_REQUIRE(damp_cells >= 0 && damp_rho2 >= 0 && std::isfinite(damp_rho2), "invalid damping layer");
+  DeviceGuard dg(ctx->device);
+  const size_t n = (size_t)nx * ny * nz;
+  std::vector<double> hc(n);
+  HFCI_HIP(hipMemcpyAsync(hc.data(), c, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HFCI_HIP(hipStreamSynchronize(ctx->stream));
+  double cmin = hc[0], cmax = hc[0];
+  for (double v : hc) {
+    HFCI_REQUIRE(v > 0 && std::isfinite(v), "wavespeed must be positive and finite");
+    cmin = std::min(cmin, v);
+    cmax = std::max(cmax, v);
+  }
+  hfci_op* op = new hfci_op();
+  try {
+    op->ctx = ctx;
+    op->device = ctx->device;
+    op->n = n;
+    op->h = h;
+    op->omega = omega;
+    op->s = cmin * cmin / (omega * omega);
+    op->s_h2 = op->s / (h * h);
+    op->damp_cells = damp_cells;
+    op->damp_rho2 = damp_rho2;
+    op->g.nx = nx;
+    op->g.ny = ny;
+    op->g.nz = nz;
+    op->g.damp_cells = damp_cells;
+    op->g.damp_scale = damp_cells > 0 ? damp_rho2 / ((double)damp_cells * damp_cells) : 0.0;
+    op->g.s_h2 = op->s_h2;
+    std::vector<float> k32(n);
+    double kmin = 1e300, kmax = 0;
+    for (size_t i = 0; i < n; ++i) {
+      const double r = cmin / hc[i];
+      hc[i] = r * r;  // kappa = c_min^2 / c^2
+      k32[i] = (float)hc[i];
+      kmin = std::min(kmin, hc[i]);
+      kmax = std::max(kmax, hc[i]);
+    }
+    op->kmin = kmin;
+    op->kmax = kmax;
+    op_rectangle(*op);
+    HFCI_HIP(hipMalloc(&op->kappa64, n * sizeof(double)));
+    HFCI_HIP(hipMalloc(&op->kappa32, n * sizeof(float)));
+    HFCI_HIP(hipMemcpy(op->kappa64, hc.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    HFCI_HIP(hipMemcpy(op->kappa32, k32.data(), n * sizeof(float), hipMemcpyHostToDevice));
+  } catch (...) {
+    if (op->kappa64) (void)hipFree(op->kappa64);
+    if (op->kappa32) (void)hipFree(op->kappa32);
+    delete op;
+    throw;
+  }
+  *out = op;
+  return HFCI_OK;
+  HFCI_API_END
+}
+
+void hfci_op_destroy(hfci_op* op) {
+  if (!op) return;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(op->device);
+  // hipFree waits for outstanding work on the device; the context is not touched, so an
+  // operator may be released after its context.
+  if (op->kappa64) (void)hipFree(op->kappa64);
+  if (op->kappa32) (void)hipFree(op->kappa32);
+  if (prev >= 0) (void)hipSetDevice(prev);
+  delete op;
+}
+
+hfci_status hfci_op_info(const hfci_op* op, double* o) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(op && o, "NULL argument");
+  o[0] = op->s;
+  o[1] = op->s_h2;
+  o[2] = op->b1;
+  o[3] = op->b2;
+  o[4] = op->rho2;
+  o[5] = op->kmin;
+  o[6] = op->kmax;
+  return HFCI_OK;
+  HFCI_API_END
+}
+
+hfci_status hfci_apply(const hfci_op* op, hfci_c128 shift, int prec, int nvec, const void* x, void* y) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(op && x && y, "NULL argument");
+  HFCI_REQUIRE(prec == HFCI_F32 || prec == HFCI_F64, "prec must be 32 or 64");
+  HFCI_REQUIRE(nvec >= 1 && nvec <= 4096, "nvec must be in [1, 4096]");
+  const size_t bytes = (size_t)nvec * op->n * (prec == HFCI_F64 ? 16 : 8);
+  const char* xa = (const char*)x;
+  const char* ya = (const char*)y;
+  HFCI_REQUIRE(xa + bytes <= ya || ya + bytes <= xa, "x and y overlap");
+  DeviceGuard dg(op->ctx->device);
+  hipStream_t s = op->ctx->stream;
+  Profiler& pr = op->ctx->prof;
+  const double e = prec == HFCI_F64 ? 16.0 : 8.0;
+  if (pr.on) pr.begin(s);
+  if (prec == HFCI_F64)
+    Launch<double2>::apply(s, op->g, op->kappa64, shift.re, shift.im, nvec, (const double2*)x, (double2*)y);
+  else
+    Launch<float2>::apply(s, op->g, op->kappa32, shift.re, shift.im, nvec, (const float2*)x, (float2*)y);
+  if (pr.on) pr.end(s, HFCI_PROF_APPLY, (double)op->n * (2.0 * e * nvec + e / 2.0));
+  HFCI_HIP(hipGetLastError());
+  HFCI_HIP(hipStreamSynchronize(s));
+  if (pr.on) pr.harvest();
+  return HFCI_OK;
+  HFCI_API_END
+}
+
+hfci_status hfci_contour_create(const hfci_op* op, int J, double t, double eps, int q, const hfci_c128* z,
+                                const hfci_c128* sigma, const double* delta, hfci_contour** out) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(op && out, "NULL argument");
+  *out = nullptr;
+  HFCI_REQUIRE(J >= 1 && J <= 256, "J must be in [1, 256]");
+  HFCI_REQUIRE(q >= 1 && q <= 16, "q must be in [1, 16]");
+  HFCI_REQUIRE((z == nullptr) == (sigma == nullptr), "give both poles and weights or neither");
+  if (!z) HFCI_REQUIRE(t > 0 && eps > 0 && std::isfinite(t) && std::isfinite(eps), "t and eps must be > 0");
+  DeviceGuard dg(op->ctx->device);
+  hfci_contour* c = new hfci_contour();
+  try {
+    c->op = op;
+    c->device = op->device;
+    c->J = J;
+    c->q = q;
+    c->t = t;
+    c->eps = eps;
+    if (z) {
+      c->z.resize(J);
+      c->sigma.resize(J);
+      for (int j = 0; j < J; ++j) {
+        c->z[j] = cd(z[j].re, z[j].im);
+        c->sigma[j] = cd(sigma[j].re, sigma[j].im);
+        if (c->z[j] == cd(0, 0)) throw Error(HFCI_E_CONTOUR, "a pole at the origin");
+      }
+    } else {
+      contour_poles(J, t, eps, op->rho2, c->z, c->sigma);
+      for (int j = 0; j < J; ++j) {
+        const double re = c->z[j].real(), im = c->z[j].imag();
+        if (re > 1e-12 || (im < eps - 1e-12 && im > -eps - op->rho2 + 1e-12))
+          throw Error(HFCI_E_CONTOUR, "pole violates Re z <= 0 and Im z outside (-eps-rho2, eps)");
+      }
+    }
+    c->delta.resize(J);
+    c->nu.resize(J);
+    c->z0.resize(J);
+    c->pz.resize(J);
+    c->coef.resize((size_t)J * q);
+    c->pdev.resize(J);
+    const std::vector<cd> bd = rectangle_boundary(op->b1, op->b2, op->rho2, 2000);
+    for (int j = 0; j < J; ++j) {
+      const cd zj = c->z[j];
+      if (zj.imag() <= 0.0 && zj.imag() >= -op->rho2)
+        throw Error(HFCI_E_CONTOUR, "pole inside the imaginary band [-rho2, 0] of the spectrum");
+      if (delta) {
+        c->delta[j] = delta[j];
+        c->z0[j] = cd(0.5 * (op->b1 + op->b2), zj.imag());
+        c->nu[j] = rate_on_boundary(delta[j], zj, c->z0[j], q, bd);
+      } else {
+        optimise_delta(zj, op->b1, op->b2, op->rho2, q, c->delta[j], c->nu[j], c->z0[j]);
+      }
+      if (!(c->nu[j] < 1.0)) throw Error(HFCI_E_CONTOUR, "no contraction for a pole (nu >= 1)");
+      stage_coefficients(zj, c->z0[j], c->delta[j], q, &c->coef[(size_t)j * q], c->pz[j]);
+      const cd zz = zj - c->z0[j];
+      c->pdev[j] = PoleDev{c->z0[j].real(), c->z0[j].imag(), zz.real(), zz.imag()};
+    }
+    HFCI_HIP(hipMalloc(&c->d_coef, c->coef.size() * sizeof(StageCoef)));
+    HFCI_HIP(hipMalloc(&c->d_poles, c->pdev.size() * sizeof(PoleDev)));
+    HFCI_HIP(hipMemcpy(c->d_coef, c->coef.data(), c->coef.size() * sizeof(StageCoef), hipMemcpyHostToDevice));
+    HFCI_HIP(hipMemcpy(c->d_poles, c->pdev.data(), c->pdev.size() * sizeof(PoleDev), hipMemcpyHostToDevice));
+  } catch (...) {
+    if (c->d_coef) (void)hipFree(c->d_coef);
+    if (c->d_poles) (void)hipFree(c->d_poles);
+    delete c;
+    throw;
+  }
+  *out = c;
+  return HFCI_OK;
+  HFCI_API_END
+}
+
+void hfci_contour_destroy(hfci_contour* c) {
+  if (!c) return;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(c->device);
+  if (c->d_coef) (void)hipFree(c->d_coef);
+  if (c->d_poles) (void)hipFree(c->d_poles);
+  if (prev >= 0) (void)hipSetDevice(prev);
+  delete c;
+}
+
+hfci_status hfci_contour_get(const hfci_contour* c, hfci_c128* z, hfci_c128* sigma, double* delta, hfci_c128* z0,
+                             double* nu) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(c, "NULL contour");
+  for (int j = 0; j < c->J; ++j) {
+    if (z) z[j] = hfci_c128{c->z[j].real(), c->z[j].imag()};
+    if (sigma) sigma[j] = hfci_c128{c->sigma[j].real(), c->sigma[j].imag()};
+    if (delta) delta[j] = c->delta[j];
+    if (z0) z0[j] = hfci_c128{c->z0[j].real(), c->z0[j].imag()};
+    if (nu) nu[j] = c->nu[j];
+  }
+  return HFCI_OK;
+  HFCI_API_END
+}
+
+hfci_status hfci_shifted_solve(const hfci_op* op, const hfci_contour* c, int prec, int nrhs, const void* f,
+                               void* y, int steps, double reduce, int max_steps, int* steps_taken) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(op && c && f && y, "NULL argument");
+  if (c->op != op) throw Error(HFCI_E_STATE, "contour was created for another operator");
+  HFCI_REQUIRE(prec == HFCI_F32 || prec == HFCI_F64, "prec must be 32 or 64");
+  HFCI_REQUIRE(nrhs >= 1 && (long)nrhs * c->J <= 65536, "nrhs out of range");
+  HFCI_REQUIRE(steps > 0 || (reduce > 1.0 && max_steps >= 1), "give steps > 0, or reduce > 1 and max_steps >= 1");
+  DeviceGuard dg(op->ctx->device);
+  FciStats st;
+  if (prec == HFCI_F64)
+    shifted_solve_batch<double2>(*op, *c, nrhs, (const double2*)f, (double2*)y, steps, reduce, max_steps,
+                                 steps_taken, st);
+  else
+    shifted_solve_batch<float2>(*op, *c, nrhs, (const float2*)f, (float2*)y, steps, reduce, max_steps,
+                                steps_taken, st);
+  HFCI_HIP(hipGetLastError());
+  HFCI_HIP(hipStreamSynchronize(op->ctx->stream));
+  return HFCI_OK;
+  HFCI_API_END
+}
+
+hfci_status hfci_fci_apply(const hfci_op* op, const hfci_contour* c, const hfci_solve_opts* o, int nrhs,
+                           const hfci_c128* f, hfci_c128* out, hfci_stats* stats) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(op && c && f && out, "NULL argument");
+  if (c->op != op) throw Error(HFCI_E_STATE, "contour was created for another operator");
+  check_opts(o);
+  HFCI_REQUIRE(nrhs >= 1 && (long)nrhs * c->J <= 65536, "nrhs out of range");
+  HFCI_REQUIRE(!stats || stats->size == sizeof(hfci_stats), "stats->size mismatch");
+  DeviceGuard dg(op->ctx->device);
+  FciStats st;
+  fci_apply(*op, *c, *o, nrhs, (const double2*)f, (double2*)out, st);
+  HFCI_HIP(hipGetLastError());
+  HFCI_HIP(hipStreamSynchronize(op->ctx->stream));
+  if (stats) {
+    std::memset((char*)stats + sizeof(size_t), 0, sizeof(hfci_stats) - sizeof(size_t));
+    stats->matvecs = st.matvecs;
+    stats->fp_steps = st.fp_steps;
+  }
+  return HFCI_OK;
+  HFCI_API_END
+}
+
+hfci_status hfci_solve(const hfci_op* op, const hfci_contour* c, const hfci_solve_opts* o, int nrhs,
+                       const hfci_c128* f, hfci_c128* u, hfci_stats* stats) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(op && f && u, "NULL argument");
+  check_opts(o);
+  if (o->precond == HFCI_PRECOND_FCI) {
+    HFCI_REQUIRE(c != nullptr, "FCI preconditioning needs a contour");
+    if (c->op != op) throw Error(HFCI_E_STATE, "contour was created for another operator");
+  }
+  HFCI_REQUIRE(nrhs >= 1 && nrhs <= 64, "nrhs must be in [1, 64]");
+  HFCI_REQUIRE(!stats || stats->size == sizeof(hfci_stats), "stats->size mismatch");
+  DeviceGuard dg(op->ctx->device);
+  const hfci_status st = fgmres_solve(*op, c, *o, nrhs, (const double2*)f, (double2*)u, stats);
+  HFCI_HIP(hipGetLastError());
+  if (st == HFCI_W_NOCONV) g_err = "FGMRES reached max_it before the tolerance";
+  return st;
+  HFCI_API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Internal interface between the host runtime and the HIP kernels of libhfci.
+//
+// Vectors are complex, interleaved (re, im) as float2 / double2, over an
+// nx*ny*nz grid with x fastest.  Batches of vectors are strided by n.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+namespace hfci {
+
+// Geometry and operator scalars of the normalised A = (s/h^2) L7 - kappa - i D.
+struct GridDesc {
+  int nx, ny, nz;
+  int damp_cells;        // L
+  double damp_scale;     // rho2 / L^2, so D = damp_scale * depth^2
+  double s_h2;           // s / h^2
+};
+
+// Coefficients of one Horner stage of the exponential-Taylor step, per pole:
+//   w_out = cB * (A - z0) w_in + alpha * y + gam * f.
+struct StageCoef {
+  double cB_re, cB_im, al_re, al_im, ga_re, ga_im;
+};
+
+// Per-pole constants used inside the stage kernels.
+struct PoleDev {
+  double z0_re, z0_im;   // Taylor centre (shift applied by the stencil)
+  double zz_re, zz_im;   // z - z0 (residual of the first stage)
+};
+
+// Work description of one batched fixed-point launch: systems s in [0, nsys),
+// global system index gs = sys0 + s, pole = gs / nrhs, rhs = gs % nrhs.
+template <typename T2>
+struct StageArgs {
+  const T2* win;         // stage input (w or y), stride n per system
+  const T2* y;           // current iterate, stride n per system
+  const T2* f;           // right-hand sides, stride n per rhs
+  T2* wout;              // stage output, stride n per system
+  const StageCoef* coef; // [pole][stage], stage index m in [0, q)
+  const PoleDev* poles;  // [pole]
+  const int* active;     // [nsys], 0 = converged / skipped
+  double* partial;       // residual partial sums [nsys][nblk] (first stage only)
+  int nsys, sys0, nrhs, q, m;
+};
+
+template <typename T2>
+struct Launch {
+  static void apply(hipStream_t st, const GridDesc& g, const void* kappa, double shift_re,
+                    double shift_im, int nvec, const T2* x, T2* y);
+  // first: w_in is y and a residual partial is produced; the caller picks m.
+  static void stage(hipStream_t st, const GridDesc& g, const void* kappa,
+                    const StageArgs<T2>& a, bool first);
+  // partial sums for the step size d: conj(A w).f and |A w|^2, per rhs.
+  static void dstep_partials(hipStream_t st, const GridDesc& g, const void* kappa, int nrhs,
+                             const T2* w, const T2* f, double* partial);
+  static int partial_blocks(const GridDesc& g);
+};
+
+// FP64 residual r = b - A u (shift 0) with partial sums of |r|^2.
+void launch_residual64(hipStream_t st, const GridDesc& g, const double* kappa, const double2* b,
+                       const double2* u, double2* r, double* partial);
+
+// ---- BLAS-1 and reductions (blas.hip) ----
+int blas_blocks(size_t n);
+// partial[k][blk] over nblk blocks -> out[k], for k < ncomp (deterministic order).
+void launch_reduce(hipStream_t st, const double* partial, int nblk, int ncomp, double* out);
+// FGMRES building blocks (complex128).
+// Basis vector i of V starts at V + i*vstride.
+void launch_multidot(hipStream_t st, const double2* V, int nv, size_t n, size_t vstride,
+                     const double2* w, double* partial);     // partial[(2i+c)][blk]
+void launch_multiaxpy(hipStream_t st, double2* w, const double2* V, int nv, size_t n,
+                      size_t vstride, const double* h, double sign);  // w += sign * sum h_i V_i
+void launch_norm2_partial(hipStream_t st, const void* x, bool f32, size_t n, double* partial);
+void launch_scale_inv(hipStream_t st, double2* v, const double2* w, size_t n, const double* nrm2);
+void launch_fill_zero(hipStream_t st, void* p, size_t bytes);
+void launch_copy_scaled64(hipStream_t st, double2* dst, const double2* src, size_t n, double s);
+void launch_convert_64_to_32(hipStream_t st, float2* dst, const double2* src, size_t n);
+void launch_convert_32_to_64(hipStream_t st, double2* dst, const float2* src, size_t n);
+// w_r = sum_p c_p y_{p,r} (+= if accumulate), systems laid out pole-major.
+template <typename T2>
+void launch_combine(hipStream_t st, T2* w, const T2* y, const double* coef /*[npole][2]*/,
+                    int npole, int nrhs, size_t n, bool accumulate);
+// out64_r = d_r * w_r  (d from device array d[2r], d[2r+1])
+template <typename T2>
+void launch_scale_out(hipStream_t st, double2* out, const T2* w, const double* d, int nrhs,
+                      size_t n);
+// fixed-point bookkeeping: residual norms -> active flags and step counters.
+void launch_fp_check(hipStream_t st, const double* partial, int nblk, int nsys, int sys0,
+                     int nrhs, const double* fnorm2, int fixed_steps, double reduce,
+                     int max_steps, int* active, int* steps, double* rnorm2);
+// d_r = num_r / den_r from reduced sums [nrhs][3]
+void launch_dfinish(hipStream_t st, const double* sums, int nrhs, double* d);
+void launch_set_int(hipStream_t st, int* p, int v, int count);
+
+}  // namespace hfci

@@ -1,0 +1,487 @@
+// Host drivers: batched polynomial fixed-point iteration (Sec. 4.2, eq. fix-pt-exp),
+// the FCI preconditioner (Algorithm 1) and flexible GMRES(m) (Sec. 2) in FP64.
+//
+// All (pole, right-hand side) shifted systems of one FCI application advance together:
+// every Horner stage is a single launch over all systems, so a step at 256^3 with
+// 16 poles x 8 RHS is one launch of ~260k workgroups.  Systems stop independently
+// (per-system active flags decided on the device from the residual norms); the host
+// only reads the flags to know when every system has stopped.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+
+namespace hfci {
+namespace {
+
+template <typename T2> struct Prec;
+template <> struct Prec<float2> { static const void* kappa(const Op& op) { return op.kappa32; } };
+template <> struct Prec<double2> { static const void* kappa(const Op& op) { return op.kappa64; } };
+
+template <typename T2>
+void copy_active(hipStream_t st, T2* dst, const T2* src, const int* active, int nsys, size_t n);
+
+}  // namespace
+
+void launch_copy_active_f(hipStream_t st, float2* dst, const float2* src, const int* active, int nsys, size_t n);
+void launch_copy_active_d(hipStream_t st, double2* dst, const double2* src, const int* active, int nsys,
+                          size_t n);
+
+namespace {
+template <>
+void copy_active<float2>(hipStream_t st, float2* d, const float2* s, const int* a, int nsys, size_t n) {
+  launch_copy_active_f(st, d, s, a, nsys, n);
+}
+template <>
+void copy_active<double2>(hipStream_t st, double2* d, const double2* s, const int* a, int nsys, size_t n) {
+  launch_copy_active_d(st, d, s, a, nsys, n);
+}
+
+// Iterate eq. fix-pt-exp (Horner-staged) for systems gs in [sys0, sys0 + nsys) from y = 0.
+template <typename T2>
+void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sys0, int nsys,
+            int fixed_steps, double reduce, int max_steps, int* steps_out, FciStats& st) {
+  Ctx& ctx = *op.ctx;
+  hipStream_t s = ctx.stream;
+  const size_t n = op.n;
+  const int q = c.q;
+  const size_t vbytes = n * sizeof(T2);
+  T2* wA = (T2*)ctx.ws.get("fp_wA", (size_t)nsys * vbytes);
+  T2* wB = (q >= 3) ? (T2*)ctx.ws.get("fp_wB", (size_t)nsys * vbytes) : nullptr;
+  const int nblk = Launch<T2>::partial_blocks(op.g);
+  double* partial = (double*)ctx.ws.get("fp_partial", (size_t)nsys * nblk * sizeof(double));
+  int* active = (int*)ctx.ws.get("fp_active", (size_t)nsys * sizeof(int));
+  int* steps = (int*)ctx.ws.get("fp_steps", (size_t)nsys * sizeof(int));
+  double* rnorm2 = (double*)ctx.ws.get("fp_rnorm2", (size_t)nsys * sizeof(double));
+  const int nb = blas_blocks(n);
+  double* fpart = (double*)ctx.ws.get("fp_fpart", (size_t)nrhs * nb * sizeof(double));
+  double* fnorm2 = (double*)ctx.ws.get("fp_fnorm2", (size_t)nrhs * sizeof(double));
+
+  launch_fill_zero(s, y, (size_t)nsys * vbytes);
+  for (int r = 0; r < nrhs; ++r) launch_norm2_partial(s, f + (size_t)r * n, sizeof(T2) == 8, n, fpart + (size_t)r * nb);
+  launch_reduce(s, fpart, nb, nrhs, fnorm2);
+  launch_set_int(s, active, 1, nsys);
+  launch_set_int(s, steps, 0, nsys);
+
+  StageArgs<T2> a{};
+  a.y = y;
+  a.f = f;
+  a.coef = c.d_coef;
+  a.poles = c.d_poles;
+  a.active = active;
+  a.partial = partial;
+  a.nsys = nsys;
+  a.sys0 = sys0;
+  a.nrhs = nrhs;
+  a.q = q;
+  const void* kap = Prec<T2>::kappa(op);
+  const bool fixed = fixed_steps > 0;
+  const int cap = fixed ? fixed_steps : max_steps;
+  Profiler& pr = ctx.prof;
+  // algorithmic bytes of one stage launch: per active system its own vectors (first stage: y in,
+  // w out; later stages: w in, y in, w out), plus kappa and each active rhs's f once per launch
+  const double e = (double)sizeof(T2), ek = e / 2.0;
+  std::vector<int> hact(nsys, 1);
+  auto launch_bytes = [&](double per_sys) {
+    int na = 0;
+    std::vector<char> rhs_used(nrhs, 0);
+    for (int k = 0; k < nsys; ++k)
+      if (hact[k]) {
+        ++na;
+        rhs_used[(sys0 + k) % nrhs] = 1;
+      }
+    int nr = 0;
+    for (char u : rhs_used) nr += u;
+    return (double)n * (per_sys * e * na + ek + e * nr);
+  };
+  int prev_active = nsys;
+  for (int it = 0; it <= cap; ++it) {
+    if (fixed && it == cap) break;  // exact count: no final residual check needed
+    // first stage: w_{q-1} from y, plus ||f - (A - z) y||^2 partials
+    a.win = y;
+    a.wout = wA;
+    a.m = q - 1;
+    if (pr.on) pr.begin(s);
+    Launch<T2>::stage(s, op.g, kap, a, true);
+    if (pr.on) pr.end(s, HFCI_PROF_FP_FIRST, launch_bytes(2.0));
+    launch_fp_check(s, partial, nblk, nsys, sys0, nrhs, fnorm2, fixed_steps, reduce, max_steps, active, steps,
+                    rnorm2);
+    int now_active = nsys;
+    if (!fixed) {
+      HFCI_HIP(hipMemcpyAsync(ctx.pinned_int, active, nsys * sizeof(int), hipMemcpyDeviceToHost, s));
+      HFCI_HIP(hipStreamSynchronize(s));
+      if (pr.on) pr.harvest();
+      now_active = 0;
+      for (int k = 0; k < nsys; ++k) {
+        hact[k] = ctx.pinned_int[k] != 0;
+        now_active += hact[k];
+      }
+    }
+    const double stage_bytes = pr.on ? launch_bytes(3.0) : 0.0;
+    st.matvecs += prev_active;
+    if (now_active == 0) break;
+    st.matvecs += (long long)(q - 1) * now_active;
+    st.fp_steps += now_active;
+    prev_active = now_active;
+    // middle stages ping-pong between wA and wB, the last stage writes y in place
+    T2* cur = wA;
+    for (int m = q - 2; m >= 1; --m) {
+      T2* nxt = (cur == wA) ? wB : wA;
+      a.win = cur;
+      a.wout = nxt;
+      a.m = m;
+      if (pr.on) pr.begin(s);
+      Launch<T2>::stage(s, op.g, kap, a, false);
+      if (pr.on) pr.end(s, HFCI_PROF_FP_STAGE, stage_bytes);
+      cur = nxt;
+    }
+    if (q >= 2) {
+      a.win = cur;
+      a.wout = y;
+      a.m = 0;
+      if (pr.on) pr.begin(s);
+      Launch<T2>::stage(s, op.g, kap, a, false);
+      if (pr.on) pr.end(s, HFCI_PROF_FP_STAGE, stage_bytes);
+    } else {
+      copy_active<T2>(s, y, wA, active, nsys, n);
+    }
+  }
+  if (steps_out) {
+    HFCI_HIP(hipMemcpyAsync(ctx.pinned_int, steps, nsys * sizeof(int), hipMemcpyDeviceToHost, s));
+    HFCI_HIP(hipStreamSynchronize(s));
+    std::memcpy(steps_out, ctx.pinned_int, nsys * sizeof(int));
+  }
+  if (pr.on) {
+    HFCI_HIP(hipStreamSynchronize(s));
+    pr.harvest();
+  }
+}
+
+// Alg. 1 steps 1-3 in precision T2: w = sum sigma_j/z_j y_j, d = (Aw)^H f / |Aw|^2, out = d w.
+template <typename T2>
+void fci_body(const Op& op, const Contour& c, const hfci_solve_opts& o, int nrhs, const T2* f, double2* out,
+              FciStats& st) {
+  Ctx& ctx = *op.ctx;
+  hipStream_t s = ctx.stream;
+  const size_t n = op.n;
+  const int J = c.J;
+  int pb = o.pole_batch > 0 ? std::min(o.pole_batch, J) : J;
+  T2* w = (T2*)ctx.ws.get("fci_w", (size_t)nrhs * n * sizeof(T2));
+  T2* y = (T2*)ctx.ws.get("fci_y", (size_t)pb * nrhs * n * sizeof(T2));
+  // quadrature weights of eq. rational: sigma_j / z_j
+  double* cc = (double*)ctx.ws.get("fci_cc", (size_t)2 * J * sizeof(double));
+  double* stage = ctx.pinned_dbl + kPinnedFciOffset;
+  for (int j = 0; j < J; ++j) {
+    const cd v = c.sigma[j] / c.z[j];
+    stage[2 * j] = v.real();
+    stage[2 * j + 1] = v.imag();
+  }
+  HFCI_HIP(hipMemcpyAsync(cc, stage, 2 * J * sizeof(double), hipMemcpyHostToDevice, s));
+  for (int p0 = 0; p0 < J; p0 += pb) {
+    const int np = std::min(pb, J - p0);
+    fp_run<T2>(op, c, nrhs, f, y, p0 * nrhs, np * nrhs, o.fp_steps, o.fp_reduce, o.fp_max_steps, nullptr, st);
+    launch_combine<T2>(s, w, y, cc + 2 * p0, np, nrhs, n, p0 > 0);
+  }
+  // step 3: minimise ||f - d A w|| over d
+  const int nblk = Launch<T2>::partial_blocks(op.g);
+  double* part = (double*)ctx.ws.get("fci_dpart", (size_t)nrhs * 3 * nblk * sizeof(double));
+  double* sums = (double*)ctx.ws.get("fci_dsums", (size_t)nrhs * 3 * sizeof(double));
+  double* d = (double*)ctx.ws.get("fci_d", (size_t)nrhs * 2 * sizeof(double));
+  Launch<T2>::dstep_partials(s, op.g, Prec<T2>::kappa(op), nrhs, w, f, part);
+  launch_reduce(s, part, nblk, 3 * nrhs, sums);
+  launch_dfinish(s, sums, nrhs, d);
+  st.matvecs += nrhs;
+  launch_scale_out<T2>(s, out, w, d, nrhs, n);
+}
+
+}  // namespace
+
+template <typename T2>
+void shifted_solve_batch(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int fixed_steps,
+                         double reduce, int max_steps, int* steps_out, FciStats& st) {
+  fp_run<T2>(op, c, nrhs, f, y, 0, c.J * nrhs, fixed_steps, reduce, max_steps, steps_out, st);
+}
+template void shifted_solve_batch<float2>(const Op&, const Contour&, int, const float2*, float2*, int, double, int,
+                                          int*, FciStats&);
+template void shifted_solve_batch<double2>(const Op&, const Contour&, int, const double2*, double2*, int, double,
+                                           int, int*, FciStats&);
+
+void fci_apply(const Op& op, const Contour& c, const hfci_solve_opts& o, int nrhs, const double2* f, double2* out,
+               FciStats& st) {
+  Ctx& ctx = *op.ctx;
+  if (o.precision == HFCI_F32) {
+    float2* f32 = (float2*)ctx.ws.get("fci_f32", (size_t)nrhs * op.n * sizeof(float2));
+    launch_convert_64_to_32(ctx.stream, f32, f, (size_t)nrhs * op.n);
+    fci_body<float2>(op, c, o, nrhs, f32, out, st);
+  } else {
+    fci_body<double2>(op, c, o, nrhs, f, out, st);
+  }
+}
+
+namespace {
+
+struct Timer {
+  hipEvent_t a, b;
+  hipStream_t s;
+  explicit Timer(hipStream_t st) : s(st) {
+    HFCI_HIP(hipEventCreate(&a));
+    HFCI_HIP(hipEventCreate(&b));
+  }
+  ~Timer() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  void start() { HFCI_HIP(hipEventRecord(a, s)); }
+  double stop_ms() {
+    HFCI_HIP(hipEventRecord(b, s));
+    HFCI_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    HFCI_HIP(hipEventElapsedTime(&ms, a, b));
+    return ms;
+  }
+};
+
+// Givens rotation (c, s) with [c s; -conj(s) c] [a; b] = [rho; 0], c real.
+void givens(cd a, cd b, double& c, cd& s, cd& rho) {
+  if (std::abs(a) == 0.0) {
+    c = 0.0;
+    s = cd(1.0, 0.0);
+    rho = b;
+    return;
+  }
+  const double nrm = std::sqrt(std::norm(a) + std::norm(b));
+  const cd ph = a / std::abs(a);
+  c = std::abs(a) / nrm;
+  s = ph * std::conj(b) / nrm;
+  rho = ph * nrm;
+}
+
+}  // namespace
+
+// Flexible GMRES(m) with CGS2 and Givens, FP64, batched over right-hand sides.
+// Krylov bases are laid out [j][rhs][n] so that the FCI of step j reads V[j] and
+// writes Z[j] for all right-hand sides as two contiguous blocks.
+hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& o, int nrhs, const double2* f,
+                         double2* u, hfci_stats* stats) {
+  Ctx& ctx = *op.ctx;
+  hipStream_t s = ctx.stream;
+  const auto t_wall0 = std::chrono::steady_clock::now();
+  const size_t n = op.n;
+  const int m = o.restart;
+  const size_t vs = (size_t)nrhs * n;  // stride between basis vectors of the same rhs
+  double2* b = (double2*)ctx.ws.get("gm_b", vs * sizeof(double2));
+  double2* V = (double2*)ctx.ws.get("gm_V", (size_t)(m + 1) * vs * sizeof(double2));
+  double2* Z = (double2*)ctx.ws.get("gm_Z", (size_t)m * vs * sizeof(double2));
+  double2* stage_in = nullptr;
+  double2* stage_out = nullptr;
+  const int nbs = Launch<double2>::partial_blocks(op.g);
+  const int nbb = blas_blocks(n);
+  const int npart = std::max(nbs, nbb * 2 * (m + 1));
+  double* part = (double*)ctx.ws.get("gm_part", (size_t)npart * sizeof(double));
+  // per rhs: h1[2(m+1)], h2[2(m+1)], hn2[1], beta2[1], y[2m]
+  const int hstride = 4 * (m + 1) + 2 + 2 * m;
+  double* hdev = (double*)ctx.ws.get("gm_h", (size_t)nrhs * hstride * sizeof(double));
+  double* hhost = ctx.pinned_dbl;
+  if ((size_t)nrhs * hstride > kPinnedFciOffset) throw Error(HFCI_E_ARG, "too many right-hand sides for the restart length");
+
+  for (int r = 0; r < nrhs; ++r) launch_copy_scaled64(s, b + r * n, f + r * n, n, op.s);
+  std::vector<double> bnorm(nrhs);
+  for (int r = 0; r < nrhs; ++r) launch_norm2_partial(s, b + r * n, false, n, part + (size_t)r * nbb);
+  launch_reduce(s, part, nbb, nrhs, hdev);
+  HFCI_HIP(hipMemcpyAsync(hhost, hdev, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  HFCI_HIP(hipStreamSynchronize(s));
+  for (int r = 0; r < nrhs; ++r) bnorm[r] = std::sqrt(hhost[r]);
+
+  std::vector<char> done(nrhs, 0);
+  std::vector<double> relres(nrhs, 1.0);
+  std::vector<std::vector<cd>> H(nrhs), G(nrhs), SN(nrhs);
+  std::vector<std::vector<double>> CS(nrhs);
+  std::vector<int> kr(nrhs, 0);
+  int its = 0, cycles = 0;
+  long long res_mv = 0;
+  FciStats fst;
+  double t_fci = 0, t_arn = 0;
+  Timer tm(s);
+  hfci_status status = HFCI_OK;
+
+  for (int r = 0; r < nrhs; ++r)
+    if (bnorm[r] == 0.0) {
+      launch_fill_zero(s, u + r * n, n * sizeof(double2));
+      done[r] = 1;
+      relres[r] = 0.0;
+    }
+
+  while (true) {
+    // true FP64 residual of every unfinished rhs, written into V[0]
+    tm.start();
+    std::vector<int> act;
+    for (int r = 0; r < nrhs; ++r) {
+      if (done[r]) continue;
+      launch_residual64(s, op.g, op.kappa64, b + r * n, u + r * n, V + r * n, part);
+      launch_reduce(s, part, nbs, 1, hdev + (size_t)r * hstride + 4 * (m + 1) + 1);
+      act.push_back(r);
+      ++res_mv;
+    }
+    for (int r : act)
+      HFCI_HIP(hipMemcpyAsync(hhost + r, hdev + (size_t)r * hstride + 4 * (m + 1) + 1, sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    HFCI_HIP(hipStreamSynchronize(s));
+    t_arn += tm.stop_ms();
+    std::vector<int> cyc;
+    for (int r : act) {
+      const double beta = std::sqrt(hhost[r]);
+      if (!(beta == beta)) throw Error(HFCI_E_NUMERIC, "NaN in the FGMRES residual");
+      relres[r] = beta / bnorm[r];
+      if (relres[r] <= o.tol)
+        done[r] = 1;
+      else
+        cyc.push_back(r);
+    }
+    if (o.verbose) {
+      double mx = 0.0;
+      for (int r : act) mx = std::max(mx, relres[r]);
+      std::fprintf(stderr, "[hfci] cycle %d: its %d, max true relres %.3e, %zu of %d rhs open, fci %.0f ms, "
+                   "arnoldi %.0f ms\n", cycles, its, mx, cyc.size(), nrhs, t_fci, t_arn);
+      std::fflush(stderr);
+    }
+    if (cyc.empty()) break;
+    if (its >= o.max_it) {
+      status = HFCI_W_NOCONV;
+      break;
+    }
+    ++cycles;
+    std::vector<double> beta(nrhs, 0.0);
+    for (int r : cyc) {
+      beta[r] = std::sqrt(hhost[r]);
+      launch_scale_inv(s, V + r * n, V + r * n, n, hdev + (size_t)r * hstride + 4 * (m + 1) + 1);
+      H[r].assign((size_t)(m + 1) * m, cd(0, 0));
+      G[r].assign(m + 1, cd(0, 0));
+      G[r][0] = beta[r];
+      CS[r].assign(m, 0.0);
+      SN[r].assign(m, cd(0, 0));
+      kr[r] = 0;
+    }
+    std::vector<int> live = cyc;  // rhs still extending this cycle
+    for (int j = 0; j < m && !live.empty(); ++j) {
+      // ---- preconditioner: Z[j] = FCI(V[j]) for the live right-hand sides ----
+      tm.start();
+      const int nl = (int)live.size();
+      const bool all = (nl == nrhs);
+      const double2* fin = V + (size_t)j * vs;
+      double2* fout = Z + (size_t)j * vs;
+      if (!all) {
+        stage_in = (double2*)ctx.ws.get("gm_stage_in", (size_t)nl * n * sizeof(double2));
+        stage_out = (double2*)ctx.ws.get("gm_stage_out", (size_t)nl * n * sizeof(double2));
+        for (int k = 0; k < nl; ++k)
+          HFCI_HIP(hipMemcpyAsync(stage_in + k * n, V + (size_t)j * vs + live[k] * n, n * sizeof(double2),
+                                  hipMemcpyDeviceToDevice, s));
+        fin = stage_in;
+        fout = stage_out;
+      }
+      if (c && o.precond == HFCI_PRECOND_FCI) {
+        fci_apply(op, *c, o, nl, fin, fout, fst);
+      } else {
+        HFCI_HIP(hipMemcpyAsync(fout, fin, (size_t)nl * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      }
+      if (!all)
+        for (int k = 0; k < nl; ++k)
+          HFCI_HIP(hipMemcpyAsync(Z + (size_t)j * vs + live[k] * n, stage_out + k * n, n * sizeof(double2),
+                                  hipMemcpyDeviceToDevice, s));
+      t_fci += tm.stop_ms();
+      // ---- Arnoldi: w = A z_j, CGS2 against V[0..j], normalise ----
+      tm.start();
+      for (int r : live) {
+        double2* w = V + (size_t)(j + 1) * vs + r * n;
+        const double2* Vr = V + r * n;
+        double* hb = hdev + (size_t)r * hstride;
+        Launch<double2>::apply(s, op.g, op.kappa64, 0.0, 0.0, 1, Z + (size_t)j * vs + r * n, w);
+        launch_multidot(s, Vr, j + 1, n, vs, w, part);
+        launch_reduce(s, part, nbb, 2 * (j + 1), hb);
+        launch_multiaxpy(s, w, Vr, j + 1, n, vs, hb, -1.0);
+        launch_multidot(s, Vr, j + 1, n, vs, w, part);
+        launch_reduce(s, part, nbb, 2 * (j + 1), hb + 2 * (m + 1));
+        launch_multiaxpy(s, w, Vr, j + 1, n, vs, hb + 2 * (m + 1), -1.0);
+        launch_norm2_partial(s, w, false, n, part);
+        launch_reduce(s, part, nbb, 1, hb + 4 * (m + 1));
+        launch_scale_inv(s, w, w, n, hb + 4 * (m + 1));
+        HFCI_HIP(hipMemcpyAsync(hhost + (size_t)r * hstride, hb, (4 * (m + 1) + 1) * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+      }
+      fst.matvecs += nl;
+      HFCI_HIP(hipStreamSynchronize(s));
+      t_arn += tm.stop_ms();
+      ++its;
+      // ---- Givens update of the Hessenberg column on the host ----
+      std::vector<int> next;
+      for (int r : live) {
+        const double* hh = hhost + (size_t)r * hstride;
+        std::vector<cd>& Hr = H[r];
+        auto Hat = [&](int i, int jj) -> cd& { return Hr[(size_t)i * m + jj]; };
+        for (int i = 0; i <= j; ++i)
+          Hat(i, j) = cd(hh[2 * i] + hh[2 * (m + 1) + 2 * i], hh[2 * i + 1] + hh[2 * (m + 1) + 2 * i + 1]);
+        const double hn = std::sqrt(hh[4 * (m + 1)]);
+        if (!(hn == hn)) throw Error(HFCI_E_NUMERIC, "NaN in the Arnoldi process");
+        Hat(j + 1, j) = hn;
+        for (int i = 0; i < j; ++i) {
+          const cd x = Hat(i, j), yv = Hat(i + 1, j);
+          Hat(i, j) = CS[r][i] * x + SN[r][i] * yv;
+          Hat(i + 1, j) = -std::conj(SN[r][i]) * x + CS[r][i] * yv;
+        }
+        double cs;
+        cd sn, rho;
+        givens(Hat(j, j), Hat(j + 1, j), cs, sn, rho);
+        CS[r][j] = cs;
+        SN[r][j] = sn;
+        Hat(j, j) = rho;
+        Hat(j + 1, j) = 0.0;
+        G[r][j + 1] = -std::conj(sn) * G[r][j];
+        G[r][j] = cs * G[r][j];
+        kr[r] = j + 1;
+        relres[r] = std::abs(G[r][j + 1]) / bnorm[r];
+        if (!(relres[r] <= o.tol) && its < o.max_it && hn > 0.0) next.push_back(r);
+      }
+      live = next;
+      if (its >= o.max_it) break;
+    }
+    // ---- u += Z_k y_k with H_k y_k = g_k (back substitution) ----
+    tm.start();
+    for (int r : cyc) {
+      const int k = kr[r];
+      std::vector<cd> yv(k);
+      for (int i = k - 1; i >= 0; --i) {
+        cd acc = G[r][i];
+        for (int l = i + 1; l < k; ++l) acc -= H[r][(size_t)i * m + l] * yv[l];
+        yv[i] = acc / H[r][(size_t)i * m + i];
+      }
+      double* yd = hhost + (size_t)r * hstride + 4 * (m + 1) + 2;
+      for (int i = 0; i < k; ++i) {
+        yd[2 * i] = yv[i].real();
+        yd[2 * i + 1] = yv[i].imag();
+      }
+      HFCI_HIP(hipMemcpyAsync(hdev + (size_t)r * hstride + 4 * (m + 1) + 2, yd, 2 * k * sizeof(double),
+                              hipMemcpyHostToDevice, s));
+      launch_multiaxpy(s, u + r * n, Z + r * n, k, n, vs, hdev + (size_t)r * hstride + 4 * (m + 1) + 2, 1.0);
+    }
+    HFCI_HIP(hipStreamSynchronize(s));
+    t_arn += tm.stop_ms();
+  }
+  if (stats) {
+    stats->its = its;
+    stats->restarts = cycles;
+    stats->matvecs = fst.matvecs + res_mv;
+    stats->fp_steps = fst.fp_steps;
+    double mx = 0;
+    for (double v : relres) mx = std::max(mx, v);
+    stats->final_relres = mx;
+    stats->time_fci_ms = t_fci;
+    stats->time_arnoldi_ms = t_arn;
+    stats->time_total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_wall0).count();
+  }
+  return status;
+}
+
+}  // namespace hfci

@@ -1,0 +1,330 @@
+"""Thin ctypes binding of libhfci (include/hfci.h).
+
+Every function here only marshals arguments and calls the C ABI of the same
+name; all arithmetic runs in the library's HIP kernels.  torch tensors are used
+for device memory only (their data_ptr() crosses the boundary).  If the built
+library is missing the import fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes
+import os
+import sys
+import weakref
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhfci.so")
+
+HFCI_OK, HFCI_W_NOCONV = 0, 1
+HFCI_F32, HFCI_F64 = 32, 64
+HFCI_PRECOND_NONE, HFCI_PRECOND_FCI = 0, 1
+
+STATUS_NAMES = {0: "HFCI_OK", 1: "HFCI_W_NOCONV", -1: "HFCI_E_ARG", -2: "HFCI_E_HIP", -3: "HFCI_E_OOM",
+                -4: "HFCI_E_CONTOUR", -5: "HFCI_E_NUMERIC", -6: "HFCI_E_STATE"}
+
+# every symbol include/hfci.h declares
+EXPORTED = ["hfci_default_opts", "hfci_last_error", "hfci_version", "hfci_ctx_create", "hfci_ctx_destroy",
+            "hfci_op_create", "hfci_op_destroy", "hfci_op_info", "hfci_apply", "hfci_contour_create",
+            "hfci_contour_destroy", "hfci_contour_get", "hfci_shifted_solve", "hfci_fci_apply", "hfci_solve",
+            "hfci_ctx_profile", "hfci_ctx_profile_read"]
+PROF_CLASSES = ["fp_stage", "fp_stage_first", "apply"]
+
+
+class HfciError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+class c128(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class KernelProf(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_longlong), ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_size_t), ("precision", ctypes.c_int), ("restart", ctypes.c_int),
+                ("max_it", ctypes.c_int), ("tol", ctypes.c_double), ("fp_steps", ctypes.c_int),
+                ("fp_reduce", ctypes.c_double), ("fp_max_steps", ctypes.c_int), ("k_in", ctypes.c_int),
+                ("precond", ctypes.c_int), ("pole_batch", ctypes.c_int), ("verbose", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_size_t), ("its", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("matvecs", ctypes.c_longlong), ("fp_steps", ctypes.c_longlong),
+                ("final_relres", ctypes.c_double), ("time_fci_ms", ctypes.c_double),
+                ("time_arnoldi_ms", ctypes.c_double), ("time_total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "size"}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libhfci.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libhfci.so not found at %s: build it with `python -m paper_1811_12378_amd.build`"
+                          % path)
+    lib = ctypes.CDLL(path)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "hfci_default_opts": (None, [P(SolveOpts)]),
+        "hfci_last_error": (ctypes.c_char_p, []),
+        "hfci_version": (ctypes.c_char_p, []),
+        "hfci_ctx_create": (ip, [ip, vp, P(vp)]),
+        "hfci_ctx_destroy": (None, [vp]),
+        "hfci_op_create": (ip, [vp, ip, ip, ip, dp, vp, dp, ip, dp, P(vp)]),
+        "hfci_op_destroy": (None, [vp]),
+        "hfci_op_info": (ip, [vp, P(dp)]),
+        "hfci_apply": (ip, [vp, c128, ip, ip, vp, vp]),
+        "hfci_contour_create": (ip, [vp, ip, dp, dp, ip, vp, vp, vp, P(vp)]),
+        "hfci_contour_destroy": (None, [vp]),
+        "hfci_contour_get": (ip, [vp, vp, vp, vp, vp, vp]),
+        "hfci_shifted_solve": (ip, [vp, vp, ip, ip, vp, vp, ip, dp, ip, vp]),
+        "hfci_fci_apply": (ip, [vp, vp, P(SolveOpts), ip, vp, vp, P(Stats)]),
+        "hfci_solve": (ip, [vp, vp, P(SolveOpts), ip, vp, vp, P(Stats)]),
+        "hfci_ctx_profile": (ip, [vp, ip]),
+        "hfci_ctx_profile_read": (ip, [vp, P(KernelProf)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status < 0:
+        raise HfciError(status, load_library().hfci_last_error().decode())
+    return status
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _ptr(t, dtype=None, what="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) torch tensor" % what)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must have dtype %s, got %s" % (what, dtype, t.dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    load_library().hfci_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+_live_contexts = weakref.WeakSet()
+
+
+class _Handle:
+    """Owner of one library handle; released by close(), __del__ or interpreter exit."""
+
+    _destroy = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            getattr(load_library(), self._destroy)(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # at interpreter shutdown the atexit hook has already released every handle
+        try:
+            if not _finalizing():
+                self.close()
+        except Exception:
+            pass
+
+
+class Context(_Handle):
+    """hfci_ctx_create / hfci_ctx_destroy.  Closing a context first closes the
+    operators and contours created from it."""
+
+    _destroy = "hfci_ctx_destroy"
+
+    def __init__(self, device: int = 0):
+        self.h = ctypes.c_void_p()
+        self._children = weakref.WeakSet()
+        _check(load_library().hfci_ctx_create(device, None, ctypes.byref(self.h)))
+        self.device = device
+        _live_contexts.add(self)
+
+    def _adopt(self, child):
+        self._children.add(child)
+
+    def profile(self, enable: bool = True):
+        """hfci_ctx_profile: start (counters reset) or stop kernel timing."""
+        _check(load_library().hfci_ctx_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """hfci_ctx_profile_read -> {class: {launches, total_ms, alg_bytes}}."""
+        out = (KernelProf * len(PROF_CLASSES))()
+        _check(load_library().hfci_ctx_profile_read(self.h, out))
+        return {name: {"launches": out[k].launches, "total_ms": out[k].total_ms, "alg_bytes": out[k].alg_bytes}
+                for k, name in enumerate(PROF_CLASSES)}
+
+    def close(self):
+        kids = list(self._children)
+        for k in kids:  # contours before operators
+            if isinstance(k, Contour):
+                k.close()
+        for k in kids:
+            k.close()
+        super().close()
+
+
+@atexit.register
+def _close_all():
+    for c in list(_live_contexts):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
+class Operator(_Handle):
+    """hfci_op_create: c is a float64 CUDA tensor [nz, ny, nx] (x fastest)."""
+
+    _destroy = "hfci_op_destroy"
+
+    def __init__(self, ctx: Context, c, h: float, omega: float, damp_cells: int, damp_rho2: float):
+        import torch
+        self.h = ctypes.c_void_p()
+        if c.dim() != 3:
+            raise ValueError("c must be [nz, ny, nx]")
+        self.ctx = ctx
+        self.shape = tuple(c.shape)
+        nz, ny, nx = self.shape
+        _sync()
+        _check(load_library().hfci_op_create(ctx.h, nx, ny, nz, h, _ptr(c, torch.float64, "c"), omega,
+                                             damp_cells, damp_rho2, ctypes.byref(self.h)))
+        self.n = nx * ny * nz
+        ctx._adopt(self)
+
+    def info(self):
+        out = (ctypes.c_double * 7)()
+        _check(load_library().hfci_op_info(self.h, out))
+        keys = ["s", "s_h2", "b1", "b2", "rho2", "kappa_min", "kappa_max"]
+        return dict(zip(keys, list(out)))
+
+
+def _prec_of(t):
+    import torch
+    if t.dtype == torch.complex128:
+        return HFCI_F64
+    if t.dtype == torch.complex64:
+        return HFCI_F32
+    raise TypeError("complex64 or complex128 expected, got %s" % t.dtype)
+
+
+def apply(op: Operator, x, shift: complex = 0.0, out=None):
+    """hfci_apply: (A - shift I) x for x of shape [..., nz, ny, nx] (batch = leading dims)."""
+    import torch
+    prec = _prec_of(x)
+    if tuple(x.shape[-3:]) != op.shape:
+        raise ValueError("x grid shape %s != operator %s" % (tuple(x.shape[-3:]), op.shape))
+    nvec = x.numel() // op.n
+    if out is None:
+        out = torch.empty_like(x)
+    _sync()
+    _check(load_library().hfci_apply(op.h, c128(shift.real, shift.imag), prec, nvec, _ptr(x, None, "x"),
+                                     _ptr(out, x.dtype, "out")))
+    return out
+
+
+class Contour(_Handle):
+    """hfci_contour_create: poles/weights/delta default to eq. quad-points and the delta search."""
+
+    _destroy = "hfci_contour_destroy"
+
+    def __init__(self, op: Operator, J: int, t: float = 1.0, eps: float = 0.5, q: int = 8,
+                 z=None, sigma=None, delta=None):
+        self.h = ctypes.c_void_p()
+        self.op = op
+        self.J = J
+        self.q = q
+        zp = sp = dp = None
+        if z is not None:
+            za = (c128 * J)(*[c128(complex(v).real, complex(v).imag) for v in z])
+            sa = (c128 * J)(*[c128(complex(v).real, complex(v).imag) for v in sigma])
+            zp, sp = ctypes.cast(za, ctypes.c_void_p), ctypes.cast(sa, ctypes.c_void_p)
+            self._keep = (za, sa)
+        if delta is not None:
+            da = (ctypes.c_double * J)(*[float(v) for v in delta])
+            dp = ctypes.cast(da, ctypes.c_void_p)
+            self._keepd = da
+        _check(load_library().hfci_contour_create(op.h, J, t, eps, q, zp, sp, dp, ctypes.byref(self.h)))
+        op.ctx._adopt(self)
+
+    def get(self):
+        J = self.J
+        z, s, z0 = (c128 * J)(), (c128 * J)(), (c128 * J)()
+        d, nu = (ctypes.c_double * J)(), (ctypes.c_double * J)()
+        _check(load_library().hfci_contour_get(self.h, z, s, d, z0, nu))
+        cz = lambda a: np.array([complex(v.re, v.im) for v in a])
+        return {"z": cz(z), "sigma": cz(s), "delta": np.array(d[:]), "z0": cz(z0), "nu": np.array(nu[:])}
+
+
+def shifted_solve(op: Operator, c: Contour, f, steps: int = 0, reduce: float = 5.0, max_steps: int = 200):
+    """hfci_shifted_solve: f [nrhs, nz, ny, nx] -> (y [J, nrhs, nz, ny, nx], steps taken [J, nrhs])."""
+    import torch
+    prec = _prec_of(f)
+    nrhs = f.shape[0]
+    y = torch.empty((c.J,) + tuple(f.shape), dtype=f.dtype, device=f.device)
+    st = (ctypes.c_int * (c.J * nrhs))()
+    _sync()
+    _check(load_library().hfci_shifted_solve(op.h, c.h, prec, nrhs, _ptr(f, None, "f"), _ptr(y), steps, reduce,
+                                             max_steps, ctypes.cast(st, ctypes.c_void_p)))
+    return y, np.array(st[:]).reshape(c.J, nrhs)
+
+
+def fci_apply(op: Operator, c: Contour, f, opts: SolveOpts | None = None):
+    """hfci_fci_apply (Algorithm 1): f complex128 [nrhs, nz, ny, nx] -> out, stats."""
+    import torch
+    opts = opts or default_opts()
+    out = torch.empty_like(f)
+    st = Stats()
+    st.size = ctypes.sizeof(Stats)
+    _sync()
+    _check(load_library().hfci_fci_apply(op.h, c.h, ctypes.byref(opts), f.shape[0],
+                                         _ptr(f, torch.complex128, "f"), _ptr(out), ctypes.byref(st)))
+    return out, st.as_dict()
+
+
+def solve(op: Operator, c: Contour | None, f, u0=None, opts: SolveOpts | None = None):
+    """hfci_solve: physical f complex128 [nrhs, nz, ny, nx] -> (u, stats, status)."""
+    import torch
+    opts = opts or default_opts()
+    u = torch.zeros_like(f) if u0 is None else u0.clone()
+    st = Stats()
+    st.size = ctypes.sizeof(Stats)
+    _sync()
+    status = _check(load_library().hfci_solve(op.h, c.h if c is not None else None, ctypes.byref(opts),
+                                              f.shape[0], _ptr(f, torch.complex128, "f"), _ptr(u),
+                                              ctypes.byref(st)))
+    d = st.as_dict()
+    d["status"] = STATUS_NAMES[status]
+    return u, d

@@ -1,0 +1,290 @@
+"""HIP path versus the FP64 oracle, through the C ABI (needs an MI355X).
+
+Tolerances:
+  * FP64 kernels: 1e-13 relative (stencil), 1e-12 (fixed-point / FCI in lockstep),
+    1e-10 (full FGMRES solve in lockstep, fixed counts and parameters);
+  * FP32 kernels: 2e-6 relative for one stencil application (7 terms of
+    magnitude <= 12 s/h^2 |x| each rounded at 2^-24); 2e-4 for the fixed-point
+    iteration (the Horner partial sums grow by up to exp(|delta| (b2 - b1)/2),
+    about 40 here, over q = 8 stages per step).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import contour as OC
+from oracle import fci as OF
+from oracle import fixed_point as OFP
+from oracle import operator as OO
+from oracle import polynomial as OP
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+hf = pytest.importorskip("paper_1811_12378_amd.hfci")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hf.load_library()
+    c = hf.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+def medium(shape, seed, lo=1.0, hi=3.0):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=shape)
+
+
+def make_ops(ctx, c, omega, cells, rho2, h=None):
+    h = 1.0 / c.shape[0] if h is None else h
+    o = OO.Operator(c, omega, cells, rho2, h=h)
+    g = hf.Operator(ctx, dev(c), h, omega, cells, rho2)
+    return o, g
+
+
+SHAPES = [(8, 8, 8), (9, 17, 33), (70, 9, 5), (5, 7, 130), (1, 1, 1), (2, 3, 1)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_apply_parity(ctx, shape, prec):
+    c = medium(shape, 1)
+    o, g = make_ops(ctx, c, 9.0, 2, 0.8)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((3,) + shape) + 1j * rng.standard_normal((3,) + shape)
+    shift = 0.37 - 1.21j
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    y = host(hf.apply(g, dev(x).to(dt), shift))
+    tol = 1e-13 if prec == "f64" else 2e-6
+    for k in range(3):
+        ref = o.apply(x[k], shift)
+        assert rel(y[k], ref) <= tol, (shape, prec, k, rel(y[k], ref))
+
+
+def test_op_info_matches_oracle(ctx):
+    c = medium((6, 7, 8), 3)
+    o, g = make_ops(ctx, c, 11.0, 3, 1.2, h=0.1)
+    info = g.info()
+    b1, b2, rho2 = o.rectangle()
+    assert info["s"] == pytest.approx(o.s, rel=1e-15)
+    assert info["s_h2"] == pytest.approx(o.s_h2, rel=1e-15)
+    assert (info["b1"], info["b2"], info["rho2"]) == pytest.approx((b1, b2, rho2), rel=1e-14, abs=1e-14)
+
+
+def test_contour_parameters_match_oracle(ctx):
+    c = medium((12, 12, 12), 4)
+    o, g = make_ops(ctx, c, 14.0, 3, 1.0)
+    b1, b2, rho2 = o.rectangle()
+    for J, t, eps, q in [(8, 1.0, 0.5, 8), (6, 0.1, 0.3, 3), (12, 0.5, 0.4, 4)]:
+        cg = hf.Contour(g, J, t, eps, q).get()
+        z, sigma, _ = OC.poles_and_weights(J, t, eps, rho2)
+        assert np.abs(cg["z"] - z).max() <= 1e-13 * np.abs(z).max()
+        assert np.abs(cg["sigma"] - sigma).max() <= 1e-13 * np.abs(sigma).max()
+        bd = OP.rectangle_boundary(b1, b2, rho2, 2000)
+        for j in range(J):
+            d_o, nu_o, z0_o = OP.optimise_delta(z[j], b1, b2, rho2, q, per_side=2000)
+            assert abs(cg["z0"][j] - z0_o) <= 1e-13 * abs(z0_o)
+            assert np.sign(cg["delta"][j]) == np.sign(z[j].imag)
+            # both minimise the same objective: equal minima, and the library's delta is
+            # (near-)optimal when scored by the oracle
+            assert abs(cg["nu"][j] - nu_o) <= 1e-6
+            assert OP.rate(cg["delta"][j], z[j], z0_o, q, bd) <= nu_o + 1e-6
+
+
+def oracle_poles(o, J, t, eps, q):
+    return OF.pole_parameters(o, J, t, eps, q)
+
+
+def gpu_contour(g, poles, J, q):
+    return hf.Contour(g, J, 1.0, 0.5, q, z=[p.z for p in poles], sigma=[p.sigma for p in poles],
+                      delta=[p.delta for p in poles])
+
+
+@pytest.mark.parametrize("prec,q,steps", [("f64", 8, 3), ("f64", 3, 4), ("f64", 1, 5), ("f64", 2, 2),
+                                          ("f32", 8, 3), ("f32", 4, 2)])
+def test_shifted_solve_fixed_steps(ctx, prec, q, steps):
+    shape = (9, 17, 33)
+    c = medium(shape, 5)
+    o, g = make_ops(ctx, c, 18.0, 3, 1.0)
+    poles = oracle_poles(o, 6, 1.0, 0.5, q)
+    cg = gpu_contour(g, poles, 6, q)
+    rng = np.random.default_rng(6)
+    f = rng.standard_normal((2,) + shape) + 1j * rng.standard_normal((2,) + shape)
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    y, st = hf.shifted_solve(g, cg, dev(f).to(dt), steps=steps)
+    y = host(y)
+    assert np.all(st == steps)
+    tol = 1e-12 if prec == "f64" else 2e-4
+    Am = lambda x, s: o.apply(x, s)
+    for j, p in enumerate(poles):
+        for r in range(2):
+            ref, _ = OFP.fixed_point_solve(Am, f[r], p.z, p.z0, p.delta, q, steps=steps)
+            assert rel(y[j, r], ref) <= tol, (j, r, rel(y[j, r], ref))
+
+
+def test_shifted_solve_adaptive_stop_rule(ctx):
+    shape = (12, 12, 12)
+    c = medium(shape, 7)
+    o, g = make_ops(ctx, c, 16.0, 3, 1.0)
+    poles = oracle_poles(o, 8, 1.0, 0.5, 8)
+    cg = gpu_contour(g, poles, 8, 8)
+    rng = np.random.default_rng(8)
+    f = rng.standard_normal((1,) + shape) + 1j * rng.standard_normal((1,) + shape)
+    y, st = hf.shifted_solve(g, cg, dev(f), reduce=5.0, max_steps=300)
+    y = host(y)
+    Am = lambda x, s: o.apply(x, s)
+    fn = np.linalg.norm(f[0])
+    for j, p in enumerate(poles):
+        ref, hist = OFP.fixed_point_solve(Am, f[0], p.z, p.z0, p.delta, 8, reduce=5.0, m_max=300)
+        k = st[j, 0]
+        # the returned iterate satisfies the rule and the previous one did not
+        r = np.linalg.norm(f[0] - o.apply(y[j, 0], p.z))
+        assert r <= fn / 5 * (1 + 1e-9)
+        assert hist[k - 1] > fn / 5 * (1 - 1e-9)
+        if k == len(hist) - 1:
+            assert rel(y[j, 0], ref) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fci_lockstep(ctx, prec):
+    shape = (10, 11, 12)
+    c = medium(shape, 9)
+    o, g = make_ops(ctx, c, 15.0, 3, 1.0)
+    poles = oracle_poles(o, 8, 1.0, 0.5, 8)
+    cg = gpu_contour(g, poles, 8, 8)
+    rng = np.random.default_rng(10)
+    f = rng.standard_normal((3,) + shape) + 1j * rng.standard_normal((3,) + shape)
+    opts = hf.default_opts(fp_steps=4, precision=64 if prec == "f64" else 32)
+    out, st = hf.fci_apply(g, cg, dev(f), opts)
+    out = host(out)
+    assert st["fp_steps"] == 8 * 3 * 4
+    tol = 1e-12 if prec == "f64" else 2e-4
+    for r in range(3):
+        ref = OF.fci(o, f[r], poles, steps=4)
+        assert rel(out[r], ref) <= tol, (r, rel(out[r], ref))
+    # chunking the poles gives the same result
+    opts.pole_batch = 3
+    out2, _ = hf.fci_apply(g, cg, dev(f), opts)
+    assert rel(host(out2), out) <= (1e-14 if prec == "f64" else 1e-6)
+
+
+def test_solve_lockstep_fp64(ctx):
+    wl = W.config_constant_32(n=16)
+    o, g = make_ops(ctx, wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
+    poles = oracle_poles(o, 8, 1.0, 0.5, 8)
+    cg = gpu_contour(g, poles, 8, 8)
+    f = wl.rhs[0]
+    for m, its in [(30, 10), (4, 10)]:  # one cycle; several restarts
+        opts = hf.default_opts(fp_steps=3, tol=0.0, max_it=its, restart=m)
+        u, st = hf.solve(g, cg, dev(f[None]), opts=opts)
+        uo, info = OF.solve(o, f, poles, m=m, tol=0.0, max_it=its, steps=3)
+        assert st["its"] == info["its"] == its
+        assert rel(host(u)[0], uo) <= 1e-10, rel(host(u)[0], uo)
+
+
+def residual(o, u, f):
+    A = o.assemble()
+    return np.linalg.norm(o.s * f.ravel() - A @ u.ravel()) / np.linalg.norm(o.s * f.ravel())
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_solve_config_constant_32(ctx, prec):
+    wl = W.config_constant_32(n=32)
+    o, g = make_ops(ctx, wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
+    cg = hf.Contour(g, 8, 1.0, 0.5, 8)
+    opts = hf.default_opts(tol=1e-8, precision=prec, max_it=300)
+    u, st = hf.solve(g, cg, dev(wl.rhs[0][None]), opts=opts)
+    u = host(u)[0]
+    assert st["status"] == "HFCI_OK"
+    assert st["final_relres"] <= 1e-8
+    assert residual(o, u, wl.rhs[0]) <= 1.05e-8  # checked by the oracle's assembled matrix
+
+
+def test_mixed_precision_matches_fp64_solution(ctx):
+    # FP32 sweeps inside FP64 FGMRES: the Krylov wrapper refines to FP64 accuracy, so the
+    # mixed solution converged to 1e-10 agrees with the FP64 one to better than 1e-6
+    wl = W.config_grf_96(n=24, nrhs=2)
+    o, g = make_ops(ctx, wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
+    cg = hf.Contour(g, 12, 1.0, 0.5, 8)
+    f = dev(np.stack(wl.rhs))
+    u64, s64 = hf.solve(g, cg, f, opts=hf.default_opts(tol=1e-11, precision=64, max_it=400))
+    u32, s32 = hf.solve(g, cg, f, opts=hf.default_opts(tol=1e-10, precision=32, max_it=400))
+    u64, u32 = host(u64), host(u32)
+    for r in range(2):
+        assert residual(o, u32[r], wl.rhs[r]) <= 1.05e-10
+        assert residual(o, u64[r], wl.rhs[r]) <= 1.05e-11
+        assert rel(u32[r], u64[r]) <= 1e-6
+
+
+def test_identity_preconditioner_is_gmres(ctx):
+    shape = (6, 6, 6)
+    c = medium(shape, 11)
+    o, g = make_ops(ctx, c, 6.0, 2, 1.0)
+    rng = np.random.default_rng(12)
+    f = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    opts = hf.default_opts(precond=0, tol=0.0, max_it=7)
+    u, st = hf.solve(g, None, dev(f[None]), opts=opts)
+    from oracle import krylov as K
+    uo = K.gmres(lambda v: o.apply(v).ravel(), o.s * f.ravel(), 7)
+    assert rel(host(u)[0].ravel(), uo) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_full_size_apply_sampled(ctx, prec):
+    # 256^3, the size the benchmark times: sampled outputs against the oracle, point by point
+    wl_c = W.layered_medium(256, seed=0)
+    omega = W.omega_for_ppw(float(wl_c.min()), 256, 8.0)
+    g = hf.Operator(ctx, dev(wl_c), 1.0 / 256, omega, 8, 1.0)
+    s, s_h2, kappa = OO.normalisation(wl_c, omega, 1.0 / 256)
+    rng = np.random.default_rng(13)
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    x = (torch.randn(256, 256, 256, dtype=torch.float64, device="cuda")
+         + 1j * torch.randn(256, 256, 256, dtype=torch.float64, device="cuda")).to(dt)
+    shift = -7.1 + 0.5j
+    y = host(hf.apply(g, x, shift))
+    xh = host(x).astype(np.complex128)
+    pts = [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(300)]
+    pts += [(0, 0, 0), (255, 255, 255), (0, 255, 128), (7, 8, 9), (128, 0, 255), (255, 1, 63), (3, 64, 64)]
+    ref = OO.apply_at(xh, kappa, 8, 1.0, s_h2, shift, pts)
+    got = np.array([y[p] for p in pts])
+    tol = 1e-13 if prec == "f64" else 2e-6
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+def test_error_paths(ctx):
+    c = medium((4, 4, 4), 14)
+    o, g = make_ops(ctx, c, 5.0, 1, 1.0)
+    with pytest.raises(hf.HfciError) as e:
+        hf.Contour(g, 0, 1.0, 0.5, 8)
+    assert e.value.status == -1
+    with pytest.raises(hf.HfciError) as e:  # a pole inside the damping band
+        hf.Contour(g, 1, 1.0, 0.5, 4, z=[-0.5j], sigma=[1.0])
+    assert e.value.status == -4
+    bad = dev(-np.ones((4, 4, 4)))
+    with pytest.raises(hf.HfciError):
+        hf.Operator(ctx, bad, 0.25, 5.0, 1, 1.0)
+    x = torch.zeros((4, 4, 4), dtype=torch.complex128, device="cuda")
+    with pytest.raises(hf.HfciError):
+        hf.apply(g, x, 0.0, out=x)  # overlapping buffers
+    cg = hf.Contour(g, 4, 1.0, 0.5, 4)
+    f = dev(np.ones((1, 4, 4, 4), dtype=complex))
+    u, st = hf.solve(g, cg, f, opts=hf.default_opts(tol=1e-14, max_it=2))
+    assert st["status"] == "HFCI_W_NOCONV" and st["its"] == 2

@@ -98,3 +98,12 @@ def test_damping_profile_layer():
     assert D[0, 10, 10] == pytest.approx(1.0)
     assert D[5, 10, 10] == pytest.approx((1 / 6) ** 2)
     assert D[10, 10, 13] == 0.0 and D[10, 10, 14] == pytest.approx((1 / 6) ** 2)
+
+
+def test_pointwise_evaluator_matches_full_apply():
+    op, x = random_setup((7, 5, 6), 9, cells=2, rho2=0.7)
+    pts = [(0, 0, 0), (6, 4, 5), (3, 2, 1), (0, 4, 3), (6, 0, 2)]
+    got = O.apply_at(x, op.kappa, 2, 0.7, op.s_h2, 0.2 + 0.4j, pts)
+    full = op.apply(x, 0.2 + 0.4j)
+    ref = np.array([full[p] for p in pts])
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()

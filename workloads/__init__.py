@@ -57,7 +57,7 @@ def gaussian_random_field(shape, corr_len: float, seed: int) -> np.ndarray:
     kx = np.fft.rfftfreq(nx, d=1.0 / nx) * 2.0 * math.pi
     k2 = kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2
     filt = np.exp(-0.5 * k2 * corr_len**2)
-    g = np.fft.irfftn(np.fft.rfftn(noise) * filt, s=shape)
+    g = np.fft.irfftn(np.fft.rfftn(noise) * filt, s=shape, axes=(0, 1, 2))
     g -= g.mean()
     std = g.std()
     return g / std if std > 0 else g
