@@ -61,24 +61,38 @@ __device__ __forceinline__ void block_sum(double (&acc)[NACC], double* sh) {
   }
 }
 
+// Lanes outside the grid (x >= nx or y >= ny) and the Dirichlet ghosts read a clamped,
+// always-valid address and zero the value with a select, so the loop body has no
+// divergent branches.  Loads for plane z+1 are issued before plane z is computed and
+// stored (one plane of software pipelining): the stores cannot alias-block them.
 template <typename T, class Epi>
-__global__ __launch_bounds__(NT) void zmarch_kernel(GridDesc g, int nzc, int czlen, Epi epi) {
+__global__ __launch_bounds__(NT) void zmarch_kernel(GridDesc g, int nzc, int czlen, int xcd_slab, Epi epi) {
   using T2 = typename V2<T>::t;
+  using Aux = typename Epi::Aux;
   constexpr int NACC = Epi::NACC;
   __shared__ double sh[(NT / 64) * (NACC > 0 ? NACC : 1)];
-  const int x = blockIdx.x * TX + threadIdx.x;
-  const int y = blockIdx.y * TY + threadIdx.y;
-  const int zc = blockIdx.z % nzc;
+  // XCD-aware tile order: consecutive workgroups go round-robin over the 8 XCDs, so
+  // workgroup b is given tile (b % 8) * slab + b / 8 and every XCD walks a contiguous
+  // run of tiles whose y/z neighbours it shares in its own L2.
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int per_sys = gx * gy * nzc;
   const int s = blockIdx.z / nzc;
+  int b = blockIdx.x + gx * (blockIdx.y + gy * (blockIdx.z % nzc));
+  if (xcd_slab > 0) b = (b % 8) * xcd_slab + b / 8;
+  const int bx = b % gx, by = (b / gx) % gy, zc = b / (gx * gy);
+  (void)per_sys;
   if (!epi.active(s)) return;  // uniform over the block
+  const int x = bx * TX + threadIdx.x;
+  const int y = by * TY + threadIdx.y;
   const bool valid = (x < g.nx) && (y < g.ny);
   const int zb = zc * czlen;
   const int ze = min(g.nz, zb + czlen);
   const size_t plane = (size_t)g.nx * (size_t)g.ny;
   const T2* __restrict__ X = epi.in(s);
   const T* __restrict__ K = epi.kappa;
+  const typename Epi::Sys sys = epi.sys(s);
   T sre, sim;
-  epi.shift(s, sre, sim);
+  epi.shift(sys, sre, sim);
   const T sh2 = (T)g.s_h2;
   const T dsc = (T)g.damp_scale;
   const T diag0 = (T)6 * sh2 - sre;
@@ -86,47 +100,69 @@ __global__ __launch_bounds__(NT) void zmarch_kernel(GridDesc g, int nzc, int czl
 #pragma unroll
   for (int k = 0; k < (NACC > 0 ? NACC : 1); ++k) acc[k] = 0.0;
 
-  if (valid) {
+  if (valid && zb < ze) {
     const int dxy = max(layer_depth(x, g.nx, g.damp_cells), layer_depth(y, g.ny, g.damp_cells));
+    const T mxm = x > 0 ? (T)1 : (T)0, mxp = x + 1 < g.nx ? (T)1 : (T)0;
+    const T mym = y > 0 ? (T)1 : (T)0, myp = y + 1 < g.ny ? (T)1 : (T)0;
+    const size_t oxm = x > 0 ? 1 : 0, oxp = x + 1 < g.nx ? 1 : 0;
+    const size_t oym = y > 0 ? (size_t)g.nx : 0, oyp = y + 1 < g.ny ? (size_t)g.nx : 0;
     size_t p = (size_t)x + (size_t)g.nx * (size_t)y + plane * (size_t)zb;
-    const T2 zero = {(T)0, (T)0};
-    T2 prev = zero, cur = X[p];
-    if (zb > 0) prev = X[p - plane];
+    // plane zb: centre, z-1 neighbour, in-plane neighbours, kappa, epilogue inputs
+    T2 prev = X[zb > 0 ? p - plane : p];
+    if (zb == 0) prev = T2{(T)0, (T)0};
+    T2 cur = X[p];
+    T2 nxt = X[zb + 1 < g.nz ? p + plane : p];
+    T2 xm = X[p - oxm], xp = X[p + oxp], ym = X[p - oym], yp = X[p + oyp];
+    T kap = K[p];
+    Aux aux = epi.load_aux(sys, s, p);
+#pragma unroll 2
     for (int z = zb; z < ze; ++z, p += plane) {
-      T2 next = zero, xm = zero, xp = zero, ym = zero, yp = zero;
-      if (z + 1 < g.nz) next = X[p + plane];
-      if (x > 0) xm = X[p - 1];
-      if (x + 1 < g.nx) xp = X[p + 1];
-      if (y > 0) ym = X[p - g.nx];
-      if (y + 1 < g.ny) yp = X[p + g.nx];
+      // ---- issue the loads of plane z+1 (clamped to plane z on the last plane) ----
+      const bool more = z + 1 < ze;
+      const size_t q1 = more ? p + plane : p;
+      const T2 nn = X[z + 2 < g.nz ? p + 2 * plane : q1];
+      const T2 xm1 = X[q1 - oxm], xp1 = X[q1 + oxp], ym1 = X[q1 - oym], yp1 = X[q1 + oyp];
+      const T kap1 = K[q1];
+      const Aux aux1 = epi.load_aux(sys, s, q1);
+      // ---- compute and store plane z ----
+      const T2 zn = (z + 1 < g.nz) ? nxt : T2{(T)0, (T)0};
       const int d = max(dxy, layer_depth(z, g.nz, g.damp_cells));
-      const T dre = diag0 - K[p];
+      const T dre = diag0 - kap;
       const T dim = -((T)(d * d) * dsc + sim);
-      const T nbr = ((prev.x + next.x) + (xm.x + xp.x)) + (ym.x + yp.x);
-      const T nbi = ((prev.y + next.y) + (xm.y + xp.y)) + (ym.y + yp.y);
+      const T nbr = ((prev.x + zn.x) + (mxm * xm.x + mxp * xp.x)) + (mym * ym.x + myp * yp.x);
+      const T nbi = ((prev.y + zn.y) + (mxm * xm.y + mxp * xp.y)) + (mym * ym.y + myp * yp.y);
       T2 Sx;
       Sx.x = dre * cur.x - dim * cur.y - sh2 * nbr;
       Sx.y = dre * cur.y + dim * cur.x - sh2 * nbi;
-      epi.point(s, p, Sx, cur, acc);
+      epi.point(sys, s, p, Sx, cur, aux, acc);
+      // ---- rotate ----
       prev = cur;
-      cur = next;
+      cur = zn;
+      nxt = nn;
+      xm = xm1; xp = xp1; ym = ym1; yp = yp1;
+      kap = kap1;
+      aux = aux1;
     }
   }
   if constexpr (NACC > 0) {
     block_sum<NACC>(acc, sh);
     if (threadIdx.x == 0 && threadIdx.y == 0) {
-      const int nblk = gridDim.x * gridDim.y * nzc;
-      const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * zc);
+      const int nblk = gx * gy * nzc;
+      const int blk = bx + gx * (by + gy * zc);
 #pragma unroll
       for (int k = 0; k < NACC; ++k) epi.partial_out(s, k, nblk, blk, acc[k]);
     }
   }
 }
 
+struct NoAux {};
+
 template <typename T>
 struct EpiApply {
   using T2 = typename V2<T>::t;
   static constexpr int NACC = 0;
+  struct Sys {};
+  using Aux = NoAux;
   const T2* x;
   T2* y;
   const T* kappa;
@@ -134,8 +170,10 @@ struct EpiApply {
   T sre, sim;
   __device__ bool active(int) const { return true; }
   __device__ const T2* in(int s) const { return x + (size_t)s * n; }
-  __device__ void shift(int, T& re, T& im) const { re = sre; im = sim; }
-  __device__ void point(int s, size_t p, const T2& Sx, const T2&, double*) const {
+  __device__ Sys sys(int) const { return Sys{}; }
+  __device__ void shift(const Sys&, T& re, T& im) const { re = sre; im = sim; }
+  __device__ Aux load_aux(const Sys&, int, size_t) const { return Aux{}; }
+  __device__ void point(const Sys&, int s, size_t p, const T2& Sx, const T2&, const Aux&, double*) const {
     y[(size_t)s * n + p] = Sx;
   }
   __device__ void partial_out(int, int, int, int, double) const {}
@@ -145,33 +183,48 @@ template <typename T, bool FIRST>
 struct EpiStage {
   using T2 = typename V2<T>::t;
   static constexpr int NACC = FIRST ? 1 : 0;
+  struct Sys {
+    T cBr, cBi, alr, ali, gar, gai, z0r, z0i;
+    double zzr, zzi;
+    const T2* y;
+    const T2* f;
+    T2* out;
+  };
+  struct Aux {
+    T2 y, f;
+  };
   StageArgs<T2> a;
   const T* kappa;
   size_t n;
   __device__ bool active(int s) const { return a.active[s] != 0; }
   __device__ const T2* in(int s) const { return a.win + (size_t)s * n; }
-  __device__ void shift(int s, T& re, T& im) const {
-    const int pole = (a.sys0 + s) / a.nrhs;
-    re = (T)a.poles[pole].z0_re;
-    im = (T)a.poles[pole].z0_im;
-  }
-  __device__ void point(int s, size_t p, const T2& Sx, const T2& cur, double* acc) const {
+  __device__ Sys sys(int s) const {
     const int gs = a.sys0 + s;
     const int pole = gs / a.nrhs, r = gs % a.nrhs;
     const StageCoef c = a.coef[pole * a.q + a.m];
-    const T2 yv = FIRST ? cur : a.y[(size_t)s * n + p];
-    const T2 fv = a.f[(size_t)r * n + p];
+    const PoleDev pd = a.poles[pole];
+    return Sys{(T)c.cB_re, (T)c.cB_im, (T)c.al_re, (T)c.al_im, (T)c.ga_re, (T)c.ga_im, (T)pd.z0_re,
+               (T)pd.z0_im, pd.zz_re, pd.zz_im, a.y + (size_t)s * n, a.f + (size_t)r * n, a.wout + (size_t)s * n};
+  }
+  __device__ void shift(const Sys& c, T& re, T& im) const { re = c.z0r; im = c.z0i; }
+  __device__ Aux load_aux(const Sys& c, int, size_t p) const {
+    Aux x;
+    if constexpr (FIRST) x.y = T2{(T)0, (T)0};
+    else x.y = c.y[p];
+    x.f = c.f[p];
+    return x;
+  }
+  __device__ void point(const Sys& c, int, size_t p, const T2& Sx, const T2& cur, const Aux& ax, double* acc) const {
+    const T2 yv = FIRST ? cur : ax.y;
+    const T2 fv = ax.f;
     T2 o;
-    o.x = (T)c.cB_re * Sx.x - (T)c.cB_im * Sx.y + (T)c.al_re * yv.x - (T)c.al_im * yv.y +
-          (T)c.ga_re * fv.x - (T)c.ga_im * fv.y;
-    o.y = (T)c.cB_re * Sx.y + (T)c.cB_im * Sx.x + (T)c.al_re * yv.y + (T)c.al_im * yv.x +
-          (T)c.ga_re * fv.y + (T)c.ga_im * fv.x;
-    a.wout[(size_t)s * n + p] = o;
+    o.x = c.cBr * Sx.x - c.cBi * Sx.y + c.alr * yv.x - c.ali * yv.y + c.gar * fv.x - c.gai * fv.y;
+    o.y = c.cBr * Sx.y + c.cBi * Sx.x + c.alr * yv.y + c.ali * yv.x + c.gar * fv.y + c.gai * fv.x;
+    c.out[p] = o;
     if constexpr (FIRST) {
       // r = f - (A - z) y = f - (A - z0) y + (z - z0) y
-      const PoleDev pd = a.poles[pole];
-      const double rr = (double)fv.x - (double)Sx.x + pd.zz_re * (double)yv.x - pd.zz_im * (double)yv.y;
-      const double ri = (double)fv.y - (double)Sx.y + pd.zz_re * (double)yv.y + pd.zz_im * (double)yv.x;
+      const double rr = (double)fv.x - (double)Sx.x + c.zzr * (double)yv.x - c.zzi * (double)yv.y;
+      const double ri = (double)fv.y - (double)Sx.y + c.zzr * (double)yv.y + c.zzi * (double)yv.x;
       acc[0] += rr * rr + ri * ri;
     }
   }
@@ -184,6 +237,12 @@ template <typename T>
 struct EpiDstep {
   using T2 = typename V2<T>::t;
   static constexpr int NACC = 3;
+  struct Sys {
+    const T2* f;
+  };
+  struct Aux {
+    T2 f;
+  };
   const T2* w;
   const T2* f;
   const T* kappa;
@@ -191,10 +250,11 @@ struct EpiDstep {
   size_t n;
   __device__ bool active(int) const { return true; }
   __device__ const T2* in(int s) const { return w + (size_t)s * n; }
-  __device__ void shift(int, T& re, T& im) const { re = (T)0; im = (T)0; }
-  __device__ void point(int s, size_t p, const T2& Sx, const T2&, double* acc) const {
-    const T2 fv = f[(size_t)s * n + p];
-    const double ar = Sx.x, ai = Sx.y, fr = fv.x, fi = fv.y;
+  __device__ Sys sys(int s) const { return Sys{f + (size_t)s * n}; }
+  __device__ void shift(const Sys&, T& re, T& im) const { re = (T)0; im = (T)0; }
+  __device__ Aux load_aux(const Sys& c, int, size_t p) const { return Aux{c.f[p]}; }
+  __device__ void point(const Sys&, int, size_t, const T2& Sx, const T2&, const Aux& ax, double* acc) const {
+    const double ar = Sx.x, ai = Sx.y, fr = ax.f.x, fi = ax.f.y;
     acc[0] += ar * fr + ai * fi;  // Re conj(Aw) f
     acc[1] += ar * fi - ai * fr;  // Im conj(Aw) f
     acc[2] += ar * ar + ai * ai;  // |Aw|^2
@@ -206,6 +266,10 @@ struct EpiDstep {
 
 struct EpiResidual {
   static constexpr int NACC = 1;
+  struct Sys {};
+  struct Aux {
+    double2 b;
+  };
   const double2* u;
   const double2* b;
   double2* r;
@@ -213,12 +277,14 @@ struct EpiResidual {
   double* partial;
   __device__ bool active(int) const { return true; }
   __device__ const double2* in(int) const { return u; }
-  __device__ void shift(int, double& re, double& im) const { re = 0.0; im = 0.0; }
-  __device__ void point(int, size_t p, const double2& Sx, const double2&, double* acc) const {
-    const double2 bv = b[p];
+  __device__ Sys sys(int) const { return Sys{}; }
+  __device__ void shift(const Sys&, double& re, double& im) const { re = 0.0; im = 0.0; }
+  __device__ Aux load_aux(const Sys&, int, size_t p) const { return Aux{b[p]}; }
+  __device__ void point(const Sys&, int, size_t p, const double2& Sx, const double2&, const Aux& ax,
+                        double* acc) const {
     double2 o;
-    o.x = bv.x - Sx.x;
-    o.y = bv.y - Sx.y;
+    o.x = ax.b.x - Sx.x;
+    o.y = ax.b.y - Sx.y;
     r[p] = o;
     acc[0] += o.x * o.x + o.y * o.y;
   }
@@ -227,7 +293,7 @@ struct EpiResidual {
 
 struct Shape {
   dim3 grid;
-  int nzc, czlen;
+  int nzc, czlen, xcd_slab;
 };
 
 Shape shape_for(const GridDesc& g, int nsys) {
@@ -239,6 +305,8 @@ Shape shape_for(const GridDesc& g, int nsys) {
   sh.czlen = cz;
   sh.nzc = (g.nz + cz - 1) / cz;
   sh.grid = dim3(gx, gy, sh.nzc * nsys);
+  const int per_sys = gx * gy * sh.nzc;
+  sh.xcd_slab = (per_sys % 8 == 0 && per_sys >= 64) ? per_sys / 8 : 0;
   return sh;
 }
 
@@ -246,7 +314,7 @@ template <typename T, class Epi>
 void run(hipStream_t st, const GridDesc& g, int nsys, const Epi& epi) {
   if (nsys <= 0) return;
   const Shape sh = shape_for(g, nsys);
-  hipLaunchKernelGGL((zmarch_kernel<T, Epi>), sh.grid, dim3(TX, TY), 0, st, g, sh.nzc, sh.czlen, epi);
+  hipLaunchKernelGGL((zmarch_kernel<T, Epi>), sh.grid, dim3(TX, TY), 0, st, g, sh.nzc, sh.czlen, sh.xcd_slab, epi);
 }
 
 }  // namespace
