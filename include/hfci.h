@@ -56,11 +56,12 @@ typedef enum {
 } hfci_status;
 
 enum { HFCI_F32 = 32, HFCI_F64 = 64 };
-enum { HFCI_PRECOND_NONE = 0, HFCI_PRECOND_FCI = 1 };
+enum { HFCI_PRECOND_NONE = 0, HFCI_PRECOND_FCI = 1, HFCI_PRECOND_LEARNED = 2 };
 
 typedef struct hfci_ctx hfci_ctx;
 typedef struct hfci_op hfci_op;
 typedef struct hfci_contour hfci_contour;
+typedef struct hfci_net hfci_net;
 
 /* Options of the FCI preconditioner and the FGMRES wrapper (Sec. 2, Alg. 1). */
 typedef struct {
@@ -82,6 +83,16 @@ typedef struct {
   int pole_batch;       /* poles advanced together per launch (x every RHS);
                            0 = all J                                              */
   int verbose;          /* 1: one line per FGMRES cycle on stderr               */
+  /* learned preconditioner (precond = HFCI_PRECOND_LEARNED): z_j = net(v_j) is kept
+     when ||v_j - A z_j|| <= learned_tau ||v_j||, otherwise z_j = FCI(v_j) (fallback,
+     needs the contour).                                           default 0.9 */
+  hfci_net* net;
+  double learned_tau;
+  /* training-pair harvest: each Arnoldi step of each RHS appends (v_j, FCI(v_j)) as
+     complex64 to the DEVICE arrays harvest_v / harvest_z (harvest_cap vectors of n). */
+  int harvest_cap;
+  void* harvest_v;
+  void* harvest_z;
 } hfci_solve_opts;
 
 /* Counters of one call. */
@@ -95,6 +106,10 @@ typedef struct {
   double time_fci_ms;       /* device time in the preconditioner                 */
   double time_arnoldi_ms;   /* device time in matvec/CGS2/update                 */
   double time_total_ms;     /* wall time of the call                             */
+  int harvested;            /* pairs appended to the harvest arrays              */
+  int learned_accepted;     /* Arnoldi steps that kept the network's output      */
+  int learned_fallbacks;    /* Arnoldi steps that fell back to FCI               */
+  double time_net_ms;       /* device time in the network                        */
 } hfci_stats;
 
 /* Per-kernel timing collected by hfci_ctx_profile (device time from HIP events
@@ -206,6 +221,68 @@ hfci_status hfci_fci_apply(const hfci_op* op, const hfci_contour* c,
 hfci_status hfci_solve(const hfci_op* op, const hfci_contour* c,
                        const hfci_solve_opts* opts, int nrhs,
                        const hfci_c128* f, hfci_c128* u, hfci_stats* stats);
+
+/* ---- learned preconditioner (not part of the paper) -------------------------
+ * A 3-level 3D U-Net (16/32/64 channels, 3x3x3 kernels, ReLU, 2x2x2 average
+ * pooling, nearest up-sampling, skip concatenation, 1x1x1 head 16 -> 2) on
+ * channels-last BF16 activations with FP32 accumulation on the matrix cores;
+ * FP32 master weights trained with Adam.  Input channels: (Re r, Im r)/rms(r) and
+ * omega^2 h^2/c^2; output: the correction divided by rms(r).  Grid sizes must be
+ * multiples of 4.  Parameters are one FP32 array: per layer (c1a, c1b, c2a, c2b,
+ * c3a, c3b, d2a, d2b, d1a, d1b) weights [27][Cout][Cin] then biases [Cout]
+ * (c1a has Cin = 16: three real input channels, the rest must stay zero), then
+ * the head weights [2][16] and biases [2]. */
+typedef struct {
+  size_t size;                 /* = sizeof(hfci_net_desc) */
+  unsigned long long seed;     /* weight initialisation */
+} hfci_net_desc;
+
+typedef struct {
+  size_t size;                 /* = sizeof(hfci_train_desc) */
+  int nx, ny, nz;              /* grid of the pairs (multiples of 4 >= crop) */
+  int npairs;
+  const void* v;               /* DEVICE complex64 [npairs][n] residuals            */
+  const void* e;               /* DEVICE complex64 [npairs][n] corrections          */
+  const float* kch;            /* DEVICE float [nmedia][n]: omega^2 h^2 / c^2       */
+  int nmedia;
+  const int* medium_of_pair;   /* HOST int [npairs]: medium index of each pair, each
+                                  in [0, nmedia) (checked)                          */
+  int crop;                    /* training crop edge (multiple of 4)                */
+  int steps;                   /* Adam steps (one crop each)                        */
+  float lr, lr_min;            /* cosine schedule from lr to lr_min                 */
+  int phase_aug;               /* 1: random global phase per step                   */
+  unsigned long long seed;
+  int log_every;               /* loss readback period (0 = never)                  */
+  int verbose;                 /* 1: print the readbacks on stderr                  */
+  double* loss_curve;          /* HOST array for the readbacks, or NULL             */
+  int loss_curve_cap;
+} hfci_train_desc;
+
+hfci_status hfci_net_create(hfci_ctx* ctx, const hfci_net_desc* desc, hfci_net** out);
+void hfci_net_destroy(hfci_net* net);
+/* Number of FP32 parameters; copy them to / from HOST arrays. */
+long long hfci_net_param_count(const hfci_net* net);
+hfci_status hfci_net_get_params(const hfci_net* net, float* host);
+hfci_status hfci_net_set_params(hfci_net* net, const float* host);
+hfci_status hfci_net_get_grads(const hfci_net* net, float* host);
+/* Raw evaluation: x16 DEVICE bf16 [nz][ny][nx][16] (channels 3..15 zero), out DEVICE
+ * float [nz][ny][nx][2]. */
+hfci_status hfci_net_eval(hfci_net* net, int nx, int ny, int nz, const uint16_t* x16, float* out);
+/* One forward/backward pass on (x16, target float [n][2]) with loss
+ * ||out - target||^2 / ||target||^2; update != 0 also takes an Adam step with lr.
+ * *loss receives the loss (HOST). */
+hfci_status hfci_net_train_step(hfci_net* net, int nx, int ny, int nz, const uint16_t* x16,
+                                const float* target, float lr, int update, double* loss);
+/* Training loop over random crops of the pairs; returns the last loss read back. */
+hfci_status hfci_net_train(hfci_net* net, const hfci_train_desc* desc, double* final_loss);
+/* The preconditioner itself: z_k = rms(r_k) N(r_k / rms(r_k)) for complex128 DEVICE
+ * vectors on op's grid (dims multiples of 4). */
+hfci_status hfci_net_apply(hfci_net* net, const hfci_op* op, int nvec, const hfci_c128* r, hfci_c128* z);
+/* omega^2 h^2 / c^2 of op as a DEVICE float array of n (the medium input channel). */
+hfci_status hfci_op_medium_channel(const hfci_op* op, float* out);
+/* Parameters and Adam state to / from a file (little-endian, with a header). */
+hfci_status hfci_net_save(const hfci_net* net, const char* path);
+hfci_status hfci_net_load(hfci_net* net, const char* path);
 
 #ifdef __cplusplus
 }

@@ -26,4 +26,4 @@ using contour integration and polynomial preconditioning") step by step:
 
 Parity status of each function is stated in its module header.
 """
-from . import operator, contour, polynomial, fixed_point, fci, krylov  # noqa: F401
+from . import operator, contour, polynomial, fixed_point, fci, krylov, conv  # noqa: F401

@@ -3,5 +3,5 @@
 The compute path lives in libhfci.so (HIP for gfx950, C ABI in include/hfci.h);
 `hfci` is its thin ctypes binding.
 """
-from .hfci import (Context, Contour, HfciError, Operator, SolveOpts, Stats, apply, default_opts,  # noqa: F401
-                   fci_apply, load_library, shifted_solve, solve, LIB_PATH, EXPORTED)
+from .hfci import (Context, Contour, HfciError, Net, Operator, SolveOpts, Stats, apply, default_opts,  # noqa: F401
+                   fci_apply, load_library, medium_channel, shifted_solve, solve, LIB_PATH, EXPORTED)

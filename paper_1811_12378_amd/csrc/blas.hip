@@ -89,6 +89,20 @@ __global__ __launch_bounds__(NT) void multiaxpy_kernel(double2* __restrict__ w, 
   }
 }
 
+__global__ __launch_bounds__(NT) void diffnorm2_kernel(const double2* __restrict__ a, const double2* __restrict__ b,
+                                                       size_t n, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double v[1] = {0.0};
+  const size_t stride = (size_t)gridDim.x * NT;
+  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < n; p += stride) {
+    const double2 x = a[p], y = b[p];
+    const double dr = x.x - y.x, di = x.y - y.y;
+    v[0] += dr * dr + di * di;
+  }
+  block_sum_n<1>(v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
+}
+
 template <typename T2>
 __global__ __launch_bounds__(NT) void norm2_kernel(const T2* __restrict__ x, size_t n,
                                                    double* __restrict__ partial) {
@@ -298,6 +312,10 @@ void launch_norm2_partial(hipStream_t st, const void* x, bool f32, size_t n, dou
     hipLaunchKernelGGL(norm2_kernel<float2>, dim3(blas_blocks(n)), dim3(NT), 0, st, (const float2*)x, n, partial);
   else
     hipLaunchKernelGGL(norm2_kernel<double2>, dim3(blas_blocks(n)), dim3(NT), 0, st, (const double2*)x, n, partial);
+}
+
+void launch_diffnorm2_partial(hipStream_t st, const double2* a, const double2* b, size_t n, double* partial) {
+  hipLaunchKernelGGL(diffnorm2_kernel, dim3(blas_blocks(n)), dim3(NT), 0, st, a, b, n, partial);
 }
 
 void launch_scale_inv(hipStream_t st, double2* v, const double2* w, size_t n, const double* nrm2) {

@@ -16,6 +16,8 @@ constexpr size_t kPinnedInts = 65536;
 constexpr size_t kPinnedDbls = 65536;
 }  // namespace
 
+void set_last_error(const char* msg) { g_err = msg; }
+
 void throw_hip(hipError_t e, const char* what, const char* file, int line) {
   const char* base = std::strrchr(file, '/');
   std::string msg = std::string(hipGetErrorString(e)) + " in " + what + " (" + (base ? base + 1 : file) + ":" +
@@ -139,7 +141,13 @@ static void check_opts(const hfci_solve_opts* o) {
   HFCI_REQUIRE(o->fp_steps > 0 || (o->fp_reduce > 1.0 && o->fp_max_steps >= 1),
                "adaptive stopping needs fp_reduce > 1 and fp_max_steps >= 1");
   HFCI_REQUIRE(o->k_in == 0, "k_in > 0 (Alg. 1 step 4) is not supported by this build");
-  HFCI_REQUIRE(o->precond == HFCI_PRECOND_FCI || o->precond == HFCI_PRECOND_NONE, "unknown precond");
+  HFCI_REQUIRE(o->precond == HFCI_PRECOND_FCI || o->precond == HFCI_PRECOND_NONE ||
+                   o->precond == HFCI_PRECOND_LEARNED,
+               "unknown precond");
+  HFCI_REQUIRE(o->precond != HFCI_PRECOND_LEARNED || (o->net != nullptr && o->learned_tau > 0.0),
+               "the learned preconditioner needs opts->net and learned_tau > 0");
+  HFCI_REQUIRE(o->harvest_cap >= 0 && (o->harvest_cap == 0 || (o->harvest_v && o->harvest_z)),
+               "harvest_cap > 0 needs harvest_v and harvest_z");
   HFCI_REQUIRE(o->pole_batch >= 0, "pole_batch must be >= 0");
 }
 
@@ -147,9 +155,6 @@ static void check_opts(const hfci_solve_opts* o) {
 
 using namespace hfci;
 
-struct hfci_ctx : public hfci::Ctx {};
-struct hfci_op : public hfci::Op {};
-struct hfci_contour : public hfci::Contour {};
 
 extern "C" {
 
@@ -168,6 +173,11 @@ void hfci_default_opts(hfci_solve_opts* o) {
   o->precond = HFCI_PRECOND_FCI;
   o->pole_batch = 0;
   o->verbose = 0;
+  o->net = nullptr;
+  o->learned_tau = 0.9;
+  o->harvest_cap = 0;
+  o->harvest_v = nullptr;
+  o->harvest_z = nullptr;
 }
 
 const char* hfci_last_error(void) { return g_err.c_str(); }
@@ -504,12 +514,16 @@ hfci_status hfci_solve(const hfci_op* op, const hfci_contour* c, const hfci_solv
   HFCI_API_BEGIN
   HFCI_REQUIRE(op && f && u, "NULL argument");
   check_opts(o);
-  if (o->precond == HFCI_PRECOND_FCI) {
-    HFCI_REQUIRE(c != nullptr, "FCI preconditioning needs a contour");
+  if (o->precond == HFCI_PRECOND_FCI || o->precond == HFCI_PRECOND_LEARNED) {
+    HFCI_REQUIRE(c != nullptr, "FCI preconditioning (or its use as the learned fallback) needs a contour");
     if (c->op != op) throw Error(HFCI_E_STATE, "contour was created for another operator");
   }
   HFCI_REQUIRE(nrhs >= 1 && nrhs <= 64, "nrhs must be in [1, 64]");
   HFCI_REQUIRE(!stats || stats->size == sizeof(hfci_stats), "stats->size mismatch");
+  if (o->precond == HFCI_PRECOND_LEARNED)
+    HFCI_REQUIRE(op->g.nx % 4 == 0 && op->g.ny % 4 == 0 && op->g.nz % 4 == 0 && op->g.nx >= 4 && op->g.ny >= 4 &&
+                     op->g.nz >= 4,
+                 "the learned preconditioner needs grid sizes that are multiples of 4");
   DeviceGuard dg(op->ctx->device);
   const hfci_status st = fgmres_solve(*op, c, *o, nrhs, (const double2*)f, (double2*)u, stats);
   HFCI_HIP(hipGetLastError());

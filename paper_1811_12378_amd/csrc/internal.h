@@ -12,6 +12,7 @@
 
 #include "../../include/hfci.h"
 #include "kernels.h"
+#include "netkern.h"
 
 namespace hfci {
 
@@ -117,6 +118,64 @@ struct Contour {
   PoleDev* d_poles = nullptr;
 };
 
+// ---- net.cpp: the learned preconditioner ----
+struct TrainData {
+  int nx, ny, nz, npairs;
+  const float2* v;            // [npairs][n] residuals (complex64, device)
+  const float2* e;            // [npairs][n] corrections (complex64, device)
+  const float* kch;           // [nmedia][n] omega^2 h^2 / c^2 (device)
+  const int* medium_of_pair;  // [npairs] (host)
+};
+struct TrainOpts {
+  int crop, steps, phase_aug, log_every, verbose;
+  float lr, lr_min;
+  unsigned long long seed;
+};
+
+struct Net {
+  struct Layer {
+    int cin = 0, cout = 0;
+    long w_off = 0, b_off = 0;
+  };
+  struct Acts {
+    Dims d1, d2, d3;
+    long V1, V2, V3;
+    uint16_t *a1, *cat1, *p1, *a2, *cat2, *p2, *a3, *b3, *g2, *dd2, *g1, *dd1;
+    float* o;
+    uint16_t *gd1 = nullptr, *gz = nullptr, *gg1 = nullptr, *gcat1 = nullptr, *gd2 = nullptr, *gg2 = nullptr,
+             *gcat2 = nullptr, *gb3 = nullptr, *ga3 = nullptr, *gp2 = nullptr, *ge2 = nullptr, *ga2 = nullptr,
+             *gp1 = nullptr, *ge1 = nullptr, *ga1 = nullptr;
+    float* dout = nullptr;
+    float* part = nullptr;
+  };
+  Ctx* ctx;
+  int device;
+  Layer layers[10];
+  long head_off = 0, nparam = 0;
+  float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;  // FP32 master, grads, Adam moments
+  uint16_t *wb = nullptr, *wt = nullptr;  // BF16 copies; wt = tap-flipped, Cin/Cout-transposed
+  int step = 0;
+
+  Net(Ctx* c, unsigned long long seed);
+  ~Net();
+  void set_params(const float* host);
+  void get_params(float* host) const;
+  void get_grads(float* host) const;
+  void zero_moments();
+  void refresh_bf16();
+  Acts acts(Dims d, bool backward);
+  void forward(Dims d, const uint16_t* x16, const Acts& a);
+  void backward(const uint16_t* x16, const Acts& a);
+  double train_step(Dims d, const uint16_t* x16, const float* target, float lr, bool update, bool read_loss);
+  void eval(Dims d, const uint16_t* x16, float* out);
+  void apply(const Op& op, int nvec, const double2* r, double2* z);
+  double train(const TrainData& td, const TrainOpts& to, std::vector<double>& curve);
+
+ private:
+  void conv(const Acts& a, int l, Dims d, View in, View out, bool relu);
+  void conv_back(const Acts& a, int l, Dims d, View in, View post, View dh, View din);
+};
+
 // ---- params.cpp ----
 void op_rectangle(Op& op);
 void contour_poles(int J, double t, double eps, double rho2, std::vector<cd>& z, std::vector<cd>& sigma);
@@ -137,5 +196,16 @@ void fci_apply(const Op& op, const Contour& c, const hfci_solve_opts& o, int nrh
                double2* out, FciStats& st);
 hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& o, int nrhs,
                          const double2* f, double2* u, hfci_stats* stats);
+void launch_diffnorm2_partial(hipStream_t st, const double2* a, const double2* b, size_t n, double* partial);
+
+void set_last_error(const char* msg);
 
 }  // namespace hfci
+
+// The opaque C handles are the internal structures.
+struct hfci_ctx : public hfci::Ctx {};
+struct hfci_op : public hfci::Op {};
+struct hfci_contour : public hfci::Contour {};
+struct hfci_net : public hfci::Net {
+  using hfci::Net::Net;
+};

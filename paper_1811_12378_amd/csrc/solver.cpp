@@ -302,6 +302,8 @@ hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& 
   std::vector<int> kr(nrhs, 0);
   int its = 0, cycles = 0;
   long long res_mv = 0;
+  int harvested = 0, n_accept = 0, n_fallback = 0;
+  double t_net = 0.0;
   FciStats fst;
   double t_fci = 0, t_arn = 0;
   Timer tm(s);
@@ -381,7 +383,39 @@ hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& 
         fin = stage_in;
         fout = stage_out;
       }
-      if (c && o.precond == HFCI_PRECOND_FCI) {
+      if (o.precond == HFCI_PRECOND_LEARNED) {
+        // the network proposes z = N(v); FCI judges it by the residual ||v - A z|| / ||v||
+        // (v has unit norm) and replaces the rejected proposals
+        Timer tn(s);
+        tn.start();
+        o.net->apply(op, nl, fin, fout);
+        double2* wt = (double2*)ctx.ws.get("gm_wjudge", n * sizeof(double2));
+        double* jd = (double*)ctx.ws.get("gm_judge", (size_t)nl * sizeof(double));
+        for (int k = 0; k < nl; ++k) {
+          Launch<double2>::apply(s, op.g, op.kappa64, 0.0, 0.0, 1, fout + k * n, wt);
+          launch_diffnorm2_partial(s, fin + k * n, wt, n, part);
+          launch_reduce(s, part, nbb, 1, jd + k);
+        }
+        fst.matvecs += nl;
+        double* jh = ctx.pinned_dbl + kPinnedFciOffset + 1024;
+        HFCI_HIP(hipMemcpyAsync(jh, jd, nl * sizeof(double), hipMemcpyDeviceToHost, s));
+        t_net += tn.stop_ms();
+        std::vector<int> rej;
+        for (int k = 0; k < nl; ++k)
+          if (!(std::sqrt(jh[k]) <= o.learned_tau)) rej.push_back(k);
+        n_accept += nl - (int)rej.size();
+        n_fallback += (int)rej.size();
+        if (!rej.empty()) {
+          const int nr = (int)rej.size();
+          double2* rin = (double2*)ctx.ws.get("gm_rej_in", (size_t)nr * n * sizeof(double2));
+          double2* rout = (double2*)ctx.ws.get("gm_rej_out", (size_t)nr * n * sizeof(double2));
+          for (int k = 0; k < nr; ++k)
+            HFCI_HIP(hipMemcpyAsync(rin + k * n, fin + rej[k] * n, n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+          fci_apply(op, *c, o, nr, rin, rout, fst);
+          for (int k = 0; k < nr; ++k)
+            HFCI_HIP(hipMemcpyAsync(fout + rej[k] * n, rout + k * n, n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        }
+      } else if (c && o.precond == HFCI_PRECOND_FCI) {
         fci_apply(op, *c, o, nl, fin, fout, fst);
       } else {
         HFCI_HIP(hipMemcpyAsync(fout, fin, (size_t)nl * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
@@ -390,6 +424,13 @@ hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& 
         for (int k = 0; k < nl; ++k)
           HFCI_HIP(hipMemcpyAsync(Z + (size_t)j * vs + live[k] * n, stage_out + k * n, n * sizeof(double2),
                                   hipMemcpyDeviceToDevice, s));
+      // training-pair harvest: (v_j, z_j) as complex64
+      for (int r : live) {
+        if (harvested >= o.harvest_cap) break;
+        launch_convert_64_to_32(s, (float2*)o.harvest_v + (size_t)harvested * n, V + (size_t)j * vs + r * n, n);
+        launch_convert_64_to_32(s, (float2*)o.harvest_z + (size_t)harvested * n, Z + (size_t)j * vs + r * n, n);
+        ++harvested;
+      }
       t_fci += tm.stop_ms();
       // ---- Arnoldi: w = A z_j, CGS2 against V[0..j], normalise ----
       tm.start();
@@ -477,6 +518,10 @@ hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& 
     for (double v : relres) mx = std::max(mx, v);
     stats->final_relres = mx;
     stats->time_fci_ms = t_fci;
+    stats->harvested = harvested;
+    stats->learned_accepted = n_accept;
+    stats->learned_fallbacks = n_fallback;
+    stats->time_net_ms = t_net;
     stats->time_arnoldi_ms = t_arn;
     stats->time_total_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_wall0).count();

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libhfci.so")
 
 HFCI_OK, HFCI_W_NOCONV = 0, 1
 HFCI_F32, HFCI_F64 = 32, 64
-HFCI_PRECOND_NONE, HFCI_PRECOND_FCI = 0, 1
+HFCI_PRECOND_NONE, HFCI_PRECOND_FCI, HFCI_PRECOND_LEARNED = 0, 1, 2
 
 STATUS_NAMES = {0: "HFCI_OK", 1: "HFCI_W_NOCONV", -1: "HFCI_E_ARG", -2: "HFCI_E_HIP", -3: "HFCI_E_OOM",
                 -4: "HFCI_E_CONTOUR", -5: "HFCI_E_NUMERIC", -6: "HFCI_E_STATE"}
@@ -29,7 +29,10 @@ STATUS_NAMES = {0: "HFCI_OK", 1: "HFCI_W_NOCONV", -1: "HFCI_E_ARG", -2: "HFCI_E_
 EXPORTED = ["hfci_default_opts", "hfci_last_error", "hfci_version", "hfci_ctx_create", "hfci_ctx_destroy",
             "hfci_op_create", "hfci_op_destroy", "hfci_op_info", "hfci_apply", "hfci_contour_create",
             "hfci_contour_destroy", "hfci_contour_get", "hfci_shifted_solve", "hfci_fci_apply", "hfci_solve",
-            "hfci_ctx_profile", "hfci_ctx_profile_read"]
+            "hfci_ctx_profile", "hfci_ctx_profile_read", "hfci_net_create", "hfci_net_destroy",
+            "hfci_net_param_count", "hfci_net_get_params", "hfci_net_set_params", "hfci_net_get_grads",
+            "hfci_net_eval", "hfci_net_train_step", "hfci_net_train", "hfci_net_apply", "hfci_op_medium_channel",
+            "hfci_net_save", "hfci_net_load"]
 PROF_CLASSES = ["fp_stage", "fp_stage_first", "apply"]
 
 
@@ -51,17 +54,35 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("size", ctypes.c_size_t), ("precision", ctypes.c_int), ("restart", ctypes.c_int),
                 ("max_it", ctypes.c_int), ("tol", ctypes.c_double), ("fp_steps", ctypes.c_int),
                 ("fp_reduce", ctypes.c_double), ("fp_max_steps", ctypes.c_int), ("k_in", ctypes.c_int),
-                ("precond", ctypes.c_int), ("pole_batch", ctypes.c_int), ("verbose", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("pole_batch", ctypes.c_int), ("verbose", ctypes.c_int),
+                ("net", ctypes.c_void_p), ("learned_tau", ctypes.c_double), ("harvest_cap", ctypes.c_int),
+                ("harvest_v", ctypes.c_void_p), ("harvest_z", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("size", ctypes.c_size_t), ("its", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("matvecs", ctypes.c_longlong), ("fp_steps", ctypes.c_longlong),
                 ("final_relres", ctypes.c_double), ("time_fci_ms", ctypes.c_double),
-                ("time_arnoldi_ms", ctypes.c_double), ("time_total_ms", ctypes.c_double)]
+                ("time_arnoldi_ms", ctypes.c_double), ("time_total_ms", ctypes.c_double),
+                ("harvested", ctypes.c_int), ("learned_accepted", ctypes.c_int), ("learned_fallbacks", ctypes.c_int),
+                ("time_net_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "size"}
+
+
+class NetDesc(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_size_t), ("seed", ctypes.c_ulonglong)]
+
+
+class TrainDesc(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_size_t), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("npairs", ctypes.c_int), ("v", ctypes.c_void_p), ("e", ctypes.c_void_p),
+                ("kch", ctypes.c_void_p), ("nmedia", ctypes.c_int), ("medium_of_pair", ctypes.c_void_p),
+                ("crop", ctypes.c_int),
+                ("steps", ctypes.c_int), ("lr", ctypes.c_float), ("lr_min", ctypes.c_float),
+                ("phase_aug", ctypes.c_int), ("seed", ctypes.c_ulonglong), ("log_every", ctypes.c_int),
+                ("verbose", ctypes.c_int), ("loss_curve", ctypes.c_void_p), ("loss_curve_cap", ctypes.c_int)]
 
 
 _lib = None
@@ -95,6 +116,19 @@ def load_library(path: str = LIB_PATH):
         "hfci_fci_apply": (ip, [vp, vp, P(SolveOpts), ip, vp, vp, P(Stats)]),
         "hfci_solve": (ip, [vp, vp, P(SolveOpts), ip, vp, vp, P(Stats)]),
         "hfci_ctx_profile": (ip, [vp, ip]),
+        "hfci_net_create": (ip, [vp, P(NetDesc), P(vp)]),
+        "hfci_net_destroy": (None, [vp]),
+        "hfci_net_param_count": (ctypes.c_longlong, [vp]),
+        "hfci_net_get_params": (ip, [vp, vp]),
+        "hfci_net_set_params": (ip, [vp, vp]),
+        "hfci_net_get_grads": (ip, [vp, vp]),
+        "hfci_net_eval": (ip, [vp, ip, ip, ip, vp, vp]),
+        "hfci_net_train_step": (ip, [vp, ip, ip, ip, vp, vp, ctypes.c_float, ip, P(dp)]),
+        "hfci_net_train": (ip, [vp, P(TrainDesc), P(dp)]),
+        "hfci_net_apply": (ip, [vp, vp, ip, vp, vp]),
+        "hfci_op_medium_channel": (ip, [vp, vp]),
+        "hfci_net_save": (ip, [vp, ctypes.c_char_p]),
+        "hfci_net_load": (ip, [vp, ctypes.c_char_p]),
         "hfci_ctx_profile_read": (ip, [vp, P(KernelProf)]),
     }
     for name, (res, args) in sig.items():
@@ -229,6 +263,98 @@ class Operator(_Handle):
         _check(load_library().hfci_op_info(self.h, out))
         keys = ["s", "s_h2", "b1", "b2", "rho2", "kappa_min", "kappa_max"]
         return dict(zip(keys, list(out)))
+
+
+class Net(_Handle):
+    """hfci_net_create: the learned preconditioner (3-level 3D U-Net, BF16 on the matrix cores)."""
+
+    _destroy = "hfci_net_destroy"
+
+    def __init__(self, ctx: Context, seed: int = 1234):
+        self.h = ctypes.c_void_p()
+        d = NetDesc(ctypes.sizeof(NetDesc), seed)
+        _check(load_library().hfci_net_create(ctx.h, ctypes.byref(d), ctypes.byref(self.h)))
+        self.ctx = ctx
+        self.nparam = int(load_library().hfci_net_param_count(self.h))
+        ctx._adopt(self)
+
+    def get_params(self):
+        out = np.empty(self.nparam, dtype=np.float32)
+        _check(load_library().hfci_net_get_params(self.h, out.ctypes.data))
+        return out
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        assert flat.size == self.nparam
+        _check(load_library().hfci_net_set_params(self.h, flat.ctypes.data))
+
+    def get_grads(self):
+        out = np.empty(self.nparam, dtype=np.float32)
+        _check(load_library().hfci_net_get_grads(self.h, out.ctypes.data))
+        return out
+
+    def eval(self, x16):
+        """hfci_net_eval: x16 bf16 CUDA tensor [nz, ny, nx, 16] -> float32 [nz, ny, nx, 2]."""
+        import torch
+        nz, ny, nx, c = x16.shape
+        out = torch.empty((nz, ny, nx, 2), dtype=torch.float32, device=x16.device)
+        _sync()
+        _check(load_library().hfci_net_eval(self.h, nx, ny, nz, _ptr(x16, torch.bfloat16, "x16"), _ptr(out)))
+        return out
+
+    def train_step(self, x16, target, lr: float = 1e-3, update: bool = True):
+        import torch
+        nz, ny, nx, _ = x16.shape
+        loss = ctypes.c_double()
+        _sync()
+        _check(load_library().hfci_net_train_step(self.h, nx, ny, nz, _ptr(x16, torch.bfloat16, "x16"),
+                                                  _ptr(target, torch.float32, "target"), lr, 1 if update else 0,
+                                                  ctypes.byref(loss)))
+        return loss.value
+
+    def train(self, v, e, kch, medium_of_pair, crop: int, steps: int, lr: float = 1e-3, lr_min: float = 1e-5,
+              phase_aug: bool = True, seed: int = 0, log_every: int = 0, verbose: bool = False):
+        """hfci_net_train: v, e complex64 [P, nz, ny, nx]; kch float32 [M, nz, ny, nx]."""
+        import torch
+        P, nz, ny, nx = v.shape
+        mop = np.ascontiguousarray(medium_of_pair, dtype=np.int32)
+        ncurve = (steps // log_every + 2) if log_every > 0 else 0
+        curve = np.zeros(max(ncurve, 1))
+        if kch.dim() != 4 or tuple(kch.shape[1:]) != (nz, ny, nx) or tuple(e.shape) != tuple(v.shape):
+            raise ValueError("v, e [P, nz, ny, nx] and kch [M, nz, ny, nx] must share the grid")
+        d = TrainDesc(ctypes.sizeof(TrainDesc), nx, ny, nz, P, _ptr(v, torch.complex64, "v"),
+                      _ptr(e, torch.complex64, "e"), _ptr(kch, torch.float32, "kch"), kch.shape[0],
+                      mop.ctypes.data, crop, steps,
+                      lr, lr_min, 1 if phase_aug else 0, seed, log_every, 1 if verbose else 0,
+                      curve.ctypes.data, ncurve)
+        final = ctypes.c_double()
+        _sync()
+        _check(load_library().hfci_net_train(self.h, ctypes.byref(d), ctypes.byref(final)))
+        return final.value, curve[:ncurve]
+
+    def apply(self, op, r):
+        """hfci_net_apply: complex128 [nvec, nz, ny, nx] -> z of the same shape."""
+        import torch
+        z = torch.empty_like(r)
+        nvec = r.numel() // op.n
+        _sync()
+        _check(load_library().hfci_net_apply(self.h, op.h, nvec, _ptr(r, torch.complex128, "r"), _ptr(z)))
+        return z
+
+    def save(self, path: str):
+        _check(load_library().hfci_net_save(self.h, path.encode()))
+
+    def load(self, path: str):
+        _check(load_library().hfci_net_load(self.h, path.encode()))
+
+
+def medium_channel(op):
+    """hfci_op_medium_channel: omega^2 h^2 / c^2 as a float32 CUDA tensor [nz, ny, nx]."""
+    import torch
+    out = torch.empty(op.shape, dtype=torch.float32, device="cuda")
+    _sync()
+    _check(load_library().hfci_op_medium_channel(op.h, _ptr(out)))
+    return out
 
 
 def _prec_of(t):

@@ -1,0 +1,197 @@
+"""Learned preconditioner on the GPU versus the FP64 oracle network (needs an MI355X).
+
+Both sides use the same BF16-rounded weights and inputs; the oracle additionally rounds
+every stored intermediate to BF16 where the GPU stores one (its arithmetic stays
+FP64), so the remaining differences are FP32-vs-FP64 accumulation and isolated
+one-ulp BF16 rounding flips: the bar is 1e-2 relative (forward) and 3e-2 (gradients),
+where a wrong lane layout, tap or channel offset gives O(1) errors.
+"""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import conv as C
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+hf = pytest.importorskip("paper_1811_12378_amd.hfci")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hf.load_library()
+    c = hf.Context(0)
+    yield c
+    c.close()
+
+
+def bf16(a):
+    """Round float64 values to the nearest bfloat16 (ties to even), returned as float64."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+CIN_PAD = {"c1a": 16}
+
+
+def to_flat(p):
+    parts = []
+    for name, cin, cout in C.LAYERS:
+        w = p[name + ".w"]
+        cp = CIN_PAD.get(name, cin)
+        wp = np.zeros((27, cout, cp))
+        wp[:, :, :cin] = w
+        parts += [wp.ravel(), p[name + ".b"].ravel()]
+    parts += [p["out.w"].ravel(), p["out.b"].ravel()]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def from_flat(flat):
+    p, k = {}, 0
+    for name, cin, cout in C.LAYERS:
+        cp = CIN_PAD.get(name, cin)
+        n = 27 * cout * cp
+        p[name + ".w"] = flat[k:k + n].reshape(27, cout, cp)[:, :, :cin].astype(np.float64)
+        k += n
+        p[name + ".b"] = flat[k:k + cout].astype(np.float64)
+        k += cout
+    p["out.w"] = flat[k:k + 32].reshape(2, 16).astype(np.float64)
+    p["out.b"] = flat[k + 32:k + 34].astype(np.float64)
+    return p
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+def setup_net(ctx, seed=3):
+    rng = np.random.default_rng(seed)
+    p = C.init_params(seed)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = rng.standard_normal(p[k].shape) * 0.05
+        p[k] = bf16(p[k])
+    net = hf.Net(ctx, seed=seed)
+    net.set_params(to_flat(p))
+    return net, p
+
+
+def x16_of(x3):
+    x = np.zeros(x3.shape[:3] + (16,))
+    x[..., :3] = x3
+    return torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).cuda()
+
+
+def test_param_layout_roundtrip(ctx):
+    net, p = setup_net(ctx)
+    assert net.nparam == to_flat(p).size
+    back = from_flat(net.get_params())
+    for k in p:
+        assert np.array_equal(back[k], p[k]), k
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (8, 12, 16)])
+def test_forward_parity(ctx, shape):
+    net, p = setup_net(ctx)
+    rng = np.random.default_rng(4)
+    x3 = bf16(rng.standard_normal(shape + (3,)))
+    out = net.eval(x16_of(x3)).cpu().numpy().astype(np.float64)
+    ref, _ = C.forward(p, x3, q=bf16)
+    assert rel(out, ref) <= 1e-2, rel(out, ref)
+
+
+def test_backward_parity(ctx):
+    net, p = setup_net(ctx, seed=5)
+    rng = np.random.default_rng(6)
+    shape = (8, 8, 12)
+    x3 = bf16(rng.standard_normal(shape + (3,)))
+    t = rng.standard_normal(shape + (2,)).astype(np.float32)
+    L = net.train_step(x16_of(x3), torch.from_numpy(t).cuda(), update=False)
+    out, cache = C.forward(p, x3, q=bf16)
+    Lref, dout = C.loss(out, t.astype(np.float64))
+    g_ref, _ = C.backward(p, cache, dout, q=bf16)
+    assert abs(L - Lref) <= 1e-2 * abs(Lref)
+    g = from_flat(net.get_grads())
+    for k in g_ref:
+        assert rel(g[k], g_ref[k]) <= 3e-2, (k, rel(g[k], g_ref[k]))
+
+
+def test_adam_step_matches_oracle(ctx):
+    net, p = setup_net(ctx, seed=7)
+    rng = np.random.default_rng(8)
+    shape = (8, 8, 8)
+    x3 = bf16(rng.standard_normal(shape + (3,)))
+    t = torch.from_numpy(rng.standard_normal(shape + (2,)).astype(np.float32)).cuda()
+    flat0 = net.get_params().astype(np.float64)
+    net.train_step(x16_of(x3), t, lr=1e-3, update=True)
+    g = net.get_grads().astype(np.float64)
+    flat1 = net.get_params().astype(np.float64)
+    pp, gg = {"a": flat0.copy()}, {"a": g}
+    C.adam_step(pp, gg, {"a": np.zeros_like(g)}, {"a": np.zeros_like(g)}, 1, lr=1e-3)
+    assert np.abs(flat1 - pp["a"]).max() <= 1e-6
+    # the padded input channels of the first layer stay zero
+    first = net.get_params()[:27 * 16 * 16].reshape(27, 16, 16)
+    assert np.all(first[:, :, 3:] == 0.0)
+
+
+def test_apply_on_complex_vector(ctx):
+    import workloads as W
+    from oracle import operator as OO
+    net, p = setup_net(ctx, seed=9)
+    wl = W.config_grf_96(n=16, nrhs=1)
+    o = OO.Operator(wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
+    op = hf.Operator(ctx, torch.from_numpy(wl.c).cuda(), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
+    r = wl.rhs[0]
+    z = net.apply(op, torch.from_numpy(r[None]).cuda()).cpu().numpy()[0]
+    s = np.sqrt(np.mean(np.abs(r) ** 2))
+    kch = hf.medium_channel(op).cpu().numpy().astype(np.float64)
+    assert np.allclose(kch, o.kappa / o.s_h2, rtol=1e-6)
+    x3 = np.stack([bf16(r.real / s), bf16(r.imag / s), bf16(kch)], axis=-1)
+    out, _ = C.forward(p, x3, q=bf16)
+    ref = s * (out[..., 0] + 1j * out[..., 1])
+    assert rel(z, ref) <= 1e-2
+
+
+def test_save_load_roundtrip(ctx):
+    net, p = setup_net(ctx, seed=11)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "net.bin")
+        net.save(path)
+        other = hf.Net(ctx, seed=99)
+        other.load(path)
+        assert np.array_equal(other.get_params(), net.get_params())
+
+
+def test_harvest_train_and_learned_fgmres(ctx):
+    # pairs (v_j, FCI(v_j)) harvested from FGMRES on a random medium, a short training run,
+    # then the learned preconditioner inside FGMRES with FCI as judge and fallback
+    import workloads as W
+    wl = W.config_grf_96(n=32, nrhs=1)
+    op = hf.Operator(ctx, torch.from_numpy(wl.c).cuda(), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
+    cont = hf.Contour(op, 8, 1.0, 0.25, 8)
+    f = torch.from_numpy(wl.rhs[0][None]).cuda()
+    cap = 24
+    hv = torch.empty((cap, 32, 32, 32), dtype=torch.complex64, device="cuda")
+    hz = torch.empty_like(hv)
+    opts = hf.default_opts(precision=32, tol=1e-8, max_it=200)
+    opts.harvest_cap, opts.harvest_v, opts.harvest_z = cap, hv.data_ptr(), hz.data_ptr()
+    u, st = hf.solve(op, cont, f, opts=opts)
+    assert st["harvested"] == cap
+    # the harvested pairs are (unit Arnoldi vector, its FCI image)
+    nrm = torch.linalg.vector_norm(hv.reshape(cap, -1).to(torch.complex128), dim=1).cpu().numpy()
+    assert np.allclose(nrm, 1.0, atol=1e-5)
+    kch = hf.medium_channel(op)[None].contiguous()
+    net = hf.Net(ctx, seed=1)
+    final, curve = net.train(hv, hz, kch, np.zeros(cap, dtype=np.int32), crop=32, steps=150, lr=2e-3,
+                             lr_min=1e-4, log_every=25, seed=3)
+    assert np.all(np.isfinite(curve)) and curve[-1] < curve[0]
+    lopts = hf.default_opts(precision=32, tol=1e-8, max_it=300, precond=2, learned_tau=0.95)
+    lopts.net = net.h.value
+    u2, st2 = hf.solve(op, cont, f, opts=lopts)
+    assert st2["status"] == "HFCI_OK" and st2["final_relres"] <= 1e-8
+    assert st2["learned_accepted"] + st2["learned_fallbacks"] == st2["its"]

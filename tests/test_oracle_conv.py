@@ -1,0 +1,104 @@
+"""Pins of the oracle's convolution network: brute force and finite differences."""
+import numpy as np
+import pytest
+
+from oracle import conv as C
+
+
+def brute_conv(x, w, b):
+    Z, Y, X, cin = x.shape
+    cout = w.shape[1]
+    y = np.zeros((Z, Y, X, cout))
+    for z in range(Z):
+        for yy in range(Y):
+            for xx in range(X):
+                for co in range(cout):
+                    s = b[co]
+                    for t, (dz, dy, dx) in enumerate(C.OFFSETS):
+                        zz, y2, x2 = z + dz, yy + dy, xx + dx
+                        if 0 <= zz < Z and 0 <= y2 < Y and 0 <= x2 < X:
+                            for ci in range(cin):
+                                s += w[t, co, ci] * x[zz, y2, x2, ci]
+                    y[z, yy, xx, co] = s
+    return y
+
+
+def test_conv_matches_brute_force():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((3, 4, 5, 2))
+    w = rng.standard_normal((27, 3, 2))
+    b = rng.standard_normal(3)
+    assert np.allclose(C.conv3d(x, w, b), brute_conv(x, w, b), atol=1e-12)
+
+
+def test_conv_gradients_by_finite_differences():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((4, 3, 5, 3))
+    w = rng.standard_normal((27, 2, 3))
+    b = rng.standard_normal(2)
+    gy = rng.standard_normal((4, 3, 5, 2))
+    L = lambda x, w, b: np.sum(gy * C.conv3d(x, w, b))
+    dx = C.conv3d_dgrad(gy, w)
+    dw, db = C.conv3d_wgrad(x, gy)
+    h = 1e-6
+    for idx in [(0, 0, 0, 0), (3, 2, 4, 2), (1, 1, 2, 1)]:
+        e = np.zeros_like(x)
+        e[idx] = h
+        assert abs((L(x + e, w, b) - L(x - e, w, b)) / (2 * h) - dx[idx]) < 1e-6
+    for idx in [(0, 0, 0), (13, 1, 2), (26, 0, 1)]:
+        e = np.zeros_like(w)
+        e[idx] = h
+        assert abs((L(x, w + e, b) - L(x, w - e, b)) / (2 * h) - dw[idx]) < 1e-6
+    e = np.zeros_like(b)
+    e[1] = h
+    assert abs((L(x, w, b + e) - L(x, w, b - e)) / (2 * h) - db[1]) < 1e-6
+
+
+def test_pool_up_adjoints():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((4, 6, 8, 3))
+    y = rng.standard_normal((2, 3, 4, 3))
+    assert np.isclose(np.sum(C.pool(x) * y), np.sum(x * C.pool_back(y)))
+    assert np.isclose(np.sum(C.up(y) * x), np.sum(y * C.up_back(x)))
+
+
+def test_unet_gradients_by_finite_differences():
+    rng = np.random.default_rng(3)
+    p = C.init_params(7)
+    for k in p:  # non-zero biases so that every term is exercised
+        if k.endswith(".b"):
+            p[k] = rng.standard_normal(p[k].shape) * 0.1
+    x = rng.standard_normal((4, 4, 4, 3))
+    t = rng.standard_normal((4, 4, 4, 2))
+    out, cache = C.forward(p, x)
+    L, dout = C.loss(out, t)
+    g, dx = C.backward(p, cache, dout)
+    h = 1e-6
+
+    def Lof(pp, xx):
+        return C.loss(C.forward(pp, xx)[0], t)[0]
+
+    for name, idx in [("c1a.w", (13, 3, 1)), ("c2b.w", (0, 5, 7)), ("c3b.w", (26, 63, 10)),
+                      ("d2a.w", (4, 1, 70)), ("d1a.w", (9, 15, 40)), ("d1b.b", (2,)), ("out.w", (1, 5)),
+                      ("c3a.b", (11,)), ("out.b", (0,))]:
+        pp = {k: v.copy() for k, v in p.items()}
+        pm = {k: v.copy() for k, v in p.items()}
+        pp[name][idx] += h
+        pm[name][idx] -= h
+        fd = (Lof(pp, x) - Lof(pm, x)) / (2 * h)
+        assert abs(fd - g[name][idx]) <= 1e-6 * max(1.0, abs(fd)), (name, fd, g[name][idx])
+    for idx in [(0, 0, 0, 0), (3, 1, 2, 2)]:
+        e = np.zeros_like(x)
+        e[idx] = h
+        fd = (Lof(p, x + e) - Lof(p, x - e)) / (2 * h)
+        assert abs(fd - dx[idx]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_adam_step_closed_form():
+    p = {"a": np.array([1.0, -2.0])}
+    g = {"a": np.array([0.5, -0.25])}
+    m = {"a": np.zeros(2)}
+    v = {"a": np.zeros(2)}
+    C.adam_step(p, g, m, v, 1, lr=0.1)
+    # first bias-corrected step moves every coordinate by lr * sign(g)
+    assert np.allclose(p["a"], [1.0 - 0.1, -2.0 + 0.1], atol=1e-7)
