@@ -85,6 +85,59 @@ def cpu_baseline(wl, poles_oracle, n_matvecs, budget_s=20.0):
             "per_matvec_s": per_mv}
 
 
+def unet_flops_per_voxel():
+    """Multiply-adds x 2 of the U-Net per fine voxel (3 real input channels)."""
+    k = 2 * 27
+    lvl1 = k * (3 * 16 + 16 * 16 + 48 * 16 + 16 * 16) + 2 * 16 * 2
+    lvl2 = k * (16 * 32 + 32 * 32 + 96 * 32 + 32 * 32) / 8.0
+    lvl3 = k * (32 * 64 + 64 * 64) / 64.0
+    return lvl1 + lvl2 + lvl3
+
+
+def learned_arm(args, ctx, op, cont, f_d, t_mixed, fp64, verbose):
+    """Train the network on pairs from FCI-preconditioned FGMRES (untimed), then time the solve
+    with the learned preconditioner (FCI as judge and fallback) and the network's throughput."""
+    import torch
+    from paper_1811_12378_amd import hfci
+    from paper_1811_12378_amd import learned as L
+    t0 = time.perf_counter()
+    net, info = L.train(ctx, None, n=64, media=args.learn_media, pairs=48, steps=args.learn_steps)
+    train_s = time.perf_counter() - t0
+    log("learned: %d pairs, training %.1f s, final loss %.4f" % (info["pairs"], train_s, info["final_loss"]))
+    # network throughput on the benchmark grid (BF16 MFMA, FP32 accumulate)
+    r = torch.randn((1,) + tuple(f_d.shape[1:]), dtype=torch.complex128, device="cuda")
+    net.apply(op, r)
+    torch.cuda.synchronize()
+    reps = 3
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        net.apply(op, r)
+    torch.cuda.synchronize()
+    t_net = (time.perf_counter() - t1) / reps
+    del r
+    tflops = unet_flops_per_voxel() * op.n / t_net / 1e12
+    lo = hfci.default_opts(precision=32, tol=args.tol, max_it=args.max_it, precond=2, verbose=verbose)
+    lo.net = net.h.value
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    _, st = hfci.solve(op, cont, f_d, opts=lo)
+    torch.cuda.synchronize()
+    t_l = time.perf_counter() - t2
+    log("learned+FP32: %.3f s, its %d (%d kept, %d FCI), relres %.3e" % (t_l, st["its"], st["learned_accepted"],
+                                                                       st["learned_fallbacks"], st["final_relres"]))
+    out = {"time_s": t_l, "its": st["its"], "final_relres": st["final_relres"], "kept": st["learned_accepted"],
+           "fci_steps": st["learned_fallbacks"], "net_rho_mean": st["net_rho_mean"],
+           "fci_rho_mean": st["fci_rho_mean"], "train_pairs": info["pairs"], "train_s": train_s,
+           "train_final_loss": info["final_loss"], "speedup_vs_mixed_fci": t_mixed / t_l,
+           "net_apply_ms": t_net * 1e3,
+           "net_roofline": {"bound": "mfma", "achieved": round(tflops, 1), "peak": 2500.0, "unit": "TFLOP/s",
+                            "frac": round(tflops / 2500.0, 4)}}
+    if fp64:
+        out["speedup_vs_fp64"] = fp64["time_s"] / t_l
+    net.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +154,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--quiet", action="store_true", help="no per-cycle progress lines from the solver")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner arm")
+    ap.add_argument("--learn-media", type=int, default=12, help="64^3 training media for the learned arm")
+    ap.add_argument("--learn-steps", type=int, default=2000, help="Adam steps for the learned arm")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -186,6 +242,10 @@ def main():
                                                                          gbs64))
         del u64
 
+    learned = None
+    if not args.no_learned:
+        learned = learned_arm(args, ctx, op, cont, f_d, t_mixed, fp64, verbose)
+
     cpu = None
     if not args.no_cpu:
         from oracle import fci as OF
@@ -224,6 +284,7 @@ def main():
         "relres_oracle_rhs0": relres_oracle,
         "first_stage_gbs": round(first_gbs, 1),
         "fp64": fp64,
+        "learned": learned,
     }
     print(json.dumps(out), flush=True)
 

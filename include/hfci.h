@@ -83,11 +83,16 @@ typedef struct {
   int pole_batch;       /* poles advanced together per launch (x every RHS);
                            0 = all J                                              */
   int verbose;          /* 1: one line per FGMRES cycle on stderr               */
-  /* learned preconditioner (precond = HFCI_PRECOND_LEARNED): z_j = net(v_j) is kept
-     when ||v_j - A z_j|| <= learned_tau ||v_j||, otherwise z_j = FCI(v_j) (fallback,
-     needs the contour).                                           default 0.9 */
+  /* learned preconditioner (precond = HFCI_PRECOND_LEARNED): the proposal z = net(v_j)
+     is scaled by the complex d minimising rho = ||v_j - d A z|| / ||v_j|| (Alg. 1 step 3)
+     and kept when rho <= learned_tau * (mean rho of FCI over this solve's FCI steps)
+     and rho < 0.99; otherwise, and until FCI has run once, z_j = FCI(v_j) (needs the
+     contour).  0 < learned_tau <= 4.                               default 1.0 */
   hfci_net* net;
   double learned_tau;
+  int learned_patience;  /* after this many consecutive rejected proposals the network
+                            is no longer consulted in this solve (0 = never stop)
+                                                                     default 8 */
   /* training-pair harvest: each Arnoldi step of each RHS appends (v_j, FCI(v_j)) as
      complex64 to the DEVICE arrays harvest_v / harvest_z (harvest_cap vectors of n). */
   int harvest_cap;
@@ -110,6 +115,8 @@ typedef struct {
   int learned_accepted;     /* Arnoldi steps that kept the network's output      */
   int learned_fallbacks;    /* Arnoldi steps that fell back to FCI               */
   double time_net_ms;       /* device time in the network                        */
+  double net_rho_mean;      /* mean scaled residual rho of the network proposals */
+  double fci_rho_mean;      /* mean scaled residual rho of the FCI steps taken   */
 } hfci_stats;
 
 /* Per-kernel timing collected by hfci_ctx_profile (device time from HIP events
@@ -256,6 +263,9 @@ typedef struct {
   int verbose;                 /* 1: print the readbacks on stderr                  */
   double* loss_curve;          /* HOST array for the readbacks, or NULL             */
   int loss_curve_cap;
+  int loss_kind;               /* 0: ||out - t||^2/||t||^2; 1: 1 - |<o,t>|^2/(||o||^2||t||^2)
+                                  with o, t read as complex fields (scale and phase
+                                  invariant: FGMRES only needs the direction)         */
 } hfci_train_desc;
 
 hfci_status hfci_net_create(hfci_ctx* ctx, const hfci_net_desc* desc, hfci_net** out);
@@ -268,11 +278,11 @@ hfci_status hfci_net_get_grads(const hfci_net* net, float* host);
 /* Raw evaluation: x16 DEVICE bf16 [nz][ny][nx][16] (channels 3..15 zero), out DEVICE
  * float [nz][ny][nx][2]. */
 hfci_status hfci_net_eval(hfci_net* net, int nx, int ny, int nz, const uint16_t* x16, float* out);
-/* One forward/backward pass on (x16, target float [n][2]) with loss
- * ||out - target||^2 / ||target||^2; update != 0 also takes an Adam step with lr.
+/* One forward/backward pass on (x16, target float [n][2]) with the loss loss_kind
+ * (as in hfci_train_desc); update != 0 also takes an Adam step with lr.
  * *loss receives the loss (HOST). */
 hfci_status hfci_net_train_step(hfci_net* net, int nx, int ny, int nz, const uint16_t* x16,
-                                const float* target, float lr, int update, double* loss);
+                                const float* target, float lr, int update, int loss_kind, double* loss);
 /* Training loop over random crops of the pairs; returns the last loss read back. */
 hfci_status hfci_net_train(hfci_net* net, const hfci_train_desc* desc, double* final_loss);
 /* The preconditioner itself: z_k = rms(r_k) N(r_k / rms(r_k)) for complex128 DEVICE

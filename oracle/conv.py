@@ -20,7 +20,8 @@ Network (3 levels, 16/32/64 channels):
     d2 = relu(d2b(relu(d2a(concat(up(b3), e2)))))    [N/2, 32]
     d1 = relu(d1b(relu(d1a(concat(up(d2), e1)))))    [N,   16]
     out = p(d1)  (1x1x1 conv 16 -> 2, no activation)
-Loss: relative squared error ||out - t||^2 / ||t||^2.  Optimiser: Adam.
+Losses: relative squared error ||out - t||^2 / ||t||^2, or its scale- and
+phase-invariant form 1 - |<o, t>|^2/(||o||^2 ||t||^2).  Optimiser: Adam.
 
 Pins (tests/test_oracle_conv.py): the convolution against a brute-force loop
 over every index; every gradient against central finite differences.
@@ -167,6 +168,23 @@ def loss(out, t):
     den = np.sum(t * t)
     r = out - t
     return np.sum(r * r) / den, 2.0 * r / den
+
+
+def loss_phase_invariant(out, t):
+    """Scale- and phase-invariant loss of the two-channel output read as a complex field:
+        L = 1 - |<o, t>|^2 / (||o||^2 ||t||^2),  o = out[..., 0] + i out[..., 1] (same for t),
+    i.e. the relative error of the best complex multiple of o.  Returns (L, dL/dout), the
+    gradient with respect to the real and imaginary channels:
+        dL/dRe o + i dL/dIm o = -2 conj(S) (t - (S/P) o) / (P Q),  S = <o, t>, P = ||o||^2, Q = ||t||^2.
+    """
+    o = out[..., 0] + 1j * out[..., 1]
+    tc = t[..., 0] + 1j * t[..., 1]
+    S = np.vdot(o, tc)
+    P = np.vdot(o, o).real
+    Q = np.vdot(tc, tc).real
+    L = 1.0 - abs(S) ** 2 / (P * Q)
+    gc = -2.0 * np.conj(S) * (tc - (S / P) * o) / (P * Q)
+    return L, np.stack([gc.real, gc.imag], axis=-1)
 
 
 def adam_step(p, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

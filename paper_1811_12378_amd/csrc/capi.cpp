@@ -144,8 +144,10 @@ static void check_opts(const hfci_solve_opts* o) {
   HFCI_REQUIRE(o->precond == HFCI_PRECOND_FCI || o->precond == HFCI_PRECOND_NONE ||
                    o->precond == HFCI_PRECOND_LEARNED,
                "unknown precond");
-  HFCI_REQUIRE(o->precond != HFCI_PRECOND_LEARNED || (o->net != nullptr && o->learned_tau > 0.0),
-               "the learned preconditioner needs opts->net and learned_tau > 0");
+  HFCI_REQUIRE(o->precond != HFCI_PRECOND_LEARNED ||
+                   (o->net != nullptr && o->learned_tau > 0.0 && o->learned_tau <= 4.0),
+               "the learned preconditioner needs opts->net and 0 < learned_tau <= 4");
+  HFCI_REQUIRE(o->learned_patience >= 0, "learned_patience must be >= 0");
   HFCI_REQUIRE(o->harvest_cap >= 0 && (o->harvest_cap == 0 || (o->harvest_v && o->harvest_z)),
                "harvest_cap > 0 needs harvest_v and harvest_z");
   HFCI_REQUIRE(o->pole_batch >= 0, "pole_batch must be >= 0");
@@ -174,7 +176,8 @@ void hfci_default_opts(hfci_solve_opts* o) {
   o->pole_batch = 0;
   o->verbose = 0;
   o->net = nullptr;
-  o->learned_tau = 0.9;
+  o->learned_tau = 1.0;
+  o->learned_patience = 8;
   o->harvest_cap = 0;
   o->harvest_v = nullptr;
   o->harvest_z = nullptr;

@@ -127,7 +127,7 @@ struct TrainData {
   const int* medium_of_pair;  // [npairs] (host)
 };
 struct TrainOpts {
-  int crop, steps, phase_aug, log_every, verbose;
+  int crop, steps, phase_aug, log_every, verbose, loss_kind;
   float lr, lr_min;
   unsigned long long seed;
 };
@@ -166,7 +166,8 @@ struct Net {
   Acts acts(Dims d, bool backward);
   void forward(Dims d, const uint16_t* x16, const Acts& a);
   void backward(const uint16_t* x16, const Acts& a);
-  double train_step(Dims d, const uint16_t* x16, const float* target, float lr, bool update, bool read_loss);
+  double train_step(Dims d, const uint16_t* x16, const float* target, float lr, bool update, bool read_loss,
+                    int loss_kind);
   void eval(Dims d, const uint16_t* x16, float* out);
   void apply(const Op& op, int nvec, const double2* r, double2* z);
   double train(const TrainData& td, const TrainOpts& to, std::vector<double>& curve);

@@ -218,13 +218,14 @@ void Net::backward(const uint16_t* x16, const Acts& a) {
   conv_back(a, C1A, a.d1, x, V(a.a1, 16), V(a.ga1, 16), none);
 }
 
-double Net::train_step(Dims d, const uint16_t* x16, const float* target, float lr, bool update, bool read_loss) {
+double Net::train_step(Dims d, const uint16_t* x16, const float* target, float lr, bool update, bool read_loss,
+                       int loss_kind) {
   hipStream_t s = ctx->stream;
   const Acts a = acts(d, true);
-  double* lpart = (double*)ctx->ws.get("net_lpart", 2 * 1024 * sizeof(double));
-  double* lsum = (double*)ctx->ws.get("net_lsum", 2 * sizeof(double));
+  double* lpart = (double*)ctx->ws.get("net_lpart", 4 * 1024 * sizeof(double));
+  double* lsum = (double*)ctx->ws.get("net_lsum", 5 * sizeof(double));
   forward(d, x16, a);
-  launch_loss(s, a.V1, a.o, target, lpart, lsum, a.dout);
+  launch_loss(s, a.V1, a.o, target, lpart, lsum, a.dout, loss_kind);
   backward(x16, a);
   if (update) {
     ++step;
@@ -233,7 +234,7 @@ double Net::train_step(Dims d, const uint16_t* x16, const float* target, float l
       launch_flip_transpose(s, wb + layers[l].w_off, layers[l].cout, layers[l].cin, wt + layers[l].w_off);
   }
   if (!read_loss) return -1.0;
-  double h[2];
+  double h[1];
   HFCI_HIP(hipMemcpyAsync(h, lsum, sizeof(h), hipMemcpyDeviceToHost, s));
   HFCI_HIP(hipStreamSynchronize(s));
   return h[0];
@@ -294,7 +295,7 @@ double Net::train(const TrainData& td, const TrainOpts& to, std::vector<double>&
     const double frac = to.steps > 1 ? (double)it / (to.steps - 1) : 1.0;
     const float lr = (float)(to.lr_min + 0.5 * (to.lr - to.lr_min) * (1.0 + std::cos(M_PI * frac)));
     const bool read = to.log_every > 0 && (it % to.log_every == 0 || it == to.steps - 1);
-    const double L = train_step(crop, x16, tgt, lr, true, read);
+    const double L = train_step(crop, x16, tgt, lr, true, read, to.loss_kind);
     if (read) {
       curve.push_back(L);
       last = L;

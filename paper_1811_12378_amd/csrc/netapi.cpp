@@ -115,13 +115,14 @@ hfci_status hfci_net_eval(hfci_net* net, int nx, int ny, int nz, const uint16_t*
 }
 
 hfci_status hfci_net_train_step(hfci_net* net, int nx, int ny, int nz, const uint16_t* x16, const float* target,
-                                float lr, int update, double* loss) {
+                                float lr, int update, int loss_kind, double* loss) {
   NET_BEGIN
   HFCI_REQUIRE(net && x16 && target, "NULL argument");
   check_dims(nx, ny, nz);
   HFCI_REQUIRE(!update || (lr > 0.f && lr < 1.f), "lr must be in (0, 1)");
+  HFCI_REQUIRE(loss_kind == 0 || loss_kind == 1, "loss_kind must be 0 or 1");
   Dev dg(net->device);
-  const double L = net->train_step(Dims{nz, ny, nx}, x16, target, lr, update != 0, true);
+  const double L = net->train_step(Dims{nz, ny, nx}, x16, target, lr, update != 0, true, loss_kind);
   HFCI_HIP(hipGetLastError());
   if (loss) *loss = L;
   return HFCI_OK;
@@ -139,10 +140,11 @@ hfci_status hfci_net_train(hfci_net* net, const hfci_train_desc* d, double* fina
   HFCI_REQUIRE(d->crop >= 4 && d->crop % 4 == 0 && d->crop <= d->nx && d->crop <= d->ny && d->crop <= d->nz,
                "crop must be a multiple of 4 no larger than the grid");
   HFCI_REQUIRE(d->steps >= 1 && d->lr > 0.f && d->lr < 1.f && d->lr_min >= 0.f, "bad schedule");
+  HFCI_REQUIRE(d->loss_kind == 0 || d->loss_kind == 1, "loss_kind must be 0 or 1");
   Dev dg(net->device);
   TrainData td{d->nx, d->ny, d->nz, d->npairs, (const float2*)d->v, (const float2*)d->e, d->kch,
                d->medium_of_pair};
-  TrainOpts to{d->crop, d->steps, d->phase_aug, d->log_every, d->verbose, d->lr, d->lr_min, d->seed};
+  TrainOpts to{d->crop, d->steps, d->phase_aug, d->log_every, d->verbose, d->loss_kind, d->lr, d->lr_min, d->seed};
   std::vector<double> curve;
   const double L = net->train(td, to, curve);
   HFCI_HIP(hipGetLastError());

@@ -55,7 +55,10 @@ void launch_sumsq_crop_c64(hipStream_t s, Dims full, Dims crop, int oz, int oy, 
 void launch_sumsq_c128(hipStream_t s, long n, const double2* r, double* part);
 // scale = sqrt(sum / count) (or 1 if zero) from partials
 void launch_finish_rms(hipStream_t s, const double* part, int nblk, double count, double* scale);
-// relative squared loss: sums over blocks of |o - t|^2 and |t|^2, then dout = 2 (o - t) / |t|^2
-void launch_loss(hipStream_t s, long nvox, const float* o, const float* t, double* part, double* sums, float* dout);
+// kind 0: relative squared loss |o - t|^2 / |t|^2, dout = 2 (o - t) / |t|^2;
+// kind 1: scale- and phase-invariant loss 1 - |<o,t>|^2 / (|o|^2 |t|^2) of the complex field.
+// sums[0] receives the loss; part needs 4 * rms_blocks(2 * nvox) doubles, sums 5.
+void launch_loss(hipStream_t s, long nvox, const float* o, const float* t, double* part, double* sums, float* dout,
+                 int kind);
 
 }  // namespace hfci

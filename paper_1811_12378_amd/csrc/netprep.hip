@@ -166,6 +166,65 @@ __global__ void loss_grad_kernel(long nvox, const float* __restrict__ o, const f
   dout[i] = (float)(2.0 * ((double)o[i] - (double)t[i]) / den);
 }
 
+// scale- and phase-invariant loss: S = <o, t> (complex), P = |o|^2, Q = |t|^2 per block
+__global__ __launch_bounds__(256) void loss_pi_sums_kernel(long nvox, const float* __restrict__ o,
+                                                            const float* __restrict__ t, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double sr = 0.0, si = 0.0, pp = 0.0, qq = 0.0;
+  for (long v = (long)blockIdx.x * 256 + threadIdx.x; v < nvox; v += (long)gridDim.x * 256) {
+    const double o0 = o[2 * v], o1 = o[2 * v + 1], t0 = t[2 * v], t1 = t[2 * v + 1];
+    sr += o0 * t0 + o1 * t1;
+    si += o0 * t1 - o1 * t0;
+    pp += o0 * o0 + o1 * o1;
+    qq += t0 * t0 + t1 * t1;
+  }
+  const double a = block_sum256(sr, sh);
+  const double b = block_sum256(si, sh);
+  const double c = block_sum256(pp, sh);
+  const double d = block_sum256(qq, sh);
+  if (threadIdx.x == 0) {
+    part[4 * blockIdx.x] = a;
+    part[4 * blockIdx.x + 1] = b;
+    part[4 * blockIdx.x + 2] = c;
+    part[4 * blockIdx.x + 3] = d;
+  }
+}
+
+__global__ __launch_bounds__(256) void loss_pi_finish_kernel(const double* __restrict__ part, int nblk,
+                                                              double* __restrict__ sums) {
+  __shared__ double sh[256];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nblk; i += 256)
+    for (int k = 0; k < 4; ++k) acc[k] += part[4 * i + k];
+  double tot[4];
+  for (int k = 0; k < 4; ++k) tot[k] = block_sum256(acc[k], sh);
+  if (threadIdx.x == 0) {
+    const double den = tot[2] * tot[3];
+    sums[0] = den > 0 ? 1.0 - (tot[0] * tot[0] + tot[1] * tot[1]) / den : 1.0;
+    for (int k = 0; k < 4; ++k) sums[1 + k] = tot[k];
+  }
+}
+
+// dL/dRe o + i dL/dIm o = -2 conj(S) (t - (S/P) o) / (P Q)
+__global__ void loss_pi_grad_kernel(long nvox, const float* __restrict__ o, const float* __restrict__ t,
+                                    const double* __restrict__ sums, float* __restrict__ dout) {
+  const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvox) return;
+  const double Sr = sums[1], Si = sums[2], P = sums[3], Q = sums[4];
+  if (!(P > 0 && Q > 0)) {
+    dout[2 * v] = 0.f;
+    dout[2 * v + 1] = 0.f;
+    return;
+  }
+  const double qr = Sr / P, qi = Si / P;  // S / P
+  const double o0 = o[2 * v], o1 = o[2 * v + 1];
+  const double ur = t[2 * v] - (qr * o0 - qi * o1), ui = t[2 * v + 1] - (qr * o1 + qi * o0);
+  const double k = -2.0 / (P * Q);
+  // conj(S) * u
+  dout[2 * v] = (float)(k * (Sr * ur + Si * ui));
+  dout[2 * v + 1] = (float)(k * (Sr * ui - Si * ur));
+}
+
 __global__ void scale_f32_kernel(const float* __restrict__ in, long n, float a, float* __restrict__ out) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = a * in[i];
@@ -223,7 +282,15 @@ void launch_finish_rms(hipStream_t s, const double* part, int nblk, double count
   hipLaunchKernelGGL(finish_rms_kernel, dim3(1), dim3(256), 0, s, part, nblk, count, scale);
 }
 
-void launch_loss(hipStream_t s, long nvox, const float* o, const float* t, double* part, double* sums, float* dout) {
+void launch_loss(hipStream_t s, long nvox, const float* o, const float* t, double* part, double* sums, float* dout,
+                 int kind) {
+  if (kind == 1) {
+    const int b = rms_blocks(nvox);
+    hipLaunchKernelGGL(loss_pi_sums_kernel, dim3(b), dim3(256), 0, s, nvox, o, t, part);
+    hipLaunchKernelGGL(loss_pi_finish_kernel, dim3(1), dim3(256), 0, s, part, b, sums);
+    if (dout) hipLaunchKernelGGL(loss_pi_grad_kernel, dim3(nb(nvox)), dim3(256), 0, s, nvox, o, t, sums, dout);
+    return;
+  }
   const int b = rms_blocks(2 * nvox);
   hipLaunchKernelGGL(loss_sums_kernel, dim3(b), dim3(256), 0, s, nvox, o, t, part);
   hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(256), 0, s, part, b, sums);

@@ -303,7 +303,9 @@ hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& 
   int its = 0, cycles = 0;
   long long res_mv = 0;
   int harvested = 0, n_accept = 0, n_fallback = 0;
-  double t_net = 0.0;
+  double t_net = 0.0, net_rho_sum = 0.0, fci_rho_sum = 0.0;
+  long net_rho_n = 0, fci_rho_n = 0;
+  int net_rejects_in_row = 0;
   FciStats fst;
   double t_fci = 0, t_arn = 0;
   Timer tm(s);
@@ -383,28 +385,46 @@ hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& 
         fin = stage_in;
         fout = stage_out;
       }
-      if (o.precond == HFCI_PRECOND_LEARNED) {
-        // the network proposes z = N(v); FCI judges it by the residual ||v - A z|| / ||v||
-        // (v has unit norm) and replaces the rejected proposals
+      const bool consult_net = o.precond == HFCI_PRECOND_LEARNED &&
+                               (o.learned_patience == 0 || net_rejects_in_row < o.learned_patience);
+      if (o.precond == HFCI_PRECOND_LEARNED && !consult_net) {
+        fci_apply(op, *c, o, nl, fin, fout, fst);
+        n_fallback += nl;
+      } else if (consult_net) {
+        // the network proposes z = N(v).  Alg. 1 step 3 on the proposal: d = (Az)^H v / |Az|^2
+        // minimises ||v - d A z||; with |v| = 1 that residual is sqrt(1 - |(Az)^H v|^2 / |Az|^2).
+        // A proposal is kept (scaled by d) when that residual is at most learned_tau times the
+        // mean of FCI's own scaled residual over this solve's FCI steps (and below 0.99);
+        // otherwise, and until FCI has run once, z = FCI(v).
         Timer tn(s);
         tn.start();
         o.net->apply(op, nl, fin, fout);
-        double2* wt = (double2*)ctx.ws.get("gm_wjudge", n * sizeof(double2));
-        double* jd = (double*)ctx.ws.get("gm_judge", (size_t)nl * sizeof(double));
-        for (int k = 0; k < nl; ++k) {
-          Launch<double2>::apply(s, op.g, op.kappa64, 0.0, 0.0, 1, fout + k * n, wt);
-          launch_diffnorm2_partial(s, fin + k * n, wt, n, part);
-          launch_reduce(s, part, nbb, 1, jd + k);
-        }
+        const int nbs2 = Launch<double2>::partial_blocks(op.g);
+        double* jp = (double*)ctx.ws.get("gm_jpart", (size_t)nl * 3 * nbs2 * sizeof(double));
+        double* js = (double*)ctx.ws.get("gm_jsums", (size_t)nl * 3 * sizeof(double));
+        double* jd = (double*)ctx.ws.get("gm_jd", (size_t)nl * 2 * sizeof(double));
+        Launch<double2>::dstep_partials(s, op.g, op.kappa64, nl, fout, fin, jp);
+        launch_reduce(s, jp, nbs2, 3 * nl, js);
+        launch_dfinish(s, js, nl, jd);
+        launch_scale_out<double2>(s, fout, fout, jd, nl, n);
         fst.matvecs += nl;
         double* jh = ctx.pinned_dbl + kPinnedFciOffset + 1024;
-        HFCI_HIP(hipMemcpyAsync(jh, jd, nl * sizeof(double), hipMemcpyDeviceToHost, s));
+        HFCI_HIP(hipMemcpyAsync(jh, js, 3 * nl * sizeof(double), hipMemcpyDeviceToHost, s));
         t_net += tn.stop_ms();
         std::vector<int> rej;
-        for (int k = 0; k < nl; ++k)
-          if (!(std::sqrt(jh[k]) <= o.learned_tau)) rej.push_back(k);
+        const double thr = fci_rho_n > 0 ? std::min(0.99, o.learned_tau * fci_rho_sum / fci_rho_n) : -1.0;
+        for (int k = 0; k < nl; ++k) {
+          const double num2 = jh[3 * k] * jh[3 * k] + jh[3 * k + 1] * jh[3 * k + 1], den = jh[3 * k + 2];
+          const double rho = den > 0.0 ? std::sqrt(std::max(0.0, 1.0 - num2 / den)) : 1.0;
+          net_rho_sum += rho;
+          ++net_rho_n;
+          if (!(den > 0.0) || !(rho <= thr)) rej.push_back(k);
+          if (o.verbose > 1)
+            std::fprintf(stderr, "[hfci] step %d slot %d: network residual %.3f, threshold %.3f\n", its, k, rho, thr);
+        }
         n_accept += nl - (int)rej.size();
         n_fallback += (int)rej.size();
+        net_rejects_in_row = rej.size() == (size_t)nl ? net_rejects_in_row + 1 : 0;
         if (!rej.empty()) {
           const int nr = (int)rej.size();
           double2* rin = (double2*)ctx.ws.get("gm_rej_in", (size_t)nr * n * sizeof(double2));
@@ -414,6 +434,17 @@ hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& 
           fci_apply(op, *c, o, nr, rin, rout, fst);
           for (int k = 0; k < nr; ++k)
             HFCI_HIP(hipMemcpyAsync(fout + rej[k] * n, rout + k * n, n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+          // FCI's own scaled residual from its step-3 sums ((Aw)^H v, |Aw|^2; |v| = 1)
+          const double* fs = (const double*)ctx.ws.get("fci_dsums", (size_t)nr * 3 * sizeof(double));
+          HFCI_HIP(hipMemcpyAsync(jh, fs, 3 * nr * sizeof(double), hipMemcpyDeviceToHost, s));
+          HFCI_HIP(hipStreamSynchronize(s));
+          for (int k = 0; k < nr; ++k) {
+            const double num2 = jh[3 * k] * jh[3 * k] + jh[3 * k + 1] * jh[3 * k + 1], den = jh[3 * k + 2];
+            if (den > 0.0) {
+              fci_rho_sum += std::sqrt(std::max(0.0, 1.0 - num2 / den));
+              ++fci_rho_n;
+            }
+          }
         }
       } else if (c && o.precond == HFCI_PRECOND_FCI) {
         fci_apply(op, *c, o, nl, fin, fout, fst);
@@ -522,6 +553,8 @@ hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& 
     stats->learned_accepted = n_accept;
     stats->learned_fallbacks = n_fallback;
     stats->time_net_ms = t_net;
+    stats->net_rho_mean = net_rho_n ? net_rho_sum / net_rho_n : 0.0;
+    stats->fci_rho_mean = fci_rho_n ? fci_rho_sum / fci_rho_n : 0.0;
     stats->time_arnoldi_ms = t_arn;
     stats->time_total_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_wall0).count();

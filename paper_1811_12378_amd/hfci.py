@@ -55,7 +55,8 @@ class SolveOpts(ctypes.Structure):
                 ("max_it", ctypes.c_int), ("tol", ctypes.c_double), ("fp_steps", ctypes.c_int),
                 ("fp_reduce", ctypes.c_double), ("fp_max_steps", ctypes.c_int), ("k_in", ctypes.c_int),
                 ("precond", ctypes.c_int), ("pole_batch", ctypes.c_int), ("verbose", ctypes.c_int),
-                ("net", ctypes.c_void_p), ("learned_tau", ctypes.c_double), ("harvest_cap", ctypes.c_int),
+                ("net", ctypes.c_void_p), ("learned_tau", ctypes.c_double), ("learned_patience", ctypes.c_int),
+                ("harvest_cap", ctypes.c_int),
                 ("harvest_v", ctypes.c_void_p), ("harvest_z", ctypes.c_void_p)]
 
 
@@ -65,7 +66,8 @@ class Stats(ctypes.Structure):
                 ("final_relres", ctypes.c_double), ("time_fci_ms", ctypes.c_double),
                 ("time_arnoldi_ms", ctypes.c_double), ("time_total_ms", ctypes.c_double),
                 ("harvested", ctypes.c_int), ("learned_accepted", ctypes.c_int), ("learned_fallbacks", ctypes.c_int),
-                ("time_net_ms", ctypes.c_double)]
+                ("time_net_ms", ctypes.c_double), ("net_rho_mean", ctypes.c_double),
+                ("fci_rho_mean", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "size"}
@@ -82,7 +84,8 @@ class TrainDesc(ctypes.Structure):
                 ("crop", ctypes.c_int),
                 ("steps", ctypes.c_int), ("lr", ctypes.c_float), ("lr_min", ctypes.c_float),
                 ("phase_aug", ctypes.c_int), ("seed", ctypes.c_ulonglong), ("log_every", ctypes.c_int),
-                ("verbose", ctypes.c_int), ("loss_curve", ctypes.c_void_p), ("loss_curve_cap", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("loss_curve", ctypes.c_void_p), ("loss_curve_cap", ctypes.c_int),
+                ("loss_kind", ctypes.c_int)]
 
 
 _lib = None
@@ -123,7 +126,7 @@ def load_library(path: str = LIB_PATH):
         "hfci_net_set_params": (ip, [vp, vp]),
         "hfci_net_get_grads": (ip, [vp, vp]),
         "hfci_net_eval": (ip, [vp, ip, ip, ip, vp, vp]),
-        "hfci_net_train_step": (ip, [vp, ip, ip, ip, vp, vp, ctypes.c_float, ip, P(dp)]),
+        "hfci_net_train_step": (ip, [vp, ip, ip, ip, vp, vp, ctypes.c_float, ip, ip, P(dp)]),
         "hfci_net_train": (ip, [vp, P(TrainDesc), P(dp)]),
         "hfci_net_apply": (ip, [vp, vp, ip, vp, vp]),
         "hfci_op_medium_channel": (ip, [vp, vp]),
@@ -302,18 +305,19 @@ class Net(_Handle):
         _check(load_library().hfci_net_eval(self.h, nx, ny, nz, _ptr(x16, torch.bfloat16, "x16"), _ptr(out)))
         return out
 
-    def train_step(self, x16, target, lr: float = 1e-3, update: bool = True):
+    def train_step(self, x16, target, lr: float = 1e-3, update: bool = True, loss_kind: int = 0):
         import torch
         nz, ny, nx, _ = x16.shape
         loss = ctypes.c_double()
         _sync()
         _check(load_library().hfci_net_train_step(self.h, nx, ny, nz, _ptr(x16, torch.bfloat16, "x16"),
                                                   _ptr(target, torch.float32, "target"), lr, 1 if update else 0,
-                                                  ctypes.byref(loss)))
+                                                  loss_kind, ctypes.byref(loss)))
         return loss.value
 
     def train(self, v, e, kch, medium_of_pair, crop: int, steps: int, lr: float = 1e-3, lr_min: float = 1e-5,
-              phase_aug: bool = True, seed: int = 0, log_every: int = 0, verbose: bool = False):
+              phase_aug: bool = True, seed: int = 0, log_every: int = 0, verbose: bool = False,
+              loss_kind: int = 1):
         """hfci_net_train: v, e complex64 [P, nz, ny, nx]; kch float32 [M, nz, ny, nx]."""
         import torch
         P, nz, ny, nx = v.shape
@@ -326,7 +330,7 @@ class Net(_Handle):
                       _ptr(e, torch.complex64, "e"), _ptr(kch, torch.float32, "kch"), kch.shape[0],
                       mop.ctypes.data, crop, steps,
                       lr, lr_min, 1 if phase_aug else 0, seed, log_every, 1 if verbose else 0,
-                      curve.ctypes.data, ncurve)
+                      curve.ctypes.data, ncurve, loss_kind)
         final = ctypes.c_double()
         _sync()
         _check(load_library().hfci_net_train(self.h, ctypes.byref(d), ctypes.byref(final)))

@@ -190,8 +190,27 @@ def test_harvest_train_and_learned_fgmres(ctx):
     final, curve = net.train(hv, hz, kch, np.zeros(cap, dtype=np.int32), crop=32, steps=150, lr=2e-3,
                              lr_min=1e-4, log_every=25, seed=3)
     assert np.all(np.isfinite(curve)) and curve[-1] < curve[0]
-    lopts = hf.default_opts(precision=32, tol=1e-8, max_it=300, precond=2, learned_tau=0.95)
+    lopts = hf.default_opts(precision=32, tol=1e-8, max_it=300, precond=2, learned_tau=1.0)
     lopts.net = net.h.value
     u2, st2 = hf.solve(op, cont, f, opts=lopts)
     assert st2["status"] == "HFCI_OK" and st2["final_relres"] <= 1e-8
     assert st2["learned_accepted"] + st2["learned_fallbacks"] == st2["its"]
+    assert st2["learned_fallbacks"] >= 1 and 0.0 < st2["fci_rho_mean"] < 1.0
+    # the judge admits no proposal whose scaled residual is worse than FCI's running mean
+    assert st2["learned_accepted"] == 0 or st2["net_rho_mean"] < 1.0
+
+
+def test_phase_invariant_loss_gradients(ctx):
+    net, p = setup_net(ctx, seed=13)
+    rng = np.random.default_rng(14)
+    shape = (8, 8, 8)
+    x3 = bf16(rng.standard_normal(shape + (3,)))
+    t = rng.standard_normal(shape + (2,)).astype(np.float32)
+    L = net.train_step(x16_of(x3), torch.from_numpy(t).cuda(), update=False, loss_kind=1)
+    out, cache = C.forward(p, x3, q=bf16)
+    Lref, dout = C.loss_phase_invariant(out, t.astype(np.float64))
+    g_ref, _ = C.backward(p, cache, dout, q=bf16)
+    assert abs(L - Lref) <= 1e-2 * abs(Lref) + 1e-4
+    g = from_flat(net.get_grads())
+    for k in g_ref:
+        assert rel(g[k], g_ref[k]) <= 3e-2, (k, rel(g[k], g_ref[k]))

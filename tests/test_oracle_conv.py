@@ -102,3 +102,23 @@ def test_adam_step_closed_form():
     C.adam_step(p, g, m, v, 1, lr=0.1)
     # first bias-corrected step moves every coordinate by lr * sign(g)
     assert np.allclose(p["a"], [1.0 - 0.1, -2.0 + 0.1], atol=1e-7)
+
+
+def test_phase_invariant_loss():
+    rng = np.random.default_rng(11)
+    out = rng.standard_normal((3, 4, 5, 2))
+    t = rng.standard_normal((3, 4, 5, 2))
+    L, g = C.loss_phase_invariant(out, t)
+    h = 1e-6
+    for idx in [(0, 0, 0, 0), (2, 3, 4, 1), (1, 2, 3, 0)]:
+        e = np.zeros_like(out)
+        e[idx] = h
+        fd = (C.loss_phase_invariant(out + e, t)[0] - C.loss_phase_invariant(out - e, t)[0]) / (2 * h)
+        assert abs(fd - g[idx]) < 1e-7
+    # invariant to a complex scale of the output; zero for a complex multiple of the target
+    a = 0.3 - 1.7j
+    tc = t[..., 0] + 1j * t[..., 1]
+    oc = a * tc
+    assert C.loss_phase_invariant(np.stack([oc.real, oc.imag], -1), t)[0] < 1e-14
+    o2 = (out[..., 0] + 1j * out[..., 1]) * a
+    assert abs(C.loss_phase_invariant(np.stack([o2.real, o2.imag], -1), t)[0] - L) < 1e-12
