@@ -130,10 +130,13 @@ typedef struct {
 } hfci_kernel_prof;
 
 enum {
-  HFCI_PROF_FP_STAGE = 0,  /* Horner stages 2..q of the fixed-point step         */
-  HFCI_PROF_FP_FIRST = 1,  /* first stage (also forms the shifted residual)      */
-  HFCI_PROF_APPLY = 2,     /* hfci_apply                                         */
-  HFCI_PROF_N = 3
+  HFCI_PROF_FP_STAGE = 0,  /* middle factors w <- a (A - z0) w + b w of a fixed-point
+                              step (product form of eq. fix-pt-exp)                */
+  HFCI_PROF_FP_FIRST = 1,  /* first factor of a step (also forms the shifted residual) */
+  HFCI_PROF_APPLY = 2,     /* hfci_apply                                           */
+  HFCI_PROF_FP_LAST = 3,   /* last factor of a step (adds the constant term y1)    */
+  HFCI_PROF_FP_INIT = 4,   /* first and last factor of step one (from f, to y1)    */
+  HFCI_PROF_N = 5
 };
 
 /* Fill *o with the defaults listed above. */
@@ -171,6 +174,33 @@ void hfci_op_destroy(hfci_op* op);
  * where [b1, b2] x [-rho2, 0] is the spectrum rectangle of Lemma 3.1 (Weyl
  * bounds of S - M with the exact extreme Dirichlet Laplacian eigenvalues). */
 hfci_status hfci_op_info(const hfci_op* op, double* out7);
+
+/* Launch shape of the operator's z-marching stencil kernels for one precision
+ * (HFCI_F32 or HFCI_F64), tune[4] (HOST array):
+ *   tune[0] kern: 0 = in-plane neighbours as cached global loads, 1 = each plane
+ *           staged through LDS with its halo;
+ *   tune[1] ty:   the thread tile is 64 x ty (4 or 8);
+ *   tune[2] pd:   HBM streams are issued pd planes ahead (kern 0: 1 or 2;
+ *                 kern 1: 1..3 with ty = 4, 2..3 with ty = 8);
+ *   tune[3] cz:   z-chunk length in planes (1..4096, or 0 = chosen from the grid).
+ * Shapes change launch geometry only: every grid point gets the same arithmetic,
+ * while reductions (residual norms, the step size d) sum their block partials in a
+ * different order.  Errors: HFCI_E_ARG. */
+hfci_status hfci_op_set_tune(hfci_op* op, int prec, const int* tune4);
+hfci_status hfci_op_get_tune(const hfci_op* op, int prec, int* tune4);
+
+/* Launch-shape autotuner: times the middle-factor kernel of the fixed-point
+ * iteration (the dominant launch) over nsys systems (1..64, e.g. the number of
+ * shifted systems that usually iterate together) for every valid shape, keeps the
+ * fastest for this operator and precision and writes it to best4 (HOST, may be
+ * NULL).  timings (HOST, may be NULL if cap = 0) receives up to cap rows of
+ * {kern, ty, pd, cz, milliseconds per launch}; *count (may be NULL) the number of
+ * shapes timed.  Uses the context's workspace (2 nsys vectors of the precision);
+ * the operator's inputs and outputs of other calls are not touched.  Timing-based,
+ * so two runs may pick different shapes (results then differ only in the summation
+ * order of reductions).  Errors: HFCI_E_ARG. */
+hfci_status hfci_op_autotune(hfci_op* op, int prec, int nsys, int* best4, double* timings, int cap,
+                             int* count);
 
 /* y_k = (A - shift I) x_k for k < nvec (normalised A).  prec: HFCI_F64
  * (complex128 x, y) or HFCI_F32 (complex64).  x and y are DEVICE buffers of

@@ -235,6 +235,43 @@ __global__ __launch_bounds__(NT) void fp_check_kernel(const double* __restrict__
   }
 }
 
+// After the first fixed-point step (from y = 0, which never meets the stopping test
+// unless f = 0): every system is active and listed; one step is counted unless the
+// adaptive test already holds (f = 0).
+__global__ void fp_start_kernel(int nsys, int sys0, int nrhs, const double* __restrict__ fnorm2, int fixed,
+                                int* __restrict__ active, int* __restrict__ steps, int* __restrict__ list) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nsys) {
+    active[s] = 1;
+    list[s] = s;
+    steps[s] = (fixed || fnorm2[(sys0 + s) % nrhs] > 0.0) ? 1 : 0;
+  }
+}
+
+// Stream compaction of the active flags in one block: wave ballots give each lane its
+// rank within the wave, LDS carries the wave totals, chunks of NT go in order.
+__global__ __launch_bounds__(NT) void build_list_kernel(const int* __restrict__ active, int nsys,
+                                                        int* __restrict__ list) {
+  __shared__ int wtot[NT / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int base = 0;
+  for (int c0 = 0; c0 < nsys; c0 += NT) {
+    const int s = c0 + threadIdx.x;
+    const bool a = s < nsys && active[s] != 0;
+    const unsigned long long m = __ballot(a);
+    const int below = __popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+    if (lane == 0) wtot[wid] = __popcll(m);
+    __syncthreads();
+    int off = base;
+    for (int w = 0; w < wid; ++w) off += wtot[w];
+    if (a) list[off + below] = s;
+    int tot = 0;
+    for (int w = 0; w < NT / 64; ++w) tot += wtot[w];
+    base += tot;
+    __syncthreads();
+  }
+}
+
 __global__ void dfinish_kernel(const double* __restrict__ sums, int nrhs, double* __restrict__ d) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < nrhs) {
@@ -369,6 +406,17 @@ void launch_dfinish(hipStream_t st, const double* sums, int nrhs, double* d) {
 
 void launch_set_int(hipStream_t st, int* p, int v, int count) {
   if (count > 0) hipLaunchKernelGGL(set_int_kernel, dim3((count + 255) / 256), dim3(256), 0, st, p, v, count);
+}
+
+void launch_fp_start(hipStream_t st, int nsys, int sys0, int nrhs, const double* fnorm2, bool fixed, int* active,
+                     int* steps, int* list) {
+  if (nsys > 0)
+    hipLaunchKernelGGL(fp_start_kernel, dim3((nsys + 255) / 256), dim3(256), 0, st, nsys, sys0, nrhs, fnorm2,
+                       fixed ? 1 : 0, active, steps, list);
+}
+
+void launch_build_list(hipStream_t st, const int* active, int nsys, int* list) {
+  if (nsys > 0) hipLaunchKernelGGL(build_list_kernel, dim3(1), dim3(NT), 0, st, active, nsys, list);
 }
 
 void launch_copy_active_f(hipStream_t st, float2* d, const float2* s, const int* a, int nsys, size_t n) {

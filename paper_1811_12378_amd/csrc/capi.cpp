@@ -344,6 +344,63 @@ hfci_status hfci_op_info(const hfci_op* op, double* o) {
   HFCI_API_END
 }
 
+hfci_status hfci_op_set_tune(hfci_op* op, int prec, const int* t3) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(op && t3, "NULL argument");
+  HFCI_REQUIRE(prec == HFCI_F32 || prec == HFCI_F64, "prec must be HFCI_F32 or HFCI_F64");
+  KernelTune t;
+  t.kern = t3[0];
+  t.ty = t3[1];
+  t.pd = t3[2];
+  t.cz = t3[3];
+  HFCI_REQUIRE(tune_valid(t), "tune must be {0, ty in {4, 8}, pd in {1, 2}, cz} or {1, 4, pd in 1..3, cz} or "
+                              "{1, 8, pd in {2, 3}, cz}, cz in [0, 4096]");
+  (prec == HFCI_F32 ? op->g.tune32 : op->g.tune64) = t;
+  return HFCI_OK;
+  HFCI_API_END
+}
+
+hfci_status hfci_op_get_tune(const hfci_op* op, int prec, int* t3) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(op && t3, "NULL argument");
+  HFCI_REQUIRE(prec == HFCI_F32 || prec == HFCI_F64, "prec must be HFCI_F32 or HFCI_F64");
+  const KernelTune& t = prec == HFCI_F32 ? op->g.tune32 : op->g.tune64;
+  t3[0] = t.kern;
+  t3[1] = t.ty;
+  t3[2] = t.pd;
+  t3[3] = t.cz;
+  return HFCI_OK;
+  HFCI_API_END
+}
+
+hfci_status hfci_op_autotune(hfci_op* op, int prec, int nsys, int* best4, double* timings, int cap, int* count) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(op, "NULL operator");
+  HFCI_REQUIRE(prec == HFCI_F32 || prec == HFCI_F64, "prec must be HFCI_F32 or HFCI_F64");
+  HFCI_REQUIRE(nsys >= 1 && nsys <= 64, "nsys must be in [1, 64]");
+  HFCI_REQUIRE(cap >= 0 && (cap == 0 || timings != nullptr), "timings is NULL");
+  DeviceGuard dg(op->device);
+  std::vector<std::pair<KernelTune, double>> tm;
+  const KernelTune b = prec == HFCI_F32 ? autotune_shapes<float2>(*op, nsys, tm) : autotune_shapes<double2>(*op, nsys, tm);
+  if (best4) {
+    best4[0] = b.kern;
+    best4[1] = b.ty;
+    best4[2] = b.pd;
+    best4[3] = b.cz;
+  }
+  const int m = std::min<int>(cap, (int)tm.size());
+  for (int k = 0; k < m; ++k) {
+    timings[5 * k + 0] = tm[k].first.kern;
+    timings[5 * k + 1] = tm[k].first.ty;
+    timings[5 * k + 2] = tm[k].first.pd;
+    timings[5 * k + 3] = tm[k].first.cz;
+    timings[5 * k + 4] = tm[k].second;
+  }
+  if (count) *count = (int)tm.size();
+  return HFCI_OK;
+  HFCI_API_END
+}
+
 hfci_status hfci_apply(const hfci_op* op, hfci_c128 shift, int prec, int nvec, const void* x, void* y) {
   HFCI_API_BEGIN
   HFCI_REQUIRE(op && x && y, "NULL argument");
@@ -408,7 +465,8 @@ hfci_status hfci_contour_create(const hfci_op* op, int J, double t, double eps, 
     c->nu.resize(J);
     c->z0.resize(J);
     c->pz.resize(J);
-    c->coef.resize((size_t)J * q);
+    c->cstride = q + std::max(q - 1, 1);
+    c->coef.resize((size_t)J * c->cstride);
     c->pdev.resize(J);
     const std::vector<cd> bd = rectangle_boundary(op->b1, op->b2, op->rho2, 2000);
     for (int j = 0; j < J; ++j) {
@@ -423,13 +481,18 @@ hfci_status hfci_contour_create(const hfci_op* op, int J, double t, double eps, 
         optimise_delta(zj, op->b1, op->b2, op->rho2, q, c->delta[j], c->nu[j], c->z0[j]);
       }
       if (!(c->nu[j] < 1.0)) throw Error(HFCI_E_CONTOUR, "no contraction for a pole (nu >= 1)");
-      stage_coefficients(zj, c->z0[j], c->delta[j], q, &c->coef[(size_t)j * q], c->pz[j]);
+      FactorCoef* cj = &c->coef[(size_t)j * c->cstride];
+      factor_coefficients(zj, c->z0[j], c->delta[j], q, cj, cj + q, c->pz[j]);
+      for (int k = 0; k < c->cstride; ++k)
+        if (!std::isfinite(cj[k].a_re) || !std::isfinite(cj[k].a_im) || !std::isfinite(cj[k].b_re) ||
+            !std::isfinite(cj[k].b_im))
+          throw Error(HFCI_E_NUMERIC, "non-finite factor coefficient");
       const cd zz = zj - c->z0[j];
       c->pdev[j] = PoleDev{c->z0[j].real(), c->z0[j].imag(), zz.real(), zz.imag()};
     }
-    HFCI_HIP(hipMalloc(&c->d_coef, c->coef.size() * sizeof(StageCoef)));
+    HFCI_HIP(hipMalloc(&c->d_coef, c->coef.size() * sizeof(FactorCoef)));
     HFCI_HIP(hipMalloc(&c->d_poles, c->pdev.size() * sizeof(PoleDev)));
-    HFCI_HIP(hipMemcpy(c->d_coef, c->coef.data(), c->coef.size() * sizeof(StageCoef), hipMemcpyHostToDevice));
+    HFCI_HIP(hipMemcpy(c->d_coef, c->coef.data(), c->coef.size() * sizeof(FactorCoef), hipMemcpyHostToDevice));
     HFCI_HIP(hipMemcpy(c->d_poles, c->pdev.data(), c->pdev.size() * sizeof(PoleDev), hipMemcpyHostToDevice));
   } catch (...) {
     if (c->d_coef) (void)hipFree(c->d_coef);

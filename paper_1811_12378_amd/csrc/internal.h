@@ -112,9 +112,11 @@ struct Contour {
   double t = 0, eps = 0;
   std::vector<cd> z, sigma, z0, pz;  // poles, weights, Taylor centres, p~(z)
   std::vector<double> delta, nu;
-  std::vector<StageCoef> coef;       // [J][q]
+  // per pole: q factors of L = p~(B)/p~(z), then max(q-1, 1) factors building y1
+  int cstride = 0;                   // = q + max(q-1, 1)
+  std::vector<FactorCoef> coef;      // [J][cstride]
   std::vector<PoleDev> pdev;         // [J]
-  StageCoef* d_coef = nullptr;       // device copies
+  FactorCoef* d_coef = nullptr;      // device copies
   PoleDev* d_poles = nullptr;
 };
 
@@ -184,9 +186,12 @@ cd ptilde(cd lam, cd z0, double delta, int q);
 double rate_on_boundary(double delta, cd z, cd z0, int q, const std::vector<cd>& boundary);
 std::vector<cd> rectangle_boundary(double b1, double b2, double rho2, int per_side);
 void optimise_delta(cd z, double b1, double b2, double rho2, int q, double& delta, double& nu, cd& z0);
-void stage_coefficients(cd z, cd z0, double delta, int q, StageCoef* out, cd& pz);
+std::vector<cd> poly_roots(std::vector<cd> coeffs);
+void factor_coefficients(cd z, cd z0, double delta, int q, FactorCoef* out_L, FactorCoef* out_P, cd& pz);
 
 // ---- solver.cpp ----
+template <typename T2>
+KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, double>>& timings);
 struct FciStats {
   long long matvecs = 0, fp_steps = 0;
 };

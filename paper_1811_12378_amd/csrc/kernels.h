@@ -9,18 +9,28 @@
 
 namespace hfci {
 
-// Geometry and operator scalars of the normalised A = (s/h^2) L7 - kappa - i D.
+// Launch shape of the z-marching stencil kernels: kern 0 keeps the in-plane neighbours
+// as cached global loads, kern 1 stages each plane through LDS; a 64 x ty thread tile,
+// HBM streams prefetched pd planes ahead, z-chunks of cz planes (0: from the grid size).
+struct KernelTune {
+  int kern = 1, ty = 8, pd = 2, cz = 0;
+};
+
+// Geometry and operator scalars of the normalised A = (s/h^2) L7 - kappa - i D, plus
+// the launch shapes used for complex64 and complex128 vectors.
 struct GridDesc {
   int nx, ny, nz;
   int damp_cells;        // L
   double damp_scale;     // rho2 / L^2, so D = damp_scale * depth^2
   double s_h2;           // s / h^2
+  KernelTune tune32, tune64;
 };
+bool tune_valid(const KernelTune& t);
 
-// Coefficients of one Horner stage of the exponential-Taylor step, per pole:
-//   w_out = cB * (A - z0) w_in + alpha * y + gam * f.
-struct StageCoef {
-  double cB_re, cB_im, al_re, al_im, ga_re, ga_im;
+// One linear factor of the product-form fixed-point step, per pole:
+//   w_out = a * (A - z0) w_in + b * w_in   (+ y1 on the last factor of a step).
+struct FactorCoef {
+  double a_re, a_im, b_re, b_im;
 };
 
 // Per-pole constants used inside the stage kernels.
@@ -29,28 +39,37 @@ struct PoleDev {
   double zz_re, zz_im;   // z - z0 (residual of the first stage)
 };
 
-// Work description of one batched fixed-point launch: systems s in [0, nsys),
-// global system index gs = sys0 + s, pole = gs / nrhs, rhs = gs % nrhs.
+// Kinds of factor launch (bit set):
+//   RESID  the input is the iterate y; also forms |f - (A - z) y|^2 partials
+//   ADD    adds the step's constant vector y1 (last factor of a step)
+//   DUAL   writes the output to a second vector as well
+//   INF    the input is the system's right-hand side f (first factor of step one)
+enum : int { kFacResid = 1, kFacAdd = 2, kFacDual = 4, kFacInF = 8 };
+
+// Work description of one batched factor launch over the systems listed in
+// list[0..count) (indices s in [0, nsys), global system gs = sys0 + s,
+// pole = gs / nrhs, rhs = gs % nrhs).  Vectors are strided by n per system (per rhs for f).
 template <typename T2>
-struct StageArgs {
-  const T2* win;         // stage input (w or y), stride n per system
-  const T2* y;           // current iterate, stride n per system
-  const T2* f;           // right-hand sides, stride n per rhs
-  T2* wout;              // stage output, stride n per system
-  const StageCoef* coef; // [pole][stage], stage index m in [0, q)
-  const PoleDev* poles;  // [pole]
-  const int* active;     // [nsys], 0 = converged / skipped
-  double* partial;       // residual partial sums [nsys][nblk] (first stage only)
-  int nsys, sys0, nrhs, q, m;
+struct FactorArgs {
+  const T2* win;          // input w (or y with RESID), per system
+  const T2* f;            // right-hand sides, per rhs
+  const T2* y1;           // constant term of the step (ADD), per system
+  T2* wout;               // output, per system
+  T2* wout2;              // second output (DUAL), per system
+  const FactorCoef* coef; // [pole][cstride]; this launch uses entry k
+  const PoleDev* poles;   // [pole]
+  const int* list;        // DEVICE array of the systems to run, count entries
+  double* partial;        // residual partial sums [nsys][nblk] (RESID only)
+  int count, sys0, nrhs, cstride, k;
 };
 
 template <typename T2>
 struct Launch {
   static void apply(hipStream_t st, const GridDesc& g, const void* kappa, double shift_re,
                     double shift_im, int nvec, const T2* x, T2* y);
-  // first: w_in is y and a residual partial is produced; the caller picks m.
-  static void stage(hipStream_t st, const GridDesc& g, const void* kappa,
-                    const StageArgs<T2>& a, bool first);
+  // one factor launch of the given kind (kFac* bits) over a.list; false for an
+  // unsupported combination of bits (nothing is launched)
+  static bool factor(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a, int kind);
   // partial sums for the step size d: conj(A w).f and |A w|^2, per rhs.
   static void dstep_partials(hipStream_t st, const GridDesc& g, const void* kappa, int nrhs,
                              const T2* w, const T2* f, double* partial);
@@ -92,5 +111,11 @@ void launch_fp_check(hipStream_t st, const double* partial, int nblk, int nsys, 
 // d_r = num_r / den_r from reduced sums [nrhs][3]
 void launch_dfinish(hipStream_t st, const double* sums, int nrhs, double* d);
 void launch_set_int(hipStream_t st, int* p, int v, int count);
+// start of the fixed-point iteration: every system active and listed, steps = 1 (or 0
+// for a zero right-hand side in adaptive mode), after the first step.
+void launch_fp_start(hipStream_t st, int nsys, int sys0, int nrhs, const double* fnorm2, bool fixed,
+                     int* active, int* steps, int* list);
+// list[0..count) = indices s with active[s] != 0, in increasing order (one block).
+void launch_build_list(hipStream_t st, const int* active, int nsys, int* list);
 
 }  // namespace hfci

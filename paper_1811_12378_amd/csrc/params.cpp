@@ -1,6 +1,6 @@
 // Host-side parameters of the method: spectrum rectangle, contour poles and weights,
-// the delta search of the exponential-Taylor iteration, and the Horner stage
-// coefficients that the stage kernels consume.
+// the delta search of the exponential-Taylor iteration, and the linear-factor
+// coefficients of its product form that the stage kernels consume.
 #include <algorithm>
 #include <cmath>
 
@@ -108,35 +108,132 @@ void optimise_delta(cd z, double b1, double b2, double rho2, int q, double& delt
   nu = vm;
 }
 
-// Horner re-association of one step of eq. fix-pt-exp.  With B = -i delta (A - z0 I),
-// beta = -i delta (z - z0), g = i delta f, the step's unrolled recursion gives
-//   y + k_1 + ... + k_q = sum_{m=0..q} B^m a_m,  a_m = y/m! + e_m g,
-//   e_m = sum_{j=m+1..q} beta^(j-1-m)/j!   (e_q = 0),
-// so y_new = (Horner over m = q..0) / p~(z).  Stage m (q-1 down to 0) computes
-//   w_m = cB_m (A - z0) w_{m+1} + alpha_m y + gamma_m f
-// with w_q = y (the 1/q! is folded into cB_{q-1}) and 1/p~(z) folded into stage 0.
-void stage_coefficients(cd z, cd z0, double delta, int q, StageCoef* out, cd& pz) {
+// Roots of sum_k c[k] x^k (c.back() != 0, degree <= 16) by the Aberth-Ehrlich
+// simultaneous iteration (Aberth 1973), then two Newton corrections per root.
+std::vector<cd> poly_roots(std::vector<cd> c) {
+  const int deg = (int)c.size() - 1;
+  std::vector<cd> r;
+  if (deg < 1) return r;
+  const cd lead = c.back();
+  for (cd& v : c) v /= lead;
+  // start on a circle of the Fujiwara-type radius max |c_k|^(1/(deg-k)), rotated off the axes
+  double R = 0.0;
+  for (int k = 0; k < deg; ++k) R = std::max(R, std::pow(std::abs(c[k]), 1.0 / (deg - k)));
+  R = std::max(R, 1e-3);
+  r.resize(deg);
+  for (int k = 0; k < deg; ++k) r[k] = std::polar(R, 2.0 * M_PI * k / deg + 0.4);
+  auto eval = [&](cd x, cd& p, cd& dp) {
+    p = c[deg];
+    dp = 0.0;
+    for (int k = deg - 1; k >= 0; --k) {
+      dp = dp * x + p;
+      p = p * x + c[k];
+    }
+  };
+  for (int it = 0; it < 500; ++it) {
+    double worst = 0.0;
+    for (int k = 0; k < deg; ++k) {
+      cd p, dp;
+      eval(r[k], p, dp);
+      if (p == cd(0.0, 0.0)) continue;
+      const cd ratio = p / dp;
+      cd sum(0.0, 0.0);
+      for (int j = 0; j < deg; ++j)
+        if (j != k) sum += 1.0 / (r[k] - r[j]);
+      const cd step = ratio / (1.0 - ratio * sum);
+      r[k] -= step;
+      worst = std::max(worst, std::abs(step) / std::max(std::abs(r[k]), 1e-300));
+    }
+    if (worst < 1e-15) break;
+  }
+  for (cd& x : r)
+    for (int k = 0; k < 2; ++k) {
+      cd p, dp;
+      eval(x, p, dp);
+      if (dp != cd(0.0, 0.0)) x -= p / dp;
+    }
+  return r;
+}
+
+namespace {
+
+// Leja order: largest modulus first, then each next root maximises the product of
+// its distances to the roots already taken (keeps partial products balanced).
+std::vector<cd> leja_order(std::vector<cd> r) {
+  std::vector<cd> out;
+  if (r.empty()) return out;
+  size_t k0 = 0;
+  for (size_t k = 1; k < r.size(); ++k)
+    if (std::abs(r[k]) > std::abs(r[k0])) k0 = k;
+  out.push_back(r[k0]);
+  r.erase(r.begin() + k0);
+  while (!r.empty()) {
+    size_t best = 0;
+    double bv = -1.0;
+    for (size_t k = 0; k < r.size(); ++k) {
+      double lp = 0.0;
+      for (const cd& o : out) lp += std::log(std::abs(r[k] - o) + 1e-300);
+      if (lp > bv) {
+        bv = lp;
+        best = k;
+      }
+    }
+    out.push_back(r[best]);
+    r.erase(r.begin() + best);
+  }
+  return out;
+}
+
+}  // namespace
+
+// Product form of one step of eq. fix-pt-exp.  With B = -i delta (A - z0 I),
+// beta = -i delta (z - z0) and g = i delta f, unrolling the k-recursion gives
+//   y_new = [ p~(B) y + P2(B) g ] / p~(z),   P2(x) = sum_{m<q} e_m x^m,
+//   e_m = sum_{j=m+1..q} beta^(j-1-m) / j!,
+// i.e. an affine map y_new = L y + y1 with L = p~(B)/p~(z) (the error propagator of
+// Thm 4.2) and y1 = P2(B) g / p~(z) (the first step from y = 0).  Both polynomials are
+// applied as products of linear factors over their roots, L = s^q prod_k (B - rho_k)
+// with p~(x) = (1/q!) prod (x - rho_k) and s = (q! p~(z))^(-1/q), so every factor is
+//   w <- a (A - z0) w + b w,   a = -i delta s,  b = -s rho_k,
+// and one full step is q such factors plus the added y1.  y1 uses the q-1 roots mu_k
+// of P2 (leading coefficient e_{q-1} = 1/q!) in the same way; for q = 1, y1 = g / p~(z)
+// is a single factor with a = 0.
+// out_L: q factors, out_P: max(q-1, 1) factors, both in application order.
+void factor_coefficients(cd z, cd z0, double delta, int q, FactorCoef* out_L, FactorCoef* out_P, cd& pz) {
   const cd beta = cd(0.0, -delta) * (z - z0);
+  const cd mid(0.0, -delta);  // B = mid * (A - z0)
   pz = ptilde(z, z0, delta, q);
-  const cd inv_pz = 1.0 / pz;
   std::vector<double> fact(q + 1, 1.0);
   for (int j = 1; j <= q; ++j) fact[j] = fact[j - 1] * j;
+  // p~(x) = sum_m x^m / m!
+  std::vector<cd> cp(q + 1);
+  for (int m = 0; m <= q; ++m) cp[m] = 1.0 / fact[m];
+  const std::vector<cd> rho = leja_order(poly_roots(cp));
+  const cd sL = std::pow(1.0 / (fact[q] * pz), 1.0 / q);
+  for (int k = 0; k < q; ++k) {
+    const cd a = sL * mid, b = -sL * rho[k];
+    out_L[k] = FactorCoef{a.real(), a.imag(), b.real(), b.imag()};
+  }
+  const cd g_scale = cd(0.0, delta) / pz;  // y1 = P2(B) (i delta f) / p~(z)
+  if (q == 1) {
+    // P2 = e_0 = 1
+    out_P[0] = FactorCoef{0.0, 0.0, g_scale.real(), g_scale.imag()};
+    return;
+  }
+  std::vector<cd> ce(q);
   for (int m = 0; m < q; ++m) {
     cd e(0.0, 0.0), bp(1.0, 0.0);
     for (int j = m + 1; j <= q; ++j) {
       e += bp / fact[j];
       bp *= beta;
     }
-    cd cB = cd(0.0, -delta);
-    if (m == q - 1) cB /= fact[q];
-    cd al = cd(1.0 / fact[m], 0.0);
-    cd ga = cd(0.0, delta) * e;
-    if (m == 0) {
-      cB *= inv_pz;
-      al *= inv_pz;
-      ga *= inv_pz;
-    }
-    out[m] = StageCoef{cB.real(), cB.imag(), al.real(), al.imag(), ga.real(), ga.imag()};
+    ce[m] = e;
+  }
+  const std::vector<cd> mu = leja_order(poly_roots(ce));
+  const cd s2 = std::pow(g_scale * ce[q - 1], 1.0 / (q - 1));
+  for (int k = 0; k < q - 1; ++k) {
+    const cd a = s2 * mid, b = -s2 * mu[k];
+    out_P[k] = FactorCoef{a.real(), a.imag(), b.real(), b.imag()};
   }
 }
 

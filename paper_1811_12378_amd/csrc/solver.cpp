@@ -2,10 +2,12 @@
 // the FCI preconditioner (Algorithm 1) and flexible GMRES(m) (Sec. 2) in FP64.
 //
 // All (pole, right-hand side) shifted systems of one FCI application advance together:
-// every Horner stage is a single launch over all systems, so a step at 256^3 with
-// 16 poles x 8 RHS is one launch of ~260k workgroups.  Systems stop independently
-// (per-system active flags decided on the device from the residual norms); the host
-// only reads the flags to know when every system has stopped.
+// every factor of a fixed-point step is a single launch over the systems still
+// iterating, so a step at 256^3 with 16 poles x 8 RHS is one launch of ~260k
+// workgroups.  Systems stop independently: the device turns residual norms into
+// per-system active flags and a compacted list of the systems left, which the next
+// launches read; the host reads the flags once per step to size the grid and to know
+// when every system has stopped.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -40,7 +42,10 @@ void copy_active<double2>(hipStream_t st, double2* d, const double2* s, const in
   launch_copy_active_d(st, d, s, a, nsys, n);
 }
 
-// Iterate eq. fix-pt-exp (Horner-staged) for systems gs in [sys0, sys0 + nsys) from y = 0.
+// Iterate eq. fix-pt-exp for systems gs in [sys0, sys0 + nsys) from y = 0, in the
+// product form of params.cpp: step one builds y1 = P2(B) g / p~(z) (written to y1 and
+// y), every later step is y <- L y + y1 as q factor launches, the first of which also
+// forms the residual of the current y for the stopping test (Table 4's "reduced by 5").
 template <typename T2>
 void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sys0, int nsys,
             int fixed_steps, double reduce, int max_steps, int* steps_out, FciStats& st) {
@@ -49,104 +54,125 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
   const size_t n = op.n;
   const int q = c.q;
   const size_t vbytes = n * sizeof(T2);
-  T2* wA = (T2*)ctx.ws.get("fp_wA", (size_t)nsys * vbytes);
-  T2* wB = (q >= 3) ? (T2*)ctx.ws.get("fp_wB", (size_t)nsys * vbytes) : nullptr;
-  const int nblk = Launch<T2>::partial_blocks(op.g);
-  double* partial = (double*)ctx.ws.get("fp_partial", (size_t)nsys * nblk * sizeof(double));
-  int* active = (int*)ctx.ws.get("fp_active", (size_t)nsys * sizeof(int));
-  int* steps = (int*)ctx.ws.get("fp_steps", (size_t)nsys * sizeof(int));
-  double* rnorm2 = (double*)ctx.ws.get("fp_rnorm2", (size_t)nsys * sizeof(double));
-  const int nb = blas_blocks(n);
-  double* fpart = (double*)ctx.ws.get("fp_fpart", (size_t)nrhs * nb * sizeof(double));
-  double* fnorm2 = (double*)ctx.ws.get("fp_fnorm2", (size_t)nrhs * sizeof(double));
-
-  launch_fill_zero(s, y, (size_t)nsys * vbytes);
-  for (int r = 0; r < nrhs; ++r) launch_norm2_partial(s, f + (size_t)r * n, sizeof(T2) == 8, n, fpart + (size_t)r * nb);
-  launch_reduce(s, fpart, nb, nrhs, fnorm2);
-  launch_set_int(s, active, 1, nsys);
-  launch_set_int(s, steps, 0, nsys);
-
-  StageArgs<T2> a{};
-  a.y = y;
-  a.f = f;
-  a.coef = c.d_coef;
-  a.poles = c.d_poles;
-  a.active = active;
-  a.partial = partial;
-  a.nsys = nsys;
-  a.sys0 = sys0;
-  a.nrhs = nrhs;
-  a.q = q;
-  const void* kap = Prec<T2>::kappa(op);
   const bool fixed = fixed_steps > 0;
   const int cap = fixed ? fixed_steps : max_steps;
-  Profiler& pr = ctx.prof;
-  // algorithmic bytes of one stage launch: per active system its own vectors (first stage: y in,
-  // w out; later stages: w in, y in, w out), plus kappa and each active rhs's f once per launch
-  const double e = (double)sizeof(T2), ek = e / 2.0;
-  std::vector<int> hact(nsys, 1);
-  auto launch_bytes = [&](double per_sys) {
-    int na = 0;
-    std::vector<char> rhs_used(nrhs, 0);
-    for (int k = 0; k < nsys; ++k)
-      if (hact[k]) {
-        ++na;
-        rhs_used[(sys0 + k) % nrhs] = 1;
-      }
-    int nr = 0;
-    for (char u : rhs_used) nr += u;
-    return (double)n * (per_sys * e * na + ek + e * nr);
-  };
-  int prev_active = nsys;
-  for (int it = 0; it <= cap; ++it) {
-    if (fixed && it == cap) break;  // exact count: no final residual check needed
-    // first stage: w_{q-1} from y, plus ||f - (A - z) y||^2 partials
-    a.win = y;
-    a.wout = wA;
-    a.m = q - 1;
-    if (pr.on) pr.begin(s);
-    Launch<T2>::stage(s, op.g, kap, a, true);
-    if (pr.on) pr.end(s, HFCI_PROF_FP_FIRST, launch_bytes(2.0));
-    launch_fp_check(s, partial, nblk, nsys, sys0, nrhs, fnorm2, fixed_steps, reduce, max_steps, active, steps,
-                    rnorm2);
-    int now_active = nsys;
-    if (!fixed) {
-      HFCI_HIP(hipMemcpyAsync(ctx.pinned_int, active, nsys * sizeof(int), hipMemcpyDeviceToHost, s));
-      HFCI_HIP(hipStreamSynchronize(s));
-      if (pr.on) pr.harvest();
-      now_active = 0;
-      for (int k = 0; k < nsys; ++k) {
-        hact[k] = ctx.pinned_int[k] != 0;
-        now_active += hact[k];
-      }
-    }
-    const double stage_bytes = pr.on ? launch_bytes(3.0) : 0.0;
-    st.matvecs += prev_active;
-    if (now_active == 0) break;
-    st.matvecs += (long long)(q - 1) * now_active;
-    st.fp_steps += now_active;
-    prev_active = now_active;
-    // middle stages ping-pong between wA and wB, the last stage writes y in place
-    T2* cur = wA;
-    for (int m = q - 2; m >= 1; --m) {
-      T2* nxt = (cur == wA) ? wB : wA;
-      a.win = cur;
-      a.wout = nxt;
-      a.m = m;
+  int* steps = (int*)ctx.ws.get("fp_steps", (size_t)nsys * sizeof(int));
+  if (cap <= 0) {
+    launch_fill_zero(s, y, (size_t)nsys * vbytes);
+    launch_set_int(s, steps, 0, nsys);
+  } else {
+    T2* y1 = (T2*)ctx.ws.get("fp_y1", (size_t)nsys * vbytes);
+    T2* wA = (T2*)ctx.ws.get("fp_wA", (size_t)nsys * vbytes);
+    T2* wB = (q >= 3) ? (T2*)ctx.ws.get("fp_wB", (size_t)nsys * vbytes) : nullptr;
+    const int nblk = Launch<T2>::partial_blocks(op.g);
+    double* partial = (double*)ctx.ws.get("fp_partial", (size_t)nsys * nblk * sizeof(double));
+    int* active = (int*)ctx.ws.get("fp_active", (size_t)nsys * sizeof(int));
+    int* list = (int*)ctx.ws.get("fp_list", (size_t)nsys * sizeof(int));
+    double* rnorm2 = (double*)ctx.ws.get("fp_rnorm2", (size_t)nsys * sizeof(double));
+    const int nb = blas_blocks(n);
+    double* fpart = (double*)ctx.ws.get("fp_fpart", (size_t)nrhs * nb * sizeof(double));
+    double* fnorm2 = (double*)ctx.ws.get("fp_fnorm2", (size_t)nrhs * sizeof(double));
+    for (int r = 0; r < nrhs; ++r)
+      launch_norm2_partial(s, f + (size_t)r * n, sizeof(T2) == 8, n, fpart + (size_t)r * nb);
+    launch_reduce(s, fpart, nb, nrhs, fnorm2);
+    launch_fp_start(s, nsys, sys0, nrhs, fnorm2, fixed, active, steps, list);
+
+    FactorArgs<T2> a{};
+    a.f = f;
+    a.y1 = y1;
+    a.coef = c.d_coef;
+    a.poles = c.d_poles;
+    a.list = list;
+    a.partial = partial;
+    a.sys0 = sys0;
+    a.nrhs = nrhs;
+    a.cstride = c.cstride;
+    const void* kap = Prec<T2>::kappa(op);
+    Profiler& pr = ctx.prof;
+    // algorithmic bytes of one launch: per listed system its own vectors (vec_per_sys of
+    // them), plus kappa once and the right-hand sides of the listed systems once each
+    const double e = (double)sizeof(T2), ek = e / 2.0;
+    std::vector<int> hact(nsys, 1);
+    auto launch_bytes = [&](double vec_per_sys, bool reads_f) {
+      int na = 0;
+      std::vector<char> rhs_used(nrhs, 0);
+      for (int k = 0; k < nsys; ++k)
+        if (hact[k]) {
+          ++na;
+          rhs_used[(sys0 + k) % nrhs] = 1;
+        }
+      int nr = 0;
+      for (char u : rhs_used) nr += u;
+      return (double)n * (vec_per_sys * e * na + ek + (reads_f ? e * nr : 0.0));
+    };
+    auto launch = [&](int kind, int k, const T2* win, T2* wout, T2* wout2, int cls, double bytes) {
+      a.k = k;
+      a.win = win;
+      a.wout = wout;
+      a.wout2 = wout2;
       if (pr.on) pr.begin(s);
-      Launch<T2>::stage(s, op.g, kap, a, false);
-      if (pr.on) pr.end(s, HFCI_PROF_FP_STAGE, stage_bytes);
-      cur = nxt;
+      HFCI_REQUIRE(Launch<T2>::factor(s, op.g, kap, a, kind), "internal: unsupported factor kind");
+      if (pr.on) pr.end(s, cls, bytes);
+    };
+
+    // ---- step one: y1 = prod over the max(q-1, 1) factors of P2, applied to f ----
+    a.count = nsys;
+    const int nP = std::max(q - 1, 1);
+    {
+      const T2* cur = nullptr;
+      for (int k = 0; k < nP; ++k) {
+        const bool first = k == 0, last = k == nP - 1;
+        T2* dst = last ? y1 : ((cur == wA) ? wB : wA);
+        const int kind = (first ? kFacInF : 0) | (last ? kFacDual : 0);
+        const double bytes = pr.on ? launch_bytes(1.0 + (first ? 0.0 : 1.0) + (last ? 1.0 : 0.0), first) : 0.0;
+        launch(kind, q + k, cur, dst, last ? y : nullptr, kind == 0 ? HFCI_PROF_FP_STAGE : HFCI_PROF_FP_INIT,
+               bytes);
+        cur = dst;
+      }
+      st.matvecs += (long long)(q - 1) * nsys;
+      st.fp_steps += nsys;
     }
-    if (q >= 2) {
-      a.win = cur;
-      a.wout = y;
-      a.m = 0;
-      if (pr.on) pr.begin(s);
-      Launch<T2>::stage(s, op.g, kap, a, false);
-      if (pr.on) pr.end(s, HFCI_PROF_FP_STAGE, stage_bytes);
-    } else {
-      copy_active<T2>(s, y, wA, active, nsys, n);
+
+    // ---- steps two and on: y <- L y + y1 ----
+    int nact = nsys;
+    for (int it = 1; it <= cap; ++it) {
+      if (fixed && it == cap) break;  // exact count: no final residual check needed
+      // first factor from y, plus ||f - (A - z) y||^2 partials of the current iterate
+      const int kind0 = kFacResid | (q == 1 ? kFacAdd : 0);
+      launch(kind0, 0, y, wA, nullptr, HFCI_PROF_FP_FIRST,
+             pr.on ? launch_bytes(q == 1 ? 3.0 : 2.0, true) : 0.0);
+      st.matvecs += nact;
+      launch_fp_check(s, partial, nblk, nsys, sys0, nrhs, fnorm2, fixed_steps, reduce, max_steps, active, steps,
+                      rnorm2);
+      if (!fixed) {
+        // the list shrinks only in adaptive mode (a fixed count keeps every system; one
+        // stopped by a NaN residual then just carries its NaN on, reported by the caller)
+        launch_build_list(s, active, nsys, list);
+        HFCI_HIP(hipMemcpyAsync(ctx.pinned_int, active, nsys * sizeof(int), hipMemcpyDeviceToHost, s));
+        HFCI_HIP(hipStreamSynchronize(s));
+        if (pr.on) pr.harvest();
+        nact = 0;
+        for (int k = 0; k < nsys; ++k) {
+          hact[k] = ctx.pinned_int[k] != 0;
+          nact += hact[k];
+        }
+      }
+      if (nact == 0) break;
+      a.count = nact;
+      st.matvecs += (long long)(q - 1) * nact;
+      st.fp_steps += nact;
+      if (q == 1) {
+        copy_active<T2>(s, y, wA, active, nsys, n);
+        continue;
+      }
+      // middle factors ping-pong between wA and wB, the last adds y1 and writes y
+      T2* cur = wA;
+      for (int k = 1; k < q - 1; ++k) {
+        T2* nxt = (cur == wA) ? wB : wA;
+        launch(0, k, cur, nxt, nullptr, HFCI_PROF_FP_STAGE, pr.on ? launch_bytes(2.0, false) : 0.0);
+        cur = nxt;
+      }
+      launch(kFacAdd, q - 1, cur, y, nullptr, HFCI_PROF_FP_LAST, pr.on ? launch_bytes(3.0, false) : 0.0);
     }
   }
   if (steps_out) {
@@ -154,11 +180,98 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
     HFCI_HIP(hipStreamSynchronize(s));
     std::memcpy(steps_out, ctx.pinned_int, nsys * sizeof(int));
   }
-  if (pr.on) {
+  if (ctx.prof.on) {
     HFCI_HIP(hipStreamSynchronize(s));
-    pr.harvest();
+    ctx.prof.harvest();
   }
 }
+
+}  // namespace
+
+// Launch-shape autotuner: times the middle-factor kernel (the dominant launch of the
+// fixed-point iteration) over nsys systems for every valid shape and keeps the fastest
+// for this operator and precision.  Inputs are zeros and the factor is a fixed benign
+// one: the kernel's time does not depend on the values.
+template <typename T2>
+KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, double>>& timings) {
+  Ctx& ctx = *op.ctx;
+  hipStream_t s = ctx.stream;
+  const size_t n = op.n;
+  const size_t vbytes = n * sizeof(T2);
+  T2* win = (T2*)ctx.ws.get("fp_wA", (size_t)nsys * vbytes);
+  T2* wout = (T2*)ctx.ws.get("fp_wB", (size_t)nsys * vbytes);
+  FactorCoef* coef = (FactorCoef*)ctx.ws.get("tune_coef", sizeof(FactorCoef));
+  PoleDev* pole = (PoleDev*)ctx.ws.get("tune_pole", sizeof(PoleDev));
+  int* list = (int*)ctx.ws.get("tune_list", (size_t)nsys * sizeof(int));
+  const FactorCoef c0{1e-3, 0.0, 0.5, 0.0};
+  const PoleDev p0{0.5 * (op.b1 + op.b2), 0.5, 0.0, 0.0};
+  std::vector<int> ids(nsys);
+  for (int k = 0; k < nsys; ++k) ids[k] = k;
+  HFCI_HIP(hipMemcpyAsync(coef, &c0, sizeof(c0), hipMemcpyHostToDevice, s));
+  HFCI_HIP(hipMemcpyAsync(pole, &p0, sizeof(p0), hipMemcpyHostToDevice, s));
+  HFCI_HIP(hipMemcpyAsync(list, ids.data(), nsys * sizeof(int), hipMemcpyHostToDevice, s));
+  launch_fill_zero(s, win, (size_t)nsys * vbytes);
+  FactorArgs<T2> a{};
+  a.win = win;
+  a.wout = wout;
+  a.coef = coef;
+  a.poles = pole;
+  a.list = list;
+  a.count = nsys;
+  a.sys0 = 0;
+  a.nrhs = 1;
+  a.cstride = 1;
+  a.k = 0;
+  KernelTune& cur = (sizeof(T2) == 8) ? op.g.tune32 : op.g.tune64;
+  const KernelTune saved = cur;
+  const void* kap = Prec<T2>::kappa(op);
+  std::vector<KernelTune> cands;
+  for (int cz : {0, 16, 64}) {
+    for (int ty : {4, 8})
+      for (int pd : {1, 2}) cands.push_back(KernelTune{0, ty, pd, cz});
+    for (int pd : {1, 2, 3}) cands.push_back(KernelTune{1, 4, pd, cz});
+    for (int pd : {2, 3}) cands.push_back(KernelTune{1, 8, pd, cz});
+  }
+  hipEvent_t e0, e1;
+  HFCI_HIP(hipEventCreate(&e0));
+  HFCI_HIP(hipEventCreate(&e1));
+  KernelTune best = saved;
+  double best_ms = 1e300;
+  timings.clear();
+  try {
+    for (const KernelTune& t : cands) {
+      if (t.cz > 0 && t.cz >= op.g.nz) continue;  // same as one chunk per column: covered by cz = 0 or larger
+      cur = t;
+      Launch<T2>::factor(s, op.g, kap, a, 0);  // warm-up
+      HFCI_HIP(hipEventRecord(e0, s));
+      const int reps = 3;
+      for (int r = 0; r < reps; ++r) Launch<T2>::factor(s, op.g, kap, a, 0);
+      HFCI_HIP(hipEventRecord(e1, s));
+      HFCI_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HFCI_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const double avg = ms / reps;
+      timings.emplace_back(t, avg);
+      if (avg < best_ms) {
+        best_ms = avg;
+        best = t;
+      }
+    }
+  } catch (...) {
+    cur = saved;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  cur = best;
+  return best;
+}
+template KernelTune autotune_shapes<float2>(Op&, int, std::vector<std::pair<KernelTune, double>>&);
+template KernelTune autotune_shapes<double2>(Op&, int, std::vector<std::pair<KernelTune, double>>&);
+
+namespace {
 
 // Alg. 1 steps 1-3 in precision T2: w = sum sigma_j/z_j y_j, d = (Aw)^H f / |Aw|^2, out = d w.
 template <typename T2>

@@ -14,9 +14,10 @@
 //
 // Epilogues fused into the sweep:
 //   EpiApply    y = (A - shift) x
-//   EpiStage    one Horner stage of the exponential-Taylor fixed-point step
-//               (eq. fix-pt-exp re-associated, see solver.cpp); the first stage
-//               also forms the residual f - (A - z) y and its squared norm.
+//   EpiFactor   one linear factor a (A - z0) + b of the product-form
+//               exponential-Taylor fixed-point step (eq. fix-pt-exp, factored in
+//               params.cpp); the first factor of a step also forms the residual
+//               f - (A - z) y and its squared norm, the last adds the constant y1.
 //   EpiDstep    partial sums of (A w)^H f and |A w|^2 for Alg. 1 step 3.
 //   EpiResidual r = b - A u and |r|^2 (FP64 true residual of FGMRES).
 #include "kernels.h"
@@ -24,7 +25,7 @@
 namespace hfci {
 namespace {
 
-constexpr int TX = 64, TY = 4, NT = TX * TY;
+constexpr int TX = 64;
 
 template <typename T> struct V2;
 template <> struct V2<float> { using t = float2; };
@@ -39,7 +40,7 @@ __device__ __forceinline__ int layer_depth(int i, int n, int L) {
 }
 
 // Block-wide sum of NACC doubles; result valid in thread 0.
-template <int NACC>
+template <int NT, int NACC>
 __device__ __forceinline__ void block_sum(double (&acc)[NACC], double* sh) {
   const int t = threadIdx.x + TX * threadIdx.y;
   const int lane = t & 63, wid = t >> 6;
@@ -63,10 +64,15 @@ __device__ __forceinline__ void block_sum(double (&acc)[NACC], double* sh) {
 
 // Lanes outside the grid (x >= nx or y >= ny) and the Dirichlet ghosts read a clamped,
 // always-valid address and zero the value with a select, so the loop body has no
-// divergent branches.  Loads for plane z+1 are issued before plane z is computed and
-// stored (one plane of software pipelining): the stores cannot alias-block them.
-template <typename T, class Epi>
-__global__ __launch_bounds__(NT) void zmarch_kernel(GridDesc g, int nzc, int czlen, int xcd_slab, Epi epi) {
+// divergent branches.  Software pipelining: the streams that come from HBM (the centre
+// plane, kappa and the epilogue's vectors) are issued PD planes ahead of their use, the
+// in-plane neighbours (lines the block's own centre loads or the adjacent tiles have
+// just pulled into L2) one plane ahead.  Loads never reach beyond the chunk's z-halo:
+// past it they repeat the current plane's (cached) address.
+template <typename T, class Epi, int TY, int PD>
+__global__ __launch_bounds__(TX * TY) void zmarch_kernel(GridDesc g, int nzc, int czlen, int xcd_slab, Epi epi) {
+  static_assert(PD == 1 || PD == 2, "prefetch depth 1 or 2");
+  constexpr int NT = TX * TY;
   using T2 = typename V2<T>::t;
   using Aux = typename Epi::Aux;
   constexpr int NACC = Epi::NACC;
@@ -75,13 +81,10 @@ __global__ __launch_bounds__(NT) void zmarch_kernel(GridDesc g, int nzc, int czl
   // workgroup b is given tile (b % 8) * slab + b / 8 and every XCD walks a contiguous
   // run of tiles whose y/z neighbours it shares in its own L2.
   const int gx = gridDim.x, gy = gridDim.y;
-  const int per_sys = gx * gy * nzc;
-  const int s = blockIdx.z / nzc;
+  const int s = epi.system(blockIdx.z / nzc);
   int b = blockIdx.x + gx * (blockIdx.y + gy * (blockIdx.z % nzc));
   if (xcd_slab > 0) b = (b % 8) * xcd_slab + b / 8;
   const int bx = b % gx, by = (b / gx) % gy, zc = b / (gx * gy);
-  (void)per_sys;
-  if (!epi.active(s)) return;  // uniform over the block
   const int x = bx * TX + threadIdx.x;
   const int y = by * TY + threadIdx.y;
   const bool valid = (x < g.nx) && (y < g.ny);
@@ -107,23 +110,35 @@ __global__ __launch_bounds__(NT) void zmarch_kernel(GridDesc g, int nzc, int czl
     const size_t oxm = x > 0 ? 1 : 0, oxp = x + 1 < g.nx ? 1 : 0;
     const size_t oym = y > 0 ? (size_t)g.nx : 0, oyp = y + 1 < g.ny ? (size_t)g.nx : 0;
     size_t p = (size_t)x + (size_t)g.nx * (size_t)y + plane * (size_t)zb;
-    // plane zb: centre, z-1 neighbour, in-plane neighbours, kappa, epilogue inputs
+    // the centre planes a chunk needs are zb-1 .. ze (within the grid)
+    const int zlast = min(ze, g.nz - 1);
+    auto centre = [&](int zz, size_t pz) { return X[(zz <= zlast) ? pz : p]; };
+    // prologue: planes zb-1 .. zb+PD of the centre, plane zb's neighbours, and the
+    // HBM streams of planes zb .. zb+PD-1
     T2 prev = X[zb > 0 ? p - plane : p];
     if (zb == 0) prev = T2{(T)0, (T)0};
     T2 cur = X[p];
-    T2 nxt = X[zb + 1 < g.nz ? p + plane : p];
+    T2 nxt = centre(zb + 1, p + plane);
+    T2 nx2 = (PD == 2) ? centre(zb + 2, p + 2 * plane) : T2{};
     T2 xm = X[p - oxm], xp = X[p + oxp], ym = X[p - oym], yp = X[p + oyp];
     T kap = K[p];
     Aux aux = epi.load_aux(sys, s, p);
+    T kap1{};
+    Aux aux1{};
+    if constexpr (PD == 2) {
+      const size_t p1 = (zb + 1 < ze) ? p + plane : p;
+      kap1 = K[p1];
+      aux1 = epi.load_aux(sys, s, p1);
+    }
 #pragma unroll 2
     for (int z = zb; z < ze; ++z, p += plane) {
-      // ---- issue the loads of plane z+1 (clamped to plane z on the last plane) ----
-      const bool more = z + 1 < ze;
-      const size_t q1 = more ? p + plane : p;
-      const T2 nn = X[z + 2 < g.nz ? p + 2 * plane : q1];
+      // ---- issue loads: neighbours of plane z+1, HBM streams PD planes ahead ----
+      const size_t q1 = (z + 1 < ze) ? p + plane : p;
+      const size_t qf = (z + PD < ze) ? p + PD * plane : p;
+      const T2 cn = centre(z + PD + 1, p + (PD + 1) * plane);
       const T2 xm1 = X[q1 - oxm], xp1 = X[q1 + oxp], ym1 = X[q1 - oym], yp1 = X[q1 + oyp];
-      const T kap1 = K[q1];
-      const Aux aux1 = epi.load_aux(sys, s, q1);
+      const T kapf = K[qf];
+      const Aux auxf = epi.load_aux(sys, s, qf);
       // ---- compute and store plane z ----
       const T2 zn = (z + 1 < g.nz) ? nxt : T2{(T)0, (T)0};
       const int d = max(dxy, layer_depth(z, g.nz, g.damp_cells));
@@ -138,14 +153,160 @@ __global__ __launch_bounds__(NT) void zmarch_kernel(GridDesc g, int nzc, int czl
       // ---- rotate ----
       prev = cur;
       cur = zn;
-      nxt = nn;
+      if constexpr (PD == 2) {
+        nxt = nx2;
+        nx2 = cn;
+        kap = kap1;
+        kap1 = kapf;
+        aux = aux1;
+        aux1 = auxf;
+      } else {
+        nxt = cn;
+        kap = kapf;
+        aux = auxf;
+      }
       xm = xm1; xp = xp1; ym = ym1; yp = yp1;
-      kap = kap1;
-      aux = aux1;
     }
   }
   if constexpr (NACC > 0) {
-    block_sum<NACC>(acc, sh);
+    block_sum<NT, NACC>(acc, sh);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+      const int nblk = gx * gy * nzc;
+      const int blk = bx + gx * (by + gy * zc);
+#pragma unroll
+      for (int k = 0; k < NACC; ++k) epi.partial_out(s, k, nblk, blk, acc[k]);
+    }
+  }
+}
+
+// LDS-staged variant.  Each plane's 64 x TY tile and its one-point halo (rows y0-1 and
+// y0+TY, columns x0-1 and x0+64; zeros outside the grid, i.e. the Dirichlet ghosts) go
+// through a double-buffered LDS tile, one barrier per plane, and the x/y neighbours are
+// read from LDS.  Every global load is a plane record PR[k] = {centre of plane k+1,
+// halo of plane k, kappa_k, epilogue vectors at k}, issued D planes ahead into a queue
+// of U register slots indexed by the plane modulo U inside a U-times unrolled loop, so
+// the queue rotates by renaming (no copies of registers with loads in flight) and the
+// in-order load counter lets D records stay in flight while plane z is computed.
+template <typename T, class Aux>
+struct PlaneRec {
+  typename V2<T>::t c, h;
+  T kap;
+  Aux aux;
+};
+
+template <typename T, class Epi, int TY, int D>
+__global__ __launch_bounds__(TX * TY) void zlds_kernel(GridDesc g, int nzc, int czlen, int xcd_slab, Epi epi) {
+  constexpr int NT = TX * TY, U = 4, LW = TX + 2;
+  static_assert(D >= 1 && D < U, "prefetch depth 1..3");
+  static_assert(TY >= 3, "the halo assignment needs three waves");
+  using T2 = typename V2<T>::t;
+  using Aux = typename Epi::Aux;
+  using Rec = PlaneRec<T, Aux>;
+  constexpr int NACC = Epi::NACC;
+  __shared__ T2 tile[2][TY + 2][LW];
+  __shared__ double sh[(NT / 64) * (NACC > 0 ? NACC : 1)];
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int s = epi.system(blockIdx.z / nzc);
+  int b = blockIdx.x + gx * (blockIdx.y + gy * (blockIdx.z % nzc));
+  if (xcd_slab > 0) b = (b % 8) * xcd_slab + b / 8;
+  const int bx = b % gx, by = (b / gx) % gy, zc = b / (gx * gy);
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int x0 = bx * TX, y0 = by * TY;
+  const int x = x0 + lx, y = y0 + ly;
+  const bool valid = (x < g.nx) && (y < g.ny);
+  const int zb = zc * czlen;
+  const int ze = min(g.nz, zb + czlen);
+  const size_t plane = (size_t)g.nx * (size_t)g.ny;
+  const T2* __restrict__ X = epi.in(s);
+  const T* __restrict__ K = epi.kappa;
+  const typename Epi::Sys sys = epi.sys(s);
+  T sre, sim;
+  epi.shift(sys, sre, sim);
+  const T sh2 = (T)g.s_h2;
+  const T dsc = (T)g.damp_scale;
+  const T diag0 = (T)6 * sh2 - sre;
+  double acc[NACC > 0 ? NACC : 1];
+#pragma unroll
+  for (int k = 0; k < (NACC > 0 ? NACC : 1); ++k) acc[k] = 0.0;
+
+  // halo duty: wave 0 row y0-1, wave TY-1 row y0+TY, wave 1 the two side columns
+  int hx = 0, hy = 0, hr = 0, hc = 0;
+  bool has_h = true;
+  if (ly == 0) {
+    hx = x; hy = y0 - 1; hr = 0; hc = lx + 1;
+  } else if (ly == TY - 1) {
+    hx = x; hy = y0 + TY; hr = TY + 1; hc = lx + 1;
+  } else if (ly == 1 && lx < TY) {
+    hx = x0 - 1; hy = y0 + lx; hr = lx + 1; hc = 0;
+  } else if (ly == 1 && lx >= 32 && lx < 32 + TY) {
+    hx = x0 + TX; hy = y0 + lx - 32; hr = lx - 32 + 1; hc = TX + 1;
+  } else {
+    has_h = false;
+  }
+  const bool hval = has_h && hx >= 0 && hx < g.nx && hy >= 0 && hy < g.ny;
+  const size_t pc = valid ? (size_t)x + (size_t)g.nx * (size_t)y : 0;
+  const size_t ph = hval ? (size_t)hx + (size_t)g.nx * (size_t)hy : pc;
+  const int dxy = max(layer_depth(x, g.nx, g.damp_cells), layer_depth(y, g.ny, g.damp_cells));
+
+  // plane record k (k in [zb, ze)); loads past the needed range repeat plane zb's address
+  auto load_rec = [&](int k) {
+    Rec r;
+    const bool need = k < ze;
+    const size_t off = need ? plane * (size_t)k : plane * (size_t)zb;
+    const bool cn = need && (k + 1 < g.nz);
+    r.c = X[pc + (cn ? off + plane : off)];
+    if (!(valid && cn)) r.c = T2{(T)0, (T)0};
+    r.h = T2{(T)0, (T)0};
+    if (hval) r.h = X[ph + off];
+    r.kap = K[pc + off];
+    r.aux = epi.load_aux(sys, s, pc + off);
+    return r;
+  };
+
+  const int len = ze - zb;
+  if (len > 0) {
+    Rec q[U];
+    T2 prev = T2{(T)0, (T)0};
+    if (zb > 0) prev = X[pc + plane * (size_t)(zb - 1)];
+    if (!valid) prev = T2{(T)0, (T)0};
+    T2 cur = X[pc + plane * (size_t)zb];
+    if (!valid) cur = T2{(T)0, (T)0};
+#pragma unroll
+    for (int d = 0; d < D; ++d) q[d] = load_rec(zb + d);
+    for (int r0 = 0; r0 < len; r0 += U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = r0 + u;
+        if (r < len) {
+          const int z = zb + r;
+          q[(u + D) % U] = load_rec(z + D);
+          const Rec& rc = q[u];
+          T2(*tb)[LW] = tile[u & 1];
+          tb[ly + 1][lx + 1] = cur;
+          if (has_h) tb[hr][hc] = rc.h;
+          __syncthreads();
+          const T2 nxt = rc.c;
+          const T2 xm = tb[ly + 1][lx], xp = tb[ly + 1][lx + 2];
+          const T2 ym = tb[ly][lx + 1], yp = tb[ly + 2][lx + 1];
+          if (valid) {
+            const int d = max(dxy, layer_depth(z, g.nz, g.damp_cells));
+            const T dre = diag0 - rc.kap;
+            const T dim = -((T)(d * d) * dsc + sim);
+            const T nbr = ((prev.x + nxt.x) + (xm.x + xp.x)) + (ym.x + yp.x);
+            const T nbi = ((prev.y + nxt.y) + (xm.y + xp.y)) + (ym.y + yp.y);
+            T2 Sx;
+            Sx.x = dre * cur.x - dim * cur.y - sh2 * nbr;
+            Sx.y = dre * cur.y + dim * cur.x - sh2 * nbi;
+            epi.point(sys, s, pc + plane * (size_t)z, Sx, cur, rc.aux, acc);
+          }
+          prev = cur;
+          cur = nxt;
+        }
+      }
+    }
+  }
+  if constexpr (NACC > 0) {
+    block_sum<NT, NACC>(acc, sh);
     if (threadIdx.x == 0 && threadIdx.y == 0) {
       const int nblk = gx * gy * nzc;
       const int blk = bx + gx * (by + gy * zc);
@@ -168,7 +329,7 @@ struct EpiApply {
   const T* kappa;
   size_t n;
   T sre, sim;
-  __device__ bool active(int) const { return true; }
+  __device__ int system(int slot) const { return slot; }
   __device__ const T2* in(int s) const { return x + (size_t)s * n; }
   __device__ Sys sys(int) const { return Sys{}; }
   __device__ void shift(const Sys&, T& re, T& im) const { re = sre; im = sim; }
@@ -179,52 +340,69 @@ struct EpiApply {
   __device__ void partial_out(int, int, int, int, double) const {}
 };
 
-template <typename T, bool FIRST>
-struct EpiStage {
+// One factor of the product-form step, per listed system s:
+//   out = a (A - z0) in + b in  [+ y1]   (a, b per pole and factor)
+// kFacResid: in is the iterate y; also accumulates |f - (A - z) y|^2 with
+//            f - (A - z) y = f - (A - z0) y + (z - z0) y.
+// kFacAdd:   adds the step's constant vector y1.
+// kFacDual:  also stores out to wout2.
+// kFacInF:   in is the right-hand side f of the system's rhs.
+template <typename T, int KIND>
+struct EpiFactor {
   using T2 = typename V2<T>::t;
-  static constexpr int NACC = FIRST ? 1 : 0;
+  static constexpr bool RESID = (KIND & kFacResid) != 0, ADD = (KIND & kFacAdd) != 0,
+                        DUAL = (KIND & kFacDual) != 0, INF = (KIND & kFacInF) != 0;
+  static constexpr int NACC = RESID ? 1 : 0;
   struct Sys {
-    T cBr, cBi, alr, ali, gar, gai, z0r, z0i;
+    T ar, ai, br, bi, z0r, z0i;
     double zzr, zzi;
-    const T2* y;
     const T2* f;
+    const T2* y1;
     T2* out;
+    T2* out2;
   };
   struct Aux {
-    T2 y, f;
+    T2 f, y1;
   };
-  StageArgs<T2> a;
+  FactorArgs<T2> a;
   const T* kappa;
   size_t n;
-  __device__ bool active(int s) const { return a.active[s] != 0; }
-  __device__ const T2* in(int s) const { return a.win + (size_t)s * n; }
+  __device__ int system(int slot) const { return a.list[slot]; }
+  __device__ const T2* in(int s) const {
+    if constexpr (INF) return a.f + (size_t)((a.sys0 + s) % a.nrhs) * n;
+    else return a.win + (size_t)s * n;
+  }
   __device__ Sys sys(int s) const {
     const int gs = a.sys0 + s;
     const int pole = gs / a.nrhs, r = gs % a.nrhs;
-    const StageCoef c = a.coef[pole * a.q + a.m];
+    const FactorCoef c = a.coef[pole * a.cstride + a.k];
     const PoleDev pd = a.poles[pole];
-    return Sys{(T)c.cB_re, (T)c.cB_im, (T)c.al_re, (T)c.al_im, (T)c.ga_re, (T)c.ga_im, (T)pd.z0_re,
-               (T)pd.z0_im, pd.zz_re, pd.zz_im, a.y + (size_t)s * n, a.f + (size_t)r * n, a.wout + (size_t)s * n};
+    return Sys{(T)c.a_re, (T)c.a_im, (T)c.b_re, (T)c.b_im, (T)pd.z0_re, (T)pd.z0_im, pd.zz_re, pd.zz_im,
+               a.f + (size_t)r * n, ADD ? a.y1 + (size_t)s * n : nullptr, a.wout + (size_t)s * n,
+               DUAL ? a.wout2 + (size_t)s * n : nullptr};
   }
   __device__ void shift(const Sys& c, T& re, T& im) const { re = c.z0r; im = c.z0i; }
   __device__ Aux load_aux(const Sys& c, int, size_t p) const {
     Aux x;
-    if constexpr (FIRST) x.y = T2{(T)0, (T)0};
-    else x.y = c.y[p];
-    x.f = c.f[p];
+    if constexpr (RESID) x.f = c.f[p];
+    else x.f = T2{(T)0, (T)0};
+    if constexpr (ADD) x.y1 = c.y1[p];
+    else x.y1 = T2{(T)0, (T)0};
     return x;
   }
   __device__ void point(const Sys& c, int, size_t p, const T2& Sx, const T2& cur, const Aux& ax, double* acc) const {
-    const T2 yv = FIRST ? cur : ax.y;
-    const T2 fv = ax.f;
     T2 o;
-    o.x = c.cBr * Sx.x - c.cBi * Sx.y + c.alr * yv.x - c.ali * yv.y + c.gar * fv.x - c.gai * fv.y;
-    o.y = c.cBr * Sx.y + c.cBi * Sx.x + c.alr * yv.y + c.ali * yv.x + c.gar * fv.y + c.gai * fv.x;
+    o.x = c.ar * Sx.x - c.ai * Sx.y + c.br * cur.x - c.bi * cur.y;
+    o.y = c.ar * Sx.y + c.ai * Sx.x + c.br * cur.y + c.bi * cur.x;
+    if constexpr (ADD) {
+      o.x += ax.y1.x;
+      o.y += ax.y1.y;
+    }
     c.out[p] = o;
-    if constexpr (FIRST) {
-      // r = f - (A - z) y = f - (A - z0) y + (z - z0) y
-      const double rr = (double)fv.x - (double)Sx.x + c.zzr * (double)yv.x - c.zzi * (double)yv.y;
-      const double ri = (double)fv.y - (double)Sx.y + c.zzr * (double)yv.y + c.zzi * (double)yv.x;
+    if constexpr (DUAL) c.out2[p] = o;
+    if constexpr (RESID) {
+      const double rr = (double)ax.f.x - (double)Sx.x + c.zzr * (double)cur.x - c.zzi * (double)cur.y;
+      const double ri = (double)ax.f.y - (double)Sx.y + c.zzr * (double)cur.y + c.zzi * (double)cur.x;
       acc[0] += rr * rr + ri * ri;
     }
   }
@@ -248,7 +426,7 @@ struct EpiDstep {
   const T* kappa;
   double* partial;
   size_t n;
-  __device__ bool active(int) const { return true; }
+  __device__ int system(int slot) const { return slot; }
   __device__ const T2* in(int s) const { return w + (size_t)s * n; }
   __device__ Sys sys(int s) const { return Sys{f + (size_t)s * n}; }
   __device__ void shift(const Sys&, T& re, T& im) const { re = (T)0; im = (T)0; }
@@ -275,7 +453,7 @@ struct EpiResidual {
   double2* r;
   const double* kappa;
   double* partial;
-  __device__ bool active(int) const { return true; }
+  __device__ int system(int slot) const { return slot; }
   __device__ const double2* in(int) const { return u; }
   __device__ Sys sys(int) const { return Sys{}; }
   __device__ void shift(const Sys&, double& re, double& im) const { re = 0.0; im = 0.0; }
@@ -292,19 +470,30 @@ struct EpiResidual {
 };
 
 struct Shape {
-  dim3 grid;
+  dim3 grid, block;
   int nzc, czlen, xcd_slab;
 };
 
+template <typename T>
+const KernelTune& tune_of(const GridDesc& g) {
+  return sizeof(T) == 4 ? g.tune32 : g.tune64;
+}
+
+template <typename T>
 Shape shape_for(const GridDesc& g, int nsys) {
+  const KernelTune& t = tune_of<T>(g);
   Shape sh;
-  const int gx = (g.nx + TX - 1) / TX, gy = (g.ny + TY - 1) / TY;
-  // z-chunk: keep >= ~2048 blocks per system on large grids, chunks of >= 8 planes.
-  int cz = 32;
-  while (cz > 8 && (long)gx * gy * ((g.nz + cz - 1) / cz) < 2048) cz /= 2;
+  const int gx = (g.nx + TX - 1) / TX, gy = (g.ny + t.ty - 1) / t.ty;
+  int cz = t.cz;
+  if (cz <= 0) {
+    // keep >= ~2048 blocks per system on large grids, chunks of >= 8 planes
+    cz = 32;
+    while (cz > 8 && (long)gx * gy * ((g.nz + cz - 1) / cz) < 2048) cz /= 2;
+  }
   sh.czlen = cz;
   sh.nzc = (g.nz + cz - 1) / cz;
   sh.grid = dim3(gx, gy, sh.nzc * nsys);
+  sh.block = dim3(TX, t.ty);
   const int per_sys = gx * gy * sh.nzc;
   sh.xcd_slab = (per_sys % 8 == 0 && per_sys >= 64) ? per_sys / 8 : 0;
   return sh;
@@ -313,15 +502,52 @@ Shape shape_for(const GridDesc& g, int nsys) {
 template <typename T, class Epi>
 void run(hipStream_t st, const GridDesc& g, int nsys, const Epi& epi) {
   if (nsys <= 0) return;
-  const Shape sh = shape_for(g, nsys);
-  hipLaunchKernelGGL((zmarch_kernel<T, Epi>), sh.grid, dim3(TX, TY), 0, st, g, sh.nzc, sh.czlen, sh.xcd_slab, epi);
+  const Shape sh = shape_for<T>(g, nsys);
+  const KernelTune& t = tune_of<T>(g);
+  const int key = t.kern * 100 + t.ty * 10 + t.pd;
+  switch (key) {
+    case 141:
+      hipLaunchKernelGGL((zlds_kernel<T, Epi, 4, 1>), sh.grid, sh.block, 0, st, g, sh.nzc, sh.czlen, sh.xcd_slab, epi);
+      break;
+    case 142:
+      hipLaunchKernelGGL((zlds_kernel<T, Epi, 4, 2>), sh.grid, sh.block, 0, st, g, sh.nzc, sh.czlen, sh.xcd_slab, epi);
+      break;
+    case 143:
+      hipLaunchKernelGGL((zlds_kernel<T, Epi, 4, 3>), sh.grid, sh.block, 0, st, g, sh.nzc, sh.czlen, sh.xcd_slab, epi);
+      break;
+    case 182:
+      hipLaunchKernelGGL((zlds_kernel<T, Epi, 8, 2>), sh.grid, sh.block, 0, st, g, sh.nzc, sh.czlen, sh.xcd_slab, epi);
+      break;
+    case 183:
+      hipLaunchKernelGGL((zlds_kernel<T, Epi, 8, 3>), sh.grid, sh.block, 0, st, g, sh.nzc, sh.czlen, sh.xcd_slab, epi);
+      break;
+    case 41:
+      hipLaunchKernelGGL((zmarch_kernel<T, Epi, 4, 1>), sh.grid, sh.block, 0, st, g, sh.nzc, sh.czlen, sh.xcd_slab, epi);
+      break;
+    case 81:
+      hipLaunchKernelGGL((zmarch_kernel<T, Epi, 8, 1>), sh.grid, sh.block, 0, st, g, sh.nzc, sh.czlen, sh.xcd_slab, epi);
+      break;
+    case 82:
+      hipLaunchKernelGGL((zmarch_kernel<T, Epi, 8, 2>), sh.grid, sh.block, 0, st, g, sh.nzc, sh.czlen, sh.xcd_slab, epi);
+      break;
+    default:
+      hipLaunchKernelGGL((zmarch_kernel<T, Epi, 4, 2>), sh.grid, sh.block, 0, st, g, sh.nzc, sh.czlen, sh.xcd_slab, epi);
+      break;
+  }
 }
 
 }  // namespace
 
+bool tune_valid(const KernelTune& t) {
+  if (t.cz < 0 || t.cz > 4096 || !(t.ty == 4 || t.ty == 8)) return false;
+  if (t.kern == 0) return t.pd == 1 || t.pd == 2;
+  if (t.kern == 1) return (t.ty == 4 && t.pd >= 1 && t.pd <= 3) || (t.ty == 8 && (t.pd == 2 || t.pd == 3));
+  return false;
+}
+
 template <typename T2>
 int Launch<T2>::partial_blocks(const GridDesc& g) {
-  const Shape sh = shape_for(g, 1);
+  const Shape sh = shape_for<typename Scal<T2>::t>(g, 1);
   return (int)(sh.grid.x * sh.grid.y * sh.nzc);
 }
 
@@ -333,18 +559,26 @@ void Launch<T2>::apply(hipStream_t st, const GridDesc& g, const void* kappa, dou
   run<T>(st, g, nvec, e);
 }
 
+template <typename T, int KIND, typename T2>
+void run_factor(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a) {
+  EpiFactor<T, KIND> e{a, (const T*)kappa, (size_t)g.nx * g.ny * g.nz};
+  run<T>(st, g, a.count, e);
+}
+
 template <typename T2>
-void Launch<T2>::stage(hipStream_t st, const GridDesc& g, const void* kappa, const StageArgs<T2>& a,
-                       bool first) {
+bool Launch<T2>::factor(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a, int kind) {
   using T = typename Scal<T2>::t;
-  const size_t n = (size_t)g.nx * g.ny * g.nz;
-  if (first) {
-    EpiStage<T, true> e{a, (const T*)kappa, n};
-    run<T>(st, g, a.nsys, e);
-  } else {
-    EpiStage<T, false> e{a, (const T*)kappa, n};
-    run<T>(st, g, a.nsys, e);
+  switch (kind) {
+    case 0: run_factor<T, 0>(st, g, kappa, a); break;
+    case kFacResid: run_factor<T, kFacResid>(st, g, kappa, a); break;
+    case kFacResid | kFacAdd: run_factor<T, kFacResid | kFacAdd>(st, g, kappa, a); break;
+    case kFacAdd: run_factor<T, kFacAdd>(st, g, kappa, a); break;
+    case kFacDual: run_factor<T, kFacDual>(st, g, kappa, a); break;
+    case kFacInF: run_factor<T, kFacInF>(st, g, kappa, a); break;
+    case kFacInF | kFacDual: run_factor<T, kFacInF | kFacDual>(st, g, kappa, a); break;
+    default: return false;
   }
+  return true;
 }
 
 template <typename T2>

@@ -32,8 +32,8 @@ EXPORTED = ["hfci_default_opts", "hfci_last_error", "hfci_version", "hfci_ctx_cr
             "hfci_ctx_profile", "hfci_ctx_profile_read", "hfci_net_create", "hfci_net_destroy",
             "hfci_net_param_count", "hfci_net_get_params", "hfci_net_set_params", "hfci_net_get_grads",
             "hfci_net_eval", "hfci_net_train_step", "hfci_net_train", "hfci_net_apply", "hfci_op_medium_channel",
-            "hfci_net_save", "hfci_net_load"]
-PROF_CLASSES = ["fp_stage", "fp_stage_first", "apply"]
+            "hfci_net_save", "hfci_net_load", "hfci_op_set_tune", "hfci_op_get_tune", "hfci_op_autotune"]
+PROF_CLASSES = ["fp_stage", "fp_stage_first", "apply", "fp_stage_last", "fp_stage_init"]
 
 
 class HfciError(RuntimeError):
@@ -266,6 +266,26 @@ class Operator(_Handle):
         _check(load_library().hfci_op_info(self.h, out))
         keys = ["s", "s_h2", "b1", "b2", "rho2", "kappa_min", "kappa_max"]
         return dict(zip(keys, list(out)))
+
+    def set_tune(self, prec: int, kern: int, ty: int, pd: int, cz: int = 0):
+        """hfci_op_set_tune: stencil launch shape (kernel, 64 x ty tile, prefetch depth pd, z-chunk cz)."""
+        t = (ctypes.c_int * 4)(kern, ty, pd, cz)
+        _check(load_library().hfci_op_set_tune(self.h, prec, t))
+
+    def autotune(self, prec: int, nsys: int = 2):
+        """hfci_op_autotune: pick the fastest stencil launch shape; returns (best, [(shape, ms), ...])."""
+        best = (ctypes.c_int * 4)()
+        cap = 64
+        tm = (ctypes.c_double * (5 * cap))()
+        cnt = ctypes.c_int()
+        _check(load_library().hfci_op_autotune(self.h, prec, nsys, best, tm, cap, ctypes.byref(cnt)))
+        rows = [(tuple(int(v) for v in tm[5 * k:5 * k + 4]), float(tm[5 * k + 4])) for k in range(min(cnt.value, cap))]
+        return tuple(best), rows
+
+    def get_tune(self, prec: int):
+        t = (ctypes.c_int * 4)()
+        _check(load_library().hfci_op_get_tune(self.h, prec, t))
+        return tuple(t)
 
 
 class Net(_Handle):

@@ -2,8 +2,8 @@
 
     python -m paper_1811_12378_amd.profiling stage [--n 256] [--poles 16] [--nrhs 1] [--steps 2] [--prec 32]
         Runs the batched fixed-point iteration for a fixed number of steps on the
-        256^3 layered benchmark medium, so the Horner-stage kernel runs
-        steps*(q-1)*1 launches over poles*nrhs systems, all active.
+        256^3 layered benchmark medium, so the middle-factor kernel runs
+        (steps-1)*(q-2) + (q-3) launches over poles*nrhs systems, all active.
     python -m paper_1811_12378_amd.profiling copy [--mib 2048]
         A device-to-device copy of known size (read + write) for calibrating
         the FETCH_SIZE / WRITE_SIZE counters.
@@ -37,6 +37,8 @@ def _stage(a):
     wl = W.config_layered_256(n=a.n, nrhs=a.nrhs)
     ctx = hfci.Context(0)
     op = hfci.Operator(ctx, torch.from_numpy(wl.c).cuda(), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
+    if a.tune:
+        op.set_tune(a.prec, *a.tune)
     cont = hfci.Contour(op, a.poles, 1.0, 0.5, a.q)
     dt = torch.complex64 if a.prec == 32 else torch.complex128
     f = torch.from_numpy(np.stack(wl.rhs)).cuda().to(dt)
@@ -46,7 +48,8 @@ def _stage(a):
     st = prof["fp_stage"]
     avg = st["total_ms"] / max(1, st["launches"])
     gbs = st["alg_bytes"] / max(1e-12, st["total_ms"] * 1e-3) / 1e9
-    print(json.dumps({"n": a.n, "systems": a.poles * a.nrhs, "steps": a.steps, "stage_launches": st["launches"],
+    print(json.dumps({"n": a.n, "tune": op.get_tune(a.prec), "systems": a.poles * a.nrhs, "steps": a.steps,
+                      "stage_launches": st["launches"],
                       "stage_avg_ms": avg, "stage_alg_bytes_per_launch": st["alg_bytes"] / max(1, st["launches"]),
                       "stage_alg_gbs": gbs}), flush=True)
 
@@ -123,7 +126,8 @@ def _summarize(a):
         sw = copy_bytes / (cw * 1024.0)
         fetch_b = fetch_k * 1024.0 * sf
         write_b = write_k * 1024.0 * sw
-        out = {"kernel": a.kernel, "source_hash": source_hash(), "bytes_per_launch": fetch_b + write_b,
+        out = {"kernel": a.kernel, "source_hash": source_hash(), "shape": a.shape or [],
+               "bytes_per_launch": fetch_b + write_b,
                "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
                "copy_scale_fetch": sf, "copy_scale_write": sw, "dispatches": [nf, nw]}
         lines += ["", "HBM traffic of `%s` per launch (FETCH_SIZE, WRITE_SIZE in KiB, each scaled by the "
@@ -148,6 +152,7 @@ def main(argv=None):
     s.add_argument("--steps", type=int, default=2)
     s.add_argument("--q", type=int, default=8)
     s.add_argument("--prec", type=int, default=32)
+    s.add_argument("--tune", type=int, nargs=4, metavar=("KERN", "TY", "PD", "CZ"))
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=2048)
     m = sub.add_parser("summarize")
@@ -161,6 +166,7 @@ def main(argv=None):
     m.add_argument("--kernel", required=True)
     m.add_argument("--out", required=True)
     m.add_argument("--traffic-json")
+    m.add_argument("--shape", type=int, nargs=4, help="stencil launch shape the counters were taken with")
     m.add_argument("--cmd", nargs=argparse.REMAINDER)
     a = ap.parse_args(argv)
     {"stage": _stage, "copy": _copy, "summarize": _summarize}[a.cmd_name](a)

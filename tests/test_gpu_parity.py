@@ -79,6 +79,69 @@ def test_apply_parity(ctx, shape, prec):
         assert rel(y[k], ref) <= tol, (shape, prec, k, rel(y[k], ref))
 
 
+TUNES = [(0, 4, 1, 0), (0, 4, 2, 0), (0, 8, 1, 0), (0, 8, 2, 3), (0, 4, 2, 1), (1, 4, 1, 0), (1, 4, 2, 0),
+         (1, 4, 3, 0), (1, 8, 2, 0), (1, 8, 3, 0), (1, 4, 3, 1), (1, 4, 2, 5), (1, 8, 3, 7)]
+
+
+@pytest.mark.parametrize("tune", TUNES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_tune_variants_apply_and_fixed_point(ctx, tune, prec):
+    # every launch shape (register or LDS-staged kernel, tile height, prefetch depth,
+    # z-chunk, including 1-plane chunks and chunks that do not divide nz) gives the
+    # same operator and the same fixed-point iterates as the oracle
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    pr = 64 if prec == "f64" else 32
+    tol = 1e-13 if prec == "f64" else 2e-6
+    rng = np.random.default_rng(31)
+    for shape in [(9, 17, 33), (70, 9, 5), (5, 7, 130), (2, 3, 1), (33, 12, 70)]:
+        c = medium(shape, 30)
+        o, g = make_ops(ctx, c, 9.0, 2, 0.8)
+        g.set_tune(pr, *tune)
+        assert g.get_tune(pr) == tuple(tune)
+        x = rng.standard_normal((2,) + shape) + 1j * rng.standard_normal((2,) + shape)
+        y = host(hf.apply(g, dev(x).to(dt), 0.37 - 1.21j))
+        for k in range(2):
+            assert rel(y[k], o.apply(x[k], 0.37 - 1.21j)) <= tol, (shape, k)
+    shape = (11, 10, 70)
+    c = medium(shape, 32)
+    o, g = make_ops(ctx, c, 14.0, 3, 1.0)
+    g.set_tune(pr, *tune)
+    q = 4
+    poles = oracle_poles(o, 4, 1.0, 0.5, q)
+    cg = gpu_contour(g, poles, 4, q)
+    f = rng.standard_normal((2,) + shape) + 1j * rng.standard_normal((2,) + shape)
+    y, st = hf.shifted_solve(g, cg, dev(f).to(dt), steps=3)
+    y = host(y)
+    Am = lambda v, sh: o.apply(v, sh)
+    for j, p in enumerate(poles):
+        for r in range(2):
+            ref, _ = OFP.fixed_point_solve(Am, f[r], p.z, p.z0, p.delta, q, steps=3)
+            assert rel(y[j, r], ref) <= (1e-12 if prec == "f64" else 2e-4), (j, r)
+
+
+@pytest.mark.parametrize("pr", [32, 64])
+def test_autotune_picks_a_timed_shape(ctx, pr):
+    o, g = make_ops(ctx, medium((40, 33, 70), 3), 9.0, 2, 0.8)
+    best, rows = g.autotune(pr, 2)
+    assert len(rows) >= 9
+    assert all(ms > 0 for _, ms in rows)
+    assert best == min(rows, key=lambda r: r[1])[0]
+    assert g.get_tune(pr) == best
+    # the tuned shape still gives the oracle's operator
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((1, 40, 33, 70)) + 1j * rng.standard_normal((1, 40, 33, 70))
+    dt = torch.complex128 if pr == 64 else torch.complex64
+    y = host(hf.apply(g, dev(x).to(dt), 0.2 + 0.7j))
+    assert rel(y[0], o.apply(x[0], 0.2 + 0.7j)) <= (1e-13 if pr == 64 else 2e-6)
+
+
+def test_tune_rejects_invalid(ctx):
+    o, g = make_ops(ctx, medium((4, 4, 4), 1), 9.0, 1, 0.5)
+    for bad in [(2, 4, 1, 0), (0, 5, 1, 0), (0, 4, 3, 0), (1, 8, 1, 0), (1, 4, 4, 0), (0, 4, 1, -1)]:
+        with pytest.raises(hf.HfciError):
+            g.set_tune(32, *bad)
+
+
 def test_op_info_matches_oracle(ctx):
     c = medium((6, 7, 8), 3)
     o, g = make_ops(ctx, c, 11.0, 3, 1.2, h=0.1)
@@ -119,6 +182,7 @@ def gpu_contour(g, poles, J, q):
 
 
 @pytest.mark.parametrize("prec,q,steps", [("f64", 8, 3), ("f64", 3, 4), ("f64", 1, 5), ("f64", 2, 2),
+                                          ("f64", 8, 1), ("f64", 2, 1), ("f64", 1, 1),
                                           ("f32", 8, 3), ("f32", 4, 2)])
 def test_shifted_solve_fixed_steps(ctx, prec, q, steps):
     shape = (9, 17, 33)
@@ -161,6 +225,33 @@ def test_shifted_solve_adaptive_stop_rule(ctx):
         assert hist[k - 1] > fn / 5 * (1 - 1e-9)
         if k == len(hist) - 1:
             assert rel(y[j, 0], ref) <= 1e-12
+
+
+def test_adaptive_many_systems_and_zero_rhs(ctx):
+    # 24 poles x 12 right-hand sides = 288 systems (more than one block of the device-side
+    # list compaction), stopping at different steps; rhs 5 is zero: 0 steps, y = 0
+    shape = (8, 9, 10)
+    c = medium(shape, 21)
+    o, g = make_ops(ctx, c, 12.0, 2, 1.0)
+    J, q, nrhs = 24, 4, 12
+    poles = oracle_poles(o, J, 1.0, 0.5, q)
+    cg = gpu_contour(g, poles, J, q)
+    rng = np.random.default_rng(22)
+    f = rng.standard_normal((nrhs,) + shape) + 1j * rng.standard_normal((nrhs,) + shape)
+    f[3] *= 1e-3
+    f[5] = 0.0
+    y, st = hf.shifted_solve(g, cg, dev(f), reduce=5.0, max_steps=40)
+    y = host(y)
+    assert len(set(st.ravel().tolist())) >= 3  # the systems really stop at different steps
+    Am = lambda x, s: o.apply(x, s)
+    for j, p in enumerate(poles):
+        for r in range(nrhs):
+            ref, hist = OFP.fixed_point_solve(Am, f[r], p.z, p.z0, p.delta, q, reduce=5.0, m_max=40)
+            if r == 5:
+                assert st[j, r] == 0 and np.all(y[j, r] == 0)
+                continue
+            assert st[j, r] == len(hist) - 1, (j, r, st[j, r], len(hist) - 1)
+            assert rel(y[j, r], ref) <= 1e-12, (j, r, rel(y[j, r], ref))
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
