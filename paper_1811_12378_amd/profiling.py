@@ -127,13 +127,16 @@ def _summarize(a):
         fetch_b = fetch_k * 1024.0 * sf
         write_b = write_k * 1024.0 * sw
         out = {"kernel": a.kernel, "source_hash": source_hash(), "shape": a.shape or [],
-               "bytes_per_launch": fetch_b + write_b,
+               "bytes_per_launch": fetch_b + write_b, "alg_bytes_per_launch": a.alg_bytes,
                "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
                "copy_scale_fetch": sf, "copy_scale_write": sw, "dispatches": [nf, nw]}
         lines += ["", "HBM traffic of `%s` per launch (FETCH_SIZE, WRITE_SIZE in KiB, each scaled by the "
                       "copy-kernel calibration factor):" % a.kernel, "",
                   "* fetch %.1f MB, write %.1f MB, total %.1f MB (factors %.4f / %.4f)"
                   % (fetch_b / 1e6, write_b / 1e6, (fetch_b + write_b) / 1e6, sf, sw)]
+        if a.alg_bytes:
+            lines += ["* algorithmic bytes per launch in the same runs %.1f MB: measured / algorithmic = %.3f"
+                      % (a.alg_bytes / 1e6, (fetch_b + write_b) / a.alg_bytes)]
     with open(a.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     if out and a.traffic_json:
@@ -167,6 +170,7 @@ def main(argv=None):
     m.add_argument("--out", required=True)
     m.add_argument("--traffic-json")
     m.add_argument("--shape", type=int, nargs=4, help="stencil launch shape the counters were taken with")
+    m.add_argument("--alg-bytes", type=float, help="algorithmic bytes per launch of the counter runs")
     m.add_argument("--cmd", nargs=argparse.REMAINDER)
     a = ap.parse_args(argv)
     {"stage": _stage, "copy": _copy, "summarize": _summarize}[a.cmd_name](a)
