@@ -162,7 +162,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner arm")
     ap.add_argument("--learn-media", type=int, default=12, help="64^3 training media for the learned arm")
     ap.add_argument("--learn-steps", type=int, default=2000, help="Adam steps for the learned arm")
-    ap.add_argument("--shape", type=int, nargs=4, metavar=("KERN", "TY", "PD", "CZ"),
+    ap.add_argument("--shape", type=int, nargs=5, metavar=("KERN", "TY", "PD", "CZ", "FUSE"),
                     help="pin the complex64 stencil launch shape instead of autotuning it")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -302,8 +302,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_over_alg": round(traffic_ratio, 4) if traffic_ratio else None,
-                     "kernel": "%s<float, EpiFactor<float, 0>, %d, %d> (middle factor of a fixed-point step)"
-                               % ("zlds_kernel" if tune32[0] == 1 else "zmarch_kernel", tune32[1], tune32[2]),
+                     "kernel": ("zpair_kernel<float, 0> (two middle factors of a fixed-point step per pass)"
+                                if tune32[4] else
+                                "%s<float, EpiFactor<float, 0>, %d, %d> (middle factor of a fixed-point step)"
+                                % ("zlds_kernel" if tune32[0] == 1 else "zmarch_kernel", tune32[1], tune32[2])),
                      "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": bytes_per_launch,
                      "launches": stage["launches"]},
         "cpu_baseline": cpu,

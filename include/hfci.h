@@ -176,30 +176,32 @@ void hfci_op_destroy(hfci_op* op);
 hfci_status hfci_op_info(const hfci_op* op, double* out7);
 
 /* Launch shape of the operator's z-marching stencil kernels for one precision
- * (HFCI_F32 or HFCI_F64), tune[4] (HOST array):
+ * (HFCI_F32 or HFCI_F64), tune[5] (HOST array):
  *   tune[0] kern: 0 = in-plane neighbours as cached global loads, 1 = each plane
  *           staged through LDS with its halo;
  *   tune[1] ty:   the thread tile is 64 x ty (4 or 8);
  *   tune[2] pd:   HBM streams are issued pd planes ahead (kern 0: 1 or 2;
  *                 kern 1: 1..3 with ty = 4, 2..3 with ty = 8);
- *   tune[3] cz:   z-chunk length in planes (1..4096, or 0 = chosen from the grid).
+ *   tune[3] cz:   z-chunk length in planes (1..4096, or 0 = chosen from the grid);
+ *   tune[4] fuse: 1 = the fixed-point factors run two per pass over HBM (temporal
+ *                 blocking on 64 x 8 tiles with z-chunks cz), 0 = one per pass.
  * Shapes change launch geometry only: every grid point gets the same arithmetic,
  * while reductions (residual norms, the step size d) sum their block partials in a
- * different order.  Errors: HFCI_E_ARG. */
-hfci_status hfci_op_set_tune(hfci_op* op, int prec, const int* tune4);
-hfci_status hfci_op_get_tune(const hfci_op* op, int prec, int* tune4);
+ * different order.  New operators start at {1, 8, 2, 0, 0}.  Errors: HFCI_E_ARG. */
+hfci_status hfci_op_set_tune(hfci_op* op, int prec, const int* tune5);
+hfci_status hfci_op_get_tune(const hfci_op* op, int prec, int* tune5);
 
-/* Launch-shape autotuner: times the middle-factor kernel of the fixed-point
- * iteration (the dominant launch) over nsys systems (1..64, e.g. the number of
- * shifted systems that usually iterate together) for every valid shape, keeps the
- * fastest for this operator and precision and writes it to best4 (HOST, may be
- * NULL).  timings (HOST, may be NULL if cap = 0) receives up to cap rows of
- * {kern, ty, pd, cz, milliseconds per launch}; *count (may be NULL) the number of
- * shapes timed.  Uses the context's workspace (2 nsys vectors of the precision);
+/* Launch-shape autotuner: times the middle factors of the fixed-point iteration
+ * (the dominant launches) over nsys systems (1..64, e.g. the number of shifted
+ * systems that usually iterate together) for every valid shape, one and two factors
+ * per pass, keeps the fastest per factor for this operator and precision and writes
+ * it to best5 (HOST, may be NULL).  timings (HOST, may be NULL if cap = 0) receives
+ * up to cap rows of {kern, ty, pd, cz, fuse, milliseconds per factor}; *count (may
+ * be NULL) the number of shapes timed.  Uses the context's workspace (2 nsys vectors of the precision);
  * the operator's inputs and outputs of other calls are not touched.  Timing-based,
  * so two runs may pick different shapes (results then differ only in the summation
  * order of reductions).  Errors: HFCI_E_ARG. */
-hfci_status hfci_op_autotune(hfci_op* op, int prec, int nsys, int* best4, double* timings, int cap,
+hfci_status hfci_op_autotune(hfci_op* op, int prec, int nsys, int* best5, double* timings, int cap,
                              int* count);
 
 /* y_k = (A - shift I) x_k for k < nvec (normalised A).  prec: HFCI_F64

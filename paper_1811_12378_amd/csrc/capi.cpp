@@ -353,8 +353,9 @@ hfci_status hfci_op_set_tune(hfci_op* op, int prec, const int* t3) {
   t.ty = t3[1];
   t.pd = t3[2];
   t.cz = t3[3];
-  HFCI_REQUIRE(tune_valid(t), "tune must be {0, ty in {4, 8}, pd in {1, 2}, cz} or {1, 4, pd in 1..3, cz} or "
-                              "{1, 8, pd in {2, 3}, cz}, cz in [0, 4096]");
+  t.fuse = t3[4];
+  HFCI_REQUIRE(tune_valid(t), "tune must be {0, ty in {4, 8}, pd in {1, 2}, cz, fuse} or {1, 4, pd in 1..3, cz, fuse} "
+                              "or {1, 8, pd in {2, 3}, cz, fuse}, cz in [0, 4096], fuse in {0, 1}");
   (prec == HFCI_F32 ? op->g.tune32 : op->g.tune64) = t;
   return HFCI_OK;
   HFCI_API_END
@@ -369,11 +370,12 @@ hfci_status hfci_op_get_tune(const hfci_op* op, int prec, int* t3) {
   t3[1] = t.ty;
   t3[2] = t.pd;
   t3[3] = t.cz;
+  t3[4] = t.fuse;
   return HFCI_OK;
   HFCI_API_END
 }
 
-hfci_status hfci_op_autotune(hfci_op* op, int prec, int nsys, int* best4, double* timings, int cap, int* count) {
+hfci_status hfci_op_autotune(hfci_op* op, int prec, int nsys, int* best5, double* timings, int cap, int* count) {
   HFCI_API_BEGIN
   HFCI_REQUIRE(op, "NULL operator");
   HFCI_REQUIRE(prec == HFCI_F32 || prec == HFCI_F64, "prec must be HFCI_F32 or HFCI_F64");
@@ -382,19 +384,21 @@ hfci_status hfci_op_autotune(hfci_op* op, int prec, int nsys, int* best4, double
   DeviceGuard dg(op->device);
   std::vector<std::pair<KernelTune, double>> tm;
   const KernelTune b = prec == HFCI_F32 ? autotune_shapes<float2>(*op, nsys, tm) : autotune_shapes<double2>(*op, nsys, tm);
-  if (best4) {
-    best4[0] = b.kern;
-    best4[1] = b.ty;
-    best4[2] = b.pd;
-    best4[3] = b.cz;
+  if (best5) {
+    best5[0] = b.kern;
+    best5[1] = b.ty;
+    best5[2] = b.pd;
+    best5[3] = b.cz;
+    best5[4] = b.fuse;
   }
   const int m = std::min<int>(cap, (int)tm.size());
   for (int k = 0; k < m; ++k) {
-    timings[5 * k + 0] = tm[k].first.kern;
-    timings[5 * k + 1] = tm[k].first.ty;
-    timings[5 * k + 2] = tm[k].first.pd;
-    timings[5 * k + 3] = tm[k].first.cz;
-    timings[5 * k + 4] = tm[k].second;
+    timings[6 * k + 0] = tm[k].first.kern;
+    timings[6 * k + 1] = tm[k].first.ty;
+    timings[6 * k + 2] = tm[k].first.pd;
+    timings[6 * k + 3] = tm[k].first.cz;
+    timings[6 * k + 4] = tm[k].first.fuse;
+    timings[6 * k + 5] = tm[k].second;
   }
   if (count) *count = (int)tm.size();
   return HFCI_OK;

@@ -11,9 +11,10 @@ namespace hfci {
 
 // Launch shape of the z-marching stencil kernels: kern 0 keeps the in-plane neighbours
 // as cached global loads, kern 1 stages each plane through LDS; a 64 x ty thread tile,
-// HBM streams prefetched pd planes ahead, z-chunks of cz planes (0: from the grid size).
+// HBM streams prefetched pd planes ahead, z-chunks of cz planes (0: from the grid size);
+// fuse 1 applies the fixed-point factors two per pass (64 x 8 tiles, z-chunks cz).
 struct KernelTune {
-  int kern = 1, ty = 8, pd = 2, cz = 0;
+  int kern = 1, ty = 8, pd = 2, cz = 0, fuse = 0;
 };
 
 // Geometry and operator scalars of the normalised A = (s/h^2) L7 - kappa - i D, plus
@@ -70,6 +71,12 @@ struct Launch {
   // one factor launch of the given kind (kFac* bits) over a.list; false for an
   // unsupported combination of bits (nothing is launched)
   static bool factor(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a, int kind);
+  // factors a.k and a.k + 1 in one pass; kind: the first factor's input bits (kFacResid,
+  // kFacInF) and the second factor's epilogue bits (kFacAdd, kFacDual); the output must
+  // not alias the input
+  static bool factor_pair(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a,
+                          int kind);
+  static int pair_blocks(const GridDesc& g);  // residual partials per system of a pair launch
   // partial sums for the step size d: conj(A w).f and |A w|^2, per rhs.
   static void dstep_partials(hipStream_t st, const GridDesc& g, const void* kappa, int nrhs,
                              const T2* w, const T2* f, double* partial);

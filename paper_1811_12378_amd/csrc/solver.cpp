@@ -64,7 +64,10 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
     T2* y1 = (T2*)ctx.ws.get("fp_y1", (size_t)nsys * vbytes);
     T2* wA = (T2*)ctx.ws.get("fp_wA", (size_t)nsys * vbytes);
     T2* wB = (q >= 3) ? (T2*)ctx.ws.get("fp_wB", (size_t)nsys * vbytes) : nullptr;
-    const int nblk = Launch<T2>::partial_blocks(op.g);
+    const KernelTune& tn = (sizeof(T2) == 8) ? op.g.tune32 : op.g.tune64;
+    const bool fuse = tn.fuse != 0;
+    // residual partials come from the first launch of a step: a pair launch when fusing
+    const int nblk = (fuse && q >= 3) ? Launch<T2>::pair_blocks(op.g) : Launch<T2>::partial_blocks(op.g);
     double* partial = (double*)ctx.ws.get("fp_partial", (size_t)nsys * nblk * sizeof(double));
     int* active = (int*)ctx.ws.get("fp_active", (size_t)nsys * sizeof(int));
     int* list = (int*)ctx.ws.get("fp_list", (size_t)nsys * sizeof(int));
@@ -105,28 +108,50 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
       for (char u : rhs_used) nr += u;
       return (double)n * (vec_per_sys * e * na + ek + (reads_f ? e * nr : 0.0));
     };
-    auto launch = [&](int kind, int k, const T2* win, T2* wout, T2* wout2, int cls, double bytes) {
+    // One launch of `width` consecutive factors starting at coefficient k.  kind: kFacInF /
+    // kFacResid on its first factor, kFacAdd / kFacDual on its last.
+    auto launch = [&](int kind, int k, int width, const T2* win, T2* wout, T2* wout2) {
       a.k = k;
       a.win = win;
       a.wout = wout;
       a.wout2 = wout2;
+      const bool inf = kind & kFacInF, resid = kind & kFacResid, add = kind & kFacAdd, dual = kind & kFacDual;
+      const int cls = resid ? HFCI_PROF_FP_FIRST
+                            : (inf || dual) ? HFCI_PROF_FP_INIT : add ? HFCI_PROF_FP_LAST : HFCI_PROF_FP_STAGE;
+      const double vecs = (inf ? 0.0 : 1.0) + 1.0 + (add ? 1.0 : 0.0) + (dual ? 1.0 : 0.0);
       if (pr.on) pr.begin(s);
-      HFCI_REQUIRE(Launch<T2>::factor(s, op.g, kap, a, kind), "internal: unsupported factor kind");
-      if (pr.on) pr.end(s, cls, bytes);
+      const bool ok = width == 2 ? Launch<T2>::factor_pair(s, op.g, kap, a, kind)
+                                 : Launch<T2>::factor(s, op.g, kap, a, kind);
+      HFCI_REQUIRE(ok, "internal: unsupported factor kind");
+      if (pr.on) pr.end(s, cls, launch_bytes(vecs, inf || resid));
+    };
+    struct Part {
+      int k, width, kind;
+    };
+    // launches of `count` factors from coefficient k0, two per pass when fusing
+    auto plan = [&](int k0, int count, int kind_first, int kind_last, bool pairs) {
+      std::vector<Part> v;
+      for (int j = 0; j < count;) {
+        const int w = (pairs && j + 1 < count) ? 2 : 1;
+        int kind = 0;
+        if (j == 0) kind |= kind_first;
+        if (j + w == count) kind |= kind_last;
+        v.push_back(Part{k0 + j, w, kind});
+        j += w;
+      }
+      return v;
     };
 
     // ---- step one: y1 = prod over the max(q-1, 1) factors of P2, applied to f ----
     a.count = nsys;
     const int nP = std::max(q - 1, 1);
     {
+      const std::vector<Part> pl = plan(q, nP, kFacInF, kFacDual, fuse);
       const T2* cur = nullptr;
-      for (int k = 0; k < nP; ++k) {
-        const bool first = k == 0, last = k == nP - 1;
+      for (size_t i = 0; i < pl.size(); ++i) {
+        const bool last = i + 1 == pl.size();
         T2* dst = last ? y1 : ((cur == wA) ? wB : wA);
-        const int kind = (first ? kFacInF : 0) | (last ? kFacDual : 0);
-        const double bytes = pr.on ? launch_bytes(1.0 + (first ? 0.0 : 1.0) + (last ? 1.0 : 0.0), first) : 0.0;
-        launch(kind, q + k, cur, dst, last ? y : nullptr, kind == 0 ? HFCI_PROF_FP_STAGE : HFCI_PROF_FP_INIT,
-               bytes);
+        launch(pl[i].kind, pl[i].k, pl[i].width, cur, dst, last ? y : nullptr);
         cur = dst;
       }
       st.matvecs += (long long)(q - 1) * nsys;
@@ -134,13 +159,14 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
     }
 
     // ---- steps two and on: y <- L y + y1 ----
+    // (a launch never writes its own input: a step made of a single launch goes through wA)
+    const std::vector<Part> pl = plan(0, q, kFacResid, kFacAdd, fuse && q >= 3);
     int nact = nsys;
     for (int it = 1; it <= cap; ++it) {
       if (fixed && it == cap) break;  // exact count: no final residual check needed
-      // first factor from y, plus ||f - (A - z) y||^2 partials of the current iterate
-      const int kind0 = kFacResid | (q == 1 ? kFacAdd : 0);
-      launch(kind0, 0, y, wA, nullptr, HFCI_PROF_FP_FIRST,
-             pr.on ? launch_bytes(q == 1 ? 3.0 : 2.0, true) : 0.0);
+      // first launch from y, with the ||f - (A - z) y||^2 partials of the current iterate
+      const bool single = pl.size() == 1;
+      launch(pl[0].kind, pl[0].k, pl[0].width, y, wA, nullptr);
       st.matvecs += nact;
       launch_fp_check(s, partial, nblk, nsys, sys0, nrhs, fnorm2, fixed_steps, reduce, max_steps, active, steps,
                       rnorm2);
@@ -161,18 +187,17 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
       a.count = nact;
       st.matvecs += (long long)(q - 1) * nact;
       st.fp_steps += nact;
-      if (q == 1) {
+      if (single) {
         copy_active<T2>(s, y, wA, active, nsys, n);
         continue;
       }
-      // middle factors ping-pong between wA and wB, the last adds y1 and writes y
       T2* cur = wA;
-      for (int k = 1; k < q - 1; ++k) {
-        T2* nxt = (cur == wA) ? wB : wA;
-        launch(0, k, cur, nxt, nullptr, HFCI_PROF_FP_STAGE, pr.on ? launch_bytes(2.0, false) : 0.0);
-        cur = nxt;
+      for (size_t i = 1; i < pl.size(); ++i) {
+        const bool last = i + 1 == pl.size();
+        T2* dst = last ? y : ((cur == wA) ? wB : wA);
+        launch(pl[i].kind, pl[i].k, pl[i].width, cur, dst, nullptr);
+        cur = dst;
       }
-      launch(kFacAdd, q - 1, cur, y, nullptr, HFCI_PROF_FP_LAST, pr.on ? launch_bytes(3.0, false) : 0.0);
     }
   }
   if (steps_out) {
@@ -189,8 +214,8 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
 }  // namespace
 
 // Launch-shape autotuner: times the middle-factor kernel (the dominant launch of the
-// fixed-point iteration) over nsys systems for every valid shape and keeps the fastest
-// for this operator and precision.  Inputs are zeros and the factor is a fixed benign
+// fixed-point iteration) over nsys systems for every valid shape, one factor per pass and
+// two factors per pass, and keeps the fastest per factor for this operator and precision.  Inputs are zeros and the factor is a fixed benign
 // one: the kernel's time does not depend on the values.
 template <typename T2>
 KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, double>>& timings) {
@@ -200,14 +225,14 @@ KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, d
   const size_t vbytes = n * sizeof(T2);
   T2* win = (T2*)ctx.ws.get("fp_wA", (size_t)nsys * vbytes);
   T2* wout = (T2*)ctx.ws.get("fp_wB", (size_t)nsys * vbytes);
-  FactorCoef* coef = (FactorCoef*)ctx.ws.get("tune_coef", sizeof(FactorCoef));
+  FactorCoef* coef = (FactorCoef*)ctx.ws.get("tune_coef", 2 * sizeof(FactorCoef));
   PoleDev* pole = (PoleDev*)ctx.ws.get("tune_pole", sizeof(PoleDev));
   int* list = (int*)ctx.ws.get("tune_list", (size_t)nsys * sizeof(int));
-  const FactorCoef c0{1e-3, 0.0, 0.5, 0.0};
+  const FactorCoef c0[2] = {{1e-3, 0.0, 0.5, 0.0}, {1e-3, 0.0, 0.5, 0.0}};
   const PoleDev p0{0.5 * (op.b1 + op.b2), 0.5, 0.0, 0.0};
   std::vector<int> ids(nsys);
   for (int k = 0; k < nsys; ++k) ids[k] = k;
-  HFCI_HIP(hipMemcpyAsync(coef, &c0, sizeof(c0), hipMemcpyHostToDevice, s));
+  HFCI_HIP(hipMemcpyAsync(coef, c0, sizeof(c0), hipMemcpyHostToDevice, s));
   HFCI_HIP(hipMemcpyAsync(pole, &p0, sizeof(p0), hipMemcpyHostToDevice, s));
   HFCI_HIP(hipMemcpyAsync(list, ids.data(), nsys * sizeof(int), hipMemcpyHostToDevice, s));
   launch_fill_zero(s, win, (size_t)nsys * vbytes);
@@ -220,7 +245,7 @@ KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, d
   a.count = nsys;
   a.sys0 = 0;
   a.nrhs = 1;
-  a.cstride = 1;
+  a.cstride = 2;
   a.k = 0;
   KernelTune& cur = (sizeof(T2) == 8) ? op.g.tune32 : op.g.tune64;
   const KernelTune saved = cur;
@@ -228,10 +253,12 @@ KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, d
   std::vector<KernelTune> cands;
   for (int cz : {0, 16, 64}) {
     for (int ty : {4, 8})
-      for (int pd : {1, 2}) cands.push_back(KernelTune{0, ty, pd, cz});
-    for (int pd : {1, 2, 3}) cands.push_back(KernelTune{1, 4, pd, cz});
-    for (int pd : {2, 3}) cands.push_back(KernelTune{1, 8, pd, cz});
+      for (int pd : {1, 2}) cands.push_back(KernelTune{0, ty, pd, cz, 0});
+    for (int pd : {1, 2, 3}) cands.push_back(KernelTune{1, 4, pd, cz, 0});
+    for (int pd : {2, 3}) cands.push_back(KernelTune{1, 8, pd, cz, 0});
   }
+  // two factors per pass (its own 64 x 8 tiles; per-factor time = half a launch)
+  for (int cz : {0, 16, 64}) cands.push_back(KernelTune{1, 8, 2, cz, 1});
   hipEvent_t e0, e1;
   HFCI_HIP(hipEventCreate(&e0));
   HFCI_HIP(hipEventCreate(&e1));
@@ -242,15 +269,19 @@ KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, d
     for (const KernelTune& t : cands) {
       if (t.cz > 0 && t.cz >= op.g.nz) continue;  // same as one chunk per column: covered by cz = 0 or larger
       cur = t;
-      Launch<T2>::factor(s, op.g, kap, a, 0);  // warm-up
+      auto one = [&] {
+        if (t.fuse) Launch<T2>::factor_pair(s, op.g, kap, a, 0);
+        else Launch<T2>::factor(s, op.g, kap, a, 0);
+      };
+      one();  // warm-up
       HFCI_HIP(hipEventRecord(e0, s));
       const int reps = 3;
-      for (int r = 0; r < reps; ++r) Launch<T2>::factor(s, op.g, kap, a, 0);
+      for (int r = 0; r < reps; ++r) one();
       HFCI_HIP(hipEventRecord(e1, s));
       HFCI_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       HFCI_HIP(hipEventElapsedTime(&ms, e0, e1));
-      const double avg = ms / reps;
+      const double avg = ms / reps / (t.fuse ? 2.0 : 1.0);  // per factor
       timings.emplace_back(t, avg);
       if (avg < best_ms) {
         best_ms = avg;

@@ -316,6 +316,188 @@ __global__ __launch_bounds__(TX * TY) void zlds_kernel(GridDesc g, int nzc, int 
   }
 }
 
+// Two consecutive factors of the fixed-point step in one pass (temporal blocking):
+//   t = a1 (A - z0) w + b1 w,   out = a2 (A - z0) t + b2 t  [+ y1].
+// A block owns a 64 x 8 output tile and a z-chunk.  Per plane k it stages the input
+// plane k+1 on the 68 x 12 tile (two-point halo) in a 3-plane LDS ring, computes the
+// first factor on the 66 x 10 tile (one-point halo; zeros outside the grid, the
+// Dirichlet ghosts of the intermediate vector) into a second 3-plane ring, then the
+// second factor at plane k-1 on the 64 x 8 core.  One thread per first-factor point
+// (660 of 704), two barriers per plane; global loads run one plane ahead.
+// kFacResid / kFacInF select the first factor's input (y with the residual partials,
+// or f); kFacAdd / kFacDual the second factor's epilogue.
+constexpr int PX = 64, PY = 8;                  // output tile
+constexpr int PEX = PX + 2, PEY = PY + 2;       // first-factor tile
+constexpr int PIX = PX + 4, PIY = PY + 4;       // input tile
+constexpr int PNT = 704;                        // 11 waves >= PEX * PEY = 660
+
+template <typename T, int KIND>
+__global__ __launch_bounds__(PNT) void zpair_kernel(GridDesc g, int nzc, int czlen, int xcd_slab,
+                                                    FactorArgs<typename V2<T>::t> a, const T* __restrict__ K) {
+  using T2 = typename V2<T>::t;
+  constexpr bool RESID = (KIND & kFacResid) != 0, ADD = (KIND & kFacAdd) != 0, DUAL = (KIND & kFacDual) != 0,
+                 INF = (KIND & kFacInF) != 0;
+  __shared__ T2 inr[3][PIY][PIX];
+  __shared__ T2 tr[3][PEY][PEX];
+  __shared__ double sh[PNT / 64];
+  const int tid = threadIdx.x;
+  const int gx = (g.nx + PX - 1) / PX, gy = (g.ny + PY - 1) / PY;
+  const int per_sys = gx * gy * nzc;
+  const int s = a.list[blockIdx.x / per_sys];
+  int b = blockIdx.x % per_sys;
+  if (xcd_slab > 0) b = (b % 8) * xcd_slab + b / 8;
+  const int bx = b % gx, by = (b / gx) % gy, zc = b / (gx * gy);
+  const int x0 = bx * PX, y0 = by * PY;
+  const int zb = zc * czlen, ze = min(g.nz, zb + czlen);
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  const size_t plane = (size_t)g.nx * (size_t)g.ny;
+  const int gs = a.sys0 + s;
+  const int pole = gs / a.nrhs, rhs = gs % a.nrhs;
+  const FactorCoef c1 = a.coef[pole * a.cstride + a.k], c2 = a.coef[pole * a.cstride + a.k + 1];
+  const PoleDev pd = a.poles[pole];
+  const T a1r = (T)c1.a_re, a1i = (T)c1.a_im, b1r = (T)c1.b_re, b1i = (T)c1.b_im;
+  const T a2r = (T)c2.a_re, a2i = (T)c2.a_im, b2r = (T)c2.b_re, b2i = (T)c2.b_im;
+  const T2* __restrict__ X = INF ? a.f + (size_t)rhs * n : a.win + (size_t)s * n;
+  const T2* __restrict__ F = a.f + (size_t)rhs * n;
+  const T2* __restrict__ Y1 = a.y1 + (size_t)s * n;
+  T2* __restrict__ O = a.wout + (size_t)s * n;
+  T2* __restrict__ O2 = DUAL ? a.wout2 + (size_t)s * n : nullptr;
+  const T sh2 = (T)g.s_h2, dsc = (T)g.damp_scale;
+  const T diag0 = (T)6 * sh2 - (T)pd.z0_re, sim = (T)pd.z0_im;
+  const double zzr = pd.zz_re, zzi = pd.zz_im;
+
+  // input-tile duty: entries tid and tid + PNT of the 68 x 12 tile
+  constexpr int NIN = PIX * PIY;
+  bool in_ok[2];
+  size_t in_off[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i = tid + h * PNT;
+    const int ix = x0 - 2 + i % PIX, iy = y0 - 2 + i / PIX;
+    in_ok[h] = i < NIN && ix >= 0 && ix < g.nx && iy >= 0 && iy < g.ny;
+    in_off[h] = in_ok[h] ? (size_t)ix + (size_t)g.nx * (size_t)iy : 0;
+  }
+  // first-factor point of this thread (66 x 10 tile) and whether it is an output point
+  const bool tthr = tid < PEX * PEY;
+  const int ex = tid % PEX, ey = tid / PEX;
+  const int xe = x0 - 1 + ex, ye = y0 - 1 + ey;
+  const bool ine = tthr && xe >= 0 && xe < g.nx && ye >= 0 && ye < g.ny;
+  const bool core = ine && ex >= 1 && ex <= PX && ey >= 1 && ey <= PY;
+  const size_t oe = ine ? (size_t)xe + (size_t)g.nx * (size_t)ye : 0;
+  const int dxy = max(layer_depth(xe, g.nx, g.damp_cells), layer_depth(ye, g.ny, g.damp_cells));
+
+  auto load_in = [&](int kp, T2 (&r)[2]) {
+    const bool kin = kp >= 0 && kp < g.nz;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      r[h] = T2{(T)0, (T)0};
+      if (kin && in_ok[h]) r[h] = X[in_off[h] + plane * (size_t)kp];
+    }
+  };
+  auto store_in = [&](int kp, const T2 (&r)[2]) {
+    T2(*dst)[PIX] = inr[(kp + 3) % 3];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = tid + h * PNT;
+      if (i < NIN) dst[i / PIX][i % PIX] = r[h];
+    }
+  };
+  auto load_kap = [&](int kp) { return (ine && kp >= 0 && kp < g.nz) ? K[oe + plane * (size_t)kp] : (T)0; };
+
+  double acc = 0.0;
+  if (zb < ze) {
+    T2 r[2], rn[2];
+    load_in(zb - 2, r);
+    store_in(zb - 2, r);
+    load_in(zb - 1, r);
+    store_in(zb - 1, r);
+    load_in(zb, rn);
+    T kap_n = load_kap(zb - 1);
+    T2 fv_n = T2{(T)0, (T)0}, y1_n = T2{(T)0, (T)0};
+    T2 tprev = T2{(T)0, (T)0};
+    T kprev = (T)0;
+    for (int k = zb - 1; k <= ze; ++k) {
+      // inputs of this iteration (issued one plane ahead), then the next plane's loads
+      r[0] = rn[0];
+      r[1] = rn[1];
+      const T kap = kap_n;
+      const T2 fv = fv_n, y1v = y1_n;
+      load_in(k + 2, rn);
+      kap_n = load_kap(k + 1);
+      if constexpr (RESID) {
+        if (core && k + 1 >= zb && k + 1 < ze) fv_n = F[oe + plane * (size_t)(k + 1)];
+      }
+      if constexpr (ADD) {
+        if (core && k >= zb && k < ze) y1_n = Y1[oe + plane * (size_t)k];
+      }
+      store_in(k + 1, r);
+      __syncthreads();
+      // first factor at plane k on the 66 x 10 tile
+      T2 tv = T2{(T)0, (T)0};
+      if (tthr) {
+        if (ine && k >= 0 && k < g.nz) {
+          const T2(*cp)[PIX] = inr[(k + 3) % 3];
+          const T2 cen = cp[ey + 1][ex + 1];
+          const T2 xm = cp[ey + 1][ex], xp = cp[ey + 1][ex + 2], ym = cp[ey][ex + 1], yp = cp[ey + 2][ex + 1];
+          const T2 zm = inr[(k + 2) % 3][ey + 1][ex + 1], zp = inr[(k + 4) % 3][ey + 1][ex + 1];
+          const int d = max(dxy, layer_depth(k, g.nz, g.damp_cells));
+          const T dre = diag0 - kap;
+          const T dim = -((T)(d * d) * dsc + sim);
+          const T nbr = ((zm.x + zp.x) + (xm.x + xp.x)) + (ym.x + yp.x);
+          const T nbi = ((zm.y + zp.y) + (xm.y + xp.y)) + (ym.y + yp.y);
+          T2 Sx;
+          Sx.x = dre * cen.x - dim * cen.y - sh2 * nbr;
+          Sx.y = dre * cen.y + dim * cen.x - sh2 * nbi;
+          tv.x = a1r * Sx.x - a1i * Sx.y + b1r * cen.x - b1i * cen.y;
+          tv.y = a1r * Sx.y + a1i * Sx.x + b1r * cen.y + b1i * cen.x;
+          if constexpr (RESID) {
+            if (core && k >= zb && k < ze) {
+              const double rr = (double)fv.x - (double)Sx.x + zzr * (double)cen.x - zzi * (double)cen.y;
+              const double ri = (double)fv.y - (double)Sx.y + zzr * (double)cen.y + zzi * (double)cen.x;
+              acc += rr * rr + ri * ri;
+            }
+          }
+        }
+        tr[(k + 3) % 3][ey][ex] = tv;
+      }
+      __syncthreads();
+      // second factor at plane k-1 on the 64 x 8 core
+      const int km = k - 1;
+      if (core && km >= zb && km < ze) {
+        const T2(*cp)[PEX] = tr[(km + 3) % 3];
+        const T2 cen = tprev;
+        const T2 xm = cp[ey][ex - 1], xp = cp[ey][ex + 1], ym = cp[ey - 1][ex], yp = cp[ey + 1][ex];
+        const T2 zm = tr[(km + 2) % 3][ey][ex], zp = tr[(km + 4) % 3][ey][ex];
+        const int d = max(dxy, layer_depth(km, g.nz, g.damp_cells));
+        const T dre = diag0 - kprev;
+        const T dim = -((T)(d * d) * dsc + sim);
+        const T nbr = ((zm.x + zp.x) + (xm.x + xp.x)) + (ym.x + yp.x);
+        const T nbi = ((zm.y + zp.y) + (xm.y + xp.y)) + (ym.y + yp.y);
+        T2 Sx;
+        Sx.x = dre * cen.x - dim * cen.y - sh2 * nbr;
+        Sx.y = dre * cen.y + dim * cen.x - sh2 * nbi;
+        T2 o;
+        o.x = a2r * Sx.x - a2i * Sx.y + b2r * cen.x - b2i * cen.y;
+        o.y = a2r * Sx.y + a2i * Sx.x + b2r * cen.y + b2i * cen.x;
+        if constexpr (ADD) {
+          o.x += y1v.x;
+          o.y += y1v.y;
+        }
+        const size_t po = oe + plane * (size_t)km;
+        O[po] = o;
+        if constexpr (DUAL) O2[po] = o;
+      }
+      tprev = tv;
+      kprev = kap;
+    }
+  }
+  if constexpr (RESID) {
+    double v[1] = {acc};
+    block_sum<PNT, 1>(v, sh);
+    if (tid == 0) a.partial[(size_t)s * per_sys + (bx + gx * (by + gy * zc))] = v[0];
+  }
+}
+
 struct NoAux {};
 
 template <typename T>
@@ -536,10 +718,40 @@ void run(hipStream_t st, const GridDesc& g, int nsys, const Epi& epi) {
   }
 }
 
+struct PairShape {
+  int gx, gy, nzc, czlen, per_sys, xcd_slab;
+};
+
+template <typename T>
+PairShape pair_shape(const GridDesc& g) {
+  const KernelTune& t = tune_of<T>(g);
+  PairShape p;
+  p.gx = (g.nx + PX - 1) / PX;
+  p.gy = (g.ny + PY - 1) / PY;
+  int cz = t.cz;
+  if (cz <= 0) {
+    cz = 32;
+    while (cz > 8 && (long)p.gx * p.gy * ((g.nz + cz - 1) / cz) < 512) cz /= 2;
+  }
+  p.czlen = cz;
+  p.nzc = (g.nz + cz - 1) / cz;
+  p.per_sys = p.gx * p.gy * p.nzc;
+  p.xcd_slab = (p.per_sys % 8 == 0 && p.per_sys >= 64) ? p.per_sys / 8 : 0;
+  return p;
+}
+
+template <typename T, int KIND, typename T2>
+void run_pair(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a) {
+  if (a.count <= 0) return;
+  const PairShape p = pair_shape<T>(g);
+  hipLaunchKernelGGL((zpair_kernel<T, KIND>), dim3((unsigned)p.per_sys * (unsigned)a.count), dim3(PNT), 0, st, g,
+                     p.nzc, p.czlen, p.xcd_slab, a, (const T*)kappa);
+}
+
 }  // namespace
 
 bool tune_valid(const KernelTune& t) {
-  if (t.cz < 0 || t.cz > 4096 || !(t.ty == 4 || t.ty == 8)) return false;
+  if (t.cz < 0 || t.cz > 4096 || !(t.ty == 4 || t.ty == 8) || !(t.fuse == 0 || t.fuse == 1)) return false;
   if (t.kern == 0) return t.pd == 1 || t.pd == 2;
   if (t.kern == 1) return (t.ty == 4 && t.pd >= 1 && t.pd <= 3) || (t.ty == 8 && (t.pd == 2 || t.pd == 3));
   return false;
@@ -576,6 +788,27 @@ bool Launch<T2>::factor(hipStream_t st, const GridDesc& g, const void* kappa, co
     case kFacDual: run_factor<T, kFacDual>(st, g, kappa, a); break;
     case kFacInF: run_factor<T, kFacInF>(st, g, kappa, a); break;
     case kFacInF | kFacDual: run_factor<T, kFacInF | kFacDual>(st, g, kappa, a); break;
+    default: return false;
+  }
+  return true;
+}
+
+template <typename T2>
+int Launch<T2>::pair_blocks(const GridDesc& g) {
+  return pair_shape<typename Scal<T2>::t>(g).per_sys;
+}
+
+template <typename T2>
+bool Launch<T2>::factor_pair(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a,
+                             int kind) {
+  using T = typename Scal<T2>::t;
+  switch (kind) {
+    case 0: run_pair<T, 0>(st, g, kappa, a); break;
+    case kFacResid: run_pair<T, kFacResid>(st, g, kappa, a); break;
+    case kFacInF: run_pair<T, kFacInF>(st, g, kappa, a); break;
+    case kFacAdd: run_pair<T, kFacAdd>(st, g, kappa, a); break;
+    case kFacDual: run_pair<T, kFacDual>(st, g, kappa, a); break;
+    case kFacInF | kFacDual: run_pair<T, kFacInF | kFacDual>(st, g, kappa, a); break;
     default: return false;
   }
   return true;

@@ -267,23 +267,24 @@ class Operator(_Handle):
         keys = ["s", "s_h2", "b1", "b2", "rho2", "kappa_min", "kappa_max"]
         return dict(zip(keys, list(out)))
 
-    def set_tune(self, prec: int, kern: int, ty: int, pd: int, cz: int = 0):
-        """hfci_op_set_tune: stencil launch shape (kernel, 64 x ty tile, prefetch depth pd, z-chunk cz)."""
-        t = (ctypes.c_int * 4)(kern, ty, pd, cz)
+    def set_tune(self, prec: int, kern: int, ty: int, pd: int, cz: int = 0, fuse: int = 0):
+        """hfci_op_set_tune: stencil launch shape (kernel, 64 x ty tile, prefetch depth pd, z-chunk cz,
+        two fixed-point factors per pass)."""
+        t = (ctypes.c_int * 5)(kern, ty, pd, cz, fuse)
         _check(load_library().hfci_op_set_tune(self.h, prec, t))
 
     def autotune(self, prec: int, nsys: int = 2):
         """hfci_op_autotune: pick the fastest stencil launch shape; returns (best, [(shape, ms), ...])."""
-        best = (ctypes.c_int * 4)()
+        best = (ctypes.c_int * 5)()
         cap = 64
-        tm = (ctypes.c_double * (5 * cap))()
+        tm = (ctypes.c_double * (6 * cap))()
         cnt = ctypes.c_int()
         _check(load_library().hfci_op_autotune(self.h, prec, nsys, best, tm, cap, ctypes.byref(cnt)))
-        rows = [(tuple(int(v) for v in tm[5 * k:5 * k + 4]), float(tm[5 * k + 4])) for k in range(min(cnt.value, cap))]
+        rows = [(tuple(int(v) for v in tm[6 * k:6 * k + 5]), float(tm[6 * k + 5])) for k in range(min(cnt.value, cap))]
         return tuple(best), rows
 
     def get_tune(self, prec: int):
-        t = (ctypes.c_int * 4)()
+        t = (ctypes.c_int * 5)()
         _check(load_library().hfci_op_get_tune(self.h, prec, t))
         return tuple(t)
 

@@ -155,7 +155,7 @@ def main(argv=None):
     s.add_argument("--steps", type=int, default=2)
     s.add_argument("--q", type=int, default=8)
     s.add_argument("--prec", type=int, default=32)
-    s.add_argument("--tune", type=int, nargs=4, metavar=("KERN", "TY", "PD", "CZ"))
+    s.add_argument("--tune", type=int, nargs=5, metavar=("KERN", "TY", "PD", "CZ", "FUSE"))
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=2048)
     m = sub.add_parser("summarize")
@@ -169,7 +169,7 @@ def main(argv=None):
     m.add_argument("--kernel", required=True)
     m.add_argument("--out", required=True)
     m.add_argument("--traffic-json")
-    m.add_argument("--shape", type=int, nargs=4, help="stencil launch shape the counters were taken with")
+    m.add_argument("--shape", type=int, nargs=5, help="stencil launch shape the counters were taken with")
     m.add_argument("--alg-bytes", type=float, help="algorithmic bytes per launch of the counter runs")
     m.add_argument("--cmd", nargs=argparse.REMAINDER)
     a = ap.parse_args(argv)

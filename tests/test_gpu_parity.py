@@ -79,8 +79,9 @@ def test_apply_parity(ctx, shape, prec):
         assert rel(y[k], ref) <= tol, (shape, prec, k, rel(y[k], ref))
 
 
-TUNES = [(0, 4, 1, 0), (0, 4, 2, 0), (0, 8, 1, 0), (0, 8, 2, 3), (0, 4, 2, 1), (1, 4, 1, 0), (1, 4, 2, 0),
-         (1, 4, 3, 0), (1, 8, 2, 0), (1, 8, 3, 0), (1, 4, 3, 1), (1, 4, 2, 5), (1, 8, 3, 7)]
+TUNES = [(0, 4, 1, 0, 0), (0, 4, 2, 0, 0), (0, 8, 1, 0, 0), (0, 8, 2, 3, 0), (0, 4, 2, 1, 0), (1, 4, 1, 0, 0),
+         (1, 4, 2, 0, 0), (1, 4, 3, 0, 0), (1, 8, 2, 0, 0), (1, 8, 3, 0, 0), (1, 4, 3, 1, 0), (1, 4, 2, 5, 0),
+         (1, 8, 3, 7, 0), (1, 8, 2, 0, 1), (1, 8, 2, 1, 1), (1, 8, 2, 5, 1), (0, 4, 1, 3, 1)]
 
 
 @pytest.mark.parametrize("tune", TUNES)
@@ -135,9 +136,43 @@ def test_autotune_picks_a_timed_shape(ctx, pr):
     assert rel(y[0], o.apply(x[0], 0.2 + 0.7j)) <= (1e-13 if pr == 64 else 2e-6)
 
 
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5, 8])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fused_factor_pairs_every_q(ctx, q, prec):
+    # two factors per pass: every split of step one (q-1 factors) and of later steps (q)
+    # into pairs and a trailing single, adaptive stopping with the pair kernel's residual
+    # partials, on a grid with ragged 64 x 8 tiles and several z-chunks
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    pr = 64 if prec == "f64" else 32
+    shape = (21, 13, 70)
+    c = medium(shape, 41)
+    o, g = make_ops(ctx, c, 14.0, 3, 1.0)
+    g.set_tune(pr, 1, 8, 2, 8, 1)
+    poles = oracle_poles(o, 4, 1.0, 0.5, q)
+    cg = gpu_contour(g, poles, 4, q)
+    rng = np.random.default_rng(42)
+    f = rng.standard_normal((2,) + shape) + 1j * rng.standard_normal((2,) + shape)
+    Am = lambda v, sh: o.apply(v, sh)
+    y, st = hf.shifted_solve(g, cg, dev(f).to(dt), steps=3)
+    y = host(y)
+    for j, p in enumerate(poles):
+        for r in range(2):
+            ref, _ = OFP.fixed_point_solve(Am, f[r], p.z, p.z0, p.delta, q, steps=3)
+            assert rel(y[j, r], ref) <= (1e-12 if prec == "f64" else 2e-4), (j, r)
+    if prec == "f64":
+        y, st = hf.shifted_solve(g, cg, dev(f), reduce=5.0, max_steps=60)
+        y = host(y)
+        for j, p in enumerate(poles):
+            for r in range(2):
+                ref, hist = OFP.fixed_point_solve(Am, f[r], p.z, p.z0, p.delta, q, reduce=5.0, m_max=60)
+                assert st[j, r] == len(hist) - 1
+                assert rel(y[j, r], ref) <= 1e-12
+
+
 def test_tune_rejects_invalid(ctx):
     o, g = make_ops(ctx, medium((4, 4, 4), 1), 9.0, 1, 0.5)
-    for bad in [(2, 4, 1, 0), (0, 5, 1, 0), (0, 4, 3, 0), (1, 8, 1, 0), (1, 4, 4, 0), (0, 4, 1, -1)]:
+    for bad in [(2, 4, 1, 0), (0, 5, 1, 0), (0, 4, 3, 0), (1, 8, 1, 0), (1, 4, 4, 0), (0, 4, 1, -1),
+                (1, 8, 2, 0, 2)]:
         with pytest.raises(hf.HfciError):
             g.set_tune(32, *bad)
 
