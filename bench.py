@@ -99,6 +99,66 @@ def unet_flops_per_voxel():
     return lvl1 + lvl2 + lvl3
 
 
+def uneven_arm(args, ctx, verbose):
+    """Config-4 style uneven batch: independent GRF instances of sizes {48,64,96,128}^3 with
+    ppw ~ U[6,12] and 8 poles each, solved to the same tolerance as one hfci_solve_batch call
+    and one instance at a time; every solution's FP64 residual is recomputed by the oracle."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from oracle import operator as OO
+    from paper_1811_12378_amd import hfci
+    wls = W.config_uneven_batch(count=args.uneven, seed=7)
+    t0 = time.perf_counter()
+    ops, cons, fs = [], [], []
+    for wl in wls:
+        g = hfci.Operator(ctx, torch.from_numpy(wl.c).cuda(), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
+        ops.append(g)
+        cons.append(hfci.Contour(g, wl.n_poles, 1.0, args.eps, args.q))
+        fs.append(torch.from_numpy(wl.rhs[0]).cuda())
+    setup_s = time.perf_counter() - t0
+    opts = hfci.default_opts(precision=32, tol=args.tol, max_it=args.max_it)
+    hfci.solve_batch(ops, cons, fs, opts=hfci.default_opts(precision=32, tol=args.tol, max_it=1))  # allocate
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    us, sts, status = hfci.solve_batch(ops, cons, fs, opts=hfci.default_opts(precision=32, tol=args.tol,
+                                                                            max_it=args.max_it, verbose=verbose))
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t1
+    log("uneven batch of %d: %.3f s (%s), its %d..%d" % (len(ops), t_batch, status, min(s["its"] for s in sts),
+                                                          max(s["its"] for s in sts)))
+    for g, c, f in zip(ops, cons, fs):  # warm the single-instance workspaces
+        hfci.solve(g, c, f[None], opts=hfci.default_opts(precision=32, tol=args.tol, max_it=1))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    seq_its = []
+    for k, (g, c, f) in enumerate(zip(ops, cons, fs)):
+        _, st = hfci.solve(g, c, f[None], opts=opts)
+        seq_its.append(st["its"])
+        if k % 8 == 7:
+            log("sequential: %d of %d solved" % (k + 1, len(ops)))
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t2
+    log("one instance at a time: %.3f s" % t_seq)
+    worst = 0.0
+    for wl, u in zip(wls, us):
+        o = OO.Operator(wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
+        b = o.s * wl.rhs[0]
+        worst = max(worst, float(np.linalg.norm(b - o.apply(u.cpu().numpy())) / np.linalg.norm(b)))
+    sizes = {}
+    for wl in wls:
+        sizes[str(wl.c.shape[0])] = sizes.get(str(wl.c.shape[0]), 0) + 1
+    points = sum(int(wl.c.size) for wl in wls)
+    for g, c in zip(ops, cons):
+        c.close()
+        g.close()
+    return {"instances": len(wls), "grid_sizes": sizes, "points": points, "time_batch_s": round(t_batch, 4),
+            "time_sequential_s": round(t_seq, 4), "speedup_batch_vs_sequential": round(t_seq / t_batch, 3),
+            "its_min": min(s["its"] for s in sts), "its_max": max(s["its"] for s in sts),
+            "stencil_products": int(sts[0]["matvecs"] + sum(s["matvecs"] for s in sts[1:])),
+            "max_relres_oracle": worst, "status": status, "setup_s": round(setup_s, 2)}
+
+
 def learned_arm(args, ctx, op, cont, f_d, t_mixed, fp64, verbose):
     """Train the network on pairs from FCI-preconditioned FGMRES (untimed), then time the solve
     with the learned preconditioner (FCI as judge and fallback) and the network's throughput."""
@@ -162,6 +222,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner arm")
     ap.add_argument("--learn-media", type=int, default=12, help="64^3 training media for the learned arm")
     ap.add_argument("--learn-steps", type=int, default=2000, help="Adam steps for the learned arm")
+    ap.add_argument("--uneven", type=int, default=16,
+                    help="instances of the uneven-batch arm (64 = the full config; 0 skips it)")
+    ap.add_argument("--uneven-only", action="store_true", help="run only the uneven-batch arm")
     ap.add_argument("--shape", type=int, nargs=5, metavar=("KERN", "TY", "PD", "CZ", "FUSE"),
                     help="pin the complex64 stencil launch shape instead of autotuning it")
     args = ap.parse_args()
@@ -179,6 +242,15 @@ def main():
 
     hfci.load_library()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    verbose = 0 if args.quiet else 1
+    if args.uneven_only:
+        ctx = hfci.Context(0)
+        r = uneven_arm(args, ctx, verbose)
+        print(json.dumps({"metric": "uneven batch time-to-%g (s)" % args.tol, "value": r["time_batch_s"],
+                          "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f32+f64",
+                          "data": "synthetic", "config": {"workload": "uneven GRF batch"}, "uneven": r}),
+              flush=True)
+        return
     wl = W.config_layered_256(n=args.n, nrhs=args.nrhs, ppw=args.ppw)
     log("workload %s: omega %.3f, c in [%.3f, %.3f]" % (wl.name, wl.omega, wl.c.min(), wl.c.max()))
     ctx = hfci.Context(0)
@@ -269,6 +341,10 @@ def main():
                                                                          gbs64))
         del u64
 
+    uneven = None
+    if args.uneven > 0:
+        uneven = uneven_arm(args, ctx, verbose)
+
     learned = None
     if not args.no_learned:
         learned = learned_arm(args, ctx, op, cont, f_d, t_mixed, fp64, verbose)
@@ -318,6 +394,7 @@ def main():
         "factor_kernels_total_ms": launch_ms,
         "fp64": fp64,
         "learned": learned,
+        "uneven_batch": uneven,
     }
     print(json.dumps(out), flush=True)
 

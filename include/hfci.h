@@ -261,6 +261,32 @@ hfci_status hfci_solve(const hfci_op* op, const hfci_contour* c,
                        const hfci_solve_opts* opts, int nrhs,
                        const hfci_c128* f, hfci_c128* u, hfci_stats* stats);
 
+/* ---- uneven batches (independent operators of different sizes) -------------
+ * count instances (1..4096), instance i = operator ops[i] with its contour cons[i]
+ * (all on one context; all contours with the same q; at most 65536 shifted systems
+ * in all) and ONE right-hand side each.  Every factor of the fixed-point step is a
+ * single launch over the shifted systems of all instances still iterating (a work
+ * table maps workgroups to (instance, pole, tile)); the FCI quadrature, the step size
+ * and FGMRES run per instance, in lockstep over the Arnoldi steps.
+ *
+ * hfci_shifted_solve_batch: hfci_shifted_solve for every instance: f[i] DEVICE n_i
+ * values of the precision, y[i] DEVICE J_i * n_i (pole-major); steps_taken HOST,
+ * sum of J_i ints in instance order (may be NULL).
+ * hfci_solve_batch: hfci_solve for every instance: f[i], u[i] DEVICE complex128
+ * n_i (u[i] in: initial guess, out: solution), stats HOST array of count
+ * (may be NULL; each .size set).  stats[i] has instance i's FGMRES iterations,
+ * restarts, final relative residual and FGMRES products; the shifted-system products
+ * and fixed-point steps of the whole batch are added to stats[0].  precond must be
+ * HFCI_PRECOND_FCI (contours needed) or HFCI_PRECOND_NONE; no training harvest.
+ * Returns HFCI_W_NOCONV if any instance stops at max_it.  Errors: HFCI_E_ARG,
+ * HFCI_E_STATE (contour of another operator, operators on different contexts). */
+hfci_status hfci_shifted_solve_batch(int count, const hfci_op* const* ops, const hfci_contour* const* cons,
+                                     int prec, const void* const* f, void* const* y, int steps, double reduce,
+                                     int max_steps, int* steps_taken);
+hfci_status hfci_solve_batch(int count, const hfci_op* const* ops, const hfci_contour* const* cons,
+                             const hfci_solve_opts* opts, const hfci_c128* const* f, hfci_c128* const* u,
+                             hfci_stats* stats);
+
 /* ---- learned preconditioner (not part of the paper) -------------------------
  * A 3-level 3D U-Net (16/32/64 channels, 3x3x3 kernels, ReLU, 2x2x2 average
  * pooling, nearest up-sampling, skip concatenation, 1x1x1 head 16 -> 2) on

@@ -43,11 +43,18 @@ __global__ __launch_bounds__(NT) void reduce_kernel(const double* __restrict__ p
   if (threadIdx.x == 0) out[blockIdx.x] = v[0];
 }
 
+// Partial sums of conj(V_i) . w for the vectors of group blockIdx.y (NVMAX per group):
+// each thread reads w once and each vector of its group once per point.  Accumulators
+// are indexed only by compile-time constants (a runtime index would put them in scratch).
 template <int NVMAX>
 __global__ __launch_bounds__(NT) void multidot_kernel(const double2* __restrict__ V, int nv, size_t n,
                                                       size_t vstride, const double2* __restrict__ w,
                                                       double* __restrict__ partial) {
   __shared__ double sh[4 * 2 * NVMAX];
+  const int i0 = blockIdx.y * NVMAX;
+  const int ng = min(NVMAX, nv - i0);
+  V += (size_t)i0 * vstride;
+  partial += (size_t)2 * i0 * gridDim.x;
   double acc[2 * NVMAX];
 #pragma unroll
   for (int k = 0; k < 2 * NVMAX; ++k) acc[k] = 0.0;
@@ -56,7 +63,7 @@ __global__ __launch_bounds__(NT) void multidot_kernel(const double2* __restrict_
     const double2 wv = w[p];
 #pragma unroll
     for (int i = 0; i < NVMAX; ++i) {
-      if (i < nv) {
+      if (i < ng) {
         const double2 v = V[(size_t)i * vstride + p];
         acc[2 * i] += v.x * wv.x + v.y * wv.y;      // Re conj(v) w
         acc[2 * i + 1] += v.x * wv.y - v.y * wv.x;  // Im conj(v) w
@@ -65,7 +72,9 @@ __global__ __launch_bounds__(NT) void multidot_kernel(const double2* __restrict_
   }
   block_sum_n<2 * NVMAX>(acc, sh);
   if (threadIdx.x == 0) {
-    for (int k = 0; k < 2 * nv; ++k) partial[(size_t)k * gridDim.x + blockIdx.x] = acc[k];
+#pragma unroll
+    for (int k = 0; k < 2 * NVMAX; ++k)
+      if (k < 2 * ng) partial[(size_t)k * gridDim.x + blockIdx.x] = acc[k];
   }
 }
 
@@ -272,6 +281,34 @@ __global__ __launch_bounds__(NT) void build_list_kernel(const int* __restrict__ 
   }
 }
 
+// Stopping test of a batch of systems from different operators (see fp_check_kernel):
+// system s reduces its own partial row against the norm of its slot's right-hand side.
+template <typename T2>
+__global__ __launch_bounds__(NT) void fp_check_multi_kernel(const MultiSys<T2>* __restrict__ sys,
+                                                            const double* __restrict__ fnorm2, int fixed_steps,
+                                                            double inv_reduce2, int max_steps, int* __restrict__ active,
+                                                            int* __restrict__ steps, double* __restrict__ rnorm2) {
+  __shared__ double sh[4];
+  const int s = blockIdx.x;
+  if (active[s] == 0) return;
+  const MultiSys<T2> sd = sys[s];
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < sd.nblk; i += NT) v[0] += sd.partial[i];
+  block_sum_n<1>(v, sh);
+  if (threadIdx.x == 0) {
+    const double r2 = v[0];
+    rnorm2[s] = r2;
+    int act;
+    if (fixed_steps > 0)
+      act = steps[s] < fixed_steps;
+    else
+      act = (r2 > fnorm2[sd.slot] * inv_reduce2) && (steps[s] < max_steps);
+    if (!(r2 == r2) || r2 > 1e300) act = 0;
+    active[s] = act;
+    if (act) steps[s] += 1;
+  }
+}
+
 __global__ void dfinish_kernel(const double* __restrict__ sums, int nrhs, double* __restrict__ d) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < nrhs) {
@@ -319,19 +356,10 @@ void launch_reduce(hipStream_t st, const double* partial, int nblk, int ncomp, d
 
 void launch_multidot(hipStream_t st, const double2* V, int nv, size_t n, size_t vstride, const double2* w,
                      double* partial) {
+  if (nv <= 0) return;
   const int nb = blas_blocks(n);
-  if (nv > 32) {  // groups of 32 vectors; partial rows stay ordered by vector index
-    for (int i0 = 0; i0 < nv; i0 += 32)
-      launch_multidot(st, V + (size_t)i0 * vstride, nv - i0 < 32 ? nv - i0 : 32, n, vstride, w,
-                      partial + (size_t)2 * i0 * nb);
-    return;
-  }
-  if (nv <= 8)
-    hipLaunchKernelGGL(multidot_kernel<8>, dim3(nb), dim3(NT), 0, st, V, nv, n, vstride, w, partial);
-  else if (nv <= 16)
-    hipLaunchKernelGGL(multidot_kernel<16>, dim3(nb), dim3(NT), 0, st, V, nv, n, vstride, w, partial);
-  else
-    hipLaunchKernelGGL(multidot_kernel<32>, dim3(nb), dim3(NT), 0, st, V, nv, n, vstride, w, partial);
+  // groups of 8 vectors along grid y; partial rows stay ordered by vector index
+  hipLaunchKernelGGL(multidot_kernel<8>, dim3(nb, (nv + 7) / 8), dim3(NT), 0, st, V, nv, n, vstride, w, partial);
 }
 
 void launch_multiaxpy(hipStream_t st, double2* w, const double2* V, int nv, size_t n, size_t vstride,
@@ -399,6 +427,18 @@ void launch_fp_check(hipStream_t st, const double* partial, int nblk, int nsys, 
   hipLaunchKernelGGL(fp_check_kernel, dim3(nsys), dim3(NT), 0, st, partial, nblk, sys0, nrhs, fnorm2,
                      fixed_steps, 1.0 / (reduce * reduce), max_steps, active, steps, rnorm2);
 }
+
+template <typename T2>
+void launch_fp_check_multi(hipStream_t st, const MultiSys<T2>* sys, int nsys, const double* fnorm2, int fixed_steps,
+                           double reduce, int max_steps, int* active, int* steps, double* rnorm2) {
+  if (nsys > 0)
+    hipLaunchKernelGGL(fp_check_multi_kernel<T2>, dim3(nsys), dim3(NT), 0, st, sys, fnorm2, fixed_steps,
+                       1.0 / (reduce * reduce), max_steps, active, steps, rnorm2);
+}
+template void launch_fp_check_multi<float2>(hipStream_t, const MultiSys<float2>*, int, const double*, int, double, int,
+                                            int*, int*, double*);
+template void launch_fp_check_multi<double2>(hipStream_t, const MultiSys<double2>*, int, const double*, int, double,
+                                             int, int*, int*, double*);
 
 void launch_dfinish(hipStream_t st, const double* sums, int nrhs, double* d) {
   hipLaunchKernelGGL(dfinish_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, sums, nrhs, d);

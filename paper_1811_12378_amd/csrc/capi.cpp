@@ -557,6 +557,92 @@ hfci_status hfci_shifted_solve(const hfci_op* op, const hfci_contour* c, int pre
   HFCI_API_END
 }
 
+// Common checks of a batch: handles, one context, one q across the contours.
+static void check_batch(int count, const hfci_op* const* ops, const hfci_contour* const* cons, bool need_cons,
+                        std::vector<const Op*>& vo, std::vector<const Contour*>& vc) {
+  HFCI_REQUIRE(count >= 1 && count <= 4096, "count must be in [1, 4096]");
+  HFCI_REQUIRE(ops != nullptr && (!need_cons || cons != nullptr), "NULL argument");
+  long nsys = 0;
+  for (int i = 0; i < count; ++i) {
+    HFCI_REQUIRE(ops[i] != nullptr, "NULL operator in the batch");
+    if (ops[i]->ctx != ops[0]->ctx) throw Error(HFCI_E_STATE, "operators of a batch must share one context");
+    vo.push_back(ops[i]);
+    if (need_cons) {
+      HFCI_REQUIRE(cons[i] != nullptr, "NULL contour in the batch");
+      if (cons[i]->op != ops[i]) throw Error(HFCI_E_STATE, "contour was created for another operator");
+      if (cons[i]->q != cons[0]->q) throw Error(HFCI_E_ARG, "all contours of a batch must have the same q");
+      vc.push_back(cons[i]);
+      nsys += cons[i]->J;
+    }
+  }
+  HFCI_REQUIRE(nsys <= 65536, "more than 65536 shifted systems in the batch");
+}
+
+hfci_status hfci_shifted_solve_batch(int count, const hfci_op* const* ops, const hfci_contour* const* cons, int prec,
+                                     const void* const* f, void* const* y, int steps, double reduce, int max_steps,
+                                     int* steps_taken) {
+  HFCI_API_BEGIN
+  std::vector<const Op*> vo;
+  std::vector<const Contour*> vc;
+  check_batch(count, ops, cons, true, vo, vc);
+  HFCI_REQUIRE(f && y, "NULL argument");
+  for (int i = 0; i < count; ++i) HFCI_REQUIRE(f[i] && y[i], "NULL vector in the batch");
+  HFCI_REQUIRE(prec == HFCI_F32 || prec == HFCI_F64, "prec must be 32 or 64");
+  HFCI_REQUIRE(steps > 0 || (reduce > 1.0 && max_steps >= 1), "give steps > 0, or reduce > 1 and max_steps >= 1");
+  DeviceGuard dg(vo[0]->ctx->device);
+  FciStats st;
+  if (prec == HFCI_F64) {
+    std::vector<const double2*> fv(count);
+    std::vector<double2*> yv(count);
+    for (int i = 0; i < count; ++i) {
+      fv[i] = (const double2*)f[i];
+      yv[i] = (double2*)y[i];
+    }
+    shifted_solve_multi<double2>(vo[0]->ctx, vo, vc, fv, yv, steps, reduce, max_steps, steps_taken, st);
+  } else {
+    std::vector<const float2*> fv(count);
+    std::vector<float2*> yv(count);
+    for (int i = 0; i < count; ++i) {
+      fv[i] = (const float2*)f[i];
+      yv[i] = (float2*)y[i];
+    }
+    shifted_solve_multi<float2>(vo[0]->ctx, vo, vc, fv, yv, steps, reduce, max_steps, steps_taken, st);
+  }
+  HFCI_HIP(hipGetLastError());
+  HFCI_HIP(hipStreamSynchronize(vo[0]->ctx->stream));
+  return HFCI_OK;
+  HFCI_API_END
+}
+
+hfci_status hfci_solve_batch(int count, const hfci_op* const* ops, const hfci_contour* const* cons,
+                             const hfci_solve_opts* o, const hfci_c128* const* f, hfci_c128* const* u,
+                             hfci_stats* stats) {
+  HFCI_API_BEGIN
+  check_opts(o);
+  HFCI_REQUIRE(o->precond == HFCI_PRECOND_FCI || o->precond == HFCI_PRECOND_NONE,
+               "a batch takes precond = HFCI_PRECOND_FCI or HFCI_PRECOND_NONE");
+  HFCI_REQUIRE(o->harvest_cap == 0, "a batch does not harvest training pairs");
+  std::vector<const Op*> vo;
+  std::vector<const Contour*> vc;
+  check_batch(count, ops, cons, o->precond == HFCI_PRECOND_FCI, vo, vc);
+  HFCI_REQUIRE(f && u, "NULL argument");
+  for (int i = 0; i < count; ++i) HFCI_REQUIRE(f[i] && u[i], "NULL vector in the batch");
+  if (stats)
+    for (int i = 0; i < count; ++i) HFCI_REQUIRE(stats[i].size == sizeof(hfci_stats), "stats[i].size mismatch");
+  DeviceGuard dg(vo[0]->ctx->device);
+  std::vector<const double2*> fv(count);
+  std::vector<double2*> uv(count);
+  for (int i = 0; i < count; ++i) {
+    fv[i] = (const double2*)f[i];
+    uv[i] = (double2*)u[i];
+  }
+  const hfci_status st = solve_batch(vo, vc, *o, fv, uv, stats);
+  HFCI_HIP(hipGetLastError());
+  HFCI_HIP(hipStreamSynchronize(vo[0]->ctx->stream));
+  return st;
+  HFCI_API_END
+}
+
 hfci_status hfci_fci_apply(const hfci_op* op, const hfci_contour* c, const hfci_solve_opts* o, int nrhs,
                            const hfci_c128* f, hfci_c128* out, hfci_stats* stats) {
   HFCI_API_BEGIN

@@ -195,6 +195,16 @@ KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, d
 struct FciStats {
   long long matvecs = 0, fp_steps = 0;
 };
+
+// ---- batch.cpp: uneven batches of operators ----
+template <typename T2>
+void shifted_solve_multi(Ctx* ctx, const std::vector<const Op*>& ops, const std::vector<const Contour*>& cons,
+                         const std::vector<const T2*>& f, const std::vector<T2*>& y, int fixed_steps, double reduce,
+                         int max_steps, int* steps_out, FciStats& st);
+hfci_status solve_batch(const std::vector<const Op*>& ops, const std::vector<const Contour*>& cons,
+                        const hfci_solve_opts& o, const std::vector<const double2*>& f, const std::vector<double2*>& u,
+                        hfci_stats* stats);
+
 template <typename T2>
 void shifted_solve_batch(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int fixed_steps,
                          double reduce, int max_steps, int* steps_out, FciStats& st);

@@ -83,6 +83,41 @@ struct Launch {
   static int partial_blocks(const GridDesc& g);
 };
 
+// ---- uneven batches: many operators in one launch (work table) ----
+// Per instance: its grid, kappa and the launch geometry of its stencil tiles.
+struct MultiInst {
+  GridDesc g;
+  const void* kappa;  // float* or double*
+  int gx, gy, nzc, czlen, xcd_slab, per_sys;
+};
+// Per shifted system (instance, pole): its vectors by role (0 f, 1 y, 2 y1, 3 wA, 4 wB),
+// the pole's factor coefficients and constants, its residual-partial row.
+enum : int { kRoleF = 0, kRoleY = 1, kRoleY1 = 2, kRoleWA = 3, kRoleWB = 4, kRoleNone = -1 };
+template <typename T2>
+struct MultiSys {
+  T2* vec[5];
+  const FactorCoef* coef;  // this pole's cstride coefficients
+  const PoleDev* pole;
+  double* partial;         // nblk doubles
+  int inst, nblk, slot, pad;
+};
+// One factor launch over the systems listed in the work table seg[i] = {first block,
+// system}, ascending in the first block; a block finds its system by binary search.
+template <typename T2>
+struct MultiLaunch {
+  static constexpr int kTy = 8, kPd = 2;  // launch shape of the multi-instance kernel
+  static void factor(hipStream_t st, const MultiInst* inst, const MultiSys<T2>* sys, const int2* seg, int nseg,
+                     int nblocks, int kind, int role_in, int role_out, int role_out2, int k, int cstride,
+                     bool f64);
+  // geometry of one instance for this launch shape (host)
+  static MultiInst describe(const GridDesc& g, const void* kappa);
+};
+// fixed-point bookkeeping of a batch: per system s, its partial row (sys[s].partial,
+// sys[s].nblk) against fnorm2[sys[s].slot]
+template <typename T2>
+void launch_fp_check_multi(hipStream_t st, const MultiSys<T2>* sys, int nsys, const double* fnorm2,
+                           int fixed_steps, double reduce, int max_steps, int* active, int* steps, double* rnorm2);
+
 // FP64 residual r = b - A u (shift 0) with partial sums of |r|^2.
 void launch_residual64(hipStream_t st, const GridDesc& g, const double* kappa, const double2* b,
                        const double2* u, double2* r, double* partial);

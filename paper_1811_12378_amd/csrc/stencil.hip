@@ -194,8 +194,11 @@ struct PlaneRec {
   Aux aux;
 };
 
+// The work of one block: tile (bx, by) of the gx x gy tiles of a plane, z-chunk zc of
+// nzc, system s of the epilogue.
 template <typename T, class Epi, int TY, int D>
-__global__ __launch_bounds__(TX * TY) void zlds_kernel(GridDesc g, int nzc, int czlen, int xcd_slab, Epi epi) {
+__device__ __forceinline__ void zlds_tile(const GridDesc& g, int nzc, int czlen, const Epi& epi, int s, int bx,
+                                          int by, int zc, int gx, int gy) {
   constexpr int NT = TX * TY, U = 4, LW = TX + 2;
   static_assert(D >= 1 && D < U, "prefetch depth 1..3");
   static_assert(TY >= 3, "the halo assignment needs three waves");
@@ -205,11 +208,6 @@ __global__ __launch_bounds__(TX * TY) void zlds_kernel(GridDesc g, int nzc, int 
   constexpr int NACC = Epi::NACC;
   __shared__ T2 tile[2][TY + 2][LW];
   __shared__ double sh[(NT / 64) * (NACC > 0 ? NACC : 1)];
-  const int gx = gridDim.x, gy = gridDim.y;
-  const int s = epi.system(blockIdx.z / nzc);
-  int b = blockIdx.x + gx * (blockIdx.y + gy * (blockIdx.z % nzc));
-  if (xcd_slab > 0) b = (b % 8) * xcd_slab + b / 8;
-  const int bx = b % gx, by = (b / gx) % gy, zc = b / (gx * gy);
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int x0 = bx * TX, y0 = by * TY;
   const int x = x0 + lx, y = y0 + ly;
@@ -314,6 +312,15 @@ __global__ __launch_bounds__(TX * TY) void zlds_kernel(GridDesc g, int nzc, int 
       for (int k = 0; k < NACC; ++k) epi.partial_out(s, k, nblk, blk, acc[k]);
     }
   }
+}
+
+template <typename T, class Epi, int TY, int D>
+__global__ __launch_bounds__(TX * TY) void zlds_kernel(GridDesc g, int nzc, int czlen, int xcd_slab, Epi epi) {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int s = epi.system(blockIdx.z / nzc);
+  int b = blockIdx.x + gx * (blockIdx.y + gy * (blockIdx.z % nzc));
+  if (xcd_slab > 0) b = (b % 8) * xcd_slab + b / 8;
+  zlds_tile<T, Epi, TY, D>(g, nzc, czlen, epi, s, b % gx, (b / gx) % gy, b / (gx * gy), gx, gy);
 }
 
 // Two consecutive factors of the fixed-point step in one pass (temporal blocking):
@@ -651,6 +658,50 @@ struct EpiResidual {
   __device__ void partial_out(int, int, int, int blk, double v) const { partial[blk] = v; }
 };
 
+// Uneven batches: one factor launch over the shifted systems of many operators.  A block
+// finds its system in the work table (binary search over the first-block column), reads
+// the system's vectors and its operator's geometry from the descriptors, and runs the
+// LDS-staged tile of that operator with the factor epilogue on that system alone.
+template <typename T, int KIND, int TY, int D>
+__global__ __launch_bounds__(TX * TY) void zmulti_kernel(const MultiInst* __restrict__ inst,
+                                                         const MultiSys<typename V2<T>::t>* __restrict__ sys,
+                                                         const int2* __restrict__ seg, int nseg, int rin, int rout,
+                                                         int rout2, int k, int cstride) {
+  using T2 = typename V2<T>::t;
+  const int b = blockIdx.x;
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (seg[mid].x <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int G = seg[lo].y;
+  int local = b - seg[lo].x;
+  // fields are read through the pointer: a dynamic index into a copied descriptor
+  // (vec[role]) would put the copy in scratch memory
+  const MultiSys<T2>* __restrict__ sd = sys + G;
+  const MultiInst id = inst[sd->inst];
+  if (id.xcd_slab > 0) local = (local % 8) * id.xcd_slab + local / 8;
+  FactorArgs<T2> a{};
+  a.win = sd->vec[rin];
+  a.f = sd->vec[kRoleF];
+  a.y1 = sd->vec[kRoleY1];
+  a.wout = sd->vec[rout];
+  a.wout2 = rout2 >= 0 ? sd->vec[rout2] : nullptr;
+  a.coef = sd->coef;
+  a.poles = sd->pole;
+  a.list = nullptr;
+  a.partial = sd->partial;
+  a.count = 1;
+  a.sys0 = 0;
+  a.nrhs = 1;
+  a.cstride = cstride;
+  a.k = k;
+  const EpiFactor<T, KIND> e{a, (const T*)id.kappa, (size_t)id.g.nx * id.g.ny * id.g.nz};
+  zlds_tile<T, EpiFactor<T, KIND>, TY, D>(id.g, id.nzc, id.czlen, e, 0, local % id.gx, (local / id.gx) % id.gy,
+                                          local / (id.gx * id.gy), id.gx, id.gy);
+}
+
 struct Shape {
   dim3 grid, block;
   int nzc, czlen, xcd_slab;
@@ -815,6 +866,58 @@ bool Launch<T2>::factor_pair(hipStream_t st, const GridDesc& g, const void* kapp
 }
 
 template <typename T2>
+MultiInst MultiLaunch<T2>::describe(const GridDesc& g0, const void* kappa) {
+  using T = typename Scal<T2>::t;
+  GridDesc g = g0;
+  KernelTune& t = sizeof(T) == 4 ? g.tune32 : g.tune64;
+  t.kern = 1;
+  t.ty = kTy;
+  t.pd = kPd;
+  t.cz = 0;
+  t.fuse = 0;
+  const Shape sh = shape_for<T>(g, 1);
+  MultiInst m;
+  m.g = g;
+  m.kappa = kappa;
+  m.gx = (int)sh.grid.x;
+  m.gy = (int)sh.grid.y;
+  m.nzc = sh.nzc;
+  m.czlen = sh.czlen;
+  m.xcd_slab = sh.xcd_slab;
+  m.per_sys = m.gx * m.gy * m.nzc;
+  return m;
+}
+
+template <typename T, int KIND, typename T2>
+void run_multi(hipStream_t st, const MultiInst* inst, const MultiSys<T2>* sys, const int2* seg, int nseg, int nblocks,
+               int rin, int rout, int rout2, int k, int cstride) {
+  constexpr int TY = MultiLaunch<T2>::kTy, PD = MultiLaunch<T2>::kPd;
+  hipLaunchKernelGGL((zmulti_kernel<T, KIND, TY, PD>), dim3((unsigned)nblocks), dim3(TX, TY), 0, st, inst, sys, seg,
+                     nseg, rin, rout, rout2, k, cstride);
+}
+
+template <typename T2>
+void MultiLaunch<T2>::factor(hipStream_t st, const MultiInst* inst, const MultiSys<T2>* sys, const int2* seg, int nseg,
+                             int nblocks, int kind, int rin, int rout, int rout2, int k, int cstride, bool) {
+  using T = typename Scal<T2>::t;
+  if (nseg <= 0 || nblocks <= 0) return;
+  switch (kind) {
+    case 0: run_multi<T, 0>(st, inst, sys, seg, nseg, nblocks, rin, rout, rout2, k, cstride); break;
+    case kFacResid: run_multi<T, kFacResid>(st, inst, sys, seg, nseg, nblocks, rin, rout, rout2, k, cstride); break;
+    case kFacResid | kFacAdd:
+      run_multi<T, kFacResid | kFacAdd>(st, inst, sys, seg, nseg, nblocks, rin, rout, rout2, k, cstride);
+      break;
+    case kFacAdd: run_multi<T, kFacAdd>(st, inst, sys, seg, nseg, nblocks, rin, rout, rout2, k, cstride); break;
+    case kFacDual: run_multi<T, kFacDual>(st, inst, sys, seg, nseg, nblocks, rin, rout, rout2, k, cstride); break;
+    case kFacInF: run_multi<T, kFacInF>(st, inst, sys, seg, nseg, nblocks, rin, rout, rout2, k, cstride); break;
+    case kFacInF | kFacDual:
+      run_multi<T, kFacInF | kFacDual>(st, inst, sys, seg, nseg, nblocks, rin, rout, rout2, k, cstride);
+      break;
+    default: break;
+  }
+}
+
+template <typename T2>
 void Launch<T2>::dstep_partials(hipStream_t st, const GridDesc& g, const void* kappa, int nrhs,
                                 const T2* w, const T2* f, double* partial) {
   using T = typename Scal<T2>::t;
@@ -830,5 +933,7 @@ void launch_residual64(hipStream_t st, const GridDesc& g, const double* kappa, c
 
 template struct Launch<float2>;
 template struct Launch<double2>;
+template struct MultiLaunch<float2>;
+template struct MultiLaunch<double2>;
 
 }  // namespace hfci

@@ -32,7 +32,8 @@ EXPORTED = ["hfci_default_opts", "hfci_last_error", "hfci_version", "hfci_ctx_cr
             "hfci_ctx_profile", "hfci_ctx_profile_read", "hfci_net_create", "hfci_net_destroy",
             "hfci_net_param_count", "hfci_net_get_params", "hfci_net_set_params", "hfci_net_get_grads",
             "hfci_net_eval", "hfci_net_train_step", "hfci_net_train", "hfci_net_apply", "hfci_op_medium_channel",
-            "hfci_net_save", "hfci_net_load", "hfci_op_set_tune", "hfci_op_get_tune", "hfci_op_autotune"]
+            "hfci_net_save", "hfci_net_load", "hfci_op_set_tune", "hfci_op_get_tune", "hfci_op_autotune",
+            "hfci_shifted_solve_batch", "hfci_solve_batch"]
 PROF_CLASSES = ["fp_stage", "fp_stage_first", "apply", "fp_stage_last", "fp_stage_init"]
 
 
@@ -133,6 +134,11 @@ def load_library(path: str = LIB_PATH):
         "hfci_net_save": (ip, [vp, ctypes.c_char_p]),
         "hfci_net_load": (ip, [vp, ctypes.c_char_p]),
         "hfci_ctx_profile_read": (ip, [vp, P(KernelProf)]),
+        "hfci_op_set_tune": (ip, [vp, ip, vp]),
+        "hfci_op_get_tune": (ip, [vp, ip, vp]),
+        "hfci_op_autotune": (ip, [vp, ip, ip, vp, vp, ip, vp]),
+        "hfci_shifted_solve_batch": (ip, [ip, vp, vp, ip, vp, vp, ip, dp, ip, vp]),
+        "hfci_solve_batch": (ip, [ip, vp, vp, P(SolveOpts), vp, vp, P(Stats)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -271,7 +277,7 @@ class Operator(_Handle):
         """hfci_op_set_tune: stencil launch shape (kernel, 64 x ty tile, prefetch depth pd, z-chunk cz,
         two fixed-point factors per pass)."""
         t = (ctypes.c_int * 5)(kern, ty, pd, cz, fuse)
-        _check(load_library().hfci_op_set_tune(self.h, prec, t))
+        _check(load_library().hfci_op_set_tune(self.h, prec, ctypes.cast(t, ctypes.c_void_p)))
 
     def autotune(self, prec: int, nsys: int = 2):
         """hfci_op_autotune: pick the fastest stencil launch shape; returns (best, [(shape, ms), ...])."""
@@ -279,13 +285,15 @@ class Operator(_Handle):
         cap = 64
         tm = (ctypes.c_double * (6 * cap))()
         cnt = ctypes.c_int()
-        _check(load_library().hfci_op_autotune(self.h, prec, nsys, best, tm, cap, ctypes.byref(cnt)))
+        _check(load_library().hfci_op_autotune(self.h, prec, nsys, ctypes.cast(best, ctypes.c_void_p),
+                                               ctypes.cast(tm, ctypes.c_void_p), cap,
+                                               ctypes.cast(ctypes.byref(cnt), ctypes.c_void_p)))
         rows = [(tuple(int(v) for v in tm[6 * k:6 * k + 5]), float(tm[6 * k + 5])) for k in range(min(cnt.value, cap))]
         return tuple(best), rows
 
     def get_tune(self, prec: int):
         t = (ctypes.c_int * 5)()
-        _check(load_library().hfci_op_get_tune(self.h, prec, t))
+        _check(load_library().hfci_op_get_tune(self.h, prec, ctypes.cast(t, ctypes.c_void_p)))
         return tuple(t)
 
 
@@ -479,3 +487,52 @@ def solve(op: Operator, c: Contour | None, f, u0=None, opts: SolveOpts | None = 
     d = st.as_dict()
     d["status"] = STATUS_NAMES[status]
     return u, d
+
+
+def _ptr_array(ts, dtype=None, what="vector"):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = _ptr(t, dtype, what)
+    return arr
+
+
+def shifted_solve_batch(ops, contours, fs, steps: int = 0, reduce: float = 5.0, max_steps: int = 200):
+    """hfci_shifted_solve_batch: fs[i] [nz_i, ny_i, nx_i] (one rhs per instance, complex64 or complex128)
+    -> ([y_i [J_i, nz_i, ny_i, nx_i]], [steps_i [J_i]])."""
+    import torch
+    prec = _prec_of(fs[0])
+    ys = [torch.empty((c.J,) + tuple(f.shape), dtype=f.dtype, device=f.device) for c, f in zip(contours, fs)]
+    nsys = sum(c.J for c in contours)
+    st = (ctypes.c_int * nsys)()
+    oh = (ctypes.c_void_p * len(ops))(*[o.h.value for o in ops])
+    ch = (ctypes.c_void_p * len(ops))(*[c.h.value for c in contours])
+    _sync()
+    _check(load_library().hfci_shifted_solve_batch(len(ops), ctypes.cast(oh, ctypes.c_void_p),
+                                                   ctypes.cast(ch, ctypes.c_void_p), prec,
+                                                   ctypes.cast(_ptr_array(fs, None, "f"), ctypes.c_void_p),
+                                                   ctypes.cast(_ptr_array(ys), ctypes.c_void_p), steps, reduce,
+                                                   max_steps, ctypes.cast(st, ctypes.c_void_p)))
+    out, k = [], 0
+    for c in contours:
+        out.append(np.array(st[k:k + c.J]))
+        k += c.J
+    return ys, out
+
+
+def solve_batch(ops, contours, fs, opts: SolveOpts | None = None, u0s=None):
+    """hfci_solve_batch: physical fs[i] complex128 [nz_i, ny_i, nx_i] -> ([u_i], [stats_i], status)."""
+    import torch
+    opts = opts or default_opts()
+    n = len(ops)
+    us = [torch.zeros_like(f) if u0s is None else u0s[i].clone() for i, f in enumerate(fs)]
+    sts = (Stats * n)()
+    for k in range(n):
+        sts[k].size = ctypes.sizeof(Stats)
+    oh = (ctypes.c_void_p * n)(*[o.h.value for o in ops])
+    ch = (ctypes.c_void_p * n)(*[c.h.value for c in contours]) if contours is not None else None
+    _sync()
+    status = _check(load_library().hfci_solve_batch(
+        n, ctypes.cast(oh, ctypes.c_void_p), ctypes.cast(ch, ctypes.c_void_p) if ch is not None else None,
+        ctypes.byref(opts), ctypes.cast(_ptr_array(fs, torch.complex128, "f"), ctypes.c_void_p),
+        ctypes.cast(_ptr_array(us), ctypes.c_void_p), sts))
+    return us, [sts[k].as_dict() for k in range(n)], STATUS_NAMES[status]

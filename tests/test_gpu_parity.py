@@ -414,3 +414,103 @@ def test_error_paths(ctx):
     f = dev(np.ones((1, 4, 4, 4), dtype=complex))
     u, st = hf.solve(g, cg, f, opts=hf.default_opts(tol=1e-14, max_it=2))
     assert st["status"] == "HFCI_W_NOCONV" and st["its"] == 2
+
+
+# ---- uneven batches (several operators in one launch per factor) ----
+
+def _batch_instances(ctx, shapes, q, seed=50):
+    out = []
+    for k, shape in enumerate(shapes):
+        c = medium(shape, seed + k, 1.0, 2.5)
+        o, g = make_ops(ctx, c, 10.0 + 2.0 * k, 2 + (k % 2), 1.0)
+        J = 4 + 2 * (k % 2)
+        poles = oracle_poles(o, J, 1.0, 0.5, q)
+        out.append((o, g, poles, gpu_contour(g, poles, J, q), J))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_shifted_solve_batch_matches_oracle(ctx, prec):
+    shapes = [(9, 12, 20), (16, 16, 16), (7, 10, 70), (12, 5, 9)]
+    q = 4
+    inst = _batch_instances(ctx, shapes, q)
+    rng = np.random.default_rng(51)
+    fs = [rng.standard_normal(sh) + 1j * rng.standard_normal(sh) for sh in shapes]
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    tol = 1e-12 if prec == "f64" else 2e-4
+    ys, st = hf.shifted_solve_batch([i[1] for i in inst], [i[3] for i in inst], [dev(f).to(dt) for f in fs], steps=3)
+    for (o, g, poles, cg, J), y, f, s in zip(inst, ys, fs, st):
+        assert np.all(s == 3)
+        y = host(y)
+        Am = lambda v, sh, o=o: o.apply(v, sh)
+        for j, p in enumerate(poles):
+            ref, _ = OFP.fixed_point_solve(Am, f, p.z, p.z0, p.delta, q, steps=3)
+            assert rel(y[j], ref) <= tol, (j, rel(y[j], ref))
+    if prec == "f64":
+        # adaptive stopping: every (instance, pole) stops at the oracle's step with the oracle's iterate
+        ys, st = hf.shifted_solve_batch([i[1] for i in inst], [i[3] for i in inst], [dev(f) for f in fs],
+                                        reduce=5.0, max_steps=80)
+        counts = set()
+        for (o, g, poles, cg, J), y, f, s in zip(inst, ys, fs, st):
+            y = host(y)
+            Am = lambda v, sh, o=o: o.apply(v, sh)
+            for j, p in enumerate(poles):
+                ref, hist = OFP.fixed_point_solve(Am, f, p.z, p.z0, p.delta, q, reduce=5.0, m_max=80)
+                assert s[j] == len(hist) - 1
+                assert rel(y[j], ref) <= 1e-12
+                counts.add(int(s[j]))
+        assert len(counts) >= 3
+
+
+def test_solve_batch_equals_single_solves(ctx):
+    # FP64 sweeps with a fixed step count: the batch runs the same arithmetic per point as
+    # the single-operator path, so every instance's FGMRES history and solution agree
+    shapes = [(12, 12, 12), (10, 14, 18), (16, 9, 11)]
+    q = 4
+    inst = _batch_instances(ctx, shapes, q, seed=60)
+    rng = np.random.default_rng(61)
+    fs = [dev(rng.standard_normal(sh) + 1j * rng.standard_normal(sh)) for sh in shapes]
+    opts = hf.default_opts(precision=64, tol=1e-9, max_it=200, fp_steps=2)
+    us, sts, status = hf.solve_batch([i[1] for i in inst], [i[3] for i in inst], fs, opts=opts)
+    assert status == "HFCI_OK"
+    for (o, g, poles, cg, J), u, f, stb in zip(inst, us, fs, sts):
+        u1, st1 = hf.solve(g, cg, f[None], opts=opts)
+        assert stb["its"] == st1["its"]
+        assert rel(host(u), host(u1)[0]) <= 1e-11
+        # the oracle's FP64 residual of the returned solution
+        b = o.s * host(f)
+        assert np.linalg.norm(b - o.apply(host(u))) / np.linalg.norm(b) <= 1e-8
+
+
+def test_solve_batch_mixed_precision_uneven_sizes(ctx):
+    import workloads as W
+    wls = W.config_uneven_batch(count=5, seed=3, sizes=(12, 16, 20, 24))
+    ops, cons, fs, os_ = [], [], [], []
+    for wl in wls:
+        g = hf.Operator(ctx, dev(wl.c), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
+        ops.append(g)
+        cons.append(hf.Contour(g, wl.n_poles, 1.0, 0.25, 8))
+        fs.append(dev(wl.rhs[0]))
+        os_.append(OO.Operator(wl.c, wl.omega, wl.damp_cells, wl.damp_rho2))
+    opts = hf.default_opts(precision=32, tol=1e-7, max_it=400)
+    us, sts, status = hf.solve_batch(ops, cons, fs, opts=opts)
+    assert status == "HFCI_OK"
+    assert sts[0]["fp_steps"] > 0
+    for o, u, f, st in zip(os_, us, fs, sts):
+        b = o.s * host(f)
+        r = np.linalg.norm(b - o.apply(host(u))) / np.linalg.norm(b)
+        assert r <= 1e-7 * 1.01 and st["final_relres"] <= 1e-7
+
+
+def test_batch_error_paths(ctx):
+    o, g = make_ops(ctx, medium((6, 6, 6), 1), 9.0, 1, 0.5)
+    o2, g2 = make_ops(ctx, medium((6, 6, 7), 2), 9.0, 1, 0.5)
+    poles = oracle_poles(o, 4, 1.0, 0.5, 4)
+    c1 = gpu_contour(g, poles, 4, 4)
+    c8 = hf.Contour(g2, 4, 1.0, 0.5, 8)
+    f = dev(np.ones((6, 6, 6), dtype=np.complex128))
+    f2 = dev(np.ones((6, 6, 7), dtype=np.complex128))
+    with pytest.raises(hf.HfciError):  # q differs across the batch
+        hf.solve_batch([g, g2], [c1, c8], [f, f2])
+    with pytest.raises(hf.HfciError):  # contour of another operator
+        hf.solve_batch([g, g2], [c8, c1], [f, f2])
