@@ -184,7 +184,7 @@ hfci_status hfci_op_info(const hfci_op* op, double* out7);
  *                 kern 1: 1..3 with ty = 4, 2..3 with ty = 8);
  *   tune[3] cz:   z-chunk length in planes (1..4096, or 0 = chosen from the grid);
  *   tune[4] fuse: 1 = the fixed-point factors run two per pass over HBM (temporal
- *                 blocking on 64 x 8 tiles with z-chunks cz), 0 = one per pass.
+ *                 blocking on 64 x 12 tiles with z-chunks cz), 0 = one per pass.
  * Shapes change launch geometry only: every grid point gets the same arithmetic,
  * while reductions (residual norms, the step size d) sum their block partials in a
  * different order.  New operators start at {1, 8, 2, 0, 0}.  Errors: HFCI_E_ARG. */

@@ -12,7 +12,7 @@ namespace hfci {
 // Launch shape of the z-marching stencil kernels: kern 0 keeps the in-plane neighbours
 // as cached global loads, kern 1 stages each plane through LDS; a 64 x ty thread tile,
 // HBM streams prefetched pd planes ahead, z-chunks of cz planes (0: from the grid size);
-// fuse 1 applies the fixed-point factors two per pass (64 x 8 tiles, z-chunks cz).
+// fuse 1 applies the fixed-point factors two per pass (64 x 12 tiles, z-chunks cz).
 struct KernelTune {
   int kern = 1, ty = 8, pd = 2, cz = 0, fuse = 0;
 };

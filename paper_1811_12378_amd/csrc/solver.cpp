@@ -257,7 +257,7 @@ KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, d
     for (int pd : {1, 2, 3}) cands.push_back(KernelTune{1, 4, pd, cz, 0});
     for (int pd : {2, 3}) cands.push_back(KernelTune{1, 8, pd, cz, 0});
   }
-  // two factors per pass (its own 64 x 8 tiles; per-factor time = half a launch)
+  // two factors per pass (its own 64 x 12 tiles; per-factor time = half a launch)
   for (int cz : {0, 16, 64}) cands.push_back(KernelTune{1, 8, 2, cz, 1});
   hipEvent_t e0, e1;
   HFCI_HIP(hipEventCreate(&e0));

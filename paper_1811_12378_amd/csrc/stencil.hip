@@ -325,18 +325,18 @@ __global__ __launch_bounds__(TX * TY) void zlds_kernel(GridDesc g, int nzc, int 
 
 // Two consecutive factors of the fixed-point step in one pass (temporal blocking):
 //   t = a1 (A - z0) w + b1 w,   out = a2 (A - z0) t + b2 t  [+ y1].
-// A block owns a 64 x 8 output tile and a z-chunk.  Per plane k it stages the input
-// plane k+1 on the 68 x 12 tile (two-point halo) in a 3-plane LDS ring, computes the
-// first factor on the 66 x 10 tile (one-point halo; zeros outside the grid, the
+// A block owns a 64 x 12 output tile and a z-chunk.  Per plane k it stages the input
+// plane k+1 on the 68 x 16 tile (two-point halo) in a 3-plane LDS ring, computes the
+// first factor on the 66 x 14 tile (one-point halo; zeros outside the grid, the
 // Dirichlet ghosts of the intermediate vector) into a second 3-plane ring, then the
-// second factor at plane k-1 on the 64 x 8 core.  One thread per first-factor point
-// (660 of 704), two barriers per plane; global loads run one plane ahead.
+// second factor at plane k-1 on the 64 x 12 core.  One thread per first-factor point
+// (924 of 960), two barriers per plane; global loads run one plane ahead.
 // kFacResid / kFacInF select the first factor's input (y with the residual partials,
 // or f); kFacAdd / kFacDual the second factor's epilogue.
-constexpr int PX = 64, PY = 8;                  // output tile
+constexpr int PX = 64, PY = 12;                 // output tile
 constexpr int PEX = PX + 2, PEY = PY + 2;       // first-factor tile
 constexpr int PIX = PX + 4, PIY = PY + 4;       // input tile
-constexpr int PNT = 704;                        // 11 waves >= PEX * PEY = 660
+constexpr int PNT = 960;                        // 15 waves >= PEX * PEY = 924
 
 template <typename T, int KIND>
 __global__ __launch_bounds__(PNT) void zpair_kernel(GridDesc g, int nzc, int czlen, int xcd_slab,
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(PNT) void zpair_kernel(GridDesc g, int nzc, int czl
   const T diag0 = (T)6 * sh2 - (T)pd.z0_re, sim = (T)pd.z0_im;
   const double zzr = pd.zz_re, zzi = pd.zz_im;
 
-  // input-tile duty: entries tid and tid + PNT of the 68 x 12 tile
+  // input-tile duty: entries tid and tid + PNT of the 68 x 16 tile
   constexpr int NIN = PIX * PIY;
   bool in_ok[2];
   size_t in_off[2];
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(PNT) void zpair_kernel(GridDesc g, int nzc, int czl
     in_ok[h] = i < NIN && ix >= 0 && ix < g.nx && iy >= 0 && iy < g.ny;
     in_off[h] = in_ok[h] ? (size_t)ix + (size_t)g.nx * (size_t)iy : 0;
   }
-  // first-factor point of this thread (66 x 10 tile) and whether it is an output point
+  // first-factor point of this thread (66 x 14 tile) and whether it is an output point
   const bool tthr = tid < PEX * PEY;
   const int ex = tid % PEX, ey = tid / PEX;
   const int xe = x0 - 1 + ex, ye = y0 - 1 + ey;
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(PNT) void zpair_kernel(GridDesc g, int nzc, int czl
       }
       store_in(k + 1, r);
       __syncthreads();
-      // first factor at plane k on the 66 x 10 tile
+      // first factor at plane k on the 66 x 14 tile
       T2 tv = T2{(T)0, (T)0};
       if (tthr) {
         if (ine && k >= 0 && k < g.nz) {
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(PNT) void zpair_kernel(GridDesc g, int nzc, int czl
         tr[(k + 3) % 3][ey][ex] = tv;
       }
       __syncthreads();
-      // second factor at plane k-1 on the 64 x 8 core
+      // second factor at plane k-1 on the 64 x 12 core
       const int km = k - 1;
       if (core && km >= zb && km < ze) {
         const T2(*cp)[PEX] = tr[(km + 3) % 3];
