@@ -99,6 +99,59 @@ def unet_flops_per_voxel():
     return lvl1 + lvl2 + lvl3
 
 
+def small_configs_arm(args, ctx):
+    """The two small configurations, timed with direct launches and with each fixed-point
+    step replayed from a captured HIP graph:
+      constant c = 1, 32^3, 10 ppw, 8 poles (eps 0.5), q = 8, FP64, FGMRES(30) to 1e-8;
+      GRF medium, 96^3, 10 ppw, 12 poles, 4 Gaussian RHS, plain FP64 and mixed, to 1e-6.
+    Every solution's FP64 residual is recomputed by the oracle."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from oracle import operator as OO
+    from paper_1811_12378_amd import hfci
+
+    def run(wl, J, eps, prec, tol, graphs, reps=3):
+        g = hfci.Operator(ctx, torch.from_numpy(wl.c).cuda(), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
+        g.autotune(prec, 2)
+        c = hfci.Contour(g, J, 1.0, eps, args.q)
+        f = torch.from_numpy(np.stack(wl.rhs)).cuda()
+        o = hfci.default_opts(precision=prec, tol=tol, max_it=args.max_it, graphs=graphs)
+        hfci.solve(g, c, f, opts=o)  # warm-up: workspace, graph instantiation
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            u, st = hfci.solve(g, c, f, opts=o)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        oo = OO.Operator(wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
+        un = u.cpu().numpy()
+        rr = max(float(np.linalg.norm(oo.s * wl.rhs[k] - oo.apply(un[k])) / np.linalg.norm(oo.s * wl.rhs[k]))
+                 for k in range(len(wl.rhs)))
+        c.close()
+        g.close()
+        return {"time_s": round(best, 4), "its": st["its"], "relres_oracle": rr}
+
+    out = {}
+    w1 = W.config_constant_32()
+    out["constant_32_fp64_tol1e-8"] = {"direct": run(w1, 8, 0.5, 64, 1e-8, 0), "graphs": run(w1, 8, 0.5, 64, 1e-8, 1)}
+    w2 = W.config_grf_96()
+    out["grf_96_4rhs_fp64"] = {"direct": run(w2, 12, args.eps, 64, args.tol, 0),
+                               "graphs": run(w2, 12, args.eps, 64, args.tol, 1, reps=1)}
+    out["grf_96_4rhs_mixed"] = {"direct": run(w2, 12, args.eps, 32, args.tol, 0),
+                                "graphs": run(w2, 12, args.eps, 32, args.tol, 1, reps=1)}
+    for k, v in out.items():
+        v["graph_speedup"] = round(v["direct"]["time_s"] / v["graphs"]["time_s"], 3)
+        log("%s: direct %.3f s, graphs %.3f s, its %d, oracle relres %.2e"
+            % (k, v["direct"]["time_s"], v["graphs"]["time_s"], v["graphs"]["its"], v["graphs"]["relres_oracle"]))
+    out["grf_96_speedup_mixed_vs_fp64"] = round(
+        min(out["grf_96_4rhs_fp64"]["direct"]["time_s"], out["grf_96_4rhs_fp64"]["graphs"]["time_s"]) /
+        min(out["grf_96_4rhs_mixed"]["direct"]["time_s"], out["grf_96_4rhs_mixed"]["graphs"]["time_s"]), 3)
+    return out
+
+
 def uneven_arm(args, ctx, verbose):
     """Config-4 style uneven batch: independent GRF instances of sizes {48,64,96,128}^3 with
     ppw ~ U[6,12] and 8 poles each, solved to the same tolerance as one hfci_solve_batch call
@@ -225,6 +278,8 @@ def main():
     ap.add_argument("--uneven", type=int, default=16,
                     help="instances of the uneven-batch arm (64 = the full config; 0 skips it)")
     ap.add_argument("--uneven-only", action="store_true", help="run only the uneven-batch arm")
+    ap.add_argument("--no-small", action="store_true", help="skip the 32^3 / 96^3 configurations")
+    ap.add_argument("--small-only", action="store_true", help="run only the 32^3 / 96^3 configurations")
     ap.add_argument("--shape", type=int, nargs=5, metavar=("KERN", "TY", "PD", "CZ", "FUSE"),
                     help="pin the complex64 stencil launch shape instead of autotuning it")
     args = ap.parse_args()
@@ -243,6 +298,11 @@ def main():
     hfci.load_library()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     verbose = 0 if args.quiet else 1
+    if args.small_only:
+        ctx = hfci.Context(0)
+        r = small_configs_arm(args, ctx)
+        print(json.dumps({"metric": "small configurations", "small_configs": r}), flush=True)
+        return
     if args.uneven_only:
         ctx = hfci.Context(0)
         r = uneven_arm(args, ctx, verbose)
@@ -341,6 +401,10 @@ def main():
                                                                          gbs64))
         del u64
 
+    small = None
+    if not args.no_small:
+        small = small_configs_arm(args, ctx)
+
     uneven = None
     if args.uneven > 0:
         uneven = uneven_arm(args, ctx, verbose)
@@ -395,6 +459,7 @@ def main():
         "fp64": fp64,
         "learned": learned,
         "uneven_batch": uneven,
+        "small_configs": small,
     }
     print(json.dumps(out), flush=True)
 

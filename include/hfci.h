@@ -98,6 +98,13 @@ typedef struct {
   int harvest_cap;
   void* harvest_v;
   void* harvest_z;
+  int graphs;           /* fixed-point steps of the FCI: 1 = each step (its remaining
+                           factors, the next step's first factor, the stopping test and
+                           the read-back of the flags) replayed from a captured HIP graph,
+                           one graph launch per step, every launch sized for all systems
+                           (stopped ones exit at once); 0 = direct launches sized for the
+                           systems still iterating; -1 = graphs when the grid has at most
+                           2^16 points                                     default 0 */
 } hfci_solve_opts;
 
 /* Counters of one call. */

@@ -258,7 +258,8 @@ __global__ void fp_start_kernel(int nsys, int sys0, int nrhs, const double* __re
 }
 
 // Stream compaction of the active flags in one block: wave ballots give each lane its
-// rank within the wave, LDS carries the wave totals, chunks of NT go in order.
+// rank within the wave, LDS carries the wave totals, chunks of NT go in order; the
+// tail of the list is filled with -1.
 __global__ __launch_bounds__(NT) void build_list_kernel(const int* __restrict__ active, int nsys,
                                                         int* __restrict__ list) {
   __shared__ int wtot[NT / 64];
@@ -279,6 +280,8 @@ __global__ __launch_bounds__(NT) void build_list_kernel(const int* __restrict__ 
     base += tot;
     __syncthreads();
   }
+  // entries past the count are -1: launches sized for every system skip them
+  for (int s = base + threadIdx.x; s < nsys; s += NT) list[s] = -1;
 }
 
 // Stopping test of a batch of systems from different operators (see fp_check_kernel):

@@ -45,6 +45,21 @@ void* Workspace::get(const std::string& tag, size_t bytes) {
   return p;
 }
 
+hipGraphExec_t GraphCache::find(const std::string& key) const {
+  auto it = map_.find(key);
+  return it == map_.end() ? nullptr : it->second;
+}
+
+void GraphCache::put(const std::string& key, hipGraphExec_t exec) {
+  if (map_.size() >= 16) clear();
+  map_[key] = exec;
+}
+
+void GraphCache::clear() {
+  for (auto& kv : map_) (void)hipGraphExecDestroy(kv.second);
+  map_.clear();
+}
+
 void Workspace::release_all() {
   for (auto& kv : bufs_)
     if (kv.second.p) (void)hipFree(kv.second.p);
@@ -151,6 +166,7 @@ static void check_opts(const hfci_solve_opts* o) {
   HFCI_REQUIRE(o->harvest_cap >= 0 && (o->harvest_cap == 0 || (o->harvest_v && o->harvest_z)),
                "harvest_cap > 0 needs harvest_v and harvest_z");
   HFCI_REQUIRE(o->pole_batch >= 0, "pole_batch must be >= 0");
+  HFCI_REQUIRE(o->graphs >= -1 && o->graphs <= 1, "graphs must be -1, 0 or 1");
 }
 
 }  // namespace hfci
@@ -181,6 +197,7 @@ void hfci_default_opts(hfci_solve_opts* o) {
   o->harvest_cap = 0;
   o->harvest_v = nullptr;
   o->harvest_z = nullptr;
+  o->graphs = 0;
 }
 
 const char* hfci_last_error(void) { return g_err.c_str(); }
@@ -224,6 +241,7 @@ void hfci_ctx_destroy(hfci_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   c->prof.release();
+  c->graphs.clear();
   c->ws.release_all();
   if (c->pinned_int) (void)hipHostFree(c->pinned_int);
   if (c->pinned_dbl) (void)hipHostFree(c->pinned_dbl);

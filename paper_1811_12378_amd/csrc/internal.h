@@ -82,12 +82,26 @@ class Profiler {
   hipEvent_t open_ = nullptr;
 };
 
+// Instantiated HIP graphs of fixed-point steps, keyed by every value their launches
+// captured (pointers, sizes, coefficients' indices, shapes).  A few entries; cleared when full.
+class GraphCache {
+ public:
+  hipGraphExec_t find(const std::string& key) const;
+  void put(const std::string& key, hipGraphExec_t exec);
+  void clear();
+  ~GraphCache() { clear(); }
+
+ private:
+  std::map<std::string, hipGraphExec_t> map_;
+};
+
 struct Ctx {
   int device = 0;
   Profiler prof;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   Workspace ws;
+  GraphCache graphs;
   int* pinned_int = nullptr;     // host-pinned staging for small D2H reads
   double* pinned_dbl = nullptr;  // host-pinned staging (65536 doubles)
 };

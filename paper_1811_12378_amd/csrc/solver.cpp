@@ -48,7 +48,7 @@ void copy_active<double2>(hipStream_t st, double2* d, const double2* s, const in
 // forms the residual of the current y for the stopping test (Table 4's "reduced by 5").
 template <typename T2>
 void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sys0, int nsys,
-            int fixed_steps, double reduce, int max_steps, int* steps_out, FciStats& st) {
+            int fixed_steps, double reduce, int max_steps, int* steps_out, FciStats& st, bool graphs = false) {
   Ctx& ctx = *op.ctx;
   hipStream_t s = ctx.stream;
   const size_t n = op.n;
@@ -161,35 +161,24 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
     // ---- steps two and on: y <- L y + y1 ----
     // (a launch never writes its own input: a step made of a single launch goes through wA)
     const std::vector<Part> pl = plan(0, q, kFacResid, kFacAdd, fuse && q >= 3);
-    int nact = nsys;
-    for (int it = 1; it <= cap; ++it) {
-      if (fixed && it == cap) break;  // exact count: no final residual check needed
-      // first launch from y, with the ||f - (A - z) y||^2 partials of the current iterate
-      const bool single = pl.size() == 1;
+    const bool single = pl.size() == 1;
+    // first launch of a step from y, with the ||f - (A - z) y||^2 partials of the current
+    // iterate, the stopping test, and in adaptive mode the compacted list and the flags
+    auto head = [&](bool read_flags) {
       launch(pl[0].kind, pl[0].k, pl[0].width, y, wA, nullptr);
-      st.matvecs += nact;
       launch_fp_check(s, partial, nblk, nsys, sys0, nrhs, fnorm2, fixed_steps, reduce, max_steps, active, steps,
                       rnorm2);
       if (!fixed) {
-        // the list shrinks only in adaptive mode (a fixed count keeps every system; one
-        // stopped by a NaN residual then just carries its NaN on, reported by the caller)
         launch_build_list(s, active, nsys, list);
-        HFCI_HIP(hipMemcpyAsync(ctx.pinned_int, active, nsys * sizeof(int), hipMemcpyDeviceToHost, s));
-        HFCI_HIP(hipStreamSynchronize(s));
-        if (pr.on) pr.harvest();
-        nact = 0;
-        for (int k = 0; k < nsys; ++k) {
-          hact[k] = ctx.pinned_int[k] != 0;
-          nact += hact[k];
-        }
+        if (read_flags)
+          HFCI_HIP(hipMemcpyAsync(ctx.pinned_int, active, nsys * sizeof(int), hipMemcpyDeviceToHost, s));
       }
-      if (nact == 0) break;
-      a.count = nact;
-      st.matvecs += (long long)(q - 1) * nact;
-      st.fp_steps += nact;
+    };
+    // the rest of a step: middle factors ping-pong between wA and wB, the last adds y1
+    auto rest = [&]() {
       if (single) {
         copy_active<T2>(s, y, wA, active, nsys, n);
-        continue;
+        return;
       }
       T2* cur = wA;
       for (size_t i = 1; i < pl.size(); ++i) {
@@ -197,6 +186,90 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
         T2* dst = last ? y : ((cur == wA) ? wB : wA);
         launch(pl[i].kind, pl[i].k, pl[i].width, cur, dst, nullptr);
         cur = dst;
+      }
+    };
+    auto read_active = [&]() {
+      int na = 0;
+      for (int k = 0; k < nsys; ++k) {
+        hact[k] = ctx.pinned_int[k] != 0;
+        na += hact[k];
+      }
+      return na;
+    };
+    int nact = nsys;
+    if (!(graphs && !pr.on)) {
+      for (int it = 1; it <= cap; ++it) {
+        if (fixed && it == cap) break;  // exact count: no final residual check needed
+        head(!fixed);
+        st.matvecs += nact;
+        if (!fixed) {
+          HFCI_HIP(hipStreamSynchronize(s));
+          if (pr.on) pr.harvest();
+          nact = read_active();
+        }
+        if (nact == 0) break;
+        a.count = nact;
+        st.matvecs += (long long)(q - 1) * nact;
+        st.fp_steps += nact;
+        rest();
+      }
+    } else if (cap > 1 || !fixed) {
+      // Graph replay: launches cover every system (stopped ones find -1 in the list and
+      // exit), so one step's launch sequence is the same every step and is captured once:
+      // adaptive [rest of step, head of the next step, read-back], fixed [head, rest].
+      a.count = nsys;
+      std::string key;
+      auto put = [&](const void* p, size_t b) { key.append((const char*)p, b); };
+      const void* ptrs[] = {f, y, y1, wA, wB, partial, active, list, steps, rnorm2, fnorm2, c.d_coef, c.d_poles,
+                            kap, ctx.pinned_int};
+      put(ptrs, sizeof(ptrs));
+      const int ints[] = {(int)sizeof(T2), nsys, sys0, nrhs, q, c.cstride, fixed_steps, max_steps, nblk,
+                          fuse ? 1 : 0, op.g.nx, op.g.ny, op.g.nz};
+      put(ints, sizeof(ints));
+      put(&reduce, sizeof(reduce));
+      put(&op.g, sizeof(op.g));
+      hipGraphExec_t exec = ctx.graphs.find(key);
+      if (!exec) {
+        hipGraph_t graph = nullptr;
+        HFCI_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+          if (fixed) {
+            head(false);
+            rest();
+          } else {
+            rest();
+            head(true);
+          }
+        } catch (...) {
+          (void)hipStreamEndCapture(s, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          throw;
+        }
+        HFCI_HIP(hipStreamEndCapture(s, &graph));
+        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HFCI_HIP(e);
+        ctx.graphs.put(key, exec);
+      }
+      if (fixed) {
+        for (int it = 1; it < cap; ++it) {
+          HFCI_HIP(hipGraphLaunch(exec, s));
+          st.matvecs += (long long)q * nsys;
+          st.fp_steps += nsys;
+        }
+      } else {
+        head(true);
+        st.matvecs += nsys;
+        HFCI_HIP(hipStreamSynchronize(s));
+        nact = read_active();
+        for (int it = 1; it <= cap && nact > 0; ++it) {
+          st.matvecs += (long long)(q - 1) * nact;
+          st.fp_steps += nact;
+          HFCI_HIP(hipGraphLaunch(exec, s));
+          HFCI_HIP(hipStreamSynchronize(s));
+          st.matvecs += nact;
+          nact = read_active();
+        }
       }
     }
   }
@@ -326,7 +399,9 @@ void fci_body(const Op& op, const Contour& c, const hfci_solve_opts& o, int nrhs
   HFCI_HIP(hipMemcpyAsync(cc, stage, 2 * J * sizeof(double), hipMemcpyHostToDevice, s));
   for (int p0 = 0; p0 < J; p0 += pb) {
     const int np = std::min(pb, J - p0);
-    fp_run<T2>(op, c, nrhs, f, y, p0 * nrhs, np * nrhs, o.fp_steps, o.fp_reduce, o.fp_max_steps, nullptr, st);
+    const bool graphs = o.graphs == 1 || (o.graphs < 0 && op.n <= ((size_t)1 << 16));
+    fp_run<T2>(op, c, nrhs, f, y, p0 * nrhs, np * nrhs, o.fp_steps, o.fp_reduce, o.fp_max_steps, nullptr, st,
+               graphs);
     launch_combine<T2>(s, w, y, cc + 2 * p0, np, nrhs, n, p0 > 0);
   }
   // step 3: minimise ||f - d A w|| over d

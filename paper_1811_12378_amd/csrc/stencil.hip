@@ -82,6 +82,7 @@ __global__ __launch_bounds__(TX * TY) void zmarch_kernel(GridDesc g, int nzc, in
   // run of tiles whose y/z neighbours it shares in its own L2.
   const int gx = gridDim.x, gy = gridDim.y;
   const int s = epi.system(blockIdx.z / nzc);
+  if (s < 0) return;  // a stopped system past the end of the active list (uniform)
   int b = blockIdx.x + gx * (blockIdx.y + gy * (blockIdx.z % nzc));
   if (xcd_slab > 0) b = (b % 8) * xcd_slab + b / 8;
   const int bx = b % gx, by = (b / gx) % gy, zc = b / (gx * gy);
@@ -318,6 +319,7 @@ template <typename T, class Epi, int TY, int D>
 __global__ __launch_bounds__(TX * TY) void zlds_kernel(GridDesc g, int nzc, int czlen, int xcd_slab, Epi epi) {
   const int gx = gridDim.x, gy = gridDim.y;
   const int s = epi.system(blockIdx.z / nzc);
+  if (s < 0) return;  // a stopped system past the end of the active list (uniform)
   int b = blockIdx.x + gx * (blockIdx.y + gy * (blockIdx.z % nzc));
   if (xcd_slab > 0) b = (b % 8) * xcd_slab + b / 8;
   zlds_tile<T, Epi, TY, D>(g, nzc, czlen, epi, s, b % gx, (b / gx) % gy, b / (gx * gy), gx, gy);
@@ -351,6 +353,7 @@ __global__ __launch_bounds__(PNT) void zpair_kernel(GridDesc g, int nzc, int czl
   const int gx = (g.nx + PX - 1) / PX, gy = (g.ny + PY - 1) / PY;
   const int per_sys = gx * gy * nzc;
   const int s = a.list[blockIdx.x / per_sys];
+  if (s < 0) return;  // a stopped system past the end of the active list (uniform)
   int b = blockIdx.x % per_sys;
   if (xcd_slab > 0) b = (b % 8) * xcd_slab + b / 8;
   const int bx = b % gx, by = (b / gx) % gy, zc = b / (gx * gy);

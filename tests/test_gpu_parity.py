@@ -514,3 +514,26 @@ def test_batch_error_paths(ctx):
         hf.solve_batch([g, g2], [c1, c8], [f, f2])
     with pytest.raises(hf.HfciError):  # contour of another operator
         hf.solve_batch([g, g2], [c8, c1], [f, f2])
+
+
+# ---- fixed-point steps replayed from captured HIP graphs ----
+
+@pytest.mark.parametrize("prec,fused,fixed", [(64, 0, 0), (32, 0, 0), (32, 1, 0), (64, 1, 2), (32, 0, 3)])
+def test_graph_replay_equals_direct_launches(ctx, prec, fused, fixed):
+    # each FCI application replays the captured step graph many times, with the eager
+    # Arnoldi work of FGMRES between replays; every replay must give exactly what direct
+    # launches give, so the whole solve is bitwise identical
+    wl = W.config_grf_96(n=20, nrhs=2)
+    g = hf.Operator(ctx, dev(wl.c), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
+    g.set_tune(prec, 1, 8, 2, 0, fused)
+    c = hf.Contour(g, 8, 1.0, 0.25, 8)
+    f = dev(np.stack(wl.rhs))
+    res = {}
+    for gr in (0, 1, 1):  # the second graph run reuses the cached instantiation
+        o = hf.default_opts(precision=prec, tol=1e-8, max_it=120, graphs=gr, fp_steps=fixed)
+        u, st = hf.solve(g, c, f, opts=o)
+        res.setdefault(gr, []).append((host(u), st))
+    u0, st0 = res[0][0]
+    for u1, st1 in res[1]:
+        assert st1["its"] == st0["its"] and st1["matvecs"] == st0["matvecs"]
+        assert np.array_equal(u1, u0)
