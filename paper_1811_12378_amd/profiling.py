@@ -4,6 +4,9 @@
         Runs the batched fixed-point iteration for a fixed number of steps on the
         256^3 layered benchmark medium, so the middle-factor kernel runs
         (steps-1)*(q-2) + (q-3) launches over poles*nrhs systems, all active.
+    python -m paper_1811_12378_amd.profiling net [--n 256] [--reps 5]
+        Applies an (untrained) learned preconditioner to a random vector on the 256^3
+        layered medium: the BF16-MFMA convolution kernels of one forward pass per rep.
     python -m paper_1811_12378_amd.profiling copy [--mib 2048]
         A device-to-device copy of known size (read + write) for calibrating
         the FETCH_SIZE / WRITE_SIZE counters.
@@ -52,6 +55,30 @@ def _stage(a):
                       "stage_launches": st["launches"],
                       "stage_avg_ms": avg, "stage_alg_bytes_per_launch": st["alg_bytes"] / max(1, st["launches"]),
                       "stage_alg_gbs": gbs}), flush=True)
+
+
+def _net(a):
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, ROOT)
+    import workloads as W
+    from paper_1811_12378_amd import hfci
+
+    wl = W.config_layered_256(n=a.n, nrhs=1)
+    ctx = hfci.Context(0)
+    op = hfci.Operator(ctx, torch.from_numpy(wl.c).cuda(), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
+    net = hfci.Net(ctx, seed=1)
+    r = torch.randn((1, a.n, a.n, a.n), dtype=torch.complex128, device="cuda")
+    net.apply(op, r)
+    torch.cuda.synchronize()
+    import time
+    t0 = time.perf_counter()
+    for _ in range(a.reps):
+        net.apply(op, r)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.reps
+    print(json.dumps({"n": a.n, "reps": a.reps, "apply_ms": dt * 1e3}), flush=True)
 
 
 def _copy(a):
@@ -156,6 +183,9 @@ def main(argv=None):
     s.add_argument("--q", type=int, default=8)
     s.add_argument("--prec", type=int, default=32)
     s.add_argument("--tune", type=int, nargs=5, metavar=("KERN", "TY", "PD", "CZ", "FUSE"))
+    nn = sub.add_parser("net")
+    nn.add_argument("--n", type=int, default=256)
+    nn.add_argument("--reps", type=int, default=5)
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=2048)
     m = sub.add_parser("summarize")
@@ -173,7 +203,7 @@ def main(argv=None):
     m.add_argument("--alg-bytes", type=float, help="algorithmic bytes per launch of the counter runs")
     m.add_argument("--cmd", nargs=argparse.REMAINDER)
     a = ap.parse_args(argv)
-    {"stage": _stage, "copy": _copy, "summarize": _summarize}[a.cmd_name](a)
+    {"stage": _stage, "net": _net, "copy": _copy, "summarize": _summarize}[a.cmd_name](a)
 
 
 if __name__ == "__main__":
