@@ -130,6 +130,85 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(Dims d, View in, int cin,
   }
 }
 
+// 16 -> 16 channel layers (the full-resolution level of the U-Net) as a z-marching
+// implicit GEMM.  A block owns a 64 x 4 voxel tile of each plane of a z-chunk; the input
+// tile with its one-voxel halo (66 x 6 voxels x 16 channels) of planes z-1, z, z+1 sits
+// in a 3-plane LDS ring and the 27 x 16 x 16 weights in LDS, so every input voxel is read
+// from memory about once per chunk instead of once per tap.  Wave w computes row y0+w:
+// four 16-voxel blocks, one MFMA per (tap, block) with the weights as A (cout x cin) and
+// the input as B (cin x voxels), so the accumulator of lane l holds output channels
+// 4(l/16)..4(l/16)+3 of voxel l%16 and is stored as one 8-byte write.
+constexpr int ZCX = 64, ZCY = 4, ZLX = ZCX + 2, ZLY = ZCY + 2;
+
+__global__ __launch_bounds__(256) void zconv16_kernel(Dims d, View in, const uint16_t* __restrict__ w,
+                                                      const float* __restrict__ bias, int relu, View out, int zlen) {
+  __shared__ __align__(16) uint16_t ring[3][ZLY][ZLX][16];
+  __shared__ __align__(16) uint16_t ws[27][16][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gx = (d.x + ZCX - 1) / ZCX, gy = (d.y + ZCY - 1) / ZCY;
+  const int b = blockIdx.x;
+  const int bx = b % gx, by = (b / gx) % gy, zc = b / (gx * gy);
+  const int x0 = bx * ZCX, y0 = by * ZCY;
+  const int zb = zc * zlen, ze = min(d.z, zb + zlen);
+  for (int i = threadIdx.x; i < 27 * 16 * 16 / 8; i += 256)
+    reinterpret_cast<uint4*>(&ws[0][0][0])[i] = reinterpret_cast<const uint4*>(w)[i];
+  // plane zp of the input tile into ring slot zp mod 3 (zeros outside the grid)
+  auto load_plane = [&](int zp) {
+    uint4* dst = reinterpret_cast<uint4*>(&ring[(zp + 3) % 3][0][0][0]);
+    for (int c = threadIdx.x; c < ZLY * ZLX * 2; c += 256) {
+      const int vox = c >> 1, half = c & 1;
+      const int lx = vox % ZLX, ly = vox / ZLX;
+      const int xg = x0 - 1 + lx, yg = y0 - 1 + ly;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (zp >= 0 && zp < d.z && xg >= 0 && xg < d.x && yg >= 0 && yg < d.y)
+        v = *reinterpret_cast<const uint4*>(in.p + (((long)zp * d.y + yg) * d.x + xg) * in.cs + in.off + half * 8);
+      dst[c] = v;
+    }
+  };
+  if (zb >= ze) return;
+  load_plane(zb - 1);
+  load_plane(zb);
+  const int row = lane & 15, kq = lane >> 4;
+  const int yo = y0 + wave;
+  float bv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) bv[r] = bias ? bias[4 * kq + r] : 0.f;
+  for (int z = zb; z < ze; ++z) {
+    load_plane(z + 1);
+    __syncthreads();
+    f4v acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int tap = 0; tap < 27; ++tap) {
+      const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+      const s4v wa = *reinterpret_cast<const s4v*>(&ws[tap][row][4 * kq]);
+      const uint16_t(*pl)[ZLX][16] = ring[(z + dz + 3) % 3];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const s4v xb = *reinterpret_cast<const s4v*>(&pl[wave + 1 + dy][q * 16 + row + 1 + dx][4 * kq]);
+        acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa, xb, acc[q], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int xo = x0 + q * 16 + row;
+      if (xo < d.x && yo < d.y) {
+        uint16_t h[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float v = acc[q][r] + bv[r];
+          if (relu) v = fmaxf(v, 0.f);
+          h[r] = f2bf(v);
+        }
+        const uint2 pk = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+        *reinterpret_cast<uint2*>(out.p + (((long)z * d.y + yo) * d.x + xo) * out.cs + out.off + 4 * kq) = pk;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Weight gradient partials for one tap: P[chunk][tap][co][ci] = sum over the chunk's voxels
 // of dz[v][co] * x[v + off_tap][ci].  GEMM with k = voxel (16 voxels per MFMA step);
 // the 16 k-values of a lane are gathered (4 per lane) from channels-last memory.
@@ -414,6 +493,16 @@ bool conv_shape_ok(int cin, int cout) {
 
 void launch_conv_fwd(hipStream_t s, Dims d, View in, int cin, const uint16_t* w, const float* bias, bool relu,
                      View out, int cout) {
+  // the 16 -> 16 layers take the z-marching kernel when the views allow 16-byte vector
+  // access (channel stride and offset multiples of 8)
+  if (cin == 16 && cout == 16 && in.cs % 8 == 0 && in.off % 8 == 0 && out.cs % 4 == 0 && out.off % 4 == 0) {
+    const int gx = (d.x + ZCX - 1) / ZCX, gy = (d.y + ZCY - 1) / ZCY;
+    int zlen = 32;
+    while (zlen > 4 && (long)gx * gy * ((d.z + zlen - 1) / zlen) < 2048) zlen /= 2;
+    const unsigned nb = (unsigned)((long)gx * gy * ((d.z + zlen - 1) / zlen));
+    hipLaunchKernelGGL(zconv16_kernel, dim3(nb), dim3(256), 0, s, d, in, w, bias, relu ? 1 : 0, out, zlen);
+    return;
+  }
   if (cin % 32 == 0)
     fwd_dispatch<8>(s, d, in, cin, w, bias, relu ? 1 : 0, out, cout);
   else

@@ -95,7 +95,7 @@ def test_param_layout_roundtrip(ctx):
         assert np.array_equal(back[k], p[k]), k
 
 
-@pytest.mark.parametrize("shape", [(8, 8, 8), (8, 12, 16)])
+@pytest.mark.parametrize("shape", [(8, 8, 8), (8, 12, 16), (12, 20, 68)])
 def test_forward_parity(ctx, shape):
     net, p = setup_net(ctx)
     rng = np.random.default_rng(4)
