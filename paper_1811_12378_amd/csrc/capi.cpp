@@ -12,7 +12,7 @@ namespace hfci {
 
 namespace {
 thread_local std::string g_err;
-constexpr size_t kPinnedInts = 65536;
+constexpr size_t kPinnedInts = 2 * (size_t)kPinnedIntHalf;
 constexpr size_t kPinnedDbls = 65536;
 }  // namespace
 
@@ -223,8 +223,12 @@ hfci_status hfci_ctx_create(int device, void* stream, hfci_ctx** out) {
     }
     HFCI_HIP(hipHostMalloc((void**)&c->pinned_int, kPinnedInts * sizeof(int), hipHostMallocDefault));
     HFCI_HIP(hipHostMalloc((void**)&c->pinned_dbl, kPinnedDbls * sizeof(double), hipHostMallocDefault));
+    for (hipEvent_t& e : c->step_event) HFCI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   } catch (...) {
+    for (hipEvent_t e : c->step_event)
+      if (e) (void)hipEventDestroy(e);
     if (c->pinned_int) (void)hipHostFree(c->pinned_int);
+    if (c->pinned_dbl) (void)hipHostFree(c->pinned_dbl);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     throw;
@@ -242,6 +246,8 @@ void hfci_ctx_destroy(hfci_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   c->prof.release();
   c->graphs.clear();
+  for (hipEvent_t e : c->step_event)
+    if (e) (void)hipEventDestroy(e);
   c->ws.release_all();
   if (c->pinned_int) (void)hipHostFree(c->pinned_int);
   if (c->pinned_dbl) (void)hipHostFree(c->pinned_dbl);

@@ -53,6 +53,8 @@ class Workspace {
 
 // Layout of Ctx::pinned_dbl: [0, kPinnedFciOffset) FGMRES scalars, then FCI weights.
 constexpr size_t kPinnedFciOffset = 60000;
+// Ctx::pinned_int holds 2 * kPinnedIntHalf ints (the two flag buffers of pipelined steps).
+constexpr int kPinnedIntHalf = 32768;
 
 // Opt-in kernel timing on the context's stream: HIP events around selected launches,
 // with the algorithmic bytes each launch moves.  Harvested at the driver's sync points.
@@ -67,6 +69,12 @@ class Profiler {
   void begin(hipStream_t s);
   void end(hipStream_t s, int cls, double bytes);
   void harvest();  // call after the stream has been synchronised
+  // index of the next pending launch, and a correction of a pending launch's bytes (for
+  // launches whose work is known only after they were queued)
+  size_t mark() const { return pending_.size(); }
+  void set_bytes(size_t i, double bytes) {
+    if (i < pending_.size()) pending_[i].bytes = bytes;
+  }
   void reset();
   void release();
 
@@ -102,7 +110,8 @@ struct Ctx {
   bool own_stream = false;
   Workspace ws;
   GraphCache graphs;
-  int* pinned_int = nullptr;     // host-pinned staging for small D2H reads
+  hipEvent_t step_event[2] = {nullptr, nullptr};  // read-backs of the pipelined fixed-point steps
+  int* pinned_int = nullptr;     // host-pinned staging for small D2H reads (65536 ints)
   double* pinned_dbl = nullptr;  // host-pinned staging (65536 doubles)
 };
 

@@ -12,7 +12,8 @@ namespace hfci {
 // Launch shape of the z-marching stencil kernels: kern 0 keeps the in-plane neighbours
 // as cached global loads, kern 1 stages each plane through LDS; a 64 x ty thread tile,
 // HBM streams prefetched pd planes ahead, z-chunks of cz planes (0: from the grid size);
-// fuse 1 applies the fixed-point factors two per pass (64 x 12 tiles, z-chunks cz).
+// fuse 1 applies the fixed-point factors two per pass (64 x 12 tiles, z-chunks cz; loads
+// one plane ahead, two when pd is 3).
 struct KernelTune {
   int kern = 1, ty = 8, pd = 2, cz = 0, fuse = 0;
 };
@@ -77,6 +78,8 @@ struct Launch {
   static bool factor_pair(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a,
                           int kind);
   static int pair_blocks(const GridDesc& g);  // residual partials per system of a pair launch
+  // whether factor_pair runs on this grid (32-bit byte offsets: each vector under 4 GiB)
+  static bool pair_fits(const GridDesc& g);
   // partial sums for the step size d: conj(A w).f and |A w|^2, per rhs.
   static void dstep_partials(hipStream_t st, const GridDesc& g, const void* kappa, int nrhs,
                              const T2* w, const T2* f, double* partial);

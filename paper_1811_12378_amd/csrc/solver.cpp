@@ -65,7 +65,7 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
     T2* wA = (T2*)ctx.ws.get("fp_wA", (size_t)nsys * vbytes);
     T2* wB = (q >= 3) ? (T2*)ctx.ws.get("fp_wB", (size_t)nsys * vbytes) : nullptr;
     const KernelTune& tn = (sizeof(T2) == 8) ? op.g.tune32 : op.g.tune64;
-    const bool fuse = tn.fuse != 0;
+    const bool fuse = tn.fuse != 0 && Launch<T2>::pair_fits(op.g);
     // residual partials come from the first launch of a step: a pair launch when fusing
     const int nblk = (fuse && q >= 3) ? Launch<T2>::pair_blocks(op.g) : Launch<T2>::partial_blocks(op.g);
     double* partial = (double*)ctx.ws.get("fp_partial", (size_t)nsys * nblk * sizeof(double));
@@ -108,6 +108,14 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
       for (char u : rhs_used) nr += u;
       return (double)n * (vec_per_sys * e * na + ek + (reads_f ? e * nr : 0.0));
     };
+    // launches queued before the systems they run over are known: their bytes are set
+    // once the flags have been read back
+    struct Fixup {
+      size_t idx;
+      double vecs;
+      bool reads_f;
+    };
+    std::vector<Fixup>* fixups = nullptr;
     // One launch of `width` consecutive factors starting at coefficient k.  kind: kFacInF /
     // kFacResid on its first factor, kFacAdd / kFacDual on its last.
     auto launch = [&](int kind, int k, int width, const T2* win, T2* wout, T2* wout2) {
@@ -123,7 +131,10 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
       const bool ok = width == 2 ? Launch<T2>::factor_pair(s, op.g, kap, a, kind)
                                  : Launch<T2>::factor(s, op.g, kap, a, kind);
       HFCI_REQUIRE(ok, "internal: unsupported factor kind");
-      if (pr.on) pr.end(s, cls, launch_bytes(vecs, inf || resid));
+      if (pr.on) {
+        if (fixups) fixups->push_back(Fixup{pr.mark(), vecs, inf || resid});
+        pr.end(s, cls, launch_bytes(vecs, inf || resid));
+      }
     };
     struct Part {
       int k, width, kind;
@@ -197,7 +208,48 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
       return na;
     };
     int nact = nsys;
-    if (!(graphs && !pr.on)) {
+    if (!(graphs && !pr.on) && !fixed && nsys <= kPinnedIntHalf) {
+      // Adaptive, pipelined: the launches of step `it` (sized for the systems that were
+      // active after the previous test, an upper bound: the compacted list ends in -1s)
+      // and the next step's head are queued before the host waits for this step's flags,
+      // so the device never idles on the host's read-back.  Flags alternate between the
+      // two halves of the pinned buffer; an event marks each read-back.
+      hipEvent_t ev[2] = {ctx.step_event[0], ctx.step_event[1]};
+      int* flags[2] = {ctx.pinned_int, ctx.pinned_int + kPinnedIntHalf};
+      auto head_to = [&](int slot) {
+        launch(pl[0].kind, pl[0].k, pl[0].width, y, wA, nullptr);
+        launch_fp_check(s, partial, nblk, nsys, sys0, nrhs, fnorm2, fixed_steps, reduce, max_steps, active, steps,
+                        rnorm2);
+        launch_build_list(s, active, nsys, list);
+        HFCI_HIP(hipMemcpyAsync(flags[slot], active, nsys * sizeof(int), hipMemcpyDeviceToHost, s));
+        HFCI_HIP(hipEventRecord(ev[slot], s));
+      };
+      std::vector<Fixup> fx;
+      fixups = &fx;
+      head_to(0);
+      st.matvecs += nact;
+      int slot = 0;
+      for (int it = 1; it <= cap; ++it) {
+        // queue the rest of step `it` and the head of step it + 1, then read step it's flags
+        fx.clear();
+        rest();
+        head_to(slot ^ 1);
+        HFCI_HIP(hipEventSynchronize(ev[slot]));
+        int na = 0;
+        for (int k = 0; k < nsys; ++k) {
+          hact[k] = flags[slot][k] != 0;
+          na += hact[k];
+        }
+        for (const Fixup& x : fx) pr.set_bytes(x.idx, launch_bytes(x.vecs, x.reads_f));
+        st.matvecs += (long long)(q - 1) * na + na;
+        st.fp_steps += na;
+        nact = na;
+        if (nact == 0) break;  // the queued rest and head found an empty list: no work
+        a.count = nact;
+        slot ^= 1;
+      }
+      fixups = nullptr;
+    } else if (!(graphs && !pr.on)) {
       for (int it = 1; it <= cap; ++it) {
         if (fixed && it == cap) break;  // exact count: no final residual check needed
         head(!fixed);
@@ -331,7 +383,9 @@ KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, d
     for (int pd : {2, 3}) cands.push_back(KernelTune{1, 8, pd, cz, 0});
   }
   // two factors per pass (its own 64 x 12 tiles; per-factor time = half a launch)
-  for (int cz : {0, 16, 64}) cands.push_back(KernelTune{1, 8, 2, cz, 1});
+  if (Launch<T2>::pair_fits(op.g))
+    for (int cz : {0, 16, 64})
+      for (int pd : {2, 3}) cands.push_back(KernelTune{1, 8, pd, cz, 1});
   hipEvent_t e0, e1;
   HFCI_HIP(hipEventCreate(&e0));
   HFCI_HIP(hipEventCreate(&e1));

@@ -325,6 +325,51 @@ __global__ __launch_bounds__(TX * TY) void zlds_kernel(GridDesc g, int nzc, int 
   zlds_tile<T, Epi, TY, D>(g, nzc, czlen, epi, s, b % gx, (b / gx) % gy, b / (gx * gy), gx, gy);
 }
 
+// Raw buffer access (gfx9 buffer resource: base, no stride, the full 32-bit range, the
+// word-3 format bits of a raw buffer): the lane's byte offset in a VGPR, the uniform one
+// in an SGPR.  Callers keep every access inside the buffer.
+using BufRsrc = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ BufRsrc buf_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)0xffffffff, 0x00020000);
+}
+template <typename V>
+__device__ __forceinline__ V buf_load(const BufRsrc& r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float buf_load<float>(const BufRsrc& r, uint32_t voff, uint32_t soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(const BufRsrc& r, uint32_t voff, uint32_t soff) {
+  const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+  return __hiloint2double((int)v.y, (int)v.x);
+}
+template <>
+__device__ __forceinline__ float2 buf_load<float2>(const BufRsrc& r, uint32_t voff, uint32_t soff) {
+  const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+  return float2{__uint_as_float(v.x), __uint_as_float(v.y)};
+}
+template <>
+__device__ __forceinline__ double2 buf_load<double2>(const BufRsrc& r, uint32_t voff, uint32_t soff) {
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  return double2{__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z)};
+}
+template <typename V>
+__device__ __forceinline__ void buf_store(const BufRsrc& r, uint32_t voff, uint32_t soff, const V& x);
+template <>
+__device__ __forceinline__ void buf_store<float2>(const BufRsrc& r, uint32_t voff, uint32_t soff, const float2& x) {
+  const u32x2 v = {__float_as_uint(x.x), __float_as_uint(x.y)};
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+}
+template <>
+__device__ __forceinline__ void buf_store<double2>(const BufRsrc& r, uint32_t voff, uint32_t soff, const double2& x) {
+  const unsigned long long lx = (unsigned long long)__double_as_longlong(x.x);
+  const unsigned long long ly = (unsigned long long)__double_as_longlong(x.y);
+  const u32x4 v = {(unsigned)lx, (unsigned)(lx >> 32), (unsigned)ly, (unsigned)(ly >> 32)};
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, 0);
+}
+
 // Two consecutive factors of the fixed-point step in one pass (temporal blocking):
 //   t = a1 (A - z0) w + b1 w,   out = a2 (A - z0) t + b2 t  [+ y1].
 // A block owns a 64 x 12 output tile and a z-chunk.  Per plane k it stages the input
@@ -332,22 +377,51 @@ __global__ __launch_bounds__(TX * TY) void zlds_kernel(GridDesc g, int nzc, int 
 // first factor on the 66 x 14 tile (one-point halo; zeros outside the grid, the
 // Dirichlet ghosts of the intermediate vector) into a second 3-plane ring, then the
 // second factor at plane k-1 on the 64 x 12 core.  One thread per first-factor point
-// (924 of 960), two barriers per plane; global loads run one plane ahead.
+// (924 of 960), two barriers per plane; global loads run D planes ahead (D = 2 when the
+// shape's prefetch depth pd is 3, else 1).
 // kFacResid / kFacInF select the first factor's input (y with the residual partials,
 // or f); kFacAdd / kFacDual the second factor's epilogue.
+//
+// The loop body is written for the scalar unit as much as for the vector unit (one
+// scalar ALU serves the four SIMDs of a CU): the plane loop is unrolled three times and
+// the ring slots count from the chunk's first plane, so every slot is a compile-time
+// constant; the first factor and the residual are computed by every lane and masked
+// (no divergent branch), and lanes without a tile entry of their own write to LDS
+// padding; every global load is issued unconditionally from an in-bounds address and
+// masked where it is consumed, so no load sits under a divergent branch (which would
+// make the compiler's wait counts assume it might not have been issued, and wait for
+// every load in flight).
 constexpr int PX = 64, PY = 12;                 // output tile
 constexpr int PEX = PX + 2, PEY = PY + 2;       // first-factor tile
 constexpr int PIX = PX + 4, PIY = PY + 4;       // input tile
 constexpr int PNT = 960;                        // 15 waves >= PEX * PEY = 924
+constexpr int NIN = PIX * PIY;                  // 1088 input-tile entries
+constexpr int NINP = NIN + 64;                  // plus a write-only pad for lanes without an entry
 
+template <typename T2, typename T>
+struct PairRec {
+  T2 in[2];  // the thread's two entries of the 68 x 16 input tile
+  T kap;
+  T2 fv, y1;
+};
+
+// Two blocks per CU need eight waves per SIMD, i.e. at most 64 VGPRs: asked of the
+// complex64 kernels whose registers fit without spilling (not the residual or the y1
+// epilogue, which keep more per-point values in flight).
 template <typename T, int KIND>
-__global__ __launch_bounds__(PNT) void zpair_kernel(GridDesc g, int nzc, int czlen, int xcd_slab,
+constexpr int pair_waves_per_eu() {
+  return (sizeof(T) == 4 && (KIND & (kFacResid | kFacAdd)) == 0) ? 8 : 1;
+}
+
+template <typename T, int KIND, int D>
+__global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(pair_waves_per_eu<T, KIND>()))) void zpair_kernel(GridDesc g, int nzc, int czlen, int xcd_slab,
                                                     FactorArgs<typename V2<T>::t> a, const T* __restrict__ K) {
   using T2 = typename V2<T>::t;
   constexpr bool RESID = (KIND & kFacResid) != 0, ADD = (KIND & kFacAdd) != 0, DUAL = (KIND & kFacDual) != 0,
                  INF = (KIND & kFacInF) != 0;
-  __shared__ T2 inr[3][PIY][PIX];
-  __shared__ T2 tr[3][PEY][PEX];
+  static_assert(D == 1 || D == 2, "prefetch depth 1 or 2");
+  __shared__ T2 inr[3][NINP];  // input planes, [row][col] flattened as row * PIX + col
+  __shared__ T2 tr[3][PNT];    // first-factor planes, [row][col] as row * PEX + col (= tid)
   __shared__ double sh[PNT / 64];
   const int tid = threadIdx.x;
   const int gx = (g.nx + PX - 1) / PX, gy = (g.ny + PY - 1) / PY;
@@ -376,129 +450,161 @@ __global__ __launch_bounds__(PNT) void zpair_kernel(GridDesc g, int nzc, int czl
   const T diag0 = (T)6 * sh2 - (T)pd.z0_re, sim = (T)pd.z0_im;
   const double zzr = pd.zz_re, zzi = pd.zz_im;
 
-  // input-tile duty: entries tid and tid + PNT of the 68 x 16 tile
-  constexpr int NIN = PIX * PIY;
+  // Addresses: raw buffer accesses with a uniform plane offset (scalar) and a 32-bit
+  // per-lane byte offset (every vector is under 4 GiB when this kernel runs), so each
+  // lane keeps one 32-bit offset per stream and the plane advance is scalar work.
+  const uint32_t pb = (uint32_t)(plane * sizeof(T2)), pbk = (uint32_t)(plane * sizeof(T));
+  auto clampz = [&](int kp) { return (uint32_t)min(max(kp, 0), g.nz - 1); };
+  const BufRsrc rX = buf_rsrc(X), rK = buf_rsrc(K), rF = buf_rsrc(F), rY1 = buf_rsrc(Y1), rO = buf_rsrc(O),
+                rO2 = buf_rsrc(O2);
+  auto ld = [](const BufRsrc& r, uint32_t uoff, uint32_t loff) { return buf_load<T2>(r, loff, uoff); };
+
+  // input-tile duty: entries tid and tid + PNT of the 68 x 16 tile (the second only for
+  // the first 128 lanes; the others write it to the pad)
   bool in_ok[2];
-  size_t in_off[2];
+  uint32_t in_b[2];
+  int in_idx[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int i = tid + h * PNT;
     const int ix = x0 - 2 + i % PIX, iy = y0 - 2 + i / PIX;
     in_ok[h] = i < NIN && ix >= 0 && ix < g.nx && iy >= 0 && iy < g.ny;
-    in_off[h] = in_ok[h] ? (size_t)ix + (size_t)g.nx * (size_t)iy : 0;
+    in_b[h] = in_ok[h] ? (uint32_t)((ix + g.nx * iy) * sizeof(T2)) : 0u;
+    in_idx[h] = i < NIN ? i : NIN + (tid & 63);
   }
-  // first-factor point of this thread (66 x 14 tile) and whether it is an output point
+  // first-factor point of this thread (66 x 14 tile) and whether it is an output point;
+  // lanes past the tile read the tile's last row and are masked
   const bool tthr = tid < PEX * PEY;
-  const int ex = tid % PEX, ey = tid / PEX;
+  const int ex = tid % PEX, ey = min(tid / PEX, PEY - 1);
   const int xe = x0 - 1 + ex, ye = y0 - 1 + ey;
   const bool ine = tthr && xe >= 0 && xe < g.nx && ye >= 0 && ye < g.ny;
   const bool core = ine && ex >= 1 && ex <= PX && ey >= 1 && ey <= PY;
-  const size_t oe = ine ? (size_t)xe + (size_t)g.nx * (size_t)ye : 0;
+  const uint32_t oe = ine ? (uint32_t)(xe + g.nx * ye) : 0u;
+  const uint32_t oe_b = oe * (uint32_t)sizeof(T2), oe_k = oe * (uint32_t)sizeof(T);
+  // per-point vectors (f, y1) are read at the nearest output point of the tile, so the
+  // lanes of the halo ring fetch no cache line the core does not
+  const int xc = min(max(xe, x0), min(x0 + PX, g.nx) - 1), yc = min(max(ye, y0), min(y0 + PY, g.ny) - 1);
+  const uint32_t oc_b = (uint32_t)((xc + g.nx * yc) * sizeof(T2));
+  // second-factor neighbours in the first-factor ring, clamped into the tile for the
+  // lanes that are not output points (their result is not stored)
+  const int fx = min(max(ex, 1), PX), fy = min(max(ey, 1), PY);
+  const int fc = fy * PEX + fx;
+  // damping: dsc * max(dxy, dz)^2 = max(dsc dxy^2, dsc dz^2) (both depths >= 0)
   const int dxy = max(layer_depth(xe, g.nx, g.damp_cells), layer_depth(ye, g.ny, g.damp_cells));
+  const T dampxy = (T)(dxy * dxy) * dsc;
+  auto dampz = [&](int k) {
+    const int dz = layer_depth(k, g.nz, g.damp_cells);
+    return (T)(dz * dz) * dsc;
+  };
 
   auto load_in = [&](int kp, T2 (&r)[2]) {
+    const uint32_t off = pb * clampz(kp);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) r[h] = ld(rX, off, in_b[h]);
+  };
+  // ring slot of input plane kp is (kp - zb + 2) mod 3, of first-factor plane kp is
+  // (kp - zb + 1) mod 3: compile-time constants in the three-times unrolled loop
+  auto store_in = [&](int kp, int slot, const T2 (&r)[2]) {
     const bool kin = kp >= 0 && kp < g.nz;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      r[h] = T2{(T)0, (T)0};
-      if (kin && in_ok[h]) r[h] = X[in_off[h] + plane * (size_t)kp];
-    }
+    for (int h = 0; h < 2; ++h) inr[slot][in_idx[h]] = (kin && in_ok[h]) ? r[h] : T2{(T)0, (T)0};
   };
-  auto store_in = [&](int kp, const T2 (&r)[2]) {
-    T2(*dst)[PIX] = inr[(kp + 3) % 3];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = tid + h * PNT;
-      if (i < NIN) dst[i / PIX][i % PIX] = r[h];
-    }
+  // record of iteration k: input plane k+1, kappa at plane k (first factor), f at plane
+  // k (residual of the first factor), y1 at plane k-1 (second factor's epilogue); kappa,
+  // f and y1 are used only at points and planes where they were read in bounds
+  auto load_rec = [&](int k, PairRec<T2, T>& r) {
+    load_in(k + 1, r.in);
+    const uint32_t ck = clampz(k);
+    r.kap = buf_load<T>(rK, oe_k, pbk * ck);
+    if constexpr (RESID) r.fv = ld(rF, pb * ck, oc_b);
+    if constexpr (ADD) r.y1 = ld(rY1, pb * clampz(k - 1), oc_b);
   };
-  auto load_kap = [&](int kp) { return (ine && kp >= 0 && kp < g.nz) ? K[oe + plane * (size_t)kp] : (T)0; };
 
   double acc = 0.0;
   if (zb < ze) {
-    T2 r[2], rn[2];
-    load_in(zb - 2, r);
-    store_in(zb - 2, r);
-    load_in(zb - 1, r);
-    store_in(zb - 1, r);
-    load_in(zb, rn);
-    T kap_n = load_kap(zb - 1);
-    T2 fv_n = T2{(T)0, (T)0}, y1_n = T2{(T)0, (T)0};
+    {
+      T2 r[2];
+      load_in(zb - 2, r);
+      store_in(zb - 2, 0, r);
+      load_in(zb - 1, r);
+      store_in(zb - 1, 1, r);
+    }
+    // records are issued D iterations ahead into a queue of three register slots indexed
+    // by the iteration modulo 3: the queue rotates by renaming, so no register with a
+    // load in flight is ever copied and the loads stay in flight across the plane's
+    // barriers and stores
+    PairRec<T2, T> q[3];
+#pragma unroll
+    for (int d = 0; d < D; ++d) load_rec(zb - 1 + d, q[d]);
     T2 tprev = T2{(T)0, (T)0};
     T kprev = (T)0;
-    for (int k = zb - 1; k <= ze; ++k) {
-      // inputs of this iteration (issued one plane ahead), then the next plane's loads
-      r[0] = rn[0];
-      r[1] = rn[1];
-      const T kap = kap_n;
-      const T2 fv = fv_n, y1v = y1_n;
-      load_in(k + 2, rn);
-      kap_n = load_kap(k + 1);
-      if constexpr (RESID) {
-        if (core && k + 1 >= zb && k + 1 < ze) fv_n = F[oe + plane * (size_t)(k + 1)];
-      }
-      if constexpr (ADD) {
-        if (core && k >= zb && k < ze) y1_n = Y1[oe + plane * (size_t)k];
-      }
-      store_in(k + 1, r);
-      __syncthreads();
-      // first factor at plane k on the 66 x 14 tile
-      T2 tv = T2{(T)0, (T)0};
-      if (tthr) {
-        if (ine && k >= 0 && k < g.nz) {
-          const T2(*cp)[PIX] = inr[(k + 3) % 3];
-          const T2 cen = cp[ey + 1][ex + 1];
-          const T2 xm = cp[ey + 1][ex], xp = cp[ey + 1][ex + 2], ym = cp[ey][ex + 1], yp = cp[ey + 2][ex + 1];
-          const T2 zm = inr[(k + 2) % 3][ey + 1][ex + 1], zp = inr[(k + 4) % 3][ey + 1][ex + 1];
-          const int d = max(dxy, layer_depth(k, g.nz, g.damp_cells));
-          const T dre = diag0 - kap;
-          const T dim = -((T)(d * d) * dsc + sim);
-          const T nbr = ((zm.x + zp.x) + (xm.x + xp.x)) + (ym.x + yp.x);
-          const T nbi = ((zm.y + zp.y) + (xm.y + xp.y)) + (ym.y + yp.y);
-          T2 Sx;
-          Sx.x = dre * cen.x - dim * cen.y - sh2 * nbr;
-          Sx.y = dre * cen.y + dim * cen.x - sh2 * nbi;
-          tv.x = a1r * Sx.x - a1i * Sx.y + b1r * cen.x - b1i * cen.y;
-          tv.y = a1r * Sx.y + a1i * Sx.x + b1r * cen.y + b1i * cen.x;
-          if constexpr (RESID) {
-            if (core && k >= zb && k < ze) {
-              const double rr = (double)fv.x - (double)Sx.x + zzr * (double)cen.x - zzi * (double)cen.y;
-              const double ri = (double)fv.y - (double)Sx.y + zzr * (double)cen.y + zzi * (double)cen.x;
-              acc += rr * rr + ri * ri;
+    const int len = ze - zb + 2;  // iterations k = zb-1 .. ze
+    for (int r0 = 0; r0 < len; r0 += 3) {
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        if (r0 + u < len) {
+          const int k = zb - 1 + r0 + u;
+          load_rec(k + D, q[(u + D) % 3]);
+          const PairRec<T2, T>& rc = q[u];
+          // input slots: plane k-1 -> u, k -> u+1, k+1 -> u+2; first-factor slots:
+          // plane k-2 -> u+1, k-1 -> u+2, k -> u (all mod 3)
+          store_in(k + 1, (u + 2) % 3, rc.in);
+          __syncthreads();
+          // first factor at plane k on the 66 x 14 tile (every lane; masked)
+          {
+            const T2* cp = inr[(u + 1) % 3];
+            const int c0 = (ey + 1) * PIX + ex + 1;
+            const T2 cen = cp[c0];
+            const T2 xm = cp[c0 - 1], xp = cp[c0 + 1], ym = cp[c0 - PIX], yp = cp[c0 + PIX];
+            const T2 zm = inr[u][c0], zp = inr[(u + 2) % 3][c0];
+            const T dre = diag0 - rc.kap;
+            const T dim = -(max(dampxy, dampz(k)) + sim);
+            const T nbr = ((zm.x + zp.x) + (xm.x + xp.x)) + (ym.x + yp.x);
+            const T nbi = ((zm.y + zp.y) + (xm.y + xp.y)) + (ym.y + yp.y);
+            T2 Sx;
+            Sx.x = dre * cen.x - dim * cen.y - sh2 * nbr;
+            Sx.y = dre * cen.y + dim * cen.x - sh2 * nbi;
+            const bool live = ine && k >= 0 && k < g.nz;
+            T2 tv;
+            tv.x = live ? a1r * Sx.x - a1i * Sx.y + b1r * cen.x - b1i * cen.y : (T)0;
+            tv.y = live ? a1r * Sx.y + a1i * Sx.x + b1r * cen.y + b1i * cen.x : (T)0;
+            if constexpr (RESID) {
+              const double rr = (double)rc.fv.x - (double)Sx.x + zzr * (double)cen.x - zzi * (double)cen.y;
+              const double ri = (double)rc.fv.y - (double)Sx.y + zzr * (double)cen.y + zzi * (double)cen.x;
+              acc += (core && k >= zb && k < ze) ? rr * rr + ri * ri : 0.0;
             }
+            tr[u][tid] = tv;
+            // second factor at plane k-1 on the 64 x 12 core, after the barrier
+            __syncthreads();
+            const int km = k - 1;
+            const T2* cq = tr[(u + 2) % 3];
+            const T2 cen2 = tprev;
+            const T2 xm2 = cq[fc - 1], xp2 = cq[fc + 1], ym2 = cq[fc - PEX], yp2 = cq[fc + PEX];
+            const T2 zm2 = tr[(u + 1) % 3][fc], zp2 = tr[u][fc];
+            const T dre2 = diag0 - kprev;
+            const T dim2 = -(max(dampxy, dampz(km)) + sim);
+            const T nbr2 = ((zm2.x + zp2.x) + (xm2.x + xp2.x)) + (ym2.x + yp2.x);
+            const T nbi2 = ((zm2.y + zp2.y) + (xm2.y + xp2.y)) + (ym2.y + yp2.y);
+            T2 S2;
+            S2.x = dre2 * cen2.x - dim2 * cen2.y - sh2 * nbr2;
+            S2.y = dre2 * cen2.y + dim2 * cen2.x - sh2 * nbi2;
+            T2 o;
+            o.x = a2r * S2.x - a2i * S2.y + b2r * cen2.x - b2i * cen2.y;
+            o.y = a2r * S2.y + a2i * S2.x + b2r * cen2.y + b2i * cen2.x;
+            if constexpr (ADD) {
+              o.x += rc.y1.x;
+              o.y += rc.y1.y;
+            }
+            if (core && km >= zb && km < ze) {
+              const uint32_t po = pb * (uint32_t)km;
+              buf_store<T2>(rO, oe_b, po, o);
+              if constexpr (DUAL) buf_store<T2>(rO2, oe_b, po, o);
+            }
+            tprev = tv;
+            kprev = rc.kap;
           }
         }
-        tr[(k + 3) % 3][ey][ex] = tv;
       }
-      __syncthreads();
-      // second factor at plane k-1 on the 64 x 12 core
-      const int km = k - 1;
-      if (core && km >= zb && km < ze) {
-        const T2(*cp)[PEX] = tr[(km + 3) % 3];
-        const T2 cen = tprev;
-        const T2 xm = cp[ey][ex - 1], xp = cp[ey][ex + 1], ym = cp[ey - 1][ex], yp = cp[ey + 1][ex];
-        const T2 zm = tr[(km + 2) % 3][ey][ex], zp = tr[(km + 4) % 3][ey][ex];
-        const int d = max(dxy, layer_depth(km, g.nz, g.damp_cells));
-        const T dre = diag0 - kprev;
-        const T dim = -((T)(d * d) * dsc + sim);
-        const T nbr = ((zm.x + zp.x) + (xm.x + xp.x)) + (ym.x + yp.x);
-        const T nbi = ((zm.y + zp.y) + (xm.y + xp.y)) + (ym.y + yp.y);
-        T2 Sx;
-        Sx.x = dre * cen.x - dim * cen.y - sh2 * nbr;
-        Sx.y = dre * cen.y + dim * cen.x - sh2 * nbi;
-        T2 o;
-        o.x = a2r * Sx.x - a2i * Sx.y + b2r * cen.x - b2i * cen.y;
-        o.y = a2r * Sx.y + a2i * Sx.x + b2r * cen.y + b2i * cen.x;
-        if constexpr (ADD) {
-          o.x += y1v.x;
-          o.y += y1v.y;
-        }
-        const size_t po = oe + plane * (size_t)km;
-        O[po] = o;
-        if constexpr (DUAL) O2[po] = o;
-      }
-      tprev = tv;
-      kprev = kap;
     }
   }
   if constexpr (RESID) {
@@ -798,8 +904,13 @@ template <typename T, int KIND, typename T2>
 void run_pair(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a) {
   if (a.count <= 0) return;
   const PairShape p = pair_shape<T>(g);
-  hipLaunchKernelGGL((zpair_kernel<T, KIND>), dim3((unsigned)p.per_sys * (unsigned)a.count), dim3(PNT), 0, st, g,
-                     p.nzc, p.czlen, p.xcd_slab, a, (const T*)kappa);
+  const dim3 grid((unsigned)p.per_sys * (unsigned)a.count);
+  if (tune_of<T>(g).pd >= 3)
+    hipLaunchKernelGGL((zpair_kernel<T, KIND, 2>), grid, dim3(PNT), 0, st, g, p.nzc, p.czlen, p.xcd_slab, a,
+                       (const T*)kappa);
+  else
+    hipLaunchKernelGGL((zpair_kernel<T, KIND, 1>), grid, dim3(PNT), 0, st, g, p.nzc, p.czlen, p.xcd_slab, a,
+                       (const T*)kappa);
 }
 
 }  // namespace
@@ -853,9 +964,15 @@ int Launch<T2>::pair_blocks(const GridDesc& g) {
 }
 
 template <typename T2>
+bool Launch<T2>::pair_fits(const GridDesc& g) {
+  return (size_t)g.nx * g.ny * g.nz * sizeof(T2) < ((size_t)1 << 32);
+}
+
+template <typename T2>
 bool Launch<T2>::factor_pair(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a,
                              int kind) {
   using T = typename Scal<T2>::t;
+  if (!pair_fits(g)) return false;
   switch (kind) {
     case 0: run_pair<T, 0>(st, g, kappa, a); break;
     case kFacResid: run_pair<T, kFacResid>(st, g, kappa, a); break;
