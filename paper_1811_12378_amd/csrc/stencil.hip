@@ -373,17 +373,19 @@ __device__ __forceinline__ void buf_store<double2>(const BufRsrc& r, uint32_t vo
 // Two consecutive factors of the fixed-point step in one pass (temporal blocking):
 //   t = a1 (A - z0) w + b1 w,   out = a2 (A - z0) t + b2 t  [+ y1].
 // A block owns a 64 x 12 output tile and a z-chunk.  Per plane k it stages the input
-// plane k+1 on the 68 x 16 tile (two-point halo) in a 3-plane LDS ring, computes the
-// first factor on the 66 x 14 tile (one-point halo; zeros outside the grid, the
-// Dirichlet ghosts of the intermediate vector) into a second 3-plane ring, then the
-// second factor at plane k-1 on the 64 x 12 core.  One thread per first-factor point
-// (924 of 960), two barriers per plane; global loads run D planes ahead (D = 2 when the
-// shape's prefetch depth pd is 3, else 1).
+// plane k+1 on the 68 x 16 tile (two-point halo) in a 4-plane LDS ring and, after one
+// barrier, computes the second factor at plane k-2 on the 64 x 12 core from the
+// first-factor ring, then the first factor at plane k on the 66 x 14 tile (one-point
+// halo; zeros outside the grid, the Dirichlet ghosts of the intermediate vector) into
+// that 4-plane ring.  Four slots per ring let one barrier per plane order every write
+// against every read of the same slot.  One thread per first-factor point (924 of
+// 960); global loads run D planes ahead (D = 2 when the shape's prefetch depth pd is
+// 3, else 1).
 // kFacResid / kFacInF select the first factor's input (y with the residual partials,
 // or f); kFacAdd / kFacDual the second factor's epilogue.
 //
 // The loop body is written for the scalar unit as much as for the vector unit (one
-// scalar ALU serves the four SIMDs of a CU): the plane loop is unrolled three times and
+// scalar ALU serves the four SIMDs of a CU): the plane loop is unrolled four times and
 // the ring slots count from the chunk's first plane, so every slot is a compile-time
 // constant; the first factor and the residual are computed by every lane and masked
 // (no divergent branch), and lanes without a tile entry of their own write to LDS
@@ -420,8 +422,8 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(pair_waves_
   constexpr bool RESID = (KIND & kFacResid) != 0, ADD = (KIND & kFacAdd) != 0, DUAL = (KIND & kFacDual) != 0,
                  INF = (KIND & kFacInF) != 0;
   static_assert(D == 1 || D == 2, "prefetch depth 1 or 2");
-  __shared__ T2 inr[3][NINP];  // input planes, [row][col] flattened as row * PIX + col
-  __shared__ T2 tr[3][PNT];    // first-factor planes, [row][col] as row * PEX + col (= tid)
+  __shared__ T2 inr[4][NINP];  // input planes, [row][col] flattened as row * PIX + col
+  __shared__ T2 tr[4][PNT];    // first-factor planes, [row][col] as row * PEX + col (= tid)
   __shared__ double sh[PNT / 64];
   const int tid = threadIdx.x;
   const int gx = (g.nx + PX - 1) / PX, gy = (g.ny + PY - 1) / PY;
@@ -502,22 +504,22 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(pair_waves_
 #pragma unroll
     for (int h = 0; h < 2; ++h) r[h] = ld(rX, off, in_b[h]);
   };
-  // ring slot of input plane kp is (kp - zb + 2) mod 3, of first-factor plane kp is
-  // (kp - zb + 1) mod 3: compile-time constants in the three-times unrolled loop
+  // ring slot of input plane kp is (kp - zb + 2) mod 4, of first-factor plane kp is
+  // (kp - zb + 1) mod 4: compile-time constants in the four-times unrolled loop
   auto store_in = [&](int kp, int slot, const T2 (&r)[2]) {
     const bool kin = kp >= 0 && kp < g.nz;
 #pragma unroll
     for (int h = 0; h < 2; ++h) inr[slot][in_idx[h]] = (kin && in_ok[h]) ? r[h] : T2{(T)0, (T)0};
   };
   // record of iteration k: input plane k+1, kappa at plane k (first factor), f at plane
-  // k (residual of the first factor), y1 at plane k-1 (second factor's epilogue); kappa,
+  // k (residual of the first factor), y1 at plane k-2 (second factor's epilogue); kappa,
   // f and y1 are used only at points and planes where they were read in bounds
   auto load_rec = [&](int k, PairRec<T2, T>& r) {
     load_in(k + 1, r.in);
     const uint32_t ck = clampz(k);
     r.kap = buf_load<T>(rK, oe_k, pbk * ck);
     if constexpr (RESID) r.fv = ld(rF, pb * ck, oc_b);
-    if constexpr (ADD) r.y1 = ld(rY1, pb * clampz(k - 1), oc_b);
+    if constexpr (ADD) r.y1 = ld(rY1, pb * clampz(k - 2), oc_b);
   };
 
   double acc = 0.0;
@@ -529,59 +531,40 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(pair_waves_
       load_in(zb - 1, r);
       store_in(zb - 1, 1, r);
     }
-    // records are issued D iterations ahead into a queue of three register slots indexed
-    // by the iteration modulo 3: the queue rotates by renaming, so no register with a
+    // records are issued D iterations ahead into a queue of four register slots indexed
+    // by the iteration modulo 4: the queue rotates by renaming, so no register with a
     // load in flight is ever copied and the loads stay in flight across the plane's
-    // barriers and stores
-    PairRec<T2, T> q[3];
+    // barrier and stores
+    PairRec<T2, T> q[4];
 #pragma unroll
     for (int d = 0; d < D; ++d) load_rec(zb - 1 + d, q[d]);
-    T2 tprev = T2{(T)0, (T)0};
-    T kprev = (T)0;
-    const int len = ze - zb + 2;  // iterations k = zb-1 .. ze
-    for (int r0 = 0; r0 < len; r0 += 3) {
+    T k1 = (T)0, k2 = (T)0;  // kappa at planes k-1, k-2 (kept when two records are in flight)
+    const int len = ze - zb + 3;  // iterations k = zb-1 .. ze+1
+    for (int r0 = 0; r0 < len; r0 += 4) {
 #pragma unroll
-      for (int u = 0; u < 3; ++u) {
+      for (int u = 0; u < 4; ++u) {
         if (r0 + u < len) {
           const int k = zb - 1 + r0 + u;
-          load_rec(k + D, q[(u + D) % 3]);
+          load_rec(k + D, q[(u + D) % 4]);
           const PairRec<T2, T>& rc = q[u];
           // input slots: plane k-1 -> u, k -> u+1, k+1 -> u+2; first-factor slots:
-          // plane k-2 -> u+1, k-1 -> u+2, k -> u (all mod 3)
-          store_in(k + 1, (u + 2) % 3, rc.in);
+          // plane k-3 -> u+1, k-2 -> u+2, k-1 -> u+3, k -> u (all mod 4).  The one barrier
+          // publishes input plane k+1 and first-factor plane k-1.  The input slot u+2
+          // written before it is not one the previous iteration's first factor reads
+          // (u-1, u, u+1), and the first-factor slot u written after it is not one this
+          // iteration's second factor reads (u+1, u+2, u+3): a barrier separates every
+          // write from every read of the same slot.
+          store_in(k + 1, (u + 2) % 4, rc.in);
           __syncthreads();
-          // first factor at plane k on the 66 x 14 tile (every lane; masked)
+          // second factor at plane k-2 on the 64 x 12 core
           {
-            const T2* cp = inr[(u + 1) % 3];
-            const int c0 = (ey + 1) * PIX + ex + 1;
-            const T2 cen = cp[c0];
-            const T2 xm = cp[c0 - 1], xp = cp[c0 + 1], ym = cp[c0 - PIX], yp = cp[c0 + PIX];
-            const T2 zm = inr[u][c0], zp = inr[(u + 2) % 3][c0];
-            const T dre = diag0 - rc.kap;
-            const T dim = -(max(dampxy, dampz(k)) + sim);
-            const T nbr = ((zm.x + zp.x) + (xm.x + xp.x)) + (ym.x + yp.x);
-            const T nbi = ((zm.y + zp.y) + (xm.y + xp.y)) + (ym.y + yp.y);
-            T2 Sx;
-            Sx.x = dre * cen.x - dim * cen.y - sh2 * nbr;
-            Sx.y = dre * cen.y + dim * cen.x - sh2 * nbi;
-            const bool live = ine && k >= 0 && k < g.nz;
-            T2 tv;
-            tv.x = live ? a1r * Sx.x - a1i * Sx.y + b1r * cen.x - b1i * cen.y : (T)0;
-            tv.y = live ? a1r * Sx.y + a1i * Sx.x + b1r * cen.y + b1i * cen.x : (T)0;
-            if constexpr (RESID) {
-              const double rr = (double)rc.fv.x - (double)Sx.x + zzr * (double)cen.x - zzi * (double)cen.y;
-              const double ri = (double)rc.fv.y - (double)Sx.y + zzr * (double)cen.y + zzi * (double)cen.x;
-              acc += (core && k >= zb && k < ze) ? rr * rr + ri * ri : 0.0;
-            }
-            tr[u][tid] = tv;
-            // second factor at plane k-1 on the 64 x 12 core, after the barrier
-            __syncthreads();
-            const int km = k - 1;
-            const T2* cq = tr[(u + 2) % 3];
-            const T2 cen2 = tprev;
+            const int km = k - 2;
+            const T2* cq = tr[(u + 2) % 4];
+            const T2 cen2 = cq[fc];
             const T2 xm2 = cq[fc - 1], xp2 = cq[fc + 1], ym2 = cq[fc - PEX], yp2 = cq[fc + PEX];
-            const T2 zm2 = tr[(u + 1) % 3][fc], zp2 = tr[u][fc];
-            const T dre2 = diag0 - kprev;
+            const T2 zm2 = tr[(u + 1) % 4][fc], zp2 = tr[(u + 3) % 4][fc];
+            // kappa at plane k-2: with one record in flight its slot is still intact
+            const T dre2 = diag0 - (D == 1 ? q[(u + 2) % 4].kap : k2);
             const T dim2 = -(max(dampxy, dampz(km)) + sim);
             const T nbr2 = ((zm2.x + zp2.x) + (xm2.x + xp2.x)) + (ym2.x + yp2.x);
             const T nbi2 = ((zm2.y + zp2.y) + (xm2.y + xp2.y)) + (ym2.y + yp2.y);
@@ -600,8 +583,33 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(pair_waves_
               buf_store<T2>(rO, oe_b, po, o);
               if constexpr (DUAL) buf_store<T2>(rO2, oe_b, po, o);
             }
-            tprev = tv;
-            kprev = rc.kap;
+          }
+          // first factor at plane k on the 66 x 14 tile (every lane; masked)
+          {
+            const T2* cp = inr[(u + 1) % 4];
+            const int c0 = (ey + 1) * PIX + ex + 1;
+            const T2 cen = cp[c0];
+            const T2 xm = cp[c0 - 1], xp = cp[c0 + 1], ym = cp[c0 - PIX], yp = cp[c0 + PIX];
+            const T2 zm = inr[u][c0], zp = inr[(u + 2) % 4][c0];
+            const T dre = diag0 - rc.kap;
+            const T dim = -(max(dampxy, dampz(k)) + sim);
+            const T nbr = ((zm.x + zp.x) + (xm.x + xp.x)) + (ym.x + yp.x);
+            const T nbi = ((zm.y + zp.y) + (xm.y + xp.y)) + (ym.y + yp.y);
+            T2 Sx;
+            Sx.x = dre * cen.x - dim * cen.y - sh2 * nbr;
+            Sx.y = dre * cen.y + dim * cen.x - sh2 * nbi;
+            const bool live = ine && k >= 0 && k < g.nz;
+            T2 tv;
+            tv.x = live ? a1r * Sx.x - a1i * Sx.y + b1r * cen.x - b1i * cen.y : (T)0;
+            tv.y = live ? a1r * Sx.y + a1i * Sx.x + b1r * cen.y + b1i * cen.x : (T)0;
+            if constexpr (RESID) {
+              const double rr = (double)rc.fv.x - (double)Sx.x + zzr * (double)cen.x - zzi * (double)cen.y;
+              const double ri = (double)rc.fv.y - (double)Sx.y + zzr * (double)cen.y + zzi * (double)cen.x;
+              acc += (core && k >= zb && k < ze) ? rr * rr + ri * ri : 0.0;
+            }
+            tr[u][tid] = tv;
+            k2 = k1;
+            k1 = rc.kap;
           }
         }
       }
