@@ -415,16 +415,8 @@ void solve_multi(MultiFp<T2>* M, const std::vector<const Op*>& ops, const hfci_s
         const size_t n = op.n;
         double2* w = V[i] + (size_t)(j + 1) * n;
         double* hb = hdev[i];
-        const int nbb = blas_blocks(n);
         Launch<double2>::apply(s, op.g, op.kappa64, 0.0, 0.0, 1, Z[i] + (size_t)j * n, w);
-        launch_multidot(s, V[i], j + 1, n, n, w, part);
-        launch_reduce(s, part, nbb, 2 * (j + 1), hb);
-        launch_multiaxpy(s, w, V[i], j + 1, n, n, hb, -1.0);
-        launch_multidot(s, V[i], j + 1, n, n, w, part);
-        launch_reduce(s, part, nbb, 2 * (j + 1), hb + 2 * (m + 1));
-        launch_multiaxpy(s, w, V[i], j + 1, n, n, hb + 2 * (m + 1), -1.0);
-        launch_norm2_partial(s, w, false, n, part);
-        launch_reduce(s, part, nbb, 1, hb + 4 * (m + 1));
+        launch_cgs2(s, V[i], j + 1, n, n, w, part, hb, hb + 2 * (m + 1), hb + 4 * (m + 1));
         launch_scale_inv(s, w, w, n, hb + 4 * (m + 1));
         HFCI_HIP(hipMemcpyAsync(hhost(i), hb, (4 * (m + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
         ++mv_i[i];

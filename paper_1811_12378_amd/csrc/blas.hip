@@ -98,6 +98,89 @@ __global__ __launch_bounds__(NT) void multiaxpy_kernel(double2* __restrict__ w, 
   }
 }
 
+// The second and third passes of CGS2 over the basis V[0..nv) (nv <= 4 * NQ):
+//   w <- w + sign * sum_i h_i V_i, then partial sums of conj(V_i) . w      (DOT)
+//   w <- w + sign * sum_i h_i V_i, then partial sums of |w|^2               (NORM)
+// Each point belongs to a quad of four lanes; lane q holds the vectors i = 4j + q
+// (j < NQ) of that point in registers, the quad sums the update through lane shuffles,
+// so V is read once from HBM for both the update and the dot products.  Lanes past nv
+// read a valid vector (V_{nv-1}) with a zero coefficient.  Partial row k (= 2i + c for
+// DOT, 0 for NORM) of block b is at partial[k * gridDim.x + b], as for multidot.
+template <int NQ, bool DOT>
+__global__ __launch_bounds__(NT) void axpy_reduce_kernel(double2* __restrict__ w, const double2* __restrict__ V,
+                                                         int nv, size_t n, size_t vstride,
+                                                         const double* __restrict__ h, double sign,
+                                                         double* __restrict__ partial) {
+  constexpr int NA = DOT ? 2 * NQ : 1;
+  __shared__ double hs[2 * 4 * NQ];
+  __shared__ double sh[(NT / 64) * 4 * NA];
+  for (int t = threadIdx.x; t < 2 * 4 * NQ; t += NT) hs[t] = t < 2 * nv ? sign * h[t] : 0.0;
+  __syncthreads();
+  const int q = threadIdx.x & 3;
+  double acc[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+  const size_t pstride = (size_t)gridDim.x * (NT / 4);
+  for (size_t p = (size_t)blockIdx.x * (NT / 4) + threadIdx.x / 4; p < n; p += pstride) {
+    double2 v[NQ];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      const int i = min(4 * j + q, nv - 1);
+      v[j] = V[(size_t)i * vstride + p];
+    }
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      const double hr = hs[2 * (4 * j + q)], hi = hs[2 * (4 * j + q) + 1];
+      sx += hr * v[j].x - hi * v[j].y;
+      sy += hr * v[j].y + hi * v[j].x;
+    }
+    sx += __shfl_xor(sx, 1, 64);
+    sy += __shfl_xor(sy, 1, 64);
+    sx += __shfl_xor(sx, 2, 64);
+    sy += __shfl_xor(sy, 2, 64);
+    const double2 wv = w[p];
+    const double2 wn = make_double2(wv.x + sx, wv.y + sy);
+    if (q == 0) w[p] = wn;
+    if constexpr (DOT) {
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) {
+        acc[2 * j] += v[j].x * wn.x + v[j].y * wn.y;      // Re conj(v) w
+        acc[2 * j + 1] += v[j].x * wn.y - v[j].y * wn.x;  // Im conj(v) w
+      }
+    } else {
+      if (q == 0) acc[0] += wn.x * wn.x + wn.y * wn.y;
+    }
+  }
+  // lanes q, q + 4, ..., q + 60 of a wave hold the same vectors: sum them into lane q
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    double x = acc[k];
+#pragma unroll
+    for (int o = 32; o >= 4; o >>= 1) x += __shfl_down(x, o, 64);
+    if (lane < 4) sh[(wid * 4 + lane) * NA + k] = x;
+  }
+  __syncthreads();
+  if (DOT) {
+    // thread t < 4 * NA: lane group q = t / NA, entry k = t % NA -> vector 4 (k / 2) + q
+    const int t = threadIdx.x;
+    if (t < 4 * NA) {
+      const int qq = t / NA, k = t % NA;
+      double x = 0.0;
+#pragma unroll
+      for (int w4 = 0; w4 < NT / 64; ++w4) x += sh[(w4 * 4 + qq) * NA + k];
+      const int i = 4 * (k / 2) + qq;
+      if (i < nv) partial[(size_t)(2 * i + (k & 1)) * gridDim.x + blockIdx.x] = x;
+    }
+  } else if (threadIdx.x == 0) {
+    double x = 0.0;
+#pragma unroll
+    for (int w4 = 0; w4 < NT / 64; ++w4) x += sh[(w4 * 4) * NA];
+    partial[blockIdx.x] = x;
+  }
+}
+
 __global__ __launch_bounds__(NT) void diffnorm2_kernel(const double2* __restrict__ a, const double2* __restrict__ b,
                                                        size_t n, double* __restrict__ partial) {
   __shared__ double sh[4];
@@ -373,6 +456,41 @@ void launch_multiaxpy(hipStream_t st, double2* w, const double2* V, int nv, size
     return;
   }
   hipLaunchKernelGGL(multiaxpy_kernel, dim3(blas_blocks(n)), dim3(NT), 0, st, w, V, nv, n, vstride, h, sign);
+}
+
+template <bool DOT>
+static bool launch_axpy_reduce(hipStream_t st, double2* w, const double2* V, int nv, size_t n, size_t vstride,
+                               const double* h, double sign, double* partial) {
+  if (nv <= 0 || nv > 32) return false;
+  const dim3 grid(blas_blocks(n)), block(NT);
+  if (nv <= 4)
+    hipLaunchKernelGGL((axpy_reduce_kernel<1, DOT>), grid, block, 0, st, w, V, nv, n, vstride, h, sign, partial);
+  else if (nv <= 8)
+    hipLaunchKernelGGL((axpy_reduce_kernel<2, DOT>), grid, block, 0, st, w, V, nv, n, vstride, h, sign, partial);
+  else if (nv <= 16)
+    hipLaunchKernelGGL((axpy_reduce_kernel<4, DOT>), grid, block, 0, st, w, V, nv, n, vstride, h, sign, partial);
+  else
+    hipLaunchKernelGGL((axpy_reduce_kernel<8, DOT>), grid, block, 0, st, w, V, nv, n, vstride, h, sign, partial);
+  return true;
+}
+
+void launch_cgs2(hipStream_t st, const double2* V, int nv, size_t n, size_t vstride, double2* w, double* partial,
+                 double* h1, double* h2, double* nrm2) {
+  const int nb = blas_blocks(n);
+  launch_multidot(st, V, nv, n, vstride, w, partial);
+  launch_reduce(st, partial, nb, 2 * nv, h1);
+  if (launch_axpy_reduce<true>(st, w, V, nv, n, vstride, h1, -1.0, partial)) {
+    launch_reduce(st, partial, nb, 2 * nv, h2);
+    launch_axpy_reduce<false>(st, w, V, nv, n, vstride, h2, -1.0, partial);
+    launch_reduce(st, partial, nb, 1, nrm2);
+    return;
+  }
+  launch_multiaxpy(st, w, V, nv, n, vstride, h1, -1.0);
+  launch_multidot(st, V, nv, n, vstride, w, partial);
+  launch_reduce(st, partial, nb, 2 * nv, h2);
+  launch_multiaxpy(st, w, V, nv, n, vstride, h2, -1.0);
+  launch_norm2_partial(st, w, false, n, partial);
+  launch_reduce(st, partial, nb, 1, nrm2);
 }
 
 void launch_norm2_partial(hipStream_t st, const void* x, bool f32, size_t n, double* partial) {

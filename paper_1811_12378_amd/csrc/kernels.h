@@ -135,6 +135,12 @@ void launch_multidot(hipStream_t st, const double2* V, int nv, size_t n, size_t 
                      const double2* w, double* partial);     // partial[(2i+c)][blk]
 void launch_multiaxpy(hipStream_t st, double2* w, const double2* V, int nv, size_t n,
                       size_t vstride, const double* h, double sign);  // w += sign * sum h_i V_i
+// Classical Gram-Schmidt twice of w against V[0..nv), then |w|^2:
+//   h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, nrm2 = |w|^2  (device h1, h2: 2 nv
+//   doubles each, nrm2: 1; partial: 2 nv * blas_blocks(n) doubles of scratch).
+// For nv <= 32 the update and the next reduction share one pass over V.
+void launch_cgs2(hipStream_t st, const double2* V, int nv, size_t n, size_t vstride, double2* w, double* partial,
+                 double* h1, double* h2, double* nrm2);
 void launch_norm2_partial(hipStream_t st, const void* x, bool f32, size_t n, double* partial);
 void launch_scale_inv(hipStream_t st, double2* v, const double2* w, size_t n, const double* nrm2);
 void launch_fill_zero(hipStream_t st, void* p, size_t bytes);

@@ -743,14 +743,7 @@ hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& 
         const double2* Vr = V + r * n;
         double* hb = hdev + (size_t)r * hstride;
         Launch<double2>::apply(s, op.g, op.kappa64, 0.0, 0.0, 1, Z + (size_t)j * vs + r * n, w);
-        launch_multidot(s, Vr, j + 1, n, vs, w, part);
-        launch_reduce(s, part, nbb, 2 * (j + 1), hb);
-        launch_multiaxpy(s, w, Vr, j + 1, n, vs, hb, -1.0);
-        launch_multidot(s, Vr, j + 1, n, vs, w, part);
-        launch_reduce(s, part, nbb, 2 * (j + 1), hb + 2 * (m + 1));
-        launch_multiaxpy(s, w, Vr, j + 1, n, vs, hb + 2 * (m + 1), -1.0);
-        launch_norm2_partial(s, w, false, n, part);
-        launch_reduce(s, part, nbb, 1, hb + 4 * (m + 1));
+        launch_cgs2(s, Vr, j + 1, n, vs, w, part, hb, hb + 2 * (m + 1), hb + 4 * (m + 1));
         launch_scale_inv(s, w, w, n, hb + 4 * (m + 1));
         HFCI_HIP(hipMemcpyAsync(hhost + (size_t)r * hstride, hb, (4 * (m + 1) + 1) * sizeof(double),
                                 hipMemcpyDeviceToHost, s));
