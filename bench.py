@@ -33,7 +33,12 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-1e-6 residual & stencil GB/s at 256³: learned/FP32 vs plain FP64 (1 GPU)"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fp_stage_c64_256.json")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def traffic_file(shape):
+    """Counter summary of the complex64 stage kernel at 256^3 for one launch shape."""
+    return os.path.join(PROFILES, "traffic_fp_stage_c64_256_shape%s.json" % "-".join(str(v) for v in shape))
 
 
 def log(*a):
@@ -53,7 +58,7 @@ def measured_traffic(shape):
     kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), if the counters were
     taken on this source with the same launch shape."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(shape)) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -442,7 +447,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_over_alg": round(traffic_ratio, 4) if traffic_ratio else None,
-                     "kernel": ("zpair_kernel<float, 0> (two middle factors of a fixed-point step per pass)"
+                     "kernel": ("zpair_kernel<float, 0, %d> (two middle factors of a fixed-point step per pass)"
+                                % (2 if tune32[2] >= 3 else 1)
                                 if tune32[4] else
                                 "%s<float, EpiFactor<float, 0>, %d, %d> (middle factor of a fixed-point step)"
                                 % ("zlds_kernel" if tune32[0] == 1 else "zmarch_kernel", tune32[1], tune32[2])),
