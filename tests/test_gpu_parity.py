@@ -81,7 +81,8 @@ def test_apply_parity(ctx, shape, prec):
 
 TUNES = [(0, 4, 1, 0, 0), (0, 4, 2, 0, 0), (0, 8, 1, 0, 0), (0, 8, 2, 3, 0), (0, 4, 2, 1, 0), (1, 4, 1, 0, 0),
          (1, 4, 2, 0, 0), (1, 4, 3, 0, 0), (1, 8, 2, 0, 0), (1, 8, 3, 0, 0), (1, 4, 3, 1, 0), (1, 4, 2, 5, 0),
-         (1, 8, 3, 7, 0), (1, 8, 2, 0, 1), (1, 8, 2, 1, 1), (1, 8, 2, 5, 1), (0, 4, 1, 3, 1)]
+         (1, 8, 3, 7, 0), (1, 8, 2, 0, 1), (1, 8, 2, 1, 1), (1, 8, 2, 5, 1), (0, 4, 1, 3, 1),
+         (1, 8, 3, 0, 1), (1, 8, 3, 2, 1), (1, 8, 3, 5, 1)]
 
 
 @pytest.mark.parametrize("tune", TUNES)
@@ -138,16 +139,18 @@ def test_autotune_picks_a_timed_shape(ctx, pr):
 
 @pytest.mark.parametrize("q", [1, 2, 3, 4, 5, 8])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_fused_factor_pairs_every_q(ctx, q, prec):
+@pytest.mark.parametrize("pd", [2, 3])
+def test_fused_factor_pairs_every_q(ctx, q, prec, pd):
     # two factors per pass: every split of step one (q-1 factors) and of later steps (q)
     # into pairs and a trailing single, adaptive stopping with the pair kernel's residual
-    # partials, on a grid with ragged 64 x 8 tiles and several z-chunks
+    # partials, on a grid with ragged 64 x 12 tiles and several z-chunks; loads one plane
+    # ahead (pd 2) and two (pd 3)
     dt = torch.complex128 if prec == "f64" else torch.complex64
     pr = 64 if prec == "f64" else 32
     shape = (21, 13, 70)
     c = medium(shape, 41)
     o, g = make_ops(ctx, c, 14.0, 3, 1.0)
-    g.set_tune(pr, 1, 8, 2, 8, 1)
+    g.set_tune(pr, 1, 8, pd, 8, 1)
     poles = oracle_poles(o, 4, 1.0, 0.5, q)
     cg = gpu_contour(g, poles, 4, q)
     rng = np.random.default_rng(42)
@@ -318,7 +321,9 @@ def test_solve_lockstep_fp64(ctx):
     poles = oracle_poles(o, 8, 1.0, 0.5, 8)
     cg = gpu_contour(g, poles, 8, 8)
     f = wl.rhs[0]
-    for m, its in [(30, 10), (4, 10)]:  # one cycle; several restarts
+    # one cycle deep enough for every width of the fused CGS2 passes (up to 25 basis
+    # vectors); several restarts
+    for m, its in [(30, 24), (4, 10)]:
         opts = hf.default_opts(fp_steps=3, tol=0.0, max_it=its, restart=m)
         u, st = hf.solve(g, cg, dev(f[None]), opts=opts)
         uo, info = OF.solve(o, f, poles, m=m, tol=0.0, max_it=its, steps=3)
