@@ -259,9 +259,12 @@ template <typename T2> struct ScalOf;
 template <> struct ScalOf<float2> { using t = float; };
 template <> struct ScalOf<double2> { using t = double; };
 
+// w_r (+)= sum_j c_j y_{j,r}; with steps given, system (j, r) reads y1 instead of y when it
+// took at most one fixed-point step (its iterate was left in y1)
 template <typename T2>
 __global__ void combine_kernel(T2* __restrict__ w, const T2* __restrict__ y, const double* __restrict__ coef,
-                               int npole, int nrhs, size_t n, int accumulate) {
+                               int npole, int nrhs, size_t n, int accumulate, const T2* __restrict__ y1,
+                               const int* __restrict__ steps) {
   using T = typename ScalOf<T2>::t;
   const int r = blockIdx.y;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -273,7 +276,9 @@ __global__ void combine_kernel(T2* __restrict__ w, const T2* __restrict__ y, con
       ai = o.y;
     }
     for (int j = 0; j < npole; ++j) {
-      const T2 v = y[((size_t)j * nrhs + r) * n + p];
+      const size_t ls = (size_t)j * nrhs + r;
+      const T2* src = (steps != nullptr && steps[ls] <= 1) ? y1 : y;
+      const T2 v = src[ls * n + p];
       const double cr = coef[2 * j], ci = coef[2 * j + 1];
       ar += cr * (double)v.x - ci * (double)v.y;
       ai += cr * (double)v.y + ci * (double)v.x;
@@ -404,6 +409,17 @@ __global__ void dfinish_kernel(const double* __restrict__ sums, int nrhs, double
   }
 }
 
+// d = s for the systems that took at most one fixed-point step (their y is y1)
+template <typename T2>
+__global__ void copy_unstepped_kernel(T2* __restrict__ d, const T2* __restrict__ s, const int* __restrict__ steps,
+                                      size_t n) {
+  const int sys = blockIdx.y;
+  if (steps[sys] > 1) return;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride)
+    d[(size_t)sys * n + p] = s[(size_t)sys * n + p];
+}
+
 template <typename T2>
 __global__ void copy_active_kernel(T2* __restrict__ d, const T2* __restrict__ s, const int* __restrict__ active,
                                    size_t n) {
@@ -530,10 +546,10 @@ void launch_convert_32_to_64(hipStream_t st, double2* dst, const float2* src, si
 
 template <typename T2>
 void launch_combine(hipStream_t st, T2* w, const T2* y, const double* coef, int npole, int nrhs, size_t n,
-                    bool accumulate) {
+                    bool accumulate, const T2* y1, const int* steps) {
   const unsigned bx = ew_blocks(n) / (nrhs > 8 ? 8 : (unsigned)nrhs) + 1;
   hipLaunchKernelGGL(combine_kernel<T2>, dim3(bx, nrhs), dim3(NT), 0, st, w, y, coef, npole, nrhs, n,
-                     accumulate ? 1 : 0);
+                     accumulate ? 1 : 0, y1, steps);
 }
 
 template <typename T2>
@@ -580,6 +596,15 @@ void launch_build_list(hipStream_t st, const int* active, int nsys, int* list) {
   if (nsys > 0) hipLaunchKernelGGL(build_list_kernel, dim3(1), dim3(NT), 0, st, active, nsys, list);
 }
 
+void launch_copy_unstepped(hipStream_t st, void* d, const void* s, bool f64, const int* steps, int nsys,
+                           size_t n) {
+  const dim3 grid(ew_blocks(n) / 4 + 1, nsys);
+  if (f64)
+    hipLaunchKernelGGL(copy_unstepped_kernel<double2>, grid, dim3(NT), 0, st, (double2*)d, (const double2*)s, steps, n);
+  else
+    hipLaunchKernelGGL(copy_unstepped_kernel<float2>, grid, dim3(NT), 0, st, (float2*)d, (const float2*)s, steps, n);
+}
+
 void launch_copy_active_f(hipStream_t st, float2* d, const float2* s, const int* a, int nsys, size_t n) {
   hipLaunchKernelGGL(copy_active_kernel<float2>, dim3(ew_blocks(n) / 4 + 1, nsys), dim3(NT), 0, st, d, s, a, n);
 }
@@ -588,9 +613,10 @@ void launch_copy_active_d(hipStream_t st, double2* d, const double2* s, const in
   hipLaunchKernelGGL(copy_active_kernel<double2>, dim3(ew_blocks(n) / 4 + 1, nsys), dim3(NT), 0, st, d, s, a, n);
 }
 
-template void launch_combine<float2>(hipStream_t, float2*, const float2*, const double*, int, int, size_t, bool);
+template void launch_combine<float2>(hipStream_t, float2*, const float2*, const double*, int, int, size_t, bool,
+                                     const float2*, const int*);
 template void launch_combine<double2>(hipStream_t, double2*, const double2*, const double*, int, int, size_t,
-                                      bool);
+                                      bool, const double2*, const int*);
 template void launch_scale_out<float2>(hipStream_t, double2*, const float2*, const double*, int, size_t);
 template void launch_scale_out<double2>(hipStream_t, double2*, const double2*, const double*, int, size_t);
 

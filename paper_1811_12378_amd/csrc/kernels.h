@@ -147,10 +147,12 @@ void launch_fill_zero(hipStream_t st, void* p, size_t bytes);
 void launch_copy_scaled64(hipStream_t st, double2* dst, const double2* src, size_t n, double s);
 void launch_convert_64_to_32(hipStream_t st, float2* dst, const double2* src, size_t n);
 void launch_convert_32_to_64(hipStream_t st, double2* dst, const float2* src, size_t n);
-// w_r = sum_p c_p y_{p,r} (+= if accumulate), systems laid out pole-major.
+// w_r = sum_p c_p y_{p,r} (+= if accumulate), systems laid out pole-major; with steps
+// (device, per system) the systems with steps <= 1 read y1 instead of y.
 template <typename T2>
 void launch_combine(hipStream_t st, T2* w, const T2* y, const double* coef /*[npole][2]*/,
-                    int npole, int nrhs, size_t n, bool accumulate);
+                    int npole, int nrhs, size_t n, bool accumulate, const T2* y1 = nullptr,
+                    const int* steps = nullptr);
 // out64_r = d_r * w_r  (d from device array d[2r], d[2r+1])
 template <typename T2>
 void launch_scale_out(hipStream_t st, double2* out, const T2* w, const double* d, int nrhs,

@@ -31,6 +31,8 @@ void copy_active(hipStream_t st, T2* dst, const T2* src, const int* active, int 
 void launch_copy_active_f(hipStream_t st, float2* dst, const float2* src, const int* active, int nsys, size_t n);
 void launch_copy_active_d(hipStream_t st, double2* dst, const double2* src, const int* active, int nsys,
                           size_t n);
+void launch_copy_unstepped(hipStream_t st, void* dst, const void* src, bool f64, const int* steps, int nsys,
+                           size_t n);
 
 namespace {
 template <>
@@ -41,14 +43,30 @@ template <>
 void copy_active<double2>(hipStream_t st, double2* d, const double2* s, const int* a, int nsys, size_t n) {
   launch_copy_active_d(st, d, s, a, nsys, n);
 }
+// d_s = s_s for the systems with steps[s] <= 1
+template <typename T2>
+void copy_unstepped(hipStream_t st, T2* d, const T2* s, const int* steps, int nsys, size_t n) {
+  launch_copy_unstepped(st, d, s, sizeof(T2) == 16, steps, nsys, n);
+}
+
+// Systems whose iterate was left in y1 (they took at most one fixed-point step): the
+// caller selects y1 for them through their step counts.
+template <typename T2>
+struct Deferred {
+  const T2* y1 = nullptr;
+  const int* steps = nullptr;
+};
 
 // Iterate eq. fix-pt-exp for systems gs in [sys0, sys0 + nsys) from y = 0, in the
-// product form of params.cpp: step one builds y1 = P2(B) g / p~(z) (written to y1 and
-// y), every later step is y <- L y + y1 as q factor launches, the first of which also
-// forms the residual of the current y for the stopping test (Table 4's "reduced by 5").
+// product form of params.cpp: step one builds y1 = P2(B) g / p~(z) (y = y1 after it),
+// every later step is y <- L y + y1 as q factor launches, the first of which also forms
+// the residual of the current y for the stopping test (Table 4's "reduced by 5").  With
+// defer (not null), systems that took at most one step may keep their iterate in y1:
+// defer->y1 and defer->steps are then set for the caller to select it (else both null).
 template <typename T2>
 void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sys0, int nsys,
-            int fixed_steps, double reduce, int max_steps, int* steps_out, FciStats& st, bool graphs = false) {
+            int fixed_steps, double reduce, int max_steps, int* steps_out, FciStats& st, bool graphs = false,
+            Deferred<T2>* defer = nullptr) {
   Ctx& ctx = *op.ctx;
   hipStream_t s = ctx.stream;
   const size_t n = op.n;
@@ -139,11 +157,13 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
     struct Part {
       int k, width, kind;
     };
-    // launches of `count` factors from coefficient k0, two per pass when fusing
-    auto plan = [&](int k0, int count, int kind_first, int kind_last, bool pairs) {
+    // launches of `count` factors from coefficient k0, two per pass when fusing; an odd
+    // count leaves one single launch, at the end or (single_first) at the start
+    auto plan = [&](int k0, int count, int kind_first, int kind_last, bool pairs, bool single_first) {
       std::vector<Part> v;
       for (int j = 0; j < count;) {
-        const int w = (pairs && j + 1 < count) ? 2 : 1;
+        const bool lone = single_first && j == 0 && count % 2 == 1;
+        const int w = (pairs && j + 1 < count && !lone) ? 2 : 1;
         int kind = 0;
         if (j == 0) kind |= kind_first;
         if (j + w == count) kind |= kind_last;
@@ -154,29 +174,35 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
     };
 
     // ---- step one: y1 = prod over the max(q-1, 1) factors of P2, applied to f ----
+    // After it y = y1.  Unless a captured graph replays the later steps (their first launch
+    // reads y) or no later step runs, step one writes y1 only, the first later step reads
+    // y1, and the systems that stop before any later step get y = y1 at the end.  With an
+    // odd number of factors the single launch comes first: it reads f, shared by the poles.
     a.count = nsys;
     const int nP = std::max(q - 1, 1);
+    const bool dual = (graphs && !pr.on) || (fixed && cap <= 1);
     {
-      const std::vector<Part> pl = plan(q, nP, kFacInF, kFacDual, fuse);
+      const std::vector<Part> pl = plan(q, nP, kFacInF, dual ? kFacDual : 0, fuse, true);
       const T2* cur = nullptr;
       for (size_t i = 0; i < pl.size(); ++i) {
         const bool last = i + 1 == pl.size();
         T2* dst = last ? y1 : ((cur == wA) ? wB : wA);
-        launch(pl[i].kind, pl[i].k, pl[i].width, cur, dst, last ? y : nullptr);
+        launch(pl[i].kind, pl[i].k, pl[i].width, cur, dst, (last && dual) ? y : nullptr);
         cur = dst;
       }
       st.matvecs += (long long)(q - 1) * nsys;
       st.fp_steps += nsys;
     }
+    const T2* y_first = dual ? y : y1;  // the iterate read by the first later step
 
     // ---- steps two and on: y <- L y + y1 ----
     // (a launch never writes its own input: a step made of a single launch goes through wA)
-    const std::vector<Part> pl = plan(0, q, kFacResid, kFacAdd, fuse && q >= 3);
+    const std::vector<Part> pl = plan(0, q, kFacResid, kFacAdd, fuse && q >= 3, false);
     const bool single = pl.size() == 1;
     // first launch of a step from y, with the ||f - (A - z) y||^2 partials of the current
     // iterate, the stopping test, and in adaptive mode the compacted list and the flags
-    auto head = [&](bool read_flags) {
-      launch(pl[0].kind, pl[0].k, pl[0].width, y, wA, nullptr);
+    auto head = [&](bool read_flags, const T2* yin) {
+      launch(pl[0].kind, pl[0].k, pl[0].width, yin, wA, nullptr);
       launch_fp_check(s, partial, nblk, nsys, sys0, nrhs, fnorm2, fixed_steps, reduce, max_steps, active, steps,
                       rnorm2);
       if (!fixed) {
@@ -216,8 +242,8 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
       // two halves of the pinned buffer; an event marks each read-back.
       hipEvent_t ev[2] = {ctx.step_event[0], ctx.step_event[1]};
       int* flags[2] = {ctx.pinned_int, ctx.pinned_int + kPinnedIntHalf};
-      auto head_to = [&](int slot) {
-        launch(pl[0].kind, pl[0].k, pl[0].width, y, wA, nullptr);
+      auto head_to = [&](int slot, const T2* yin) {
+        launch(pl[0].kind, pl[0].k, pl[0].width, yin, wA, nullptr);
         launch_fp_check(s, partial, nblk, nsys, sys0, nrhs, fnorm2, fixed_steps, reduce, max_steps, active, steps,
                         rnorm2);
         launch_build_list(s, active, nsys, list);
@@ -226,14 +252,14 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
       };
       std::vector<Fixup> fx;
       fixups = &fx;
-      head_to(0);
+      head_to(0, y_first);
       st.matvecs += nact;
       int slot = 0;
       for (int it = 1; it <= cap; ++it) {
         // queue the rest of step `it` and the head of step it + 1, then read step it's flags
         fx.clear();
         rest();
-        head_to(slot ^ 1);
+        head_to(slot ^ 1, y);
         HFCI_HIP(hipEventSynchronize(ev[slot]));
         int na = 0;
         for (int k = 0; k < nsys; ++k) {
@@ -252,7 +278,7 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
     } else if (!(graphs && !pr.on)) {
       for (int it = 1; it <= cap; ++it) {
         if (fixed && it == cap) break;  // exact count: no final residual check needed
-        head(!fixed);
+        head(!fixed, it == 1 ? y_first : y);
         st.matvecs += nact;
         if (!fixed) {
           HFCI_HIP(hipStreamSynchronize(s));
@@ -286,11 +312,11 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
         HFCI_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         try {
           if (fixed) {
-            head(false);
+            head(false, y);
             rest();
           } else {
             rest();
-            head(true);
+            head(true, y);
           }
         } catch (...) {
           (void)hipStreamEndCapture(s, &graph);
@@ -310,7 +336,7 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
           st.fp_steps += nsys;
         }
       } else {
-        head(true);
+        head(true, y);
         st.matvecs += nsys;
         HFCI_HIP(hipStreamSynchronize(s));
         nact = read_active();
@@ -322,6 +348,17 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
           st.matvecs += nact;
           nact = read_active();
         }
+      }
+    }
+    // adaptive without the dual write: the systems that stopped before any later step
+    // (steps <= 1) hold their iterate in y1 (fixed counts >= 2 run a later step on every
+    // system); the caller selects it, or it is copied to y
+    if (!dual && !fixed) {
+      if (defer) {
+        defer->y1 = y1;
+        defer->steps = steps;
+      } else {
+        copy_unstepped<T2>(s, y, y1, steps, nsys, n);
       }
     }
   }
@@ -454,9 +491,10 @@ void fci_body(const Op& op, const Contour& c, const hfci_solve_opts& o, int nrhs
   for (int p0 = 0; p0 < J; p0 += pb) {
     const int np = std::min(pb, J - p0);
     const bool graphs = o.graphs == 1 || (o.graphs < 0 && op.n <= ((size_t)1 << 16));
+    Deferred<T2> dfr;
     fp_run<T2>(op, c, nrhs, f, y, p0 * nrhs, np * nrhs, o.fp_steps, o.fp_reduce, o.fp_max_steps, nullptr, st,
-               graphs);
-    launch_combine<T2>(s, w, y, cc + 2 * p0, np, nrhs, n, p0 > 0);
+               graphs, &dfr);
+    launch_combine<T2>(s, w, y, cc + 2 * p0, np, nrhs, n, p0 > 0, dfr.y1, dfr.steps);
   }
   // step 3: minimise ||f - d A w|| over d
   const int nblk = Launch<T2>::partial_blocks(op.g);
