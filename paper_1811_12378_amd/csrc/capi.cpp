@@ -72,8 +72,8 @@ hipEvent_t Profiler::take() {
     free_.pop_back();
     return e;
   }
-  hipEvent_t e;
-  HFCI_HIP(hipEventCreate(&e));
+  hipEvent_t e;  // timing only: no system-scope fence (no cache writeback) per record
+  HFCI_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   return e;
 }
 

@@ -424,8 +424,8 @@ KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, d
     for (int cz : {0, 16, 64})
       for (int pd : {2, 3}) cands.push_back(KernelTune{1, 8, pd, cz, 1});
   hipEvent_t e0, e1;
-  HFCI_HIP(hipEventCreate(&e0));
-  HFCI_HIP(hipEventCreate(&e1));
+  HFCI_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+  HFCI_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
   KernelTune best = saved;
   double best_ms = 1e300;
   timings.clear();
@@ -538,20 +538,25 @@ struct Timer {
   hipEvent_t a, b;
   hipStream_t s;
   explicit Timer(hipStream_t st) : s(st) {
-    HFCI_HIP(hipEventCreate(&a));
-    HFCI_HIP(hipEventCreate(&b));
+    HFCI_HIP(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+    HFCI_HIP(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
   }
   ~Timer() {
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
   }
   void start() { HFCI_HIP(hipEventRecord(a, s)); }
-  double stop_ms() {
-    HFCI_HIP(hipEventRecord(b, s));
+  void stop() { HFCI_HIP(hipEventRecord(b, s)); }
+  // after stop(): waits for the end event (free after a stream synchronisation)
+  double elapsed_ms() {
     HFCI_HIP(hipEventSynchronize(b));
     float ms = 0;
     HFCI_HIP(hipEventElapsedTime(&ms, a, b));
     return ms;
+  }
+  double stop_ms() {
+    stop();
+    return elapsed_ms();
   }
 };
 
@@ -619,7 +624,7 @@ hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& 
   int net_rejects_in_row = 0;
   FciStats fst;
   double t_fci = 0, t_arn = 0;
-  Timer tm(s);
+  Timer tm(s), tf(s);  // tf: the preconditioner of an Arnoldi step, read at the step's sync
   hfci_status status = HFCI_OK;
 
   for (int r = 0; r < nrhs; ++r)
@@ -682,7 +687,7 @@ hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& 
     std::vector<int> live = cyc;  // rhs still extending this cycle
     for (int j = 0; j < m && !live.empty(); ++j) {
       // ---- preconditioner: Z[j] = FCI(V[j]) for the live right-hand sides ----
-      tm.start();
+      tf.start();
       const int nl = (int)live.size();
       const bool all = (nl == nrhs);
       const double2* fin = V + (size_t)j * vs;
@@ -773,7 +778,7 @@ hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& 
         launch_convert_64_to_32(s, (float2*)o.harvest_z + (size_t)harvested * n, Z + (size_t)j * vs + r * n, n);
         ++harvested;
       }
-      t_fci += tm.stop_ms();
+      tf.stop();  // no wait here: the Arnoldi launches queue behind the preconditioner
       // ---- Arnoldi: w = A z_j, CGS2 against V[0..j], normalise ----
       tm.start();
       for (int r : live) {
@@ -789,6 +794,7 @@ hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& 
       fst.matvecs += nl;
       HFCI_HIP(hipStreamSynchronize(s));
       t_arn += tm.stop_ms();
+      t_fci += tf.elapsed_ms();
       ++its;
       // ---- Givens update of the Hessenberg column on the host ----
       std::vector<int> next;
