@@ -77,6 +77,10 @@ struct Launch {
   // not alias the input
   static bool factor_pair(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a,
                           int kind);
+  // a kFacInF single factor over systems s = j * nrhs + r (all listed, count a multiple of
+  // nrhs, at most 64 poles): each point forms the stencil of f once for all poles; false
+  // (nothing launched) when those conditions do not hold
+  static bool factor_fanout(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a);
   static int pair_blocks(const GridDesc& g);  // residual partials per system of a pair launch
   // whether factor_pair runs on this grid (32-bit byte offsets: each vector under 4 GiB)
   static bool pair_fits(const GridDesc& g);

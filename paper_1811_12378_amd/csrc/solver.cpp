@@ -136,7 +136,7 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
     std::vector<Fixup>* fixups = nullptr;
     // One launch of `width` consecutive factors starting at coefficient k.  kind: kFacInF /
     // kFacResid on its first factor, kFacAdd / kFacDual on its last.
-    auto launch = [&](int kind, int k, int width, const T2* win, T2* wout, T2* wout2) {
+    auto launch = [&](int kind, int k, int width, const T2* win, T2* wout, T2* wout2, bool fan = false) {
       a.k = k;
       a.win = win;
       a.wout = wout;
@@ -147,7 +147,8 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
       const double vecs = (inf ? 0.0 : 1.0) + 1.0 + (add ? 1.0 : 0.0) + (dual ? 1.0 : 0.0);
       if (pr.on) pr.begin(s);
       const bool ok = width == 2 ? Launch<T2>::factor_pair(s, op.g, kap, a, kind)
-                                 : Launch<T2>::factor(s, op.g, kap, a, kind);
+                                 : (fan && Launch<T2>::factor_fanout(s, op.g, kap, a)) ||
+                                       Launch<T2>::factor(s, op.g, kap, a, kind);
       HFCI_REQUIRE(ok, "internal: unsupported factor kind");
       if (pr.on) {
         if (fixups) fixups->push_back(Fixup{pr.mark(), vecs, inf || resid});
@@ -187,7 +188,10 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
       for (size_t i = 0; i < pl.size(); ++i) {
         const bool last = i + 1 == pl.size();
         T2* dst = last ? y1 : ((cur == wA) ? wB : wA);
-        launch(pl[i].kind, pl[i].k, pl[i].width, cur, dst, (last && dual) ? y : nullptr);
+        // every system is listed in order here: a lone first factor from f serves all
+        // poles of a right-hand side in one pass
+        const bool fan = i == 0 && pl[i].width == 1 && pl[i].kind == kFacInF;
+        launch(pl[i].kind, pl[i].k, pl[i].width, cur, dst, (last && dual) ? y : nullptr, fan);
         cur = dst;
       }
       st.matvecs += (long long)(q - 1) * nsys;

@@ -646,6 +646,55 @@ struct EpiApply {
   __device__ void partial_out(int, int, int, int, double) const {}
 };
 
+// The first factor of step one for every pole of a right-hand side at once (kFacInF, one
+// factor per pass): w_j = a_j (A - z0_j) f + b_j f = a_j (A f) + (b_j - a_j z0_j) f, so f,
+// kappa and the stencil of f are read and formed once per point for all poles.  Slot r is
+// the right-hand side; the launch's systems are s = j * nrhs + r for j < np, all listed.
+template <typename T>
+struct EpiFanout {
+  using T2 = typename V2<T>::t;
+  static constexpr int NACC = 0;
+  static constexpr int kMaxPoles = 64;
+  struct Sys {
+    const T2* cf;  // LDS: per pole a_j, then b_j - a_j z0_j
+    int r;
+  };
+  using Aux = NoAux;
+  FactorArgs<T2> a;
+  const T* kappa;
+  size_t n;
+  int np;
+  __device__ int system(int slot) const { return slot; }
+  __device__ const T2* in(int r) const { return a.f + (size_t)r * n; }
+  // called once per block by every thread, before the plane loop
+  __device__ Sys sys(int r) const {
+    __shared__ T2 cf[2 * kMaxPoles];
+    const int t = threadIdx.x + blockDim.x * threadIdx.y;
+    if (t < np) {
+      const int pole = (a.sys0 + t * a.nrhs + r) / a.nrhs;
+      const FactorCoef c = a.coef[pole * a.cstride + a.k];
+      const PoleDev pd = a.poles[pole];
+      cf[2 * t] = T2{(T)c.a_re, (T)c.a_im};
+      cf[2 * t + 1] = T2{(T)(c.b_re - (c.a_re * pd.z0_re - c.a_im * pd.z0_im)),
+                         (T)(c.b_im - (c.a_re * pd.z0_im + c.a_im * pd.z0_re))};
+    }
+    __syncthreads();
+    return Sys{cf, r};
+  }
+  __device__ void shift(const Sys&, T& re, T& im) const { re = (T)0; im = (T)0; }
+  __device__ Aux load_aux(const Sys&, int, size_t) const { return Aux{}; }
+  __device__ void point(const Sys& c, int, size_t p, const T2& Sx, const T2& cur, const Aux&, double*) const {
+    for (int j = 0; j < np; ++j) {
+      const T2 aj = c.cf[2 * j], cj = c.cf[2 * j + 1];
+      T2 o;
+      o.x = aj.x * Sx.x - aj.y * Sx.y + cj.x * cur.x - cj.y * cur.y;
+      o.y = aj.x * Sx.y + aj.y * Sx.x + cj.x * cur.y + cj.y * cur.x;
+      a.wout[((size_t)j * a.nrhs + c.r) * n + p] = o;
+    }
+  }
+  __device__ void partial_out(int, int, int, int, double) const {}
+};
+
 // One factor of the product-form step, per listed system s:
 //   out = a (A - z0) in + b in  [+ y1]   (a, b per pole and factor)
 // kFacResid: in is the iterate y; also accumulates |f - (A - z) y|^2 with
@@ -942,6 +991,16 @@ void Launch<T2>::apply(hipStream_t st, const GridDesc& g, const void* kappa, dou
   using T = typename Scal<T2>::t;
   EpiApply<T> e{x, y, (const T*)kappa, (size_t)g.nx * g.ny * g.nz, (T)sre, (T)sim};
   run<T>(st, g, nvec, e);
+}
+
+template <typename T2>
+bool Launch<T2>::factor_fanout(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a) {
+  using T = typename Scal<T2>::t;
+  const int np = a.nrhs > 0 ? a.count / a.nrhs : 0;
+  if (np < 1 || np * a.nrhs != a.count || np > EpiFanout<T>::kMaxPoles || a.sys0 % a.nrhs != 0) return false;
+  EpiFanout<T> e{a, (const T*)kappa, (size_t)g.nx * g.ny * g.nz, np};
+  run<T>(st, g, a.nrhs, e);
+  return true;
 }
 
 template <typename T, int KIND, typename T2>
