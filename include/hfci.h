@@ -161,7 +161,8 @@ const char* hfci_version(void);
 hfci_status hfci_ctx_create(int device, void* stream, hfci_ctx** out);
 void hfci_ctx_destroy(hfci_ctx* ctx);
 
-/* Start (enable = 1, counters reset) or stop (0) kernel timing on the context. */
+/* Start (enable = k >= 1, counters reset: every k-th launch of each class is timed) or
+ * stop (0) kernel timing on the context.  Errors: HFCI_E_ARG for enable < 0. */
 hfci_status hfci_ctx_profile(hfci_ctx* ctx, int enable);
 /* Copy the counters into out[HFCI_PROF_N] (HOST array). */
 hfci_status hfci_ctx_profile_read(const hfci_ctx* ctx, hfci_kernel_prof* out);

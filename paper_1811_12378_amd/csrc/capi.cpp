@@ -105,6 +105,7 @@ void Profiler::harvest() {
 
 void Profiler::reset() {
   for (auto& a : acc) a = Acc{};
+  for (auto& k : seen_) k = 0;
 }
 
 void Profiler::release() {
@@ -261,9 +262,11 @@ hfci_status hfci_ctx_profile(hfci_ctx* ctx, int enable) {
   HFCI_REQUIRE(ctx, "NULL context");
   DeviceGuard dg(ctx->device);
   HFCI_HIP(hipStreamSynchronize(ctx->stream));
+  HFCI_REQUIRE(enable >= 0, "enable must be >= 0");
   ctx->prof.harvest();
   if (enable) ctx->prof.reset();
   ctx->prof.on = enable != 0;
+  ctx->prof.period = enable > 0 ? enable : 1;
   return HFCI_OK;
   HFCI_API_END
 }
@@ -442,12 +445,13 @@ hfci_status hfci_apply(const hfci_op* op, hfci_c128 shift, int prec, int nvec, c
   hipStream_t s = op->ctx->stream;
   Profiler& pr = op->ctx->prof;
   const double e = prec == HFCI_F64 ? 16.0 : 8.0;
-  if (pr.on) pr.begin(s);
+  const bool timed = pr.sample(HFCI_PROF_APPLY);
+  if (timed) pr.begin(s);
   if (prec == HFCI_F64)
     Launch<double2>::apply(s, op->g, op->kappa64, shift.re, shift.im, nvec, (const double2*)x, (double2*)y);
   else
     Launch<float2>::apply(s, op->g, op->kappa32, shift.re, shift.im, nvec, (const float2*)x, (float2*)y);
-  if (pr.on) pr.end(s, HFCI_PROF_APPLY, (double)op->n * (2.0 * e * nvec + e / 2.0));
+  if (timed) pr.end(s, HFCI_PROF_APPLY, (double)op->n * (2.0 * e * nvec + e / 2.0));
   HFCI_HIP(hipGetLastError());
   HFCI_HIP(hipStreamSynchronize(s));
   if (pr.on) pr.harvest();

@@ -61,6 +61,9 @@ constexpr int kPinnedIntHalf = 32768;
 class Profiler {
  public:
   bool on = false;
+  int period = 1;  // time every period-th launch of each class
+  // whether this launch of class cls is timed (counts the launch either way)
+  bool sample(int cls) { return on && (seen_[cls]++ % period) == 0; }
   struct Acc {
     long long launches = 0;
     double ms = 0.0, bytes = 0.0;
@@ -85,6 +88,7 @@ class Profiler {
     double bytes;
   };
   hipEvent_t take();
+  long long seen_[HFCI_PROF_N] = {};
   std::vector<hipEvent_t> free_;
   std::vector<Pending> pending_;
   hipEvent_t open_ = nullptr;

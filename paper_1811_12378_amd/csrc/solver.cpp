@@ -145,12 +145,13 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
       const int cls = resid ? HFCI_PROF_FP_FIRST
                             : (inf || dual) ? HFCI_PROF_FP_INIT : add ? HFCI_PROF_FP_LAST : HFCI_PROF_FP_STAGE;
       const double vecs = (inf ? 0.0 : 1.0) + 1.0 + (add ? 1.0 : 0.0) + (dual ? 1.0 : 0.0);
-      if (pr.on) pr.begin(s);
+      const bool timed = pr.sample(cls);
+      if (timed) pr.begin(s);
       const bool ok = width == 2 ? Launch<T2>::factor_pair(s, op.g, kap, a, kind)
                                  : (fan && Launch<T2>::factor_fanout(s, op.g, kap, a)) ||
                                        Launch<T2>::factor(s, op.g, kap, a, kind);
       HFCI_REQUIRE(ok, "internal: unsupported factor kind");
-      if (pr.on) {
+      if (timed) {
         if (fixups) fixups->push_back(Fixup{pr.mark(), vecs, inf || resid});
         pr.end(s, cls, launch_bytes(vecs, inf || resid));
       }

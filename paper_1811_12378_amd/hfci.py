@@ -218,9 +218,10 @@ class Context(_Handle):
     def _adopt(self, child):
         self._children.add(child)
 
-    def profile(self, enable: bool = True):
-        """hfci_ctx_profile: start (counters reset) or stop kernel timing."""
-        _check(load_library().hfci_ctx_profile(self.h, 1 if enable else 0))
+    def profile(self, enable: bool = True, every: int = 1):
+        """hfci_ctx_profile: start (counters reset; every k-th launch of each class timed)
+        or stop kernel timing."""
+        _check(load_library().hfci_ctx_profile(self.h, int(every) if enable else 0))
 
     def profile_read(self):
         """hfci_ctx_profile_read -> {class: {launches, total_ms, alg_bytes}}."""

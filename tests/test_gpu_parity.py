@@ -172,6 +172,23 @@ def test_fused_factor_pairs_every_q(ctx, q, prec, pd):
                 assert rel(y[j, r], ref) <= 1e-12
 
 
+def test_profiler_times_every_kth_launch(ctx):
+    # hfci_ctx_profile(k): every k-th launch of a class is bracketed by events; the counters
+    # cover exactly the timed launches (7 applies, k = 3: launches 0, 3, 6)
+    o, g = make_ops(ctx, medium((9, 8, 7), 1), 9.0, 1, 0.5)
+    x = dev(np.ones((1, 9, 8, 7), complex)).to(torch.complex64)
+    ctx.profile(True, every=3)
+    for _ in range(7):
+        hf.apply(g, x, 0.0)
+    p = ctx.profile_read()
+    ctx.profile(False)
+    assert p["apply"]["launches"] == 3
+    assert p["apply"]["total_ms"] > 0
+    assert p["apply"]["alg_bytes"] == pytest.approx(3 * 9 * 8 * 7 * (2 * 8 + 4))
+    with pytest.raises(hf.HfciError):
+        ctx.profile(True, every=-1)
+
+
 def test_tune_rejects_invalid(ctx):
     o, g = make_ops(ctx, medium((4, 4, 4), 1), 9.0, 1, 0.5)
     for bad in [(2, 4, 1, 0), (0, 5, 1, 0), (0, 4, 3, 0), (1, 8, 1, 0), (1, 4, 4, 0), (0, 4, 1, -1),
