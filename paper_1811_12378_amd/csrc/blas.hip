@@ -345,6 +345,55 @@ __global__ void fp_start_kernel(int nsys, int sys0, int nrhs, const double* __re
   }
 }
 
+// The stopping test of every listed system and the compacted list in one block (adaptive
+// mode; see fp_check_kernel and build_list_kernel): wave w sums the partial row of systems
+// w, w + 16, ... in a fixed order and its lane 0 decides; after the barrier the block
+// compacts the flags into the list (-1 tail) and also writes them to host_flags, pinned
+// host memory that the host reads once the launch's event has completed.
+constexpr int FTT = 1024;
+__global__ __launch_bounds__(FTT) void fp_test_kernel(const double* __restrict__ partial, int nblk, int nsys,
+                                                      int sys0, int nrhs, const double* __restrict__ fnorm2,
+                                                      double inv_reduce2, int max_steps, int* __restrict__ active,
+                                                      int* __restrict__ steps, double* __restrict__ rnorm2,
+                                                      int* __restrict__ list, int* __restrict__ host_flags) {
+  __shared__ int wtot[FTT / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int s = wid; s < nsys; s += FTT / 64) {
+    if (active[s] == 0) continue;  // converged earlier: its partial row was not written
+    const double* row = partial + (size_t)s * nblk;
+    double v = 0.0;
+    for (int i = lane; i < nblk; i += 64) v += row[i];
+    v = wave_sum(v);
+    if (lane == 0) {
+      const double r2 = v;
+      rnorm2[s] = r2;
+      int act = (r2 > fnorm2[(sys0 + s) % nrhs] * inv_reduce2) && (steps[s] < max_steps);
+      if (!(r2 == r2) || r2 > 1e300) act = 0;  // NaN / overflow: stop, reported by the host
+      active[s] = act;
+      if (act) steps[s] += 1;
+    }
+  }
+  __syncthreads();
+  int base = 0;
+  for (int c0 = 0; c0 < nsys; c0 += FTT) {
+    const int s = c0 + threadIdx.x;
+    const bool a = s < nsys && active[s] != 0;
+    if (s < nsys) host_flags[s] = a ? 1 : 0;
+    const unsigned long long m = __ballot(a);
+    const int below = __popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+    if (lane == 0) wtot[wid] = __popcll(m);
+    __syncthreads();
+    int off = base;
+    for (int w = 0; w < wid; ++w) off += wtot[w];
+    if (a) list[off + below] = s;
+    int tot = 0;
+    for (int w = 0; w < FTT / 64; ++w) tot += wtot[w];
+    base += tot;
+    __syncthreads();
+  }
+  for (int s = base + threadIdx.x; s < nsys; s += FTT) list[s] = -1;
+}
+
 // Stream compaction of the active flags in one block: wave ballots give each lane its
 // rank within the wave, LDS carries the wave totals, chunks of NT go in order; the
 // tail of the list is filled with -1.
@@ -590,6 +639,14 @@ void launch_fp_start(hipStream_t st, int nsys, int sys0, int nrhs, const double*
   if (nsys > 0)
     hipLaunchKernelGGL(fp_start_kernel, dim3((nsys + 255) / 256), dim3(256), 0, st, nsys, sys0, nrhs, fnorm2,
                        fixed ? 1 : 0, active, steps, list);
+}
+
+void launch_fp_test(hipStream_t st, const double* partial, int nblk, int nsys, int sys0, int nrhs,
+                    const double* fnorm2, double reduce, int max_steps, int* active, int* steps, double* rnorm2,
+                    int* list, int* host_flags) {
+  if (nsys > 0)
+    hipLaunchKernelGGL(fp_test_kernel, dim3(1), dim3(FTT), 0, st, partial, nblk, nsys, sys0, nrhs, fnorm2,
+                       1.0 / (reduce * reduce), max_steps, active, steps, rnorm2, list, host_flags);
 }
 
 void launch_build_list(hipStream_t st, const int* active, int nsys, int* list) {

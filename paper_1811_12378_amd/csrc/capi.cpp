@@ -223,6 +223,7 @@ hfci_status hfci_ctx_create(int device, void* stream, hfci_ctx** out) {
       c->own_stream = true;
     }
     HFCI_HIP(hipHostMalloc((void**)&c->pinned_int, kPinnedInts * sizeof(int), hipHostMallocDefault));
+    HFCI_HIP(hipHostGetDevicePointer((void**)&c->pinned_int_dev, c->pinned_int, 0));
     HFCI_HIP(hipHostMalloc((void**)&c->pinned_dbl, kPinnedDbls * sizeof(double), hipHostMallocDefault));
     for (hipEvent_t& e : c->step_event) HFCI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   } catch (...) {

@@ -116,6 +116,7 @@ struct Ctx {
   GraphCache graphs;
   hipEvent_t step_event[2] = {nullptr, nullptr};  // read-backs of the pipelined fixed-point steps
   int* pinned_int = nullptr;     // host-pinned staging for small D2H reads (65536 ints)
+  int* pinned_int_dev = nullptr; // the same memory as the device addresses it
   double* pinned_dbl = nullptr;  // host-pinned staging (65536 doubles)
 };
 

@@ -174,5 +174,10 @@ void launch_fp_start(hipStream_t st, int nsys, int sys0, int nrhs, const double*
                      int* active, int* steps, int* list);
 // list[0..count) = indices s with active[s] != 0, in increasing order (one block).
 void launch_build_list(hipStream_t st, const int* active, int nsys, int* list);
+// adaptive stopping test + list compaction in one launch; the flags also go to
+// host_flags (device-visible pinned host memory, nsys ints)
+void launch_fp_test(hipStream_t st, const double* partial, int nblk, int nsys, int sys0, int nrhs,
+                    const double* fnorm2, double reduce, int max_steps, int* active, int* steps, double* rnorm2,
+                    int* list, int* host_flags);
 
 }  // namespace hfci

@@ -247,12 +247,11 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
       // two halves of the pinned buffer; an event marks each read-back.
       hipEvent_t ev[2] = {ctx.step_event[0], ctx.step_event[1]};
       int* flags[2] = {ctx.pinned_int, ctx.pinned_int + kPinnedIntHalf};
+      int* flags_dev[2] = {ctx.pinned_int_dev, ctx.pinned_int_dev + kPinnedIntHalf};
       auto head_to = [&](int slot, const T2* yin) {
         launch(pl[0].kind, pl[0].k, pl[0].width, yin, wA, nullptr);
-        launch_fp_check(s, partial, nblk, nsys, sys0, nrhs, fnorm2, fixed_steps, reduce, max_steps, active, steps,
-                        rnorm2);
-        launch_build_list(s, active, nsys, list);
-        HFCI_HIP(hipMemcpyAsync(flags[slot], active, nsys * sizeof(int), hipMemcpyDeviceToHost, s));
+        launch_fp_test(s, partial, nblk, nsys, sys0, nrhs, fnorm2, reduce, max_steps, active, steps, rnorm2, list,
+                       flags_dev[slot]);
         HFCI_HIP(hipEventRecord(ev[slot], s));
       };
       std::vector<Fixup> fx;
