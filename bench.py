@@ -286,6 +286,8 @@ def main():
     ap.add_argument("--uneven-only", action="store_true", help="run only the uneven-batch arm")
     ap.add_argument("--no-small", action="store_true", help="skip the 32^3 / 96^3 configurations")
     ap.add_argument("--small-only", action="store_true", help="run only the 32^3 / 96^3 configurations")
+    ap.add_argument("--profile-every", type=int, default=PROFILE_EVERY,
+                    help="time every k-th launch of each kernel class in the timed solves")
     ap.add_argument("--shape", type=int, nargs=5, metavar=("KERN", "TY", "PD", "CZ", "FUSE"),
                     help="pin the complex64 stencil launch shape instead of autotuning it")
     args = ap.parse_args()
@@ -346,9 +348,10 @@ def main():
         hfci.solve(op, cont, f_d, opts=mixed)
         log("warmup %d done" % w)
 
-    # the roofline's HIP events bracket every PROFILE_EVERY-th launch of each kernel class
-    # inside the timed solves (fewer events, less perturbation of the timed region)
-    ctx.profile(True, every=PROFILE_EVERY)
+    # the roofline's HIP events bracket every k-th launch of each kernel class inside the
+    # timed solves (fewer events, less perturbation of the timed region; k = 1 for the
+    # counter runs, whose counters cover every dispatch)
+    ctx.profile(True, every=args.profile_every)
     times, st = [], None
     for k in range(args.steps):
         torch.cuda.synchronize()
@@ -456,7 +459,7 @@ def main():
                                 "%s<float, EpiFactor<float, 0>, %d, %d> (middle factor of a fixed-point step)"
                                 % ("zlds_kernel" if tune32[0] == 1 else "zmarch_kernel", tune32[1], tune32[2])),
                      "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": bytes_per_launch,
-                     "launches": stage["launches"], "timed_every": PROFILE_EVERY},
+                     "launches": stage["launches"], "timed_every": args.profile_every},
         "cpu_baseline": cpu,
         "its": st["its"],
         "matvecs": st["matvecs"],
