@@ -98,7 +98,8 @@ __global__ __launch_bounds__(NT) void multiaxpy_kernel(double2* __restrict__ w, 
   }
 }
 
-// The second and third passes of CGS2 over the basis V[0..nv) (nv <= 4 * NQ):
+// The passes of CGS2 over the basis V[0..nv) (nv <= 4 * NQ):
+//   partial sums of conj(V_i) . w                                           (DOT, !UPD)
 //   w <- w + sign * sum_i h_i V_i, then partial sums of conj(V_i) . w      (DOT)
 //   w <- w + sign * sum_i h_i V_i, then partial sums of |w|^2               (NORM)
 // Each point belongs to a quad of four lanes; lane q holds the vectors i = 4j + q
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(NT) void multiaxpy_kernel(double2* __restrict__ w, 
 // so V is read once from HBM for both the update and the dot products.  Lanes past nv
 // read a valid vector (V_{nv-1}) with a zero coefficient.  Partial row k (= 2i + c for
 // DOT, 0 for NORM) of block b is at partial[k * gridDim.x + b], as for multidot.
-template <int NQ, bool DOT>
+template <int NQ, bool DOT, bool UPD = true>
 __global__ __launch_bounds__(NT) void axpy_reduce_kernel(double2* __restrict__ w, const double2* __restrict__ V,
                                                          int nv, size_t n, size_t vstride,
                                                          const double* __restrict__ h, double sign,
@@ -114,8 +115,10 @@ __global__ __launch_bounds__(NT) void axpy_reduce_kernel(double2* __restrict__ w
   constexpr int NA = DOT ? 2 * NQ : 1;
   __shared__ double hs[2 * 4 * NQ];
   __shared__ double sh[(NT / 64) * 4 * NA];
-  for (int t = threadIdx.x; t < 2 * 4 * NQ; t += NT) hs[t] = t < 2 * nv ? sign * h[t] : 0.0;
-  __syncthreads();
+  if constexpr (UPD) {
+    for (int t = threadIdx.x; t < 2 * 4 * NQ; t += NT) hs[t] = t < 2 * nv ? sign * h[t] : 0.0;
+    __syncthreads();
+  }
   const int q = threadIdx.x & 3;
   double acc[NA];
 #pragma unroll
@@ -128,20 +131,23 @@ __global__ __launch_bounds__(NT) void axpy_reduce_kernel(double2* __restrict__ w
       const int i = min(4 * j + q, nv - 1);
       v[j] = V[(size_t)i * vstride + p];
     }
-    double sx = 0.0, sy = 0.0;
-#pragma unroll
-    for (int j = 0; j < NQ; ++j) {
-      const double hr = hs[2 * (4 * j + q)], hi = hs[2 * (4 * j + q) + 1];
-      sx += hr * v[j].x - hi * v[j].y;
-      sy += hr * v[j].y + hi * v[j].x;
-    }
-    sx += __shfl_xor(sx, 1, 64);
-    sy += __shfl_xor(sy, 1, 64);
-    sx += __shfl_xor(sx, 2, 64);
-    sy += __shfl_xor(sy, 2, 64);
     const double2 wv = w[p];
-    const double2 wn = make_double2(wv.x + sx, wv.y + sy);
-    if (q == 0) w[p] = wn;
+    double2 wn = wv;
+    if constexpr (UPD) {
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) {
+        const double hr = hs[2 * (4 * j + q)], hi = hs[2 * (4 * j + q) + 1];
+        sx += hr * v[j].x - hi * v[j].y;
+        sy += hr * v[j].y + hi * v[j].x;
+      }
+      sx += __shfl_xor(sx, 1, 64);
+      sy += __shfl_xor(sy, 1, 64);
+      sx += __shfl_xor(sx, 2, 64);
+      sy += __shfl_xor(sy, 2, 64);
+      wn = make_double2(wv.x + sx, wv.y + sy);
+      if (q == 0) w[p] = wn;
+    }
     if constexpr (DOT) {
 #pragma unroll
       for (int j = 0; j < NQ; ++j) {
@@ -523,26 +529,32 @@ void launch_multiaxpy(hipStream_t st, double2* w, const double2* V, int nv, size
   hipLaunchKernelGGL(multiaxpy_kernel, dim3(blas_blocks(n)), dim3(NT), 0, st, w, V, nv, n, vstride, h, sign);
 }
 
-template <bool DOT>
+template <bool DOT, bool UPD = true>
 static bool launch_axpy_reduce(hipStream_t st, double2* w, const double2* V, int nv, size_t n, size_t vstride,
                                const double* h, double sign, double* partial) {
   if (nv <= 0 || nv > 32) return false;
   const dim3 grid(blas_blocks(n)), block(NT);
   if (nv <= 4)
-    hipLaunchKernelGGL((axpy_reduce_kernel<1, DOT>), grid, block, 0, st, w, V, nv, n, vstride, h, sign, partial);
+    hipLaunchKernelGGL((axpy_reduce_kernel<1, DOT, UPD>), grid, block, 0, st, w, V, nv, n, vstride, h, sign,
+                       partial);
   else if (nv <= 8)
-    hipLaunchKernelGGL((axpy_reduce_kernel<2, DOT>), grid, block, 0, st, w, V, nv, n, vstride, h, sign, partial);
+    hipLaunchKernelGGL((axpy_reduce_kernel<2, DOT, UPD>), grid, block, 0, st, w, V, nv, n, vstride, h, sign,
+                       partial);
   else if (nv <= 16)
-    hipLaunchKernelGGL((axpy_reduce_kernel<4, DOT>), grid, block, 0, st, w, V, nv, n, vstride, h, sign, partial);
+    hipLaunchKernelGGL((axpy_reduce_kernel<4, DOT, UPD>), grid, block, 0, st, w, V, nv, n, vstride, h, sign,
+                       partial);
   else
-    hipLaunchKernelGGL((axpy_reduce_kernel<8, DOT>), grid, block, 0, st, w, V, nv, n, vstride, h, sign, partial);
+    hipLaunchKernelGGL((axpy_reduce_kernel<8, DOT, UPD>), grid, block, 0, st, w, V, nv, n, vstride, h, sign,
+                       partial);
   return true;
 }
 
 void launch_cgs2(hipStream_t st, const double2* V, int nv, size_t n, size_t vstride, double2* w, double* partial,
                  double* h1, double* h2, double* nrm2) {
   const int nb = blas_blocks(n);
-  launch_multidot(st, V, nv, n, vstride, w, partial);
+  // first pass: the quad-lane kernel without the update (w read once), else the multi-dot
+  if (!launch_axpy_reduce<true, false>(st, w, V, nv, n, vstride, nullptr, 0.0, partial))
+    launch_multidot(st, V, nv, n, vstride, w, partial);
   launch_reduce(st, partial, nb, 2 * nv, h1);
   if (launch_axpy_reduce<true>(st, w, V, nv, n, vstride, h1, -1.0, partial)) {
     launch_reduce(st, partial, nb, 2 * nv, h2);
