@@ -332,6 +332,31 @@ def test_fci_lockstep(ctx, prec):
     assert rel(host(out2), out) <= (1e-14 if prec == "f64" else 1e-6)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("max_steps", [1, 2])
+def test_fci_adaptive_stops_after_step_one(ctx, prec, max_steps):
+    # adaptive FCI where every pole stops after step one (max_steps 1) or after at most one
+    # later step: the quadrature combine must take those poles' iterate from y1, which step
+    # one writes instead of y; a zero right-hand side stops at the first test as well
+    shape = (10, 11, 12)
+    c = medium(shape, 19)
+    o, g = make_ops(ctx, c, 15.0, 3, 1.0)
+    poles = oracle_poles(o, 8, 1.0, 0.5, 8)
+    cg = gpu_contour(g, poles, 8, 8)
+    rng = np.random.default_rng(12)
+    f = rng.standard_normal((3,) + shape) + 1j * rng.standard_normal((3,) + shape)
+    f[1] = 0.0
+    opts = hf.default_opts(fp_steps=0, fp_reduce=5.0, fp_max_steps=max_steps,
+                           precision=64 if prec == "f64" else 32)
+    out, st = hf.fci_apply(g, cg, dev(f), opts)
+    out = host(out)
+    tol = 1e-12 if prec == "f64" else 2e-4
+    for r in (0, 2):
+        ref = OF.fci(o, f[r], poles, reduce=5.0, m_max=max_steps)
+        assert rel(out[r], ref) <= tol, (r, rel(out[r], ref))
+    assert np.abs(out[1]).max() == 0.0
+
+
 def test_solve_lockstep_fp64(ctx):
     wl = W.config_constant_32(n=16)
     o, g = make_ops(ctx, wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
