@@ -37,16 +37,18 @@ struct MultiFp {
   int count = 0, q = 0, cstride = 0, nsys = 0;
   std::vector<const Op*> ops;
   std::vector<const Contour*> cons;
-  std::vector<int> sys0, J, per_sys;  // per instance
+  std::vector<int> sys0, J, per_sys, per_sys_p;  // per instance (single-factor and pair tiles)
+  bool pairs = false;                 // factors two per pass (every instance supports it)
   std::vector<size_t> n;
   std::vector<int> slot_of;           // per system
   std::vector<T2*> f, y;              // per instance: f (n), y (J n)
   std::vector<MultiSys<T2>> h_sys;
-  std::vector<int2> h_seg;
+  std::vector<int2> h_seg, h_segp;
   std::vector<int> h_init;  // host sources of asynchronous copies live as long as the batch
   MultiInst* d_inst = nullptr;
   MultiSys<T2>* d_sys = nullptr;
   int2* d_seg = nullptr;
+  int2* d_segp = nullptr;
   int *active = nullptr, *steps = nullptr;
   double *rnorm2 = nullptr, *fnorm2 = nullptr, *fpart = nullptr, *dpart = nullptr;
   std::vector<double*> cc;            // per instance: sigma_j / z_j (device)
@@ -60,14 +62,20 @@ struct MultiFp {
     cstride = cons[0]->cstride;
     std::vector<MultiInst> h_inst(count);
     size_t npart = 0;
+    pairs = q >= 3;
     for (int i = 0; i < count; ++i) {
       h_inst[i] = MultiLaunch<T2>::describe(ops[i]->g, kappa_of<T2>(*ops[i]));
+      pairs = pairs && h_inst[i].pper_sys > 0;
+    }
+    for (int i = 0; i < count; ++i) {
       sys0.push_back(nsys);
       J.push_back(cons[i]->J);
       n.push_back(ops[i]->n);
       per_sys.push_back(h_inst[i].per_sys);
+      per_sys_p.push_back(h_inst[i].pper_sys);
       nsys += cons[i]->J;
-      npart += (size_t)cons[i]->J * h_inst[i].per_sys;
+      // residual partials: one per block of the launch that forms them (a pair when fusing)
+      npart += (size_t)cons[i]->J * (pairs ? h_inst[i].pper_sys : h_inst[i].per_sys);
       nb_max = std::max(nb_max, blas_blocks(ops[i]->n));
       nd_max = std::max(nd_max, Launch<T2>::partial_blocks(ops[i]->g));
     }
@@ -75,6 +83,7 @@ struct MultiFp {
     d_inst = (MultiInst*)ws.get("mb_inst", count * sizeof(MultiInst));
     d_sys = (MultiSys<T2>*)ws.get("mb_sys", nsys * sizeof(MultiSys<T2>));
     d_seg = (int2*)ws.get("mb_seg", nsys * sizeof(int2));
+    d_segp = (int2*)ws.get("mb_segp", nsys * sizeof(int2));
     active = (int*)ws.get("mb_active", nsys * sizeof(int));
     steps = (int*)ws.get("mb_steps", nsys * sizeof(int));
     rnorm2 = (double*)ws.get("mb_rnorm2", nsys * sizeof(double));
@@ -116,10 +125,10 @@ struct MultiFp {
         d.pole = cons[i]->d_poles + p;
         d.partial = part + poff;
         d.inst = i;
-        d.nblk = per_sys[i];
+        d.nblk = pairs ? per_sys_p[i] : per_sys[i];
         d.slot = i;
         d.pad = 0;
-        poff += per_sys[i];
+        poff += d.nblk;
         slot_of[G] = i;
       }
     }
@@ -128,18 +137,29 @@ struct MultiFp {
     HFCI_HIP(hipStreamSynchronize(s));
   }
 
-  // work table of the systems with hact[G] != 0; returns (segments, workgroups)
-  std::pair<int, int> upload_segments(const std::vector<int>& hact) {
+  // work tables of the systems with hact[G] != 0, for single-factor and pair launches
+  struct Tables {
+    int nseg, blocks, blocks_p;
+  };
+  Tables upload_segments(const std::vector<int>& hact) {
     h_seg.clear();
-    int blocks = 0;
+    h_segp.clear();
+    int blocks = 0, blocks_p = 0;
     for (int G = 0; G < nsys; ++G)
       if (hact[G]) {
         h_seg.push_back(int2{blocks, G});
         blocks += per_sys[slot_of[G]];
+        if (pairs) {
+          h_segp.push_back(int2{blocks_p, G});
+          blocks_p += per_sys_p[slot_of[G]];
+        }
       }
     if (!h_seg.empty())
       HFCI_HIP(hipMemcpyAsync(d_seg, h_seg.data(), h_seg.size() * sizeof(int2), hipMemcpyHostToDevice, ctx->stream));
-    return {(int)h_seg.size(), blocks};
+    if (!h_segp.empty())
+      HFCI_HIP(hipMemcpyAsync(d_segp, h_segp.data(), h_segp.size() * sizeof(int2), hipMemcpyHostToDevice,
+                              ctx->stream));
+    return Tables{(int)h_seg.size(), blocks, blocks_p};
   }
 
   // The fixed-point iteration of every system of the live instances (live[i] != 0) on
@@ -169,24 +189,54 @@ struct MultiFp {
     HFCI_HIP(hipMemcpyAsync(steps, h_init.data(), nsys * sizeof(int), hipMemcpyHostToDevice, s));
     auto sg = upload_segments(hact);
     const bool f64 = sizeof(T2) == 16;
-    auto launch = [&](int kind, int k, int rin, int rout, int rout2) {
-      MultiLaunch<T2>::factor(s, d_inst, d_sys, d_seg, sg.first, sg.second, kind, rin, rout, rout2, k, cstride, f64);
+    // one launch of `width` factors from coefficient k over the listed systems
+    auto launch = [&](int kind, int k, int width, int rin, int rout, int rout2) {
+      if (width == 2) {
+        const bool ok = MultiLaunch<T2>::factor_pair(s, d_inst, d_sys, d_segp, sg.nseg, sg.blocks_p, kind, rin, rout,
+                                                     rout2, k, cstride);
+        HFCI_REQUIRE(ok, "internal: unsupported factor kind");
+      } else {
+        MultiLaunch<T2>::factor(s, d_inst, d_sys, d_seg, sg.nseg, sg.blocks, kind, rin, rout, rout2, k, cstride, f64);
+      }
     };
+    struct Part {
+      int k, width, kind;
+    };
+    // launches of cnt factors from coefficient k0, two per pass when fusing; an odd count
+    // leaves one single launch, at the end or (single_first) at the start
+    auto plan = [&](int k0, int cnt, int kind_first, int kind_last, bool single_first) {
+      std::vector<Part> v;
+      for (int j = 0; j < cnt;) {
+        const bool lone = single_first && j == 0 && cnt % 2 == 1;
+        const int w = (pairs && j + 1 < cnt && !lone) ? 2 : 1;
+        int kind = 0;
+        if (j == 0) kind |= kind_first;
+        if (j + w == cnt) kind |= kind_last;
+        v.push_back(Part{k0 + j, w, kind});
+        j += w;
+      }
+      return v;
+    };
+    // step one: the max(q-1, 1) factors of P2 from f into y1 (and y)
     const int nP = std::max(q - 1, 1);
     {
+      const std::vector<Part> pl = plan(q, nP, kFacInF, kFacDual, true);
       int cur = kRoleF;
-      for (int j = 0; j < nP; ++j) {
-        const bool first = j == 0, last = j == nP - 1;
+      for (size_t i = 0; i < pl.size(); ++i) {
+        const bool last = i + 1 == pl.size();
         const int dst = last ? kRoleY1 : (cur == kRoleWA ? kRoleWB : kRoleWA);
-        launch((first ? kFacInF : 0) | (last ? kFacDual : 0), q + j, cur, dst, last ? kRoleY : kRoleNone);
+        launch(pl[i].kind, pl[i].k, pl[i].width, cur, dst, last ? kRoleY : kRoleNone);
         cur = dst;
       }
       st.matvecs += (long long)(q - 1) * nact;
       st.fp_steps += nact;
     }
+    // later steps: the first launch reads y and forms the residual partials, the last adds
+    // y1 into y; the launches in between ping-pong between wA and wB
+    const std::vector<Part> pl = plan(0, q, kFacResid, kFacAdd, false);
     for (int it = 1; it <= cap; ++it) {
       if (fixed && it == cap) break;
-      launch(kFacResid | (q == 1 ? kFacAdd : 0), 0, kRoleY, kRoleWA, kRoleNone);
+      launch(pl[0].kind, pl[0].k, pl[0].width, kRoleY, kRoleWA, kRoleNone);
       st.matvecs += nact;
       launch_fp_check_multi<T2>(s, d_sys, nsys, fnorm2, fixed_steps, reduce, max_steps, active, steps, rnorm2);
       if (!fixed) {
@@ -202,7 +252,7 @@ struct MultiFp {
       }
       st.matvecs += (long long)(q - 1) * nact;
       st.fp_steps += nact;
-      if (q == 1) {
+      if (pl.size() == 1) {  // a step of one launch went to wA
         for (int G = 0; G < nsys; ++G)
           if (hact[G])
             HFCI_HIP(hipMemcpyAsync(h_sys[G].vec[kRoleY], h_sys[G].vec[kRoleWA], n[slot_of[G]] * sizeof(T2),
@@ -210,12 +260,12 @@ struct MultiFp {
         continue;
       }
       int cur = kRoleWA;
-      for (int k = 1; k < q - 1; ++k) {
-        const int nxt = cur == kRoleWA ? kRoleWB : kRoleWA;
-        launch(0, k, cur, nxt, kRoleNone);
-        cur = nxt;
+      for (size_t i = 1; i < pl.size(); ++i) {
+        const bool last = i + 1 == pl.size();
+        const int dst = last ? kRoleY : (cur == kRoleWA ? kRoleWB : kRoleWA);
+        launch(pl[i].kind, pl[i].k, pl[i].width, cur, dst, kRoleNone);
+        cur = dst;
       }
-      launch(kFacAdd, q - 1, cur, kRoleY, kRoleNone);
     }
   }
 

@@ -96,6 +96,8 @@ struct MultiInst {
   GridDesc g;
   const void* kappa;  // float* or double*
   int gx, gy, nzc, czlen, xcd_slab, per_sys;
+  // the same for two factors per pass (64 x 12 tiles); pper_sys = 0 where it does not run
+  int pgx, pgy, pnzc, pczlen, pxcd_slab, pper_sys;
 };
 // Per shifted system (instance, pole): its vectors by role (0 f, 1 y, 2 y1, 3 wA, 4 wB),
 // the pole's factor coefficients and constants, its residual-partial row.
@@ -116,6 +118,10 @@ struct MultiLaunch {
   static void factor(hipStream_t st, const MultiInst* inst, const MultiSys<T2>* sys, const int2* seg, int nseg,
                      int nblocks, int kind, int role_in, int role_out, int role_out2, int k, int cstride,
                      bool f64);
+  // factors k and k + 1 in one pass over the work table of pair tiles (kind as for
+  // Launch::factor_pair); false for an unsupported kind
+  static bool factor_pair(hipStream_t st, const MultiInst* inst, const MultiSys<T2>* sys, const int2* seg, int nseg,
+                          int nblocks, int kind, int role_in, int role_out, int role_out2, int k, int cstride);
   // geometry of one instance for this launch shape (host)
   static MultiInst describe(const GridDesc& g, const void* kappa);
 };

@@ -415,9 +415,11 @@ constexpr int pair_waves_per_eu() {
   return (sizeof(T) == 4 && (KIND & (kFacResid | kFacAdd)) == 0) ? 8 : 1;
 }
 
+// The work of one block: tile b (of the gx x gy x nzc pair tiles of a system, per_sys in
+// all) of system s of the factor arguments.
 template <typename T, int KIND, int D>
-__global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(pair_waves_per_eu<T, KIND>()))) void zpair_kernel(GridDesc g, int nzc, int czlen, int xcd_slab,
-                                                    FactorArgs<typename V2<T>::t> a, const T* __restrict__ K) {
+__device__ __forceinline__ void pair_tile(const GridDesc& g, int czlen, int gx, int gy, int per_sys, int s, int b,
+                                          const FactorArgs<typename V2<T>::t>& a, const T* __restrict__ K) {
   using T2 = typename V2<T>::t;
   constexpr bool RESID = (KIND & kFacResid) != 0, ADD = (KIND & kFacAdd) != 0, DUAL = (KIND & kFacDual) != 0,
                  INF = (KIND & kFacInF) != 0;
@@ -426,12 +428,6 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(pair_waves_
   __shared__ T2 tr[4][PNT];    // first-factor planes, [row][col] as row * PEX + col (= tid)
   __shared__ double sh[PNT / 64];
   const int tid = threadIdx.x;
-  const int gx = (g.nx + PX - 1) / PX, gy = (g.ny + PY - 1) / PY;
-  const int per_sys = gx * gy * nzc;
-  const int s = a.list[blockIdx.x / per_sys];
-  if (s < 0) return;  // a stopped system past the end of the active list (uniform)
-  int b = blockIdx.x % per_sys;
-  if (xcd_slab > 0) b = (b % 8) * xcd_slab + b / 8;
   const int bx = b % gx, by = (b / gx) % gy, zc = b / (gx * gy);
   const int x0 = bx * PX, y0 = by * PY;
   const int zb = zc * czlen, ze = min(g.nz, zb + czlen);
@@ -620,6 +616,55 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(pair_waves_
     block_sum<PNT, 1>(v, sh);
     if (tid == 0) a.partial[(size_t)s * per_sys + (bx + gx * (by + gy * zc))] = v[0];
   }
+}
+
+template <typename T, int KIND, int D>
+__global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(pair_waves_per_eu<T, KIND>()))) void zpair_kernel(GridDesc g, int nzc, int czlen, int xcd_slab,
+                                                    FactorArgs<typename V2<T>::t> a, const T* __restrict__ K) {
+  const int gx = (g.nx + PX - 1) / PX, gy = (g.ny + PY - 1) / PY;
+  const int per_sys = gx * gy * nzc;
+  const int s = a.list[blockIdx.x / per_sys];
+  if (s < 0) return;  // a stopped system past the end of the active list (uniform)
+  int b = blockIdx.x % per_sys;
+  if (xcd_slab > 0) b = (b % 8) * xcd_slab + b / 8;
+  pair_tile<T, KIND, D>(g, czlen, gx, gy, per_sys, s, b, a, K);
+}
+
+// Uneven batches, two factors per pass: as zmulti_kernel, with the pair tile of the
+// block's system on its operator's pair geometry (pgx x pgy x pnzc tiles).
+template <typename T, int KIND>
+__global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(pair_waves_per_eu<T, KIND>()))) void zmulti_pair_kernel(
+    const MultiInst* __restrict__ inst, const MultiSys<typename V2<T>::t>* __restrict__ sys,
+    const int2* __restrict__ seg, int nseg, int rin, int rout, int rout2, int k, int cstride) {
+  using T2 = typename V2<T>::t;
+  const int blk = blockIdx.x;
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (seg[mid].x <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  const int G = seg[lo].y;
+  int local = blk - seg[lo].x;
+  const MultiSys<T2>* __restrict__ sd = sys + G;
+  const MultiInst id = inst[sd->inst];
+  if (id.pxcd_slab > 0) local = (local % 8) * id.pxcd_slab + local / 8;
+  FactorArgs<T2> a{};
+  a.win = sd->vec[rin];
+  a.f = sd->vec[kRoleF];
+  a.y1 = sd->vec[kRoleY1];
+  a.wout = sd->vec[rout];
+  a.wout2 = rout2 >= 0 ? sd->vec[rout2] : nullptr;
+  a.coef = sd->coef;
+  a.poles = sd->pole;
+  a.list = nullptr;
+  a.partial = sd->partial;
+  a.count = 1;
+  a.sys0 = 0;
+  a.nrhs = 1;
+  a.cstride = cstride;
+  a.k = k;
+  pair_tile<T, KIND, 1>(id.g, id.pczlen, id.pgx, id.pgy, id.pper_sys, 0, local, a, (const T*)id.kappa);
 }
 
 struct NoAux {};
@@ -1072,6 +1117,17 @@ MultiInst MultiLaunch<T2>::describe(const GridDesc& g0, const void* kappa) {
   m.czlen = sh.czlen;
   m.xcd_slab = sh.xcd_slab;
   m.per_sys = m.gx * m.gy * m.nzc;
+  // pair geometry (64 x 12 tiles, automatic z-chunks), when the pair kernel runs on this grid
+  m.pgx = m.pgy = m.pnzc = m.pczlen = m.pxcd_slab = m.pper_sys = 0;
+  if (Launch<T2>::pair_fits(g)) {
+    const PairShape p = pair_shape<T>(g);  // g carries cz = 0: automatic chunks
+    m.pgx = p.gx;
+    m.pgy = p.gy;
+    m.pnzc = p.nzc;
+    m.pczlen = p.czlen;
+    m.pxcd_slab = p.xcd_slab;
+    m.pper_sys = p.per_sys;
+  }
   return m;
 }
 
@@ -1102,6 +1158,34 @@ void MultiLaunch<T2>::factor(hipStream_t st, const MultiInst* inst, const MultiS
       break;
     default: break;
   }
+}
+
+template <typename T, int KIND, typename T2>
+void run_multi_pair(hipStream_t st, const MultiInst* inst, const MultiSys<T2>* sys, const int2* seg, int nseg,
+                    int nblocks, int rin, int rout, int rout2, int k, int cstride) {
+  hipLaunchKernelGGL((zmulti_pair_kernel<T, KIND>), dim3((unsigned)nblocks), dim3(PNT), 0, st, inst, sys, seg, nseg,
+                     rin, rout, rout2, k, cstride);
+}
+
+template <typename T2>
+bool MultiLaunch<T2>::factor_pair(hipStream_t st, const MultiInst* inst, const MultiSys<T2>* sys, const int2* seg,
+                                  int nseg, int nblocks, int kind, int rin, int rout, int rout2, int k, int cstride) {
+  using T = typename Scal<T2>::t;
+  if (nseg <= 0 || nblocks <= 0) return true;
+  switch (kind) {
+    case 0: run_multi_pair<T, 0>(st, inst, sys, seg, nseg, nblocks, rin, rout, rout2, k, cstride); break;
+    case kFacResid:
+      run_multi_pair<T, kFacResid>(st, inst, sys, seg, nseg, nblocks, rin, rout, rout2, k, cstride);
+      break;
+    case kFacInF: run_multi_pair<T, kFacInF>(st, inst, sys, seg, nseg, nblocks, rin, rout, rout2, k, cstride); break;
+    case kFacAdd: run_multi_pair<T, kFacAdd>(st, inst, sys, seg, nseg, nblocks, rin, rout, rout2, k, cstride); break;
+    case kFacDual: run_multi_pair<T, kFacDual>(st, inst, sys, seg, nseg, nblocks, rin, rout, rout2, k, cstride); break;
+    case kFacInF | kFacDual:
+      run_multi_pair<T, kFacInF | kFacDual>(st, inst, sys, seg, nseg, nblocks, rin, rout, rout2, k, cstride);
+      break;
+    default: return false;
+  }
+  return true;
 }
 
 template <typename T2>

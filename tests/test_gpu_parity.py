@@ -477,9 +477,12 @@ def _batch_instances(ctx, shapes, q, seed=50):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_shifted_solve_batch_matches_oracle(ctx, prec):
+@pytest.mark.parametrize("q", [3, 4, 5, 8])
+def test_shifted_solve_batch_matches_oracle(ctx, prec, q):
+    # one launch per factor (two per pass for q >= 3) over every instance's poles: step one
+    # with a lone first factor (odd q - 1) or all pairs, later steps with a trailing single
+    # (odd q) or all pairs
     shapes = [(9, 12, 20), (16, 16, 16), (7, 10, 70), (12, 5, 9)]
-    q = 4
     inst = _batch_instances(ctx, shapes, q)
     rng = np.random.default_rng(51)
     fs = [rng.standard_normal(sh) + 1j * rng.standard_normal(sh) for sh in shapes]
