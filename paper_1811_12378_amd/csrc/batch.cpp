@@ -49,6 +49,7 @@ struct MultiFp {
   MultiSys<T2>* d_sys = nullptr;
   int2* d_seg = nullptr;
   int2* d_segp = nullptr;
+  int2* d_bps = nullptr;              // per system: {single-factor, pair} blocks
   int *active = nullptr, *steps = nullptr;
   double *rnorm2 = nullptr, *fnorm2 = nullptr, *fpart = nullptr, *dpart = nullptr;
   std::vector<double*> cc;            // per instance: sigma_j / z_j (device)
@@ -82,8 +83,9 @@ struct MultiFp {
     Workspace& ws = ctx->ws;
     d_inst = (MultiInst*)ws.get("mb_inst", count * sizeof(MultiInst));
     d_sys = (MultiSys<T2>*)ws.get("mb_sys", nsys * sizeof(MultiSys<T2>));
-    d_seg = (int2*)ws.get("mb_seg", nsys * sizeof(int2));
-    d_segp = (int2*)ws.get("mb_segp", nsys * sizeof(int2));
+    d_seg = (int2*)ws.get("mb_seg", (nsys + 1) * sizeof(int2));
+    d_segp = (int2*)ws.get("mb_segp", (nsys + 1) * sizeof(int2));
+    d_bps = (int2*)ws.get("mb_bps", nsys * sizeof(int2));
     active = (int*)ws.get("mb_active", nsys * sizeof(int));
     steps = (int*)ws.get("mb_steps", nsys * sizeof(int));
     rnorm2 = (double*)ws.get("mb_rnorm2", nsys * sizeof(double));
@@ -134,13 +136,29 @@ struct MultiFp {
     }
     HFCI_HIP(hipMemcpyAsync(d_inst, h_inst.data(), count * sizeof(MultiInst), hipMemcpyHostToDevice, s));
     HFCI_HIP(hipMemcpyAsync(d_sys, h_sys.data(), nsys * sizeof(MultiSys<T2>), hipMemcpyHostToDevice, s));
+    std::vector<int2> h_bps(nsys);
+    for (int G = 0; G < nsys; ++G)
+      h_bps[G] = int2{per_sys[slot_of[G]], pairs ? per_sys_p[slot_of[G]] : 0};
+    HFCI_HIP(hipMemcpyAsync(d_bps, h_bps.data(), nsys * sizeof(int2), hipMemcpyHostToDevice, s));
     HFCI_HIP(hipStreamSynchronize(s));
   }
 
-  // work tables of the systems with hact[G] != 0, for single-factor and pair launches
+  // Launch bounds of the systems with hact[G] != 0: rows to search (the live rows and
+  // the sentinel) and blocks of single-factor and pair launches.
   struct Tables {
     int nseg, blocks, blocks_p;
   };
+  Tables bounds(const std::vector<int>& hact) const {
+    Tables t{1, 0, 0};
+    for (int G = 0; G < nsys; ++G)
+      if (hact[G]) {
+        ++t.nseg;
+        t.blocks += per_sys[slot_of[G]];
+        if (pairs) t.blocks_p += per_sys_p[slot_of[G]];
+      }
+    return t;
+  }
+  // the work tables of those systems, each ending in its sentinel {total blocks, -1}
   Tables upload_segments(const std::vector<int>& hact) {
     h_seg.clear();
     h_segp.clear();
@@ -148,17 +166,15 @@ struct MultiFp {
     for (int G = 0; G < nsys; ++G)
       if (hact[G]) {
         h_seg.push_back(int2{blocks, G});
+        h_segp.push_back(int2{blocks_p, G});
         blocks += per_sys[slot_of[G]];
-        if (pairs) {
-          h_segp.push_back(int2{blocks_p, G});
-          blocks_p += per_sys_p[slot_of[G]];
-        }
+        if (pairs) blocks_p += per_sys_p[slot_of[G]];
       }
-    if (!h_seg.empty())
-      HFCI_HIP(hipMemcpyAsync(d_seg, h_seg.data(), h_seg.size() * sizeof(int2), hipMemcpyHostToDevice, ctx->stream));
-    if (!h_segp.empty())
-      HFCI_HIP(hipMemcpyAsync(d_segp, h_segp.data(), h_segp.size() * sizeof(int2), hipMemcpyHostToDevice,
-                              ctx->stream));
+    h_seg.push_back(int2{blocks, -1});
+    h_segp.push_back(int2{blocks_p, -1});
+    HFCI_HIP(hipMemcpyAsync(d_seg, h_seg.data(), h_seg.size() * sizeof(int2), hipMemcpyHostToDevice, ctx->stream));
+    HFCI_HIP(hipMemcpyAsync(d_segp, h_segp.data(), h_segp.size() * sizeof(int2), hipMemcpyHostToDevice,
+                            ctx->stream));
     return Tables{(int)h_seg.size(), blocks, blocks_p};
   }
 
@@ -234,6 +250,50 @@ struct MultiFp {
     // later steps: the first launch reads y and forms the residual partials, the last adds
     // y1 into y; the launches in between ping-pong between wA and wB
     const std::vector<Part> pl = plan(0, q, kFacResid, kFacAdd, false);
+    auto rest = [&]() {
+      int cur = kRoleWA;
+      for (size_t i = 1; i < pl.size(); ++i) {
+        const bool last = i + 1 == pl.size();
+        const int dst = last ? kRoleY : (cur == kRoleWA ? kRoleWB : kRoleWA);
+        launch(pl[i].kind, pl[i].k, pl[i].width, cur, dst, kRoleNone);
+        cur = dst;
+      }
+    };
+    if (!fixed && pl.size() > 1 && nsys <= kPinnedIntHalf) {
+      // Adaptive, pipelined as the single-operator loop: the stopping test rebuilds the
+      // work tables on the device, so the rest of step `it` and the head of step it + 1
+      // are queued before the host reads step it's flags.  Their launches are sized for
+      // the systems active after the previous test (a superset; surplus blocks meet the
+      // sentinel and exit).  Flags alternate between the halves of the pinned buffer.
+      hipEvent_t ev[2] = {ctx->step_event[0], ctx->step_event[1]};
+      int* flags[2] = {ctx->pinned_int, ctx->pinned_int + kPinnedIntHalf};
+      int* flags_dev[2] = {ctx->pinned_int_dev, ctx->pinned_int_dev + kPinnedIntHalf};
+      auto head_to = [&](int slot) {
+        launch(pl[0].kind, pl[0].k, pl[0].width, kRoleY, kRoleWA, kRoleNone);
+        launch_fp_test_multi<T2>(s, d_sys, nsys, d_bps, fnorm2, reduce, max_steps, active, steps, rnorm2, d_seg,
+                                 d_segp, flags_dev[slot]);
+        HFCI_HIP(hipEventRecord(ev[slot], s));
+      };
+      head_to(0);
+      st.matvecs += nact;
+      int slot = 0;
+      for (int it = 1; it <= cap; ++it) {
+        rest();
+        head_to(slot ^ 1);
+        HFCI_HIP(hipEventSynchronize(ev[slot]));
+        nact = 0;
+        for (int G = 0; G < nsys; ++G) {
+          hact[G] = flags[slot][G] != 0;
+          nact += hact[G];
+        }
+        st.matvecs += (long long)q * nact;  // the rest of step it and the head of step it + 1
+        st.fp_steps += nact;
+        if (nact == 0) break;  // the queued launches found only the sentinel
+        sg = bounds(hact);
+        slot ^= 1;
+      }
+      return;
+    }
     for (int it = 1; it <= cap; ++it) {
       if (fixed && it == cap) break;
       launch(pl[0].kind, pl[0].k, pl[0].width, kRoleY, kRoleWA, kRoleNone);
@@ -259,13 +319,7 @@ struct MultiFp {
                                     hipMemcpyDeviceToDevice, s));
         continue;
       }
-      int cur = kRoleWA;
-      for (size_t i = 1; i < pl.size(); ++i) {
-        const bool last = i + 1 == pl.size();
-        const int dst = last ? kRoleY : (cur == kRoleWA ? kRoleWB : kRoleWA);
-        launch(pl[i].kind, pl[i].k, pl[i].width, cur, dst, kRoleNone);
-        cur = dst;
-      }
+      rest();
     }
   }
 

@@ -4,6 +4,8 @@
 // partial per block (wavefront shuffle tree, then 4 waves through LDS), and a second
 // kernel sums the partials of each component in a fixed order.  No floating-point
 // atomics, so FP64 results are bit-reproducible run to run.
+#include <climits>
+
 #include "kernels.h"
 
 namespace hfci {
@@ -455,6 +457,87 @@ __global__ __launch_bounds__(NT) void fp_check_multi_kernel(const MultiSys<T2>* 
   }
 }
 
+// Adaptive stopping test of a batch with the work tables rebuilt on the device (one
+// block): wave w decides systems w, w + 16, ... as fp_check_multi_kernel does; then the
+// active systems, in increasing order, get their rows {first block, system} of the
+// single-factor table (seg, bps[s].x blocks each) and of the pair table (segp, bps[s].y
+// blocks).  Exclusive prefix sums run per chunk of FTT systems: ballots give the row,
+// shuffle scans the first blocks, LDS carries the wave totals.  Row `count` of each table
+// is the sentinel {total blocks, -1}, the rows after it {INT_MAX, -1}: a launch sized for
+// an earlier, larger set of systems searches past the live rows and its surplus blocks
+// land on the sentinel and exit.  The flags also go to host_flags (pinned host memory).
+template <typename T2>
+__global__ __launch_bounds__(FTT) void fp_test_multi_kernel(const MultiSys<T2>* __restrict__ sys, int nsys,
+                                                            const int2* __restrict__ bps,
+                                                            const double* __restrict__ fnorm2, double inv_reduce2,
+                                                            int max_steps, int* __restrict__ active,
+                                                            int* __restrict__ steps, double* __restrict__ rnorm2,
+                                                            int2* __restrict__ seg, int2* __restrict__ segp,
+                                                            int* __restrict__ host_flags) {
+  __shared__ int wtot[3][FTT / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int s = wid; s < nsys; s += FTT / 64) {
+    if (active[s] == 0) continue;  // stopped earlier: its partial row was not written
+    const MultiSys<T2>& sd = sys[s];
+    double v = 0.0;
+    for (int i = lane; i < sd.nblk; i += 64) v += sd.partial[i];
+    v = wave_sum(v);
+    if (lane == 0) {
+      const double r2 = v;
+      rnorm2[s] = r2;
+      int act = (r2 > fnorm2[sd.slot] * inv_reduce2) && (steps[s] < max_steps);
+      if (!(r2 == r2) || r2 > 1e300) act = 0;
+      active[s] = act;
+      if (act) steps[s] += 1;
+    }
+  }
+  __syncthreads();
+  int base = 0, bbase = 0, pbase = 0;
+  for (int c0 = 0; c0 < nsys; c0 += FTT) {
+    const int s = c0 + threadIdx.x;
+    const bool a = s < nsys && active[s] != 0;
+    if (s < nsys) host_flags[s] = a ? 1 : 0;
+    const int2 w = a ? bps[s] : make_int2(0, 0);
+    const unsigned long long m = __ballot(a);
+    const int below = __popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+    int ib = w.x, ip = w.y;  // inclusive scans within the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int tb = __shfl_up(ib, o, 64), tp = __shfl_up(ip, o, 64);
+      if (lane >= o) {
+        ib += tb;
+        ip += tp;
+      }
+    }
+    if (lane == 63) {
+      wtot[0][wid] = __popcll(m);
+      wtot[1][wid] = ib;
+      wtot[2][wid] = ip;
+    }
+    __syncthreads();
+    int off = base, boff = bbase, poff = pbase;
+    for (int v = 0; v < wid; ++v) {
+      off += wtot[0][v];
+      boff += wtot[1][v];
+      poff += wtot[2][v];
+    }
+    if (a) {
+      seg[off + below] = make_int2(boff + ib - w.x, s);
+      segp[off + below] = make_int2(poff + ip - w.y, s);
+    }
+    for (int v = 0; v < FTT / 64; ++v) {
+      base += wtot[0][v];
+      bbase += wtot[1][v];
+      pbase += wtot[2][v];
+    }
+    __syncthreads();
+  }
+  for (int r = base + threadIdx.x; r <= nsys; r += FTT) {
+    seg[r] = make_int2(r == base ? bbase : INT_MAX, -1);
+    segp[r] = make_int2(r == base ? pbase : INT_MAX, -1);
+  }
+}
+
 __global__ void dfinish_kernel(const double* __restrict__ sums, int nrhs, double* __restrict__ d) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < nrhs) {
@@ -637,6 +720,19 @@ template void launch_fp_check_multi<float2>(hipStream_t, const MultiSys<float2>*
                                             int*, int*, double*);
 template void launch_fp_check_multi<double2>(hipStream_t, const MultiSys<double2>*, int, const double*, int, double,
                                              int, int*, int*, double*);
+
+template <typename T2>
+void launch_fp_test_multi(hipStream_t st, const MultiSys<T2>* sys, int nsys, const int2* bps, const double* fnorm2,
+                          double reduce, int max_steps, int* active, int* steps, double* rnorm2, int2* seg,
+                          int2* segp, int* host_flags) {
+  if (nsys > 0)
+    hipLaunchKernelGGL(fp_test_multi_kernel<T2>, dim3(1), dim3(FTT), 0, st, sys, nsys, bps, fnorm2,
+                       1.0 / (reduce * reduce), max_steps, active, steps, rnorm2, seg, segp, host_flags);
+}
+template void launch_fp_test_multi<float2>(hipStream_t, const MultiSys<float2>*, int, const int2*, const double*,
+                                           double, int, int*, int*, double*, int2*, int2*, int*);
+template void launch_fp_test_multi<double2>(hipStream_t, const MultiSys<double2>*, int, const int2*, const double*,
+                                            double, int, int*, int*, double*, int2*, int2*, int*);
 
 void launch_dfinish(hipStream_t st, const double* sums, int nrhs, double* d) {
   hipLaunchKernelGGL(dfinish_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, sums, nrhs, d);

@@ -111,7 +111,8 @@ struct MultiSys {
   int inst, nblk, slot, pad;
 };
 // One factor launch over the systems listed in the work table seg[i] = {first block,
-// system}, ascending in the first block; a block finds its system by binary search.
+// system}, ascending in the first block; a block finds its system by binary search over
+// the nseg rows.  A row with system -1 is a sentinel: blocks that land on it exit.
 template <typename T2>
 struct MultiLaunch {
   static constexpr int kTy = 8, kPd = 2;  // launch shape of the multi-instance kernel
@@ -130,6 +131,14 @@ struct MultiLaunch {
 template <typename T2>
 void launch_fp_check_multi(hipStream_t st, const MultiSys<T2>* sys, int nsys, const double* fnorm2,
                            int fixed_steps, double reduce, int max_steps, int* active, int* steps, double* rnorm2);
+// adaptive test of a batch that also rebuilds the work tables on the device: rows
+// {first block, system} of the active systems in seg (bps[s].x blocks each) and segp
+// (bps[s].y), then the sentinel {total, -1} and {INT_MAX, -1} up to row nsys; the flags
+// also go to host_flags (device-visible pinned host memory, nsys ints)
+template <typename T2>
+void launch_fp_test_multi(hipStream_t st, const MultiSys<T2>* sys, int nsys, const int2* bps, const double* fnorm2,
+                          double reduce, int max_steps, int* active, int* steps, double* rnorm2, int2* seg,
+                          int2* segp, int* host_flags);
 
 // FP64 residual r = b - A u (shift 0) with partial sums of |r|^2.
 void launch_residual64(hipStream_t st, const GridDesc& g, const double* kappa, const double2* b,

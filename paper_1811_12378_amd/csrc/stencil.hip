@@ -645,6 +645,7 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(pair_waves_
     else hi = mid - 1;
   }
   const int G = seg[lo].y;
+  if (G < 0) return;  // past the live rows of a table rebuilt since the launch was sized
   int local = blk - seg[lo].x;
   const MultiSys<T2>* __restrict__ sd = sys + G;
   const MultiInst id = inst[sd->inst];
@@ -887,6 +888,7 @@ __global__ __launch_bounds__(TX * TY) void zmulti_kernel(const MultiInst* __rest
     else hi = mid - 1;
   }
   const int G = seg[lo].y;
+  if (G < 0) return;  // past the live rows of a table rebuilt since the launch was sized
   int local = b - seg[lo].x;
   // fields are read through the pointer: a dynamic index into a copied descriptor
   // (vec[role]) would put the copy in scratch memory

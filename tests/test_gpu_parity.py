@@ -477,11 +477,12 @@ def _batch_instances(ctx, shapes, q, seed=50):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("q", [3, 4, 5, 8])
+@pytest.mark.parametrize("q", [2, 3, 4, 5, 8])
 def test_shifted_solve_batch_matches_oracle(ctx, prec, q):
     # one launch per factor (two per pass for q >= 3) over every instance's poles: step one
     # with a lone first factor (odd q - 1) or all pairs, later steps with a trailing single
-    # (odd q) or all pairs
+    # (odd q) or all pairs; the adaptive run stops systems at different steps, so the
+    # pipelined steps launch past the live rows of the rebuilt work tables
     shapes = [(9, 12, 20), (16, 16, 16), (7, 10, 70), (12, 5, 9)]
     inst = _batch_instances(ctx, shapes, q)
     rng = np.random.default_rng(51)
