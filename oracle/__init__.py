@@ -21,9 +21,12 @@ using contour integration and polynomial preconditioning") step by step:
   fci        -- Algorithm 1 (FCI).
   krylov     -- flexible GMRES (the Krylov wrapper of Sec. 2) with classical
                 Gram-Schmidt applied twice and Givens rotations; plain GMRES.
+  case_two   -- the double-size formulation of eq. mat-2x2 (B = iC - I), its
+                spectrum box from Thm 3.2 and the remark after it, and FGMRES
+                with FCI on it.
   conv       -- direct-loop 3D convolution forward/backward for the learned
                 preconditioner extension (not part of the paper).
 
 Parity status of each function is stated in its module header.
 """
-from . import operator, contour, polynomial, fixed_point, fci, krylov, conv  # noqa: F401
+from . import operator, contour, polynomial, fixed_point, fci, krylov, conv, case_two  # noqa: F401
