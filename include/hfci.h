@@ -218,6 +218,21 @@ hfci_status hfci_op_autotune(hfci_op* op, int prec, int nsys, int* best5, double
 hfci_status hfci_apply(const hfci_op* op, hfci_c128 shift, int prec, int nvec,
                        const void* x, void* y);
 
+/* ---- case two: the double-size formulation (Sec. 3, eq. mat-2x2) -----------
+ * Creates a second operator handle for B = iC - I, C = [[0, I], [-(A1 + I), -A2]],
+ * built on op's A = A1 - i A2 (A1 = S - M, A2 = D).  Solving B [x1; x2] = [0; f] gives
+ * x2 = u and x1 = i u with A u = f.  Vectors of B hold 2n complex values: x1 (n, x
+ * fastest) then x2 (n).  Its spectrum box, reported by hfci_op_info as [b1, b2] (rho2
+ * unchanged), is [-1 - R, -1 + R] x [-rho2, 0] with R = rho2/2 + sqrt(rho2^2/4 + rho1)
+ * and rho1 = b2 + 1 from op's box (Thm 3.2 and the remark after it).
+ * On the returned handle: hfci_op_info, hfci_op_get_tune, hfci_apply ((B - shift) x),
+ * hfci_contour_create / hfci_contour_get (poles and delta for B's box) and
+ * hfci_shifted_solve (vectors of 2n values; one launch per fixed-point factor, every
+ * shifted system in one grid).  The other entry points return HFCI_E_STATE for it.
+ * The handle copies op's medium (op may be destroyed first); release it with
+ * hfci_op_destroy.  Errors: HFCI_E_ARG, HFCI_E_STATE (op is itself a case-two handle). */
+hfci_status hfci_op_case_two(const hfci_op* op, hfci_op** out);
+
 /* ---- contour and per-pole parameters (Sec. 6.1-6.2, Sec. 4.2) -------------
  * J poles on the shifted-centre ellipse of eq. quad-points with radius
  * r = (rho2/2 + eps)/sin(pi/J) (eq. quad-radius), weights

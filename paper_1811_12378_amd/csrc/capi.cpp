@@ -345,6 +345,46 @@ hfci_status hfci_op_create(hfci_ctx* ctx, int nx, int ny, int nz, double h, cons
   HFCI_API_END
 }
 
+// Entry points that run the case-one kernels only.
+static void require_case_one(const hfci::Op* op) {
+  if (op && op->form != 1) throw Error(HFCI_E_STATE, "not available for a case-two operator");
+}
+
+hfci_status hfci_op_case_two(const hfci_op* op, hfci_op** out) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(op && out, "NULL argument");
+  *out = nullptr;
+  require_case_one(op);
+  DeviceGuard dg(op->ctx->device);
+  const size_t npt = op->n;
+  hfci_op* o2 = new hfci_op();
+  try {
+    static_cast<Op&>(*o2) = static_cast<const Op&>(*op);
+    o2->kappa64 = nullptr;
+    o2->kappa32 = nullptr;
+    o2->form = 2;
+    o2->n = 2 * npt;
+    // Thm 3.2 and the remark after it: spec(B) in |mu + 1| <= R, Im mu in [-rho2, 0],
+    // R = rho2/2 + sqrt(rho2^2/4 + rho1), rho1 = rho(A1 + I) <= b2 + 1
+    const double rho1 = op->b2 + 1.0;
+    const double R = 0.5 * op->rho2 + std::sqrt(0.25 * op->rho2 * op->rho2 + rho1);
+    o2->b1 = -1.0 - R;
+    o2->b2 = -1.0 + R;
+    HFCI_HIP(hipMalloc(&o2->kappa64, npt * sizeof(double)));
+    HFCI_HIP(hipMalloc(&o2->kappa32, npt * sizeof(float)));
+    HFCI_HIP(hipMemcpy(o2->kappa64, op->kappa64, npt * sizeof(double), hipMemcpyDeviceToDevice));
+    HFCI_HIP(hipMemcpy(o2->kappa32, op->kappa32, npt * sizeof(float), hipMemcpyDeviceToDevice));
+  } catch (...) {
+    if (o2->kappa64) (void)hipFree(o2->kappa64);
+    if (o2->kappa32) (void)hipFree(o2->kappa32);
+    delete o2;
+    throw;
+  }
+  *out = o2;
+  return HFCI_OK;
+  HFCI_API_END
+}
+
 void hfci_op_destroy(hfci_op* op) {
   if (!op) return;
   int prev = -1;
@@ -375,6 +415,7 @@ hfci_status hfci_op_info(const hfci_op* op, double* o) {
 hfci_status hfci_op_set_tune(hfci_op* op, int prec, const int* t3) {
   HFCI_API_BEGIN
   HFCI_REQUIRE(op && t3, "NULL argument");
+  require_case_one(op);
   HFCI_REQUIRE(prec == HFCI_F32 || prec == HFCI_F64, "prec must be HFCI_F32 or HFCI_F64");
   KernelTune t;
   t.kern = t3[0];
@@ -406,6 +447,7 @@ hfci_status hfci_op_get_tune(const hfci_op* op, int prec, int* t3) {
 hfci_status hfci_op_autotune(hfci_op* op, int prec, int nsys, int* best5, double* timings, int cap, int* count) {
   HFCI_API_BEGIN
   HFCI_REQUIRE(op, "NULL operator");
+  require_case_one(op);
   HFCI_REQUIRE(prec == HFCI_F32 || prec == HFCI_F64, "prec must be HFCI_F32 or HFCI_F64");
   HFCI_REQUIRE(nsys >= 1 && nsys <= 64, "nsys must be in [1, 64]");
   HFCI_REQUIRE(cap >= 0 && (cap == 0 || timings != nullptr), "timings is NULL");
@@ -448,7 +490,11 @@ hfci_status hfci_apply(const hfci_op* op, hfci_c128 shift, int prec, int nvec, c
   const double e = prec == HFCI_F64 ? 16.0 : 8.0;
   const bool timed = pr.sample(HFCI_PROF_APPLY);
   if (timed) pr.begin(s);
-  if (prec == HFCI_F64)
+  if (op->form == 2 && prec == HFCI_F64)
+    launch_b2_apply<double2>(s, op->g, op->kappa64, nvec, (const double2*)x, (double2*)y, shift.re, shift.im);
+  else if (op->form == 2)
+    launch_b2_apply<float2>(s, op->g, op->kappa32, nvec, (const float2*)x, (float2*)y, shift.re, shift.im);
+  else if (prec == HFCI_F64)
     Launch<double2>::apply(s, op->g, op->kappa64, shift.re, shift.im, nvec, (const double2*)x, (double2*)y);
   else
     Launch<float2>::apply(s, op->g, op->kappa32, shift.re, shift.im, nvec, (const float2*)x, (float2*)y);
@@ -574,7 +620,13 @@ hfci_status hfci_shifted_solve(const hfci_op* op, const hfci_contour* c, int pre
   HFCI_REQUIRE(steps > 0 || (reduce > 1.0 && max_steps >= 1), "give steps > 0, or reduce > 1 and max_steps >= 1");
   DeviceGuard dg(op->ctx->device);
   FciStats st;
-  if (prec == HFCI_F64)
+  if (op->form == 2 && prec == HFCI_F64)
+    shifted_solve_case_two<double2>(*op, *c, nrhs, (const double2*)f, (double2*)y, steps, reduce, max_steps,
+                                    steps_taken, st);
+  else if (op->form == 2)
+    shifted_solve_case_two<float2>(*op, *c, nrhs, (const float2*)f, (float2*)y, steps, reduce, max_steps,
+                                   steps_taken, st);
+  else if (prec == HFCI_F64)
     shifted_solve_batch<double2>(*op, *c, nrhs, (const double2*)f, (double2*)y, steps, reduce, max_steps,
                                  steps_taken, st);
   else
@@ -594,6 +646,7 @@ static void check_batch(int count, const hfci_op* const* ops, const hfci_contour
   long nsys = 0;
   for (int i = 0; i < count; ++i) {
     HFCI_REQUIRE(ops[i] != nullptr, "NULL operator in the batch");
+    require_case_one(ops[i]);
     if (ops[i]->ctx != ops[0]->ctx) throw Error(HFCI_E_STATE, "operators of a batch must share one context");
     vo.push_back(ops[i]);
     if (need_cons) {
@@ -676,6 +729,7 @@ hfci_status hfci_fci_apply(const hfci_op* op, const hfci_contour* c, const hfci_
                            const hfci_c128* f, hfci_c128* out, hfci_stats* stats) {
   HFCI_API_BEGIN
   HFCI_REQUIRE(op && c && f && out, "NULL argument");
+  require_case_one(op);
   if (c->op != op) throw Error(HFCI_E_STATE, "contour was created for another operator");
   check_opts(o);
   HFCI_REQUIRE(nrhs >= 1 && (long)nrhs * c->J <= 65536, "nrhs out of range");
@@ -698,6 +752,7 @@ hfci_status hfci_solve(const hfci_op* op, const hfci_contour* c, const hfci_solv
                        const hfci_c128* f, hfci_c128* u, hfci_stats* stats) {
   HFCI_API_BEGIN
   HFCI_REQUIRE(op && f && u, "NULL argument");
+  require_case_one(op);
   check_opts(o);
   if (o->precond == HFCI_PRECOND_FCI || o->precond == HFCI_PRECOND_LEARNED) {
     HFCI_REQUIRE(c != nullptr, "FCI preconditioning (or its use as the learned fallback) needs a contour");

@@ -1,0 +1,217 @@
+// Case two (Sec. 3, eq. mat-2x2): the double-size operator B = iC - I with
+// C = [[0, I], [-(A1 + I), -A2]], A = A1 - i A2, A1 = S - M, A2 = D.  Written out,
+//   B [x1; x2] = [ -x1 + i x2 ;  -i (A1 + I) x1 - (I + i A2) x2 ],
+// one 7-point stencil on x1 plus pointwise terms.  A vector of B holds x1 (n values)
+// then x2 (n values), n the grid points.
+//
+// Kernels: one factor of the product-form fixed-point step (eq. fix-pt-exp, as the
+// factors of params.cpp) over all shifted systems, w_out = a (B - z0) w + b w with the
+// epilogues of the case-one kernels (residual partials, adding y1, a second output),
+// and the plain product (B - shift) x.  One thread per grid point and both blocks; the
+// neighbours of x1 come through the cache (no LDS staging: a single-factor kernel).
+#include "kernels.h"
+
+namespace hfci {
+namespace {
+
+constexpr int NT = 256;
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using t = float2; };
+template <> struct Vec2<double> { using t = double2; };
+template <typename T2> struct Scal;
+template <> struct Scal<float2> { using t = float; };
+template <> struct Scal<double2> { using t = double; };
+
+__device__ __forceinline__ int depth_in_layer(int i, int n, int L) { return max(0, L - min(i, n - 1 - i)); }
+
+template <typename T>
+struct Cx {
+  T x, y;
+};
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(T ar, T ai, Cx<T> v) {
+  return Cx<T>{ar * v.x - ai * v.y, ar * v.y + ai * v.x};
+}
+
+// (B - z0) x at point p = i + nx (j + ny k) of the vector x (x1 at x, x2 at x + npt);
+// also returns the point's x1 and x2.
+template <typename T, typename T2>
+__device__ __forceinline__ void b2_point(const GridDesc& g, const T* __restrict__ K, const T2* __restrict__ x,
+                                         size_t npt, size_t p, int i, int j, int k, T z0r, T z0i, Cx<T>& o1,
+                                         Cx<T>& o2, Cx<T>& x1, Cx<T>& x2) {
+  const size_t sx = 1, sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const T2 c = x[p];
+  x1 = Cx<T>{c.x, c.y};
+  const T2 c2 = x[npt + p];
+  x2 = Cx<T>{c2.x, c2.y};
+  T nr = (T)0, ni = (T)0;
+  if (i > 0) { const T2 v = x[p - sx]; nr += v.x; ni += v.y; }
+  if (i + 1 < g.nx) { const T2 v = x[p + sx]; nr += v.x; ni += v.y; }
+  if (j > 0) { const T2 v = x[p - sy]; nr += v.x; ni += v.y; }
+  if (j + 1 < g.ny) { const T2 v = x[p + sy]; nr += v.x; ni += v.y; }
+  if (k > 0) { const T2 v = x[p - sz]; nr += v.x; ni += v.y; }
+  if (k + 1 < g.nz) { const T2 v = x[p + sz]; nr += v.x; ni += v.y; }
+  const T sh2 = (T)g.s_h2, kap = K[p];
+  // (A1 + I) x1 = s/h^2 (6 x1 - neighbours) - kappa x1 + x1
+  const T ar = sh2 * ((T)6 * x1.x - nr) + ((T)1 - kap) * x1.x;
+  const T ai = sh2 * ((T)6 * x1.y - ni) + ((T)1 - kap) * x1.y;
+  const int d = max(max(depth_in_layer(i, g.nx, g.damp_cells), depth_in_layer(j, g.ny, g.damp_cells)),
+                    depth_in_layer(k, g.nz, g.damp_cells));
+  const T dmp = (T)(d * d) * (T)g.damp_scale;
+  const Cx<T> s1 = cmul((T)1 + z0r, z0i, x1), s2 = cmul((T)1 + z0r, z0i, x2);
+  // block 1: -(1 + z0) x1 + i x2
+  o1 = Cx<T>{-s1.x - x2.y, -s1.y + x2.x};
+  // block 2: -i (A1 + I) x1 - (1 + z0) x2 - i D x2
+  o2 = Cx<T>{ai - s2.x + dmp * x2.y, -ar - s2.y - dmp * x2.x};
+}
+
+__device__ __forceinline__ double block_sum_nt(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NT / 64; ++w) t += sh[w];
+  return t;
+}
+
+template <typename T, int KIND>
+__global__ __launch_bounds__(NT) void b2_factor_kernel(GridDesc g, const T* __restrict__ K,
+                                                       B2Args<typename Vec2<T>::t> a) {
+  using T2 = typename Vec2<T>::t;
+  constexpr bool RESID = (KIND & kFacResid) != 0, ADD = (KIND & kFacAdd) != 0, DUAL = (KIND & kFacDual) != 0,
+                 INF = (KIND & kFacInF) != 0;
+  __shared__ double sh[NT / 64];
+  const int s = blockIdx.y;
+  if (a.active[s] == 0) return;  // block-uniform: stopped systems are skipped
+  const int pole = s / a.nrhs, r = s % a.nrhs;
+  const size_t npt = (size_t)g.nx * g.ny * g.nz, n2 = 2 * npt;
+  const FactorCoef cf = a.coef[(size_t)pole * a.cstride + a.k];
+  const PoleDev pd = a.poles[pole];
+  const T car = (T)cf.a_re, cai = (T)cf.a_im, cbr = (T)cf.b_re, cbi = (T)cf.b_im;
+  const T z0r = (T)pd.z0_re, z0i = (T)pd.z0_im;
+  const T2* __restrict__ X = INF ? a.win + (size_t)r * n2 : a.win + (size_t)s * n2;
+  const T2* __restrict__ F = a.f + (size_t)r * n2;
+  const T2* __restrict__ Y1 = a.y1 + (size_t)s * n2;
+  T2* __restrict__ O = a.wout + (size_t)s * n2;
+  T2* __restrict__ O2 = DUAL ? a.wout2 + (size_t)s * n2 : nullptr;
+  double acc = 0.0;
+  const size_t stride = (size_t)gridDim.x * NT;
+  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < npt; p += stride) {
+    const int i = (int)(p % g.nx), j = (int)((p / g.nx) % g.ny), k = (int)(p / ((size_t)g.nx * g.ny));
+    Cx<T> o1, o2, x1, x2;
+    b2_point<T, T2>(g, K, X, npt, p, i, j, k, z0r, z0i, o1, o2, x1, x2);
+    const Cx<T> u1 = cmul(car, cai, o1), v1 = cmul(cbr, cbi, x1);
+    const Cx<T> u2 = cmul(car, cai, o2), v2 = cmul(cbr, cbi, x2);
+    T2 w1, w2;
+    w1.x = u1.x + v1.x;
+    w1.y = u1.y + v1.y;
+    w2.x = u2.x + v2.x;
+    w2.y = u2.y + v2.y;
+    if constexpr (ADD) {
+      const T2 a1 = Y1[p], a2 = Y1[npt + p];
+      w1.x += a1.x;
+      w1.y += a1.y;
+      w2.x += a2.x;
+      w2.y += a2.y;
+    }
+    O[p] = w1;
+    O[npt + p] = w2;
+    if constexpr (DUAL) {
+      O2[p] = w1;
+      O2[npt + p] = w2;
+    }
+    if constexpr (RESID) {
+      // g - (B - z) y = g - (B - z0) y + (z - z0) y, both blocks, in FP64
+      const double zr = pd.zz_re, zi = pd.zz_im;
+      const T2 g1 = F[p], g2 = F[npt + p];
+      const double r1x = (double)g1.x - (double)o1.x + zr * (double)x1.x - zi * (double)x1.y;
+      const double r1y = (double)g1.y - (double)o1.y + zr * (double)x1.y + zi * (double)x1.x;
+      const double r2x = (double)g2.x - (double)o2.x + zr * (double)x2.x - zi * (double)x2.y;
+      const double r2y = (double)g2.y - (double)o2.y + zr * (double)x2.y + zi * (double)x2.x;
+      acc += r1x * r1x + r1y * r1y + r2x * r2x + r2y * r2y;
+    }
+  }
+  if constexpr (RESID) {
+    const double t = block_sum_nt(acc, sh);
+    if (threadIdx.x == 0) a.partial[(size_t)s * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void b2_apply_kernel(GridDesc g, const T* __restrict__ K,
+                                                      const typename Vec2<T>::t* __restrict__ x,
+                                                      typename Vec2<T>::t* __restrict__ y, double sr, double si) {
+  using T2 = typename Vec2<T>::t;
+  const size_t npt = (size_t)g.nx * g.ny * g.nz, n2 = 2 * npt;
+  const T2* __restrict__ X = x + (size_t)blockIdx.y * n2;
+  T2* __restrict__ Y = y + (size_t)blockIdx.y * n2;
+  const size_t stride = (size_t)gridDim.x * NT;
+  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < npt; p += stride) {
+    const int i = (int)(p % g.nx), j = (int)((p / g.nx) % g.ny), k = (int)(p / ((size_t)g.nx * g.ny));
+    Cx<T> o1, o2, x1, x2;
+    b2_point<T, T2>(g, K, X, npt, p, i, j, k, (T)sr, (T)si, o1, o2, x1, x2);
+    T2 w1, w2;
+    w1.x = o1.x;
+    w1.y = o1.y;
+    w2.x = o2.x;
+    w2.y = o2.y;
+    Y[p] = w1;
+    Y[npt + p] = w2;
+  }
+}
+
+template <typename T, int KIND>
+void launch_kind(hipStream_t st, const GridDesc& g, const T* K, int nsys, int nblk,
+                 const B2Args<typename Vec2<T>::t>& a) {
+  hipLaunchKernelGGL((b2_factor_kernel<T, KIND>), dim3((unsigned)nblk, (unsigned)nsys), dim3(NT), 0, st, g, K, a);
+}
+
+}  // namespace
+
+int b2_blocks(const GridDesc& g) {
+  const size_t npt = (size_t)g.nx * g.ny * g.nz;
+  size_t b = (npt + NT - 1) / NT;
+  if (b > 1024) b = 1024;
+  return (int)b;
+}
+
+template <typename T2>
+bool launch_b2_factor(hipStream_t st, const GridDesc& g, const void* K, int kind, int nsys,
+                      const B2Args<T2>& a) {
+  using T = typename Scal<T2>::t;
+  const T* k = (const T*)K;
+  const int nb = b2_blocks(g);
+  if (nsys <= 0) return true;
+  switch (kind) {
+    case 0: launch_kind<T, 0>(st, g, k, nsys, nb, a); return true;
+    case kFacResid: launch_kind<T, kFacResid>(st, g, k, nsys, nb, a); return true;
+    case kFacAdd: launch_kind<T, kFacAdd>(st, g, k, nsys, nb, a); return true;
+    case kFacResid | kFacAdd: launch_kind<T, kFacResid | kFacAdd>(st, g, k, nsys, nb, a); return true;
+    case kFacInF: launch_kind<T, kFacInF>(st, g, k, nsys, nb, a); return true;
+    case kFacInF | kFacDual: launch_kind<T, kFacInF | kFacDual>(st, g, k, nsys, nb, a); return true;
+    case kFacDual: launch_kind<T, kFacDual>(st, g, k, nsys, nb, a); return true;
+    default: return false;
+  }
+}
+template bool launch_b2_factor<float2>(hipStream_t, const GridDesc&, const void*, int, int, const B2Args<float2>&);
+template bool launch_b2_factor<double2>(hipStream_t, const GridDesc&, const void*, int, int,
+                                        const B2Args<double2>&);
+
+template <typename T2>
+void launch_b2_apply(hipStream_t st, const GridDesc& g, const void* K, int nvec, const T2* x, T2* y, double sr,
+                     double si) {
+  using T = typename Scal<T2>::t;
+  if (nvec <= 0) return;
+  hipLaunchKernelGGL(b2_apply_kernel<T>, dim3((unsigned)b2_blocks(g), (unsigned)nvec), dim3(NT), 0, st, g,
+                     (const T*)K, x, y, sr, si);
+}
+template void launch_b2_apply<float2>(hipStream_t, const GridDesc&, const void*, int, const float2*, float2*,
+                                      double, double);
+template void launch_b2_apply<double2>(hipStream_t, const GridDesc&, const void*, int, const double2*, double2*,
+                                       double, double);
+
+}  // namespace hfci

@@ -131,6 +131,9 @@ struct Op {
   int damp_cells = 0;
   double* kappa64 = nullptr;
   float* kappa32 = nullptr;
+  // 1: the operator A itself; 2: B = iC - I of eq. mat-2x2 built on A (n = 2 x the grid
+  // points, [b1, b2] x [-rho2, 0] the box of Thm 3.2's remark)
+  int form = 1;
 };
 
 struct Contour {
@@ -238,6 +241,10 @@ void shifted_solve_batch(const Op& op, const Contour& c, int nrhs, const T2* f, 
                          double reduce, int max_steps, int* steps_out, FciStats& st);
 void fci_apply(const Op& op, const Contour& c, const hfci_solve_opts& o, int nrhs, const double2* f,
                double2* out, FciStats& st);
+// case_two.cpp: the shifted solves of a case-two operator (op.form == 2)
+template <typename T2>
+void shifted_solve_case_two(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int fixed_steps,
+                            double reduce, int max_steps, int* steps_out, FciStats& st);
 hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& o, int nrhs,
                          const double2* f, double2* u, hfci_stats* stats);
 void launch_diffnorm2_partial(hipStream_t st, const double2* a, const double2* b, size_t n, double* partial);

@@ -65,6 +65,32 @@ struct FactorArgs {
   int count, sys0, nrhs, cstride, k;
 };
 
+// Case two (eq. mat-2x2): factors of the fixed-point step on B = iC - I, whose vectors
+// hold 2 n values (x1 then x2).  System s = pole * nrhs + rhs, vectors strided by 2 n;
+// kind bits as for the case-one factors (kFacResid, kFacAdd, kFacInF, kFacDual), and a
+// system with active[s] == 0 is skipped.  Residual partials: [nsys][b2_blocks(g)].
+template <typename T2>
+struct B2Args {
+  const T2* win;           // input, per system (the right-hand sides, per rhs, with kFacInF)
+  const T2* f;             // right-hand sides, per rhs (kFacResid)
+  const T2* y1;            // constant term of the step, per system (kFacAdd)
+  T2* wout;                // output, per system
+  T2* wout2;               // second output, per system (kFacDual)
+  const FactorCoef* coef;  // [pole][cstride]; this launch uses entry k
+  const PoleDev* poles;    // [pole]
+  const int* active;       // [nsys]
+  double* partial;         // [nsys][b2_blocks(g)] (kFacResid)
+  int nrhs, cstride, k;
+};
+int b2_blocks(const GridDesc& g);
+// false for an unsupported combination of kind bits (nothing is launched)
+template <typename T2>
+bool launch_b2_factor(hipStream_t st, const GridDesc& g, const void* K, int kind, int nsys, const B2Args<T2>& a);
+// y_v = (B - shift) x_v for v < nvec (vectors of 2 n values, not overlapping)
+template <typename T2>
+void launch_b2_apply(hipStream_t st, const GridDesc& g, const void* K, int nvec, const T2* x, T2* y, double sr,
+                     double si);
+
 template <typename T2>
 struct Launch {
   static void apply(hipStream_t st, const GridDesc& g, const void* kappa, double shift_re,

@@ -159,6 +159,7 @@ hfci_status hfci_net_apply(hfci_net* net, const hfci_op* op, int nvec, const hfc
   NET_BEGIN
   HFCI_REQUIRE(net && op && r && z, "NULL argument");
   const hfci::Op& o = *op;
+  if (o.form != 1) throw hfci::Error(HFCI_E_STATE, "not available for a case-two operator");
   check_dims(o.g.nx, o.g.ny, o.g.nz);
   HFCI_REQUIRE(nvec >= 1, "nvec must be >= 1");
   Dev dg(net->device);
@@ -173,6 +174,7 @@ hfci_status hfci_op_medium_channel(const hfci_op* op, float* out) {
   NET_BEGIN
   HFCI_REQUIRE(op && out, "NULL argument");
   const hfci::Op& o = *op;
+  if (o.form != 1) throw hfci::Error(HFCI_E_STATE, "not available for a case-two operator");
   Dev dg(o.device);
   launch_scale_f32(o.ctx->stream, o.kappa32, (long)o.n, (float)(1.0 / o.s_h2), out);
   HFCI_HIP(hipGetLastError());

@@ -33,7 +33,7 @@ EXPORTED = ["hfci_default_opts", "hfci_last_error", "hfci_version", "hfci_ctx_cr
             "hfci_net_param_count", "hfci_net_get_params", "hfci_net_set_params", "hfci_net_get_grads",
             "hfci_net_eval", "hfci_net_train_step", "hfci_net_train", "hfci_net_apply", "hfci_op_medium_channel",
             "hfci_net_save", "hfci_net_load", "hfci_op_set_tune", "hfci_op_get_tune", "hfci_op_autotune",
-            "hfci_shifted_solve_batch", "hfci_solve_batch"]
+            "hfci_shifted_solve_batch", "hfci_solve_batch", "hfci_op_case_two"]
 PROF_CLASSES = ["fp_stage", "fp_stage_first", "apply", "fp_stage_last", "fp_stage_init"]
 
 
@@ -111,6 +111,7 @@ def load_library(path: str = LIB_PATH):
         "hfci_ctx_destroy": (None, [vp]),
         "hfci_op_create": (ip, [vp, ip, ip, ip, dp, vp, dp, ip, dp, P(vp)]),
         "hfci_op_destroy": (None, [vp]),
+        "hfci_op_case_two": (ip, [vp, P(vp)]),
         "hfci_op_info": (ip, [vp, P(dp)]),
         "hfci_apply": (ip, [vp, c128, ip, ip, vp, vp]),
         "hfci_contour_create": (ip, [vp, ip, dp, dp, ip, vp, vp, vp, P(vp)]),
@@ -297,6 +298,31 @@ class Operator(_Handle):
         _check(load_library().hfci_op_get_tune(self.h, prec, ctypes.cast(t, ctypes.c_void_p)))
         return tuple(t)
 
+    def case_two(self):
+        """hfci_op_case_two: the double-size operator B = iC - I of eq. mat-2x2 on this A."""
+        return CaseTwoOperator(self)
+
+
+class CaseTwoOperator(_Handle):
+    """hfci_op_case_two: B = iC - I (eq. mat-2x2); vectors have shape [2, nz, ny, nx] (x1 then x2)."""
+
+    _destroy = "hfci_op_destroy"
+
+    def __init__(self, base: Operator):
+        self.h = ctypes.c_void_p()
+        self.ctx = base.ctx
+        self.base = base
+        self.shape = (2,) + tuple(base.shape)
+        self.n = 2 * base.n
+        _check(load_library().hfci_op_case_two(base.h, ctypes.byref(self.h)))
+        base.ctx._adopt(self)
+
+    def info(self):
+        out = (ctypes.c_double * 7)()
+        _check(load_library().hfci_op_info(self.h, out))
+        keys = ["s", "s_h2", "b1", "b2", "rho2", "kappa_min", "kappa_max"]
+        return dict(zip(keys, list(out)))
+
 
 class Net(_Handle):
     """hfci_net_create: the learned preconditioner (3-level 3D U-Net, BF16 on the matrix cores)."""
@@ -400,12 +426,14 @@ def _prec_of(t):
     raise TypeError("complex64 or complex128 expected, got %s" % t.dtype)
 
 
-def apply(op: Operator, x, shift: complex = 0.0, out=None):
-    """hfci_apply: (A - shift I) x for x of shape [..., nz, ny, nx] (batch = leading dims)."""
+def apply(op, x, shift: complex = 0.0, out=None):
+    """hfci_apply: (A - shift I) x for x of shape [..., nz, ny, nx] (batch = leading dims); for a
+    case-two operator (B - shift I) x with x of shape [..., 2, nz, ny, nx]."""
     import torch
     prec = _prec_of(x)
-    if tuple(x.shape[-3:]) != op.shape:
-        raise ValueError("x grid shape %s != operator %s" % (tuple(x.shape[-3:]), op.shape))
+    k = len(op.shape)
+    if tuple(x.shape[-k:]) != op.shape:
+        raise ValueError("x shape %s != operator %s" % (tuple(x.shape[-k:]), op.shape))
     nvec = x.numel() // op.n
     if out is None:
         out = torch.empty_like(x)
@@ -448,8 +476,8 @@ class Contour(_Handle):
         return {"z": cz(z), "sigma": cz(s), "delta": np.array(d[:]), "z0": cz(z0), "nu": np.array(nu[:])}
 
 
-def shifted_solve(op: Operator, c: Contour, f, steps: int = 0, reduce: float = 5.0, max_steps: int = 200):
-    """hfci_shifted_solve: f [nrhs, nz, ny, nx] -> (y [J, nrhs, nz, ny, nx], steps taken [J, nrhs])."""
+def shifted_solve(op, c: Contour, f, steps: int = 0, reduce: float = 5.0, max_steps: int = 200):
+    """hfci_shifted_solve: f [nrhs, *op.shape] -> (y [J, nrhs, *op.shape], steps taken [J, nrhs])."""
     import torch
     prec = _prec_of(f)
     nrhs = f.shape[0]

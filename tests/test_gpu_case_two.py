@@ -1,0 +1,203 @@
+"""Case two (eq. mat-2x2) on the HIP path versus the FP64 oracle, through the C ABI.
+
+Tolerances as for case one: FP64 1e-13 (one product with B), 1e-12 (fixed-point
+steps); FP32 2e-6 for one product (the stencil terms of block two, rounded at
+2^-24) and 2e-4 for the fixed-point iteration.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import case_two as OCT
+from oracle import fixed_point as OFP
+from oracle import operator as OO
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+hf = pytest.importorskip("paper_1811_12378_amd.hfci")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hf.load_library()
+    c = hf.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+def make(ctx, shape, seed, omega, cells, rho2):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(1.0, 3.0, size=shape)
+    h = 1.0 / shape[0]
+    o = OO.Operator(c, omega, cells, rho2, h=h)
+    g = hf.Operator(ctx, dev(c), h, omega, cells, rho2)
+    return OCT.CaseTwoOperator(o), g.case_two(), g
+
+
+def contour_pair(o2, g2, J, q, eps=0.5):
+    poles = OCT.pole_parameters(o2, J, 1.0, eps, q)
+    cg = hf.Contour(g2, J, 1.0, eps, q, z=[p.z for p in poles], sigma=[p.sigma for p in poles],
+                    delta=[p.delta for p in poles])
+    return poles, cg
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (11, 13, 37), (5, 7, 130), (1, 1, 1), (2, 3, 1)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_case_two_apply_parity(ctx, shape, prec):
+    o2, g2, _ = make(ctx, shape, 1, 9.0, 2, 0.8)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((3,) + o2.shape) + 1j * rng.standard_normal((3,) + o2.shape)
+    shift = 0.37 - 1.21j
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    y = host(hf.apply(g2, dev(x).to(dt), shift))
+    tol = 1e-13 if prec == "f64" else 2e-6
+    for k in range(3):
+        ref = o2.apply(x[k], shift)
+        assert rel(y[k], ref) <= tol, (shape, prec, k, rel(y[k], ref))
+
+
+def test_case_two_box_and_contour(ctx):
+    o2, g2, g = make(ctx, (9, 10, 11), 3, 14.0, 2, 1.0)
+    info, info1 = g2.info(), g.info()
+    b1, b2, rho2 = o2.rectangle()
+    assert math.isclose(info["b1"], b1, rel_tol=1e-13) and math.isclose(info["b2"], b2, rel_tol=1e-13)
+    assert info["rho2"] == rho2 == info1["rho2"]
+    # width rho2 + sqrt(rho2^2 + 4 rho1) with rho1 = b2(A) + 1 (the remark after Thm 3.2)
+    rho1 = info1["b2"] + 1.0
+    assert math.isclose(info["b2"] - info["b1"], rho2 + math.sqrt(rho2 ** 2 + 4 * rho1), rel_tol=1e-13)
+    # the library's own contour on B's box: same poles as the oracle's, and its delta
+    # search reaches the oracle's rate to the grid of the search
+    poles = OCT.pole_parameters(o2, 6, 1.0, 0.5, 8)
+    cg = hf.Contour(g2, 6, 1.0, 0.5, 8)
+    got = cg.get()
+    for j, p in enumerate(poles):
+        assert abs(got["z"][j] - p.z) <= 1e-12 * abs(p.z)
+        assert abs(got["z0"][j] - p.z0) <= 1e-12 * max(1.0, abs(p.z0))
+        assert got["nu"][j] < 1.0
+
+
+@pytest.mark.parametrize("prec,q,steps", [("f64", 8, 3), ("f64", 3, 4), ("f64", 2, 2), ("f64", 1, 3),
+                                          ("f64", 4, 1), ("f32", 8, 3), ("f32", 3, 2)])
+def test_case_two_shifted_solve_fixed_steps(ctx, prec, q, steps):
+    o2, g2, _ = make(ctx, (9, 17, 33), 5, 18.0, 3, 1.0)
+    poles, cg = contour_pair(o2, g2, 4, q)
+    rng = np.random.default_rng(6)
+    f = rng.standard_normal((2,) + o2.shape) + 1j * rng.standard_normal((2,) + o2.shape)
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    y, st = hf.shifted_solve(g2, cg, dev(f).to(dt), steps=steps)
+    y = host(y)
+    assert np.all(st == steps)
+    Bm = lambda v, sh: o2.apply(v, sh)
+    tol = 1e-12 if prec == "f64" else 2e-4
+    for j, p in enumerate(poles):
+        for r in range(2):
+            ref, _ = OFP.fixed_point_solve(Bm, f[r], p.z, p.z0, p.delta, q, steps=steps)
+            assert rel(y[j, r], ref) <= tol, (j, r, rel(y[j, r], ref))
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 8])
+def test_case_two_shifted_solve_adaptive(ctx, q):
+    # every (pole, rhs) stops at the oracle's step with the oracle's iterate; rhs 1 is
+    # zero: its systems stop at step 0 with y = 0 while the others iterate, so the later
+    # launches skip stopped systems
+    o2, g2, _ = make(ctx, (10, 12, 14), 7, 15.0, 3, 1.0)
+    poles, cg = contour_pair(o2, g2, 6, q)
+    rng = np.random.default_rng(8)
+    f = rng.standard_normal((3,) + o2.shape) + 1j * rng.standard_normal((3,) + o2.shape)
+    f[1] = 0.0
+    f[2] *= 1e-3
+    y, st = hf.shifted_solve(g2, cg, dev(f), reduce=5.0, max_steps=60)
+    y = host(y)
+    Bm = lambda v, sh: o2.apply(v, sh)
+    for j, p in enumerate(poles):
+        for r in range(3):
+            if r == 1:
+                assert st[j, r] == 0 and np.all(y[j, r] == 0)
+                continue
+            ref, hist = OFP.fixed_point_solve(Bm, f[r], p.z, p.z0, p.delta, q, reduce=5.0, m_max=60)
+            assert st[j, r] == len(hist) - 1, (j, r, st[j, r], len(hist) - 1)
+            assert rel(y[j, r], ref) <= 1e-12, (j, r, rel(y[j, r], ref))
+            assert st[j, r] >= 1
+
+
+def test_case_two_step_cap(ctx):
+    o2, g2, _ = make(ctx, (8, 9, 10), 9, 12.0, 2, 1.0)
+    poles, cg = contour_pair(o2, g2, 4, 4)
+    rng = np.random.default_rng(10)
+    f = rng.standard_normal((1,) + o2.shape) + 1j * rng.standard_normal((1,) + o2.shape)
+    y, st = hf.shifted_solve(g2, cg, dev(f), reduce=1e12, max_steps=2)
+    assert np.all(st == 2)
+    Bm = lambda v, sh: o2.apply(v, sh)
+    for j, p in enumerate(poles):
+        ref, _ = OFP.fixed_point_solve(Bm, f[0], p.z, p.z0, p.delta, 4, steps=2)
+        assert rel(host(y)[j, 0], ref) <= 1e-12
+
+
+def test_case_two_unsupported_entry_points(ctx):
+    import ctypes
+    o2, g2, g = make(ctx, (6, 6, 6), 11, 9.0, 1, 0.5)
+    poles, cg = contour_pair(o2, g2, 4, 4)
+    f = dev(np.ones((1, 6, 6, 6), dtype=np.complex128))
+    for call in (lambda: hf.fci_apply(g2, cg, f),
+                 lambda: hf.solve(g2, cg, f),
+                 lambda: hf.Operator.set_tune(g2, 32, 1, 8, 2, 0, 0),
+                 lambda: hf.Operator.autotune(g2, 32, 2),
+                 lambda: hf._check(hf.load_library().hfci_op_case_two(g2.h, ctypes.byref(ctypes.c_void_p())))):
+        with pytest.raises(hf.HfciError) as e:
+            call()
+        assert e.value.status == -6
+    # a contour of the case-one operator is rejected for the case-two handle
+    c1 = hf.Contour(g, 4, 1.0, 0.5, 4)
+    with pytest.raises(hf.HfciError) as e:
+        hf.shifted_solve(g2, c1, dev(np.ones((1, 2, 6, 6, 6), dtype=np.complex128)), steps=1)
+    assert e.value.status == -6
+    # the case-one operator still works after its case-two handle is released
+    g2.close()
+    y, st = hf.shifted_solve(g, c1, f, steps=1)
+    assert np.all(st == 1)
+
+
+def test_case_two_apply_sampled_at_256(ctx):
+    # the headline medium at 256^3 (complex64, the precision of its sweeps): sampled
+    # outputs of (B - z0) x against the oracle's point formula
+    wl = W.config_layered_256(nrhs=1)
+    g = hf.Operator(ctx, dev(wl.c), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
+    g2 = g.case_two()
+    o = OO.Operator(wl.c, wl.omega, wl.damp_cells, wl.damp_rho2, h=wl.h)
+    n = wl.c.shape[0]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(13)
+    x = torch.randn((2, n, n, n), dtype=torch.complex64, device="cuda", generator=gen)
+    shift = -0.21 + 0.6j
+    y = hf.apply(g2, x, shift)
+    rng = np.random.default_rng(14)
+    pts = [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(300)]
+    pts += [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 5), (n // 2, 0, n - 1)]
+    xh = host(x).astype(np.complex128)
+    yh = host(y)
+    a1 = OO.apply_at(xh[0], o.kappa, 0, 0.0, o.s_h2, 0.0, pts)  # A1 x1 (no damping term)
+    for t, (k, j, i) in enumerate(pts):
+        x1, x2 = xh[0, k, j, i], xh[1, k, j, i]
+        d = o.damp[k, j, i]
+        r1 = -x1 + 1j * x2 - shift * x1
+        r2 = -1j * (a1[t] + x1) - (1.0 + 1j * d) * x2 - shift * x2
+        scale = max(abs(r2), o.s_h2 * (abs(x1) + 1.0))
+        assert abs(yh[0, k, j, i] - r1) <= 2e-6 * max(abs(r1), 1.0), (k, j, i)
+        assert abs(yh[1, k, j, i] - r2) <= 2e-6 * scale * 12, (k, j, i)
