@@ -266,6 +266,59 @@ def learned_arm(args, ctx, op, cont, f_d, t_mixed, fp64, verbose):
     return out
 
 
+def case_two_arm(args, ctx, op, cont, wl):
+    """Case one versus case two (eq. mat-2x2) on the headline workload: the shifted solves of
+    one FCI application, every pole of the same contour construction (eq. quad-points with
+    the same eps, J, q; delta searched on each operator's own box), reducing each residual
+    by fp_reduce = 5 from y = 0 with the physical right-hand side (s f for A, [0; s f] for B).
+    Reports steps and stencil products per pole, the time of each batch of shifted solves,
+    and the case-two kernel's algorithmic bandwidth over its solve (wall clock)."""
+    import numpy as np
+    import torch
+    from paper_1811_12378_amd import hfci
+    info = op.info()
+    n = wl.n
+    f1 = (info["s"] * torch.from_numpy(wl.rhs[0]).cuda()).to(torch.complex64).reshape(1, n, n, n)
+    g2 = op.case_two()
+    c2 = hfci.Contour(g2, args.poles, 1.0, args.eps, args.q)
+    rhs2 = torch.zeros((1, 2, n, n, n), dtype=torch.complex64, device="cuda")
+    rhs2[0, 1] = f1[0]
+    out = {}
+    for name, o_, c_, f_ in (("case_one", op, cont, f1), ("case_two", g2, c2, rhs2)):
+        hfci.shifted_solve(o_, c_, f_, steps=1)  # untimed: workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y, st = hfci.shifted_solve(o_, c_, f_, reduce=5.0, max_steps=400)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        steps = [int(v) for v in st[:, 0]]
+        cg = c_.get()
+        out[name] = {"time_s": round(t, 4), "steps_per_pole": steps, "stencil_products": int(args.q * sum(steps)),
+                     "nu_per_pole": [round(float(v), 4) for v in cg["nu"]],
+                     "box": [round(o_.info()["b1"], 4), round(o_.info()["b2"], 4), o_.info()["rho2"]]}
+        log("%s: %.3f s, steps per pole %s" % (name, t, steps))
+        del y
+    # algorithmic bytes of the case-two solve (complex64 blocks, float kappa): a factor reads
+    # x (2 x 8 B) and kappa (4 B) and writes 2 x 8 B per grid point; step one's first factor
+    # reads the right-hand side instead and its last also writes y; a later step's first
+    # factor reads g for the residual, its last reads y1
+    q, nP = args.q, max(args.q - 1, 1)
+    per = 0.0
+    for m in out["case_two"]["steps_per_pole"]:
+        per += nP * 36 + 16 + max(m - 1, 0) * (q * 36 + 32) + (36 + 16)
+    alg = per * n ** 3
+    t2 = out["case_two"]["time_s"]
+    out["case_two"]["alg_bytes"] = alg
+    out["case_two"]["achieved_gbs_wall"] = round(alg / t2 / 1e9, 1)
+    out["case_two"]["kernel"] = "b2_factor_kernel<float, KIND> (one factor per pass, no LDS staging)"
+    out["stencil_products_ratio_two_over_one"] = round(out["case_two"]["stencil_products"] /
+                                                       max(out["case_one"]["stencil_products"], 1), 3)
+    out["time_ratio_two_over_one"] = round(t2 / out["case_one"]["time_s"], 3)
+    g2.close()
+    c2.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,6 +342,9 @@ def main():
                     help="instances of the uneven-batch arm (64 = the full config; 0 skips it)")
     ap.add_argument("--uneven-only", action="store_true", help="run only the uneven-batch arm")
     ap.add_argument("--no-small", action="store_true", help="skip the 32^3 / 96^3 configurations")
+    ap.add_argument("--no-case-two", action="store_true", help="skip the case-one versus case-two shifted solves")
+    ap.add_argument("--case-two-only", action="store_true",
+                    help="run only the case-one versus case-two shifted solves at the headline workload")
     ap.add_argument("--small-only", action="store_true", help="run only the 32^3 / 96^3 configurations")
     ap.add_argument("--profile-every", type=int, default=PROFILE_EVERY,
                     help="time every k-th launch of each kernel class in the timed solves")
@@ -343,6 +399,13 @@ def main():
     else:
         tune32, rows32 = op.autotune(32, 2)
         log("autotuned complex64 shape %s (%.3f ms)" % (tune32, min(r[1] for r in rows32)))
+    if args.case_two_only:
+        r = case_two_arm(args, ctx, op, cont, wl)
+        print(json.dumps({"metric": "shifted solves of one FCI application, case one vs case two (s)",
+                          "value": r["case_two"]["time_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+                          "dtype": "c64", "data": "synthetic", "config": {"workload": wl.name}, "case_two": r}),
+              flush=True)
+        return
     tune64, rows64 = op.autotune(64, 2)
     log("autotuned complex128 shape %s (%.3f ms)" % (tune64, min(r[1] for r in rows64)))
     mixed = hfci.default_opts(precision=32, tol=args.tol, max_it=args.max_it, verbose=verbose)
@@ -424,6 +487,10 @@ def main():
     if args.uneven > 0:
         uneven = uneven_arm(args, ctx, verbose)
 
+    case_two = None
+    if not args.no_case_two:
+        case_two = case_two_arm(args, ctx, op, cont, wl)
+
     learned = None
     if not args.no_learned:
         learned = learned_arm(args, ctx, op, cont, f_d, t_mixed, fp64, verbose)
@@ -476,6 +543,7 @@ def main():
         "learned": learned,
         "uneven_batch": uneven,
         "small_configs": small,
+        "case_two": case_two,
     }
     print(json.dumps(out), flush=True)
 
