@@ -226,9 +226,12 @@ hfci_status hfci_apply(const hfci_op* op, hfci_c128 shift, int prec, int nvec,
  * unchanged), is [-1 - R, -1 + R] x [-rho2, 0] with R = rho2/2 + sqrt(rho2^2/4 + rho1)
  * and rho1 = b2 + 1 from op's box (Thm 3.2 and the remark after it).
  * On the returned handle: hfci_op_info, hfci_op_get_tune, hfci_apply ((B - shift) x),
- * hfci_contour_create / hfci_contour_get (poles and delta for B's box) and
+ * hfci_contour_create / hfci_contour_get (poles and delta for B's box),
  * hfci_shifted_solve (vectors of 2n values; one launch per fixed-point factor, every
- * shifted system in one grid).  The other entry points return HFCI_E_STATE for it.
+ * shifted system in one grid), hfci_fci_apply (Algorithm 1 on B, all poles in one batch:
+ * opts->pole_batch and opts->graphs do not apply) and hfci_solve (FGMRES on B; pass the
+ * physical right-hand side [0; f] to get [i u; u]; precond FCI or NONE).  The other
+ * entry points, and the learned preconditioner, return HFCI_E_STATE for it.
  * The handle copies op's medium (op may be destroyed first); release it with
  * hfci_op_destroy.  Errors: HFCI_E_ARG, HFCI_E_STATE (op is itself a case-two handle). */
 hfci_status hfci_op_case_two(const hfci_op* op, hfci_op** out);

@@ -729,7 +729,6 @@ hfci_status hfci_fci_apply(const hfci_op* op, const hfci_contour* c, const hfci_
                            const hfci_c128* f, hfci_c128* out, hfci_stats* stats) {
   HFCI_API_BEGIN
   HFCI_REQUIRE(op && c && f && out, "NULL argument");
-  require_case_one(op);
   if (c->op != op) throw Error(HFCI_E_STATE, "contour was created for another operator");
   check_opts(o);
   HFCI_REQUIRE(nrhs >= 1 && (long)nrhs * c->J <= 65536, "nrhs out of range");
@@ -752,7 +751,8 @@ hfci_status hfci_solve(const hfci_op* op, const hfci_contour* c, const hfci_solv
                        const hfci_c128* f, hfci_c128* u, hfci_stats* stats) {
   HFCI_API_BEGIN
   HFCI_REQUIRE(op && f && u, "NULL argument");
-  require_case_one(op);
+  if (op->form != 1 && o && o->precond == HFCI_PRECOND_LEARNED)
+    throw Error(HFCI_E_STATE, "the learned preconditioner is not available for a case-two operator");
   check_opts(o);
   if (o->precond == HFCI_PRECOND_FCI || o->precond == HFCI_PRECOND_LEARNED) {
     HFCI_REQUIRE(c != nullptr, "FCI preconditioning (or its use as the learned fallback) needs a contour");

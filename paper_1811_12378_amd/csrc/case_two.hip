@@ -164,6 +164,66 @@ __global__ __launch_bounds__(NT) void b2_apply_kernel(GridDesc g, const T* __res
   }
 }
 
+// Alg. 1 step 3 on B: per right-hand side r (grid y), partial sums of (B w)^H f (real and
+// imaginary parts) and |B w|^2 over both blocks; partial[(3 r + c) * gridDim.x + block].
+template <typename T>
+__global__ __launch_bounds__(NT) void b2_dstep_kernel(GridDesc g, const T* __restrict__ K,
+                                                      const typename Vec2<T>::t* __restrict__ w,
+                                                      const typename Vec2<T>::t* __restrict__ f,
+                                                      double* __restrict__ partial) {
+  using T2 = typename Vec2<T>::t;
+  __shared__ double sh[NT / 64];
+  const size_t npt = (size_t)g.nx * g.ny * g.nz, n2 = 2 * npt;
+  const int r = blockIdx.y;
+  const T2* __restrict__ W = w + (size_t)r * n2;
+  const T2* __restrict__ F = f + (size_t)r * n2;
+  double nr = 0.0, ni = 0.0, den = 0.0;
+  const size_t stride = (size_t)gridDim.x * NT;
+  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < npt; p += stride) {
+    const int i = (int)(p % g.nx), j = (int)((p / g.nx) % g.ny), k = (int)(p / ((size_t)g.nx * g.ny));
+    Cx<T> o1, o2, x1, x2;
+    b2_point<T, T2>(g, K, W, npt, p, i, j, k, (T)0, (T)0, o1, o2, x1, x2);
+    const T2 f1 = F[p], f2 = F[npt + p];
+    nr += (double)o1.x * f1.x + (double)o1.y * f1.y + (double)o2.x * f2.x + (double)o2.y * f2.y;
+    ni += (double)o1.x * f1.y - (double)o1.y * f1.x + (double)o2.x * f2.y - (double)o2.y * f2.x;
+    den += (double)o1.x * o1.x + (double)o1.y * o1.y + (double)o2.x * o2.x + (double)o2.y * o2.y;
+  }
+  const double a = block_sum_nt(nr, sh);
+  __syncthreads();
+  const double b = block_sum_nt(ni, sh);
+  __syncthreads();
+  const double c = block_sum_nt(den, sh);
+  if (threadIdx.x == 0) {
+    partial[(size_t)(3 * r) * gridDim.x + blockIdx.x] = a;
+    partial[(size_t)(3 * r + 1) * gridDim.x + blockIdx.x] = b;
+    partial[(size_t)(3 * r + 2) * gridDim.x + blockIdx.x] = c;
+  }
+}
+
+// FP64 true residual of the double-size system: res = b - B u, partial sums of |res|^2
+// (one per block).
+__global__ __launch_bounds__(NT) void b2_residual64_kernel(GridDesc g, const double* __restrict__ K,
+                                                           const double2* __restrict__ b,
+                                                           const double2* __restrict__ u,
+                                                           double2* __restrict__ res, double* __restrict__ partial) {
+  __shared__ double sh[NT / 64];
+  const size_t npt = (size_t)g.nx * g.ny * g.nz;
+  double acc = 0.0;
+  const size_t stride = (size_t)gridDim.x * NT;
+  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < npt; p += stride) {
+    const int i = (int)(p % g.nx), j = (int)((p / g.nx) % g.ny), k = (int)(p / ((size_t)g.nx * g.ny));
+    Cx<double> o1, o2, x1, x2;
+    b2_point<double, double2>(g, K, u, npt, p, i, j, k, 0.0, 0.0, o1, o2, x1, x2);
+    const double2 b1 = b[p], b2 = b[npt + p];
+    const double2 r1 = make_double2(b1.x - o1.x, b1.y - o1.y), r2 = make_double2(b2.x - o2.x, b2.y - o2.y);
+    res[p] = r1;
+    res[npt + p] = r2;
+    acc += r1.x * r1.x + r1.y * r1.y + r2.x * r2.x + r2.y * r2.y;
+  }
+  const double t = block_sum_nt(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
 template <typename T, int KIND>
 void launch_kind(hipStream_t st, const GridDesc& g, const T* K, int nsys, int nblk,
                  const B2Args<typename Vec2<T>::t>& a) {
@@ -213,5 +273,23 @@ template void launch_b2_apply<float2>(hipStream_t, const GridDesc&, const void*,
                                       double, double);
 template void launch_b2_apply<double2>(hipStream_t, const GridDesc&, const void*, int, const double2*, double2*,
                                        double, double);
+
+template <typename T2>
+void launch_b2_dstep(hipStream_t st, const GridDesc& g, const void* K, int nrhs, const T2* w, const T2* f,
+                     double* partial) {
+  using T = typename Scal<T2>::t;
+  if (nrhs <= 0) return;
+  hipLaunchKernelGGL(b2_dstep_kernel<T>, dim3((unsigned)b2_blocks(g), (unsigned)nrhs), dim3(NT), 0, st, g,
+                     (const T*)K, w, f, partial);
+}
+template void launch_b2_dstep<float2>(hipStream_t, const GridDesc&, const void*, int, const float2*, const float2*,
+                                      double*);
+template void launch_b2_dstep<double2>(hipStream_t, const GridDesc&, const void*, int, const double2*,
+                                       const double2*, double*);
+
+void launch_b2_residual64(hipStream_t st, const GridDesc& g, const double* K, const double2* b, const double2* u,
+                          double2* res, double* partial, int nblk) {
+  hipLaunchKernelGGL(b2_residual64_kernel, dim3((unsigned)nblk), dim3(NT), 0, st, g, K, b, u, res, partial);
+}
 
 }  // namespace hfci

@@ -86,6 +86,13 @@ int b2_blocks(const GridDesc& g);
 // false for an unsupported combination of kind bits (nothing is launched)
 template <typename T2>
 bool launch_b2_factor(hipStream_t st, const GridDesc& g, const void* K, int kind, int nsys, const B2Args<T2>& a);
+// Alg. 1 step 3 on B: partial[(3 r + c)][b2_blocks(g)] = Re, Im of (B w_r)^H f_r and |B w_r|^2
+template <typename T2>
+void launch_b2_dstep(hipStream_t st, const GridDesc& g, const void* K, int nrhs, const T2* w, const T2* f,
+                     double* partial);
+// res = b - B u in FP64 with nblk partial sums of |res|^2 (nblk >= 1 blocks)
+void launch_b2_residual64(hipStream_t st, const GridDesc& g, const double* K, const double2* b, const double2* u,
+                          double2* res, double* partial, int nblk);
 // y_v = (B - shift) x_v for v < nvec (vectors of 2 n values, not overlapping)
 template <typename T2>
 void launch_b2_apply(hipStream_t st, const GridDesc& g, const void* K, int nvec, const T2* x, T2* y, double sr,

@@ -11,6 +11,7 @@ import pytest
 
 import workloads as W
 from oracle import case_two as OCT
+from oracle import fci as OF
 from oracle import fixed_point as OFP
 from oracle import operator as OO
 
@@ -155,8 +156,7 @@ def test_case_two_unsupported_entry_points(ctx):
     o2, g2, g = make(ctx, (6, 6, 6), 11, 9.0, 1, 0.5)
     poles, cg = contour_pair(o2, g2, 4, 4)
     f = dev(np.ones((1, 6, 6, 6), dtype=np.complex128))
-    for call in (lambda: hf.fci_apply(g2, cg, f),
-                 lambda: hf.solve(g2, cg, f),
+    for call in (lambda: hf.solve(g2, cg, f, opts=hf.default_opts(precond=hf.HFCI_PRECOND_LEARNED)),
                  lambda: hf.Operator.set_tune(g2, 32, 1, 8, 2, 0, 0),
                  lambda: hf.Operator.autotune(g2, 32, 2),
                  lambda: hf._check(hf.load_library().hfci_op_case_two(g2.h, ctypes.byref(ctypes.c_void_p())))):
@@ -172,6 +172,68 @@ def test_case_two_unsupported_entry_points(ctx):
     g2.close()
     y, st = hf.shifted_solve(g, c1, f, steps=1)
     assert np.all(st == 1)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_case_two_fci_lockstep(ctx, prec):
+    # Algorithm 1 on B with a fixed step count: shifted solves, quadrature, step 3 with B w
+    o2, g2, _ = make(ctx, (10, 11, 12), 9, 15.0, 3, 1.0)
+    poles, cg = contour_pair(o2, g2, 8, 8)
+    rng = np.random.default_rng(10)
+    f = rng.standard_normal((3,) + o2.shape) + 1j * rng.standard_normal((3,) + o2.shape)
+    opts = hf.default_opts(fp_steps=4, precision=64 if prec == "f64" else 32)
+    out, st = hf.fci_apply(g2, cg, dev(f), opts)
+    out = host(out)
+    assert st["fp_steps"] == 8 * 3 * 4
+    tol = 1e-12 if prec == "f64" else 2e-4
+    for r in range(3):
+        ref = OF.fci(o2, f[r], poles, steps=4)
+        assert rel(out[r], ref) <= tol, (r, rel(out[r], ref))
+
+
+def test_case_two_solve_lockstep_and_direct(ctx):
+    # FGMRES on eq. mat-2x2 with FCI(B), FP64 sweeps and a fixed step count: the same
+    # iteration count as the oracle's, x2 = u and x1 = i u of the direct solve of A u = s f
+    o2, g2, g = make(ctx, (8, 9, 10), 12, 12.0, 2, 1.0)
+    poles, cg = contour_pair(o2, g2, 6, 6)
+    rng = np.random.default_rng(13)
+    f = rng.standard_normal(o2.base.shape) + 1j * rng.standard_normal(o2.base.shape)
+    rhs = np.stack([np.zeros_like(f), f])[None]
+    opts = hf.default_opts(precision=64, tol=1e-9, max_it=300, fp_steps=2, restart=20)
+    x, st = hf.solve(g2, cg, dev(rhs), opts=opts)
+    assert st["status"] == "HFCI_OK"
+    x = host(x)[0]
+    u_o, info = OCT.solve(o2.base, f, poles, m=20, tol=1e-9, max_it=300, steps=2)
+    assert st["its"] == info["its"]
+    A = o2.base.assemble().tocsc()
+    import scipy.sparse.linalg as spla
+    uref = spla.spsolve(A, (o2.base.s * f).ravel()).reshape(f.shape)
+    assert rel(x[1], uref) <= 1e-8
+    assert rel(x[0], 1j * uref) <= 1e-8
+    assert rel(x[1], u_o) <= 1e-8
+
+
+def test_case_two_solve_mixed_adaptive(ctx):
+    # mixed precision (FP32 sweeps, FP64 FGMRES), adaptive fixed-point steps.  FGMRES meets
+    # the tolerance on the double-size system (the oracle's FP64 residual of x on B); for
+    # u = x2 the residual on A is b - A x2 = i (A1 + I) r1 - r2 with [r1; r2] the residual of
+    # x, so it is bounded by (rho1 + 1) times the tolerance
+    o2, g2, g = make(ctx, (12, 13, 14), 14, 16.0, 3, 1.0)
+    cg = hf.Contour(g2, 8, 1.0, 0.5, 8)
+    rng = np.random.default_rng(15)
+    f = rng.standard_normal(o2.base.shape) + 1j * rng.standard_normal(o2.base.shape)
+    rhs = np.stack([np.zeros_like(f), f])[None]
+    tol = 1e-7
+    opts = hf.default_opts(precision=32, tol=tol, max_it=400)
+    x, st = hf.solve(g2, cg, dev(rhs), opts=opts)
+    assert st["status"] == "HFCI_OK" and st["fp_steps"] > 0
+    x = host(x)[0]
+    b = o2.base.s * f
+    b2 = o2.rhs(b)
+    r2 = np.linalg.norm(b2 - o2.apply(x)) / np.linalg.norm(b2)
+    assert r2 <= tol * 1.01, r2
+    ra = np.linalg.norm(b - o2.base.apply(x[1])) / np.linalg.norm(b)
+    assert ra <= (o2.rho1() + 1.0) * tol, ra
 
 
 def test_case_two_apply_sampled_at_256(ctx):
