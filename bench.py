@@ -266,13 +266,15 @@ def learned_arm(args, ctx, op, cont, f_d, t_mixed, fp64, verbose):
     return out
 
 
-def case_two_arm(args, ctx, op, cont, wl):
+def case_two_arm(args, ctx, op, cont, wl, solve=True):
     """Case one versus case two (eq. mat-2x2) on the headline workload: the shifted solves of
     one FCI application, every pole of the same contour construction (eq. quad-points with
-    the same eps, J, q; delta searched on each operator's own box), reducing each residual
+    the same J, q and eps for A, eps / 2 for B; delta searched on each operator's own box),
+    reducing each residual
     by fp_reduce = 5 from y = 0 with the physical right-hand side (s f for A, [0; s f] for B).
     Reports steps and stencil products per pole, the time of each batch of shifted solves,
-    and the case-two kernel's algorithmic bandwidth over its solve (wall clock)."""
+    and the case-two kernel's algorithmic bandwidth over its solve (wall clock); with `solve`,
+    also the full mixed-precision FGMRES solve on B to the headline tolerance."""
     import numpy as np
     import torch
     from paper_1811_12378_amd import hfci
@@ -280,7 +282,10 @@ def case_two_arm(args, ctx, op, cont, wl):
     n = wl.n
     f1 = (info["s"] * torch.from_numpy(wl.rhs[0]).cuda()).to(torch.complex64).reshape(1, n, n, n)
     g2 = op.case_two()
-    c2 = hfci.Contour(g2, args.poles, 1.0, args.eps, args.q)
+    # near the origin B's eigenvalues are about half of A's (mu = sqrt(a + 1) - 1, the map of
+    # eq. shifted-2x2's equivalent shifts), so eps / 2 keeps the same modes inside the contour
+    eps2 = args.case_two_eps if args.case_two_eps > 0 else args.eps / 2
+    c2 = hfci.Contour(g2, args.poles, 1.0, eps2, args.q)
     rhs2 = torch.zeros((1, 2, n, n, n), dtype=torch.complex64, device="cuda")
     rhs2[0, 1] = f1[0]
     out = {}
@@ -293,7 +298,8 @@ def case_two_arm(args, ctx, op, cont, wl):
         t = time.perf_counter() - t0
         steps = [int(v) for v in st[:, 0]]
         cg = c_.get()
-        out[name] = {"time_s": round(t, 4), "steps_per_pole": steps, "stencil_products": int(args.q * sum(steps)),
+        out[name] = {"time_s": round(t, 4), "eps": args.eps if name == "case_one" else eps2,
+                     "steps_per_pole": steps, "stencil_products": int(args.q * sum(steps)),
                      "nu_per_pole": [round(float(v), 4) for v in cg["nu"]],
                      "box": [round(o_.info()["b1"], 4), round(o_.info()["b2"], 4), o_.info()["rho2"]]}
         log("%s: %.3f s, steps per pole %s" % (name, t, steps))
@@ -314,6 +320,29 @@ def case_two_arm(args, ctx, op, cont, wl):
     out["stencil_products_ratio_two_over_one"] = round(out["case_two"]["stencil_products"] /
                                                        max(out["case_one"]["stencil_products"], 1), 3)
     out["time_ratio_two_over_one"] = round(t2 / out["case_one"]["time_s"], 3)
+    if solve:
+        # end to end: FGMRES(30) with FCI(B) on eq. mat-2x2, mixed precision, to the headline
+        # tolerance on the double-size system; u = x2, whose FP64 residual on A the oracle
+        # recomputes on the host
+        from oracle import operator as OO
+        rhs = torch.zeros((1, 2, n, n, n), dtype=torch.complex128, device="cuda")
+        rhs[0, 1] = torch.from_numpy(wl.rhs[0]).cuda()
+        hfci.solve(g2, c2, rhs, opts=hfci.default_opts(precision=32, tol=args.tol, max_it=1))  # workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st = hfci.solve(g2, c2, rhs, opts=hfci.default_opts(precision=32, tol=args.tol, max_it=args.max_it))
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        o = OO.Operator(wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
+        b = o.s * wl.rhs[0]
+        u = x[0, 1].cpu().numpy()
+        ra = float(np.linalg.norm(b - o.apply(u)) / np.linalg.norm(b))
+        out["solve"] = {"time_s": round(ts, 4), "its": st["its"], "status": st["status"],
+                        "final_relres_double_size": st["final_relres"], "relres_on_A_oracle": ra,
+                        "stencil_products": st["matvecs"]}
+        log("case two solve: %.3f s, its %d, relres %.3e (double-size), %.3e on A (oracle)"
+            % (ts, st["its"], st["final_relres"], ra))
+        del x
     g2.close()
     c2.close()
     return out
@@ -343,6 +372,8 @@ def main():
     ap.add_argument("--uneven-only", action="store_true", help="run only the uneven-batch arm")
     ap.add_argument("--no-small", action="store_true", help="skip the 32^3 / 96^3 configurations")
     ap.add_argument("--no-case-two", action="store_true", help="skip the case-one versus case-two shifted solves")
+    ap.add_argument("--case-two-eps", type=float, default=0.0,
+                    help="contour eps of the case-two arm (0: half the headline eps)")
     ap.add_argument("--case-two-only", action="store_true",
                     help="run only the case-one versus case-two shifted solves at the headline workload")
     ap.add_argument("--small-only", action="store_true", help="run only the 32^3 / 96^3 configurations")
