@@ -21,6 +21,8 @@ using contour integration and polynomial preconditioning") step by step:
   fci        -- Algorithm 1 (FCI).
   krylov     -- flexible GMRES (the Krylov wrapper of Sec. 2) with classical
                 Gram-Schmidt applied twice and Givens rotations; plain GMRES.
+  laplacian  -- the regularised sine-transform inverse of the discrete Laplacian,
+                the inner preconditioner of Alg. 1 step 4 (Sec. 6.3).
   case_two   -- the double-size formulation of eq. mat-2x2 (B = iC - I), its
                 spectrum box from Thm 3.2 and the remark after it, and FGMRES
                 with FCI on it.
@@ -29,4 +31,4 @@ using contour integration and polynomial preconditioning") step by step:
 
 Parity status of each function is stated in its module header.
 """
-from . import operator, contour, polynomial, fixed_point, fci, krylov, conv, case_two  # noqa: F401
+from . import operator, contour, polynomial, fixed_point, fci, krylov, conv, case_two, laplacian  # noqa: F401

@@ -8,7 +8,9 @@ Algorithm 1 (FCI) for a right-hand side f:
   2. w = sum_i sigma_i / z_i y_i   (quadrature of P A^{-1} f);
   3. d = argmin_d ||f - d A w||_2 = (Aw)^H f / (Aw)^H (Aw);
   4. v = argmin_v ||A v - (f - d A w)|| by a few GMRES steps (k_in; default 0,
-     in which case v = 0);
+     in which case v = 0), optionally right-preconditioned by an approximate
+     inverse M of the Laplacian (Sec. 6.3; see laplacian.py): v = M t with t from
+     k_in steps on A M;
   return v + d w.
 The solver wraps FCI in FGMRES (Sec. 2).
 
@@ -49,7 +51,7 @@ def pole_parameters(op: operator.Operator, J: int, t: float, eps: float, q: int,
 
 
 def fci(op: operator.Operator, f, poles, steps=None, reduce: float = 5.0, m_max: int = 1000,
-        k_in: int = 0, shifted_solver=None, return_parts: bool = False):
+        k_in: int = 0, shifted_solver=None, return_parts: bool = False, inner_precond=None):
     """Algorithm 1.  `steps` fixes the fixed-point step count per pole (int or list)."""
     f = np.asarray(f, dtype=np.complex128).reshape(op.shape)
     Am = lambda x, shift: op.apply(x, shift)
@@ -70,7 +72,12 @@ def fci(op: operator.Operator, f, poles, steps=None, reduce: float = 5.0, m_max:
     out = d * w
     if k_in > 0:
         rem = (f - d * Aw).ravel()
-        v = krylov.gmres(lambda x: op.apply(x).ravel(), rem, k_in)
+        if inner_precond is None:
+            v = krylov.gmres(lambda x: op.apply(x).ravel(), rem, k_in)
+        else:
+            # right preconditioning: FGMRES with a fixed M is GMRES on A M, returning M t
+            v, _ = krylov.fgmres(lambda x: op.apply(x).ravel(), rem, lambda x: np.ravel(inner_precond(x)),
+                                 m=k_in, tol=0.0, max_it=k_in)
         out = out + v.reshape(op.shape)
     if return_parts:
         return out, {"w": w, "d": d, "ys": ys}
@@ -79,12 +86,13 @@ def fci(op: operator.Operator, f, poles, steps=None, reduce: float = 5.0, m_max:
 
 def solve(op: operator.Operator, f_phys, poles, m: int = 30, tol: float = 1e-8,
           max_it: int = 1000, steps=None, reduce: float = 5.0, m_max: int = 1000,
-          k_in: int = 0):
+          k_in: int = 0, inner_precond=None):
     """Solve the physical system (-Laplace_h - omega^2/c^2) u = f_phys by FGMRES + FCI.
 
     The normalised system is A u = s f_phys (Sec. 7.1); relative residuals are
     the same in both scalings.
     """
     b = op.s * np.asarray(f_phys, dtype=np.complex128).ravel()
-    pre = lambda v: fci(op, v, poles, steps=steps, reduce=reduce, m_max=m_max, k_in=k_in).ravel()
+    pre = lambda v: fci(op, v, poles, steps=steps, reduce=reduce, m_max=m_max, k_in=k_in,
+                        inner_precond=inner_precond).ravel()
     return krylov.fgmres(lambda x: op.apply(x).ravel(), b, pre, m=m, tol=tol, max_it=max_it)
