@@ -78,7 +78,12 @@ typedef struct {
   double fp_reduce;     /* adaptive: stop a pole when ||r|| <= ||f|| / fp_reduce
                            (Table 4 uses 5)                          default 5  */
   int fp_max_steps;     /* adaptive: cap on steps per pole           default 200 */
-  int k_in;             /* Alg. 1 step 4: GMRES steps on the remainder (0 = off) */
+  int k_in;             /* Alg. 1 step 4: GMRES steps (0..16) on the remainder
+                           f - d A w, right-preconditioned by the regularised
+                           inverse of the discrete Laplacian, V diag(1/max(lambda,
+                           1)) V^T with V the sine transform along each axis
+                           (Sec. 6.3); FP64.  Not for case-two operators or
+                           batches.                                   default 0 */
   int precond;          /* HFCI_PRECOND_FCI (default) or HFCI_PRECOND_NONE       */
   int pole_batch;       /* poles advanced together per launch (x every RHS);
                            0 = all J                                              */

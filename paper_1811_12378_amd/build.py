@@ -69,7 +69,10 @@ def build(jobs: int = 8, debug: bool = False, verbose: bool = False) -> str:
             if verbose and warn:
                 print(warn, file=sys.stderr)
     tmp = LIB + ".tmp"
-    cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + sorted(objs)
+    rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+    # rocBLAS: the complex GEMMs of the inner preconditioner's sine transforms
+    cmd = ([cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + sorted(objs)
+           + ["-L" + rocm_lib, "-lrocblas", "-Wl,-rpath," + rocm_lib])
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (res.stdout, res.stderr))

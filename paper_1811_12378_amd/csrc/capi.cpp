@@ -156,7 +156,7 @@ static void check_opts(const hfci_solve_opts* o) {
   HFCI_REQUIRE(o->fp_steps >= 0, "fp_steps must be >= 0");
   HFCI_REQUIRE(o->fp_steps > 0 || (o->fp_reduce > 1.0 && o->fp_max_steps >= 1),
                "adaptive stopping needs fp_reduce > 1 and fp_max_steps >= 1");
-  HFCI_REQUIRE(o->k_in == 0, "k_in > 0 (Alg. 1 step 4) is not supported by this build");
+  HFCI_REQUIRE(o->k_in >= 0 && o->k_in <= 16, "k_in must be in [0, 16]");
   HFCI_REQUIRE(o->precond == HFCI_PRECOND_FCI || o->precond == HFCI_PRECOND_NONE ||
                    o->precond == HFCI_PRECOND_LEARNED,
                "unknown precond");
@@ -251,6 +251,7 @@ void hfci_ctx_destroy(hfci_ctx* c) {
   for (hipEvent_t e : c->step_event)
     if (e) (void)hipEventDestroy(e);
   c->ws.release_all();
+  inner_release(*c);
   if (c->pinned_int) (void)hipHostFree(c->pinned_int);
   if (c->pinned_dbl) (void)hipHostFree(c->pinned_dbl);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -701,6 +702,7 @@ hfci_status hfci_solve_batch(int count, const hfci_op* const* ops, const hfci_co
                              hfci_stats* stats) {
   HFCI_API_BEGIN
   check_opts(o);
+  HFCI_REQUIRE(o->k_in == 0, "k_in > 0 (Alg. 1 step 4) is not available for batches");
   HFCI_REQUIRE(o->precond == HFCI_PRECOND_FCI || o->precond == HFCI_PRECOND_NONE,
                "a batch takes precond = HFCI_PRECOND_FCI or HFCI_PRECOND_NONE");
   HFCI_REQUIRE(o->harvest_cap == 0, "a batch does not harvest training pairs");
@@ -731,6 +733,7 @@ hfci_status hfci_fci_apply(const hfci_op* op, const hfci_contour* c, const hfci_
   HFCI_REQUIRE(op && c && f && out, "NULL argument");
   if (c->op != op) throw Error(HFCI_E_STATE, "contour was created for another operator");
   check_opts(o);
+  if (op->form != 1 && o->k_in > 0) throw Error(HFCI_E_STATE, "k_in > 0 is not available for a case-two operator");
   HFCI_REQUIRE(nrhs >= 1 && (long)nrhs * c->J <= 65536, "nrhs out of range");
   HFCI_REQUIRE(!stats || stats->size == sizeof(hfci_stats), "stats->size mismatch");
   DeviceGuard dg(op->ctx->device);
@@ -754,6 +757,7 @@ hfci_status hfci_solve(const hfci_op* op, const hfci_contour* c, const hfci_solv
   if (op->form != 1 && o && o->precond == HFCI_PRECOND_LEARNED)
     throw Error(HFCI_E_STATE, "the learned preconditioner is not available for a case-two operator");
   check_opts(o);
+  if (op->form != 1 && o->k_in > 0) throw Error(HFCI_E_STATE, "k_in > 0 is not available for a case-two operator");
   if (o->precond == HFCI_PRECOND_FCI || o->precond == HFCI_PRECOND_LEARNED) {
     HFCI_REQUIRE(c != nullptr, "FCI preconditioning (or its use as the learned fallback) needs a contour");
     if (c->op != op) throw Error(HFCI_E_STATE, "contour was created for another operator");

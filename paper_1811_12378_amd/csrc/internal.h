@@ -118,6 +118,8 @@ struct Ctx {
   int* pinned_int = nullptr;     // host-pinned staging for small D2H reads (65536 ints)
   int* pinned_int_dev = nullptr; // the same memory as the device addresses it
   double* pinned_dbl = nullptr;  // host-pinned staging (65536 doubles)
+  void* blas = nullptr;          // rocBLAS handle of the inner preconditioner (created on first use)
+  std::map<int, double2*> sine;  // orthonormal DST-I matrices by size (device, complex)
 };
 
 struct Op {
@@ -241,6 +243,12 @@ void shifted_solve_batch(const Op& op, const Contour& c, int nrhs, const T2* f, 
                          double reduce, int max_steps, int* steps_out, FciStats& st);
 void fci_apply(const Op& op, const Contour& c, const hfci_solve_opts& o, int nrhs, const double2* f,
                double2* out, FciStats& st);
+// inner.cpp: Alg. 1 step 4, k_in GMRES steps on the remainder f - A out (FP64, nrhs
+// vectors), right-preconditioned by the regularised Laplacian inverse; out is updated
+void inner_steps(const Op& op, int k_in, int nrhs, const double2* f, double2* out, FciStats& st);
+// y = V diag(1 / max(lambda, 1)) V^T x on the grid g (FP64, x and y distinct)
+void laplace_inverse(Ctx& ctx, const GridDesc& g, const double2* x, double2* y);
+void inner_release(Ctx& ctx);
 // case_two.cpp: the shifted solves of a case-two operator (op.form == 2)
 template <typename T2>
 void shifted_solve_case_two(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int fixed_steps,
