@@ -266,6 +266,27 @@ def learned_arm(args, ctx, op, cont, f_d, t_mixed, fp64, verbose):
     return out
 
 
+def inner_arm(args, ctx, op, cont, f_d, t_mixed, its_mixed):
+    """Alg. 1 step 4 (Sec. 6.3) on the headline solve: the same mixed-precision solve with
+    k_in GMRES steps on the remainder, right-preconditioned by the regularised Laplacian
+    inverse (three FP64 complex GEMMs per sine transform), for each k_in of --k-in-list."""
+    import torch
+    from paper_1811_12378_amd import hfci
+    out = {"baseline": {"k_in": 0, "time_s": round(t_mixed, 4), "its": its_mixed}, "runs": []}
+    for k in args.k_in_list:
+        hfci.solve(op, cont, f_d, opts=hfci.default_opts(precision=32, tol=args.tol, max_it=1, k_in=k))  # workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = hfci.solve(op, cont, f_d, opts=hfci.default_opts(precision=32, tol=args.tol, max_it=args.max_it,
+                                                                 k_in=k))
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out["runs"].append({"k_in": k, "time_s": round(t, 4), "its": st["its"], "status": st["status"],
+                            "final_relres": st["final_relres"], "speedup_vs_k0": round(t_mixed / t, 3)})
+        log("step 4, k_in %d: %.3f s, its %d, relres %.3e" % (k, t, st["its"], st["final_relres"]))
+    return out
+
+
 def case_two_arm(args, ctx, op, cont, wl, solve=True):
     """Case one versus case two (eq. mat-2x2) on the headline workload: the shifted solves of
     one FCI application, every pole of the same contour construction (eq. quad-points with
@@ -372,6 +393,10 @@ def main():
     ap.add_argument("--uneven-only", action="store_true", help="run only the uneven-batch arm")
     ap.add_argument("--no-small", action="store_true", help="skip the 32^3 / 96^3 configurations")
     ap.add_argument("--no-case-two", action="store_true", help="skip the case-one versus case-two shifted solves")
+    ap.add_argument("--k-in-list", type=int, nargs="*", default=[2, 4],
+                    help="k_in values of the Alg. 1 step 4 arm (empty list skips it)")
+    ap.add_argument("--inner-only", action="store_true",
+                    help="run only the headline solve and the Alg. 1 step 4 arm")
     ap.add_argument("--case-two-eps", type=float, default=0.0,
                     help="contour eps of the case-two arm (0: half the headline eps)")
     ap.add_argument("--case-two-only", action="store_true",
@@ -394,6 +419,9 @@ def main():
     import workloads as W
     from paper_1811_12378_amd import hfci
 
+    if args.inner_only:
+        args.no_fp64 = args.no_small = args.no_learned = args.no_cpu = args.no_case_two = True
+        args.uneven = 0
     hfci.load_library()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     verbose = 0 if args.quiet else 1
@@ -518,6 +546,10 @@ def main():
     if args.uneven > 0:
         uneven = uneven_arm(args, ctx, verbose)
 
+    inner = None
+    if args.k_in_list:
+        inner = inner_arm(args, ctx, op, cont, f_d, t_mixed, st["its"])
+
     case_two = None
     if not args.no_case_two:
         case_two = case_two_arm(args, ctx, op, cont, wl)
@@ -575,6 +607,7 @@ def main():
         "uneven_batch": uneven,
         "small_configs": small,
         "case_two": case_two,
+        "inner_step4": inner,
     }
     print(json.dumps(out), flush=True)
 
