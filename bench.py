@@ -287,6 +287,29 @@ def inner_arm(args, ctx, op, cont, f_d, t_mixed, its_mixed):
     return out
 
 
+def params_arm(args, ctx, op, f_d, t_mixed, its_mixed):
+    """Contour choices on the headline solve: the degree q chosen by Sec. 4.2's rule (q = 0
+    at creation) on the circle (t = 1) and on the paper's ellipse t = 0.1, against the
+    headline's q, each a full mixed-precision solve to the headline tolerance."""
+    import torch
+    from paper_1811_12378_amd import hfci
+    out = {"baseline": {"t": 1.0, "q": args.q, "time_s": round(t_mixed, 4), "its": its_mixed}, "runs": []}
+    for t in (1.0, 0.1):
+        c = hfci.Contour(op, args.poles, t, args.eps, 0)
+        hfci.solve(op, c, f_d, opts=hfci.default_opts(precision=32, tol=args.tol, max_it=1))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = hfci.solve(op, c, f_d, opts=hfci.default_opts(precision=32, tol=args.tol, max_it=args.max_it))
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        nu = c.get()["nu"]
+        out["runs"].append({"t": t, "q_chosen": c.q, "time_s": round(ts, 4), "its": st["its"], "status": st["status"],
+                            "final_relres": st["final_relres"], "nu_max": round(float(nu.max()), 4)})
+        log("contour t %.1f, chosen q %d: %.3f s, its %d" % (t, c.q, ts, st["its"]))
+        c.close()
+    return out
+
+
 def case_two_arm(args, ctx, op, cont, wl, solve=True):
     """Case one versus case two (eq. mat-2x2) on the headline workload: the shifted solves of
     one FCI application, every pole of the same contour construction (eq. quad-points with
@@ -397,6 +420,8 @@ def main():
                     help="k_in values of the Alg. 1 step 4 arm (empty list skips it)")
     ap.add_argument("--inner-only", action="store_true",
                     help="run only the headline solve and the Alg. 1 step 4 arm")
+    ap.add_argument("--params", action="store_true",
+                    help="also run the contour-choice arm (chosen q, ellipse t = 0.1)")
     ap.add_argument("--case-two-eps", type=float, default=0.0,
                     help="contour eps of the case-two arm (0: half the headline eps)")
     ap.add_argument("--case-two-only", action="store_true",
@@ -550,6 +575,10 @@ def main():
     if args.k_in_list:
         inner = inner_arm(args, ctx, op, cont, f_d, t_mixed, st["its"])
 
+    params = None
+    if args.params:
+        params = params_arm(args, ctx, op, f_d, t_mixed, st["its"])
+
     case_two = None
     if not args.no_case_two:
         case_two = case_two_arm(args, ctx, op, cont, wl)
@@ -608,6 +637,7 @@ def main():
         "small_configs": small,
         "case_two": case_two,
         "inner_step4": inner,
+        "contour_choice": params,
     }
     print(json.dumps(out), flush=True)
 

@@ -249,13 +249,19 @@ hfci_status hfci_op_case_two(const hfci_op* op, hfci_op** out);
  * exponential-Taylor polynomial of degree q (eq. exp-taylor).
  * z, sigma (HOST arrays of J, or NULL) override the computed poles/weights;
  * delta (HOST array of J, or NULL) overrides the delta search.
- * Errors: HFCI_E_ARG (J < 1, q < 1 or > 16, t <= 0, eps <= 0);
+ * q = 0 chooses the degree by Sec. 4.2's rule: the q in 1..8 minimising nu^(1/q) for
+ * the pole closest to the origin (not with given deltas); hfci_contour_q reads it back.
+ * Errors: HFCI_E_ARG (J < 1, q < 0 or > 16, t <= 0, eps <= 0);
  * HFCI_E_CONTOUR (a pole with Re z > 0 or Im z in (-eps-rho2, eps) when
  * computed, or nu >= 1). */
 hfci_status hfci_contour_create(const hfci_op* op, int J, double t, double eps, int q,
                                 const hfci_c128* z, const hfci_c128* sigma,
                                 const double* delta, hfci_contour** out);
 void hfci_contour_destroy(hfci_contour* c);
+
+/* The degree q of the contour's polynomial (the chosen one when created with q = 0),
+ * written to *q (HOST).  Errors: HFCI_E_ARG. */
+hfci_status hfci_contour_q(const hfci_contour* c, int* q);
 
 /* Copy the contour's parameters into HOST arrays of length J (any may be NULL):
  * poles z, weights sigma, delta, Taylor centres z0, and the rate nu of each. */

@@ -513,8 +513,9 @@ hfci_status hfci_contour_create(const hfci_op* op, int J, double t, double eps, 
   HFCI_REQUIRE(op && out, "NULL argument");
   *out = nullptr;
   HFCI_REQUIRE(J >= 1 && J <= 256, "J must be in [1, 256]");
-  HFCI_REQUIRE(q >= 1 && q <= 16, "q must be in [1, 16]");
+  HFCI_REQUIRE(q >= 0 && q <= 16, "q must be in [0, 16]");
   HFCI_REQUIRE((z == nullptr) == (sigma == nullptr), "give both poles and weights or neither");
+  HFCI_REQUIRE(q > 0 || delta == nullptr, "q = 0 (chosen here) cannot take given deltas");
   if (!z) HFCI_REQUIRE(t > 0 && eps > 0 && std::isfinite(t) && std::isfinite(eps), "t and eps must be > 0");
   DeviceGuard dg(op->ctx->device);
   hfci_contour* c = new hfci_contour();
@@ -522,7 +523,6 @@ hfci_status hfci_contour_create(const hfci_op* op, int J, double t, double eps, 
     c->op = op;
     c->device = op->device;
     c->J = J;
-    c->q = q;
     c->t = t;
     c->eps = eps;
     if (z) {
@@ -541,6 +541,14 @@ hfci_status hfci_contour_create(const hfci_op* op, int J, double t, double eps, 
           throw Error(HFCI_E_CONTOUR, "pole violates Re z <= 0 and Im z outside (-eps-rho2, eps)");
       }
     }
+    if (q == 0) {
+      // Sec. 4.2's rule for the pole closest to the origin, the slowest to converge
+      int j0 = 0;
+      for (int j = 1; j < J; ++j)
+        if (std::abs(c->z[j]) < std::abs(c->z[j0])) j0 = j;
+      q = choose_q(c->z[j0], op->b1, op->b2, op->rho2, kAutoQMax);
+    }
+    c->q = q;
     c->delta.resize(J);
     c->nu.resize(J);
     c->z0.resize(J);
@@ -594,6 +602,14 @@ void hfci_contour_destroy(hfci_contour* c) {
   if (c->d_poles) (void)hipFree(c->d_poles);
   if (prev >= 0) (void)hipSetDevice(prev);
   delete c;
+}
+
+hfci_status hfci_contour_q(const hfci_contour* c, int* q) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(c && q, "NULL argument");
+  *q = c->q;
+  return HFCI_OK;
+  HFCI_API_END
 }
 
 hfci_status hfci_contour_get(const hfci_contour* c, hfci_c128* z, hfci_c128* sigma, double* delta, hfci_c128* z0,

@@ -219,6 +219,9 @@ cd ptilde(cd lam, cd z0, double delta, int q);
 double rate_on_boundary(double delta, cd z, cd z0, int q, const std::vector<cd>& boundary);
 std::vector<cd> rectangle_boundary(double b1, double b2, double rho2, int per_side);
 void optimise_delta(cd z, double b1, double b2, double rho2, int q, double& delta, double& nu, cd& z0);
+// largest degree hfci_contour_create considers when it chooses q (q = 0)
+constexpr int kAutoQMax = 8;
+int choose_q(cd z, double b1, double b2, double rho2, int qmax);
 std::vector<cd> poly_roots(std::vector<cd> coeffs);
 void factor_coefficients(cd z, cd z0, double delta, int q, FactorCoef* out_L, FactorCoef* out_P, cd& pz);
 

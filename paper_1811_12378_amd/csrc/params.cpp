@@ -108,6 +108,25 @@ void optimise_delta(cd z, double b1, double b2, double rho2, int q, double& delt
   nu = vm;
 }
 
+// Sec. 4.2: the degree q is preferred where nu^(1/q) is smallest (the cost to reduce the
+// residual by a factor F is about q ln F / (-ln nu) products); q in 1..qmax, ties to the
+// smaller q.
+int choose_q(cd z, double b1, double b2, double rho2, int qmax) {
+  int best = 1;
+  double key_best = 0.0;
+  for (int q = 1; q <= qmax; ++q) {
+    double delta, nu;
+    cd z0;
+    optimise_delta(z, b1, b2, rho2, q, delta, nu, z0);
+    const double key = std::pow(nu, 1.0 / q);
+    if (q == 1 || key < key_best) {
+      best = q;
+      key_best = key;
+    }
+  }
+  return best;
+}
+
 // Roots of sum_k c[k] x^k (c.back() != 0, degree <= 16) by the Aberth-Ehrlich
 // simultaneous iteration (Aberth 1973), then two Newton corrections per root.
 std::vector<cd> poly_roots(std::vector<cd> c) {

@@ -33,7 +33,7 @@ EXPORTED = ["hfci_default_opts", "hfci_last_error", "hfci_version", "hfci_ctx_cr
             "hfci_net_param_count", "hfci_net_get_params", "hfci_net_set_params", "hfci_net_get_grads",
             "hfci_net_eval", "hfci_net_train_step", "hfci_net_train", "hfci_net_apply", "hfci_op_medium_channel",
             "hfci_net_save", "hfci_net_load", "hfci_op_set_tune", "hfci_op_get_tune", "hfci_op_autotune",
-            "hfci_shifted_solve_batch", "hfci_solve_batch", "hfci_op_case_two"]
+            "hfci_shifted_solve_batch", "hfci_solve_batch", "hfci_op_case_two", "hfci_contour_q"]
 PROF_CLASSES = ["fp_stage", "fp_stage_first", "apply", "fp_stage_last", "fp_stage_init"]
 
 
@@ -117,6 +117,7 @@ def load_library(path: str = LIB_PATH):
         "hfci_contour_create": (ip, [vp, ip, dp, dp, ip, vp, vp, vp, P(vp)]),
         "hfci_contour_destroy": (None, [vp]),
         "hfci_contour_get": (ip, [vp, vp, vp, vp, vp, vp]),
+        "hfci_contour_q": (ip, [vp, P(ip)]),
         "hfci_shifted_solve": (ip, [vp, vp, ip, ip, vp, vp, ip, dp, ip, vp]),
         "hfci_fci_apply": (ip, [vp, vp, P(SolveOpts), ip, vp, vp, P(Stats)]),
         "hfci_solve": (ip, [vp, vp, P(SolveOpts), ip, vp, vp, P(Stats)]),
@@ -466,6 +467,10 @@ class Contour(_Handle):
             self._keepd = da
         _check(load_library().hfci_contour_create(op.h, J, t, eps, q, zp, sp, dp, ctypes.byref(self.h)))
         op.ctx._adopt(self)
+        if q == 0:  # chosen by the library (Sec. 4.2)
+            qv = ctypes.c_int()
+            _check(load_library().hfci_contour_q(self.h, ctypes.byref(qv)))
+            self.q = qv.value
 
     def get(self):
         J = self.J

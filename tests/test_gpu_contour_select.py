@@ -1,0 +1,75 @@
+"""Contour parameters chosen by the library, through the C ABI: the degree q of Sec. 4.2
+(q = 0 at creation) against the oracle's rule, and ellipse contours (t = 0.1) against the
+pole sets printed in Sec. 7.3 (tests/golden/poles_sec7.txt)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import contour as OC
+from oracle import polynomial as OP
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+hf = pytest.importorskip("paper_1811_12378_amd.hfci")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hf.load_library()
+    c = hf.Context(0)
+    yield c
+    c.close()
+
+
+def make(ctx, shape, omega, cells, rho2, seed=1):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(1.0, 3.0, size=shape)
+    return hf.Operator(ctx, torch.from_numpy(c).cuda(), 1.0 / shape[0], omega, cells, rho2)
+
+
+@pytest.mark.parametrize("omega,J,t,eps", [(14.0, 8, 1.0, 0.5), (30.0, 6, 0.1, 0.25), (9.0, 12, 0.5, 1.0)])
+def test_chosen_degree_matches_the_rule(ctx, omega, J, t, eps):
+    g = make(ctx, (12, 12, 12), omega, 2, 1.0)
+    info = g.info()
+    b1, b2, rho2 = info["b1"], info["b2"], info["rho2"]
+    c = hf.Contour(g, J, t, eps, 0)
+    assert 1 <= c.q <= 8
+    z, _, _ = OC.poles_and_weights(J, t, eps, rho2)
+    z1 = z[np.argmin(np.abs(z))]
+    q_o, _, nu_o = OP.choose_q(z1, b1, b2, rho2, qmax=8, per_side=2000)
+    key_o = nu_o ** (1.0 / q_o)
+    _, nu_l, _ = OP.optimise_delta(z1, b1, b2, rho2, c.q, per_side=2000)
+    # the library's choice reaches the oracle's best rate per product (searches differ in detail)
+    assert nu_l ** (1.0 / c.q) <= key_o * 1.01, (c.q, q_o)
+    # the contour is usable: every pole contracts
+    assert np.all(c.get()["nu"] < 1.0)
+
+
+def test_ellipse_poles_of_section_7_3(ctx):
+    # J = 6, t = 0.1, rho2 = 0.9: the library's poles reproduce the printed sets to their two decimals
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "poles_sec7.txt")) if l.strip() and not l.startswith("#")]
+    g = make(ctx, (10, 10, 10), 20.0, 2, 0.9)
+    assert g.info()["rho2"] == 0.9
+    for eps in sorted({float(r[1]) for r in rows}, reverse=True):
+        printed = {int(r[2]): complex(float(r[3]), float(r[4])) for r in rows if float(r[1]) == eps}
+        c = hf.Contour(g, 6, 0.1, eps, 3)
+        z = c.get()["z"]
+        for j in range(6):
+            assert abs(z[j] - printed[j + 1]) <= 0.011, (eps, j, z[j], printed[j + 1])
+
+
+def test_chosen_degree_errors(ctx):
+    g = make(ctx, (6, 6, 6), 9.0, 1, 0.5)
+    with pytest.raises(hf.HfciError) as e:
+        hf.Contour(g, 4, 1.0, 0.5, 0, z=[1j, -1j, -0.5 + 1j, -0.5 - 2j], sigma=[1, 1, 1, 1],
+                   delta=[0.1, 0.1, 0.1, 0.1])
+    assert e.value.status == -1
+    with pytest.raises(hf.HfciError) as e:
+        hf.Contour(g, 4, 1.0, 0.5, -1)
+    assert e.value.status == -1
