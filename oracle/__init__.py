@@ -21,6 +21,7 @@ using contour integration and polynomial preconditioning") step by step:
   fci        -- Algorithm 1 (FCI).
   krylov     -- flexible GMRES (the Krylov wrapper of Sec. 2) with classical
                 Gram-Schmidt applied twice and Givens rotations; plain GMRES.
+  spectral   -- the Fourier-spectral operator of Sec. 7.1 (eq. eig-Laplacian-spectral).
   laplacian  -- the regularised sine-transform inverse of the discrete Laplacian,
                 the inner preconditioner of Alg. 1 step 4 (Sec. 6.3).
   case_two   -- the double-size formulation of eq. mat-2x2 (B = iC - I), its
@@ -31,4 +32,4 @@ using contour integration and polynomial preconditioning") step by step:
 
 Parity status of each function is stated in its module header.
 """
-from . import operator, contour, polynomial, fixed_point, fci, krylov, conv, case_two, laplacian  # noqa: F401
+from . import operator, contour, polynomial, fixed_point, fci, krylov, conv, case_two, laplacian, spectral  # noqa: F401
