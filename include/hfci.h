@@ -223,6 +223,20 @@ hfci_status hfci_op_autotune(hfci_op* op, int prec, int nsys, int* best5, double
 hfci_status hfci_apply(const hfci_op* op, hfci_c128 shift, int prec, int nvec,
                        const void* x, void* y);
 
+/* ---- Fourier-spectral operator (Sec. 7.1, eq. eig-Laplacian-spectral) --------
+ * As hfci_op_create, with the discrete Laplacian replaced by the Fourier-spectral one on
+ * a periodic grid: S = F^H Lambda F, lambda = s sum_j (2 pi min(m_j, N_j - m_j)/(N_j h))^2
+ * for the Fourier mode m (the paper's (l_min/N)^2 sum_j min(i_j^2, (N - i_j)^2)), applied
+ * with library 3D FFTs; kappa and the damping layer as for hfci_op_create.  The box
+ * reported by hfci_op_info is [-kappa_max, lambda_max - kappa_min] x [-rho2, 0].
+ * Accepted by hfci_op_info, hfci_op_get_tune, hfci_apply, hfci_contour_create / get / q,
+ * hfci_shifted_solve (one FFT pair and one epilogue launch per fixed-point factor),
+ * hfci_fci_apply and hfci_solve (precond FCI or NONE, k_in = 0); the other entry points
+ * return HFCI_E_STATE.  Errors: as hfci_op_create. */
+hfci_status hfci_op_create_spectral(hfci_ctx* ctx, int nx, int ny, int nz, double h,
+                                    const double* c, double omega, int damp_cells,
+                                    double damp_rho2, hfci_op** out);
+
 /* ---- case two: the double-size formulation (Sec. 3, eq. mat-2x2) -----------
  * Creates a second operator handle for B = iC - I, C = [[0, I], [-(A1 + I), -A2]],
  * built on op's A = A1 - i A2 (A1 = S - M, A2 = D).  Solving B [x1; x2] = [0; f] gives

@@ -70,9 +70,10 @@ def build(jobs: int = 8, debug: bool = False, verbose: bool = False) -> str:
                 print(warn, file=sys.stderr)
     tmp = LIB + ".tmp"
     rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
-    # rocBLAS: the complex GEMMs of the inner preconditioner's sine transforms
+    # rocBLAS: the complex GEMMs of the inner preconditioner's sine transforms;
+    # hipFFT: the 3D transforms of the Fourier-spectral operator
     cmd = ([cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + sorted(objs)
-           + ["-L" + rocm_lib, "-lrocblas", "-Wl,-rpath," + rocm_lib])
+           + ["-L" + rocm_lib, "-lrocblas", "-lhipfft", "-Wl,-rpath," + rocm_lib])
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (res.stdout, res.stderr))

@@ -252,6 +252,7 @@ void hfci_ctx_destroy(hfci_ctx* c) {
     if (e) (void)hipEventDestroy(e);
   c->ws.release_all();
   inner_release(*c);
+  spectral_release(*c);
   if (c->pinned_int) (void)hipHostFree(c->pinned_int);
   if (c->pinned_dbl) (void)hipHostFree(c->pinned_dbl);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -348,7 +349,29 @@ hfci_status hfci_op_create(hfci_ctx* ctx, int nx, int ny, int nz, double h, cons
 
 // Entry points that run the case-one kernels only.
 static void require_case_one(const hfci::Op* op) {
-  if (op && op->form != 1) throw Error(HFCI_E_STATE, "not available for a case-two operator");
+  if (op && op->form != 1) throw Error(HFCI_E_STATE, "not available for a case-two or spectral operator");
+}
+
+hfci_status hfci_op_create_spectral(hfci_ctx* ctx, int nx, int ny, int nz, double h, const double* c, double omega,
+                                    int damp_cells, double damp_rho2, hfci_op** out) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(out, "NULL argument");
+  hfci_op* op = nullptr;
+  const hfci_status st = hfci_op_create(ctx, nx, ny, nz, h, c, omega, damp_cells, damp_rho2, &op);
+  if (st != HFCI_OK) return st;
+  // Sec. 7.1: lambda = s sum_j (2 pi min(m_j, N_j - m_j) / (N_j h))^2, largest at m_j = floor(N_j / 2);
+  // Lemma 3.1's box with lambda_min = 0
+  double lmax = 0.0;
+  for (int n : {nx, ny, nz}) {
+    const double k = 2.0 * M_PI * (n / 2) / (n * h);
+    lmax += k * k;
+  }
+  op->form = 3;
+  op->b1 = -op->kmax;
+  op->b2 = op->s * lmax - op->kmin;
+  *out = op;
+  return HFCI_OK;
+  HFCI_API_END
 }
 
 hfci_status hfci_op_case_two(const hfci_op* op, hfci_op** out) {
@@ -491,7 +514,11 @@ hfci_status hfci_apply(const hfci_op* op, hfci_c128 shift, int prec, int nvec, c
   const double e = prec == HFCI_F64 ? 16.0 : 8.0;
   const bool timed = pr.sample(HFCI_PROF_APPLY);
   if (timed) pr.begin(s);
-  if (op->form == 2 && prec == HFCI_F64)
+  if (op->form == 3 && prec == HFCI_F64)
+    spectral_apply<double2>(*op, nvec, (const double2*)x, (double2*)y, shift.re, shift.im);
+  else if (op->form == 3)
+    spectral_apply<float2>(*op, nvec, (const float2*)x, (float2*)y, shift.re, shift.im);
+  else if (op->form == 2 && prec == HFCI_F64)
     launch_b2_apply<double2>(s, op->g, op->kappa64, nvec, (const double2*)x, (double2*)y, shift.re, shift.im);
   else if (op->form == 2)
     launch_b2_apply<float2>(s, op->g, op->kappa32, nvec, (const float2*)x, (float2*)y, shift.re, shift.im);
@@ -637,7 +664,13 @@ hfci_status hfci_shifted_solve(const hfci_op* op, const hfci_contour* c, int pre
   HFCI_REQUIRE(steps > 0 || (reduce > 1.0 && max_steps >= 1), "give steps > 0, or reduce > 1 and max_steps >= 1");
   DeviceGuard dg(op->ctx->device);
   FciStats st;
-  if (op->form == 2 && prec == HFCI_F64)
+  if (op->form == 3 && prec == HFCI_F64)
+    shifted_solve_spectral<double2>(*op, *c, nrhs, (const double2*)f, (double2*)y, steps, reduce, max_steps,
+                                    steps_taken, st);
+  else if (op->form == 3)
+    shifted_solve_spectral<float2>(*op, *c, nrhs, (const float2*)f, (float2*)y, steps, reduce, max_steps,
+                                   steps_taken, st);
+  else if (op->form == 2 && prec == HFCI_F64)
     shifted_solve_case_two<double2>(*op, *c, nrhs, (const double2*)f, (double2*)y, steps, reduce, max_steps,
                                     steps_taken, st);
   else if (op->form == 2)
@@ -749,7 +782,8 @@ hfci_status hfci_fci_apply(const hfci_op* op, const hfci_contour* c, const hfci_
   HFCI_REQUIRE(op && c && f && out, "NULL argument");
   if (c->op != op) throw Error(HFCI_E_STATE, "contour was created for another operator");
   check_opts(o);
-  if (op->form != 1 && o->k_in > 0) throw Error(HFCI_E_STATE, "k_in > 0 is not available for a case-two operator");
+  if (op->form != 1 && o->k_in > 0)
+    throw Error(HFCI_E_STATE, "k_in > 0 is not available for a case-two or spectral operator");
   HFCI_REQUIRE(nrhs >= 1 && (long)nrhs * c->J <= 65536, "nrhs out of range");
   HFCI_REQUIRE(!stats || stats->size == sizeof(hfci_stats), "stats->size mismatch");
   DeviceGuard dg(op->ctx->device);
@@ -771,9 +805,10 @@ hfci_status hfci_solve(const hfci_op* op, const hfci_contour* c, const hfci_solv
   HFCI_API_BEGIN
   HFCI_REQUIRE(op && f && u, "NULL argument");
   if (op->form != 1 && o && o->precond == HFCI_PRECOND_LEARNED)
-    throw Error(HFCI_E_STATE, "the learned preconditioner is not available for a case-two operator");
+    throw Error(HFCI_E_STATE, "the learned preconditioner is not available for a case-two or spectral operator");
   check_opts(o);
-  if (op->form != 1 && o->k_in > 0) throw Error(HFCI_E_STATE, "k_in > 0 is not available for a case-two operator");
+  if (op->form != 1 && o->k_in > 0)
+    throw Error(HFCI_E_STATE, "k_in > 0 is not available for a case-two or spectral operator");
   if (o->precond == HFCI_PRECOND_FCI || o->precond == HFCI_PRECOND_LEARNED) {
     HFCI_REQUIRE(c != nullptr, "FCI preconditioning (or its use as the learned fallback) needs a contour");
     if (c->op != op) throw Error(HFCI_E_STATE, "contour was created for another operator");

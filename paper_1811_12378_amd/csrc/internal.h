@@ -120,6 +120,7 @@ struct Ctx {
   double* pinned_dbl = nullptr;  // host-pinned staging (65536 doubles)
   void* blas = nullptr;          // rocBLAS handle of the inner preconditioner (created on first use)
   std::map<int, double2*> sine;  // orthonormal DST-I matrices by size (device, complex)
+  std::map<std::string, void*> fft;  // FFT plans of spectral operators by grid, precision, batch
 };
 
 struct Op {
@@ -134,7 +135,8 @@ struct Op {
   double* kappa64 = nullptr;
   float* kappa32 = nullptr;
   // 1: the operator A itself; 2: B = iC - I of eq. mat-2x2 built on A (n = 2 x the grid
-  // points, [b1, b2] x [-rho2, 0] the box of Thm 3.2's remark)
+  // points, [b1, b2] x [-rho2, 0] the box of Thm 3.2's remark); 3: A with the
+  // Fourier-spectral Laplacian of Sec. 7.1 on a periodic grid
   int form = 1;
 };
 
@@ -252,6 +254,15 @@ void inner_steps(const Op& op, int k_in, int nrhs, const double2* f, double2* ou
 // y = V diag(1 / max(lambda, 1)) V^T x on the grid g (FP64, x and y distinct)
 void laplace_inverse(Ctx& ctx, const GridDesc& g, const double2* x, double2* y);
 void inner_release(Ctx& ctx);
+// spectral.cpp: the Fourier-spectral operator (op.form == 3)
+template <typename T2>
+void spectral_S(const Op& op, int nvec, const T2* in, T2* out);
+template <typename T2>
+void spectral_apply(const Op& op, int nvec, const T2* x, T2* y, double sr, double si);
+template <typename T2>
+void shifted_solve_spectral(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int fixed_steps,
+                            double reduce, int max_steps, int* steps_out, FciStats& st);
+void spectral_release(Ctx& ctx);
 // case_two.cpp: the shifted solves of a case-two operator (op.form == 2)
 template <typename T2>
 void shifted_solve_case_two(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int fixed_steps,

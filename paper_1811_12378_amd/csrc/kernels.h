@@ -86,6 +86,40 @@ int b2_blocks(const GridDesc& g);
 // false for an unsupported combination of kind bits (nothing is launched)
 template <typename T2>
 bool launch_b2_factor(hipStream_t st, const GridDesc& g, const void* K, int kind, int nsys, const B2Args<T2>& a);
+// Fourier-spectral operator (Sec. 7.1): kernels around the library FFTs.  SpecArgs are the
+// factor arguments of B2Args plus sw = S w of the inputs (indexed as the inputs).
+template <typename T2>
+struct SpecArgs {
+  const T2* win;
+  const T2* sw;
+  const T2* f;
+  const T2* y1;
+  T2* wout;
+  T2* wout2;
+  const FactorCoef* coef;
+  const PoleDev* poles;
+  const int* active;
+  double* partial;         // [nsys][spec_blocks(g)] (kFacResid)
+  int nrhs, cstride, k;
+};
+int spec_blocks(const GridDesc& g);
+// c_v *= lambda / N (the diagonal between a forward and an unnormalised inverse FFT)
+template <typename T2>
+void launch_spec_scale(hipStream_t st, T2* c, int nvec, const GridDesc& g, double s, double h);
+template <typename T2>
+bool launch_spec_factor(hipStream_t st, const GridDesc& g, const void* K, int kind, int nsys, const SpecArgs<T2>& a);
+// y = (A - shift) x from sx = S x (y may alias sx)
+template <typename T2>
+void launch_spec_apply(hipStream_t st, const GridDesc& g, const void* K, int nvec, const T2* x, const T2* sx, T2* y,
+                       double sr, double si);
+// Alg. 1 step 3 partials from sw = S w, layout as launch_b2_dstep (spec_blocks(g) per row)
+template <typename T2>
+void launch_spec_dstep(hipStream_t st, const GridDesc& g, const void* K, int nrhs, const T2* w, const T2* sw,
+                       const T2* f, double* partial);
+// res = b - A u from su = S u (res may alias su), nblk partial sums of |res|^2
+void launch_spec_residual64(hipStream_t st, const GridDesc& g, const double* K, const double2* b, const double2* u,
+                            const double2* su, double2* res, double* partial, int nblk);
+
 // Alg. 1 step 3 on B: partial[(3 r + c)][b2_blocks(g)] = Re, Im of (B w_r)^H f_r and |B w_r|^2
 template <typename T2>
 void launch_b2_dstep(hipStream_t st, const GridDesc& g, const void* K, int nrhs, const T2* w, const T2* f,

@@ -492,17 +492,26 @@ void fci_body(const Op& op, const Contour& c, const hfci_solve_opts& o, int nrhs
     stage[2 * j + 1] = v.imag();
   }
   HFCI_HIP(hipMemcpyAsync(cc, stage, 2 * J * sizeof(double), hipMemcpyHostToDevice, s));
-  if (op.form == 2) {
-    // case two (eq. mat-2x2): every pole in one batch of shifted solves on B, the same
-    // quadrature, and step 3 with B w
+  if (op.form != 1) {
+    // case two (eq. mat-2x2) or the spectral operator: every pole in one batch of shifted
+    // solves, the same quadrature, and step 3 with the operator's own product
     T2* yall = (T2*)ctx.ws.get("fci_y", (size_t)J * nrhs * n * sizeof(T2));
-    shifted_solve_case_two<T2>(op, c, nrhs, f, yall, o.fp_steps, o.fp_reduce, o.fp_max_steps, nullptr, st);
+    if (op.form == 2)
+      shifted_solve_case_two<T2>(op, c, nrhs, f, yall, o.fp_steps, o.fp_reduce, o.fp_max_steps, nullptr, st);
+    else
+      shifted_solve_spectral<T2>(op, c, nrhs, f, yall, o.fp_steps, o.fp_reduce, o.fp_max_steps, nullptr, st);
     launch_combine<T2>(s, w, yall, cc, J, nrhs, n, false);
-    const int nb2 = b2_blocks(op.g);
+    const int nb2 = op.form == 2 ? b2_blocks(op.g) : spec_blocks(op.g);
     double* part2 = (double*)ctx.ws.get("fci_dpart", (size_t)nrhs * 3 * nb2 * sizeof(double));
     double* sums2 = (double*)ctx.ws.get("fci_dsums", (size_t)nrhs * 3 * sizeof(double));
     double* d2 = (double*)ctx.ws.get("fci_d", (size_t)nrhs * 2 * sizeof(double));
-    launch_b2_dstep<T2>(s, op.g, Prec<T2>::kappa(op), nrhs, w, f, part2);
+    if (op.form == 2) {
+      launch_b2_dstep<T2>(s, op.g, Prec<T2>::kappa(op), nrhs, w, f, part2);
+    } else {
+      T2* sw = (T2*)ctx.ws.get("fci_sw", (size_t)nrhs * n * sizeof(T2));
+      spectral_S<T2>(op, nrhs, w, sw);
+      launch_spec_dstep<T2>(s, op.g, Prec<T2>::kappa(op), nrhs, w, sw, f, part2);
+    }
     launch_reduce(s, part2, nb2, 3 * nrhs, sums2);
     launch_dfinish(s, sums2, nrhs, d2);
     st.matvecs += nrhs;
@@ -662,9 +671,12 @@ hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& 
     std::vector<int> act;
     for (int r = 0; r < nrhs; ++r) {
       if (done[r]) continue;
-      if (op.form == 2)
+      if (op.form == 2) {
         launch_b2_residual64(s, op.g, op.kappa64, b + r * n, u + r * n, V + r * n, part, nbs);
-      else
+      } else if (op.form == 3) {
+        spectral_S<double2>(op, 1, u + r * n, V + r * n);
+        launch_spec_residual64(s, op.g, op.kappa64, b + r * n, u + r * n, V + r * n, V + r * n, part, nbs);
+      } else
         launch_residual64(s, op.g, op.kappa64, b + r * n, u + r * n, V + r * n, part);
       launch_reduce(s, part, nbs, 1, hdev + (size_t)r * hstride + 4 * (m + 1) + 1);
       act.push_back(r);
@@ -812,6 +824,8 @@ hfci_status fgmres_solve(const Op& op, const Contour* c, const hfci_solve_opts& 
         double* hb = hdev + (size_t)r * hstride;
         if (op.form == 2)
           launch_b2_apply<double2>(s, op.g, op.kappa64, 1, Z + (size_t)j * vs + r * n, w, 0.0, 0.0);
+        else if (op.form == 3)
+          spectral_apply<double2>(op, 1, Z + (size_t)j * vs + r * n, w, 0.0, 0.0);
         else
           Launch<double2>::apply(s, op.g, op.kappa64, 0.0, 0.0, 1, Z + (size_t)j * vs + r * n, w);
         launch_cgs2(s, Vr, j + 1, n, vs, w, part, hb, hb + 2 * (m + 1), hb + 4 * (m + 1));

@@ -33,7 +33,8 @@ EXPORTED = ["hfci_default_opts", "hfci_last_error", "hfci_version", "hfci_ctx_cr
             "hfci_net_param_count", "hfci_net_get_params", "hfci_net_set_params", "hfci_net_get_grads",
             "hfci_net_eval", "hfci_net_train_step", "hfci_net_train", "hfci_net_apply", "hfci_op_medium_channel",
             "hfci_net_save", "hfci_net_load", "hfci_op_set_tune", "hfci_op_get_tune", "hfci_op_autotune",
-            "hfci_shifted_solve_batch", "hfci_solve_batch", "hfci_op_case_two", "hfci_contour_q"]
+            "hfci_shifted_solve_batch", "hfci_solve_batch", "hfci_op_case_two", "hfci_contour_q",
+            "hfci_op_create_spectral"]
 PROF_CLASSES = ["fp_stage", "fp_stage_first", "apply", "fp_stage_last", "fp_stage_init"]
 
 
@@ -112,6 +113,7 @@ def load_library(path: str = LIB_PATH):
         "hfci_op_create": (ip, [vp, ip, ip, ip, dp, vp, dp, ip, dp, P(vp)]),
         "hfci_op_destroy": (None, [vp]),
         "hfci_op_case_two": (ip, [vp, P(vp)]),
+        "hfci_op_create_spectral": (ip, [vp, ip, ip, ip, dp, vp, dp, ip, dp, P(vp)]),
         "hfci_op_info": (ip, [vp, P(dp)]),
         "hfci_apply": (ip, [vp, c128, ip, ip, vp, vp]),
         "hfci_contour_create": (ip, [vp, ip, dp, dp, ip, vp, vp, vp, P(vp)]),
@@ -302,6 +304,24 @@ class Operator(_Handle):
     def case_two(self):
         """hfci_op_case_two: the double-size operator B = iC - I of eq. mat-2x2 on this A."""
         return CaseTwoOperator(self)
+
+
+class SpectralOperator(Operator):
+    """hfci_op_create_spectral: the Fourier-spectral Laplacian of Sec. 7.1 on a periodic grid."""
+
+    def __init__(self, ctx: Context, c, h: float, omega: float, damp_cells: int, damp_rho2: float):
+        import torch
+        self.h = ctypes.c_void_p()
+        if c.dim() != 3:
+            raise ValueError("c must be [nz, ny, nx]")
+        self.ctx = ctx
+        self.shape = tuple(c.shape)
+        nz, ny, nx = self.shape
+        _sync()
+        _check(load_library().hfci_op_create_spectral(ctx.h, nx, ny, nz, h, _ptr(c, torch.float64, "c"), omega,
+                                                      damp_cells, damp_rho2, ctypes.byref(self.h)))
+        self.n = nx * ny * nz
+        ctx._adopt(self)
 
 
 class CaseTwoOperator(_Handle):
