@@ -310,6 +310,41 @@ def params_arm(args, ctx, op, f_d, t_mixed, its_mixed):
     return out
 
 
+def spectral_arm(args, ctx):
+    """The Fourier-spectral operator (Sec. 7.1) on the layered medium at 256^3 and the paper's
+    2.25 points per wavelength (its spectral runs, Table 5(a)): contour J = 16, the headline
+    eps, the degree chosen by Sec. 4.2's rule; the mixed-precision solve to the headline
+    tolerance, with the oracle's FP64 residual of the returned u."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from oracle import spectral as OS
+    from paper_1811_12378_amd import hfci
+    ppw = args.spectral_ppw
+    wl = W.config_layered_256(n=args.n, nrhs=1, ppw=ppw)
+    g = hfci.SpectralOperator(ctx, torch.from_numpy(wl.c).cuda(), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
+    c = hfci.Contour(g, args.poles, 1.0, args.eps, 0)
+    f_d = torch.from_numpy(np.stack(wl.rhs)).cuda()
+    hfci.solve(g, c, f_d, opts=hfci.default_opts(precision=32, tol=args.tol, max_it=1))  # workspace, FFT plans
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, st = hfci.solve(g, c, f_d, opts=hfci.default_opts(precision=32, tol=args.tol, max_it=args.max_it))
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    o = OS.SpectralOperator(wl.c, wl.omega, wl.damp_cells, wl.damp_rho2, h=wl.h)
+    b = o.s * wl.rhs[0]
+    ra = float(np.linalg.norm(b - o.apply(u[0].cpu().numpy())) / np.linalg.norm(b))
+    info = g.info()
+    out = {"ppw": ppw, "omega": wl.omega, "q_chosen": c.q, "box": [info["b1"], info["b2"], info["rho2"]],
+           "time_s": round(t, 4), "its": st["its"], "status": st["status"], "stencil_products": st["matvecs"],
+           "fp_steps": st["fp_steps"], "final_relres": st["final_relres"], "relres_oracle": ra}
+    log("spectral %g ppw: q %d, %.3f s, its %d, products %d, relres %.3e (oracle %.3e)"
+        % (ppw, c.q, t, st["its"], st["matvecs"], st["final_relres"], ra))
+    c.close()
+    g.close()
+    return out
+
+
 def case_two_arm(args, ctx, op, cont, wl, solve=True):
     """Case one versus case two (eq. mat-2x2) on the headline workload: the shifted solves of
     one FCI application, every pole of the same contour construction (eq. quad-points with
@@ -420,6 +455,9 @@ def main():
                     help="k_in values of the Alg. 1 step 4 arm (empty list skips it)")
     ap.add_argument("--inner-only", action="store_true",
                     help="run only the headline solve and the Alg. 1 step 4 arm")
+    ap.add_argument("--spectral", action="store_true", help="also run the Fourier-spectral arm")
+    ap.add_argument("--spectral-only", action="store_true", help="run only the Fourier-spectral arm")
+    ap.add_argument("--spectral-ppw", type=float, default=2.25, help="points per wavelength of the spectral arm")
     ap.add_argument("--params", action="store_true",
                     help="also run the contour-choice arm (chosen q, ellipse t = 0.1)")
     ap.add_argument("--case-two-eps", type=float, default=0.0,
@@ -454,6 +492,14 @@ def main():
         ctx = hfci.Context(0)
         r = small_configs_arm(args, ctx)
         print(json.dumps({"metric": "small configurations", "small_configs": r}), flush=True)
+        return
+    if args.spectral_only:
+        ctx = hfci.Context(0)
+        r = spectral_arm(args, ctx)
+        print(json.dumps({"metric": "spectral time-to-%g (s)" % args.tol, "value": r["time_s"], "unit": "s",
+                          "n_gpus": 1, "higher_is_better": False, "dtype": "f32+f64", "data": "synthetic",
+                          "config": {"workload": "layered medium %d^3, Fourier-spectral, %g ppw" % (args.n, r["ppw"])},
+                          "spectral": r}), flush=True)
         return
     if args.uneven_only:
         ctx = hfci.Context(0)
@@ -575,6 +621,10 @@ def main():
     if args.k_in_list:
         inner = inner_arm(args, ctx, op, cont, f_d, t_mixed, st["its"])
 
+    spectral = None
+    if args.spectral:
+        spectral = spectral_arm(args, ctx)
+
     params = None
     if args.params:
         params = params_arm(args, ctx, op, f_d, t_mixed, st["its"])
@@ -638,6 +688,7 @@ def main():
         "case_two": case_two,
         "inner_step4": inner,
         "contour_choice": params,
+        "spectral": spectral,
     }
     print(json.dumps(out), flush=True)
 

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "internal.h"
 
@@ -29,7 +30,8 @@ struct SimpleFactor {
   T2* out2;                    // per system (kFacDual)
   const T2* f;                 // right-hand sides (kFacResid, kFacInF)
   const T2* y1;                // per system (kFacAdd)
-  const int* active;           // [nsys]
+  const int* active;           // [nsys] (device)
+  const int* host_active;      // [nsys] (host): the systems this launch runs
   double* partial;             // [nsys][nblk] (kFacResid)
   int nrhs, nsys;
 };
@@ -71,7 +73,9 @@ void fp_simple(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int
   }
   // every system active for step one
   launch_fp_start(s, nsys, 0, nrhs, fnorm2, true, active, steps, list);
+  std::vector<int> hact(nsys, 1);
   SimpleFactor<T2> a{};
+  a.host_active = hact.data();
   a.f = f;
   a.y1 = y1;
   a.active = active;
@@ -116,7 +120,10 @@ void fp_simple(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int
                      ctx.pinned_int_dev);
       HFCI_HIP(hipStreamSynchronize(s));
       nact = 0;
-      for (int k = 0; k < nsys; ++k) nact += ctx.pinned_int[k] != 0;
+      for (int k = 0; k < nsys; ++k) {
+        hact[k] = ctx.pinned_int[k] != 0;
+        nact += hact[k];
+      }
       if (nact == 0) break;
     }
     if (q == 1) {
