@@ -96,10 +96,15 @@ void shifted_solve_spectral(const Op& op, const Contour& c, int nrhs, const T2* 
   T2* sw = (T2*)ctx.ws.get("sp_sw", (size_t)nsys * op.n * sizeof(T2));
   fp_simple<T2>(op, c, nrhs, f, y, fixed_steps, reduce, max_steps, steps_out, st, spec_blocks(op.g),
                 [&](const SimpleFactor<T2>& sf) {
-                  // S w of the factor's inputs: the right-hand sides (step one's first factor,
-                  // one batch) or the vectors of the systems still iterating, one by one
+                  // S w of the factor's inputs: the right-hand sides (step one's first factor)
+                  // or, when every system iterates, all vectors, each as one batch; else the
+                  // vectors of the systems still iterating, one by one
+                  int nact = 0;
+                  for (int k = 0; k < sf.nsys; ++k) nact += sf.host_active[k] != 0;
                   if ((sf.kind & kFacInF) != 0) {
                     spectral_S<T2>(op, sf.nrhs, sf.in, sw);
+                  } else if (nact == sf.nsys) {
+                    spectral_S<T2>(op, sf.nsys, sf.in, sw);
                   } else {
                     for (int k = 0; k < sf.nsys; ++k)
                       if (sf.host_active[k]) spectral_S<T2>(op, 1, sf.in + (size_t)k * op.n, sw + (size_t)k * op.n);
