@@ -3,9 +3,11 @@
 
 One step = one complete solve of the batched workload: the 256^3 layered medium
 (eight layers, velocities U[1.5, 4.5] times (1 + 0.1 g), 8 points per wavelength,
-8-cell absorbing layer), point sources (1 by default, --nrhs 8 for the full batch), 16 contour poles, exponential-Taylor
-degree q = 8, FCI inside FP64 FGMRES(30), all (pole, RHS) shifted systems advanced
-together.  Inputs are resident in HBM before the timed region starts.
+8-cell absorbing layer), 8 point sources, 16 contour poles, exponential-Taylor degree
+q = 8, FCI inside FP64 FGMRES(30), all 128 (pole, RHS) shifted systems advanced
+together.  Inputs are resident in HBM before the timed region starts.  Further arms
+(opt-in flags): Alg. 1 step 4 (--k-in-list), case two (--case-two), contour choices
+(--params), the Fourier-spectral operator (--spectral).
 
 Prints ONE JSON line on stdout (everything else goes to stderr), carrying:
   value        time-to-1e-6 of the mixed-precision batched solve (s / solve batch)
@@ -433,7 +435,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--poles", type=int, default=16)
     ap.add_argument("--eps", type=float, default=0.25)
     ap.add_argument("--q", type=int, default=8)
@@ -450,9 +452,9 @@ def main():
                     help="instances of the uneven-batch arm (64 = the full config; 0 skips it)")
     ap.add_argument("--uneven-only", action="store_true", help="run only the uneven-batch arm")
     ap.add_argument("--no-small", action="store_true", help="skip the 32^3 / 96^3 configurations")
-    ap.add_argument("--no-case-two", action="store_true", help="skip the case-one versus case-two shifted solves")
-    ap.add_argument("--k-in-list", type=int, nargs="*", default=[2, 4],
-                    help="k_in values of the Alg. 1 step 4 arm (empty list skips it)")
+    ap.add_argument("--case-two", action="store_true", help="also run the case-one versus case-two arm")
+    ap.add_argument("--k-in-list", type=int, nargs="*", default=[],
+                    help="k_in values of the Alg. 1 step 4 arm (none: the arm is skipped)")
     ap.add_argument("--inner-only", action="store_true",
                     help="run only the headline solve and the Alg. 1 step 4 arm")
     ap.add_argument("--spectral", action="store_true", help="also run the Fourier-spectral arm")
@@ -483,8 +485,11 @@ def main():
     from paper_1811_12378_amd import hfci
 
     if args.inner_only:
-        args.no_fp64 = args.no_small = args.no_learned = args.no_cpu = args.no_case_two = True
+        args.no_fp64 = args.no_small = args.no_learned = args.no_cpu = True
+        args.case_two = False
         args.uneven = 0
+        if not args.k_in_list:
+            args.k_in_list = [2, 4]
     hfci.load_library()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     verbose = 0 if args.quiet else 1
@@ -630,7 +635,7 @@ def main():
         params = params_arm(args, ctx, op, f_d, t_mixed, st["its"])
 
     case_two = None
-    if not args.no_case_two:
+    if args.case_two:
         case_two = case_two_arm(args, ctx, op, cont, wl)
 
     learned = None
