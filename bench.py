@@ -385,19 +385,24 @@ def case_two_arm(args, ctx, op, cont, wl, solve=True):
                      "box": [round(o_.info()["b1"], 4), round(o_.info()["b2"], 4), o_.info()["rho2"]]}
         log("%s: %.3f s, steps per pole %s" % (name, t, steps))
         del y
-    # algorithmic bytes of the case-two solve (complex64 blocks, float kappa): a factor reads
-    # x (2 x 8 B) and kappa (4 B) and writes 2 x 8 B per grid point; step one's first factor
-    # reads the right-hand side instead and its last also writes y; a later step's first
-    # factor reads g for the residual, its last reads y1
+    # algorithmic bytes of the case-two solve (complex64 blocks, float kappa): a launch of one
+    # factor or of a pair reads x (2 x 8 B) and kappa (4 B) and writes 2 x 8 B per grid point;
+    # step one runs its q - 1 factors as pairs after a single one when q - 1 is odd, the first
+    # launch reading the right-hand side and the last also writing y; a later step runs
+    # ceil(q / 2) launches (pairs, then a single for odd q), the first reading g for the
+    # residual, the last reading y1
     q, nP = args.q, max(args.q - 1, 1)
+    n1 = nP % 2 + nP // 2 if nP > 1 else 1
+    nl = (q + 1) // 2
     per = 0.0
     for m in out["case_two"]["steps_per_pole"]:
-        per += nP * 36 + 16 + max(m - 1, 0) * (q * 36 + 32) + (36 + 16)
+        per += n1 * 36 + 16 + max(m - 1, 0) * (nl * 36 + 32) + (36 + 16)
     alg = per * n ** 3
     t2 = out["case_two"]["time_s"]
     out["case_two"]["alg_bytes"] = alg
     out["case_two"]["achieved_gbs_wall"] = round(alg / t2 / 1e9, 1)
-    out["case_two"]["kernel"] = "b2_factor_kernel<float, KIND> (one factor per pass, no LDS staging)"
+    out["case_two"]["kernel"] = ("b2_pair_kernel<float, KIND> (two factors per pass; a lone factor: "
+                                 "b2_factor_kernel; no LDS staging)")
     out["stencil_products_ratio_two_over_one"] = round(out["case_two"]["stencil_products"] /
                                                        max(out["case_one"]["stencil_products"], 1), 3)
     out["time_ratio_two_over_one"] = round(t2 / out["case_one"]["time_s"], 3)

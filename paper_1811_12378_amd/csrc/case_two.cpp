@@ -1,7 +1,8 @@
 // Case-two shifted solves (Sec. 3 eq. mat-2x2, Sec. 4.2 eq. fix-pt-exp): for every pole
 // z_j of a contour built on B's spectrum box and every right-hand side g_r (vectors of
 // 2 n values), the polynomial fixed-point iteration for (B - z_j) y = g_r from y = 0 (the
-// loop of fp_simple.h), one b2_factor_kernel launch per factor over all systems.
+// loop of fp_simple.h): the later steps two factors per launch (b2_pair_kernel), step one
+// and a trailing factor of an odd q one per launch (b2_factor_kernel), all systems at once.
 #include "fp_simple.h"
 
 namespace hfci {
@@ -19,7 +20,7 @@ void shifted_solve_case_two(const Op& op, const Contour& c, int nrhs, const T2* 
                             double reduce, int max_steps, int* steps_out, FciStats& st) {
   hipStream_t s = op.ctx->stream;
   const void* K = kappa_for<T2>(op);
-  fp_simple<T2>(op, c, nrhs, f, y, fixed_steps, reduce, max_steps, steps_out, st, b2_blocks(op.g),
+  fp_simple<T2>(op, c, nrhs, f, y, fixed_steps, reduce, max_steps, steps_out, st, b2_blocks(op.g), true,
                 [&](const SimpleFactor<T2>& sf) {
                   B2Args<T2> a{};
                   a.win = sf.in;
@@ -34,7 +35,8 @@ void shifted_solve_case_two(const Op& op, const Contour& c, int nrhs, const T2* 
                   a.nrhs = sf.nrhs;
                   a.cstride = c.cstride;
                   a.k = sf.k;
-                  const bool ok = launch_b2_factor<T2>(s, op.g, K, sf.kind, sf.nsys, a);
+                  const bool ok = sf.nfac == 2 ? launch_b2_pair<T2>(s, op.g, K, sf.kind, sf.nsys, a)
+                                               : launch_b2_factor<T2>(s, op.g, K, sf.kind, sf.nsys, a);
                   HFCI_REQUIRE(ok, "internal: unsupported factor kind");
                 });
 }

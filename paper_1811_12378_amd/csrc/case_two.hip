@@ -7,8 +7,9 @@
 // Kernels: one factor of the product-form fixed-point step (eq. fix-pt-exp, as the
 // factors of params.cpp) over all shifted systems, w_out = a (B - z0) w + b w with the
 // epilogues of the case-one kernels (residual partials, adding y1, a second output),
-// and the plain product (B - shift) x.  One thread per grid point and both blocks; the
-// neighbours of x1 come through the cache (no LDS staging: a single-factor kernel).
+// two consecutive factors in one pass over HBM (b2_pair_kernel), and the plain product
+// (B - shift) x.  One thread per grid point and both blocks; the neighbours come through
+// the cache (no LDS staging).
 #include "kernels.h"
 
 namespace hfci {
@@ -34,6 +35,46 @@ __device__ __forceinline__ Cx<T> cmul(T ar, T ai, Cx<T> v) {
   return Cx<T>{ar * v.x - ai * v.y, ar * v.y + ai * v.x};
 }
 
+template <typename T, typename T2>
+__device__ __forceinline__ Cx<T> ldc(const T2* __restrict__ x, size_t p) {
+  const T2 v = x[p];
+  return Cx<T>{v.x, v.y};
+}
+
+// block 1 of (B - z0) x at a point: -(1 + z0) x1 + i x2
+template <typename T>
+__device__ __forceinline__ Cx<T> b2_block1(Cx<T> x1, Cx<T> x2, T z0r, T z0i) {
+  const Cx<T> s1 = cmul((T)1 + z0r, z0i, x1);
+  return Cx<T>{-s1.x - x2.y, -s1.y + x2.x};
+}
+
+// block 2 of (B - z0) x at a point: -i (A1 + I) x1 - (1 + z0) x2 - i D x2, from the point's
+// x1 and x2, the sum (nr, ni) of x1 over its in-grid neighbours, kappa and the damping D
+template <typename T>
+__device__ __forceinline__ Cx<T> b2_block2(const GridDesc& g, Cx<T> x1, Cx<T> x2, T nr, T ni, T kap, T dmp, T z0r,
+                                           T z0i) {
+  const T sh2 = (T)g.s_h2;
+  // (A1 + I) x1 = s/h^2 (6 x1 - neighbours) - kappa x1 + x1
+  const T ar = sh2 * ((T)6 * x1.x - nr) + ((T)1 - kap) * x1.x;
+  const T ai = sh2 * ((T)6 * x1.y - ni) + ((T)1 - kap) * x1.y;
+  const Cx<T> s2 = cmul((T)1 + z0r, z0i, x2);
+  return Cx<T>{ai - s2.x + dmp * x2.y, -ar - s2.y - dmp * x2.x};
+}
+
+template <typename T>
+__device__ __forceinline__ T b2_damping(const GridDesc& g, int i, int j, int k) {
+  const int d = max(max(depth_in_layer(i, g.nx, g.damp_cells), depth_in_layer(j, g.ny, g.damp_cells)),
+                    depth_in_layer(k, g.nz, g.damp_cells));
+  return (T)(d * d) * (T)g.damp_scale;
+}
+
+// one factor at a point: a o + b x, with o = (B - z0) x there
+template <typename T>
+__device__ __forceinline__ Cx<T> b2_fac(T ar, T ai, T br, T bi, Cx<T> o, Cx<T> x) {
+  const Cx<T> u = cmul(ar, ai, o), v = cmul(br, bi, x);
+  return Cx<T>{u.x + v.x, u.y + v.y};
+}
+
 // (B - z0) x at point p = i + nx (j + ny k) of the vector x (x1 at x, x2 at x + npt);
 // also returns the point's x1 and x2.
 template <typename T, typename T2>
@@ -41,10 +82,8 @@ __device__ __forceinline__ void b2_point(const GridDesc& g, const T* __restrict_
                                          size_t npt, size_t p, int i, int j, int k, T z0r, T z0i, Cx<T>& o1,
                                          Cx<T>& o2, Cx<T>& x1, Cx<T>& x2) {
   const size_t sx = 1, sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
-  const T2 c = x[p];
-  x1 = Cx<T>{c.x, c.y};
-  const T2 c2 = x[npt + p];
-  x2 = Cx<T>{c2.x, c2.y};
+  x1 = ldc<T>(x, p);
+  x2 = ldc<T>(x, npt + p);
   T nr = (T)0, ni = (T)0;
   if (i > 0) { const T2 v = x[p - sx]; nr += v.x; ni += v.y; }
   if (i + 1 < g.nx) { const T2 v = x[p + sx]; nr += v.x; ni += v.y; }
@@ -52,18 +91,8 @@ __device__ __forceinline__ void b2_point(const GridDesc& g, const T* __restrict_
   if (j + 1 < g.ny) { const T2 v = x[p + sy]; nr += v.x; ni += v.y; }
   if (k > 0) { const T2 v = x[p - sz]; nr += v.x; ni += v.y; }
   if (k + 1 < g.nz) { const T2 v = x[p + sz]; nr += v.x; ni += v.y; }
-  const T sh2 = (T)g.s_h2, kap = K[p];
-  // (A1 + I) x1 = s/h^2 (6 x1 - neighbours) - kappa x1 + x1
-  const T ar = sh2 * ((T)6 * x1.x - nr) + ((T)1 - kap) * x1.x;
-  const T ai = sh2 * ((T)6 * x1.y - ni) + ((T)1 - kap) * x1.y;
-  const int d = max(max(depth_in_layer(i, g.nx, g.damp_cells), depth_in_layer(j, g.ny, g.damp_cells)),
-                    depth_in_layer(k, g.nz, g.damp_cells));
-  const T dmp = (T)(d * d) * (T)g.damp_scale;
-  const Cx<T> s1 = cmul((T)1 + z0r, z0i, x1), s2 = cmul((T)1 + z0r, z0i, x2);
-  // block 1: -(1 + z0) x1 + i x2
-  o1 = Cx<T>{-s1.x - x2.y, -s1.y + x2.x};
-  // block 2: -i (A1 + I) x1 - (1 + z0) x2 - i D x2
-  o2 = Cx<T>{ai - s2.x + dmp * x2.y, -ar - s2.y - dmp * x2.x};
+  o1 = b2_block1(x1, x2, z0r, z0i);
+  o2 = b2_block2(g, x1, x2, nr, ni, K[p], b2_damping<T>(g, i, j, k), z0r, z0i);
 }
 
 __device__ __forceinline__ double block_sum_nt(double v, double* sh) {
@@ -104,13 +133,12 @@ __global__ __launch_bounds__(NT) void b2_factor_kernel(GridDesc g, const T* __re
     const int i = (int)(p % g.nx), j = (int)((p / g.nx) % g.ny), k = (int)(p / ((size_t)g.nx * g.ny));
     Cx<T> o1, o2, x1, x2;
     b2_point<T, T2>(g, K, X, npt, p, i, j, k, z0r, z0i, o1, o2, x1, x2);
-    const Cx<T> u1 = cmul(car, cai, o1), v1 = cmul(cbr, cbi, x1);
-    const Cx<T> u2 = cmul(car, cai, o2), v2 = cmul(cbr, cbi, x2);
+    const Cx<T> c1 = b2_fac(car, cai, cbr, cbi, o1, x1), c2 = b2_fac(car, cai, cbr, cbi, o2, x2);
     T2 w1, w2;
-    w1.x = u1.x + v1.x;
-    w1.y = u1.y + v1.y;
-    w2.x = u2.x + v2.x;
-    w2.y = u2.y + v2.y;
+    w1.x = c1.x;
+    w1.y = c1.y;
+    w2.x = c2.x;
+    w2.y = c2.y;
     if constexpr (ADD) {
       const T2 a1 = Y1[p], a2 = Y1[npt + p];
       w1.x += a1.x;
@@ -126,6 +154,95 @@ __global__ __launch_bounds__(NT) void b2_factor_kernel(GridDesc g, const T* __re
     }
     if constexpr (RESID) {
       // g - (B - z) y = g - (B - z0) y + (z - z0) y, both blocks, in FP64
+      const double zr = pd.zz_re, zi = pd.zz_im;
+      const T2 g1 = F[p], g2 = F[npt + p];
+      const double r1x = (double)g1.x - (double)o1.x + zr * (double)x1.x - zi * (double)x1.y;
+      const double r1y = (double)g1.y - (double)o1.y + zr * (double)x1.y + zi * (double)x1.x;
+      const double r2x = (double)g2.x - (double)o2.x + zr * (double)x2.x - zi * (double)x2.y;
+      const double r2y = (double)g2.y - (double)o2.y + zr * (double)x2.y + zi * (double)x2.x;
+      acc += r1x * r1x + r1y * r1y + r2x * r2x + r2y * r2y;
+    }
+  }
+  if constexpr (RESID) {
+    const double t = block_sum_nt(acc, sh);
+    if (threadIdx.x == 0) a.partial[(size_t)s * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// Two consecutive factors k and k + 1 of one step in one pass: w_out = F_{k+1}(F_k(w)).
+// Block one of B is pointwise, so the intermediate x1' at a neighbour is formed from the
+// input there (its Dirichlet ghosts stay zero) and one gather of x1 and x2 at the 7 points
+// serves both factors; the intermediate x2' is needed at the point only.  Kind bits on the
+// input: kFacResid (the residual partials of w, as the single factor), kFacInF (the input is
+// the right-hand side); on the output: kFacAdd (adds y1), kFacDual (a second output).
+template <typename T, int KIND>
+__global__ __launch_bounds__(NT) void b2_pair_kernel(GridDesc g, const T* __restrict__ K,
+                                                     B2Args<typename Vec2<T>::t> a) {
+  using T2 = typename Vec2<T>::t;
+  constexpr bool RESID = (KIND & kFacResid) != 0, ADD = (KIND & kFacAdd) != 0, DUAL = (KIND & kFacDual) != 0,
+                 INF = (KIND & kFacInF) != 0;
+  __shared__ double sh[NT / 64];
+  const int s = blockIdx.y;
+  if (a.active[s] == 0) return;  // block-uniform: stopped systems are skipped
+  const int pole = s / a.nrhs, r = s % a.nrhs;
+  const size_t npt = (size_t)g.nx * g.ny * g.nz, n2 = 2 * npt;
+  const FactorCoef f1 = a.coef[(size_t)pole * a.cstride + a.k], f2 = a.coef[(size_t)pole * a.cstride + a.k + 1];
+  const PoleDev pd = a.poles[pole];
+  const T a1r = (T)f1.a_re, a1i = (T)f1.a_im, b1r = (T)f1.b_re, b1i = (T)f1.b_im;
+  const T a2r = (T)f2.a_re, a2i = (T)f2.a_im, b2r = (T)f2.b_re, b2i = (T)f2.b_im;
+  const T z0r = (T)pd.z0_re, z0i = (T)pd.z0_im;
+  const T2* __restrict__ X = INF ? a.win + (size_t)r * n2 : a.win + (size_t)s * n2;
+  const T2* __restrict__ F = a.f + (size_t)r * n2;
+  const T2* __restrict__ Y1 = a.y1 + (size_t)s * n2;
+  T2* __restrict__ O = a.wout + (size_t)s * n2;
+  T2* __restrict__ O2 = DUAL ? a.wout2 + (size_t)s * n2 : nullptr;
+  const size_t sx = 1, sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  double acc = 0.0;
+  const size_t stride = (size_t)gridDim.x * NT;
+  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < npt; p += stride) {
+    const int i = (int)(p % g.nx), j = (int)((p / g.nx) % g.ny), k = (int)(p / ((size_t)g.nx * g.ny));
+    const Cx<T> x1 = ldc<T>(X, p), x2 = ldc<T>(X, npt + p);
+    // neighbour sums of x1 (first factor) and of the first factor's x1' (second factor)
+    T nr = (T)0, ni = (T)0, mr = (T)0, mi = (T)0;
+    auto nb = [&](size_t q) {
+      const Cx<T> u1 = ldc<T>(X, q), u2 = ldc<T>(X, npt + q);
+      nr += u1.x;
+      ni += u1.y;
+      const Cx<T> v = b2_fac(a1r, a1i, b1r, b1i, b2_block1(u1, u2, z0r, z0i), u1);
+      mr += v.x;
+      mi += v.y;
+    };
+    if (i > 0) nb(p - sx);
+    if (i + 1 < g.nx) nb(p + sx);
+    if (j > 0) nb(p - sy);
+    if (j + 1 < g.ny) nb(p + sy);
+    if (k > 0) nb(p - sz);
+    if (k + 1 < g.nz) nb(p + sz);
+    const T kap = K[p], dmp = b2_damping<T>(g, i, j, k);
+    const Cx<T> o1 = b2_block1(x1, x2, z0r, z0i), o2 = b2_block2(g, x1, x2, nr, ni, kap, dmp, z0r, z0i);
+    // the first factor at the point (t1, t2), then the second
+    const Cx<T> t1 = b2_fac(a1r, a1i, b1r, b1i, o1, x1), t2 = b2_fac(a1r, a1i, b1r, b1i, o2, x2);
+    const Cx<T> p1 = b2_block1(t1, t2, z0r, z0i), p2 = b2_block2(g, t1, t2, mr, mi, kap, dmp, z0r, z0i);
+    const Cx<T> c1 = b2_fac(a2r, a2i, b2r, b2i, p1, t1), c2 = b2_fac(a2r, a2i, b2r, b2i, p2, t2);
+    T2 w1, w2;
+    w1.x = c1.x;
+    w1.y = c1.y;
+    w2.x = c2.x;
+    w2.y = c2.y;
+    if constexpr (ADD) {
+      const T2 e1 = Y1[p], e2 = Y1[npt + p];
+      w1.x += e1.x;
+      w1.y += e1.y;
+      w2.x += e2.x;
+      w2.y += e2.y;
+    }
+    O[p] = w1;
+    O[npt + p] = w2;
+    if constexpr (DUAL) {
+      O2[p] = w1;
+      O2[npt + p] = w2;
+    }
+    if constexpr (RESID) {
       const double zr = pd.zz_re, zi = pd.zz_im;
       const T2 g1 = F[p], g2 = F[npt + p];
       const double r1x = (double)g1.x - (double)o1.x + zr * (double)x1.x - zi * (double)x1.y;
@@ -230,6 +347,12 @@ void launch_kind(hipStream_t st, const GridDesc& g, const T* K, int nsys, int nb
   hipLaunchKernelGGL((b2_factor_kernel<T, KIND>), dim3((unsigned)nblk, (unsigned)nsys), dim3(NT), 0, st, g, K, a);
 }
 
+template <typename T, int KIND>
+void launch_pair_kind(hipStream_t st, const GridDesc& g, const T* K, int nsys, int nblk,
+                      const B2Args<typename Vec2<T>::t>& a) {
+  hipLaunchKernelGGL((b2_pair_kernel<T, KIND>), dim3((unsigned)nblk, (unsigned)nsys), dim3(NT), 0, st, g, K, a);
+}
+
 }  // namespace
 
 int b2_blocks(const GridDesc& g) {
@@ -260,6 +383,26 @@ bool launch_b2_factor(hipStream_t st, const GridDesc& g, const void* K, int kind
 template bool launch_b2_factor<float2>(hipStream_t, const GridDesc&, const void*, int, int, const B2Args<float2>&);
 template bool launch_b2_factor<double2>(hipStream_t, const GridDesc&, const void*, int, int,
                                         const B2Args<double2>&);
+
+template <typename T2>
+bool launch_b2_pair(hipStream_t st, const GridDesc& g, const void* K, int kind, int nsys, const B2Args<T2>& a) {
+  using T = typename Scal<T2>::t;
+  const T* k = (const T*)K;
+  const int nb = b2_blocks(g);
+  if (nsys <= 0) return true;
+  switch (kind) {
+    case 0: launch_pair_kind<T, 0>(st, g, k, nsys, nb, a); return true;
+    case kFacResid: launch_pair_kind<T, kFacResid>(st, g, k, nsys, nb, a); return true;
+    case kFacAdd: launch_pair_kind<T, kFacAdd>(st, g, k, nsys, nb, a); return true;
+    case kFacResid | kFacAdd: launch_pair_kind<T, kFacResid | kFacAdd>(st, g, k, nsys, nb, a); return true;
+    case kFacInF: launch_pair_kind<T, kFacInF>(st, g, k, nsys, nb, a); return true;
+    case kFacDual: launch_pair_kind<T, kFacDual>(st, g, k, nsys, nb, a); return true;
+    case kFacInF | kFacDual: launch_pair_kind<T, kFacInF | kFacDual>(st, g, k, nsys, nb, a); return true;
+    default: return false;
+  }
+}
+template bool launch_b2_pair<float2>(hipStream_t, const GridDesc&, const void*, int, int, const B2Args<float2>&);
+template bool launch_b2_pair<double2>(hipStream_t, const GridDesc&, const void*, int, int, const B2Args<double2>&);
 
 template <typename T2>
 void launch_b2_apply(hipStream_t st, const GridDesc& g, const void* K, int nvec, const T2* x, T2* y, double sr,

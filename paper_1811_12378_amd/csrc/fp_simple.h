@@ -5,7 +5,10 @@
 // max(q-1, 1) factors; every later step is y <- L y + y1 with q factors, the first of which
 // also forms the residual partials of the current y for the stopping test
 // ||g - (A - z) y|| <= ||g|| / reduce.  Stopped systems skip their blocks; the host reads
-// the flags once a step.  The operator supplies one factor launch.
+// the flags once a step.  The operator supplies one factor launch, and optionally a launch
+// of two consecutive factors in one pass: step one then runs as a leading single factor
+// when q - 1 is odd plus pairs, and a later step as pairs (the first with the residual of
+// its input) plus a trailing single factor when q is odd.
 #pragma once
 
 #include <algorithm>
@@ -25,6 +28,8 @@ void launch_copy_active_d(hipStream_t st, double2* dst, const double2* src, cons
 template <typename T2>
 struct SimpleFactor {
   int kind, k;                 // kFac* bits; coefficient index within the pole's cstride
+  int nfac;                    // factors of this launch: 1, or 2 (k and k + 1; kFacResid and
+                               // kFacInF apply to the input, kFacAdd and kFacDual to the output)
   const T2* in;                // per system, or per rhs with kFacInF
   T2* out;                     // per system
   T2* out2;                    // per system (kFacDual)
@@ -44,10 +49,11 @@ inline void copy_active_sys(hipStream_t st, double2* d, const double2* s, const 
 }
 
 // nblk: residual partials per system of the operator's factor launch; factor(const
-// SimpleFactor<T2>&) launches one factor over all systems.
+// SimpleFactor<T2>&) launches sf.nfac factors over all systems, and is given nfac = 2 only
+// when pairs is set.
 template <typename T2, typename Factor>
 void fp_simple(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int fixed_steps, double reduce,
-               int max_steps, int* steps_out, FciStats& st, int nblk, Factor&& factor) {
+               int max_steps, int* steps_out, FciStats& st, int nblk, bool pairs, Factor&& factor) {
   Ctx& ctx = *op.ctx;
   hipStream_t s = ctx.stream;
   const size_t n = op.n;
@@ -82,9 +88,10 @@ void fp_simple(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int
   a.partial = partial;
   a.nrhs = nrhs;
   a.nsys = nsys;
-  auto run = [&](int kind, int k, const T2* in, T2* out, T2* out2) {
+  auto run = [&](int kind, int k, const T2* in, T2* out, T2* out2, int nfac) {
     a.kind = kind;
     a.k = k;
+    a.nfac = nfac;
     a.in = in;
     a.out = out;
     a.out2 = out2;
@@ -94,13 +101,15 @@ void fp_simple(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int
   const int nP = std::max(q - 1, 1);
   {
     const T2* cur = f;
-    for (int i = 0; i < nP; ++i) {
-      const bool first = i == 0, last = i + 1 == nP;
+    for (int i = 0; i < nP;) {
+      const int nf = pairs && (nP - i) % 2 == 0 ? 2 : 1;
+      const bool first = i == 0, last = i + nf == nP;
       T2* dst = last ? y1 : (cur == wA ? wB : wA);
       int kind = first ? kFacInF : 0;
       if (last) kind |= kFacDual;
-      run(kind, q + i, cur, dst, last ? y : nullptr);
+      run(kind, q + i, cur, dst, last ? y : nullptr, nf);
       cur = dst;
+      i += nf;
     }
     st.matvecs += (long long)nP * nsys;
     st.fp_steps += nsys;
@@ -109,12 +118,14 @@ void fp_simple(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int
   launch_fp_start(s, nsys, 0, nrhs, fnorm2, fixed, active, steps, list);
   int nact = nsys;
   const int cap = fixed ? fixed_steps : max_steps;
+  // factors of the head launch of a later step
+  const int nh = pairs && q >= 2 ? 2 : 1;
   for (int it = 1; it <= cap; ++it) {
     if (fixed && it == cap) break;
-    // head: the first factor of L on y (with the residual of y when adaptive)
-    const int head_kind = (fixed ? 0 : kFacResid) | (q == 1 ? kFacAdd : 0);
-    run(head_kind, 0, y, wA, nullptr);
-    st.matvecs += nact;
+    // head: the first factor (or pair) of L on y, with the residual of y when adaptive
+    const int head_kind = (fixed ? 0 : kFacResid) | (q == nh ? kFacAdd : 0);
+    run(head_kind, 0, y, wA, nullptr, nh);
+    st.matvecs += (long long)nh * nact;
     if (!fixed) {
       launch_fp_test(s, partial, nblk, nsys, 0, nrhs, fnorm2, reduce, max_steps, active, steps, rnorm2, list,
                      ctx.pinned_int_dev);
@@ -126,18 +137,21 @@ void fp_simple(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int
       }
       if (nact == 0) break;
     }
-    if (q == 1) {
+    if (q == nh) {
+      // the head wrote the whole step (a launch never writes its own input)
       copy_active_sys(s, y, wA, active, nsys, n);
     } else {
       const T2* cur = wA;
-      for (int k = 1; k < q; ++k) {
-        const bool last = k + 1 == q;
+      for (int k = nh; k < q;) {
+        const int nf = pairs && k + 1 < q ? 2 : 1;
+        const bool last = k + nf == q;
         T2* dst = last ? y : (cur == wA ? wB : wA);
-        run(last ? kFacAdd : 0, k, cur, dst, nullptr);
+        run(last ? kFacAdd : 0, k, cur, dst, nullptr, nf);
         cur = dst;
+        k += nf;
       }
     }
-    st.matvecs += (long long)(q - 1) * nact;
+    st.matvecs += (long long)(q - nh) * nact;
     st.fp_steps += nact;
   }
   if (steps_out && fixed) {

@@ -263,6 +263,11 @@ template <typename T2>
 void shifted_solve_spectral(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int fixed_steps,
                             double reduce, int max_steps, int* steps_out, FciStats& st);
 void spectral_release(Ctx& ctx);
+// case_two.hip: factors k and k + 1 of a case-two fixed-point step in one pass (a.k is k;
+// kind: kFacResid or kFacInF on the input, kFacAdd or kFacDual on the output); false for
+// other kind bits
+template <typename T2>
+bool launch_b2_pair(hipStream_t st, const GridDesc& g, const void* K, int kind, int nsys, const B2Args<T2>& a);
 // case_two.cpp: the shifted solves of a case-two operator (op.form == 2)
 template <typename T2>
 void shifted_solve_case_two(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int fixed_steps,

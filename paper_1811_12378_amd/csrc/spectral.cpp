@@ -94,11 +94,12 @@ void shifted_solve_spectral(const Op& op, const Contour& c, int nrhs, const T2* 
   const void* K = kappa_for<T2>(op);
   const int nsys = c.J * nrhs;
   T2* sw = (T2*)ctx.ws.get("sp_sw", (size_t)nsys * op.n * sizeof(T2));
-  fp_simple<T2>(op, c, nrhs, f, y, fixed_steps, reduce, max_steps, steps_out, st, spec_blocks(op.g),
+  fp_simple<T2>(op, c, nrhs, f, y, fixed_steps, reduce, max_steps, steps_out, st, spec_blocks(op.g), false,
                 [&](const SimpleFactor<T2>& sf) {
                   // S w of the factor's inputs: the right-hand sides (step one's first factor)
                   // or, when every system iterates, all vectors, each as one batch; else the
                   // vectors of the systems still iterating, one by one
+                  HFCI_REQUIRE(sf.nfac == 1, "internal: the spectral factors run one per launch");
                   int nact = 0;
                   for (int k = 0; k < sf.nsys; ++k) nact += sf.host_active[k] != 0;
                   if ((sf.kind & kFacInF) != 0) {

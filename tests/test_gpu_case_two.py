@@ -95,7 +95,8 @@ def test_case_two_box_and_contour(ctx):
 
 
 @pytest.mark.parametrize("prec,q,steps", [("f64", 8, 3), ("f64", 3, 4), ("f64", 2, 2), ("f64", 1, 3),
-                                          ("f64", 4, 1), ("f32", 8, 3), ("f32", 3, 2)])
+                                          ("f64", 4, 1), ("f64", 5, 2), ("f64", 7, 2), ("f32", 8, 3),
+                                          ("f32", 3, 2), ("f32", 5, 2)])
 def test_case_two_shifted_solve_fixed_steps(ctx, prec, q, steps):
     o2, g2, _ = make(ctx, (9, 17, 33), 5, 18.0, 3, 1.0)
     poles, cg = contour_pair(o2, g2, 4, q)
@@ -113,7 +114,39 @@ def test_case_two_shifted_solve_fixed_steps(ctx, prec, q, steps):
             assert rel(y[j, r], ref) <= tol, (j, r, rel(y[j, r], ref))
 
 
-@pytest.mark.parametrize("q", [1, 2, 3, 8])
+@pytest.mark.parametrize("prec,q", [("f64", 8), ("f64", 5), ("f32", 8)])
+def test_case_two_shifted_solve_larger_grid(ctx, prec, q):
+    # the pair and single factor kernels on a grid of several workgroups per system (48 at
+    # 16 x 24 x 32 points), fixed steps and adaptive
+    o2, g2, _ = make(ctx, (16, 24, 32), 21, 16.0, 3, 1.0)
+    poles, cg = contour_pair(o2, g2, 4, q)
+    rng = np.random.default_rng(22)
+    f = rng.standard_normal((2,) + o2.shape) + 1j * rng.standard_normal((2,) + o2.shape)
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    y, st = hf.shifted_solve(g2, cg, dev(f).to(dt), steps=2)
+    y = host(y)
+    assert np.all(st == 2)
+    Bm = lambda v, sh: o2.apply(v, sh)
+    tol = 1e-12 if prec == "f64" else 2e-4
+    for j, p in enumerate(poles):
+        for r in range(2):
+            ref, _ = OFP.fixed_point_solve(Bm, f[r], p.z, p.z0, p.delta, q, steps=2)
+            assert rel(y[j, r], ref) <= tol, (j, r, rel(y[j, r], ref))
+    # adaptive, with a zero right-hand side among iterating ones
+    f[1] = 0.0
+    y, st = hf.shifted_solve(g2, cg, dev(f).to(dt), reduce=5.0, max_steps=60)
+    y = host(y)
+    for j, p in enumerate(poles):
+        assert st[j, 1] == 0 and np.all(y[j, 1] == 0)
+        ref, hist = OFP.fixed_point_solve(Bm, f[0], p.z, p.z0, p.delta, q, reduce=5.0, m_max=60)
+        if prec == "f64":
+            assert st[j, 0] == len(hist) - 1, (j, st[j, 0], len(hist) - 1)
+            assert rel(y[j, 0], ref) <= 1e-12
+        else:
+            assert abs(int(st[j, 0]) - (len(hist) - 1)) <= 1
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 5, 8])
 def test_case_two_shifted_solve_adaptive(ctx, q):
     # every (pole, rhs) stops at the oracle's step with the oracle's iterate; rhs 1 is
     # zero: its systems stop at step 0 with y = 0 while the others iterate, so the later
