@@ -1,7 +1,7 @@
-// Shifted solves with one launch per factor over every shifted system, for the operators
-// whose factors are not fused two per pass (case two, the Fourier-spectral operator): the
-// loop of the product-form fixed-point iteration (eq. fix-pt-exp, factors of params.cpp)
-// for (A - z_j) y = g_r from y = 0.  Step one builds y1 = P2(A) g / p~(z) with
+// Shifted solves with one launch per factor (or per pair of factors) over every shifted
+// system, for the operators without the z-marching stencil kernels (case two, the
+// Fourier-spectral operator): the loop of the product-form fixed-point iteration
+// (eq. fix-pt-exp, factors of params.cpp) for (A - z_j) y = g_r from y = 0.  Step one builds y1 = P2(A) g / p~(z) with
 // max(q-1, 1) factors; every later step is y <- L y + y1 with q factors, the first of which
 // also forms the residual partials of the current y for the stopping test
 // ||g - (A - z) y|| <= ||g|| / reduce.  Stopped systems skip their blocks; the host reads
