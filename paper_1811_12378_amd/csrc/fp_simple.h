@@ -1,9 +1,10 @@
 // Shifted solves with one launch per factor (or per pair of factors) over every shifted
 // system, for the operators without the z-marching stencil kernels (case two, the
 // Fourier-spectral operator): the loop of the product-form fixed-point iteration
-// (eq. fix-pt-exp, factors of params.cpp) for (A - z_j) y = g_r from y = 0.  Step one builds y1 = P2(A) g / p~(z) with
-// max(q-1, 1) factors; every later step is y <- L y + y1 with q factors, the first of which
-// also forms the residual partials of the current y for the stopping test
+// (eq. fix-pt-exp, factors of params.cpp) for (A - z_j) y = g_r from y = 0.  Step one
+// builds y1 = P2(A) g / p~(z) with max(q-1, 1) factors; every later step is y <- L y + y1
+// with q factors, the first of which also forms the residual partials of the current y for
+// the stopping test
 // ||g - (A - z) y|| <= ||g|| / reduce.  Stopped systems skip their blocks; the host reads
 // the flags once a step.  The operator supplies one factor launch, and optionally a launch
 // of two consecutive factors in one pass: step one then runs as a leading single factor
