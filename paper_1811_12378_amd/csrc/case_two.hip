@@ -171,10 +171,24 @@ __global__ __launch_bounds__(NT) void b2_factor_kernel(GridDesc g, const T* __re
 
 // Two consecutive factors k and k + 1 of one step in one pass: w_out = F_{k+1}(F_k(w)).
 // Block one of B is pointwise, so the intermediate x1' at a neighbour is formed from the
-// input there (its Dirichlet ghosts stay zero) and one gather of x1 and x2 at the 7 points
-// serves both factors; the intermediate x2' is needed at the point only.  Kind bits on the
-// input: kFacResid (the residual partials of w, as the single factor), kFacInF (the input is
-// the right-hand side); on the output: kFacAdd (adds y1), kFacDual (a second output).
+// input there (its Dirichlet ghosts stay zero), and a one-point halo of the input serves
+// both factors; the intermediate x2' is needed at the point only.  Kind bits on the input:
+// kFacResid (the residual partials of w, as the single factor), kFacInF (the input is the
+// right-hand side); on the output: kFacAdd (adds y1), kFacDual (a second output).
+//
+// z-marching: a workgroup of PTX x PTY threads takes tiles of PTX x PTY columns by PCZ
+// planes (a grid-stride loop over the tiles of its system, so the residual partials keep
+// the single factor's layout); each thread carries x1 and x2 of planes k - 1, k and k + 1
+// of its column in registers and gathers only the in-plane neighbours through the cache.
+// With a grid width that is a multiple of 8 the workgroups of one XCD (blockIdx.x % 8)
+// sweep one contiguous eighth of the tiles.
+constexpr int PTX = 64, PTY = NT / PTX, PCZ = 32;
+
+template <typename T>
+struct Pt2 {
+  Cx<T> a, b;  // x1, x2 at a point
+};
+
 template <typename T, int KIND>
 __global__ __launch_bounds__(NT) void b2_pair_kernel(GridDesc g, const T* __restrict__ K,
                                                      B2Args<typename Vec2<T>::t> a) {
@@ -196,60 +210,80 @@ __global__ __launch_bounds__(NT) void b2_pair_kernel(GridDesc g, const T* __rest
   const T2* __restrict__ Y1 = a.y1 + (size_t)s * n2;
   T2* __restrict__ O = a.wout + (size_t)s * n2;
   T2* __restrict__ O2 = DUAL ? a.wout2 + (size_t)s * n2 : nullptr;
-  const size_t sx = 1, sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+  const int gx = (g.nx + PTX - 1) / PTX, gy = (g.ny + PTY - 1) / PTY, gz = (g.nz + PCZ - 1) / PCZ;
+  const int ntile = gx * gy * gz;
+  const int nsl = gridDim.x % 8 == 0 ? 8 : 1;
+  const int tps = (ntile + nsl - 1) / nsl;
+  const int t_lo = (int)(blockIdx.x % nsl) * tps, t_hi = min(ntile, t_lo + tps);
+  const int tx = threadIdx.x % PTX, ty = threadIdx.x / PTX;
+  const Pt2<T> zero{Cx<T>{(T)0, (T)0}, Cx<T>{(T)0, (T)0}};
+  auto ld2 = [&](size_t q) { return Pt2<T>{ldc<T>(X, q), ldc<T>(X, npt + q)}; };
+  // the first factor's x1' at a point from x1, x2 there (zero at a ghost)
+  auto fac1 = [&](const Pt2<T>& u) { return b2_fac(a1r, a1i, b1r, b1i, b2_block1(u.a, u.b, z0r, z0i), u.a); };
   double acc = 0.0;
-  const size_t stride = (size_t)gridDim.x * NT;
-  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < npt; p += stride) {
-    const int i = (int)(p % g.nx), j = (int)((p / g.nx) % g.ny), k = (int)(p / ((size_t)g.nx * g.ny));
-    const Cx<T> x1 = ldc<T>(X, p), x2 = ldc<T>(X, npt + p);
-    // neighbour sums of x1 (first factor) and of the first factor's x1' (second factor)
-    T nr = (T)0, ni = (T)0, mr = (T)0, mi = (T)0;
-    auto nb = [&](size_t q) {
-      const Cx<T> u1 = ldc<T>(X, q), u2 = ldc<T>(X, npt + q);
-      nr += u1.x;
-      ni += u1.y;
-      const Cx<T> v = b2_fac(a1r, a1i, b1r, b1i, b2_block1(u1, u2, z0r, z0i), u1);
-      mr += v.x;
-      mi += v.y;
-    };
-    if (i > 0) nb(p - sx);
-    if (i + 1 < g.nx) nb(p + sx);
-    if (j > 0) nb(p - sy);
-    if (j + 1 < g.ny) nb(p + sy);
-    if (k > 0) nb(p - sz);
-    if (k + 1 < g.nz) nb(p + sz);
-    const T kap = K[p], dmp = b2_damping<T>(g, i, j, k);
-    const Cx<T> o1 = b2_block1(x1, x2, z0r, z0i), o2 = b2_block2(g, x1, x2, nr, ni, kap, dmp, z0r, z0i);
-    // the first factor at the point (t1, t2), then the second
-    const Cx<T> t1 = b2_fac(a1r, a1i, b1r, b1i, o1, x1), t2 = b2_fac(a1r, a1i, b1r, b1i, o2, x2);
-    const Cx<T> p1 = b2_block1(t1, t2, z0r, z0i), p2 = b2_block2(g, t1, t2, mr, mi, kap, dmp, z0r, z0i);
-    const Cx<T> c1 = b2_fac(a2r, a2i, b2r, b2i, p1, t1), c2 = b2_fac(a2r, a2i, b2r, b2i, p2, t2);
-    T2 w1, w2;
-    w1.x = c1.x;
-    w1.y = c1.y;
-    w2.x = c2.x;
-    w2.y = c2.y;
-    if constexpr (ADD) {
-      const T2 e1 = Y1[p], e2 = Y1[npt + p];
-      w1.x += e1.x;
-      w1.y += e1.y;
-      w2.x += e2.x;
-      w2.y += e2.y;
-    }
-    O[p] = w1;
-    O[npt + p] = w2;
-    if constexpr (DUAL) {
-      O2[p] = w1;
-      O2[npt + p] = w2;
-    }
-    if constexpr (RESID) {
-      const double zr = pd.zz_re, zi = pd.zz_im;
-      const T2 g1 = F[p], g2 = F[npt + p];
-      const double r1x = (double)g1.x - (double)o1.x + zr * (double)x1.x - zi * (double)x1.y;
-      const double r1y = (double)g1.y - (double)o1.y + zr * (double)x1.y + zi * (double)x1.x;
-      const double r2x = (double)g2.x - (double)o2.x + zr * (double)x2.x - zi * (double)x2.y;
-      const double r2y = (double)g2.y - (double)o2.y + zr * (double)x2.y + zi * (double)x2.x;
-      acc += r1x * r1x + r1y * r1y + r2x * r2x + r2y * r2y;
+  for (int t = t_lo + (int)(blockIdx.x / nsl); t < t_hi; t += (int)(gridDim.x / nsl)) {
+    const int i = (t % gx) * PTX + tx, j = ((t / gx) % gy) * PTY + ty, zc = t / (gx * gy);
+    const int zb = zc * PCZ, ze = min(g.nz, zb + PCZ);
+    if (i >= g.nx || j >= g.ny) continue;  // no barrier inside the tile loop
+    const size_t col = (size_t)i + sy * (size_t)j;
+    Pt2<T> xm = zb > 0 ? ld2(col + sz * (size_t)(zb - 1)) : zero;
+    Pt2<T> xc = ld2(col + sz * (size_t)zb);
+    for (int k = zb; k < ze; ++k) {
+      const size_t p = col + sz * (size_t)k;
+      const Pt2<T> xp = k + 1 < g.nz ? ld2(p + sz) : zero;
+      // neighbour sums of x1 (first factor) and of the first factor's x1' (second factor),
+      // in the order -x, +x, -y, +y, -z, +z
+      T nr = (T)0, ni = (T)0, mr = (T)0, mi = (T)0;
+      auto add = [&](const Pt2<T>& u) {
+        nr += u.a.x;
+        ni += u.a.y;
+        const Cx<T> v = fac1(u);
+        mr += v.x;
+        mi += v.y;
+      };
+      if (i > 0) add(ld2(p - 1));
+      if (i + 1 < g.nx) add(ld2(p + 1));
+      if (j > 0) add(ld2(p - sy));
+      if (j + 1 < g.ny) add(ld2(p + sy));
+      if (k > 0) add(xm);
+      if (k + 1 < g.nz) add(xp);
+      const Cx<T> x1 = xc.a, x2 = xc.b;
+      const T kap = K[p], dmp = b2_damping<T>(g, i, j, k);
+      const Cx<T> o1 = b2_block1(x1, x2, z0r, z0i), o2 = b2_block2(g, x1, x2, nr, ni, kap, dmp, z0r, z0i);
+      // the first factor at the point (t1, t2), then the second
+      const Cx<T> t1 = b2_fac(a1r, a1i, b1r, b1i, o1, x1), t2 = b2_fac(a1r, a1i, b1r, b1i, o2, x2);
+      const Cx<T> p1 = b2_block1(t1, t2, z0r, z0i), p2 = b2_block2(g, t1, t2, mr, mi, kap, dmp, z0r, z0i);
+      const Cx<T> c1 = b2_fac(a2r, a2i, b2r, b2i, p1, t1), c2 = b2_fac(a2r, a2i, b2r, b2i, p2, t2);
+      T2 w1, w2;
+      w1.x = c1.x;
+      w1.y = c1.y;
+      w2.x = c2.x;
+      w2.y = c2.y;
+      if constexpr (ADD) {
+        const T2 e1 = Y1[p], e2 = Y1[npt + p];
+        w1.x += e1.x;
+        w1.y += e1.y;
+        w2.x += e2.x;
+        w2.y += e2.y;
+      }
+      O[p] = w1;
+      O[npt + p] = w2;
+      if constexpr (DUAL) {
+        O2[p] = w1;
+        O2[npt + p] = w2;
+      }
+      if constexpr (RESID) {
+        const double zr = pd.zz_re, zi = pd.zz_im;
+        const T2 g1 = F[p], g2 = F[npt + p];
+        const double r1x = (double)g1.x - (double)o1.x + zr * (double)x1.x - zi * (double)x1.y;
+        const double r1y = (double)g1.y - (double)o1.y + zr * (double)x1.y + zi * (double)x1.x;
+        const double r2x = (double)g2.x - (double)o2.x + zr * (double)x2.x - zi * (double)x2.y;
+        const double r2y = (double)g2.y - (double)o2.y + zr * (double)x2.y + zi * (double)x2.x;
+        acc += r1x * r1x + r1y * r1y + r2x * r2x + r2y * r2y;
+      }
+      xm = xc;
+      xc = xp;
     }
   }
   if constexpr (RESID) {
