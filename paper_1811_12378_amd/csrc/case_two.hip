@@ -189,9 +189,16 @@ struct Pt2 {
   Cx<T> a, b;  // x1, x2 at a point
 };
 
+// Waves per SIMD asked of the compiler: 8 (64 VGPRs) for the complex64 kinds that fit
+// without spilling (the middle pairs and the first pair of step one), else its own choice.
 template <typename T, int KIND>
-__global__ __launch_bounds__(NT) void b2_pair_kernel(GridDesc g, const T* __restrict__ K,
-                                                     B2Args<typename Vec2<T>::t> a) {
+constexpr int b2_pair_waves() {
+  return (sizeof(T) == 4 && (KIND & (kFacResid | kFacAdd | kFacDual)) == 0) ? 8 : 1;
+}
+
+template <typename T, int KIND>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(b2_pair_waves<T, KIND>()))) void b2_pair_kernel(
+    GridDesc g, const T* __restrict__ K, B2Args<typename Vec2<T>::t> a) {
   using T2 = typename Vec2<T>::t;
   constexpr bool RESID = (KIND & kFacResid) != 0, ADD = (KIND & kFacAdd) != 0, DUAL = (KIND & kFacDual) != 0,
                  INF = (KIND & kFacInF) != 0;
