@@ -259,6 +259,17 @@ template <typename T2>
 void spectral_S(const Op& op, int nvec, const T2* in, T2* out);
 template <typename T2>
 void spectral_apply(const Op& op, int nvec, const T2* x, T2* y, double sr, double si);
+// spectral.hip: a gathered batch of the systems still iterating.  launch_spec_slots fills
+// slot_sys[nvec] (the v-th active system, -1 past the last) and sys_slot[nsys] (-1 outside
+// the batch) from the device flags; launch_spec_gather copies in_{slot_sys[v]} to out_v
+// (zero for -1); launch_spec_factor_slots is launch_spec_factor with S w of system s at
+// a.sw + sys_slot[s] n (slot null: at a.sw + s n).
+void launch_spec_slots(hipStream_t st, const int* active, int nsys, int nvec, int* slot_sys, int* sys_slot);
+template <typename T2>
+void launch_spec_gather(hipStream_t st, const GridDesc& g, const T2* in, T2* out, const int* slot_sys, int nvec);
+template <typename T2>
+bool launch_spec_factor_slots(hipStream_t st, const GridDesc& g, const void* K, int kind, int nsys,
+                              const SpecArgs<T2>& a, const int* slot);
 template <typename T2>
 void shifted_solve_spectral(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int fixed_steps,
                             double reduce, int max_steps, int* steps_out, FciStats& st);

@@ -1,9 +1,10 @@
 // The Fourier-spectral operator (Sec. 7.1, eq. eig-Laplacian-spectral) on the GPU:
 // S x = F^H Lambda F x with library 3D FFTs (hipFFT, batched over vectors, in place) and
 // the diagonal between them (spec_scale_kernel); the shifted solves run the loop of
-// fp_simple.h with one FFT pair and one epilogue launch per factor.
+// fp_simple.h with one batched FFT pair and one epilogue launch per factor.
 #include <hipfft/hipfft.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 
@@ -58,16 +59,26 @@ void exec(hipfftHandle p, double2* x, int dir) {
 
 }  // namespace
 
+namespace {
+
+// x_v <- S x_v for v < nvec, in place
+template <typename T2>
+void spectral_S_inplace(const Op& op, int nvec, T2* x) {
+  Ctx& ctx = *op.ctx;
+  HFCI_REQUIRE((long long)op.g.nx * op.g.ny * op.g.nz < (1LL << 31), "grid too large for the FFT plans");
+  hipfftHandle p = plan_for<T2>(ctx, op.g, nvec);
+  if (p) exec(p, x, HIPFFT_FORWARD);
+  launch_spec_scale<T2>(ctx.stream, x, nvec, op.g, op.s, op.h);
+  if (p) exec(p, x, HIPFFT_BACKWARD);
+}
+
+}  // namespace
+
 // out_v = S in_v for v < nvec (out distinct from in)
 template <typename T2>
 void spectral_S(const Op& op, int nvec, const T2* in, T2* out) {
-  Ctx& ctx = *op.ctx;
-  HFCI_REQUIRE((long long)op.g.nx * op.g.ny * op.g.nz < (1LL << 31), "grid too large for the FFT plans");
-  HFCI_HIP(hipMemcpyAsync(out, in, (size_t)nvec * op.n * sizeof(T2), hipMemcpyDeviceToDevice, ctx.stream));
-  hipfftHandle p = plan_for<T2>(ctx, op.g, nvec);
-  if (p) exec(p, out, HIPFFT_FORWARD);
-  launch_spec_scale<T2>(ctx.stream, out, nvec, op.g, op.s, op.h);
-  if (p) exec(p, out, HIPFFT_BACKWARD);
+  HFCI_HIP(hipMemcpyAsync(out, in, (size_t)nvec * op.n * sizeof(T2), hipMemcpyDeviceToDevice, op.ctx->stream));
+  spectral_S_inplace<T2>(op, nvec, out);
 }
 template void spectral_S<float2>(const Op&, int, const float2*, float2*);
 template void spectral_S<double2>(const Op&, int, const double2*, double2*);
@@ -94,21 +105,30 @@ void shifted_solve_spectral(const Op& op, const Contour& c, int nrhs, const T2* 
   const void* K = kappa_for<T2>(op);
   const int nsys = c.J * nrhs;
   T2* sw = (T2*)ctx.ws.get("sp_sw", (size_t)nsys * op.n * sizeof(T2));
+  int* slot_sys = (int*)ctx.ws.get("sp_slot_sys", (size_t)nsys * sizeof(int));
+  int* sys_slot = (int*)ctx.ws.get("sp_sys_slot", (size_t)nsys * sizeof(int));
   fp_simple<T2>(op, c, nrhs, f, y, fixed_steps, reduce, max_steps, steps_out, st, spec_blocks(op.g), false,
                 [&](const SimpleFactor<T2>& sf) {
-                  // S w of the factor's inputs: the right-hand sides (step one's first factor)
-                  // or, when every system iterates, all vectors, each as one batch; else the
-                  // vectors of the systems still iterating, one by one
+                  // S w of the factor's inputs, one batched transform: the right-hand sides
+                  // (step one's first factor), all vectors when every system iterates, else
+                  // the vectors of the systems still iterating gathered into the first slots
+                  // of a batch of exactly that many vectors up to 16, else of the next
+                  // multiple of 16 (at most 16 + nsys / 16 cached plans; the padding slots
+                  // are zero)
                   HFCI_REQUIRE(sf.nfac == 1, "internal: the spectral factors run one per launch");
                   int nact = 0;
                   for (int k = 0; k < sf.nsys; ++k) nact += sf.host_active[k] != 0;
+                  const int* slot = nullptr;
                   if ((sf.kind & kFacInF) != 0) {
                     spectral_S<T2>(op, sf.nrhs, sf.in, sw);
                   } else if (nact == sf.nsys) {
                     spectral_S<T2>(op, sf.nsys, sf.in, sw);
                   } else {
-                    for (int k = 0; k < sf.nsys; ++k)
-                      if (sf.host_active[k]) spectral_S<T2>(op, 1, sf.in + (size_t)k * op.n, sw + (size_t)k * op.n);
+                    const int nvec = std::min(nact <= 16 ? nact : (nact + 15) / 16 * 16, sf.nsys);
+                    launch_spec_slots(s, sf.active, sf.nsys, nvec, slot_sys, sys_slot);
+                    launch_spec_gather<T2>(s, op.g, sf.in, sw, slot_sys, nvec);
+                    spectral_S_inplace<T2>(op, nvec, sw);
+                    slot = sys_slot;
                   }
                   SpecArgs<T2> a{};
                   a.win = sf.in;
@@ -124,7 +144,7 @@ void shifted_solve_spectral(const Op& op, const Contour& c, int nrhs, const T2* 
                   a.nrhs = sf.nrhs;
                   a.cstride = c.cstride;
                   a.k = sf.k;
-                  const bool ok = launch_spec_factor<T2>(s, op.g, K, sf.kind, sf.nsys, a);
+                  const bool ok = launch_spec_factor_slots<T2>(s, op.g, K, sf.kind, sf.nsys, a, slot);
                   HFCI_REQUIRE(ok, "internal: unsupported factor kind");
                 });
 }

@@ -71,9 +71,12 @@ __device__ __forceinline__ void spec_point(T2 w, T2 sw, T kap, T dmp, T z0r, T z
   oy = sw.y - (dr * w.y + z0i * w.x) - dmp * w.x;
 }
 
+// slot: null when S w of system s sits at a.sw + s n (indexed as the inputs), else the
+// batch slot of each system's S w (a gathered batch; -1 for a system outside it)
 template <typename T, int KIND>
 __global__ __launch_bounds__(NT) void spec_factor_kernel(GridDesc g, const T* __restrict__ K,
-                                                         SpecArgs<typename Vec2s<T>::t> a) {
+                                                         SpecArgs<typename Vec2s<T>::t> a,
+                                                         const int* __restrict__ slot) {
   using T2 = typename Vec2s<T>::t;
   constexpr bool RESID = (KIND & kFacResid) != 0, ADD = (KIND & kFacAdd) != 0, DUAL = (KIND & kFacDual) != 0,
                  INF = (KIND & kFacInF) != 0;
@@ -87,8 +90,10 @@ __global__ __launch_bounds__(NT) void spec_factor_kernel(GridDesc g, const T* __
   const T car = (T)cf.a_re, cai = (T)cf.a_im, cbr = (T)cf.b_re, cbi = (T)cf.b_im;
   const T z0r = (T)pd.z0_re, z0i = (T)pd.z0_im;
   const size_t vi = INF ? (size_t)r * npt : (size_t)s * npt;
+  const int sl = slot != nullptr && !INF ? slot[s] : 0;
+  if (sl < 0) return;  // block-uniform: not in the gathered batch
   const T2* __restrict__ W = a.win + vi;
-  const T2* __restrict__ SW = a.sw + vi;
+  const T2* __restrict__ SW = slot != nullptr && !INF ? a.sw + (size_t)sl * npt : a.sw + vi;
   const T2* __restrict__ F = a.f + (size_t)r * npt;
   const T2* __restrict__ Y1 = a.y1 + (size_t)s * npt;
   T2* __restrict__ O = a.wout + (size_t)s * npt;
@@ -210,9 +215,48 @@ __global__ __launch_bounds__(NT) void spec_residual64_kernel(GridDesc g, const d
 }
 
 template <typename T, int KIND>
-void launch_skind(hipStream_t st, const GridDesc& g, const T* K, int nsys, const SpecArgs<typename Vec2s<T>::t>& a) {
+void launch_skind(hipStream_t st, const GridDesc& g, const T* K, int nsys, const SpecArgs<typename Vec2s<T>::t>& a,
+                  const int* slot) {
   hipLaunchKernelGGL((spec_factor_kernel<T, KIND>), dim3((unsigned)spec_blocks(g), (unsigned)nsys), dim3(NT), 0, st,
-                     g, K, a);
+                     g, K, a, slot);
+}
+
+// The batch of the systems still iterating: slot_sys[v] for v < nvec is the v-th active
+// system in index order (-1 past the last), sys_slot[s] the slot of system s (-1 for a
+// stopped system or one past nvec slots).  One thread; nsys is at most a few thousand.
+__global__ void spec_slots_kernel(const int* __restrict__ active, int nsys, int nvec, int* __restrict__ slot_sys,
+                                  int* __restrict__ sys_slot) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int v = 0;
+  for (int s = 0; s < nsys; ++s) {
+    if (active[s] != 0 && v < nvec) {
+      slot_sys[v] = s;
+      sys_slot[s] = v++;
+    } else {
+      sys_slot[s] = -1;
+    }
+  }
+  for (; v < nvec; ++v) slot_sys[v] = -1;
+}
+
+// out_v = in_{slot_sys[v]} for v < nvec (grid y), zero for a slot past the last system
+template <typename T2>
+__global__ __launch_bounds__(NT) void spec_gather_kernel(const T2* __restrict__ in, T2* __restrict__ out,
+                                                         const int* __restrict__ slot_sys, size_t n) {
+  const int v = blockIdx.y, sys = slot_sys[v];
+  T2* __restrict__ O = out + (size_t)v * n;
+  const T2* __restrict__ I = in + (size_t)(sys < 0 ? 0 : sys) * n;
+  const size_t stride = (size_t)gridDim.x * NT;
+  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < n; p += stride) {
+    T2 x;
+    if (sys >= 0) {
+      x = I[p];
+    } else {
+      x.x = 0;
+      x.y = 0;
+    }
+    O[p] = x;
+  }
 }
 
 }  // namespace
@@ -234,25 +278,49 @@ template void launch_spec_scale<float2>(hipStream_t, float2*, int, const GridDes
 template void launch_spec_scale<double2>(hipStream_t, double2*, int, const GridDesc&, double, double);
 
 template <typename T2>
-bool launch_spec_factor(hipStream_t st, const GridDesc& g, const void* K, int kind, int nsys, const SpecArgs<T2>& a) {
+bool launch_spec_factor_slots(hipStream_t st, const GridDesc& g, const void* K, int kind, int nsys,
+                              const SpecArgs<T2>& a, const int* slot) {
   using T = typename Scals<T2>::t;
   const T* k = (const T*)K;
   if (nsys <= 0) return true;
   switch (kind) {
-    case 0: launch_skind<T, 0>(st, g, k, nsys, a); return true;
-    case kFacResid: launch_skind<T, kFacResid>(st, g, k, nsys, a); return true;
-    case kFacAdd: launch_skind<T, kFacAdd>(st, g, k, nsys, a); return true;
-    case kFacResid | kFacAdd: launch_skind<T, kFacResid | kFacAdd>(st, g, k, nsys, a); return true;
-    case kFacInF: launch_skind<T, kFacInF>(st, g, k, nsys, a); return true;
-    case kFacInF | kFacDual: launch_skind<T, kFacInF | kFacDual>(st, g, k, nsys, a); return true;
-    case kFacDual: launch_skind<T, kFacDual>(st, g, k, nsys, a); return true;
+    case 0: launch_skind<T, 0>(st, g, k, nsys, a, slot); return true;
+    case kFacResid: launch_skind<T, kFacResid>(st, g, k, nsys, a, slot); return true;
+    case kFacAdd: launch_skind<T, kFacAdd>(st, g, k, nsys, a, slot); return true;
+    case kFacResid | kFacAdd: launch_skind<T, kFacResid | kFacAdd>(st, g, k, nsys, a, slot); return true;
+    case kFacInF: launch_skind<T, kFacInF>(st, g, k, nsys, a, slot); return true;
+    case kFacInF | kFacDual: launch_skind<T, kFacInF | kFacDual>(st, g, k, nsys, a, slot); return true;
+    case kFacDual: launch_skind<T, kFacDual>(st, g, k, nsys, a, slot); return true;
     default: return false;
   }
+}
+template bool launch_spec_factor_slots<float2>(hipStream_t, const GridDesc&, const void*, int, int,
+                                               const SpecArgs<float2>&, const int*);
+template bool launch_spec_factor_slots<double2>(hipStream_t, const GridDesc&, const void*, int, int,
+                                                const SpecArgs<double2>&, const int*);
+
+template <typename T2>
+bool launch_spec_factor(hipStream_t st, const GridDesc& g, const void* K, int kind, int nsys, const SpecArgs<T2>& a) {
+  return launch_spec_factor_slots<T2>(st, g, K, kind, nsys, a, nullptr);
 }
 template bool launch_spec_factor<float2>(hipStream_t, const GridDesc&, const void*, int, int,
                                          const SpecArgs<float2>&);
 template bool launch_spec_factor<double2>(hipStream_t, const GridDesc&, const void*, int, int,
                                           const SpecArgs<double2>&);
+
+void launch_spec_slots(hipStream_t st, const int* active, int nsys, int nvec, int* slot_sys, int* sys_slot) {
+  hipLaunchKernelGGL(spec_slots_kernel, dim3(1), dim3(64), 0, st, active, nsys, nvec, slot_sys, sys_slot);
+}
+
+template <typename T2>
+void launch_spec_gather(hipStream_t st, const GridDesc& g, const T2* in, T2* out, const int* slot_sys, int nvec) {
+  if (nvec <= 0) return;
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  hipLaunchKernelGGL(spec_gather_kernel<T2>, dim3((unsigned)spec_blocks(g), (unsigned)nvec), dim3(NT), 0, st, in, out,
+                     slot_sys, n);
+}
+template void launch_spec_gather<float2>(hipStream_t, const GridDesc&, const float2*, float2*, const int*, int);
+template void launch_spec_gather<double2>(hipStream_t, const GridDesc&, const double2*, double2*, const int*, int);
 
 template <typename T2>
 void launch_spec_apply(hipStream_t st, const GridDesc& g, const void* K, int nvec, const T2* x, const T2* sx, T2* y,
