@@ -116,6 +116,27 @@ def test_spectral_shifted_solve_adaptive(ctx, q):
         assert rel(y[j, 0], ref) <= 1e-11
 
 
+def test_spectral_gathered_batches_past_16(ctx):
+    # 12 poles x 3 right-hand sides = 36 systems; rhs 1 is zero, so after step one 24 systems
+    # iterate: their vectors are gathered into a batch of 32 (8 zero padding slots), and
+    # into exact batches as the poles stop one by one
+    o, g = make(ctx, (8, 9, 10), 15, 12.0)
+    poles, cg = contour(o, g, 12, 2)
+    rng = np.random.default_rng(16)
+    f = rng.standard_normal((3,) + o.shape) + 1j * rng.standard_normal((3,) + o.shape)
+    f[1] = 0.0
+    y, st = hf.shifted_solve(g, cg, dev(f), reduce=5.0, max_steps=60)
+    y = host(y)
+    Am = lambda v, sh: o.apply(v, sh)
+    for j, p in enumerate(poles):
+        assert st[j, 1] == 0 and np.all(y[j, 1] == 0)
+        for r in (0, 2):
+            ref, hist = OFP.fixed_point_solve(Am, f[r], p.z, p.z0, p.delta, 2, reduce=5.0, m_max=60)
+            assert st[j, r] == len(hist) - 1, (j, r, st[j, r], len(hist) - 1)
+            assert rel(y[j, r], ref) <= 1e-11, (j, r)
+    assert len(set(int(v) for v in st[:, 0])) > 1  # the poles stop at different steps
+
+
 def test_spectral_fci_and_solve_lockstep(ctx):
     o, g = make(ctx, (8, 9, 10), 9, 12.0)
     poles, cg = contour(o, g, 6, 6)
