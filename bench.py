@@ -401,8 +401,8 @@ def case_two_arm(args, ctx, op, cont, wl, solve=True):
     t2 = out["case_two"]["time_s"]
     out["case_two"]["alg_bytes"] = alg
     out["case_two"]["achieved_gbs_wall"] = round(alg / t2 / 1e9, 1)
-    out["case_two"]["kernel"] = ("b2_pair_kernel<float, KIND> (two factors per pass; a lone factor: "
-                                 "b2_factor_kernel; no LDS staging)")
+    out["case_two"]["kernel"] = ("b2_zm_kernel<float, KIND, NF> (marching in z, no LDS staging; NF = 2 factors "
+                                 "per pass, NF = 1 for a lone factor)")
     out["stencil_products_ratio_two_over_one"] = round(out["case_two"]["stencil_products"] /
                                                        max(out["case_one"]["stencil_products"], 1), 3)
     out["time_ratio_two_over_one"] = round(t2 / out["case_one"]["time_s"], 3)

@@ -5,11 +5,12 @@
 // then x2 (n values), n the grid points.
 //
 // Kernels: one factor of the product-form fixed-point step (eq. fix-pt-exp, as the
-// factors of params.cpp) over all shifted systems, w_out = a (B - z0) w + b w with the
-// epilogues of the case-one kernels (residual partials, adding y1, a second output),
-// two consecutive factors in one pass over HBM (b2_pair_kernel), and the plain product
-// (B - shift) x.  One thread per grid point and both blocks; the neighbours come through
-// the cache (no LDS staging).
+// factors of params.cpp), w_out = a (B - z0) w + b w, or two consecutive factors in one
+// pass over HBM, over all shifted systems, with the epilogues of the case-one kernels
+// (residual partials, adding y1, a second output): b2_zm_kernel, one thread per grid
+// column marching in z.  Then the plain product (B - shift) x, the step-size partials and
+// the FP64 residual: one thread per grid point.  Both blocks per thread; the neighbours come
+// through the cache (no LDS staging).
 #include "kernels.h"
 
 namespace hfci {
@@ -107,74 +108,13 @@ __device__ __forceinline__ double block_sum_nt(double v, double* sh) {
   return t;
 }
 
-template <typename T, int KIND>
-__global__ __launch_bounds__(NT) void b2_factor_kernel(GridDesc g, const T* __restrict__ K,
-                                                       B2Args<typename Vec2<T>::t> a) {
-  using T2 = typename Vec2<T>::t;
-  constexpr bool RESID = (KIND & kFacResid) != 0, ADD = (KIND & kFacAdd) != 0, DUAL = (KIND & kFacDual) != 0,
-                 INF = (KIND & kFacInF) != 0;
-  __shared__ double sh[NT / 64];
-  const int s = blockIdx.y;
-  if (a.active[s] == 0) return;  // block-uniform: stopped systems are skipped
-  const int pole = s / a.nrhs, r = s % a.nrhs;
-  const size_t npt = (size_t)g.nx * g.ny * g.nz, n2 = 2 * npt;
-  const FactorCoef cf = a.coef[(size_t)pole * a.cstride + a.k];
-  const PoleDev pd = a.poles[pole];
-  const T car = (T)cf.a_re, cai = (T)cf.a_im, cbr = (T)cf.b_re, cbi = (T)cf.b_im;
-  const T z0r = (T)pd.z0_re, z0i = (T)pd.z0_im;
-  const T2* __restrict__ X = INF ? a.win + (size_t)r * n2 : a.win + (size_t)s * n2;
-  const T2* __restrict__ F = a.f + (size_t)r * n2;
-  const T2* __restrict__ Y1 = a.y1 + (size_t)s * n2;
-  T2* __restrict__ O = a.wout + (size_t)s * n2;
-  T2* __restrict__ O2 = DUAL ? a.wout2 + (size_t)s * n2 : nullptr;
-  double acc = 0.0;
-  const size_t stride = (size_t)gridDim.x * NT;
-  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < npt; p += stride) {
-    const int i = (int)(p % g.nx), j = (int)((p / g.nx) % g.ny), k = (int)(p / ((size_t)g.nx * g.ny));
-    Cx<T> o1, o2, x1, x2;
-    b2_point<T, T2>(g, K, X, npt, p, i, j, k, z0r, z0i, o1, o2, x1, x2);
-    const Cx<T> c1 = b2_fac(car, cai, cbr, cbi, o1, x1), c2 = b2_fac(car, cai, cbr, cbi, o2, x2);
-    T2 w1, w2;
-    w1.x = c1.x;
-    w1.y = c1.y;
-    w2.x = c2.x;
-    w2.y = c2.y;
-    if constexpr (ADD) {
-      const T2 a1 = Y1[p], a2 = Y1[npt + p];
-      w1.x += a1.x;
-      w1.y += a1.y;
-      w2.x += a2.x;
-      w2.y += a2.y;
-    }
-    O[p] = w1;
-    O[npt + p] = w2;
-    if constexpr (DUAL) {
-      O2[p] = w1;
-      O2[npt + p] = w2;
-    }
-    if constexpr (RESID) {
-      // g - (B - z) y = g - (B - z0) y + (z - z0) y, both blocks, in FP64
-      const double zr = pd.zz_re, zi = pd.zz_im;
-      const T2 g1 = F[p], g2 = F[npt + p];
-      const double r1x = (double)g1.x - (double)o1.x + zr * (double)x1.x - zi * (double)x1.y;
-      const double r1y = (double)g1.y - (double)o1.y + zr * (double)x1.y + zi * (double)x1.x;
-      const double r2x = (double)g2.x - (double)o2.x + zr * (double)x2.x - zi * (double)x2.y;
-      const double r2y = (double)g2.y - (double)o2.y + zr * (double)x2.y + zi * (double)x2.x;
-      acc += r1x * r1x + r1y * r1y + r2x * r2x + r2y * r2y;
-    }
-  }
-  if constexpr (RESID) {
-    const double t = block_sum_nt(acc, sh);
-    if (threadIdx.x == 0) a.partial[(size_t)s * gridDim.x + blockIdx.x] = t;
-  }
-}
-
-// Two consecutive factors k and k + 1 of one step in one pass: w_out = F_{k+1}(F_k(w)).
-// Block one of B is pointwise, so the intermediate x1' at a neighbour is formed from the
-// input there (its Dirichlet ghosts stay zero), and a one-point halo of the input serves
-// both factors; the intermediate x2' is needed at the point only.  Kind bits on the input:
-// kFacResid (the residual partials of w, as the single factor), kFacInF (the input is the
-// right-hand side); on the output: kFacAdd (adds y1), kFacDual (a second output).
+// NF = 1: one factor of the step, w_out = F_k(w).  NF = 2: two consecutive factors k and
+// k + 1 in one pass, w_out = F_{k+1}(F_k(w)); block one of B is pointwise, so the
+// intermediate x1' at a neighbour is formed from the input there (its Dirichlet ghosts stay
+// zero), and a one-point halo of the input serves both factors; the intermediate x2' is
+// needed at the point only.  Kind bits on the input: kFacResid (the residual partials of
+// w), kFacInF (the input is the right-hand side); on the output: kFacAdd (adds y1),
+// kFacDual (a second output).
 //
 // z-marching: a workgroup of PTX x PTY threads takes tiles of PTX x PTY columns by PCZ
 // planes (a grid-stride loop over the tiles of its system, so the residual partials keep
@@ -190,15 +130,17 @@ struct Pt2 {
 };
 
 // Waves per SIMD asked of the compiler: 8 (64 VGPRs) for the complex64 kinds that fit
-// without spilling (the middle pairs and the first pair of step one), else its own choice.
-template <typename T, int KIND>
-constexpr int b2_pair_waves() {
-  return (sizeof(T) == 4 && (KIND & (kFacResid | kFacAdd | kFacDual)) == 0) ? 8 : 1;
+// without spilling (single factors; the middle pairs and the first pair of step one), else
+// its own choice.
+template <typename T, int KIND, int NF>
+constexpr int b2_zm_waves() {
+  return (sizeof(T) == 4 && (NF == 1 || (KIND & (kFacResid | kFacAdd | kFacDual)) == 0)) ? 8 : 1;
 }
 
-template <typename T, int KIND>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(b2_pair_waves<T, KIND>()))) void b2_pair_kernel(
+template <typename T, int KIND, int NF>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(b2_zm_waves<T, KIND, NF>()))) void b2_zm_kernel(
     GridDesc g, const T* __restrict__ K, B2Args<typename Vec2<T>::t> a) {
+  static_assert(NF == 1 || NF == 2, "one or two factors per pass");
   using T2 = typename Vec2<T>::t;
   constexpr bool RESID = (KIND & kFacResid) != 0, ADD = (KIND & kFacAdd) != 0, DUAL = (KIND & kFacDual) != 0,
                  INF = (KIND & kFacInF) != 0;
@@ -207,7 +149,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(b2_pair_wave
   if (a.active[s] == 0) return;  // block-uniform: stopped systems are skipped
   const int pole = s / a.nrhs, r = s % a.nrhs;
   const size_t npt = (size_t)g.nx * g.ny * g.nz, n2 = 2 * npt;
-  const FactorCoef f1 = a.coef[(size_t)pole * a.cstride + a.k], f2 = a.coef[(size_t)pole * a.cstride + a.k + 1];
+  // the second coefficient only for a pair: k + 1 may lie past the pole's entries otherwise
+  const FactorCoef f1 = a.coef[(size_t)pole * a.cstride + a.k];
+  const FactorCoef f2 = NF == 2 ? a.coef[(size_t)pole * a.cstride + a.k + 1] : f1;
   const PoleDev pd = a.poles[pole];
   const T a1r = (T)f1.a_re, a1i = (T)f1.a_im, b1r = (T)f1.b_re, b1i = (T)f1.b_im;
   const T a2r = (T)f2.a_re, a2i = (T)f2.a_im, b2r = (T)f2.b_re, b2i = (T)f2.b_im;
@@ -245,9 +189,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(b2_pair_wave
       auto add = [&](const Pt2<T>& u) {
         nr += u.a.x;
         ni += u.a.y;
-        const Cx<T> v = fac1(u);
-        mr += v.x;
-        mi += v.y;
+        if constexpr (NF == 2) {
+          const Cx<T> v = fac1(u);
+          mr += v.x;
+          mi += v.y;
+        }
       };
       if (i > 0) add(ld2(p - 1));
       if (i + 1 < g.nx) add(ld2(p + 1));
@@ -258,10 +204,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(b2_pair_wave
       const Cx<T> x1 = xc.a, x2 = xc.b;
       const T kap = K[p], dmp = b2_damping<T>(g, i, j, k);
       const Cx<T> o1 = b2_block1(x1, x2, z0r, z0i), o2 = b2_block2(g, x1, x2, nr, ni, kap, dmp, z0r, z0i);
-      // the first factor at the point (t1, t2), then the second
+      // the first factor at the point (t1, t2), then the second (a pair)
       const Cx<T> t1 = b2_fac(a1r, a1i, b1r, b1i, o1, x1), t2 = b2_fac(a1r, a1i, b1r, b1i, o2, x2);
-      const Cx<T> p1 = b2_block1(t1, t2, z0r, z0i), p2 = b2_block2(g, t1, t2, mr, mi, kap, dmp, z0r, z0i);
-      const Cx<T> c1 = b2_fac(a2r, a2i, b2r, b2i, p1, t1), c2 = b2_fac(a2r, a2i, b2r, b2i, p2, t2);
+      Cx<T> c1 = t1, c2 = t2;
+      if constexpr (NF == 2) {
+        const Cx<T> p1 = b2_block1(t1, t2, z0r, z0i), p2 = b2_block2(g, t1, t2, mr, mi, kap, dmp, z0r, z0i);
+        c1 = b2_fac(a2r, a2i, b2r, b2i, p1, t1);
+        c2 = b2_fac(a2r, a2i, b2r, b2i, p2, t2);
+      }
       T2 w1, w2;
       w1.x = c1.x;
       w1.y = c1.y;
@@ -385,13 +335,13 @@ __global__ __launch_bounds__(NT) void b2_residual64_kernel(GridDesc g, const dou
 template <typename T, int KIND>
 void launch_kind(hipStream_t st, const GridDesc& g, const T* K, int nsys, int nblk,
                  const B2Args<typename Vec2<T>::t>& a) {
-  hipLaunchKernelGGL((b2_factor_kernel<T, KIND>), dim3((unsigned)nblk, (unsigned)nsys), dim3(NT), 0, st, g, K, a);
+  hipLaunchKernelGGL((b2_zm_kernel<T, KIND, 1>), dim3((unsigned)nblk, (unsigned)nsys), dim3(NT), 0, st, g, K, a);
 }
 
 template <typename T, int KIND>
 void launch_pair_kind(hipStream_t st, const GridDesc& g, const T* K, int nsys, int nblk,
                       const B2Args<typename Vec2<T>::t>& a) {
-  hipLaunchKernelGGL((b2_pair_kernel<T, KIND>), dim3((unsigned)nblk, (unsigned)nsys), dim3(NT), 0, st, g, K, a);
+  hipLaunchKernelGGL((b2_zm_kernel<T, KIND, 2>), dim3((unsigned)nblk, (unsigned)nsys), dim3(NT), 0, st, g, K, a);
 }
 
 }  // namespace
