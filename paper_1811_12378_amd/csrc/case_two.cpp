@@ -1,8 +1,9 @@
 // Case-two shifted solves (Sec. 3 eq. mat-2x2, Sec. 4.2 eq. fix-pt-exp): for every pole
 // z_j of a contour built on B's spectrum box and every right-hand side g_r (vectors of
 // 2 n values), the polynomial fixed-point iteration for (B - z_j) y = g_r from y = 0 (the
-// loop of fp_simple.h): the later steps two factors per launch (b2_pair_kernel), step one
-// and a trailing factor of an odd q one per launch (b2_factor_kernel), all systems at once.
+// loop of fp_simple.h) with pairs on: two factors per launch where the step allows, one for
+// a leading factor of step one or a trailing factor of an odd q (b2_zm_kernel), all systems
+// at once.
 #include "fp_simple.h"
 
 namespace hfci {
