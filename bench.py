@@ -226,7 +226,7 @@ def uneven_arm(args, ctx, verbose):
 
 def learned_arm(args, ctx, op, cont, f_d, t_mixed, fp64, verbose):
     """Train the network on pairs from FCI-preconditioned FGMRES (untimed), then time the solve
-    with the learned preconditioner (FCI as judge and fallback) and the network's throughput."""
+    with the learned preconditioner (FCI as arbiter and fallback) and the network's throughput."""
     import torch
     from paper_1811_12378_amd import hfci
     from paper_1811_12378_amd import learned as L
@@ -479,8 +479,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: the multi-GPU (pole-parallel) layout is a design, "
-              "not part of this build; rerun with --gpus 1", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the multi-GPU (pole-parallel) layout is not "
+              "implemented; rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

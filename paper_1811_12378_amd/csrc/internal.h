@@ -57,7 +57,7 @@ constexpr size_t kPinnedFciOffset = 60000;
 constexpr int kPinnedIntHalf = 32768;
 
 // Opt-in kernel timing on the context's stream: HIP events around selected launches,
-// with the algorithmic bytes each launch moves.  Harvested at the driver's sync points.
+// with the algorithmic bytes each launch moves.  Harvested at the solver loop's sync points.
 class Profiler {
  public:
   bool on = false;

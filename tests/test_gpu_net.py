@@ -169,7 +169,7 @@ def test_save_load_roundtrip(ctx):
 
 def test_harvest_train_and_learned_fgmres(ctx):
     # pairs (v_j, FCI(v_j)) harvested from FGMRES on a random medium, a short training run,
-    # then the learned preconditioner inside FGMRES with FCI as judge and fallback
+    # then the learned preconditioner inside FGMRES with FCI as arbiter and fallback
     import workloads as W
     wl = W.config_grf_96(n=32, nrhs=1)
     op = hf.Operator(ctx, torch.from_numpy(wl.c).cuda(), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
@@ -196,7 +196,7 @@ def test_harvest_train_and_learned_fgmres(ctx):
     assert st2["status"] == "HFCI_OK" and st2["final_relres"] <= 1e-8
     assert st2["learned_accepted"] + st2["learned_fallbacks"] == st2["its"]
     assert st2["learned_fallbacks"] >= 1 and 0.0 < st2["fci_rho_mean"] < 1.0
-    # the judge admits no proposal whose scaled residual is worse than FCI's running mean
+    # the arbiter admits no proposal whose scaled residual is worse than FCI's running mean
     assert st2["learned_accepted"] == 0 or st2["net_rho_mean"] < 1.0
 
 
