@@ -46,12 +46,15 @@ def fgmres(apply_A, f, precond, m: int = 30, tol: float = 1e-8, max_it: int = 10
     M = lambda x: np.asarray(precond(x), dtype=np.complex128).ravel()
     u = np.zeros(n, dtype=np.complex128) if u0 is None else np.array(u0, dtype=np.complex128).ravel()
     fnorm = np.linalg.norm(f)
+    # relative residuals; for f = 0 the iteration stops at once with u = 0 (if u0 is None),
+    # and its history records the absolute residual instead of 0/0
+    rel_den = fnorm if fnorm > 0 else 1.0
     its, restarts = 0, 0
     hist, true_hist = [], []
     while True:
         r = f - A(u)
         beta = np.linalg.norm(r)
-        true_hist.append(beta / fnorm)
+        true_hist.append(beta / rel_den)
         if beta <= tol * fnorm or its >= max_it:
             break
         V = np.zeros((m + 1, n), dtype=np.complex128)
@@ -87,7 +90,7 @@ def fgmres(apply_A, f, precond, m: int = 30, tol: float = 1e-8, max_it: int = 10
             g[j] = c * g[j]
             its += 1
             k = j + 1
-            hist.append(abs(g[j + 1]) / fnorm)
+            hist.append(abs(g[j + 1]) / rel_den)
             if abs(g[j + 1]) <= tol * fnorm or its >= max_it or hn == 0:
                 break
         y = np.zeros(k, dtype=np.complex128)
