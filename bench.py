@@ -5,19 +5,27 @@ One step = one complete solve of the batched workload: the 256^3 layered medium
 (eight layers, velocities U[1.5, 4.5] times (1 + 0.1 g), 8 points per wavelength,
 8-cell absorbing layer), 8 point sources, 16 contour poles, exponential-Taylor degree
 q = 8, FCI inside FP64 FGMRES(30), all 128 (pole, RHS) shifted systems advanced
-together.  Inputs are resident in HBM before the timed region starts.  Further arms
-(opt-in flags): Alg. 1 step 4 (--k-in-list), case two (--case-two), contour choices
-(--params), the Fourier-spectral operator (--spectral).
+together.  Inputs are resident in HBM before the timed region starts.
+
+The run keeps to a wall-clock budget (--budget, counted from process start): the first
+timed solve always runs; the metric's other arms (the oracle CPU baseline, the plain
+FP64 solve, the learned preconditioner) run next if their estimated time fits; further
+timed solves (up to --steps) fill what is left.  Anything the budget cuts is recorded
+in the line ("skipped": "budget", or under "not_run"), and "steps"/"warmup" are the
+counts actually run.  Opt-in arms: the 32^3 / 96^3 configurations (--small), uneven
+batches (--uneven N), Alg. 1 step 4 (--k-in-list), case two (--case-two), contour
+choices (--params), the Fourier-spectral operator (--spectral).
 
 Prints ONE JSON line on stdout (everything else goes to stderr), carrying:
-  value        time-to-1e-6 of the mixed-precision batched solve (s / solve batch)
-  roofline     the dominant kernel (middle factor of the product-form fixed-point step,
-               complex64):
-               algorithmic bytes / average launch time from HIP events on the
-               library's stream during the timed steps, against 8 TB/s
+  value        time-to-1e-6 of the mixed-precision batched solve (s / solve batch),
+               the mean over the timed solves
+  roofline     the dominant kernel (middle factors of the product-form fixed-point step,
+               complex64): algorithmic bytes / average launch time from HIP events on
+               the library's stream during the timed solves, against 8 TB/s
   cpu_baseline the FP64 oracle on the host: per-stencil time on a bounded sample,
-               scaled by the matvec count of the timed solve
+               projected to the matvec count of the timed solve
   fp64         the same solve with FP64 sweeps (plain method), and the speedup
+  learned      training on FCI pairs, then the solve with the learned preconditioner
 """
 from __future__ import annotations
 
@@ -28,6 +36,8 @@ import math
 import os
 import sys
 import time
+
+T_START = time.monotonic()  # the wall-clock budget counts from process start (before torch loads)
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -72,8 +82,25 @@ def measured_traffic(shape):
     return d["bytes_per_launch"] / d["alg_bytes_per_launch"]
 
 
-def cpu_baseline(wl, poles_oracle, n_matvecs, budget_s=20.0):
-    """Time the FP64 oracle's fixed-point step (q stencil products) on the same 256^3 input."""
+def host_description():
+    """CPU model, logical core count and the thread settings that could change the oracle's speed."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    return {"cpu_model": model, "cpu_count": os.cpu_count(), "threads_env": env}
+
+
+def cpu_baseline(wl, poles_oracle, n_matvecs, budget_s=15.0):
+    """The FP64 oracle's fixed-point step (q stencil products each) on the same 256^3 input,
+    timed on the host for a bounded sample and projected to the timed solve's product count.
+    The oracle's stencil is NumPy element-wise work, which runs on one thread."""
     import numpy as np
     from oracle import fixed_point as OFP
     from oracle import operator as OO
@@ -87,15 +114,47 @@ def cpu_baseline(wl, poles_oracle, n_matvecs, budget_s=20.0):
     while True:
         y = OFP.fixed_point_step(Am, y, f, p.z, p.z0, p.delta, p.q)
         steps += 1
-        if time.perf_counter() - t0 > budget_s * 0.5 or steps >= 4:
+        if time.perf_counter() - t0 > budget_s or steps >= 6:
             break
     dt = time.perf_counter() - t0
     per_mv = dt / (steps * p.q)
-    return {"value": per_mv * n_matvecs, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": "%d fixed-point steps (q=%d, %d stencil products) of one pole at %d^3 in FP64 NumPy "
-                      "(%.3f s per product), scaled by the %d products of the timed solve"
-                      % (steps, p.q, steps * p.q, wl.n, per_mv, n_matvecs),
-            "per_matvec_s": per_mv}
+    out = {"value": per_mv * n_matvecs, "unit": "s", "cores": 1, "kind": "oracle", "projection": True,
+           "sample": "%d fixed-point steps (q=%d, %d stencil products, %.1f s) of one pole at %d^3 in FP64 "
+                     "NumPy on one host thread (%.3f s per product); value = that per-product time x the "
+                     "%d stencil products of the timed solve (a projection: a full oracle solve at this "
+                     "size would take days)" % (steps, p.q, steps * p.q, dt, wl.n, per_mv, n_matvecs),
+           "per_matvec_s": per_mv, "sample_s": dt}
+    out.update(host_description())
+    return out
+
+
+def cpu_full_solves(args):
+    """Complete FP64 oracle solves on the host: the 32^3 constant medium to 1e-8 (8 poles,
+    q = 8, FGMRES(30)), wall clock and iterations.  The 96^3 configuration is projected
+    from its per-product time: a full oracle solve there runs for hours."""
+    import numpy as np
+    import workloads as W
+    from oracle import fci as OF
+    from oracle import operator as OO
+    out = {}
+    w1 = W.config_constant_32()
+    o1 = OO.Operator(w1.c, w1.omega, w1.damp_cells, w1.damp_rho2)
+    poles = OF.pole_parameters(o1, 8, 1.0, 0.5, args.q)
+    t0 = time.perf_counter()
+    u, info = OF.solve(o1, w1.rhs[0], poles, m=30, tol=1e-8, max_it=400)
+    t = time.perf_counter() - t0
+    b = o1.s * w1.rhs[0]
+    rr = float(np.linalg.norm(b - o1.apply(np.asarray(u).reshape(o1.shape))) / np.linalg.norm(b))
+    out["constant_32_fp64_tol1e-8"] = {"time_s": round(t, 2), "its": int(info["its"]), "relres": rr}
+    w2 = W.config_grf_96()
+    o2 = OO.Operator(w2.c, w2.omega, w2.damp_cells, w2.damp_rho2)
+    x = np.asarray(w2.rhs[0])
+    t0 = time.perf_counter()
+    for _ in range(5):
+        o2.apply(x, 0.1j)
+    out["grf_96_per_product_s"] = round((time.perf_counter() - t0) / 5, 4)
+    out.update(host_description())
+    return out
 
 
 def unet_flops_per_voxel():
@@ -222,6 +281,30 @@ def uneven_arm(args, ctx, verbose):
             "its_min": min(s["its"] for s in sts), "its_max": max(s["its"] for s in sts),
             "stencil_products": int(sts[0]["matvecs"] + sum(s["matvecs"] for s in sts[1:])),
             "max_relres_oracle": worst, "status": status, "setup_s": round(setup_s, 2)}
+
+
+def fp64_arm(args, ctx, op, cont, f_d, wl, t_mixed, verbose):
+    """The plain method: the same solve with FP64 shifted sweeps (and FP64 FGMRES)."""
+    import torch
+    from paper_1811_12378_amd import hfci
+    # FP64 sweeps need twice the bytes per shifted system: advance part of the poles at a
+    # time once the batch would exceed ~64 GB of iterate storage
+    sys_bytes = 3 * 16 * wl.n ** 3 * args.nrhs
+    pb = 0 if sys_bytes * args.poles <= 64e9 else max(1, int(64e9 // sys_bytes))
+    plain = hfci.default_opts(precision=64, tol=args.tol, max_it=args.max_it, pole_batch=pb, verbose=verbose)
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u64, st64 = hfci.solve(op, cont, f_d, opts=plain)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    p64 = ctx.profile_read()["fp_stage"]
+    ctx.profile(False)
+    gbs64 = p64["alg_bytes"] / (p64["total_ms"] * 1e-3) / 1e9 if p64["total_ms"] > 0 else 0.0
+    log("plain FP64: %.3f s, its %d, relres %.3e, stage %.0f GB/s" % (t64, st64["its"], st64["final_relres"], gbs64))
+    del u64
+    return {"time_s": t64, "its": st64["its"], "matvecs": st64["matvecs"], "final_relres": st64["final_relres"],
+            "stage_gbs": gbs64, "speedup_mixed_vs_fp64": t64 / t_mixed}
 
 
 def learned_arm(args, ctx, op, cont, f_d, t_mixed, fp64, verbose):
@@ -434,11 +517,48 @@ def case_two_arm(args, ctx, op, cont, wl, solve=True):
     return out
 
 
+class Budget:
+    """Wall-clock budget of the whole run, counted from process start.  An arm runs only if
+    its estimated duration fits in what is left; otherwise it is recorded as skipped."""
+
+    def __init__(self, total_s):
+        self.total = total_s if total_s > 0 else float("inf")
+
+    def left(self):
+        return self.total - (time.monotonic() - T_START)
+
+    def fits(self, est_s):
+        return est_s <= self.left()
+
+
+def skipped(est_s, budget):
+    return {"skipped": "budget", "estimate_s": round(est_s, 1), "left_s": round(budget.left(), 1)}
+
+
+def guarded(fn):
+    """Run one arm; an exception becomes an error record, so the JSON line is always printed."""
+    try:
+        return fn()
+    except Exception as e:
+        log("arm failed: %r" % (e,))
+        return {"error": repr(e)}
+
+
+def add_prof(acc, prof):
+    """Sum two hfci_ctx_profile_read results class by class."""
+    if acc is None:
+        return prof
+    return {k: {f: acc[k][f] + prof[k][f] for f in ("launches", "total_ms", "alg_bytes")} for k in acc}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=1, help="timed solves (a cap under --budget)")
+    ap.add_argument("--warmup", type=int, default=0, help="untimed full solves first (a cap under --budget)")
+    ap.add_argument("--budget", type=float, default=450.0,
+                    help="wall-clock budget of the run in seconds from process start (0: none); arms and extra "
+                         "steps whose estimate does not fit are skipped and recorded as such")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--poles", type=int, default=16)
@@ -449,14 +569,18 @@ def main():
     ap.add_argument("--max-it", type=int, default=1000)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time a complete FP64 oracle solve at 32^3 (and the 96^3 per-product time)")
     ap.add_argument("--quiet", action="store_true", help="no per-cycle progress lines from the solver")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner arm")
     ap.add_argument("--learn-media", type=int, default=12, help="64^3 training media for the learned arm")
     ap.add_argument("--learn-steps", type=int, default=2000, help="Adam steps for the learned arm")
-    ap.add_argument("--uneven", type=int, default=16,
+    ap.add_argument("--learn-est", type=float, default=70.0,
+                    help="estimated seconds of harvesting and training in the learned arm (budget check)")
+    ap.add_argument("--uneven", type=int, default=0,
                     help="instances of the uneven-batch arm (64 = the full config; 0 skips it)")
     ap.add_argument("--uneven-only", action="store_true", help="run only the uneven-batch arm")
-    ap.add_argument("--no-small", action="store_true", help="skip the 32^3 / 96^3 configurations")
+    ap.add_argument("--small", action="store_true", help="also run the 32^3 / 96^3 configurations")
     ap.add_argument("--case-two", action="store_true", help="also run the case-one versus case-two arm")
     ap.add_argument("--k-in-list", type=int, nargs="*", default=[],
                     help="k_in values of the Alg. 1 step 4 arm (none: the arm is skipped)")
@@ -482,6 +606,7 @@ def main():
         print("bench.py runs on exactly one GPU: the multi-GPU (pole-parallel) layout is not "
               "implemented; rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    budget = Budget(args.budget)
 
     import numpy as np
     import torch
@@ -490,8 +615,8 @@ def main():
     from paper_1811_12378_amd import hfci
 
     if args.inner_only:
-        args.no_fp64 = args.no_small = args.no_learned = args.no_cpu = True
-        args.case_two = False
+        args.no_fp64 = args.no_learned = args.no_cpu = True
+        args.small = args.case_two = False
         args.uneven = 0
         if not args.k_in_list:
             args.k_in_list = [2, 4]
@@ -520,7 +645,8 @@ def main():
               flush=True)
         return
     wl = W.config_layered_256(n=args.n, nrhs=args.nrhs, ppw=args.ppw)
-    log("workload %s: omega %.3f, c in [%.3f, %.3f]" % (wl.name, wl.omega, wl.c.min(), wl.c.max()))
+    log("workload %s: omega %.3f, c in [%.3f, %.3f] (%.1f s since start)"
+        % (wl.name, wl.omega, wl.c.min(), wl.c.max(), time.monotonic() - T_START))
     ctx = hfci.Context(0)
     c_d = torch.from_numpy(wl.c).cuda()
     f_d = torch.from_numpy(np.stack(wl.rhs)).cuda()
@@ -529,7 +655,6 @@ def main():
     info = op.info()
     log("operator:", info)
 
-    verbose = 0 if args.quiet else 1
     # untimed setup: the library's autotuner picks the stencil launch shape per precision
     # (two systems: the usual number still iterating late in an FCI application)
     if args.shape:
@@ -549,27 +674,109 @@ def main():
     tune64, rows64 = op.autotune(64, 2)
     log("autotuned complex128 shape %s (%.3f ms)" % (tune64, min(r[1] for r in rows64)))
     mixed = hfci.default_opts(precision=32, tol=args.tol, max_it=args.max_it, verbose=verbose)
-    # untimed setup: one Arnoldi step allocates every workspace buffer of the solve
+    # untimed setup: one Arnoldi step launches every kernel of the solve and allocates every
+    # workspace buffer, so the first timed solve pays no first-use cost
     hfci.solve(op, cont, f_d, opts=hfci.default_opts(precision=32, tol=args.tol, max_it=1))
-    for w in range(args.warmup):
-        hfci.solve(op, cont, f_d, opts=mixed)
-        log("warmup %d done" % w)
+    torch.cuda.synchronize()
+    log("setup done at %.1f s" % (time.monotonic() - T_START))
 
-    # the roofline's HIP events bracket every k-th launch of each kernel class inside the
-    # timed solves (fewer events, less perturbation of the timed region; k = 1 for the
-    # counter runs, whose counters cover every dispatch)
-    ctx.profile(True, every=args.profile_every)
-    times, st = [], None
-    for k in range(args.steps):
+    # roofline of the dominant kernel: HIP events on the library's stream bracket every k-th
+    # launch of each kernel class inside the timed solves (k = 1 for the counter runs, whose
+    # counters cover every dispatch)
+    times, st, u, prof = [], None, None, None
+    skip = {}
+
+    def timed_solve():
+        nonlocal st, u, prof
+        ctx.profile(True, every=args.profile_every)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         u, st = hfci.solve(op, cont, f_d, opts=mixed)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
-        log("step %d: %.3f s, its %d, relres %.3e, matvecs %d" % (k, times[-1], st["its"], st["final_relres"],
-                                                                   st["matvecs"]))
-    prof = ctx.profile_read()
-    ctx.profile(False)
+        prof = add_prof(prof, ctx.profile_read())
+        ctx.profile(False)
+        log("timed step %d: %.3f s, its %d, relres %.3e, matvecs %d (%.1f s since start)"
+            % (len(times) - 1, times[-1], st["its"], st["final_relres"], st["matvecs"], time.monotonic() - T_START))
+
+    # warm-up full solves are run only if, after them, the first timed solve and the
+    # metric's other arms would still fit; the solve time is not known before the first
+    # one, so a warm-up needs the budget to be unbounded
+    warm_done = 0
+    if args.warmup > 0 and budget.total == float("inf"):
+        for w in range(args.warmup):
+            hfci.solve(op, cont, f_d, opts=mixed)
+            warm_done += 1
+            log("warmup %d done" % w)
+    elif args.warmup > 0:
+        skip["warmup"] = ("%d warm-up solves not run: the untimed setup above (autotuning and one "
+                          "Arnoldi step) already launched every kernel and allocated every buffer, and "
+                          "a full warm-up solve would not leave room in the %.0f s budget" % (args.warmup,
+                                                                                             budget.total))
+    timed_solve()
+    t1 = times[0]
+
+    # independent residual check of the first solution with the FP64 oracle on the host
+    from oracle import operator as OO
+    o = OO.Operator(wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
+    u0 = u[0].cpu().numpy()
+    b = o.s * wl.rhs[0]
+    relres_oracle = float(np.linalg.norm(b - o.apply(u0)) / np.linalg.norm(b))
+    log("oracle FP64 relative residual of rhs 0: %.3e" % relres_oracle)
+    st_first = dict(st)
+
+    cpu = None
+    if not args.no_cpu:
+        est = 35.0
+        if budget.fits(est):
+            try:
+                from oracle import fci as OF
+                poles_o = OF.pole_parameters(o, args.poles, 1.0, args.eps, args.q)
+                cpu = cpu_baseline(wl, poles_o, st_first["matvecs"])
+                if args.cpu_full:
+                    cpu["full_solves"] = cpu_full_solves(args)
+                log("cpu baseline:", cpu["sample"])
+            except Exception as e:  # the JSON line is printed whatever an arm does
+                cpu = {"error": repr(e)}
+        else:
+            cpu = skipped(est, budget)
+
+    fp64 = None
+    if not args.no_fp64:
+        est = 2.0 * t1 + 10.0
+        if budget.fits(est):
+            fp64 = guarded(lambda: fp64_arm(args, ctx, op, cont, f_d, wl, t1, verbose))
+        else:
+            fp64 = skipped(est, budget)
+
+    learned = None
+    if not args.no_learned:
+        est = args.learn_est + 1.3 * t1
+        if budget.fits(est):
+            learned = guarded(lambda: learned_arm(args, ctx, op, cont, f_d, t1,
+                                                  fp64 if fp64 and "time_s" in fp64 else None, verbose))
+        else:
+            learned = skipped(est, budget)
+
+    optional = {}
+    for name, flag, fn in (
+            ("small_configs", args.small, lambda: small_configs_arm(args, ctx)),
+            ("uneven_batch", args.uneven > 0, lambda: uneven_arm(args, ctx, verbose)),
+            ("inner_step4", bool(args.k_in_list), lambda: inner_arm(args, ctx, op, cont, f_d, t1, st_first["its"])),
+            ("spectral", args.spectral, lambda: spectral_arm(args, ctx)),
+            ("contour_choice", args.params, lambda: params_arm(args, ctx, op, f_d, t1, st_first["its"])),
+            ("case_two", args.case_two, lambda: case_two_arm(args, ctx, op, cont, wl))):
+        if flag:
+            optional[name] = guarded(fn)
+
+    # further timed solves while the budget lasts (capped by --steps)
+    while len(times) < args.steps:
+        est = 1.15 * max(times) + 5.0
+        if not budget.fits(est):
+            skip["steps"] = ("%d of %d requested timed solves run: the next (about %.0f s) would not fit in "
+                             "the %.0f s left of the budget" % (len(times), args.steps, est, budget.left()))
+            break
+        timed_solve()
     t_mixed = sum(times) / len(times)
 
     stage = prof["fp_stage"]
@@ -588,80 +795,20 @@ def main():
     other_gbs = {k: gbs(k) for k in ("fp_stage_first", "fp_stage_last", "fp_stage_init")}
     launch_ms = {k: round(prof[k]["total_ms"], 1) for k in ("fp_stage", "fp_stage_first", "fp_stage_last",
                                                              "fp_stage_init")}
-
-    # independent residual check of the first solution with the FP64 oracle on the host
-    from oracle import operator as OO
-    o = OO.Operator(wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
-    u0 = u[0].cpu().numpy()
-    b = o.s * wl.rhs[0]
-    relres_oracle = float(np.linalg.norm(b - o.apply(u0)) / np.linalg.norm(b))
-    log("oracle FP64 relative residual of rhs 0: %.3e" % relres_oracle)
-
-    fp64 = None
-    if not args.no_fp64:
-        # FP64 sweeps need twice the bytes per shifted system: advance half the poles at a time
-        # once the batch would exceed ~64 GB of iterate storage
-        sys_bytes = 3 * 16 * wl.n ** 3 * args.nrhs
-        pb = 0 if sys_bytes * args.poles <= 64e9 else max(1, int(64e9 // sys_bytes))
-        plain = hfci.default_opts(precision=64, tol=args.tol, max_it=args.max_it, pole_batch=pb, verbose=verbose)
-        ctx.profile(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        u64, st64 = hfci.solve(op, cont, f_d, opts=plain)
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t0
-        p64 = ctx.profile_read()["fp_stage"]
-        ctx.profile(False)
-        gbs64 = p64["alg_bytes"] / (p64["total_ms"] * 1e-3) / 1e9 if p64["total_ms"] > 0 else 0.0
-        fp64 = {"time_s": t64, "its": st64["its"], "matvecs": st64["matvecs"], "final_relres": st64["final_relres"],
-                "stage_gbs": gbs64, "speedup_mixed_vs_fp64": t64 / t_mixed}
-        log("plain FP64: %.3f s, its %d, relres %.3e, stage %.0f GB/s" % (t64, st64["its"], st64["final_relres"],
-                                                                         gbs64))
-        del u64
-
-    small = None
-    if not args.no_small:
-        small = small_configs_arm(args, ctx)
-
-    uneven = None
-    if args.uneven > 0:
-        uneven = uneven_arm(args, ctx, verbose)
-
-    inner = None
-    if args.k_in_list:
-        inner = inner_arm(args, ctx, op, cont, f_d, t_mixed, st["its"])
-
-    spectral = None
-    if args.spectral:
-        spectral = spectral_arm(args, ctx)
-
-    params = None
-    if args.params:
-        params = params_arm(args, ctx, op, f_d, t_mixed, st["its"])
-
-    case_two = None
-    if args.case_two:
-        case_two = case_two_arm(args, ctx, op, cont, wl)
-
-    learned = None
-    if not args.no_learned:
-        learned = learned_arm(args, ctx, op, cont, f_d, t_mixed, fp64, verbose)
-
-    cpu = None
-    if not args.no_cpu:
-        from oracle import fci as OF
-        poles_o = OF.pole_parameters(o, args.poles, 1.0, args.eps, args.q)
-        cpu = cpu_baseline(wl, poles_o, st["matvecs"])
-        log("cpu baseline:", cpu["sample"])
+    if fp64 and "time_s" in fp64:
+        fp64["speedup_mixed_vs_fp64"] = fp64["time_s"] / t_mixed
 
     out = {
         "metric": METRIC,
         "value": round(t_mixed, 4),
         "unit": "s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": len(times),
+        "warmup": warm_done,
+        "steps_requested": args.steps,
+        "warmup_requested": args.warmup,
         "ms_per_step": round(t_mixed * 1e3, 2),
+        "step_times_s": [round(t, 3) for t in times],
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -684,22 +831,20 @@ def main():
                      "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": bytes_per_launch,
                      "launches": stage["launches"], "timed_every": args.profile_every},
         "cpu_baseline": cpu,
-        "its": st["its"],
-        "matvecs": st["matvecs"],
-        "matvecs_per_s": round(st["matvecs"] / t_mixed, 1),
-        "final_relres": st["final_relres"],
+        "its": st_first["its"],
+        "matvecs": st_first["matvecs"],
+        "matvecs_per_s": round(st_first["matvecs"] / t1, 1),
+        "final_relres": st_first["final_relres"],
         "relres_oracle_rhs0": relres_oracle,
         "factor_kernels_gbs": other_gbs,
         "factor_kernels_timed_ms": launch_ms,
         "fp64": fp64,
         "learned": learned,
-        "uneven_batch": uneven,
-        "small_configs": small,
-        "case_two": case_two,
-        "inner_step4": inner,
-        "contour_choice": params,
-        "spectral": spectral,
+        "budget_s": args.budget,
+        "run_s": round(time.monotonic() - T_START, 1),
+        "not_run": skip or None,
     }
+    out.update(optional)
     print(json.dumps(out), flush=True)
 
 

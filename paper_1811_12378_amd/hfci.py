@@ -174,6 +174,24 @@ def _ptr(t, dtype=None, what="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _check_grid(op, t, what, lead=1):
+    """Raise ValueError unless t is `lead` leading batch dimensions followed by the
+    operator's grid shape (op.shape: [nz, ny, nx], or [2, nz, ny, nx] for case two).
+    The library derives every vector length from op.n and the batch count alone, so a
+    wrongly shaped tensor must never reach it."""
+    shp = tuple(op.shape)
+    if t.dim() != lead + len(shp) or tuple(t.shape[lead:]) != shp:
+        raise ValueError("%s has shape %s; expected %d batch dimension(s) followed by %s"
+                         % (what, tuple(t.shape), lead, list(shp)))
+
+
+def _check_like(t, ref, what):
+    """t must match ref in shape, dtype and device (an initial guess against its f)."""
+    if tuple(t.shape) != tuple(ref.shape) or t.dtype != ref.dtype or t.device != ref.device:
+        raise ValueError("%s must match f: shape %s dtype %s device %s, got %s %s %s"
+                         % (what, tuple(ref.shape), ref.dtype, ref.device, tuple(t.shape), t.dtype, t.device))
+
+
 def default_opts(**kw) -> SolveOpts:
     o = SolveOpts()
     load_library().hfci_default_opts(ctypes.byref(o))
@@ -416,8 +434,9 @@ class Net(_Handle):
     def apply(self, op, r):
         """hfci_net_apply: complex128 [nvec, nz, ny, nx] -> z of the same shape."""
         import torch
+        _check_grid(op, r, "r")
         z = torch.empty_like(r)
-        nvec = r.numel() // op.n
+        nvec = r.shape[0]
         _sync()
         _check(load_library().hfci_net_apply(self.h, op.h, nvec, _ptr(r, torch.complex128, "r"), _ptr(z)))
         return z
@@ -505,6 +524,7 @@ def shifted_solve(op, c: Contour, f, steps: int = 0, reduce: float = 5.0, max_st
     """hfci_shifted_solve: f [nrhs, *op.shape] -> (y [J, nrhs, *op.shape], steps taken [J, nrhs])."""
     import torch
     prec = _prec_of(f)
+    _check_grid(op, f, "f")
     nrhs = f.shape[0]
     y = torch.empty((c.J,) + tuple(f.shape), dtype=f.dtype, device=f.device)
     st = (ctypes.c_int * (c.J * nrhs))()
@@ -517,6 +537,9 @@ def shifted_solve(op, c: Contour, f, steps: int = 0, reduce: float = 5.0, max_st
 def fci_apply(op: Operator, c: Contour, f, opts: SolveOpts | None = None):
     """hfci_fci_apply (Algorithm 1): f complex128 [nrhs, nz, ny, nx] -> out, stats."""
     import torch
+    _check_grid(op, f, "f")
+    if f.dtype != torch.complex128:
+        raise TypeError("f must be complex128, got %s" % f.dtype)
     opts = opts or default_opts()
     out = torch.empty_like(f)
     st = Stats()
@@ -530,6 +553,11 @@ def fci_apply(op: Operator, c: Contour, f, opts: SolveOpts | None = None):
 def solve(op: Operator, c: Contour | None, f, u0=None, opts: SolveOpts | None = None):
     """hfci_solve: physical f complex128 [nrhs, nz, ny, nx] -> (u, stats, status)."""
     import torch
+    _check_grid(op, f, "f")
+    if f.dtype != torch.complex128:
+        raise TypeError("f must be complex128, got %s" % f.dtype)
+    if u0 is not None:
+        _check_like(u0, f, "u0")
     opts = opts or default_opts()
     u = torch.zeros_like(f) if u0 is None else u0.clone()
     st = Stats()
@@ -554,7 +582,13 @@ def shifted_solve_batch(ops, contours, fs, steps: int = 0, reduce: float = 5.0, 
     """hfci_shifted_solve_batch: fs[i] [nz_i, ny_i, nx_i] (one rhs per instance, complex64 or complex128)
     -> ([y_i [J_i, nz_i, ny_i, nx_i]], [steps_i [J_i]])."""
     import torch
+    if not (len(ops) == len(contours) == len(fs)) or not ops:
+        raise ValueError("ops, contours and fs must be non-empty lists of one length")
     prec = _prec_of(fs[0])
+    for i, (o, f) in enumerate(zip(ops, fs)):
+        _check_grid(o, f, "fs[%d]" % i, lead=0)
+        if f.dtype != fs[0].dtype:
+            raise TypeError("fs[%d] has dtype %s; every right-hand side must be %s" % (i, f.dtype, fs[0].dtype))
     ys = [torch.empty((c.J,) + tuple(f.shape), dtype=f.dtype, device=f.device) for c, f in zip(contours, fs)]
     nsys = sum(c.J for c in contours)
     st = (ctypes.c_int * nsys)()
@@ -576,8 +610,17 @@ def shifted_solve_batch(ops, contours, fs, steps: int = 0, reduce: float = 5.0, 
 def solve_batch(ops, contours, fs, opts: SolveOpts | None = None, u0s=None):
     """hfci_solve_batch: physical fs[i] complex128 [nz_i, ny_i, nx_i] -> ([u_i], [stats_i], status)."""
     import torch
-    opts = opts or default_opts()
     n = len(ops)
+    if n == 0 or len(fs) != n or (contours is not None and len(contours) != n) or \
+            (u0s is not None and len(u0s) != n):
+        raise ValueError("ops, contours, fs (and u0s) must be non-empty lists of one length")
+    for i, (o, f) in enumerate(zip(ops, fs)):
+        _check_grid(o, f, "fs[%d]" % i, lead=0)
+        if f.dtype != torch.complex128:
+            raise TypeError("fs[%d] must be complex128, got %s" % (i, f.dtype))
+        if u0s is not None:
+            _check_like(u0s[i], f, "u0s[%d]" % i)
+    opts = opts or default_opts()
     us = [torch.zeros_like(f) if u0s is None else u0s[i].clone() for i, f in enumerate(fs)]
     sts = (Stats * n)()
     for k in range(n):

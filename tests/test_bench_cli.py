@@ -21,3 +21,36 @@ def test_bench_refuses_a_distributed_launch():
                        timeout=120, cwd=ROOT, env=env)
     assert r.returncode == 2
     assert "--gpus 1" in r.stderr
+
+
+def _bench_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return m
+
+
+def test_budget_counts_from_process_start_and_skips():
+    b = _bench_module()
+    bud = b.Budget(5.0)
+    assert bud.left() <= 5.0
+    assert not bud.fits(10.0)
+    rec = b.skipped(10.0, bud)
+    assert rec["skipped"] == "budget" and rec["estimate_s"] == 10.0
+    assert b.Budget(0).fits(1e9)  # 0 = no budget
+
+
+def test_guarded_arm_turns_errors_into_records():
+    b = _bench_module()
+    assert b.guarded(lambda: {"ok": 1}) == {"ok": 1}
+    rec = b.guarded(lambda: 1 / 0)
+    assert "ZeroDivisionError" in rec["error"]
+
+
+def test_profiles_of_several_timed_solves_add_up():
+    b = _bench_module()
+    p = {"fp_stage": {"launches": 2, "total_ms": 1.5, "alg_bytes": 10.0}}
+    q = {"fp_stage": {"launches": 3, "total_ms": 2.0, "alg_bytes": 5.0}}
+    assert b.add_prof(None, p) == p
+    assert b.add_prof(p, q) == {"fp_stage": {"launches": 5, "total_ms": 3.5, "alg_bytes": 15.0}}

@@ -189,7 +189,8 @@ def test_case_two_unsupported_entry_points(ctx):
     o2, g2, g = make(ctx, (6, 6, 6), 11, 9.0, 1, 0.5)
     poles, cg = contour_pair(o2, g2, 4, 4)
     f = dev(np.ones((1, 6, 6, 6), dtype=np.complex128))
-    for call in (lambda: hf.solve(g2, cg, f, opts=hf.default_opts(precond=hf.HFCI_PRECOND_LEARNED)),
+    f2 = dev(np.ones((1, 2, 6, 6, 6), dtype=np.complex128))
+    for call in (lambda: hf.solve(g2, cg, f2, opts=hf.default_opts(precond=hf.HFCI_PRECOND_LEARNED)),
                  lambda: hf.Operator.set_tune(g2, 32, 1, 8, 2, 0, 0),
                  lambda: hf.Operator.autotune(g2, 32, 2),
                  lambda: hf._check(hf.load_library().hfci_op_case_two(g2.h, ctypes.byref(ctypes.c_void_p())))):
