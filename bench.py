@@ -598,7 +598,7 @@ def main():
     ap.add_argument("--small-only", action="store_true", help="run only the 32^3 / 96^3 configurations")
     ap.add_argument("--profile-every", type=int, default=PROFILE_EVERY,
                     help="time every k-th launch of each kernel class in the timed solves")
-    ap.add_argument("--shape", type=int, nargs=5, metavar=("KERN", "TY", "PD", "CZ", "FUSE"),
+    ap.add_argument("--shape", type=int, nargs="+", metavar="V",
                     help="pin the complex64 stencil launch shape instead of autotuning it")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -189,7 +189,7 @@ void hfci_op_destroy(hfci_op* op);
 hfci_status hfci_op_info(const hfci_op* op, double* out7);
 
 /* Launch shape of the operator's z-marching stencil kernels for one precision
- * (HFCI_F32 or HFCI_F64), tune[5] (HOST array):
+ * (HFCI_F32 or HFCI_F64), tune[6] (HOST array):
  *   tune[0] kern: 0 = in-plane neighbours as cached global loads, 1 = each plane
  *           staged through LDS with its halo;
  *   tune[1] ty:   the thread tile is 64 x ty (4 or 8);
@@ -197,24 +197,28 @@ hfci_status hfci_op_info(const hfci_op* op, double* out7);
  *                 kern 1: 1..3 with ty = 4, 2..3 with ty = 8);
  *   tune[3] cz:   z-chunk length in planes (1..4096, or 0 = chosen from the grid);
  *   tune[4] fuse: 1 = the fixed-point factors run two per pass over HBM (temporal
- *                 blocking on 64 x 12 tiles with z-chunks cz), 0 = one per pass.
+ *                 blocking on 64 x 12 tiles with z-chunks cz), 0 = one per pass;
+ *   tune[5] sg:   1..16; with fuse = 1 on grids whose pair tiles split into 8 XCD
+ *                 slabs, the systems of a launch are taken sg at a time, tile by tile,
+ *                 so kappa of a tile is read once per sg systems (1 = one system's
+ *                 tiles after another's).
  * Shapes change launch geometry only: every grid point gets the same arithmetic,
  * while reductions (residual norms, the step size d) sum their block partials in a
- * different order.  New operators start at {1, 8, 2, 0, 0}.  Errors: HFCI_E_ARG. */
-hfci_status hfci_op_set_tune(hfci_op* op, int prec, const int* tune5);
-hfci_status hfci_op_get_tune(const hfci_op* op, int prec, int* tune5);
+ * different order.  New operators start at {1, 8, 2, 0, 0, 1}.  Errors: HFCI_E_ARG. */
+hfci_status hfci_op_set_tune(hfci_op* op, int prec, const int* tune6);
+hfci_status hfci_op_get_tune(const hfci_op* op, int prec, int* tune6);
 
 /* Launch-shape autotuner: times the middle factors of the fixed-point iteration
  * (the dominant launches) over nsys systems (1..64, e.g. the number of shifted
  * systems that usually iterate together) for every valid shape, one and two factors
  * per pass, keeps the fastest per factor for this operator and precision and writes
- * it to best5 (HOST, may be NULL).  timings (HOST, may be NULL if cap = 0) receives
- * up to cap rows of {kern, ty, pd, cz, fuse, milliseconds per factor}; *count (may
- * be NULL) the number of shapes timed.  Uses the context's workspace (2 nsys vectors of the precision);
- * the operator's inputs and outputs of other calls are not touched.  Timing-based,
- * so two runs may pick different shapes (results then differ only in the summation
- * order of reductions).  Errors: HFCI_E_ARG. */
-hfci_status hfci_op_autotune(hfci_op* op, int prec, int nsys, int* best5, double* timings, int cap,
+ * it to best6 (HOST, may be NULL).  timings (HOST, may be NULL if cap = 0) receives
+ * up to cap rows of {kern, ty, pd, cz, fuse, sg, milliseconds per factor}; *count
+ * (may be NULL) the number of shapes timed.  Uses the context's workspace (2 nsys
+ * vectors of the precision); the operator's inputs and outputs of other calls are not
+ * touched.  Timing-based, so two runs may pick different shapes (results then differ
+ * only in the summation order of reductions).  Errors: HFCI_E_ARG. */
+hfci_status hfci_op_autotune(hfci_op* op, int prec, int nsys, int* best6, double* timings, int cap,
                              int* count);
 
 /* y_k = (A - shift I) x_k for k < nvec (normalised A).  prec: HFCI_F64
@@ -292,6 +296,23 @@ hfci_status hfci_contour_get(const hfci_contour* c, hfci_c128* z, hfci_c128* sig
 hfci_status hfci_shifted_solve(const hfci_op* op, const hfci_contour* c, int prec,
                                int nrhs, const void* f, void* y, int steps,
                                double reduce, int max_steps, int* steps_taken);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): hfci_shifted_solve with every buffer
+ * beyond f and y (the iterates' step constants and factor buffers, residual partials,
+ * flags, lists and step counters) taken from a static device array of 64 MiB per GPU
+ * instead of the context's workspace.  Same arguments, results and errors as
+ * hfci_shifted_solve, bit for bit, for a case-one operator; it calls no hipMalloc,
+ * hipFree or allocating library routine.  The array is looked up once per device when a
+ * context is created there and stays allocated until the process ends.  Every call on a
+ * GPU shares that GPU's array: calls that overlap in time on one GPU race.  Kernel timing
+ * (hfci_ctx_profile) is paused during the call.
+ * Errors: as hfci_shifted_solve; HFCI_E_ARG when the solve needs more than the 64 MiB
+ * (about 3 J nrhs n complex values of the precision), before any launch; HFCI_E_STATE
+ * for a case-two or spectral operator. */
+hfci_status hfci_shifted_solve_noalloc(const hfci_op* op, const hfci_contour* c, int prec,
+                                       int nrhs, const void* f, void* y, int steps,
+                                       double reduce, int max_steps, int* steps_taken);
 
 /* ---- FCI preconditioner (Algorithm 1) --------------------------------------
  * out_k = v + d_k w_k with w_k = sum_j sigma_j/z_j y_jk (steps 1-2),

@@ -25,8 +25,34 @@ void throw_hip(hipError_t e, const char* what, const char* file, int line) {
   throw Error(e == hipErrorOutOfMemory ? HFCI_E_OOM : HFCI_E_HIP, msg);
 }
 
+void Workspace::set_arena(void* base, size_t cap) {
+  arena_ = (char*)base;
+  arena_cap_ = cap;
+  arena_used_ = 0;
+  slices_.clear();
+}
+
+void Workspace::clear_arena() {
+  arena_ = nullptr;
+  arena_cap_ = arena_used_ = 0;
+  slices_.clear();
+}
+
 void* Workspace::get(const std::string& tag, size_t bytes) {
   if (bytes == 0) bytes = 16;
+  if (arena_) {
+    Buf& sl = slices_[tag];
+    if (sl.bytes >= bytes) return sl.p;
+    const size_t off = (arena_used_ + 255) & ~(size_t)255;
+    if (off > arena_cap_ || bytes > arena_cap_ - off)
+      throw Error(HFCI_E_ARG, "the call needs more than the " + std::to_string(arena_cap_) +
+                                  "-byte static scratch buffer (at '" + tag + "': " + std::to_string(off + bytes) +
+                                  " bytes so far)");
+    sl.p = arena_ + off;
+    sl.bytes = bytes;
+    arena_used_ = off + bytes;
+    return sl.p;
+  }
   Buf& b = bufs_[tag];
   if (b.bytes >= bytes) return b.p;
   if (b.p) {
@@ -226,6 +252,7 @@ hfci_status hfci_ctx_create(int device, void* stream, hfci_ctx** out) {
     HFCI_HIP(hipHostGetDevicePointer((void**)&c->pinned_int_dev, c->pinned_int, 0));
     HFCI_HIP(hipHostMalloc((void**)&c->pinned_dbl, kPinnedDbls * sizeof(double), hipHostMallocDefault));
     for (hipEvent_t& e : c->step_event) HFCI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->noalloc_scratch = noalloc_scratch_for_device(device);
   } catch (...) {
     for (hipEvent_t e : c->step_event)
       if (e) (void)hipEventDestroy(e);
@@ -447,8 +474,10 @@ hfci_status hfci_op_set_tune(hfci_op* op, int prec, const int* t3) {
   t.pd = t3[2];
   t.cz = t3[3];
   t.fuse = t3[4];
-  HFCI_REQUIRE(tune_valid(t), "tune must be {0, ty in {4, 8}, pd in {1, 2}, cz, fuse} or {1, 4, pd in 1..3, cz, fuse} "
-                              "or {1, 8, pd in {2, 3}, cz, fuse}, cz in [0, 4096], fuse in {0, 1}");
+  t.sg = t3[5];
+  HFCI_REQUIRE(tune_valid(t), "tune must be {0, ty in {4, 8}, pd in {1, 2}, cz, fuse, sg} or {1, 4, pd in 1..3, cz, "
+                              "fuse, sg} or {1, 8, pd in {2, 3}, cz, fuse, sg}, cz in [0, 4096], fuse in {0, 1}, "
+                              "sg in [1, 16]");
   (prec == HFCI_F32 ? op->g.tune32 : op->g.tune64) = t;
   return HFCI_OK;
   HFCI_API_END
@@ -464,11 +493,12 @@ hfci_status hfci_op_get_tune(const hfci_op* op, int prec, int* t3) {
   t3[2] = t.pd;
   t3[3] = t.cz;
   t3[4] = t.fuse;
+  t3[5] = t.sg;
   return HFCI_OK;
   HFCI_API_END
 }
 
-hfci_status hfci_op_autotune(hfci_op* op, int prec, int nsys, int* best5, double* timings, int cap, int* count) {
+hfci_status hfci_op_autotune(hfci_op* op, int prec, int nsys, int* best6, double* timings, int cap, int* count) {
   HFCI_API_BEGIN
   HFCI_REQUIRE(op, "NULL operator");
   require_case_one(op);
@@ -478,21 +508,23 @@ hfci_status hfci_op_autotune(hfci_op* op, int prec, int nsys, int* best5, double
   DeviceGuard dg(op->device);
   std::vector<std::pair<KernelTune, double>> tm;
   const KernelTune b = prec == HFCI_F32 ? autotune_shapes<float2>(*op, nsys, tm) : autotune_shapes<double2>(*op, nsys, tm);
-  if (best5) {
-    best5[0] = b.kern;
-    best5[1] = b.ty;
-    best5[2] = b.pd;
-    best5[3] = b.cz;
-    best5[4] = b.fuse;
+  if (best6) {
+    best6[0] = b.kern;
+    best6[1] = b.ty;
+    best6[2] = b.pd;
+    best6[3] = b.cz;
+    best6[4] = b.fuse;
+    best6[5] = b.sg;
   }
   const int m = std::min<int>(cap, (int)tm.size());
   for (int k = 0; k < m; ++k) {
-    timings[6 * k + 0] = tm[k].first.kern;
-    timings[6 * k + 1] = tm[k].first.ty;
-    timings[6 * k + 2] = tm[k].first.pd;
-    timings[6 * k + 3] = tm[k].first.cz;
-    timings[6 * k + 4] = tm[k].first.fuse;
-    timings[6 * k + 5] = tm[k].second;
+    timings[7 * k + 0] = tm[k].first.kern;
+    timings[7 * k + 1] = tm[k].first.ty;
+    timings[7 * k + 2] = tm[k].first.pd;
+    timings[7 * k + 3] = tm[k].first.cz;
+    timings[7 * k + 4] = tm[k].first.fuse;
+    timings[7 * k + 5] = tm[k].first.sg;
+    timings[7 * k + 6] = tm[k].second;
   }
   if (count) *count = (int)tm.size();
   return HFCI_OK;
@@ -684,6 +716,44 @@ hfci_status hfci_shifted_solve(const hfci_op* op, const hfci_contour* c, int pre
                                 steps_taken, st);
   HFCI_HIP(hipGetLastError());
   HFCI_HIP(hipStreamSynchronize(op->ctx->stream));
+  return HFCI_OK;
+  HFCI_API_END
+}
+
+hfci_status hfci_shifted_solve_noalloc(const hfci_op* op, const hfci_contour* c, int prec, int nrhs, const void* f,
+                                       void* y, int steps, double reduce, int max_steps, int* steps_taken) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(op && c && f && y, "NULL argument");
+  require_case_one(op);
+  if (c->op != op) throw Error(HFCI_E_STATE, "contour was created for another operator");
+  HFCI_REQUIRE(prec == HFCI_F32 || prec == HFCI_F64, "prec must be 32 or 64");
+  HFCI_REQUIRE(nrhs >= 1 && (long)nrhs * c->J <= 65536, "nrhs out of range");
+  HFCI_REQUIRE(steps > 0 || (reduce > 1.0 && max_steps >= 1), "give steps > 0, or reduce > 1 and max_steps >= 1");
+  Ctx& ctx = *op->ctx;
+  HFCI_REQUIRE(ctx.noalloc_scratch != nullptr, "no static scratch array on this device");
+  DeviceGuard dg(ctx.device);
+  // Every buffer of the solve is a slice of the static array: the workspace allocates
+  // nothing while the arena is set, and a solve that does not fit raises HFCI_E_ARG at
+  // its first buffer request, before any launch.  Kernel timing (which takes events
+  // from a pool that may grow) is paused for the call.
+  const int period = ctx.prof.on ? ctx.prof.period : 0;
+  ctx.prof.on = false;
+  try {
+    ArenaScope arena(ctx.ws, ctx.noalloc_scratch, kNoAllocScratchBytes);
+    FciStats st;
+    if (prec == HFCI_F64)
+      shifted_solve_batch<double2>(*op, *c, nrhs, (const double2*)f, (double2*)y, steps, reduce, max_steps,
+                                   steps_taken, st);
+    else
+      shifted_solve_batch<float2>(*op, *c, nrhs, (const float2*)f, (float2*)y, steps, reduce, max_steps,
+                                  steps_taken, st);
+    HFCI_HIP(hipGetLastError());
+    HFCI_HIP(hipStreamSynchronize(ctx.stream));
+  } catch (...) {
+    if (period > 0) ctx.prof.on = true;
+    throw;
+  }
+  if (period > 0) ctx.prof.on = true;
   return HFCI_OK;
   HFCI_API_END
 }

@@ -43,12 +43,34 @@ class Workspace {
   void release_all();
   ~Workspace() { release_all(); }
 
+  // While an arena is set, get() allocates nothing: it hands out 256-byte aligned slices
+  // of [base, base + cap), one per tag (the same tag gets the same slice while the arena
+  // is set), and throws HFCI_E_ARG when a request does not fit.  ArenaScope sets one for
+  // the duration of a call.
+  void set_arena(void* base, size_t cap);
+  void clear_arena();
+  size_t arena_used() const { return arena_used_; }
+
  private:
   struct Buf {
     void* p = nullptr;
     size_t bytes = 0;
   };
   std::map<std::string, Buf> bufs_;
+  char* arena_ = nullptr;
+  size_t arena_cap_ = 0, arena_used_ = 0;
+  std::map<std::string, Buf> slices_;
+};
+
+class ArenaScope {
+ public:
+  ArenaScope(Workspace& ws, void* base, size_t cap) : ws_(ws) { ws_.set_arena(base, cap); }
+  ~ArenaScope() { ws_.clear_arena(); }
+  ArenaScope(const ArenaScope&) = delete;
+  ArenaScope& operator=(const ArenaScope&) = delete;
+
+ private:
+  Workspace& ws_;
 };
 
 // Layout of Ctx::pinned_dbl: [0, kPinnedFciOffset) FGMRES scalars, then FCI weights.
@@ -121,7 +143,13 @@ struct Ctx {
   void* blas = nullptr;          // rocBLAS handle of the inner preconditioner (created on first use)
   std::map<int, double2*> sine;  // orthonormal DST-I matrices by size (device, complex)
   std::map<std::string, void*> fft;  // FFT plans of spectral operators by grid, precision, batch
+  void* noalloc_scratch = nullptr;   // this device's static scratch array (noalloc.cpp)
 };
+
+// The device address of the static scratch array of the no-allocation entry point, looked
+// up once per device with that device current (noalloc.cpp); its size in bytes.
+void* noalloc_scratch_for_device(int device);
+extern const size_t kNoAllocScratchBytes;
 
 struct Op {
   Ctx* ctx = nullptr;

@@ -15,7 +15,9 @@ namespace hfci {
 // fuse 1 applies the fixed-point factors two per pass (64 x 12 tiles, z-chunks cz; loads
 // one plane ahead, two when pd is 3).
 struct KernelTune {
-  int kern = 1, ty = 8, pd = 2, cz = 0, fuse = 0;
+  // sg: with two factors per pass, the systems of a launch are taken sg at a time, tile
+  // by tile, inside each XCD's slab of tiles (1 = system after system)
+  int kern = 1, ty = 8, pd = 2, cz = 0, fuse = 0, sg = 1;
 };
 
 // Geometry and operator scalars of the normalised A = (s/h^2) L7 - kappa - i D, plus

@@ -618,15 +618,34 @@ __device__ __forceinline__ void pair_tile(const GridDesc& g, int czlen, int gx, 
   }
 }
 
+// Block order.  Workgroups are dispatched round-robin over the 8 XCDs, so workgroup w
+// runs on XCD w % 8 as the (w / 8)-th of that XCD.  With XCD slabs (xcd_slab > 0: a
+// system's tiles split into 8 contiguous slabs, one per XCD) each XCD walks its slab of
+// every listed system, and y/z neighbours of a tile meet in that XCD's L2.  With
+// sgrp > 1 the listed systems go sgrp at a time, tile by tile: an XCD runs tile t of
+// systems s0 .. s0+sgrp-1 back to back, then tile t+1, so kappa of a tile comes from
+// HBM once per group instead of once per system, while neighbouring tiles of one
+// system still run close together.  The last group may hold fewer systems.
 template <typename T, int KIND, int D>
 __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(pair_waves_per_eu<T, KIND>()))) void zpair_kernel(GridDesc g, int nzc, int czlen, int xcd_slab,
-                                                    FactorArgs<typename V2<T>::t> a, const T* __restrict__ K) {
+                                                    int sgrp, FactorArgs<typename V2<T>::t> a, const T* __restrict__ K) {
   const int gx = (g.nx + PX - 1) / PX, gy = (g.ny + PY - 1) / PY;
   const int per_sys = gx * gy * nzc;
-  const int s = a.list[blockIdx.x / per_sys];
+  int li, b;  // index into the active list, tile of that system
+  if (xcd_slab > 0 && sgrp > 1) {
+    const int xcd = blockIdx.x % 8, k = blockIdx.x / 8;  // k < count * xcd_slab
+    const int gsz = sgrp * xcd_slab;
+    const int s0 = (k / gsz) * sgrp, r = k % gsz;
+    const int gs = min(sgrp, a.count - s0);
+    li = s0 + r % gs;
+    b = xcd * xcd_slab + r / gs;
+  } else {
+    li = blockIdx.x / per_sys;
+    b = blockIdx.x % per_sys;
+    if (xcd_slab > 0) b = (b % 8) * xcd_slab + b / 8;
+  }
+  const int s = a.list[li];
   if (s < 0) return;  // a stopped system past the end of the active list (uniform)
-  int b = blockIdx.x % per_sys;
-  if (xcd_slab > 0) b = (b % 8) * xcd_slab + b / 8;
   pair_tile<T, KIND, D>(g, czlen, gx, gy, per_sys, s, b, a, K);
 }
 
@@ -1009,18 +1028,20 @@ void run_pair(hipStream_t st, const GridDesc& g, const void* kappa, const Factor
   if (a.count <= 0) return;
   const PairShape p = pair_shape<T>(g);
   const dim3 grid((unsigned)p.per_sys * (unsigned)a.count);
+  const int sgrp = tune_of<T>(g).sg;
   if (tune_of<T>(g).pd >= 3)
-    hipLaunchKernelGGL((zpair_kernel<T, KIND, 2>), grid, dim3(PNT), 0, st, g, p.nzc, p.czlen, p.xcd_slab, a,
-                       (const T*)kappa);
+    hipLaunchKernelGGL((zpair_kernel<T, KIND, 2>), grid, dim3(PNT), 0, st, g, p.nzc, p.czlen, p.xcd_slab, sgrp,
+                       a, (const T*)kappa);
   else
-    hipLaunchKernelGGL((zpair_kernel<T, KIND, 1>), grid, dim3(PNT), 0, st, g, p.nzc, p.czlen, p.xcd_slab, a,
-                       (const T*)kappa);
+    hipLaunchKernelGGL((zpair_kernel<T, KIND, 1>), grid, dim3(PNT), 0, st, g, p.nzc, p.czlen, p.xcd_slab, sgrp,
+                       a, (const T*)kappa);
 }
 
 }  // namespace
 
 bool tune_valid(const KernelTune& t) {
   if (t.cz < 0 || t.cz > 4096 || !(t.ty == 4 || t.ty == 8) || !(t.fuse == 0 || t.fuse == 1)) return false;
+  if (t.sg < 1 || t.sg > 16) return false;
   if (t.kern == 0) return t.pd == 1 || t.pd == 2;
   if (t.kern == 1) return (t.ty == 4 && t.pd >= 1 && t.pd <= 3) || (t.ty == 8 && (t.pd == 2 || t.pd == 3));
   return false;

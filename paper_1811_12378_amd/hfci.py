@@ -34,7 +34,7 @@ EXPORTED = ["hfci_default_opts", "hfci_last_error", "hfci_version", "hfci_ctx_cr
             "hfci_net_eval", "hfci_net_train_step", "hfci_net_train", "hfci_net_apply", "hfci_op_medium_channel",
             "hfci_net_save", "hfci_net_load", "hfci_op_set_tune", "hfci_op_get_tune", "hfci_op_autotune",
             "hfci_shifted_solve_batch", "hfci_solve_batch", "hfci_op_case_two", "hfci_contour_q",
-            "hfci_op_create_spectral"]
+            "hfci_op_create_spectral", "hfci_shifted_solve_noalloc"]
 PROF_CLASSES = ["fp_stage", "fp_stage_first", "apply", "fp_stage_last", "fp_stage_init"]
 
 
@@ -121,6 +121,7 @@ def load_library(path: str = LIB_PATH):
         "hfci_contour_get": (ip, [vp, vp, vp, vp, vp, vp]),
         "hfci_contour_q": (ip, [vp, P(ip)]),
         "hfci_shifted_solve": (ip, [vp, vp, ip, ip, vp, vp, ip, dp, ip, vp]),
+        "hfci_shifted_solve_noalloc": (ip, [vp, vp, ip, ip, vp, vp, ip, dp, ip, vp]),
         "hfci_fci_apply": (ip, [vp, vp, P(SolveOpts), ip, vp, vp, P(Stats)]),
         "hfci_solve": (ip, [vp, vp, P(SolveOpts), ip, vp, vp, P(Stats)]),
         "hfci_ctx_profile": (ip, [vp, ip]),
@@ -296,26 +297,26 @@ class Operator(_Handle):
         keys = ["s", "s_h2", "b1", "b2", "rho2", "kappa_min", "kappa_max"]
         return dict(zip(keys, list(out)))
 
-    def set_tune(self, prec: int, kern: int, ty: int, pd: int, cz: int = 0, fuse: int = 0):
+    def set_tune(self, prec: int, kern: int, ty: int, pd: int, cz: int = 0, fuse: int = 0, sg: int = 1):
         """hfci_op_set_tune: stencil launch shape (kernel, 64 x ty tile, prefetch depth pd, z-chunk cz,
-        two fixed-point factors per pass)."""
-        t = (ctypes.c_int * 5)(kern, ty, pd, cz, fuse)
+        two fixed-point factors per pass, systems taken sg at a time tile by tile)."""
+        t = (ctypes.c_int * 6)(kern, ty, pd, cz, fuse, sg)
         _check(load_library().hfci_op_set_tune(self.h, prec, ctypes.cast(t, ctypes.c_void_p)))
 
     def autotune(self, prec: int, nsys: int = 2):
         """hfci_op_autotune: pick the fastest stencil launch shape; returns (best, [(shape, ms), ...])."""
-        best = (ctypes.c_int * 5)()
-        cap = 64
-        tm = (ctypes.c_double * (6 * cap))()
+        best = (ctypes.c_int * 6)()
+        cap = 128
+        tm = (ctypes.c_double * (7 * cap))()
         cnt = ctypes.c_int()
         _check(load_library().hfci_op_autotune(self.h, prec, nsys, ctypes.cast(best, ctypes.c_void_p),
                                                ctypes.cast(tm, ctypes.c_void_p), cap,
                                                ctypes.cast(ctypes.byref(cnt), ctypes.c_void_p)))
-        rows = [(tuple(int(v) for v in tm[6 * k:6 * k + 5]), float(tm[6 * k + 5])) for k in range(min(cnt.value, cap))]
+        rows = [(tuple(int(v) for v in tm[7 * k:7 * k + 6]), float(tm[7 * k + 6])) for k in range(min(cnt.value, cap))]
         return tuple(best), rows
 
     def get_tune(self, prec: int):
-        t = (ctypes.c_int * 5)()
+        t = (ctypes.c_int * 6)()
         _check(load_library().hfci_op_get_tune(self.h, prec, ctypes.cast(t, ctypes.c_void_p)))
         return tuple(t)
 
@@ -532,6 +533,22 @@ def shifted_solve(op, c: Contour, f, steps: int = 0, reduce: float = 5.0, max_st
     _check(load_library().hfci_shifted_solve(op.h, c.h, prec, nrhs, _ptr(f, None, "f"), _ptr(y), steps, reduce,
                                              max_steps, ctypes.cast(st, ctypes.c_void_p)))
     return y, np.array(st[:]).reshape(c.J, nrhs)
+
+
+def shifted_solve_noalloc(op, c: Contour, f, y, steps: int = 0, reduce: float = 5.0, max_steps: int = 200):
+    """hfci_shifted_solve_noalloc: as shifted_solve, into a caller-provided y [J, nrhs, *op.shape]
+    of f's dtype, with every other buffer in the library's static scratch array (no device
+    allocation, by the library or here).  Returns the steps taken [J, nrhs]."""
+    prec = _prec_of(f)
+    _check_grid(op, f, "f")
+    nrhs = f.shape[0]
+    if tuple(y.shape) != (c.J,) + tuple(f.shape) or y.dtype != f.dtype or y.device != f.device:
+        raise ValueError("y must be [J, nrhs, *grid] with f's dtype and device")
+    st = (ctypes.c_int * (c.J * nrhs))()
+    _sync()
+    _check(load_library().hfci_shifted_solve_noalloc(op.h, c.h, prec, nrhs, _ptr(f, None, "f"), _ptr(y, None, "y"),
+                                                     steps, reduce, max_steps, ctypes.cast(st, ctypes.c_void_p)))
+    return np.array(st[:]).reshape(c.J, nrhs)
 
 
 def fci_apply(op: Operator, c: Contour, f, opts: SolveOpts | None = None):

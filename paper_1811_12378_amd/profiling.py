@@ -182,7 +182,8 @@ def main(argv=None):
     s.add_argument("--steps", type=int, default=2)
     s.add_argument("--q", type=int, default=8)
     s.add_argument("--prec", type=int, default=32)
-    s.add_argument("--tune", type=int, nargs=5, metavar=("KERN", "TY", "PD", "CZ", "FUSE"))
+    s.add_argument("--tune", type=int, nargs="+", metavar="V",
+                   help="kern ty pd cz fuse [sg]: the stencil launch shape")
     nn = sub.add_parser("net")
     nn.add_argument("--n", type=int, default=256)
     nn.add_argument("--reps", type=int, default=5)

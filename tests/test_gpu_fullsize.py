@@ -1,0 +1,198 @@
+"""The benchmark's own launch path against the FP64 oracle, at full size (needs an MI355X).
+
+The pair kernel (two factors of a fixed-point step per pass over HBM) renumbers its
+workgroups into per-XCD slabs only when a system has at least 64 tiles and the count is
+a multiple of 8.  At 256^3 the fused shape (1, 8, 2, 64, 1) gives 4 x 22 x 4 = 352 tiles
+per system.  The small-grid tests never reach that mapping.  These tests do:
+  * every pair-kernel kind on a grid of 2 x 4 x 8 = 64 ragged tiles per system:
+    plain middle pairs, the residual pair (first of a later step), the y1-adding pair
+    (last of a later step), the pair reading f (step one when q - 1 is even) and the
+    dual-output pair (step one as the only step), with the systems of a launch taken
+    one, three or four at a time tile by tile (sg), and adaptive stopping under groups;
+  * 256^3 lockstep fixed-point steps at the benchmark's shape, 2 poles x 2 sources, over
+    the full grid;
+  * 256^3 and 96^3 solves to 1e-6, the 256^3 one with the autotuner's shape as the
+    benchmark picks it, each residual recomputed in FP64 by the oracle.
+Comparisons are element by element (relmax); the FP32 bars are derived in
+tests/fp32_bounds.py.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fci as OF
+from oracle import fixed_point as OFP
+from oracle import operator as OO
+from tests.fp32_bounds import fixed_point_bar, relmax, round32, stencil_absrow
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+hf = pytest.importorskip("paper_1811_12378_amd.hfci")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hf.load_library()
+    c = hf.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def pair_tiles(shape, cz):
+    nz, ny, nx = shape
+    return -(-nx // 64) * -(-ny // 12) * -(-nz // cz)
+
+
+def tol_of(prec, o, p, q, steps, f, ref):
+    if prec == "f64":
+        return 1e-12
+    return fixed_point_bar(p, q, steps, o.rectangle(), stencil_absrow(o.s_h2, o.kappa, o.rho2),
+                           np.abs(f).max() / np.abs(ref).max())
+
+
+# (q, steps): q = 8 with 3 steps runs the fan-out, plain pairs, the residual pair and the
+# y1 pair; q = 8 with 1 step ends step one with the dual-output pair; q = 5 and q = 7 start
+# step one with the pair that reads f (q - 1 even) and end later steps with a lone factor
+KIND_CASES = [(8, 3), (8, 1), (5, 2), (7, 2)]
+
+
+SLAB_SHAPE = (60, 45, 100)  # ragged in x (64 + 36), y (3 x 12 + 9) and z (7 x 8 + 4)
+
+
+def slab_operator(ctx, seed=71):
+    assert pair_tiles(SLAB_SHAPE, 8) == 64  # >= 64 and a multiple of 8: XCD slabs on
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(1.0, 3.0, size=SLAB_SHAPE)
+    h = 1.0 / 60
+    return OO.Operator(c, 20.0, 3, 1.0, h=h), hf.Operator(ctx, dev(c), h, 20.0, 3, 1.0), rng
+
+
+# sg = 3 over the 8 systems of a launch: groups of 3, 3 and a ragged 2
+@pytest.mark.parametrize("q,steps", KIND_CASES)
+@pytest.mark.parametrize("pd,sg", [(2, 1), (3, 1), (2, 3), (3, 4)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_pair_kinds_with_xcd_slabs(ctx, q, steps, pd, sg, prec):
+    shape = SLAB_SHAPE
+    o, g, rng = slab_operator(ctx)
+    pr = 64 if prec == "f64" else 32
+    g.set_tune(pr, 1, 8, pd, 8, 1, sg)
+    assert g.get_tune(pr) == (1, 8, pd, 8, 1, sg)
+    poles = OF.pole_parameters(o, 4, 1.0, 0.5, q)
+    cg = hf.Contour(g, 4, 1.0, 0.5, q, z=[p.z for p in poles], sigma=[p.sigma for p in poles],
+                    delta=[p.delta for p in poles])
+    f = rng.standard_normal((2,) + shape) + 1j * rng.standard_normal((2,) + shape)
+    if prec == "f32":
+        f = round32(f)
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    y, st = hf.shifted_solve(g, cg, dev(f).to(dt), steps=steps)
+    y = host(y).astype(np.complex128)
+    assert np.all(st == steps)
+    Am = lambda v, sh: o.apply(v, sh)
+    for j, p in enumerate(poles):
+        for r in range(2):
+            ref, _ = OFP.fixed_point_solve(Am, f[r], p.z, p.z0, p.delta, q, steps=steps)
+            e, tol = relmax(y[j, r], ref), tol_of(prec, o, p, q, steps, f[r], ref)
+            assert e <= tol, (j, r, e, tol)
+
+
+@pytest.mark.parametrize("sg", [1, 3])
+def test_adaptive_stops_with_system_groups(ctx, sg):
+    # adaptive stopping at the XCD-slab geometry: the launches after each test are sized for
+    # the systems active one test earlier, so the compacted list ends in -1 entries that a
+    # group of systems must skip; rhs 1 is zero (stops at step 0), rhs 2 is small
+    o, g, rng = slab_operator(ctx, seed=73)
+    g.set_tune(64, 1, 8, 2, 8, 1, sg)
+    q = 8
+    poles = OF.pole_parameters(o, 4, 1.0, 0.5, q)
+    cg = hf.Contour(g, 4, 1.0, 0.5, q, z=[p.z for p in poles], sigma=[p.sigma for p in poles],
+                    delta=[p.delta for p in poles])
+    f = rng.standard_normal((3,) + SLAB_SHAPE) + 1j * rng.standard_normal((3,) + SLAB_SHAPE)
+    f[1] = 0.0
+    f[2] *= 1e-3
+    y, st = hf.shifted_solve(g, cg, dev(f), reduce=5.0, max_steps=60)
+    y = host(y)
+    Am = lambda v, sh: o.apply(v, sh)
+    for j, p in enumerate(poles):
+        assert st[j, 1] == 0 and np.all(y[j, 1] == 0)
+        for r in (0, 2):
+            ref, hist = OFP.fixed_point_solve(Am, f[r], p.z, p.z0, p.delta, q, reduce=5.0, m_max=60)
+            assert st[j, r] == len(hist) - 1, (j, r, st[j, r], len(hist) - 1)
+            assert relmax(y[j, r], ref) <= 1e-12, (j, r, relmax(y[j, r], ref))
+    assert len(set(int(v) for v in st[:, 0])) > 1  # the poles stop at different steps
+
+
+def layered(n, nrhs):
+    return W.config_layered_256(n=n, nrhs=nrhs)
+
+
+def test_headline_shape_lockstep_256(ctx):
+    # the benchmark's workload and fused complex64 shape: 2 of its 16 poles (the one
+    # nearest the origin, the slowest, and one across the contour) x 2 of its point
+    # sources, two fixed-point steps (step one, then residual / middle / y1 pairs)
+    wl = layered(256, 2)
+    o = OO.Operator(wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
+    g = hf.Operator(ctx, dev(wl.c), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
+    g.set_tune(32, 1, 8, 2, 64, 1, 2)
+    assert pair_tiles(o.shape, 64) == 352
+    allp = OF.pole_parameters(o, 16, 1.0, 0.25, 8)
+    poles = [allp[0], allp[8]]
+    cg = hf.Contour(g, 2, 1.0, 0.25, 8, z=[p.z for p in poles], sigma=[p.sigma for p in poles],
+                    delta=[p.delta for p in poles])
+    f = round32(np.stack(wl.rhs))
+    y, st = hf.shifted_solve(g, cg, dev(f).to(torch.complex64), steps=2)
+    assert np.all(st == 2)
+    y = host(y)
+    Am = lambda v, sh: o.apply(v, sh)
+    for j, p in enumerate(poles):
+        for r in range(2):
+            ref, _ = OFP.fixed_point_solve(Am, f[r], p.z, p.z0, p.delta, 8, steps=2)
+            e, tol = relmax(y[j, r].astype(np.complex128), ref), tol_of("f32", o, p, 8, 2, f[r], ref)
+            assert e <= tol, (j, r, e, tol)
+            del ref
+
+
+def oracle_relres(o, f, u):
+    b = o.s * f
+    return float(np.linalg.norm(b - o.apply(u)) / np.linalg.norm(b))
+
+
+def test_headline_mixed_solve_256(ctx):
+    # the benchmark's solve with one of its sources: the autotuner's complex64 shape,
+    # FP32 sweeps in FP64 FGMRES(30), to 1e-6; the oracle recomputes the FP64 residual
+    wl = layered(256, 1)
+    o = OO.Operator(wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
+    g = hf.Operator(ctx, dev(wl.c), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
+    best, _ = g.autotune(32, 2)
+    cg = hf.Contour(g, 16, 1.0, 0.25, 8)
+    u, st = hf.solve(g, cg, dev(wl.rhs[0][None]), opts=hf.default_opts(precision=32, tol=1e-6, max_it=1000))
+    assert st["status"] == "HFCI_OK", st
+    assert st["final_relres"] <= 1e-6
+    assert oracle_relres(o, wl.rhs[0], host(u)[0]) <= 1e-6 * 1.01
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_grf_96_four_sources(ctx, prec):
+    # the 96^3 random-field configuration: 12 poles, 4 Gaussian right-hand sides, plain FP64
+    # and mixed precision to 1e-6, every residual recomputed by the oracle
+    wl = W.config_grf_96()
+    o = OO.Operator(wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
+    g = hf.Operator(ctx, dev(wl.c), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
+    g.set_tune(prec, 1, 8, 2, 0, 1)
+    cg = hf.Contour(g, 12, 1.0, 0.25, 8)
+    f = np.stack(wl.rhs)
+    u, st = hf.solve(g, cg, dev(f), opts=hf.default_opts(precision=prec, tol=1e-6, max_it=1000))
+    assert st["status"] == "HFCI_OK", st
+    u = host(u)
+    for r in range(len(wl.rhs)):
+        assert oracle_relres(o, f[r], u[r]) <= 1e-6 * 1.01, r

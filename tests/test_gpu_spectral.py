@@ -1,10 +1,13 @@
 """The Fourier-spectral operator (Sec. 7.1) on the HIP path versus the FP64 oracle, through
 the C ABI.
 
-Tolerances: FP64 1e-12 for one product (FFT rounding, O(log N) eps relative to the largest
-term s lambda_max |x|), 1e-11 for fixed-point steps and FCI in lockstep; FP32 products 5e-6
-(single-precision FFTs) and 5e-4 for the fixed-point iteration (that error through q factors
-whose partial sums grow as for the stencil path).
+Comparisons are element by element (max |a - ref|).  One product goes through two FFTs,
+whose rounding is bounded in the 2-norm: at most 10 u log2 N s lambda_max ||x||_2 plus the
+diagonal's 12 u |kappa + i D + shift| |x| (tests/fp32_bounds.py, u = 2^-24 or 2^-53).  The
+max norm of an error is at most its 2-norm.  Fixed-point steps in FP32 use the product-form
+chain bound of tests/fp32_bounds.py with that per-product rounding, as a 2-norm bound
+(max |e| <= bar ||ref||_2).  FP64 fixed-point steps and FCI in lockstep agree to 1e-11 of
+max |ref|.
 """
 import numpy as np
 import pytest
@@ -12,6 +15,9 @@ import pytest
 from oracle import fci as OF
 from oracle import fixed_point as OFP
 from oracle import spectral as OS
+
+from tests.fp32_bounds import (U32, fixed_point_bar, relmax, round32, spectral_absrow, spectral_apply_bound,
+                               spectral_roundings)
 
 pytestmark = pytest.mark.gpu
 
@@ -37,8 +43,8 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def rel(a, b):
-    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+def inputs(x, prec):
+    return x if prec == "f64" else round32(x)
 
 
 def make(ctx, shape, seed, omega, cells=2, rho2=1.0):
@@ -62,15 +68,15 @@ def contour(o, g, J, q):
 def test_spectral_apply_parity(ctx, shape, prec):
     o, g = make(ctx, shape, 1, 9.0)
     rng = np.random.default_rng(2)
-    x = rng.standard_normal((3,) + shape) + 1j * rng.standard_normal((3,) + shape)
+    x = inputs(rng.standard_normal((3,) + shape) + 1j * rng.standard_normal((3,) + shape), prec)
     shift = 0.37 - 1.21j
     dt = torch.complex128 if prec == "f64" else torch.complex64
-    y = host(hf.apply(g, dev(x).to(dt), shift))
-    tol = 1e-12 if prec == "f64" else 5e-6
+    y = host(hf.apply(g, dev(x).to(dt), shift)).astype(np.complex128)
+    unit = 1.0 if prec == "f32" else 2.0 ** -53 / U32
     for k in range(3):
         ref = o.apply(x[k], shift)
-        scale = np.linalg.norm(o.lam.max() * x[k]) + np.linalg.norm(ref)
-        assert np.linalg.norm(y[k] - ref) <= tol * scale, (shape, prec, k)
+        bound = unit * spectral_apply_bound(x[k], float(o.lam.max()), o.kappa, o.damp, shift)
+        assert np.abs(y[k] - ref).max() <= bound, (shape, prec, k, np.abs(y[k] - ref).max(), bound)
 
 
 def test_spectral_box(ctx):
@@ -86,17 +92,24 @@ def test_spectral_shifted_solve_fixed_steps(ctx, prec, q, steps):
     o, g = make(ctx, (9, 12, 16), 5, 16.0)
     poles, cg = contour(o, g, 4, q)
     rng = np.random.default_rng(6)
-    f = rng.standard_normal((2,) + o.shape) + 1j * rng.standard_normal((2,) + o.shape)
+    f = inputs(rng.standard_normal((2,) + o.shape) + 1j * rng.standard_normal((2,) + o.shape), prec)
     dt = torch.complex128 if prec == "f64" else torch.complex64
     y, st = hf.shifted_solve(g, cg, dev(f).to(dt), steps=steps)
     y = host(y)
     assert np.all(st == steps)
     Am = lambda v, sh: o.apply(v, sh)
-    tol = 1e-11 if prec == "f64" else 5e-4
     for j, p in enumerate(poles):
         for r in range(2):
             ref, _ = OFP.fixed_point_solve(Am, f[r], p.z, p.z0, p.delta, q, steps=steps)
-            assert rel(y[j, r], ref) <= tol, (j, r, rel(y[j, r], ref))
+            if prec == "f64":
+                assert relmax(y[j, r], ref) <= 1e-11, (j, r, relmax(y[j, r], ref))
+            else:
+                bar2 = fixed_point_bar(p, q, steps, o.rectangle(),
+                                       spectral_absrow(float(o.lam.max()), o.kappa, o.rho2),
+                                       np.linalg.norm(f[r]) / np.linalg.norm(ref),
+                                       roundings=spectral_roundings(o.n))
+                e = np.abs(y[j, r] - ref).max()
+                assert e <= bar2 * np.linalg.norm(ref), (j, r, e, bar2 * np.linalg.norm(ref))
 
 
 @pytest.mark.parametrize("q", [2, 8])
@@ -113,7 +126,7 @@ def test_spectral_shifted_solve_adaptive(ctx, q):
         assert st[j, 1] == 0 and np.all(y[j, 1] == 0)
         ref, hist = OFP.fixed_point_solve(Am, f[0], p.z, p.z0, p.delta, q, reduce=5.0, m_max=60)
         assert st[j, 0] == len(hist) - 1, (j, st[j, 0], len(hist) - 1)
-        assert rel(y[j, 0], ref) <= 1e-11
+        assert relmax(y[j, 0], ref) <= 1e-11
 
 
 def test_spectral_gathered_batches_past_16(ctx):
@@ -133,7 +146,7 @@ def test_spectral_gathered_batches_past_16(ctx):
         for r in (0, 2):
             ref, hist = OFP.fixed_point_solve(Am, f[r], p.z, p.z0, p.delta, 2, reduce=5.0, m_max=60)
             assert st[j, r] == len(hist) - 1, (j, r, st[j, r], len(hist) - 1)
-            assert rel(y[j, r], ref) <= 1e-11, (j, r)
+            assert relmax(y[j, r], ref) <= 1e-11, (j, r)
     assert len(set(int(v) for v in st[:, 0])) > 1  # the poles stop at different steps
 
 
@@ -144,13 +157,13 @@ def test_spectral_fci_and_solve_lockstep(ctx):
     f = rng.standard_normal((2,) + o.shape) + 1j * rng.standard_normal((2,) + o.shape)
     out, _ = hf.fci_apply(g, cg, dev(f), hf.default_opts(fp_steps=3, precision=64))
     for r in range(2):
-        assert rel(host(out)[r], OF.fci(o, f[r], poles, steps=3)) <= 1e-11
+        assert relmax(host(out)[r], OF.fci(o, f[r], poles, steps=3)) <= 1e-11
     opts = hf.default_opts(precision=64, tol=1e-9, max_it=200, fp_steps=2, restart=20)
     u, st = hf.solve(g, cg, dev(f[:1]), opts=opts)
     assert st["status"] == "HFCI_OK"
     uo, info = OF.solve(o, f[0], poles, m=20, tol=1e-9, max_it=200, steps=2)
     assert st["its"] == info["its"]
-    assert rel(host(u)[0], uo) <= 1e-8
+    assert relmax(host(u)[0], uo) <= 1e-8
     b = o.s * f[0]
     assert np.linalg.norm(b - o.apply(host(u)[0])) / np.linalg.norm(b) <= 1e-9 * 1.01
 
