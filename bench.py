@@ -655,15 +655,18 @@ def main():
     info = op.info()
     log("operator:", info)
 
-    # untimed setup: the library's autotuner picks the stencil launch shape per precision
-    # (two systems: the usual number still iterating late in an FCI application)
+    # untimed setup: the library's autotuner picks the stencil launch shape per precision,
+    # timed over about as many systems as a launch of the solve carries late in an FCI
+    # application (about two per right-hand side: the slow poles)
+    tune_sys = max(2, min(16, 2 * args.nrhs))
     if args.shape:
         op.set_tune(32, *args.shape)
         tune32 = op.get_tune(32)
         log("complex64 shape pinned to", tune32)
     else:
-        tune32, rows32 = op.autotune(32, 2)
-        log("autotuned complex64 shape %s (%.3f ms)" % (tune32, min(r[1] for r in rows32)))
+        tune32, rows32 = op.autotune(32, tune_sys)
+        log("autotuned complex64 shape %s over %d systems (%.3f ms)" % (tune32, tune_sys,
+                                                                      min(r[1] for r in rows32)))
     if args.case_two_only:
         r = case_two_arm(args, ctx, op, cont, wl)
         print(json.dumps({"metric": "shifted solves of one FCI application, case one vs case two (s)",
@@ -671,7 +674,7 @@ def main():
                           "dtype": "c64", "data": "synthetic", "config": {"workload": wl.name}, "case_two": r}),
               flush=True)
         return
-    tune64, rows64 = op.autotune(64, 2)
+    tune64, rows64 = op.autotune(64, tune_sys)
     log("autotuned complex128 shape %s (%.3f ms)" % (tune64, min(r[1] for r in rows64)))
     mixed = hfci.default_opts(precision=32, tol=args.tol, max_it=args.max_it, verbose=verbose)
     # untimed setup: one Arnoldi step launches every kernel of the solve and allocates every
@@ -823,7 +826,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_over_alg": round(traffic_ratio, 4) if traffic_ratio else None,
-                     "kernel": ("zpair_kernel<float, 0, %d> (two middle factors of a fixed-point step per pass)"
+                     "kernel": (("zpair_dma_kernel<0, %d> (two middle factors of a fixed-point step per pass, "
+                                 "streams loaded straight into LDS)" % (4 if tune32[2] >= 3 else 2))
+                                if tune32[4] and tune32[0] == 2 else
+                                "zpair_kernel<float, 0, %d> (two middle factors of a fixed-point step per pass)"
                                 % (2 if tune32[2] >= 3 else 1)
                                 if tune32[4] else
                                 "%s<float, EpiFactor<float, 0>, %d, %d> (middle factor of a fixed-point step)"

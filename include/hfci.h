@@ -191,7 +191,12 @@ hfci_status hfci_op_info(const hfci_op* op, double* out7);
 /* Launch shape of the operator's z-marching stencil kernels for one precision
  * (HFCI_F32 or HFCI_F64), tune[6] (HOST array):
  *   tune[0] kern: 0 = in-plane neighbours as cached global loads, 1 = each plane
- *           staged through LDS with its halo;
+ *           staged through LDS with its halo, 2 (HFCI_F32 only, with fuse = 1 and
+ *           ty = 8) = as 1 for the two-factor passes, but every plane of every stream
+ *           is loaded from HBM straight into a ring of P + 2 LDS slots (P = 2 planes
+ *           ahead for pd = 2, 4 for pd = 3) without passing through registers, so
+ *           more planes are in flight; single factors, and two-factor passes on grids with an odd nx
+ *           or vectors of 2 GiB or more, run as kern 1;
  *   tune[1] ty:   the thread tile is 64 x ty (4 or 8);
  *   tune[2] pd:   HBM streams are issued pd planes ahead (kern 0: 1 or 2;
  *                 kern 1: 1..3 with ty = 4, 2..3 with ty = 8);

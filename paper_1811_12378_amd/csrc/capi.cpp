@@ -478,6 +478,7 @@ hfci_status hfci_op_set_tune(hfci_op* op, int prec, const int* t3) {
   HFCI_REQUIRE(tune_valid(t), "tune must be {0, ty in {4, 8}, pd in {1, 2}, cz, fuse, sg} or {1, 4, pd in 1..3, cz, "
                               "fuse, sg} or {1, 8, pd in {2, 3}, cz, fuse, sg}, cz in [0, 4096], fuse in {0, 1}, "
                               "sg in [1, 16]");
+  HFCI_REQUIRE(t.kern != 2 || prec == HFCI_F32, "kern 2 (streams loaded into LDS) is a complex64 kernel");
   (prec == HFCI_F32 ? op->g.tune32 : op->g.tune64) = t;
   return HFCI_OK;
   HFCI_API_END

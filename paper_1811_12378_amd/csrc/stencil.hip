@@ -649,6 +649,372 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(pair_waves_
   pair_tile<T, KIND, D>(g, czlen, gx, gy, per_sys, s, b, a, K);
 }
 
+// ---- Two factors per pass with the HBM streams loaded straight into LDS (kern 2) ----
+//
+// The same two factors and the same 64 x 12 tiles, 66 x 14 first-factor tile and 68 x 16
+// input tile as zpair_kernel, with the same arithmetic per point (results equal
+// zpair_kernel's bit for bit), but every stream reaches LDS without passing through
+// registers:
+//   * each input plane goes to LDS by buffer-to-LDS loads, two complex values (16 bytes)
+//     per lane, 37 pairs per wave; kappa of the first-factor tile likewise, one value per
+//     lane (lane = tile entry); f (the residual kind) or y1 (the kind that adds it) at the
+//     64 x 12 output points, two values per lane, 26 pairs per wave.  One plane of each
+//     shares one ring slot (one __shared__ array); planes are issued P planes ahead into
+//     a ring of R = P + 2 slots;
+//   * out-of-grid entries and planes come back as zeros from out-of-range offsets (the
+//     Dirichlet ghosts), and out-of-range offsets discard the stores of lanes that are not
+//     output points, so every wave issues the same memory instructions every plane;
+//   * the z-neighbours of the input and of the first-factor result stay in registers
+//     (each thread owns one column of the 66 x 14 tile), so the first-factor ring holds
+//     only the in-plane neighbours: two slots, taken by the parity of the plane.
+// Nothing in the loop loads into registers: the compiler would time its own wait for such
+// a load by the later loads of the same kind alone, and drain every load in flight.  One
+// barrier per plane: before it each wave waits until its own loads of the planes read next
+// have landed (a fixed count of the memory instructions issued since, the same in every
+// wave) and its LDS writes are done.  Per iteration k (k = zb-1 .. ze): the first factor
+// t(k) on the 66 x 14 tile, the second factor at plane k-1 on the 64 x 12 core.  The
+// caller guarantees an even nx (a pair of x-neighbours never straddles a row) and vectors
+// under 2 GiB.
+constexpr int DPW = 37;                       // input pairs per wave (15 x 37 >= 544)
+constexpr int DNP = PNT / 64 * DPW;           // 555 input pair slots per plane
+constexpr int DTP = PNT;                      // kappa / first-factor entries per plane (924 used)
+constexpr int EPW = 26;                       // output-point pairs per wave (15 x 26 >= 384)
+constexpr int DEP = PNT / 64 * EPW;           // 390 output-point pair slots per plane
+constexpr uint32_t kOOB = 0x80000000u;        // an offset past every buffer here
+
+// vmcnt wait with expcnt at its limit and lgkmcnt(0) (gfx9 encoding: vmcnt[3:0] in
+// bits 3:0 and vmcnt[5:4] in bits 15:14, expcnt bits 6:4, lgkmcnt bits 11:8)
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+  static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+}
+
+__device__ __forceinline__ BufRsrc buf_rsrc_n(const void* p, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// A ring slot: input plane, then kappa plane, then (the kinds with one) the f or y1 plane.
+template <bool EXTRA>
+struct DmaSlot {
+  static constexpr int kIn = 0, kKap = DNP * 16, kExt = kKap + DTP * 4;
+  static constexpr int kBytes = kExt + (EXTRA ? DEP * 16 : 0);
+};
+
+// Per-thread constants of the streams-into-LDS pair tile.
+struct DmaTile {
+  BufRsrc rX, rK, rE, rO, rO2;
+  uint32_t pb, pbk;               // plane strides in bytes (complex, kappa)
+  uint32_t din, dk, dex, ost;     // this lane's input pair, kappa entry, f / y1 pair, output point
+  int nz, zb, ze, damp_cells, c0, fc, ce, tid, wave;
+  bool dlane, elane, ine, core;
+  float a1r, a1i, b1r, b1i, a2r, a2i, b2r, b2i, sh2, dsc, diag0, sim, dampxy;
+  double zzr, zzi;
+};
+
+// The loads that fill ring slot `sl` for iteration i: input plane kin = k + 1 + P, kappa
+// plane kk = k + P and (EXTRA) f plane kk (residual kind) or y1 plane kk (adding kind).
+// Planes outside the grid or past what the chunk reads (input beyond ze + 1, the others
+// beyond ze) are zeros from an out-of-range offset, without touching memory; plane offsets
+// are uniform (readfirstlane keeps them in scalar registers, as the instructions need).
+// (sl is deliberately not restrict: the prologue's fills, which end with a full wait,
+// must not take entries of the compiler's table of tracked targets; the loop's fills get
+// their scope from dma_step's restrict slot.)
+template <bool EXTRA>
+__device__ __forceinline__ void dma_fill(const DmaTile& d, int kin, int kk, unsigned char* sl) {
+  auto clampz = [&](int kp) { return (uint32_t)min(max(kp, 0), d.nz - 1); };
+  const bool zin = kin >= 0 && kin < d.nz && kin <= d.ze + 1;
+  const bool zk = kk >= 0 && kk < d.nz && kk <= d.ze;
+  const uint32_t sin = __builtin_amdgcn_readfirstlane(d.pb * clampz(kin));
+  const uint32_t sk = __builtin_amdgcn_readfirstlane(d.pbk * clampz(kk));
+  if (d.dlane)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rX, (lds_void*)(sl + DmaSlot<EXTRA>::kIn + 16 * DPW * d.wave), 16,
+                                             zin ? d.din : kOOB, sin, 0, 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rK, (lds_void*)(sl + DmaSlot<EXTRA>::kKap + 4 * 64 * d.wave), 4,
+                                           zk ? d.dk : kOOB, sk, 0, 0);
+  if constexpr (EXTRA) {
+    const uint32_t se = __builtin_amdgcn_readfirstlane(d.pb * clampz(kk));
+    if (d.elane)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rE, (lds_void*)(sl + DmaSlot<EXTRA>::kExt + 16 * EPW * d.wave), 16,
+                                               zk ? d.dex : kOOB, se, 0, 0);
+  }
+}
+
+// One iteration (plane k) of the tile, after the barrier: refill slot sN, the first factor
+// at plane k from slots sK (input plane k; kappa, y1 of plane k - 1) and sP (input plane
+// k + 1; kappa, f of plane k), the second factor at plane k - 1 from the first-factor
+// slots tq (plane k - 1) and tw (plane k, written here).  The slots arrive as restrict
+// pointers to different arrays: the compiler then tells the buffer-to-LDS loads of each
+// slot apart (it tracks at most eight such targets: the loop is unrolled R times, one
+// slot per iteration) and adds no waits of its own beyond the barrier's.
+template <int KIND, int P>
+__device__ __forceinline__ void dma_step(const DmaTile& d, int k, unsigned char* __restrict__ sN,
+                                         const unsigned char* __restrict__ sK, const unsigned char* __restrict__ sP,
+                                         float2* __restrict__ tw, const float2* __restrict__ tq, float2& cm,
+                                         float2& cc, float2& tm, float2& t0, double& acc) {
+  using T = float;
+  using T2 = float2;
+  constexpr bool RESID = (KIND & kFacResid) != 0, ADD = (KIND & kFacAdd) != 0, DUAL = (KIND & kFacDual) != 0;
+  constexpr bool EXTRA = RESID || ADD;
+  using SL = DmaSlot<EXTRA>;
+  auto clampz = [&](int kp) { return (uint32_t)min(max(kp, 0), d.nz - 1); };
+  auto dampz = [&](int kp) {
+    const int dz = layer_depth(kp, d.nz, d.damp_cells);
+    return (T)(dz * dz) * d.dsc;
+  };
+  dma_fill<EXTRA>(d, k + 1 + P, k + P, sN);
+  const T2* cp = (const T2*)(sK + SL::kIn);
+  // ---- first factor at plane k on the 66 x 14 tile (every lane; masked) ----
+  const int c0 = d.c0;
+  const T2 cen = cc;
+  const T2 zp = ((const T2*)(sP + SL::kIn))[c0];
+  const T2 xm = cp[c0 - 1], xp = cp[c0 + 1], ym = cp[c0 - PIX], yp = cp[c0 + PIX];
+  const T2 zm = cm;
+  const T dre = d.diag0 - ((const T*)(sP + SL::kKap))[d.tid];
+  const T dim = -(max(d.dampxy, dampz(k)) + d.sim);
+  const T nbr = ((zm.x + zp.x) + (xm.x + xp.x)) + (ym.x + yp.x);
+  const T nbi = ((zm.y + zp.y) + (xm.y + xp.y)) + (ym.y + yp.y);
+  T2 Sx;
+  Sx.x = dre * cen.x - dim * cen.y - d.sh2 * nbr;
+  Sx.y = dre * cen.y + dim * cen.x - d.sh2 * nbi;
+  const bool live = d.ine && k >= 0 && k < d.nz;
+  T2 tv;
+  tv.x = live ? d.a1r * Sx.x - d.a1i * Sx.y + d.b1r * cen.x - d.b1i * cen.y : (T)0;
+  tv.y = live ? d.a1r * Sx.y + d.a1i * Sx.x + d.b1r * cen.y + d.b1i * cen.x : (T)0;
+  if constexpr (RESID) {
+    const T2 fv = ((const T2*)(sP + SL::kExt))[d.ce];
+    const double rr = (double)fv.x - (double)Sx.x + d.zzr * (double)cen.x - d.zzi * (double)cen.y;
+    const double ri = (double)fv.y - (double)Sx.y + d.zzr * (double)cen.y + d.zzi * (double)cen.x;
+    acc += (d.core && k >= d.zb && k < d.ze) ? rr * rr + ri * ri : 0.0;
+  }
+  tw[d.tid] = tv;
+  // ---- second factor at plane k - 1 on the 64 x 12 core (for core threads the clamped
+  // centre fc is the thread's own point, whose z-column of t it holds) ----
+  {
+    const int km = k - 1, fc = d.fc;
+    const T2 cen2 = t0;
+    const T2 xm2 = tq[fc - 1], xp2 = tq[fc + 1], ym2 = tq[fc - PEX], yp2 = tq[fc + PEX];
+    const T2 zm2 = tm, zp2 = tv;
+    const T dre2 = d.diag0 - ((const T*)(sK + SL::kKap))[d.tid];
+    const T dim2 = -(max(d.dampxy, dampz(km)) + d.sim);
+    const T nbr2 = ((zm2.x + zp2.x) + (xm2.x + xp2.x)) + (ym2.x + yp2.x);
+    const T nbi2 = ((zm2.y + zp2.y) + (xm2.y + xp2.y)) + (ym2.y + yp2.y);
+    T2 S2;
+    S2.x = dre2 * cen2.x - dim2 * cen2.y - d.sh2 * nbr2;
+    S2.y = dre2 * cen2.y + dim2 * cen2.x - d.sh2 * nbi2;
+    T2 o;
+    o.x = d.a2r * S2.x - d.a2i * S2.y + d.b2r * cen2.x - d.b2i * cen2.y;
+    o.y = d.a2r * S2.y + d.a2i * S2.x + d.b2r * cen2.y + d.b2i * cen2.x;
+    if constexpr (ADD) {
+      const T2 y1v = ((const T2*)(sK + SL::kExt))[d.ce];
+      o.x += y1v.x;
+      o.y += y1v.y;
+    }
+    const uint32_t voff = (km >= d.zb && km < d.ze) ? d.ost : kOOB;
+    const uint32_t po = __builtin_amdgcn_readfirstlane(d.pb * clampz(km));
+    buf_store<T2>(d.rO, voff, po, o);
+    if constexpr (DUAL) buf_store<T2>(d.rO2, voff, po, o);
+  }
+  cm = cen;
+  cc = zp;
+  tm = t0;
+  t0 = tv;
+}
+
+template <int KIND, int P>
+__device__ __forceinline__ void pair_tile_dma(const GridDesc& g, int czlen, int gx, int gy, int per_sys, int s,
+                                              int b, const FactorArgs<float2>& a, const float* __restrict__ K) {
+  using T = float;
+  using T2 = float2;
+  constexpr bool RESID = (KIND & kFacResid) != 0, ADD = (KIND & kFacAdd) != 0, DUAL = (KIND & kFacDual) != 0,
+                 INF = (KIND & kFacInF) != 0;
+  constexpr bool EXTRA = RESID || ADD;
+  static_assert(!(RESID && ADD), "no pair kind both forms the residual and adds y1");
+  // ring slots, and the unroll: R is even, so every slot index and the parity of the
+  // first-factor slot are constants in the unrolled body (a slot chosen at run time would
+  // hide from the compiler which loads in flight an LDS write may collide with)
+  constexpr int R = P + 2;
+  // memory instructions per plane: the fills, the store(s)
+  constexpr int V = 2 + (EXTRA ? 1 : 0) + 1 + (DUAL ? 1 : 0);
+  static_assert(P == 2 || P == 4, "prefetch depth 2 or 4");
+  constexpr int SB = DmaSlot<EXTRA>::kBytes;
+  __shared__ __align__(16) unsigned char sl0[SB], sl1[SB], sl2[SB], sl3[SB], sl4[(R > 4) ? SB : 16],
+      sl5[(R > 5) ? SB : 16];
+  __shared__ __align__(16) T2 ts0[DTP], ts1[DTP];
+  __shared__ double sh[PNT / 64];
+  auto slot = [&](int r) -> unsigned char* {
+    return r == 0 ? sl0 : r == 1 ? sl1 : r == 2 ? sl2 : r == 3 ? sl3 : r == 4 ? sl4 : sl5;
+  };
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int bx = b % gx, by = (b / gx) % gy, zc = b / (gx * gy);
+  const int x0 = bx * PX, y0 = by * PY;
+  DmaTile d;
+  d.tid = tid;
+  d.wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  d.nz = g.nz;
+  d.damp_cells = g.damp_cells;
+  d.zb = zc * czlen;
+  d.ze = min(g.nz, d.zb + czlen);
+  const int zb = d.zb, ze = d.ze;
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  const size_t plane = (size_t)g.nx * (size_t)g.ny;
+  const int gsys = a.sys0 + s;
+  const int pole = gsys / a.nrhs, rhs = gsys % a.nrhs;
+  const FactorCoef c1 = a.coef[pole * a.cstride + a.k], c2 = a.coef[pole * a.cstride + a.k + 1];
+  const PoleDev pd = a.poles[pole];
+  d.a1r = (T)c1.a_re, d.a1i = (T)c1.a_im, d.b1r = (T)c1.b_re, d.b1i = (T)c1.b_im;
+  d.a2r = (T)c2.a_re, d.a2i = (T)c2.a_im, d.b2r = (T)c2.b_re, d.b2i = (T)c2.b_im;
+  const T2* __restrict__ X = INF ? a.f + (size_t)rhs * n : a.win + (size_t)s * n;
+  const T2* __restrict__ E = RESID ? a.f + (size_t)rhs * n : ADD ? a.y1 + (size_t)s * n : X;
+  T2* __restrict__ O = a.wout + (size_t)s * n;
+  T2* __restrict__ O2 = DUAL ? a.wout2 + (size_t)s * n : O;
+  d.sh2 = (T)g.s_h2;
+  d.dsc = (T)g.damp_scale;
+  d.diag0 = (T)6 * d.sh2 - (T)pd.z0_re;
+  d.sim = (T)pd.z0_im;
+  d.zzr = pd.zz_re;
+  d.zzi = pd.zz_im;
+  d.pb = (uint32_t)(plane * sizeof(T2));
+  d.pbk = (uint32_t)(plane * sizeof(T));
+  const size_t vb = n * sizeof(T2);
+  d.rX = buf_rsrc_n(X, vb);
+  d.rK = buf_rsrc_n(K, n * sizeof(T));
+  d.rE = buf_rsrc_n(E, vb);
+  d.rO = buf_rsrc_n(O, vb);
+  d.rO2 = buf_rsrc_n(O2, vb);
+
+  // input duty: pair p = wave * 37 + lane (lanes < 37) holds entries 2p, 2p + 1 of the
+  // 68 x 16 input tile (68 is even: a pair never straddles a tile row; x0 and nx are
+  // even: a pair lies inside the grid or outside it as a whole)
+  d.dlane = lane < DPW;
+  d.din = kOOB;
+  {
+    const int e0 = 2 * (d.wave * DPW + lane);
+    const int ix = x0 - 2 + e0 % PIX, iy = y0 - 2 + e0 / PIX;
+    if (d.dlane && e0 < NIN && ix >= 0 && ix < g.nx && iy >= 0 && iy < g.ny)
+      d.din = (uint32_t)((ix + g.nx * iy) * sizeof(T2));
+  }
+  // f / y1 duty: pair p = wave * 26 + lane (lanes < 26) holds output points 2p, 2p + 1 of
+  // the 64 x 12 core, row-major (64 is even, so is x0 + 2 (p % 32))
+  d.elane = lane < EPW;
+  d.dex = kOOB;
+  {
+    const int p = d.wave * EPW + lane;
+    const int cy = p / (PX / 2), cx = 2 * (p % (PX / 2));
+    if (d.elane && cy < PY && x0 + cx < g.nx && y0 + cy < g.ny)
+      d.dex = (uint32_t)((x0 + cx + g.nx * (y0 + cy)) * sizeof(T2));
+  }
+  // the thread's first-factor point (66 x 14 tile, as in zpair_kernel), also its kappa entry
+  const bool tthr = tid < PEX * PEY;
+  const int ex = tid % PEX, ey = min(tid / PEX, PEY - 1);
+  const int xe = x0 - 1 + ex, ye = y0 - 1 + ey;
+  d.ine = tthr && xe >= 0 && xe < g.nx && ye >= 0 && ye < g.ny;
+  d.core = d.ine && ex >= 1 && ex <= PX && ey >= 1 && ey <= PY;
+  const uint32_t oe = d.ine ? (uint32_t)(xe + g.nx * ye) : 0u;
+  d.dk = d.ine ? oe * (uint32_t)sizeof(T) : kOOB;
+  d.ost = d.core ? oe * (uint32_t)sizeof(T2) : kOOB;  // output point, or discarded
+  // f / y1 are read at the nearest output point of the tile (the values of halo lanes
+  // are not used)
+  const int xc = min(max(xe, x0), min(x0 + PX, g.nx) - 1), yc = min(max(ye, y0), min(y0 + PY, g.ny) - 1);
+  d.ce = (yc - y0) * PX + (xc - x0);
+  d.fc = min(max(ey, 1), PY) * PEX + min(max(ex, 1), PX);
+  d.c0 = (ey + 1) * PIX + ex + 1;
+  const int dxy = max(layer_depth(xe, g.nx, g.damp_cells), layer_depth(ye, g.ny, g.damp_cells));
+  d.dampxy = (T)(dxy * dxy) * d.dsc;
+
+  double acc = 0.0;
+  if (zb < ze) {
+    // prologue: slot j gets input plane zb-2+j and kappa, f / y1 plane zb-3+j, so input
+    // plane kp sits in slot (kp - zb + 2) mod R and the others' plane kk in slot
+    // (kk - zb + 3) mod R: kappa and f of plane k share the slot of input plane k + 1,
+    // and y1 of plane k - 1 that of input plane k
+#pragma unroll
+    for (int j = 0; j < R; ++j) dma_fill<EXTRA>(d, zb - 2 + j, zb - 3 + j, slot(j));
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    // z-columns: the input centre of planes zb-2 (slot 0) and zb-1 (slot 1); t of planes
+    // k-2 and k-1 (zero until the chunk's first iterations compute them)
+    T2 cm = ((const T2*)sl0)[d.c0], cc = ((const T2*)sl1)[d.c0];
+    T2 tm = T2{(T)0, (T)0}, t0 = T2{(T)0, (T)0};
+    // iterations k = zb-1 .. ze, padded to a multiple of R: the padding iterations load
+    // zeros (their planes are past what the chunk reads), store nothing (their output
+    // plane is past ze) and form no residual, and without a guard per iteration the
+    // compiler sees no path that skips part of a trip (such a path would force it to wait
+    // for every load in flight)
+    const int len = ze - zb + 2;
+    const int lenp = (len + R - 1) / R * R;
+    for (int r0 = 0; r0 < lenp; r0 += R) {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        {
+          // iteration i = r0 + u (r0 a multiple of R, so even), plane k; the first-factor
+          // ring slot of plane k is the parity of i, that of u
+          const int k = zb - 1 + r0 + u;
+          const bool odd = (u & 1) != 0;
+          // the slots read now were filled P iterations ago, or in the prologue: this wave
+          // has issued at most (P - 1) V memory instructions since
+          wait_vm_lgkm0<(P - 1) * V>();
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
+          __builtin_amdgcn_s_barrier();
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
+          dma_step<KIND, P>(d, k, slot(u), slot((u + 1) % R), slot((u + 2) % R), odd ? ts1 : ts0, odd ? ts0 : ts1,
+                            cm, cc, tm, t0, acc);
+        }
+      }
+    }
+  }
+  // no buffer-to-LDS load may still be in flight when the block's LDS is handed on
+  __builtin_amdgcn_s_waitcnt(0);
+  if constexpr (RESID) {
+    __syncthreads();
+    double v[1] = {acc};
+    block_sum<PNT, 1>(v, sh);
+    if (tid == 0) a.partial[(size_t)s * per_sys + (bx + gx * (by + gy * zc))] = v[0];
+  }
+}
+
+// Block order shared by both pair kernels (see zpair_kernel).
+__device__ __forceinline__ bool pair_block(int xcd_slab, int sgrp, int per_sys, const int* list, int count, int& s,
+                                           int& b) {
+  int li;
+  if (xcd_slab > 0 && sgrp > 1) {
+    const int xcd = blockIdx.x % 8, k = blockIdx.x / 8;
+    const int gsz = sgrp * xcd_slab;
+    const int s0 = (k / gsz) * sgrp, r = k % gsz;
+    const int gs = min(sgrp, count - s0);
+    li = s0 + r % gs;
+    b = xcd * xcd_slab + r / gs;
+  } else {
+    li = blockIdx.x / per_sys;
+    b = blockIdx.x % per_sys;
+    if (xcd_slab > 0) b = (b % 8) * xcd_slab + b / 8;
+  }
+  s = list[li];
+  return s >= 0;
+}
+
+// With P = 2 the kinds without an extra stream fit two blocks per CU (LDS and 64 VGPRs);
+// the residual and y1 kinds, which hold one more plane per slot, and P = 4 run one.
+template <int KIND, int P>
+constexpr int dma_waves_per_eu() {
+  return ((KIND & (kFacResid | kFacAdd)) == 0 && P == 2) ? 8 : 4;
+}
+
+template <int KIND, int P>
+__global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(dma_waves_per_eu<KIND, P>()))) void zpair_dma_kernel(
+    GridDesc g, int nzc, int czlen, int xcd_slab, int sgrp, FactorArgs<float2> a, const float* __restrict__ K) {
+  const int gx = (g.nx + PX - 1) / PX, gy = (g.ny + PY - 1) / PY;
+  const int per_sys = gx * gy * nzc;
+  int s, b;
+  if (!pair_block(xcd_slab, sgrp, per_sys, a.list, a.count, s, b)) return;  // uniform
+  pair_tile_dma<KIND, P>(g, czlen, gx, gy, per_sys, s, b, a, K);
+}
+
 // Uneven batches, two factors per pass: as zmulti_kernel, with the pair tile of the
 // block's system on its operator's pair geometry (pgx x pgy x pnzc tiles).
 template <typename T, int KIND>
@@ -969,7 +1335,8 @@ void run(hipStream_t st, const GridDesc& g, int nsys, const Epi& epi) {
   if (nsys <= 0) return;
   const Shape sh = shape_for<T>(g, nsys);
   const KernelTune& t = tune_of<T>(g);
-  const int key = t.kern * 100 + t.ty * 10 + t.pd;
+  // kern 2 changes the pair launches only: single factors run the LDS-staged kernel
+  const int key = (t.kern == 2 ? 1 : t.kern) * 100 + t.ty * 10 + t.pd;
   switch (key) {
     case 141:
       hipLaunchKernelGGL((zlds_kernel<T, Epi, 4, 1>), sh.grid, sh.block, 0, st, g, sh.nzc, sh.czlen, sh.xcd_slab, epi);
@@ -1005,6 +1372,10 @@ struct PairShape {
   int gx, gy, nzc, czlen, per_sys, xcd_slab;
 };
 
+bool dma_pair_fits(const GridDesc& g) {
+  return g.nx % 2 == 0 && (size_t)g.nx * g.ny * g.nz * sizeof(float2) < ((size_t)1 << 31);
+}
+
 template <typename T>
 PairShape pair_shape(const GridDesc& g) {
   const KernelTune& t = tune_of<T>(g);
@@ -1029,6 +1400,20 @@ void run_pair(hipStream_t st, const GridDesc& g, const void* kappa, const Factor
   const PairShape p = pair_shape<T>(g);
   const dim3 grid((unsigned)p.per_sys * (unsigned)a.count);
   const int sgrp = tune_of<T>(g).sg;
+  if constexpr (sizeof(T) == 4) {
+    // the streams-into-LDS pair kernel: complex64, an even nx, vectors under 2 GiB
+    if (tune_of<T>(g).kern == 2 && dma_pair_fits(g)) {
+      // prefetch depth P (planes ahead): pd 2 -> 2 (the kinds without an extra stream then
+      // fit two blocks per CU), pd 3 -> 4 (one block per CU)
+      if (tune_of<T>(g).pd >= 3)
+        hipLaunchKernelGGL((zpair_dma_kernel<KIND, 4>), grid, dim3(PNT), 0, st, g, p.nzc, p.czlen, p.xcd_slab,
+                           sgrp, a, (const float*)kappa);
+      else
+        hipLaunchKernelGGL((zpair_dma_kernel<KIND, 2>), grid, dim3(PNT), 0, st, g, p.nzc, p.czlen, p.xcd_slab,
+                           sgrp, a, (const float*)kappa);
+      return;
+    }
+  }
   if (tune_of<T>(g).pd >= 3)
     hipLaunchKernelGGL((zpair_kernel<T, KIND, 2>), grid, dim3(PNT), 0, st, g, p.nzc, p.czlen, p.xcd_slab, sgrp,
                        a, (const T*)kappa);
@@ -1044,6 +1429,7 @@ bool tune_valid(const KernelTune& t) {
   if (t.sg < 1 || t.sg > 16) return false;
   if (t.kern == 0) return t.pd == 1 || t.pd == 2;
   if (t.kern == 1) return (t.ty == 4 && t.pd >= 1 && t.pd <= 3) || (t.ty == 8 && (t.pd == 2 || t.pd == 3));
+  if (t.kern == 2) return t.fuse == 1 && t.ty == 8 && (t.pd == 2 || t.pd == 3);
   return false;
 }
 

@@ -78,16 +78,19 @@ def slab_operator(ctx, seed=71):
     return OO.Operator(c, 20.0, 3, 1.0, h=h), hf.Operator(ctx, dev(c), h, 20.0, 3, 1.0), rng
 
 
-# sg = 3 over the 8 systems of a launch: groups of 3, 3 and a ragged 2
+# sg = 3 over the 8 systems of a launch: groups of 3, 3 and a ragged 2; kern 2 is the
+# complex64 pair kernel whose streams go straight into LDS (pd 2: two planes ahead, pd 3:
+# four)
 @pytest.mark.parametrize("q,steps", KIND_CASES)
-@pytest.mark.parametrize("pd,sg", [(2, 1), (3, 1), (2, 3), (3, 4)])
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_pair_kinds_with_xcd_slabs(ctx, q, steps, pd, sg, prec):
+@pytest.mark.parametrize("prec,kern,pd,sg", [("f64", 1, 2, 1), ("f64", 1, 3, 1), ("f64", 1, 2, 3), ("f64", 1, 3, 4),
+                                             ("f32", 1, 2, 1), ("f32", 1, 3, 1), ("f32", 1, 2, 3), ("f32", 1, 3, 4),
+                                             ("f32", 2, 2, 1), ("f32", 2, 3, 1), ("f32", 2, 2, 3), ("f32", 2, 3, 4)])
+def test_pair_kinds_with_xcd_slabs(ctx, q, steps, prec, kern, pd, sg):
     shape = SLAB_SHAPE
     o, g, rng = slab_operator(ctx)
     pr = 64 if prec == "f64" else 32
-    g.set_tune(pr, 1, 8, pd, 8, 1, sg)
-    assert g.get_tune(pr) == (1, 8, pd, 8, 1, sg)
+    g.set_tune(pr, kern, 8, pd, 8, 1, sg)
+    assert g.get_tune(pr) == (kern, 8, pd, 8, 1, sg)
     poles = OF.pole_parameters(o, 4, 1.0, 0.5, q)
     cg = hf.Contour(g, 4, 1.0, 0.5, q, z=[p.z for p in poles], sigma=[p.sigma for p in poles],
                     delta=[p.delta for p in poles])
@@ -132,18 +135,97 @@ def test_adaptive_stops_with_system_groups(ctx, sg):
     assert len(set(int(v) for v in st[:, 0])) > 1  # the poles stop at different steps
 
 
+@pytest.mark.parametrize("q,steps", KIND_CASES + [(3, 3)])
+@pytest.mark.parametrize("pd,cz", [(2, 8), (3, 8), (2, 0), (3, 5)])
+def test_streams_into_lds_match_the_register_pair_kernel(ctx, q, steps, pd, cz):
+    # kern 2 gives every point the same arithmetic as kern 1, up to how the compiler fuses
+    # multiply-adds: each is within the FP32 product-form bar of the oracle, so the two are
+    # within twice that bar of each other, pole by pole, every kind of pair launch; z-chunks
+    # of 8 planes (several per column, ragged last), the grid's own choice and 5
+    o, g, rng = slab_operator(ctx, seed=75)
+    poles = OF.pole_parameters(o, 4, 1.0, 0.5, q)
+    cg = hf.Contour(g, 4, 1.0, 0.5, q, z=[p.z for p in poles], sigma=[p.sigma for p in poles],
+                    delta=[p.delta for p in poles])
+    fh = round32(rng.standard_normal((2,) + SLAB_SHAPE) + 1j * rng.standard_normal((2,) + SLAB_SHAPE))
+    f = dev(fh).to(torch.complex64)
+    out = {}
+    for kern in (1, 2):
+        g.set_tune(32, kern, 8, pd, cz, 1, 2)
+        y, st = hf.shifted_solve(g, cg, f, steps=steps)
+        assert np.all(st == steps)
+        out[kern] = host(y).astype(np.complex128)
+    Am = lambda v, sh: o.apply(v, sh)
+    for j, p in enumerate(poles):
+        for r in range(2):
+            ref, _ = OFP.fixed_point_solve(Am, fh[r], p.z, p.z0, p.delta, q, steps=steps)
+            bar = tol_of("f32", o, p, q, steps, fh[r], ref)
+            scale = np.abs(ref).max()
+            assert np.abs(out[2][j, r] - out[1][j, r]).max() <= 2 * bar * scale, (j, r)
+            assert relmax(out[2][j, r], ref) <= bar, (j, r)
+
+
+def test_streams_into_lds_adaptive(ctx):
+    # adaptive stopping in FP32 with kern 2: each system stops within one step of the
+    # oracle's count (an FP32 residual can land on the other side of the threshold), its
+    # iterate is the oracle's after the steps it took, within the FP32 bar, and it meets the
+    # stopping rule; a zero right-hand side stops at once
+    o, g, rng = slab_operator(ctx, seed=79)
+    g.set_tune(32, 2, 8, 2, 8, 1, 3)
+    q = 8
+    poles = OF.pole_parameters(o, 4, 1.0, 0.5, q)
+    cg = hf.Contour(g, 4, 1.0, 0.5, q, z=[p.z for p in poles], sigma=[p.sigma for p in poles],
+                    delta=[p.delta for p in poles])
+    fh = round32(rng.standard_normal((3,) + SLAB_SHAPE) + 1j * rng.standard_normal((3,) + SLAB_SHAPE))
+    fh[1] = 0.0
+    y, st = hf.shifted_solve(g, cg, dev(fh).to(torch.complex64), reduce=5.0, max_steps=40)
+    y = host(y).astype(np.complex128)
+    Am = lambda v, sh: o.apply(v, sh)
+    for j, p in enumerate(poles):
+        assert st[j, 1] == 0 and np.all(y[j, 1] == 0)
+        for r in (0, 2):
+            _, hist = OFP.fixed_point_solve(Am, fh[r], p.z, p.z0, p.delta, q, reduce=5.0, m_max=40)
+            k = int(st[j, r])
+            assert abs(k - (len(hist) - 1)) <= 1, (j, r, k, len(hist) - 1)
+            ref, _ = OFP.fixed_point_solve(Am, fh[r], p.z, p.z0, p.delta, q, steps=k)
+            e, tol = relmax(y[j, r], ref), tol_of("f32", o, p, q, k, fh[r], ref)
+            assert e <= tol, (j, r, e, tol)
+            rn = np.linalg.norm(fh[r] - o.apply(y[j, r], p.z))
+            assert rn <= np.linalg.norm(fh[r]) / 5 * (1 + 1e-4), (j, r)
+
+
+def test_streams_into_lds_need_an_even_nx(ctx):
+    # an odd nx (pairs of x-neighbours would straddle rows) falls back to kern 1's kernel
+    shape = (20, 26, 67)
+    rng = np.random.default_rng(77)
+    c = rng.uniform(1.0, 3.0, size=shape)
+    o = OO.Operator(c, 14.0, 3, 1.0, h=1 / 20)
+    g = hf.Operator(ctx, dev(c), 1 / 20, 14.0, 3, 1.0)
+    poles = OF.pole_parameters(o, 4, 1.0, 0.5, 8)
+    cg = hf.Contour(g, 4, 1.0, 0.5, 8, z=[p.z for p in poles], sigma=[p.sigma for p in poles],
+                    delta=[p.delta for p in poles])
+    f = dev(round32(rng.standard_normal((1,) + shape) + 1j * rng.standard_normal((1,) + shape))).to(torch.complex64)
+    res = []
+    for kern in (1, 2):
+        g.set_tune(32, kern, 8, 2, 0, 1)
+        res.append(host(hf.shifted_solve(g, cg, f, steps=2)[0]))
+    assert np.array_equal(res[0], res[1])
+    with pytest.raises(hf.HfciError):  # a complex64 kernel only
+        g.set_tune(64, 2, 8, 2, 0, 1)
+
+
 def layered(n, nrhs):
     return W.config_layered_256(n=n, nrhs=nrhs)
 
 
-def test_headline_shape_lockstep_256(ctx):
-    # the benchmark's workload and fused complex64 shape: 2 of its 16 poles (the one
+@pytest.mark.parametrize("kern,pd", [(1, 2), (2, 2), (2, 3)])
+def test_headline_shape_lockstep_256(ctx, kern, pd):
+    # the benchmark's workload and fused complex64 shapes: 2 of its 16 poles (the one
     # nearest the origin, the slowest, and one across the contour) x 2 of its point
     # sources, two fixed-point steps (step one, then residual / middle / y1 pairs)
     wl = layered(256, 2)
     o = OO.Operator(wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
     g = hf.Operator(ctx, dev(wl.c), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
-    g.set_tune(32, 1, 8, 2, 64, 1, 2)
+    g.set_tune(32, kern, 8, pd, 64, 1, 2)
     assert pair_tiles(o.shape, 64) == 352
     allp = OF.pole_parameters(o, 16, 1.0, 0.25, 8)
     poles = [allp[0], allp[8]]
