@@ -400,7 +400,12 @@ typedef struct {
   int loss_curve_cap;
   int loss_kind;               /* 0: ||out - t||^2/||t||^2; 1: 1 - |<o,t>|^2/(||o||^2||t||^2)
                                   with o, t read as complex fields (scale and phase
-                                  invariant: FGMRES only needs the direction)         */
+                                  invariant: FGMRES only needs the direction);
+                                  2: the residual the output leaves, min over complex d
+                                  of ||v - d Ahat out||^2/||v||^2 with v the pair's
+                                  residual (e is not read) and Ahat = A/(s/h^2)
+                                  without damping, from the omega^2 h^2/c^2 channel
+                                  (the arbiter's measure of a proposal, Alg. 1 step 3) */
 } hfci_train_desc;
 
 hfci_status hfci_net_create(hfci_ctx* ctx, const hfci_net_desc* desc, hfci_net** out);
@@ -414,7 +419,9 @@ hfci_status hfci_net_get_grads(const hfci_net* net, float* host);
  * float [nz][ny][nx][2]. */
 hfci_status hfci_net_eval(hfci_net* net, int nx, int ny, int nz, const uint16_t* x16, float* out);
 /* One forward/backward pass on (x16, target float [n][2]) with the loss loss_kind
- * (as in hfci_train_desc); update != 0 also takes an Adam step with lr.
+ * (as in hfci_train_desc; for kind 2 the target is the residual v itself and Ahat takes
+ * omega^2 h^2/c^2 from x16's third channel, zero values outside the box); update != 0
+ * also takes an Adam step with lr.
  * *loss receives the loss (HOST). */
 hfci_status hfci_net_train_step(hfci_net* net, int nx, int ny, int nz, const uint16_t* x16,
                                 const float* target, float lr, int update, int loss_kind, double* loss);

@@ -20,8 +20,11 @@ Network (3 levels, 16/32/64 channels):
     d2 = relu(d2b(relu(d2a(concat(up(b3), e2)))))    [N/2, 32]
     d1 = relu(d1b(relu(d1a(concat(up(d2), e1)))))    [N,   16]
     out = p(d1)  (1x1x1 conv 16 -> 2, no activation)
-Losses: relative squared error ||out - t||^2 / ||t||^2, or its scale- and
-phase-invariant form 1 - |<o, t>|^2/(||o||^2 ||t||^2).  Optimiser: Adam.
+Losses: relative squared error ||out - t||^2 / ||t||^2, its scale- and
+phase-invariant form 1 - |<o, t>|^2/(||o||^2 ||t||^2), and the residual loss: with
+the network's input v as t, min over a complex d of ||v - d Ahat out||^2 / ||v||^2, the
+scaled residual a preconditioner's output leaves (Ahat = A / (s/h^2) without the
+damping term, built from the input's third channel).  Optimiser: Adam.
 
 Pins (tests/test_oracle_conv.py): the convolution against a brute-force loop
 over every index; every gradient against central finite differences.
@@ -185,6 +188,27 @@ def loss_phase_invariant(out, t):
     L = 1.0 - abs(S) ** 2 / (P * Q)
     gc = -2.0 * np.conj(S) * (tc - (S / P) * o) / (P * Q)
     return L, np.stack([gc.real, gc.imag], axis=-1)
+
+
+def ahat(x, kch):
+    """Ahat x on a box with zero values outside: (6 - kch) x - sum of the six neighbours,
+    applied to each channel of x [Z, Y, X, C] (Ahat = A / (s/h^2) of Sec. 7.1 with
+    kch = omega^2 h^2 / c^2 = kappa / (s/h^2), without the damping term).  Real and
+    symmetric, so it is its own transpose."""
+    y = (6.0 - kch)[..., None] * x
+    for off in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+        y = y - _shift(x, off)
+    return y
+
+
+def loss_residual(out, v, kch):
+    """Residual loss of a preconditioner output against its input v:
+        L = min_d ||v - d Ahat o||^2 / ||v||^2 = 1 - |<Ahat o, v>|^2 / (||Ahat o||^2 ||v||^2),
+    the phase-invariant loss of p = Ahat out against v; by the chain rule through the real
+    linear map Ahat (its own transpose), dL/dout = Ahat dL/dp."""
+    pr = ahat(out, kch)
+    L, dp = loss_phase_invariant(pr, v)
+    return L, ahat(dp, kch)
 
 
 def adam_step(p, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

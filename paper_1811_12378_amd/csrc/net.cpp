@@ -225,7 +225,13 @@ double Net::train_step(Dims d, const uint16_t* x16, const float* target, float l
   double* lpart = (double*)ctx->ws.get("net_lpart", 4 * 1024 * sizeof(double));
   double* lsum = (double*)ctx->ws.get("net_lsum", 5 * sizeof(double));
   forward(d, x16, a);
-  launch_loss(s, a.V1, a.o, target, lpart, lsum, a.dout, loss_kind);
+  if (loss_kind == 2) {
+    float* pb = (float*)ctx->ws.get("net_rp", (size_t)a.V1 * 2 * sizeof(float));
+    float* dpb = (float*)ctx->ws.get("net_rdp", (size_t)a.V1 * 2 * sizeof(float));
+    launch_residual_loss(s, d, x16, a.o, target, lpart, lsum, a.dout, pb, dpb);
+  } else {
+    launch_loss(s, a.V1, a.o, target, lpart, lsum, a.dout, loss_kind);
+  }
   backward(x16, a);
   if (update) {
     ++step;
@@ -290,7 +296,8 @@ double Net::train(const TrainData& td, const TrainOpts& to, std::vector<double>&
     launch_sumsq_crop_c64(s, full, crop, z0, y0, x0, vp, part);
     launch_finish_rms(s, part, rms_blocks(nc), (double)nc, scale);
     launch_prep_input_c64(s, full, crop, z0, y0, x0, vp, kp, pr, pi, scale, x16);
-    launch_prep_target_c64(s, full, crop, z0, y0, x0, ep, pr, pi, scale, tgt);
+    // the residual loss compares A N(v) with v itself; the other losses with the correction
+    launch_prep_target_c64(s, full, crop, z0, y0, x0, to.loss_kind == 2 ? vp : ep, pr, pi, scale, tgt);
     // cosine decay from lr to lr_min
     const double frac = to.steps > 1 ? (double)it / (to.steps - 1) : 1.0;
     const float lr = (float)(to.lr_min + 0.5 * (to.lr - to.lr_min) * (1.0 + std::cos(M_PI * frac)));

@@ -120,7 +120,7 @@ hfci_status hfci_net_train_step(hfci_net* net, int nx, int ny, int nz, const uin
   HFCI_REQUIRE(net && x16 && target, "NULL argument");
   check_dims(nx, ny, nz);
   HFCI_REQUIRE(!update || (lr > 0.f && lr < 1.f), "lr must be in (0, 1)");
-  HFCI_REQUIRE(loss_kind == 0 || loss_kind == 1, "loss_kind must be 0 or 1");
+  HFCI_REQUIRE(loss_kind >= 0 && loss_kind <= 2, "loss_kind must be 0, 1 or 2");
   Dev dg(net->device);
   const double L = net->train_step(Dims{nz, ny, nx}, x16, target, lr, update != 0, true, loss_kind);
   HFCI_HIP(hipGetLastError());
@@ -140,7 +140,7 @@ hfci_status hfci_net_train(hfci_net* net, const hfci_train_desc* d, double* fina
   HFCI_REQUIRE(d->crop >= 4 && d->crop % 4 == 0 && d->crop <= d->nx && d->crop <= d->ny && d->crop <= d->nz,
                "crop must be a multiple of 4 no larger than the grid");
   HFCI_REQUIRE(d->steps >= 1 && d->lr > 0.f && d->lr < 1.f && d->lr_min >= 0.f, "bad schedule");
-  HFCI_REQUIRE(d->loss_kind == 0 || d->loss_kind == 1, "loss_kind must be 0 or 1");
+  HFCI_REQUIRE(d->loss_kind >= 0 && d->loss_kind <= 2, "loss_kind must be 0, 1 or 2");
   Dev dg(net->device);
   TrainData td{d->nx, d->ny, d->nz, d->npairs, (const float2*)d->v, (const float2*)d->e, d->kch,
                d->medium_of_pair};

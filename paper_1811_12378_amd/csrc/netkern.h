@@ -60,5 +60,10 @@ void launch_finish_rms(hipStream_t s, const double* part, int nblk, double count
 // sums[0] receives the loss; part needs 4 * rms_blocks(2 * nvox) doubles, sums 5.
 void launch_loss(hipStream_t s, long nvox, const float* o, const float* t, double* part, double* sums, float* dout,
                  int kind);
+// residual loss (kind 2): p = Ahat o on the box d, the kind-1 loss of p against v, and
+// dout = Ahat dL/dp (Ahat is real and symmetric); Ahat = (6 - kch) - sum of the six
+// neighbours (zero outside), kch from x16's third channel; p, dp: scratch [n][2]
+void launch_residual_loss(hipStream_t s, Dims d, const uint16_t* x16, const float* o, const float* v, double* part,
+                          double* sums, float* dout, float* p, float* dp);
 
 }  // namespace hfci

@@ -225,6 +225,37 @@ __global__ void loss_pi_grad_kernel(long nvox, const float* __restrict__ o, cons
   dout[2 * v + 1] = (float)(k * (Sr * ui - Si * ur));
 }
 
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+// out = Ahat in on the box d, both channels: (6 - kch) in - sum of the six neighbours
+// (zero outside), kch from the network input's third channel
+__global__ void ahat_kernel(Dims d, const uint16_t* __restrict__ x16, const float* __restrict__ in,
+                            float* __restrict__ out) {
+  const long n = (long)d.x * d.y * d.z;
+  const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int x = (int)(v % d.x);
+  const long r = v / d.x;
+  const int y = (int)(r % d.y), z = (int)(r / d.y);
+  const long sy = d.x, sz = (long)d.x * d.y;
+  const float k = 6.f - bf2f(x16[v * 16 + 2]);
+  float s0 = k * in[2 * v], s1 = k * in[2 * v + 1];
+  auto sub = [&](bool ok, long u) {
+    if (ok) {
+      s0 -= in[2 * u];
+      s1 -= in[2 * u + 1];
+    }
+  };
+  sub(x > 0, v - 1);
+  sub(x + 1 < d.x, v + 1);
+  sub(y > 0, v - sy);
+  sub(y + 1 < d.y, v + sy);
+  sub(z > 0, v - sz);
+  sub(z + 1 < d.z, v + sz);
+  out[2 * v] = s0;
+  out[2 * v + 1] = s1;
+}
+
 __global__ void scale_f32_kernel(const float* __restrict__ in, long n, float a, float* __restrict__ out) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = a * in[i];
@@ -295,6 +326,14 @@ void launch_loss(hipStream_t s, long nvox, const float* o, const float* t, doubl
   hipLaunchKernelGGL(loss_sums_kernel, dim3(b), dim3(256), 0, s, nvox, o, t, part);
   hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(256), 0, s, part, b, sums);
   if (dout) hipLaunchKernelGGL(loss_grad_kernel, dim3(nb(2 * nvox)), dim3(256), 0, s, nvox, o, t, sums, dout);
+}
+
+void launch_residual_loss(hipStream_t s, Dims d, const uint16_t* x16, const float* o, const float* v, double* part,
+                          double* sums, float* dout, float* p, float* dp) {
+  const long n = (long)d.x * d.y * d.z;
+  hipLaunchKernelGGL(ahat_kernel, dim3(nb(n)), dim3(256), 0, s, d, x16, o, p);
+  launch_loss(s, n, p, v, part, sums, dout ? dp : nullptr, 1);
+  if (dout) hipLaunchKernelGGL(ahat_kernel, dim3(nb(n)), dim3(256), 0, s, d, x16, dp, dout);
 }
 
 }  // namespace hfci

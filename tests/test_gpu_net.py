@@ -214,3 +214,28 @@ def test_phase_invariant_loss_gradients(ctx):
     g = from_flat(net.get_grads())
     for k in g_ref:
         assert rel(g[k], g_ref[k]) <= 3e-2, (k, rel(g[k], g_ref[k]))
+
+
+def test_residual_loss_gradients(ctx):
+    """Loss kind 2 (the residual the output leaves, through Ahat built from the
+    omega^2 h^2/c^2 input channel) and its gradients against the oracle."""
+    net, p = setup_net(ctx, seed=17)
+    rng = np.random.default_rng(18)
+    shape = (8, 12, 16)
+    x3 = bf16(rng.standard_normal(shape + (3,)))
+    # a wide omega^2 h^2/c^2 range, so that a wrong sign or weight of its term in Ahat shows
+    x3[..., 2] = bf16(rng.uniform(1.0, 3.0, shape))
+    v = rng.standard_normal(shape + (2,)).astype(np.float32)
+    L = net.train_step(x16_of(x3), torch.from_numpy(v).cuda(), update=False, loss_kind=2)
+    out, cache = C.forward(p, x3, q=bf16)
+    Lref, dout = C.loss_residual(out, v.astype(np.float64), x3[..., 2])
+    g_ref, _ = C.backward(p, cache, dout, q=bf16)
+    assert abs(L - Lref) <= 1e-2 * abs(Lref) + 1e-4
+    # Ahat is applied to the output and again to the loss gradient; on the forward pass's
+    # BF16 rounding differences, which are white rather than smooth, it has about twice
+    # its gain on the signal (the oracle with white perturbations of the output: 2.1x the
+    # relative change in dL/dout for a 1e-2 perturbation), so the gradient bar is twice
+    # the other losses'
+    g = from_flat(net.get_grads())
+    for k in g_ref:
+        assert rel(g[k], g_ref[k]) <= 6e-2, (k, rel(g[k], g_ref[k]))

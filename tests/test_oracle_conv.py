@@ -122,3 +122,39 @@ def test_phase_invariant_loss():
     assert C.loss_phase_invariant(np.stack([oc.real, oc.imag], -1), t)[0] < 1e-14
     o2 = (out[..., 0] + 1j * out[..., 1]) * a
     assert abs(C.loss_phase_invariant(np.stack([o2.real, o2.imag], -1), t)[0] - L) < 1e-12
+
+
+def test_residual_loss_pins():
+    # Ahat against the operator's CSR assembly (Kronecker sums of second differences):
+    # with damping 0, kappa = kch and s/h^2 = 1 the assembled matrix is Ahat itself
+    import scipy.sparse.linalg as spla
+    from oracle import operator as OO
+    rng = np.random.default_rng(12)
+    shape = (4, 5, 6)
+    kch = rng.uniform(0.1, 0.9, size=shape)
+    Am = OO.assemble(shape, kch, np.zeros(shape), 1.0).toarray()
+    x = rng.standard_normal(shape + (2,))
+    ax = C.ahat(x, kch)
+    for c in range(2):
+        assert np.allclose(ax[..., c].ravel(), Am @ x[..., c].ravel(), atol=1e-12)
+    assert np.allclose(Am, Am.T)  # real symmetric: its own transpose
+    # the loss is the brute-force least-squares minimum over one complex coefficient d
+    out = rng.standard_normal(shape + (2,))
+    v = rng.standard_normal(shape + (2,))
+    L, g = C.loss_residual(out, v, kch)
+    vc = (v[..., 0] + 1j * v[..., 1]).ravel()
+    col = (Am @ (out[..., 0] + 1j * out[..., 1]).ravel())[:, None]
+    d, *_ = np.linalg.lstsq(col, vc, rcond=None)
+    brute = np.linalg.norm(vc - col[:, 0] * d[0]) ** 2 / np.linalg.norm(vc) ** 2
+    assert abs(L - brute) < 1e-12
+    # zero for a complex multiple of the exact solve Ahat e = v
+    e = spla.spsolve(OO.assemble(shape, kch, np.zeros(shape), 1.0).tocsc().astype(complex), vc).reshape(shape)
+    e = (0.4 + 2.1j) * e
+    assert C.loss_residual(np.stack([e.real, e.imag], -1), v, kch)[0] < 1e-13
+    # gradient by central differences
+    h = 1e-6
+    for idx in [(0, 0, 0, 0), (3, 4, 5, 1), (2, 1, 3, 0)]:
+        ep = np.zeros_like(out)
+        ep[idx] = h
+        fd = (C.loss_residual(out + ep, v, kch)[0] - C.loss_residual(out - ep, v, kch)[0]) / (2 * h)
+        assert abs(fd - g[idx]) < 1e-7
