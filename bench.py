@@ -448,7 +448,8 @@ def case_two_arm(args, ctx, op, cont, wl, solve=True):
     g2 = op.case_two()
     # near the origin B's eigenvalues are about half of A's (mu = sqrt(a + 1) - 1, the map of
     # eq. shifted-2x2's equivalent shifts), so eps / 2 keeps the same modes inside the contour
-    eps2 = args.case_two_eps if args.case_two_eps > 0 else args.eps / 2
+    eps1 = cont.params()["eps"]
+    eps2 = args.case_two_eps if args.case_two_eps > 0 else eps1 / 2
     c2 = hfci.Contour(g2, args.poles, 1.0, eps2, args.q)
     rhs2 = torch.zeros((1, 2, n, n, n), dtype=torch.complex64, device="cuda")
     rhs2[0, 1] = f1[0]
@@ -462,7 +463,7 @@ def case_two_arm(args, ctx, op, cont, wl, solve=True):
         t = time.perf_counter() - t0
         steps = [int(v) for v in st[:, 0]]
         cg = c_.get()
-        out[name] = {"time_s": round(t, 4), "eps": args.eps if name == "case_one" else eps2,
+        out[name] = {"time_s": round(t, 4), "eps": round(eps1 if name == "case_one" else eps2, 4),
                      "steps_per_pole": steps, "stencil_products": int(args.q * sum(steps)),
                      "nu_per_pole": [round(float(v), 4) for v in cg["nu"]],
                      "box": [round(o_.info()["b1"], 4), round(o_.info()["b2"], 4), o_.info()["rho2"]]}
@@ -562,7 +563,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--poles", type=int, default=16)
-    ap.add_argument("--eps", type=float, default=0.25)
+    ap.add_argument("--eps", type=float, default=0.0,
+                    help="contour eps (default 0: chosen by the library's rule for the operator's box and grid)")
     ap.add_argument("--q", type=int, default=8)
     ap.add_argument("--ppw", type=float, default=8.0)
     ap.add_argument("--tol", type=float, default=1e-6)
@@ -652,6 +654,7 @@ def main():
     f_d = torch.from_numpy(np.stack(wl.rhs)).cuda()
     op = hfci.Operator(ctx, c_d, wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
     cont = hfci.Contour(op, args.poles, 1.0, args.eps, args.q)
+    eps_used = cont.params()["eps"]  # the library's rule chooses it for --eps 0
     info = op.info()
     log("operator:", info)
 
@@ -734,7 +737,7 @@ def main():
         if budget.fits(est):
             try:
                 from oracle import fci as OF
-                poles_o = OF.pole_parameters(o, args.poles, 1.0, args.eps, args.q)
+                poles_o = OF.pole_parameters(o, args.poles, 1.0, eps_used, args.q)
                 cpu = cpu_baseline(wl, poles_o, st_first["matvecs"])
                 if args.cpu_full:
                     cpu["full_solves"] = cpu_full_solves(args)
@@ -820,7 +823,7 @@ def main():
         "config": {"workload": "layered medium %d^3, %d point sources, %d poles, q=%d, %g ppw, tol %g, "
                                "FP32 shifted sweeps + FP64 FGMRES(30)"
                                % (args.n, args.nrhs, args.poles, args.q, args.ppw, args.tol),
-                   "grid": args.n, "rhs": args.nrhs, "poles": args.poles, "q": args.q, "eps": args.eps,
+                   "grid": args.n, "rhs": args.nrhs, "poles": args.poles, "q": args.q, "eps": round(eps_used, 4),
                    "ppw": args.ppw, "tol": args.tol, "stencil_shape_c64": list(tune32),
                    "stencil_shape_c128": list(tune64)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -274,7 +274,11 @@ hfci_status hfci_op_case_two(const hfci_op* op, hfci_op** out);
  * delta (HOST array of J, or NULL) overrides the delta search.
  * q = 0 chooses the degree by Sec. 4.2's rule: the q in 1..8 minimising nu^(1/q) for
  * the pole closest to the origin (not with given deltas); hfci_contour_q reads it back.
- * Errors: HFCI_E_ARG (J < 1, q < 0 or > 16, t <= 0, eps <= 0);
+ * Without given poles, J = 0 takes J = 6 and eps = 0 takes the eps of hfci_contour_rule
+ * for this operator's box, J, t, q (8 in its model when q = 0) and fp_reduce 5;
+ * hfci_contour_params reads J, t and eps back.
+ * Errors: HFCI_E_ARG (J < 0 or > 256, J = 0 with given poles or deltas, q < 0 or > 16,
+ * t <= 0, eps < 0);
  * HFCI_E_CONTOUR (a pole with Re z > 0 or Im z in (-eps-rho2, eps) when
  * computed, or nu >= 1). */
 hfci_status hfci_contour_create(const hfci_op* op, int J, double t, double eps, int q,
@@ -285,6 +289,30 @@ void hfci_contour_destroy(hfci_contour* c);
 /* The degree q of the contour's polynomial (the chosen one when created with q = 0),
  * written to *q (HOST).  Errors: HFCI_E_ARG. */
 hfci_status hfci_contour_q(const hfci_contour* c, int* q);
+
+/* J, t and eps of the contour (the chosen ones when created with J = 0 or eps = 0),
+ * written to HOST scalars (any may be NULL).  Errors: HFCI_E_ARG. */
+hfci_status hfci_contour_params(const hfci_contour* c, int* J, double* t, double* eps);
+
+/* Contour parameters by rule, host arithmetic only (no GPU work; b1, b2, rho2 are the
+ * box of hfci_op_info, npoints the grid points nx*ny*nz).  Sec. 7.3 sets eps per
+ * frequency with a small fixed number of poles (six); here *J_out = J, or 6 for J = 0,
+ * and *eps_out is the eps, among 25 geometric steps over [0.04, 0.64], minimising the
+ * predicted solve time
+ *     T(eps) = eps * (q S + q M * 2e6 / npoints + 100),
+ *     S = sum_j s_j, M = max_j s_j, s_j = ceil(ln(fp_reduce) / -ln nu_j(eps)),
+ * where nu_j is eq. fix-pt-conv's rate for pole j of eq. quad-points (J, t, eps) at the
+ * degree q (8 in the model for q = 0), so s_j is the fixed-point steps pole j needs.
+ * The FGMRES iteration count grows about in proportion to eps (measured on the
+ * finite-difference operators for J from 4 to 16); per iteration the products of all
+ * poles cost their bytes, each launch a latency worth about 2e6 grid points of one
+ * system's pass, and the Arnoldi step with the combine about 100 products (both fitted
+ * to measured solve times on MI355X).  The rates use 200 samples per side of the box and
+ * an 80-point delta scan; ties go to the smaller eps.  Outputs HOST (any may be NULL).
+ * Errors: HFCI_E_ARG (b1 >= b2, rho2 < 0, npoints < 1, J < 0 or > 256, t <= 0, q < 0 or
+ * > 16, fp_reduce <= 1). */
+hfci_status hfci_contour_rule(double b1, double b2, double rho2, double npoints, int J, double t, int q,
+                              double fp_reduce, int* J_out, double* eps_out);
 
 /* Copy the contour's parameters into HOST arrays of length J (any may be NULL):
  * poles z, weights sigma, delta, Taylor centres z0, and the rate nu of each. */

@@ -1,0 +1,70 @@
+"""Contour parameters chosen by rule (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Sec. 7.3 uses a small fixed number of poles (six) and sets eps per frequency.  The rule
+written out here chooses eps from the spectrum box [b1, b2] x [-rho2, 0] alone: among 25
+geometric candidates over [0.04, 0.64] it takes the first one minimising the predicted
+solve time
+
+    T(eps) = eps * (q * S + q * M * LAUNCH / npoints + ITER),
+    S = sum_j s_j,  M = max_j s_j,  s_j = ceil(ln(reduce) / -ln nu_j),
+
+where nu_j is the rate of eq. fix-pt-conv (Sec. 4.2: the delta search with
+z0 = (b1 + b2)/2 + i Im z) for pole j of eq. quad-points at (J, t, eps).  By Thm 4.2 the
+error of the fixed-point iteration is multiplied by p~(A)/p~(z) each step, whose size on
+the box is at most nu_j (maximum principle), so s_j steps reduce the residual by `reduce`
+for any normal operator with its spectrum in the box.  The iteration count of FGMRES is
+taken proportional to eps, LAUNCH (grid points of one system's pass that a launch's
+latency costs) and ITER (the Arnoldi step's work in products) are measured constants of
+the hardware, not of the paper.  J = 0 means 6 (Sec. 7.3), q = 0 means the model's q = 8.
+
+The rates use the oracle's own delta search on a boundary of `per_side` samples per side.
+
+Pins (tests/test_contour_rule.py): on a diagonal operator whose eigenvalues fill the box,
+the oracle's fixed-point iteration needs at most s_j steps at every pole, and exactly s_j
+(up to the boundary sampling) when the right-hand side sits on the worst eigenvalue;
+mirror-image poles have the same rate; the per-pole charges never grow with eps; with
+the launch and iteration terms removed the rule reduces to the product count alone.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .contour import poles_and_weights
+from .polynomial import optimise_delta
+
+RULE_J, RULE_Q, LAUNCH, ITER = 6, 8, 2.0e6, 100.0
+CANDIDATES = 0.04 * 16.0 ** (np.arange(25) / 24.0)
+
+
+def pole_steps(b1: float, b2: float, rho2: float, J: int, t: float, eps: float, q: int,
+               reduce: float = 5.0, per_side: int = 200):
+    """(s_j, nu_j, delta_j, z_j, z0_j) for the poles of eq. quad-points at (J, t, eps)."""
+    z, _, _ = poles_and_weights(J, t, eps, rho2)
+    out = []
+    for zj in z:
+        d, nu, z0 = optimise_delta(zj, b1, b2, rho2, q, per_side=per_side)
+        s = math.ceil(math.log(reduce) / -math.log(nu)) if nu < 1.0 else math.inf
+        out.append((s, nu, d, complex(zj), z0))
+    return out
+
+
+def predicted_time(steps, eps: float, q: int, npoints: float, launch: float = LAUNCH, it: float = ITER) -> float:
+    s = [p[0] for p in steps]
+    return eps * (q * sum(s) + q * max(s) * launch / npoints + it)
+
+
+def rule_parameters(b1: float, b2: float, rho2: float, npoints: float, J: int = 0, t: float = 1.0, q: int = 0,
+                    reduce: float = 5.0, per_side: int = 200, launch: float = LAUNCH, it: float = ITER):
+    """Returns (J, eps, table) with table[k] = (eps_k, T(eps_k)) over the candidates."""
+    J = J if J > 0 else RULE_J
+    qm = q if q > 0 else RULE_Q
+    table = []
+    for eps in CANDIDATES:
+        st = pole_steps(b1, b2, rho2, J, t, float(eps), qm, reduce, per_side)
+        table.append((float(eps), predicted_time(st, float(eps), qm, npoints, launch, it)))
+    k = min(range(len(table)), key=lambda i: (table[i][1], i))
+    return J, table[k][0], table

@@ -572,11 +572,18 @@ hfci_status hfci_contour_create(const hfci_op* op, int J, double t, double eps, 
   HFCI_API_BEGIN
   HFCI_REQUIRE(op && out, "NULL argument");
   *out = nullptr;
-  HFCI_REQUIRE(J >= 1 && J <= 256, "J must be in [1, 256]");
-  HFCI_REQUIRE(q >= 0 && q <= 16, "q must be in [0, 16]");
   HFCI_REQUIRE((z == nullptr) == (sigma == nullptr), "give both poles and weights or neither");
+  HFCI_REQUIRE(J >= (z ? 1 : 0) && J <= 256, "J must be in [1, 256] (or 0: chosen by the rule)");
+  HFCI_REQUIRE(q >= 0 && q <= 16, "q must be in [0, 16]");
   HFCI_REQUIRE(q > 0 || delta == nullptr, "q = 0 (chosen here) cannot take given deltas");
-  if (!z) HFCI_REQUIRE(t > 0 && eps > 0 && std::isfinite(t) && std::isfinite(eps), "t and eps must be > 0");
+  HFCI_REQUIRE(J > 0 || delta == nullptr, "J = 0 (chosen here) cannot take given deltas");
+  if (!z) {
+    HFCI_REQUIRE(t > 0 && eps >= 0 && std::isfinite(t) && std::isfinite(eps),
+                 "t must be > 0 and eps >= 0 (0: chosen by the rule)");
+    if (J == 0) J = kRuleJ;
+    if (eps == 0) eps = rule_eps(op->b1, op->b2, op->rho2, (double)op->g.nx * op->g.ny * op->g.nz, J, t,
+                                 q > 0 ? q : kRuleQ, kRuleReduce);
+  }
   DeviceGuard dg(op->ctx->device);
   hfci_contour* c = new hfci_contour();
   try {
@@ -662,6 +669,34 @@ void hfci_contour_destroy(hfci_contour* c) {
   if (c->d_poles) (void)hipFree(c->d_poles);
   if (prev >= 0) (void)hipSetDevice(prev);
   delete c;
+}
+
+hfci_status hfci_contour_rule(double b1, double b2, double rho2, double npoints, int J, double t, int q,
+                              double fp_reduce, int* J_out, double* eps_out) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(std::isfinite(b1) && std::isfinite(b2) && b1 < b2 && std::isfinite(rho2) && rho2 >= 0,
+               "need b1 < b2 and rho2 >= 0");
+  HFCI_REQUIRE(npoints >= 1 && std::isfinite(npoints), "npoints must be >= 1");
+  HFCI_REQUIRE(J >= 0 && J <= 256, "J must be in [0, 256]");
+  HFCI_REQUIRE(t > 0 && std::isfinite(t), "t must be > 0");
+  HFCI_REQUIRE(q >= 0 && q <= 16, "q must be in [0, 16]");
+  HFCI_REQUIRE(fp_reduce > 1.0 && std::isfinite(fp_reduce), "fp_reduce must be > 1");
+  const int Jr = J > 0 ? J : kRuleJ;
+  const double e = rule_eps(b1, b2, rho2, npoints, Jr, t, q > 0 ? q : kRuleQ, fp_reduce);
+  if (J_out) *J_out = Jr;
+  if (eps_out) *eps_out = e;
+  return HFCI_OK;
+  HFCI_API_END
+}
+
+hfci_status hfci_contour_params(const hfci_contour* c, int* J, double* t, double* eps) {
+  HFCI_API_BEGIN
+  HFCI_REQUIRE(c, "NULL contour");
+  if (J) *J = c->J;
+  if (t) *t = c->t;
+  if (eps) *eps = c->eps;
+  return HFCI_OK;
+  HFCI_API_END
 }
 
 hfci_status hfci_contour_q(const hfci_contour* c, int* q) {

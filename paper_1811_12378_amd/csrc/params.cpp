@@ -70,11 +70,11 @@ double rate_on_boundary(double delta, cd z, cd z0, int q, const std::vector<cd>&
 // eq. fix-pt-conv: nu = min over real delta of max over the rectangle boundary of
 // |p~(lambda)/p~(z)|, with z0 = (b1+b2)/2 + i Im z and sign(delta) = sign(Im z).
 // A geometric scan of |delta| brackets the minimum, golden-section search refines it.
-void optimise_delta(cd z, double b1, double b2, double rho2, int q, double& delta, double& nu, cd& z0) {
+void optimise_delta(cd z, double b1, double b2, double rho2, int q, double& delta, double& nu, cd& z0, int per_side,
+                    int ns) {
   z0 = cd(0.5 * (b1 + b2), z.imag());
   const double sgn = z.imag() > 0 ? 1.0 : -1.0;
-  const std::vector<cd> bd = rectangle_boundary(b1, b2, rho2, 2000);
-  const int ns = 480;
+  const std::vector<cd> bd = rectangle_boundary(b1, b2, rho2, per_side);
   const double lo = 1e-4, hi = 50.0;
   std::vector<double> ds(ns), vs(ns);
   int best = 0;
@@ -125,6 +125,98 @@ int choose_q(cd z, double b1, double b2, double rho2, int qmax) {
     }
   }
   return best;
+}
+
+// max over the boundary of |p~(lambda)| / |p~(z)| with the complex products written out
+// (the rule evaluates it some 10^5 times per call; std::complex's checked products are
+// several times slower)
+static double rate_plain(double delta, cd z, cd z0, int q, const std::vector<cd>& bd) {
+  auto pt_abs2 = [&](double lr, double li) {
+    // x = -i delta (lambda - z0) = delta (Im(lambda - z0)) - i delta Re(lambda - z0)
+    const double xr = delta * (li - z0.imag()), xi = -delta * (lr - z0.real());
+    double ar = 1.0, ai = 0.0;
+    for (int j = q; j >= 1; --j) {
+      const double inv = 1.0 / j;
+      const double tr = (ar * xr - ai * xi) * inv, ti = (ar * xi + ai * xr) * inv;
+      ar = 1.0 + tr;
+      ai = ti;
+    }
+    return ar * ar + ai * ai;
+  };
+  double m = 0.0;
+  for (const cd& l : bd) m = std::max(m, pt_abs2(l.real(), l.imag()));
+  return std::sqrt(m / pt_abs2(z.real(), z.imag()));
+}
+
+// eq. fix-pt-conv's nu for the rule: a geometric scan of |delta| and a short golden-section
+// refinement (the rule needs nu to a few digits)
+static double rule_nu(cd z, double b1, double b2, double rho2, int q, const std::vector<cd>& bd) {
+  const cd z0(0.5 * (b1 + b2), z.imag());
+  const double sgn = z.imag() > 0 ? 1.0 : -1.0;
+  const double lo = 1e-4, hi = 50.0;
+  int best = 0;
+  double vbest = HUGE_VAL;
+  auto d_at = [&](int k) { return lo * std::pow(hi / lo, (double)k / (kRuleScan - 1)); };
+  for (int k = 0; k < kRuleScan; ++k) {
+    const double v = rate_plain(sgn * d_at(k), z, z0, q, bd);
+    if (v < vbest) {
+      vbest = v;
+      best = k;
+    }
+  }
+  double a = d_at(std::max(best - 1, 0)), b = d_at(std::min(best + 1, kRuleScan - 1));
+  const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+  double c = b - gr * (b - a), d = a + gr * (b - a);
+  double fc = rate_plain(sgn * c, z, z0, q, bd), fd = rate_plain(sgn * d, z, z0, q, bd);
+  for (int it = 0; it < 40 && (b - a) > 1e-7 * b; ++it) {
+    if (fc < fd) {
+      b = d; d = c; fd = fc;
+      c = b - gr * (b - a);
+      fc = rate_plain(sgn * c, z, z0, q, bd);
+    } else {
+      a = c; c = d; fc = fd;
+      d = a + gr * (b - a);
+      fd = rate_plain(sgn * d, z, z0, q, bd);
+    }
+  }
+  return std::min(vbest, std::min(fc, fd));
+}
+
+// Contour parameters by rule.  Sec. 7.3 sets eps per frequency with a small fixed J; here
+// eps is the value, among kRuleN geometric steps over [kRuleLo, kRuleHi], that minimises a
+// predicted solve time
+//   T(eps) = eps * (q sum_j s_j + q max_j s_j * kRuleLaunch / npoints + kRuleIter),
+//   s_j = ceil(ln(reduce) / -ln nu_j),
+// nu_j being eq. fix-pt-conv's rate for pole j of eq. quad-points at that eps, so s_j is
+// the fixed-point steps pole j needs.  The FGMRES iteration count grows about in
+// proportion to eps; per iteration the products of all poles cost their bytes, each
+// launch (as many as the slowest pole's products) a latency worth kRuleLaunch grid points
+// of one system's pass, and the Arnoldi step with the combine about kRuleIter products.
+// Ties go to the smaller eps.
+double rule_eps(double b1, double b2, double rho2, double npoints, int J, double t, int q, double reduce) {
+  const std::vector<cd> bd = rectangle_boundary(b1, b2, rho2, kRulePerSide);
+  double best_eps = kRuleLo, best_t = HUGE_VAL;
+  std::vector<cd> z, sigma;
+  for (int k = 0; k < kRuleN; ++k) {
+    const double eps = kRuleLo * std::pow(kRuleHi / kRuleLo, (double)k / (kRuleN - 1));
+    contour_poles(J, t, eps, rho2, z, sigma);
+    // poles j and J-1-j are mirror images about Im = -rho2/2, as is the box, so they have
+    // the same rate: evaluate the first half and count each twice (the middle pole of an
+    // odd J once)
+    double sum = 0.0, mx = 0.0;
+    for (int j = 0; j < (J + 1) / 2 && std::isfinite(sum); ++j) {
+      const double nu = rule_nu(z[j], b1, b2, rho2, q, bd);
+      const double sj = nu < 1.0 ? std::ceil(std::log(reduce) / -std::log(nu)) : HUGE_VAL;
+      sum += (2 * j + 1 == J) ? sj : 2.0 * sj;
+      mx = std::max(mx, sj);
+    }
+    const double tk = eps * (q * sum + q * mx * kRuleLaunch / npoints + kRuleIter);
+    if (tk < best_t) {
+      best_t = tk;
+      best_eps = eps;
+    }
+  }
+  return best_eps;
 }
 
 // Roots of sum_k c[k] x^k (c.back() != 0, degree <= 16) by the Aberth-Ehrlich

@@ -34,7 +34,8 @@ EXPORTED = ["hfci_default_opts", "hfci_last_error", "hfci_version", "hfci_ctx_cr
             "hfci_net_eval", "hfci_net_train_step", "hfci_net_train", "hfci_net_apply", "hfci_op_medium_channel",
             "hfci_net_save", "hfci_net_load", "hfci_op_set_tune", "hfci_op_get_tune", "hfci_op_autotune",
             "hfci_shifted_solve_batch", "hfci_solve_batch", "hfci_op_case_two", "hfci_contour_q",
-            "hfci_op_create_spectral", "hfci_shifted_solve_noalloc"]
+            "hfci_op_create_spectral", "hfci_shifted_solve_noalloc", "hfci_contour_params",
+            "hfci_contour_rule"]
 PROF_CLASSES = ["fp_stage", "fp_stage_first", "apply", "fp_stage_last", "fp_stage_init"]
 
 
@@ -120,6 +121,8 @@ def load_library(path: str = LIB_PATH):
         "hfci_contour_destroy": (None, [vp]),
         "hfci_contour_get": (ip, [vp, vp, vp, vp, vp, vp]),
         "hfci_contour_q": (ip, [vp, P(ip)]),
+        "hfci_contour_params": (ip, [vp, P(ip), P(dp), P(dp)]),
+        "hfci_contour_rule": (ip, [dp, dp, dp, dp, ip, dp, ip, dp, P(ip), P(dp)]),
         "hfci_shifted_solve": (ip, [vp, vp, ip, ip, vp, vp, ip, dp, ip, vp]),
         "hfci_shifted_solve_noalloc": (ip, [vp, vp, ip, ip, vp, vp, ip, dp, ip, vp]),
         "hfci_fci_apply": (ip, [vp, vp, P(SolveOpts), ip, vp, vp, P(Stats)]),
@@ -511,6 +514,14 @@ class Contour(_Handle):
             qv = ctypes.c_int()
             _check(load_library().hfci_contour_q(self.h, ctypes.byref(qv)))
             self.q = qv.value
+        if J == 0 or eps == 0:  # chosen by the library's rule
+            self.J = self.params()["J"]
+
+    def params(self):
+        """hfci_contour_params: {"J", "t", "eps"} (the chosen values for J = 0 or eps = 0)."""
+        Jv, tv, ev = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+        _check(load_library().hfci_contour_params(self.h, ctypes.byref(Jv), ctypes.byref(tv), ctypes.byref(ev)))
+        return {"J": Jv.value, "t": tv.value, "eps": ev.value}
 
     def get(self):
         J = self.J
@@ -519,6 +530,16 @@ class Contour(_Handle):
         _check(load_library().hfci_contour_get(self.h, z, s, d, z0, nu))
         cz = lambda a: np.array([complex(v.re, v.im) for v in a])
         return {"z": cz(z), "sigma": cz(s), "delta": np.array(d[:]), "z0": cz(z0), "nu": np.array(nu[:])}
+
+
+def contour_rule(b1: float, b2: float, rho2: float, npoints: float, J: int = 0, t: float = 1.0, q: int = 0,
+                 fp_reduce: float = 5.0):
+    """hfci_contour_rule (host arithmetic only): (J, eps) for the spectrum box [b1, b2] x [-rho2, 0]
+    of an operator on npoints grid points."""
+    Jv, ev = ctypes.c_int(), ctypes.c_double()
+    _check(load_library().hfci_contour_rule(b1, b2, rho2, float(npoints), J, t, q, fp_reduce, ctypes.byref(Jv),
+                                            ctypes.byref(ev)))
+    return Jv.value, ev.value
 
 
 def shifted_solve(op, c: Contour, f, steps: int = 0, reduce: float = 5.0, max_steps: int = 200):

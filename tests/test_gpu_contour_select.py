@@ -73,3 +73,36 @@ def test_chosen_degree_errors(ctx):
     with pytest.raises(hf.HfciError) as e:
         hf.Contour(g, 4, 1.0, 0.5, -1)
     assert e.value.status == -1
+
+
+def test_contour_by_rule_matches_the_oracle_rule(ctx):
+    """J = 0 and eps = 0 at creation: J = 6 and the eps of the rule (oracle/contour_rule.py)
+    for the operator's box and grid, poles of eq. quad-points at them, and a mixed solve
+    with that contour reaches the tolerance."""
+    from oracle import contour_rule as OR
+    shape = (24, 24, 24)
+    g = make(ctx, shape, 40.0, 4, 1.0, seed=3)
+    info = g.info()
+    b1, b2, rho2 = info["b1"], info["b2"], info["rho2"]
+    c = hf.Contour(g, 0, 1.0, 0.0, 8)
+    prm = c.params()
+    J_o, eps_o, table = OR.rule_parameters(b1, b2, rho2, float(np.prod(shape)), q=8)
+    assert prm["J"] == J_o == 6 and c.J == 6 and prm["t"] == 1.0
+    tmin = min(t for _, t in table)
+    assert prm["eps"] == eps_o or dict(table)[prm["eps"]] <= 1.02 * tmin, (prm["eps"], eps_o)
+    assert (6, prm["eps"]) == hf.contour_rule(b1, b2, rho2, float(np.prod(shape)))
+    z_o, s_o, _ = OC.poles_and_weights(6, 1.0, prm["eps"], rho2)
+    got = c.get()
+    assert np.max(np.abs(got["z"] - z_o)) <= 1e-13 * np.max(np.abs(z_o))
+    assert np.max(np.abs(got["sigma"] - s_o)) <= 1e-13 * np.max(np.abs(s_o))
+    # the same J given, eps chosen
+    c16 = hf.Contour(g, 16, 1.0, 0.0, 8)
+    assert c16.params()["J"] == 16 and c16.J == 16
+    assert c16.params()["eps"] == hf.contour_rule(b1, b2, rho2, float(np.prod(shape)), J=16)[1]
+    # a solve with the chosen contour converges
+    rng = np.random.default_rng(4)
+    f = torch.from_numpy(rng.standard_normal((1,) + shape) + 1j * rng.standard_normal((1,) + shape)).cuda()
+    u, st = hf.solve(g, c, f, opts=hf.default_opts(precision=32, tol=1e-6, max_it=400))
+    assert st["status"] == "HFCI_OK" and st["final_relres"] <= 1e-6
+    with pytest.raises(hf.HfciError):  # eps < 0 is neither a value nor the rule
+        hf.Contour(g, 0, 1.0, -0.1, 8)

@@ -480,9 +480,10 @@ def test_full_size_apply_every_point(ctx, prec):
 def test_error_paths(ctx):
     c = medium((4, 4, 4), 14)
     o, g = make_ops(ctx, c, 5.0, 1, 1.0)
-    with pytest.raises(hf.HfciError) as e:
-        hf.Contour(g, 0, 1.0, 0.5, 8)
-    assert e.value.status == -1
+    for J in (-1, 257):  # J = 0 asks the library's rule for J
+        with pytest.raises(hf.HfciError) as e:
+            hf.Contour(g, J, 1.0, 0.5, 8)
+        assert e.value.status == -1
     with pytest.raises(hf.HfciError) as e:  # a pole inside the damping band
         hf.Contour(g, 1, 1.0, 0.5, 4, z=[-0.5j], sigma=[1.0])
     assert e.value.status == -4
