@@ -200,7 +200,7 @@ def main(argv=None):
     m.add_argument("--kernel", required=True)
     m.add_argument("--out", required=True)
     m.add_argument("--traffic-json")
-    m.add_argument("--shape", type=int, nargs=5, help="stencil launch shape the counters were taken with")
+    m.add_argument("--shape", type=int, nargs="+", help="stencil launch shape the counters were taken with")
     m.add_argument("--alg-bytes", type=float, help="algorithmic bytes per launch of the counter runs")
     m.add_argument("--cmd", nargs=argparse.REMAINDER)
     a = ap.parse_args(argv)
