@@ -25,7 +25,9 @@ Prints ONE JSON line on stdout (everything else goes to stderr), carrying:
   cpu_baseline the FP64 oracle on the host: per-stencil time on a bounded sample,
                projected to the matvec count of the timed solve
   fp64         the same solve with FP64 sweeps (plain method), and the speedup
-  learned      training on FCI pairs, then the solve with the learned preconditioner
+  learned      training on the remainders FCI leaves on 128^3 random media, then the solve
+               with the network as Alg. 1 step 4's inner preconditioner, on the headline
+               workload and (against FCI alone) on an unseen 256^3 random-field medium
 """
 from __future__ import annotations
 
@@ -308,15 +310,20 @@ def fp64_arm(args, ctx, op, cont, f_d, wl, t_mixed, verbose):
 
 
 def learned_arm(args, ctx, op, cont, f_d, t_mixed, fp64, verbose):
-    """Train the network on pairs from FCI-preconditioned FGMRES (untimed), then time the solve
-    with the learned preconditioner (FCI as arbiter and fallback) and the network's throughput."""
+    """Configuration 5: train the network (untimed) on the remainders FCI leaves on random
+    128^3 media (about 2000 pairs from FCI-preconditioned FGMRES, the residual loss), then
+    time FGMRES with the network as Alg. 1 step 4's inner preconditioner (k_in = 1: FCI(v)
+    plus the best multiple of net(remainder)) on the headline workload, and FCI alone
+    against FCI with the network on an unseen 256^3 random-field medium."""
     import torch
     from paper_1811_12378_amd import hfci
     from paper_1811_12378_amd import learned as L
     t0 = time.perf_counter()
-    net, info = L.train(ctx, None, n=64, media=args.learn_media, pairs=48, steps=args.learn_steps)
+    net, info = L.train(ctx, None, n=args.learn_n, media=args.learn_media, pairs=48, steps=args.learn_steps,
+                        crop=min(64, args.learn_n))
     train_s = time.perf_counter() - t0
-    log("learned: %d pairs, training %.1f s, final loss %.4f" % (info["pairs"], train_s, info["final_loss"]))
+    log("learned: %d remainders at %d^3, harvest %.1f s, training %.1f s, final loss %.4f"
+        % (info["pairs"], args.learn_n, info["harvest_s"], info["train_s"], info["final_loss"]))
     # network throughput on the benchmark grid (BF16 MFMA, FP32 accumulate)
     r = torch.randn((1,) + tuple(f_d.shape[1:]), dtype=torch.complex128, device="cuda")
     net.apply(op, r)
@@ -329,24 +336,31 @@ def learned_arm(args, ctx, op, cont, f_d, t_mixed, fp64, verbose):
     t_net = (time.perf_counter() - t1) / reps
     del r
     tflops = unet_flops_per_voxel() * op.n / t_net / 1e12
-    lo = hfci.default_opts(precision=32, tol=args.tol, max_it=args.max_it, precond=2, verbose=verbose)
+    lo = hfci.default_opts(precision=32, tol=args.tol, max_it=args.max_it, k_in=1, inner_precond=1, verbose=verbose)
     lo.net = net.h.value
+    hfci.solve(op, cont, f_d, opts=hfci.default_opts(precision=32, tol=args.tol, max_it=1, k_in=1, inner_precond=1,
+                                                     net=net.h.value))  # untimed: workspace
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     _, st = hfci.solve(op, cont, f_d, opts=lo)
     torch.cuda.synchronize()
     t_l = time.perf_counter() - t2
-    log("learned+FP32: %.3f s, its %d (%d kept, %d FCI), relres %.3e" % (t_l, st["its"], st["learned_accepted"],
-                                                                       st["learned_fallbacks"], st["final_relres"]))
-    out = {"time_s": t_l, "its": st["its"], "final_relres": st["final_relres"], "kept": st["learned_accepted"],
-           "fci_steps": st["learned_fallbacks"], "net_rho_mean": st["net_rho_mean"],
-           "fci_rho_mean": st["fci_rho_mean"], "train_pairs": info["pairs"], "train_s": train_s,
+    log("learned (step 4) + FP32: %.3f s, its %d, relres %.3e" % (t_l, st["its"], st["final_relres"]))
+    out = {"mode": "network as Alg. 1 step 4's inner preconditioner (k_in 1)", "time_s": t_l, "its": st["its"],
+           "final_relres": st["final_relres"], "train_pairs": info["pairs"], "train_grid": args.learn_n,
+           "train_media": args.learn_media, "harvest_s": info["harvest_s"], "train_s": info["train_s"],
            "train_final_loss": info["final_loss"], "speedup_vs_mixed_fci": t_mixed / t_l,
            "net_apply_ms": t_net * 1e3,
            "net_roofline": {"bound": "mfma", "achieved": round(tflops, 1), "peak": 2500.0, "unit": "TFLOP/s",
                             "frac": round(tflops / 2500.0, 4)}}
     if fp64:
         out["speedup_vs_fp64"] = fp64["time_s"] / t_l
+    # configuration 5's evaluation: an unseen 256^3 random-field medium, one point source
+    g = L.compare(ctx, net, n=args.n, medium="grf", seed=901, tol=args.tol, max_it=args.max_it, mode="step4")
+    out["unseen_grf"] = {"workload": g["workload"],
+                         "fci": {"time_s": g["fci"]["time_s"], "its": g["fci"]["its"]},
+                         "fci_net_step4": {"time_s": g["fci+net_step4"]["time_s"], "its": g["fci+net_step4"]["its"],
+                                           "final_relres": g["fci+net_step4"]["final_relres"]}}
     net.close()
     return out
 
@@ -575,10 +589,13 @@ def main():
                     help="also time a complete FP64 oracle solve at 32^3 (and the 96^3 per-product time)")
     ap.add_argument("--quiet", action="store_true", help="no per-cycle progress lines from the solver")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner arm")
-    ap.add_argument("--learn-media", type=int, default=12, help="64^3 training media for the learned arm")
-    ap.add_argument("--learn-steps", type=int, default=2000, help="Adam steps for the learned arm")
-    ap.add_argument("--learn-est", type=float, default=70.0,
-                    help="estimated seconds of harvesting and training in the learned arm (budget check)")
+    ap.add_argument("--learn-n", type=int, default=128, help="training grid of the learned arm")
+    ap.add_argument("--learn-media", type=int, default=42,
+                    help="training media of the learned arm (48 remainders each)")
+    ap.add_argument("--learn-steps", type=int, default=4000, help="Adam steps for the learned arm")
+    ap.add_argument("--learn-est", type=float, default=110.0,
+                    help="estimated seconds of the learned arm besides its headline solve (harvesting, "
+                         "training, the unseen-medium comparison; budget check)")
     ap.add_argument("--uneven", type=int, default=0,
                     help="instances of the uneven-batch arm (64 = the full config; 0 skips it)")
     ap.add_argument("--uneven-only", action="store_true", help="run only the uneven-batch arm")
@@ -757,7 +774,7 @@ def main():
 
     learned = None
     if not args.no_learned:
-        est = args.learn_est + 1.3 * t1
+        est = args.learn_est + 1.5 * t1
         if budget.fits(est):
             learned = guarded(lambda: learned_arm(args, ctx, op, cont, f_d, t1,
                                                   fp64 if fp64 and "time_s" in fp64 else None, verbose))

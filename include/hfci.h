@@ -110,6 +110,13 @@ typedef struct {
                            (stopped ones exit at once); 0 = direct launches sized for the
                            systems still iterating; -1 = graphs when the grid has at most
                            2^16 points                                     default 0 */
+  int inner_precond;    /* the right preconditioner of Alg. 1 step 4 (k_in > 0): 0 = the
+                           regularised Laplacian inverse above, 1 = the learned network
+                           opts->net, the inner steps then being flexible GMRES steps
+                           with z_j = net(v_j) on the remainder: with k_in = 1 the result
+                           is out + beta net(r), r = f - A out, beta minimising the new
+                           remainder, so the network can only lower ||f - A out|| and FCI
+                           stays the preconditioner.  1 needs opts->net.     default 0 */
 } hfci_solve_opts;
 
 /* Counters of one call. */

@@ -194,6 +194,8 @@ static void check_opts(const hfci_solve_opts* o) {
                "harvest_cap > 0 needs harvest_v and harvest_z");
   HFCI_REQUIRE(o->pole_batch >= 0, "pole_batch must be >= 0");
   HFCI_REQUIRE(o->graphs >= -1 && o->graphs <= 1, "graphs must be -1, 0 or 1");
+  HFCI_REQUIRE(o->inner_precond == 0 || o->inner_precond == 1, "inner_precond must be 0 or 1");
+  HFCI_REQUIRE(o->inner_precond == 0 || o->net != nullptr, "inner_precond = 1 needs opts->net");
 }
 
 }  // namespace hfci
@@ -221,6 +223,7 @@ void hfci_default_opts(hfci_solve_opts* o) {
   o->net = nullptr;
   o->learned_tau = 1.0;
   o->learned_patience = 8;
+  o->inner_precond = 0;
   o->harvest_cap = 0;
   o->harvest_v = nullptr;
   o->harvest_z = nullptr;

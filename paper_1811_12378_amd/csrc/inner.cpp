@@ -3,6 +3,8 @@
 // discrete Laplacian M = V diag(1 / max(lambda, 1)) V^T, V the orthonormal sine transform
 // (DST-I) along each axis, which diagonalises the Dirichlet 7-point Laplacian exactly.
 // Returns out + M t with t minimising ||r - A M t|| over K_k(A M, r).  FP64 throughout.
+// With a learned network as the inner preconditioner, the steps are flexible GMRES steps
+// with z_j = net(v_j) (the network is not linear), and the result is out + sum_j t_j z_j.
 //
 // The sine transform is a dense contraction along each axis, run as three complex GEMMs
 // (rocBLAS): along x, S_x X with X the nx x (ny nz) matrix of the grid (x fastest); along
@@ -112,7 +114,7 @@ void inner_release(Ctx& ctx) {
   ctx.sine.clear();
 }
 
-void inner_steps(const Op& op, int k_in, int nrhs, const double2* f, double2* out, FciStats& st) {
+void inner_steps(const Op& op, int k_in, int nrhs, const double2* f, double2* out, FciStats& st, Net* net) {
   Ctx& ctx = *op.ctx;
   hipStream_t s = ctx.stream;
   const size_t n = op.n;
@@ -147,7 +149,10 @@ void inner_steps(const Op& op, int k_in, int nrhs, const double2* f, double2* ou
     auto Hat = [&](int i, int j) -> cd& { return H[(size_t)i * k + j]; };
     int kk = 0;
     for (int j = 0; j < k; ++j) {
-      laplace_inverse(ctx, op.g, V + (size_t)j * n, Z + (size_t)j * n);
+      if (net)
+        net->apply(op, 1, V + (size_t)j * n, Z + (size_t)j * n);
+      else
+        laplace_inverse(ctx, op.g, V + (size_t)j * n, Z + (size_t)j * n);
       double2* w = V + (size_t)(j + 1) * n;
       Launch<double2>::apply(s, op.g, op.kappa64, 0.0, 0.0, 1, Z + (size_t)j * n, w);
       launch_cgs2(s, V, j + 1, n, n, w, part, h1, h2, nrm2);

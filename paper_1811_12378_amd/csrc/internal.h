@@ -288,7 +288,8 @@ void fci_apply(const Op& op, const Contour& c, const hfci_solve_opts& o, int nrh
                double2* out, FciStats& st);
 // inner.cpp: Alg. 1 step 4, k_in GMRES steps on the remainder f - A out (FP64, nrhs
 // vectors), right-preconditioned by the regularised Laplacian inverse; out is updated
-void inner_steps(const Op& op, int k_in, int nrhs, const double2* f, double2* out, FciStats& st);
+// net: the inner preconditioner is this network instead of the Laplacian inverse (NULL: the latter)
+void inner_steps(const Op& op, int k_in, int nrhs, const double2* f, double2* out, FciStats& st, Net* net);
 // y = V diag(1 / max(lambda, 1)) V^T x on the grid g (FP64, x and y distinct)
 void laplace_inverse(Ctx& ctx, const GridDesc& g, const double2* x, double2* y);
 void inner_release(Ctx& ctx);

@@ -567,7 +567,8 @@ void fci_apply(const Op& op, const Contour& c, const hfci_solve_opts& o, int nrh
   } else {
     fci_body<double2>(op, c, o, nrhs, f, out, st);
   }
-  if (o.k_in > 0) inner_steps(op, o.k_in, nrhs, f, out, st);  // Alg. 1 step 4
+  if (o.k_in > 0)  // Alg. 1 step 4
+    inner_steps(op, o.k_in, nrhs, f, out, st, o.inner_precond == 1 ? static_cast<Net*>(o.net) : nullptr);
 }
 
 namespace {

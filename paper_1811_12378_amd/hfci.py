@@ -60,7 +60,8 @@ class SolveOpts(ctypes.Structure):
                 ("precond", ctypes.c_int), ("pole_batch", ctypes.c_int), ("verbose", ctypes.c_int),
                 ("net", ctypes.c_void_p), ("learned_tau", ctypes.c_double), ("learned_patience", ctypes.c_int),
                 ("harvest_cap", ctypes.c_int),
-                ("harvest_v", ctypes.c_void_p), ("harvest_z", ctypes.c_void_p), ("graphs", ctypes.c_int)]
+                ("harvest_v", ctypes.c_void_p), ("harvest_z", ctypes.c_void_p), ("graphs", ctypes.c_int),
+                ("inner_precond", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -1,19 +1,23 @@
 """Training pipeline of the learned preconditioner (all compute in libhfci's kernels).
 
-    python -m paper_1811_12378_amd.learned train --out net.bin [--n 64] [--media 24] [--pairs 48]
+    python -m paper_1811_12378_amd.learned train --out net.bin [--n 128] [--media 42] [--pairs 48]
                                                  [--steps 4000] [--crop 64]
     python -m paper_1811_12378_amd.learned eval --net net.bin [--n 256] [--medium grf|layered]
 
-Pairs: on each random medium (Gaussian random field wavespeed, 10 points per
-wavelength), FGMRES with the FCI preconditioner solves for a random right-hand side
-and hands back every Arnoldi pair (v_j, FCI(v_j)) - the shifted polynomial iteration
-generates the corrections the network learns.  Training: Adam on whole volumes (or
-crops) with a random global phase per step.  FCI(v) = d(v) w(v) where the step size d
-of Alg. 1 is a global complex scalar that a local network cannot see, and FGMRES only
-uses the direction of its search vectors, so the default loss is the scale- and
-phase-invariant 1 - |<o, t>|^2 / (|o|^2 |t|^2).  Use: FGMRES with
-precond = learned keeps the best multiple of N(v_j) when its residual ||v_j - d A N(v_j)|| is
-within tau times FCI's mean residual on the same solve, and falls back to FCI(v_j) otherwise.
+Pairs: on each random medium (Gaussian random field wavespeed, 10 points per wavelength),
+FGMRES with the FCI preconditioner solves for a point source or a random right-hand side
+and hands back every Arnoldi pair (v_j, FCI(v_j)): the shifted polynomial iteration
+generates the data.  Harvest and comparisons use a circular contour of 16 poles with
+eps = 0.25 unless told otherwise.  What the network is trained on, and how it is used:
+
+* "remainder" (the default): the remainder r_j = v_j - d A FCI(v_j) that Alg. 1 steps 1-3
+  leave (d its least-squares multiple), and the residual loss (loss kind 2)
+  min_b ||r - b Ahat N(r)||^2 / ||r||^2.  Inside FGMRES the network is Alg. 1 step 4's
+  inner preconditioner (k_in = 1, inner_precond = 1): FCI(v) + b N(r) with b minimising
+  the new remainder, so the network can only lower it and FCI stays the preconditioner.
+* "arnoldi": the Arnoldi vector v_j itself with the same loss, the network then proposing
+  z = N(v_j) in place of FCI (precond = learned), kept when its scaled residual is within
+  tau of FCI's mean and FCI(v_j) used otherwise.
 """
 from __future__ import annotations
 
@@ -33,8 +37,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def harvest_pairs(ctx, n=64, media=24, pairs=48, J=16, eps=0.25, q=8, ppw=10.0, seed=100):
-    """(v, e, kch, medium_of_pair) on the device from FGMRES runs on `media` random media."""
+def _remainders(op, v, e, batch=8):
+    """r_j = v_j - d_j A e_j with d_j = (A e_j)^H v_j / |A e_j|^2, complex64 like v."""
+    import torch
+    from . import hfci
+    r = torch.empty_like(v)
+    for i in range(0, v.shape[0], batch):
+        vi = v[i:i + batch].to(torch.complex128)
+        ae = hfci.apply(op, e[i:i + batch].to(torch.complex128))
+        a2 = ae.reshape(ae.shape[0], -1)
+        d = (a2.conj() * vi.reshape(vi.shape[0], -1)).sum(1) / (a2.abs() ** 2).sum(1)
+        r[i:i + batch] = (vi - d.reshape((-1,) + (1,) * (vi.dim() - 1)) * ae).to(torch.complex64)
+    return r
+
+
+def harvest_pairs(ctx, n=128, media=42, pairs=48, J=16, eps=0.25, q=8, ppw=10.0, seed=100, target="remainder"):
+    """(x, kch, medium_of_pair) on the device from FGMRES runs on `media` random media; x is
+    the remainder of FCI (target "remainder") or the Arnoldi vector ("arnoldi")."""
     import torch
 
     if ROOT not in sys.path:
@@ -42,8 +61,8 @@ def harvest_pairs(ctx, n=64, media=24, pairs=48, J=16, eps=0.25, q=8, ppw=10.0, 
     import workloads as W
     from . import hfci
 
-    v = torch.empty((media * pairs, n, n, n), dtype=torch.complex64, device="cuda")
-    e = torch.empty_like(v)
+    x = torch.empty((media * pairs, n, n, n), dtype=torch.complex64, device="cuda")
+    e = torch.empty((pairs, n, n, n), dtype=torch.complex64, device="cuda")
     kch = torch.empty((media, n, n, n), dtype=torch.float32, device="cuda")
     mop = np.zeros(media * pairs, dtype=np.int32)
     got = 0
@@ -54,83 +73,95 @@ def harvest_pairs(ctx, n=64, media=24, pairs=48, J=16, eps=0.25, q=8, ppw=10.0, 
         cont = hfci.Contour(op, J, 1.0, eps, q)
         kch[m] = hfci.medium_channel(op)
         if m % 2 == 0:
-            f = W.point_source(n, tuple(int(x) for x in W.source_nodes(n, 1, seed + m, 9)[0]))
+            f = W.point_source(n, tuple(int(v) for v in W.source_nodes(n, 1, seed + m, 9)[0]))
         else:
             f = W.gaussian_rhs(n, seed + 1000 + m)
         fd = torch.from_numpy(f[None]).cuda()
         opts = hfci.default_opts(precision=32, tol=1e-9, max_it=pairs)
         opts.harvest_cap = pairs
-        opts.harvest_v = v[got].data_ptr()
-        opts.harvest_z = e[got].data_ptr()
+        opts.harvest_v = x[got].data_ptr()
+        opts.harvest_z = e.data_ptr()
         _, st = hfci.solve(op, cont, fd, opts=opts)
         k = st["harvested"]
+        if target == "remainder":
+            x[got:got + k] = _remainders(op, x[got:got + k], e[:k])
         mop[got:got + k] = m
         got += k
         log("medium %d: %d pairs (relres %.2e after %d its)" % (m, k, st["final_relres"], st["its"]))
         cont.close()
         op.close()
-    return v[:got], e[:got], kch, mop[:got]
+    del e
+    return x[:got], kch, mop[:got]
 
 
-def train(ctx, out, n=64, media=24, pairs=48, steps=4000, crop=64, lr=1e-3, lr_min=1e-5, seed=0, J=16, eps=0.25,
-          loss_kind=1):
+def train(ctx, out, n=128, media=42, pairs=48, steps=4000, crop=64, lr=1e-3, lr_min=1e-5, seed=0, J=16, eps=0.25,
+          target="remainder", loss_kind=2):
     from . import hfci
     t0 = time.perf_counter()
-    v, e, kch, mop = harvest_pairs(ctx, n=n, media=media, pairs=pairs, J=J, eps=eps)
+    x, kch, mop = harvest_pairs(ctx, n=n, media=media, pairs=pairs, J=J, eps=eps, target=target)
     t1 = time.perf_counter()
     net = hfci.Net(ctx, seed=seed)
-    final, curve = net.train(v, e, kch, mop, crop=crop, steps=steps, lr=lr, lr_min=lr_min, log_every=max(1, steps // 20),
-                             seed=seed, verbose=True, loss_kind=loss_kind)
+    # the residual loss reads only the input (e is not used); the other losses need the
+    # correction as target, which this pipeline no longer keeps
+    if loss_kind != 2:
+        raise ValueError("the pipeline trains with the residual loss (kind 2)")
+    final, curve = net.train(x, x, kch, mop, crop=crop, steps=steps, lr=lr, lr_min=lr_min,
+                             log_every=max(1, steps // 20), seed=seed, verbose=True, loss_kind=loss_kind)
     t2 = time.perf_counter()
     if out:
         net.save(out)
-    info = {"pairs": int(v.shape[0]), "harvest_s": t1 - t0, "train_s": t2 - t1, "final_loss": final,
-            "curve": [float(x) for x in curve], "steps": steps, "crop": crop}
-    del v, e, kch
+    info = {"pairs": int(x.shape[0]), "harvest_n": n, "media": media, "target": target, "harvest_s": t1 - t0,
+            "train_s": t2 - t1, "final_loss": final, "curve": [float(v) for v in curve], "steps": steps,
+            "crop": crop}
+    del x, kch
     return net, info
 
 
-def compare(ctx, net, n=256, medium="grf", seed=777, J=16, eps=0.25, tol=1e-6, taus=(0.9,), max_it=1500,
-            nrhs=1, verbose=1):
-    """Time-to-tol with FCI only versus the learned preconditioner (FCI as fallback)."""
-    import torch
-
+def workload(n, medium, seed, nrhs=1):
     if ROOT not in sys.path:
         sys.path.insert(0, ROOT)
     import workloads as W
+    if medium == "layered":
+        return W.config_layered_256(n=n, nrhs=nrhs, seed=seed)
+    c = W.grf_medium(n, seed)
+    nodes = W.source_nodes(n, nrhs, seed + 5, 9)
+    return W.Workload("grf_%d" % n, c, W.omega_for_ppw(float(c.min()), n, 10.0), 8, 1.0,
+                      [W.point_source(n, p) for p in nodes])
+
+
+def compare(ctx, net, n=256, medium="grf", seed=777, J=16, eps=0.25, tol=1e-6, max_it=1500, nrhs=1, verbose=0,
+            mode="step4", taus=(1.0,), patience=8):
+    """Time-to-tol with FCI alone versus FCI with the network (mode "step4": Alg. 1 step 4
+    with the network as its inner preconditioner; mode "propose": the network's proposal in
+    place of FCI when the arbiter keeps it)."""
+    import torch
     from . import hfci
 
-    if medium == "layered":
-        wl = W.config_layered_256(n=n, nrhs=nrhs, seed=seed)
-    else:
-        c = W.grf_medium(n, seed)
-        nodes = W.source_nodes(n, nrhs, seed + 5, 9)
-        wl = W.Workload("grf_%d" % n, c, W.omega_for_ppw(float(c.min()), n, 10.0), 8, 1.0,
-                        [W.point_source(n, p) for p in nodes])
+    wl = workload(n, medium, seed, nrhs)
     op = hfci.Operator(ctx, torch.from_numpy(wl.c).cuda(), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
+    op.autotune(32, max(2, min(16, 2 * nrhs)))
     cont = hfci.Contour(op, J, 1.0, eps, 8)
     f = torch.from_numpy(np.stack(wl.rhs)).cuda()
-    res = {}
+    res = {"workload": "%s %d^3, %d rhs, contour J %d eps %.4g" % (medium, n, nrhs, cont.J, cont.params()["eps"])}
     hfci.solve(op, cont, f, opts=hfci.default_opts(precision=32, tol=tol, max_it=1))  # allocate
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, st = hfci.solve(op, cont, f, opts=hfci.default_opts(precision=32, tol=tol, max_it=max_it, verbose=verbose))
-    torch.cuda.synchronize()
-    res["fci"] = dict(st, time_s=time.perf_counter() - t0)
-    log("fci only: %.2f s, %d its, relres %.2e" % (res["fci"]["time_s"], st["its"], st["final_relres"]))
-    for tau in taus:
-        o = hfci.default_opts(precision=32, tol=tol, max_it=max_it, precond=2, learned_tau=tau, verbose=verbose)
+    runs = [("fci", hfci.default_opts(precision=32, tol=tol, max_it=max_it, verbose=verbose))]
+    if mode == "step4":
+        o = hfci.default_opts(precision=32, tol=tol, max_it=max_it, verbose=verbose, k_in=1, inner_precond=1)
         o.net = net.h.value
+        runs.append(("fci+net_step4", o))
+    else:
+        for tau in taus:
+            o = hfci.default_opts(precision=32, tol=tol, max_it=max_it, precond=2, learned_tau=tau,
+                                  verbose=verbose, learned_patience=patience)
+            o.net = net.h.value
+            runs.append(("net_proposal_tau_%g" % tau, o))
+    for name, o in runs:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, st = hfci.solve(op, cont, f, opts=o)
         torch.cuda.synchronize()
-        res["learned_tau_%g" % tau] = dict(st, time_s=time.perf_counter() - t0)
-        log("learned tau %g: %.2f s, %d its (%d kept, %d fallbacks), relres %.2e, net %.0f ms, "
-            "mean scaled residual net %.3f / fci %.3f"
-            % (tau, res["learned_tau_%g" % tau]["time_s"], st["its"], st["learned_accepted"],
-               st["learned_fallbacks"], st["final_relres"], st["time_net_ms"], st["net_rho_mean"],
-               st["fci_rho_mean"]))
+        res[name] = dict(st, time_s=time.perf_counter() - t0)
+        log("%s: %.2f s, %d its, relres %.2e" % (name, res[name]["time_s"], st["its"], st["final_relres"]))
     cont.close()
     op.close()
     return res
@@ -141,29 +172,31 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("train")
     t.add_argument("--out", required=True)
-    t.add_argument("--n", type=int, default=64)
-    t.add_argument("--media", type=int, default=24)
+    t.add_argument("--n", type=int, default=128)
+    t.add_argument("--media", type=int, default=42)
     t.add_argument("--pairs", type=int, default=48)
     t.add_argument("--steps", type=int, default=4000)
     t.add_argument("--crop", type=int, default=64)
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--target", default="remainder", choices=["remainder", "arnoldi"])
     e = sub.add_parser("eval")
     e.add_argument("--net", required=True)
     e.add_argument("--n", type=int, default=256)
     e.add_argument("--medium", default="grf")
-    e.add_argument("--taus", type=float, nargs="+", default=[0.9])
+    e.add_argument("--mode", default="step4", choices=["step4", "propose"])
+    e.add_argument("--taus", type=float, nargs="+", default=[1.0])
     a = ap.parse_args(argv)
     from . import hfci
     ctx = hfci.Context(0)
     if a.cmd == "train":
         _, info = train(ctx, a.out, n=a.n, media=a.media, pairs=a.pairs, steps=a.steps, crop=a.crop, lr=a.lr,
-                        seed=a.seed)
+                        seed=a.seed, target=a.target)
         print(json.dumps(info))
     else:
         net = hfci.Net(ctx)
         net.load(a.net)
-        print(json.dumps(compare(ctx, net, n=a.n, medium=a.medium, taus=a.taus), default=float))
+        print(json.dumps(compare(ctx, net, n=a.n, medium=a.medium, mode=a.mode, taus=a.taus), default=float))
 
 
 if __name__ == "__main__":
