@@ -202,8 +202,11 @@ hfci_status hfci_op_info(const hfci_op* op, double* out7);
  *           ty = 8) = as 1 for the two-factor passes, but every plane of every stream
  *           is loaded from HBM straight into a ring of P + 2 LDS slots (P = 2 planes
  *           ahead for pd = 2, 4 for pd = 3) without passing through registers, so
- *           more planes are in flight; single factors, and two-factor passes on grids with an odd nx
- *           or vectors of 2 GiB or more, run as kern 1;
+ *           more planes are in flight; single factors, and two-factor passes on
+ *           grids with an odd nx or vectors of 2 GiB or more, run as kern 1;
+ *           3 (HFCI_F32 only, fuse = 1, ty = 8, pd = 2) = as 2, with the middle
+ *           two-factor passes on 64 x 28 output tiles (the input halo and kappa then
+ *           cost less per output point; one 1024-thread block per CU);
  *   tune[1] ty:   the thread tile is 64 x ty (4 or 8);
  *   tune[2] pd:   HBM streams are issued pd planes ahead (kern 0: 1 or 2;
  *                 kern 1: 1..3 with ty = 4, 2..3 with ty = 8);

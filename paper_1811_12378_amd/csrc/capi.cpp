@@ -479,9 +479,9 @@ hfci_status hfci_op_set_tune(hfci_op* op, int prec, const int* t3) {
   t.fuse = t3[4];
   t.sg = t3[5];
   HFCI_REQUIRE(tune_valid(t), "tune must be {0, ty in {4, 8}, pd in {1, 2}, cz, fuse, sg} or {1, 4, pd in 1..3, cz, "
-                              "fuse, sg} or {1, 8, pd in {2, 3}, cz, fuse, sg}, cz in [0, 4096], fuse in {0, 1}, "
-                              "sg in [1, 16]");
-  HFCI_REQUIRE(t.kern != 2 || prec == HFCI_F32, "kern 2 (streams loaded into LDS) is a complex64 kernel");
+                              "fuse, sg} or {1, 8, pd in {2, 3}, cz, fuse, sg} or {2, 8, pd in {2, 3}, cz, 1, sg} or "
+                              "{3, 8, 2, cz, 1, sg}, cz in [0, 4096], fuse in {0, 1}, sg in [1, 16]");
+  HFCI_REQUIRE(t.kern < 2 || prec == HFCI_F32, "kerns 2 and 3 (streams loaded into LDS) are complex64 kernels");
   (prec == HFCI_F32 ? op->g.tune32 : op->g.tune64) = t;
   return HFCI_OK;
   HFCI_API_END

@@ -425,14 +425,15 @@ KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, d
   }
   // two factors per pass (its own 64 x 12 tiles; per-factor time = half a launch), with
   // the systems of a launch taken one, two or four at a time tile by tile
-  // (kern 2: the complex64 pair kernel whose streams are loaded straight into LDS)
+  // (kern 2: the complex64 pair kernel whose streams are loaded straight into LDS; kern 3:
+  // the same with 64 x 28 tiles for the middle pairs, two planes ahead only)
   if (Launch<T2>::pair_fits(op.g))
-    for (int kern : {1, 2}) {
-      if (kern == 2 && sizeof(T2) != 8) continue;
+    for (int kern : {1, 2, 3}) {
+      if (kern >= 2 && sizeof(T2) != 8) continue;
       for (int cz : {0, 16, 64})
         for (int pd : {2, 3})
           for (int sg : {1, 2, 4})
-            if (sg == 1 || sg <= nsys) cands.push_back(KernelTune{kern, 8, pd, cz, 1, sg});
+            if ((sg == 1 || sg <= nsys) && !(kern == 3 && pd != 2)) cands.push_back(KernelTune{kern, 8, pd, cz, 1, sg});
     }
   hipEvent_t e0, e1;
   HFCI_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));

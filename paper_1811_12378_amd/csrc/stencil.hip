@@ -1015,6 +1015,253 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(dma_waves_p
   pair_tile_dma<KIND, P>(g, czlen, gx, gy, per_sys, s, b, a, K);
 }
 
+// ---- the middle pair on tall tiles (kern 3) ----
+// The same two factors and the same streams-into-LDS ring as zpair_dma_kernel, on a
+// 64 x 28 output tile (first factor on 66 x 30, input 68 x 32), so the halo rows cost
+// 1.21x the output's input bytes instead of 1.42x and kappa 1.10x instead of 1.20x.
+// 1024 threads; thread t < 990 owns column ex = t % 66 of two row bands, first-factor
+// rows ey = t / 66 and ey + 15, and the second factor at the same two points when they
+// lie in the core.  Threads 990..1023 only load and write their first-factor values to
+// pad entries.  Middle kind only (no extra stream, no residual, one output); the LDS
+// (four 25.6 KB ring slots and a 32 KB first-factor ring) holds one block per CU.
+constexpr int QH = 15;                         // first-factor rows per band
+constexpr int QX = 64, QY = 2 * QH - 2;        // 64 x 28 output tile
+constexpr int QEX = QX + 2, QEY = QY + 2;      // 66 x 30 first-factor tile
+constexpr int QIX = QX + 4, QIY = QY + 4;      // 68 x 32 input tile
+constexpr int QNT = 1024;                      // 16 waves
+constexpr int QUSED = QEX * QH;                // 990 threads with points
+constexpr int QIP = QIX * QIY / 2;             // 1088 input pairs per plane
+constexpr int QIPW = QIP / (QNT / 64) / 2;     // 34 pairs per wave and instruction (two of them)
+constexpr int QKE = 2048;                      // kappa / first-factor entries per plane (1980 used)
+static_assert(QIPW * 2 * (QNT / 64) == QIP, "input pairs split evenly over the waves");
+static_assert(QEX * QEY + 2 * (QNT - QUSED) <= QKE, "the idle threads' pad entries fit");
+struct QSlot {
+  static constexpr int kIn = 0, kKap = QIP * 16, kBytes = kKap + QKE * 4;
+};
+
+struct QTile {
+  BufRsrc rX, rK, rO;
+  uint32_t pb, pbk;
+  uint32_t din0, din1, dk0, dk1;  // this lane's input pairs and kappa entries (byte offsets)
+  uint32_t ost[2];                // output points, or kOOB
+  int nz, zb, ze, damp_cells, wave;
+  int c0[2], f[2], fc[2];         // input-tile centre, first-factor entry, clamped core entry
+  bool live[2];                   // first-factor point inside the grid
+  float a1r, a1i, b1r, b1i, a2r, a2i, b2r, b2i, sh2, dsc, diag0, sim, dampxy[2];
+};
+
+// fill a ring slot: input plane kin and kappa plane kk (zeros outside the grid or past what
+// the chunk reads, from out-of-range offsets)
+__device__ __forceinline__ void qfill(const QTile& d, int kin, int kk, unsigned char* sl) {
+  auto clampz = [&](int kp) { return (uint32_t)min(max(kp, 0), d.nz - 1); };
+  const bool zin = kin >= 0 && kin < d.nz && kin <= d.ze + 1;
+  const bool zk = kk >= 0 && kk < d.nz && kk <= d.ze;
+  const uint32_t sin = __builtin_amdgcn_readfirstlane(d.pb * clampz(kin));
+  const uint32_t sk = __builtin_amdgcn_readfirstlane(d.pbk * clampz(kk));
+  const int lane = threadIdx.x & 63;
+  if (lane < QIPW) {
+    unsigned char* b = sl + QSlot::kIn + 16 * (2 * QIPW) * d.wave;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rX, (lds_void*)b, 16, zin ? d.din0 : kOOB, sin, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rX, (lds_void*)(b + 16 * QIPW), 16, zin ? d.din1 : kOOB, sin, 0, 0);
+  }
+  unsigned char* kb = sl + QSlot::kKap + 4 * 128 * d.wave;
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rK, (lds_void*)kb, 4, zk ? d.dk0 : kOOB, sk, 0, 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rK, (lds_void*)(kb + 4 * 64), 4, zk ? d.dk1 : kOOB, sk, 0, 0);
+}
+
+// plane k: refill sN; first factor at plane k for both points from sK (input plane k,
+// kappa of plane k - 1) and sP (input plane k + 1, kappa of plane k) into tw; second factor
+// at plane k - 1 from tq (first factor of plane k - 1), the z-column registers and tw's own
+// values, stored to HBM.
+template <int P>
+__device__ __forceinline__ void qstep(const QTile& d, int k, unsigned char* __restrict__ sN,
+                                      const unsigned char* __restrict__ sK, const unsigned char* __restrict__ sP,
+                                      float2* __restrict__ tw, const float2* __restrict__ tq, float2 (&cm)[2],
+                                      float2 (&cc)[2], float2 (&tm)[2], float2 (&t0)[2]) {
+  using T = float;
+  using T2 = float2;
+  auto clampz = [&](int kp) { return (uint32_t)min(max(kp, 0), d.nz - 1); };
+  auto dampz = [&](int kp) {
+    const int dz = layer_depth(kp, d.nz, d.damp_cells);
+    return (T)(dz * dz) * d.dsc;
+  };
+  qfill(d, k + 1 + P, k + P, sN);
+  const T2* cp = (const T2*)(sK + QSlot::kIn);
+  const T2* pp = (const T2*)(sP + QSlot::kIn);
+  const T* kP = (const T*)(sP + QSlot::kKap);
+  const T* kK = (const T*)(sK + QSlot::kKap);
+  const T dzk = dampz(k), dzm = dampz(k - 1);
+  T2 tv[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c0 = d.c0[h];
+    const T2 cen = cc[h], zp = pp[c0], zm = cm[h];
+    const T2 xm = cp[c0 - 1], xp = cp[c0 + 1], ym = cp[c0 - QIX], yp = cp[c0 + QIX];
+    const T dre = d.diag0 - kP[d.f[h]];
+    const T dim = -(max(d.dampxy[h], dzk) + d.sim);
+    const T nbr = ((zm.x + zp.x) + (xm.x + xp.x)) + (ym.x + yp.x);
+    const T nbi = ((zm.y + zp.y) + (xm.y + xp.y)) + (ym.y + yp.y);
+    T2 Sx;
+    Sx.x = dre * cen.x - dim * cen.y - d.sh2 * nbr;
+    Sx.y = dre * cen.y + dim * cen.x - d.sh2 * nbi;
+    const bool live = d.live[h] && k >= 0 && k < d.nz;
+    tv[h].x = live ? d.a1r * Sx.x - d.a1i * Sx.y + d.b1r * cen.x - d.b1i * cen.y : (T)0;
+    tv[h].y = live ? d.a1r * Sx.y + d.a1i * Sx.x + d.b1r * cen.y + d.b1i * cen.x : (T)0;
+    tw[d.f[h]] = tv[h];
+    cm[h] = cen;
+    cc[h] = zp;
+  }
+  const int km = k - 1;
+  const uint32_t po = __builtin_amdgcn_readfirstlane(d.pb * clampz(km));
+  const bool zok = km >= d.zb && km < d.ze;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int fc = d.fc[h];
+    const T2 cen2 = t0[h];
+    const T2 xm2 = tq[fc - 1], xp2 = tq[fc + 1], ym2 = tq[fc - QEX], yp2 = tq[fc + QEX];
+    const T2 zm2 = tm[h], zp2 = tv[h];
+    const T dre2 = d.diag0 - kK[d.f[h]];
+    const T dim2 = -(max(d.dampxy[h], dzm) + d.sim);
+    const T nbr2 = ((zm2.x + zp2.x) + (xm2.x + xp2.x)) + (ym2.x + yp2.x);
+    const T nbi2 = ((zm2.y + zp2.y) + (xm2.y + xp2.y)) + (ym2.y + yp2.y);
+    T2 S2;
+    S2.x = dre2 * cen2.x - dim2 * cen2.y - d.sh2 * nbr2;
+    S2.y = dre2 * cen2.y + dim2 * cen2.x - d.sh2 * nbi2;
+    T2 o;
+    o.x = d.a2r * S2.x - d.a2i * S2.y + d.b2r * cen2.x - d.b2i * cen2.y;
+    o.y = d.a2r * S2.y + d.a2i * S2.x + d.b2r * cen2.y + d.b2i * cen2.x;
+    buf_store<T2>(d.rO, zok ? d.ost[h] : kOOB, po, o);
+    tm[h] = t0[h];
+    t0[h] = tv[h];
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void pair_tile_tall(const GridDesc& g, int czlen, int gx, int gy, int s, int b,
+                                               const FactorArgs<float2>& a, const float* __restrict__ K) {
+  using T = float;
+  using T2 = float2;
+  constexpr int R = P + 2;
+  constexpr int V = 2 + 2 + 2;  // memory instructions per plane: input, kappa, the two stores
+  static_assert(P == 2, "prefetch depth 2 (four slots fill the LDS)");
+  constexpr int SB = QSlot::kBytes;
+  __shared__ __align__(16) unsigned char sl0[SB], sl1[SB], sl2[SB], sl3[SB];
+  __shared__ __align__(16) T2 ts0[QKE], ts1[QKE];
+  auto slot = [&](int r) -> unsigned char* { return r == 0 ? sl0 : r == 1 ? sl1 : r == 2 ? sl2 : sl3; };
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int bx = b % gx, by = (b / gx) % gy, zc = b / (gx * gy);
+  const int x0 = bx * QX, y0 = by * QY;
+  QTile d;
+  d.wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  d.nz = g.nz;
+  d.damp_cells = g.damp_cells;
+  d.zb = zc * czlen;
+  d.ze = min(g.nz, d.zb + czlen);
+  const int zb = d.zb, ze = d.ze;
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  const size_t plane = (size_t)g.nx * (size_t)g.ny;
+  const int gsys = a.sys0 + s;
+  const int pole = gsys / a.nrhs;
+  const FactorCoef c1 = a.coef[pole * a.cstride + a.k], c2 = a.coef[pole * a.cstride + a.k + 1];
+  const PoleDev pd = a.poles[pole];
+  d.a1r = (T)c1.a_re, d.a1i = (T)c1.a_im, d.b1r = (T)c1.b_re, d.b1i = (T)c1.b_im;
+  d.a2r = (T)c2.a_re, d.a2i = (T)c2.a_im, d.b2r = (T)c2.b_re, d.b2i = (T)c2.b_im;
+  const T2* __restrict__ X = a.win + (size_t)s * n;
+  T2* __restrict__ O = a.wout + (size_t)s * n;
+  d.sh2 = (T)g.s_h2;
+  d.dsc = (T)g.damp_scale;
+  d.diag0 = (T)6 * d.sh2 - (T)pd.z0_re;
+  d.sim = (T)pd.z0_im;
+  d.pb = (uint32_t)(plane * sizeof(T2));
+  d.pbk = (uint32_t)(plane * sizeof(T));
+  d.rX = buf_rsrc_n(X, n * sizeof(T2));
+  d.rK = buf_rsrc_n(K, n * sizeof(T));
+  d.rO = buf_rsrc_n(O, n * sizeof(T2));
+
+  // input duty: pairs p = wave * 68 + lane and p + 34 (lanes < 34) hold entries 2p, 2p + 1
+  // of the 68 x 32 input tile (68 is even and so are x0 and nx: a pair lies in one row,
+  // inside the grid or outside it as a whole)
+  auto pair_off = [&](int p) -> uint32_t {
+    const int e0 = 2 * p;
+    const int ix = x0 - 2 + e0 % QIX, iy = y0 - 2 + e0 / QIX;
+    return (lane < QIPW && ix >= 0 && ix < g.nx && iy >= 0 && iy < g.ny) ? (uint32_t)((ix + g.nx * iy) * sizeof(T2))
+                                                                          : kOOB;
+  };
+  d.din0 = pair_off(d.wave * 2 * QIPW + lane);
+  d.din1 = pair_off(d.wave * 2 * QIPW + QIPW + lane);
+  // kappa duty: entries e = wave * 128 + lane and e + 64 of the 66 x 30 first-factor tile
+  auto kap_off = [&](int e) -> uint32_t {
+    const int kx = x0 - 1 + e % QEX, ky = y0 - 1 + e / QEX;
+    return (e < QEX * QEY && kx >= 0 && kx < g.nx && ky >= 0 && ky < g.ny) ? (uint32_t)((kx + g.nx * ky) * sizeof(T))
+                                                                           : kOOB;
+  };
+  d.dk0 = kap_off(d.wave * 128 + lane);
+  d.dk1 = kap_off(d.wave * 128 + 64 + lane);
+  // the thread's two first-factor points: rows ey and ey + QH of column ex (threads past
+  // QUSED compute on clamped points and write their values to pad entries)
+  const bool used = tid < QUSED;
+  const int ex = used ? tid % QEX : (tid - QUSED) % QEX;
+  const int eyb = used ? tid / QEX : QH - 1;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int ey = eyb + h * QH;
+    const int xe = x0 - 1 + ex, ye = y0 - 1 + ey;
+    const bool in = xe >= 0 && xe < g.nx && ye >= 0 && ye < g.ny;
+    d.live[h] = used && in;
+    const bool core = d.live[h] && ex >= 1 && ex <= QX && ey >= 1 && ey <= QY;
+    d.ost[h] = core ? (uint32_t)((xe + g.nx * ye) * sizeof(T2)) : kOOB;
+    d.c0[h] = (ey + 1) * QIX + ex + 1;
+    d.f[h] = used ? ey * QEX + ex : QEX * QEY + 2 * (tid - QUSED) + h;
+    d.fc[h] = min(max(ey, 1), QY) * QEX + min(max(ex, 1), QX);
+    const int dxy = max(layer_depth(xe, g.nx, g.damp_cells), layer_depth(ye, g.ny, g.damp_cells));
+    d.dampxy[h] = (T)(dxy * dxy) * d.dsc;
+  }
+
+  if (zb < ze) {
+    // prologue as in pair_tile_dma: slot j gets input plane zb-2+j and kappa plane zb-3+j
+#pragma unroll
+    for (int j = 0; j < R; ++j) qfill(d, zb - 2 + j, zb - 3 + j, slot(j));
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    T2 cm[2], cc[2], tm[2], t0[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      cm[h] = ((const T2*)sl0)[d.c0[h]];
+      cc[h] = ((const T2*)sl1)[d.c0[h]];
+      tm[h] = T2{(T)0, (T)0};
+      t0[h] = T2{(T)0, (T)0};
+    }
+    const int len = ze - zb + 2;
+    const int lenp = (len + R - 1) / R * R;
+    for (int r0 = 0; r0 < lenp; r0 += R) {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int k = zb - 1 + r0 + u;
+        const bool odd = (u & 1) != 0;
+        wait_vm_lgkm0<(P - 1) * V>();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        qstep<P>(d, k, slot(u), slot((u + 1) % R), slot((u + 2) % R), odd ? ts1 : ts0, odd ? ts0 : ts1, cm, cc, tm,
+                 t0);
+      }
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
+__global__ __launch_bounds__(QNT) __attribute__((amdgpu_waves_per_eu(4))) void zpair_tall_kernel(
+    GridDesc g, int nzc, int czlen, int xcd_slab, int sgrp, FactorArgs<float2> a, const float* __restrict__ K) {
+  const int gx = (g.nx + QX - 1) / QX, gy = (g.ny + QY - 1) / QY;
+  const int per_sys = gx * gy * nzc;
+  int s, b;
+  if (!pair_block(xcd_slab, sgrp, per_sys, a.list, a.count, s, b)) return;  // uniform
+  pair_tile_tall<2>(g, czlen, gx, gy, s, b, a, K);
+}
+
 // Uneven batches, two factors per pass: as zmulti_kernel, with the pair tile of the
 // block's system on its operator's pair geometry (pgx x pgy x pnzc tiles).
 template <typename T, int KIND>
@@ -1335,8 +1582,8 @@ void run(hipStream_t st, const GridDesc& g, int nsys, const Epi& epi) {
   if (nsys <= 0) return;
   const Shape sh = shape_for<T>(g, nsys);
   const KernelTune& t = tune_of<T>(g);
-  // kern 2 changes the pair launches only: single factors run the LDS-staged kernel
-  const int key = (t.kern == 2 ? 1 : t.kern) * 100 + t.ty * 10 + t.pd;
+  // kerns 2 and 3 change the pair launches only: single factors run the LDS-staged kernel
+  const int key = (t.kern >= 2 ? 1 : t.kern) * 100 + t.ty * 10 + t.pd;
   switch (key) {
     case 141:
       hipLaunchKernelGGL((zlds_kernel<T, Epi, 4, 1>), sh.grid, sh.block, 0, st, g, sh.nzc, sh.czlen, sh.xcd_slab, epi);
@@ -1394,15 +1641,41 @@ PairShape pair_shape(const GridDesc& g) {
   return p;
 }
 
+// geometry of the tall-tile middle pair (kern 3)
+PairShape tall_shape(const GridDesc& g, int cz) {
+  PairShape p;
+  p.gx = (g.nx + QX - 1) / QX;
+  p.gy = (g.ny + QY - 1) / QY;
+  if (cz <= 0) {
+    cz = 32;
+    while (cz > 8 && (long)p.gx * p.gy * ((g.nz + cz - 1) / cz) < 256) cz /= 2;
+  }
+  p.czlen = cz;
+  p.nzc = (g.nz + cz - 1) / cz;
+  p.per_sys = p.gx * p.gy * p.nzc;
+  p.xcd_slab = (p.per_sys % 8 == 0 && p.per_sys >= 64) ? p.per_sys / 8 : 0;
+  return p;
+}
+
 template <typename T, int KIND, typename T2>
 void run_pair(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a) {
   if (a.count <= 0) return;
+  const int sgrp = tune_of<T>(g).sg;
+  if constexpr (sizeof(T) == 4 && KIND == 0) {
+    // kern 3: the middle pair on 64 x 28 tiles (complex64, an even nx, vectors under 2 GiB)
+    if (tune_of<T>(g).kern == 3 && dma_pair_fits(g)) {
+      const PairShape q = tall_shape(g, tune_of<T>(g).cz);
+      hipLaunchKernelGGL(zpair_tall_kernel, dim3((unsigned)q.per_sys * (unsigned)a.count), dim3(QNT), 0, st, g,
+                         q.nzc, q.czlen, q.xcd_slab, sgrp, a, (const float*)kappa);
+      return;
+    }
+  }
   const PairShape p = pair_shape<T>(g);
   const dim3 grid((unsigned)p.per_sys * (unsigned)a.count);
-  const int sgrp = tune_of<T>(g).sg;
   if constexpr (sizeof(T) == 4) {
-    // the streams-into-LDS pair kernel: complex64, an even nx, vectors under 2 GiB
-    if (tune_of<T>(g).kern == 2 && dma_pair_fits(g)) {
+    // the streams-into-LDS pair kernel: complex64, an even nx, vectors under 2 GiB (kern 3
+    // uses it for the other pair kinds)
+    if ((tune_of<T>(g).kern == 2 || tune_of<T>(g).kern == 3) && dma_pair_fits(g)) {
       // prefetch depth P (planes ahead): pd 2 -> 2 (the kinds without an extra stream then
       // fit two blocks per CU), pd 3 -> 4 (one block per CU)
       if (tune_of<T>(g).pd >= 3)
@@ -1430,6 +1703,7 @@ bool tune_valid(const KernelTune& t) {
   if (t.kern == 0) return t.pd == 1 || t.pd == 2;
   if (t.kern == 1) return (t.ty == 4 && t.pd >= 1 && t.pd <= 3) || (t.ty == 8 && (t.pd == 2 || t.pd == 3));
   if (t.kern == 2) return t.fuse == 1 && t.ty == 8 && (t.pd == 2 || t.pd == 3);
+  if (t.kern == 3) return t.fuse == 1 && t.ty == 8 && t.pd == 2;
   return false;
 }
 

@@ -164,13 +164,55 @@ def test_streams_into_lds_match_the_register_pair_kernel(ctx, q, steps, pd, cz):
             assert relmax(out[2][j, r], ref) <= bar, (j, r)
 
 
-def test_streams_into_lds_adaptive(ctx):
-    # adaptive stopping in FP32 with kern 2: each system stops within one step of the
+TALL_SHAPE = (90, 70, 100)  # ragged in x (64 + 36), y (28 + 28 + 14) and z (11 x 8 + 2)
+
+
+def tall_tiles(shape, cz):
+    nz, ny, nx = shape
+    return -(-nx // 64) * -(-ny // 28) * -(-nz // cz)
+
+
+@pytest.mark.parametrize("q,steps", KIND_CASES + [(3, 3)])
+@pytest.mark.parametrize("cz,sg", [(8, 3), (0, 1)])
+def test_tall_tiles_match_the_oracle_and_the_register_kernel(ctx, q, steps, cz, sg):
+    # kern 3: the middle pairs on 64 x 28 tiles (the other pair kinds as kern 2), at a
+    # geometry whose tall tiles split into XCD slabs (72 per system with cz 8), groups of
+    # systems taken sg at a time, every kind of pair launch; each result within the FP32
+    # bar of the oracle and within twice it of the register pair kernel
+    assert tall_tiles(TALL_SHAPE, 8) == 72
+    rng = np.random.default_rng(81)
+    c = rng.uniform(1.0, 3.0, size=TALL_SHAPE)
+    h = 1.0 / 100
+    o, g = OO.Operator(c, 30.0, 3, 1.0, h=h), hf.Operator(ctx, dev(c), h, 30.0, 3, 1.0)
+    poles = OF.pole_parameters(o, 4, 1.0, 0.5, q)
+    cg = hf.Contour(g, 4, 1.0, 0.5, q, z=[p.z for p in poles], sigma=[p.sigma for p in poles],
+                    delta=[p.delta for p in poles])
+    fh = round32(rng.standard_normal((2,) + TALL_SHAPE) + 1j * rng.standard_normal((2,) + TALL_SHAPE))
+    f = dev(fh).to(torch.complex64)
+    out = {}
+    for kern in (1, 3):
+        g.set_tune(32, kern, 8, 2, cz, 1, sg)
+        assert g.get_tune(32) == (kern, 8, 2, cz, 1, sg)
+        y, st = hf.shifted_solve(g, cg, f, steps=steps)
+        assert np.all(st == steps)
+        out[kern] = host(y).astype(np.complex128)
+    Am = lambda v, sh: o.apply(v, sh)
+    for j, p in enumerate(poles):
+        for r in range(2):
+            ref, _ = OFP.fixed_point_solve(Am, fh[r], p.z, p.z0, p.delta, q, steps=steps)
+            bar = tol_of("f32", o, p, q, steps, fh[r], ref)
+            assert relmax(out[3][j, r], ref) <= bar, (j, r, relmax(out[3][j, r], ref), bar)
+            assert np.abs(out[3][j, r] - out[1][j, r]).max() <= 2 * bar * np.abs(ref).max(), (j, r)
+
+
+@pytest.mark.parametrize("kern", [2, 3])
+def test_streams_into_lds_adaptive(ctx, kern):
+    # adaptive stopping in FP32 with kerns 2 and 3: each system stops within one step of the
     # oracle's count (an FP32 residual can land on the other side of the threshold), its
     # iterate is the oracle's after the steps it took, within the FP32 bar, and it meets the
     # stopping rule; a zero right-hand side stops at once
     o, g, rng = slab_operator(ctx, seed=79)
-    g.set_tune(32, 2, 8, 2, 8, 1, 3)
+    g.set_tune(32, kern, 8, 2, 8, 1, 3)
     q = 8
     poles = OF.pole_parameters(o, 4, 1.0, 0.5, q)
     cg = hf.Contour(g, 4, 1.0, 0.5, q, z=[p.z for p in poles], sigma=[p.sigma for p in poles],
@@ -217,7 +259,7 @@ def layered(n, nrhs):
     return W.config_layered_256(n=n, nrhs=nrhs)
 
 
-@pytest.mark.parametrize("kern,pd", [(1, 2), (2, 2), (2, 3)])
+@pytest.mark.parametrize("kern,pd", [(1, 2), (2, 2), (2, 3), (3, 2)])
 def test_headline_shape_lockstep_256(ctx, kern, pd):
     # the benchmark's workload and fused complex64 shapes: 2 of its 16 poles (the one
     # nearest the origin, the slowest, and one across the contour) x 2 of its point
