@@ -84,6 +84,21 @@ def measured_traffic(shape):
     return d["bytes_per_launch"] / d["alg_bytes_per_launch"]
 
 
+def middle_kernel_name(t):
+    """The library's kernel for the middle factors of a fixed-point step at launch shape t."""
+    kern, ty, pd, _, fuse = t[:5]
+    if fuse and kern == 3:
+        return ("zpair_tall_kernel (two middle factors of a fixed-point step per pass on 64 x 28 tiles, "
+                "streams loaded straight into LDS)")
+    if fuse and kern == 2:
+        return ("zpair_dma_kernel<0, %d> (two middle factors of a fixed-point step per pass, streams loaded "
+                "straight into LDS)" % (4 if pd >= 3 else 2))
+    if fuse:
+        return "zpair_kernel<float, 0, %d> (two middle factors of a fixed-point step per pass)" % (2 if pd >= 3 else 1)
+    return "%s<float, EpiFactor<float, 0>, %d, %d> (middle factor of a fixed-point step)" % (
+        "zlds_kernel" if kern == 1 else "zmarch_kernel", ty, pd)
+
+
 def host_description():
     """CPU model, logical core count and the thread settings that could change the oracle's speed."""
     model = None
@@ -846,14 +861,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_over_alg": round(traffic_ratio, 4) if traffic_ratio else None,
-                     "kernel": (("zpair_dma_kernel<0, %d> (two middle factors of a fixed-point step per pass, "
-                                 "streams loaded straight into LDS)" % (4 if tune32[2] >= 3 else 2))
-                                if tune32[4] and tune32[0] == 2 else
-                                "zpair_kernel<float, 0, %d> (two middle factors of a fixed-point step per pass)"
-                                % (2 if tune32[2] >= 3 else 1)
-                                if tune32[4] else
-                                "%s<float, EpiFactor<float, 0>, %d, %d> (middle factor of a fixed-point step)"
-                                % ("zlds_kernel" if tune32[0] == 1 else "zmarch_kernel", tune32[1], tune32[2])),
+                     "kernel": middle_kernel_name(tune32),
                      "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": bytes_per_launch,
                      "launches": stage["launches"], "timed_every": args.profile_every},
         "cpu_baseline": cpu,
