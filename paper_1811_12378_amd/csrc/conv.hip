@@ -209,6 +209,86 @@ __global__ __launch_bounds__(256) void zconv16_kernel(Dims d, View in, const uin
   }
 }
 
+// 48 -> 16 channel layer (the full-resolution decoder's first convolution, on the
+// concatenation of the upsampled coarse features and the skip connection) as a z-marching
+// implicit GEMM.  As zconv16, but the 48-channel planes are too large for a 64 x 4 tile to
+// leave room for two blocks per CU: a block owns a 32 x 4 tile, its input planes (34 x 6
+// voxels with the halo, 48 channels padded to 56 per voxel, so 16-byte rows stay aligned)
+// sit in a 3-plane LDS ring (68.5 KB), and the weights (27 x 16 x 48, the same for every
+// block) are read through the L1 cache.  Wave w computes row y0 + w: two 16-voxel blocks,
+// one 16x16x16 MFMA per (tap, 16-channel chunk, block), weights as A and input as B.
+constexpr int ZDX = 32, ZDY = 4, ZDLX = ZDX + 2, ZDLY = ZDY + 2, ZDC = 48, ZDCP = 56;
+
+__global__ __launch_bounds__(256) void zconv48_kernel(Dims d, View in, const uint16_t* __restrict__ w,
+                                                      const float* __restrict__ bias, int relu, View out, int zlen) {
+  __shared__ __align__(16) uint16_t ring[3][ZDLY][ZDLX][ZDCP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gx = (d.x + ZDX - 1) / ZDX, gy = (d.y + ZDY - 1) / ZDY;
+  const int b = blockIdx.x;
+  const int bx = b % gx, by = (b / gx) % gy, zc = b / (gx * gy);
+  const int x0 = bx * ZDX, y0 = by * ZDY;
+  const int zb = zc * zlen, ze = min(d.z, zb + zlen);
+  if (zb >= ze) return;
+  constexpr int PARTS = ZDC / 8;  // 16-byte pieces per voxel
+  auto load_plane = [&](int zp) {
+    uint16_t(*dst)[ZDLX][ZDCP] = ring[(zp + 3) % 3];
+    for (int c = threadIdx.x; c < ZDLY * ZDLX * PARTS; c += 256) {
+      const int vox = c / PARTS, part = c % PARTS;
+      const int lx = vox % ZDLX, ly = vox / ZDLX;
+      const int xg = x0 - 1 + lx, yg = y0 - 1 + ly;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (zp >= 0 && zp < d.z && xg >= 0 && xg < d.x && yg >= 0 && yg < d.y)
+        v = *reinterpret_cast<const uint4*>(in.p + (((long)zp * d.y + yg) * d.x + xg) * in.cs + in.off + part * 8);
+      *reinterpret_cast<uint4*>(&dst[ly][lx][part * 8]) = v;
+    }
+  };
+  load_plane(zb - 1);
+  load_plane(zb);
+  const int row = lane & 15, kq = lane >> 4;
+  const int yo = y0 + wave;
+  float bv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) bv[r] = bias ? bias[4 * kq + r] : 0.f;
+  for (int z = zb; z < ze; ++z) {
+    load_plane(z + 1);
+    __syncthreads();
+    f4v acc[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[q] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int tap = 0; tap < 27; ++tap) {
+      const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+      const uint16_t(*pl)[ZDLX][ZDCP] = ring[(z + dz + 3) % 3];
+      const uint16_t* wp = w + ((size_t)tap * 16 + row) * ZDC + 4 * kq;
+#pragma unroll
+      for (int c = 0; c < ZDC / 16; ++c) {
+        const s4v wa = Frag<4>::load(wp + 16 * c);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const s4v xb = *reinterpret_cast<const s4v*>(&pl[wave + 1 + dy][q * 16 + row + 1 + dx][16 * c + 4 * kq]);
+          acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa, xb, acc[q], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int xo = x0 + q * 16 + row;
+      if (xo < d.x && yo < d.y) {
+        uint16_t h[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float v = acc[q][r] + bv[r];
+          if (relu) v = fmaxf(v, 0.f);
+          h[r] = f2bf(v);
+        }
+        const uint2 pk = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+        *reinterpret_cast<uint2*>(out.p + (((long)z * d.y + yo) * d.x + xo) * out.cs + out.off + 4 * kq) = pk;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Weight gradient partials for one tap: P[chunk][tap][co][ci] = sum over the chunk's voxels
 // of dz[v][co] * x[v + off_tap][ci].  GEMM with k = voxel (16 voxels per MFMA step);
 // the 16 k-values of a lane are gathered (4 per lane) from channels-last memory.
@@ -501,6 +581,15 @@ void launch_conv_fwd(hipStream_t s, Dims d, View in, int cin, const uint16_t* w,
     while (zlen > 4 && (long)gx * gy * ((d.z + zlen - 1) / zlen) < 2048) zlen /= 2;
     const unsigned nb = (unsigned)((long)gx * gy * ((d.z + zlen - 1) / zlen));
     hipLaunchKernelGGL(zconv16_kernel, dim3(nb), dim3(256), 0, s, d, in, w, bias, relu ? 1 : 0, out, zlen);
+    return;
+  }
+  // the 48 -> 16 layer likewise (16-byte loads of the input, 8-byte stores of the output)
+  if (cin == ZDC && cout == 16 && in.cs % 8 == 0 && in.off % 8 == 0 && out.cs % 4 == 0 && out.off % 4 == 0) {
+    const int gx = (d.x + ZDX - 1) / ZDX, gy = (d.y + ZDY - 1) / ZDY;
+    int zlen = 32;
+    while (zlen > 4 && (long)gx * gy * ((d.z + zlen - 1) / zlen) < 2048) zlen /= 2;
+    const unsigned nb = (unsigned)((long)gx * gy * ((d.z + zlen - 1) / zlen));
+    hipLaunchKernelGGL(zconv48_kernel, dim3(nb), dim3(256), 0, s, d, in, w, bias, relu ? 1 : 0, out, zlen);
     return;
   }
   if (cin % 32 == 0)
