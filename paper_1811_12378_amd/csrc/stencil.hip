@@ -1015,88 +1015,102 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(dma_waves_p
   pair_tile_dma<KIND, P>(g, czlen, gx, gy, per_sys, s, b, a, K);
 }
 
-// ---- the middle pair on tall tiles (kern 3) ----
-// The same two factors and the same streams-into-LDS ring as zpair_dma_kernel, on a
-// 64 x 28 output tile (first factor on 66 x 30, input 68 x 32), so the halo rows cost
-// 1.21x the output's input bytes instead of 1.42x and kappa 1.10x instead of 1.20x.
-// 1024 threads; thread t < 990 owns column ex = t % 66 of two row bands, first-factor
-// rows ey = t / 66 and ey + 15, and the second factor at the same two points when they
-// lie in the core.  Threads 990..1023 only load and write their first-factor values to
-// pad entries.  Middle kind only (no extra stream, no residual, one output); the LDS
-// (four 25.6 KB ring slots and a 32 KB first-factor ring) holds one block per CU.
-constexpr int QH = 15;                         // first-factor rows per band
-constexpr int QX = 64, QY = 2 * QH - 2;        // 64 x 28 output tile
-constexpr int QEX = QX + 2, QEY = QY + 2;      // 66 x 30 first-factor tile
-constexpr int QIX = QX + 4, QIY = QY + 4;      // 68 x 32 input tile
-constexpr int QNT = 1024;                      // 16 waves
-constexpr int QUSED = QEX * QH;                // 990 threads with points
-constexpr int QIP = QIX * QIY / 2;             // 1088 input pairs per plane
-constexpr int QIPW = QIP / (QNT / 64) / 2;     // 34 pairs per wave and instruction (two of them)
-constexpr int QKE = 2048;                      // kappa / first-factor entries per plane (1980 used)
-static_assert(QIPW * 2 * (QNT / 64) == QIP, "input pairs split evenly over the waves");
-static_assert(QEX * QEY + 2 * (QNT - QUSED) <= QKE, "the idle threads' pad entries fit");
-struct QSlot {
-  static constexpr int kIn = 0, kKap = QIP * 16, kBytes = kKap + QKE * 4;
+// ---- two factors per pass on tall tiles (kern 3) ----
+// The two factors and the streams-into-LDS ring of zpair_dma_kernel on taller output tiles:
+// 64 x (2 QH - 2), first factor on 66 x 2 QH, input 68 x (2 QH + 2), with QH = 15 (64 x 28:
+// the input's halo costs 1.21x the output's input bytes instead of the 1.42x of 64 x 12
+// tiles, kappa 1.10x instead of 1.20x).  For the pair kinds without an extra stream: the
+// middle pairs, the pair reading f and the two-output pair (the residual and y1 pairs keep
+// the 64 x 12 tiles, which measured as fast as 64 x 20 ones with room for their stream).
+// Thread t < 66 QH owns column t mod 66 of two row bands (first-factor rows t / 66 and
+// t / 66 + QH) and the second factor at the same two points where they lie in the core;
+// the other threads only load and write pad entries.
+template <int QH>
+struct Tall {
+  static constexpr int X = 64, Y = 2 * QH - 2;       // output tile
+  static constexpr int EX = X + 2, EY = Y + 2;       // first-factor tile
+  static constexpr int IX = X + 4, IY = Y + 4;       // input tile
+  static constexpr int USED = EX * QH;               // threads with points
+  static constexpr int NT = (USED + 63) / 64 * 64;   // threads
+  static constexpr int NW = NT / 64;                 // waves
+  static constexpr int IP = IX * IY / 2;             // input pairs per plane
+  static constexpr int IPW = IP / NW / 2;            // per wave and instruction (two of them)
+  static constexpr int KE = NW * 128;                // kappa / first-factor entries per plane
+  static_assert(IPW * 2 * NW == IP, "input pairs split evenly over the waves");
+  static_assert(EX * EY + 2 * (NT - USED) <= KE, "the idle threads' pad entries fit");
+};
+constexpr int kTallQH = 15;
+
+template <int QH>
+struct TallSlot {
+  using G = Tall<QH>;
+  static constexpr int kIn = 0, kKap = G::IP * 16, kBytes = kKap + G::KE * 4;
 };
 
 struct QTile {
-  BufRsrc rX, rK, rO;
+  BufRsrc rX, rK, rO, rO2;
   uint32_t pb, pbk;
-  uint32_t din0, din1, dk0, dk1;  // this lane's input pairs and kappa entries (byte offsets)
+  uint32_t din0, din1, dk0, dk1;  // this lane's input pairs and kappa entries
   uint32_t ost[2];                // output points, or kOOB
   int nz, zb, ze, damp_cells, wave;
-  int c0[2], f[2], fc[2];         // input-tile centre, first-factor entry, clamped core entry
-  bool live[2];                   // first-factor point inside the grid
+  int c0[2], f[2], fc[2];         // input centre, first-factor entry, clamped core entry
+  bool live[2];
   float a1r, a1i, b1r, b1i, a2r, a2i, b2r, b2i, sh2, dsc, diag0, sim, dampxy[2];
 };
 
-// fill a ring slot: input plane kin and kappa plane kk (zeros outside the grid or past what
-// the chunk reads, from out-of-range offsets)
+// fill a ring slot: input plane kin and kappa plane kk; zeros outside the grid or past
+// what the chunk reads, from out-of-range offsets
+template <int QH>
 __device__ __forceinline__ void qfill(const QTile& d, int kin, int kk, unsigned char* sl) {
+  using G = Tall<QH>;
+  using SL = TallSlot<QH>;
   auto clampz = [&](int kp) { return (uint32_t)min(max(kp, 0), d.nz - 1); };
   const bool zin = kin >= 0 && kin < d.nz && kin <= d.ze + 1;
   const bool zk = kk >= 0 && kk < d.nz && kk <= d.ze;
   const uint32_t sin = __builtin_amdgcn_readfirstlane(d.pb * clampz(kin));
   const uint32_t sk = __builtin_amdgcn_readfirstlane(d.pbk * clampz(kk));
   const int lane = threadIdx.x & 63;
-  if (lane < QIPW) {
-    unsigned char* b = sl + QSlot::kIn + 16 * (2 * QIPW) * d.wave;
+  if (lane < G::IPW) {
+    unsigned char* b = sl + SL::kIn + 16 * (2 * G::IPW) * d.wave;
     __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rX, (lds_void*)b, 16, zin ? d.din0 : kOOB, sin, 0, 0);
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rX, (lds_void*)(b + 16 * QIPW), 16, zin ? d.din1 : kOOB, sin, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rX, (lds_void*)(b + 16 * G::IPW), 16, zin ? d.din1 : kOOB, sin, 0, 0);
   }
-  unsigned char* kb = sl + QSlot::kKap + 4 * 128 * d.wave;
+  unsigned char* kb = sl + SL::kKap + 4 * 128 * d.wave;
   __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rK, (lds_void*)kb, 4, zk ? d.dk0 : kOOB, sk, 0, 0);
   __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rK, (lds_void*)(kb + 4 * 64), 4, zk ? d.dk1 : kOOB, sk, 0, 0);
 }
 
-// plane k: refill sN; first factor at plane k for both points from sK (input plane k,
-// kappa of plane k - 1) and sP (input plane k + 1, kappa of plane k) into tw; second factor
-// at plane k - 1 from tq (first factor of plane k - 1), the z-column registers and tw's own
-// values, stored to HBM.
-template <int P>
+// plane k: refill sN; the first factor at plane k for both points from sK (input plane k;
+// kappa of plane k - 1) and sP (input plane k + 1; kappa of plane k) into tw; the second
+// factor at plane k - 1 from tq (first factor of plane k - 1), the z-column registers and
+// the values just written, to HBM
+template <int KIND, int QH>
 __device__ __forceinline__ void qstep(const QTile& d, int k, unsigned char* __restrict__ sN,
                                       const unsigned char* __restrict__ sK, const unsigned char* __restrict__ sP,
                                       float2* __restrict__ tw, const float2* __restrict__ tq, float2 (&cm)[2],
                                       float2 (&cc)[2], float2 (&tm)[2], float2 (&t0)[2]) {
   using T = float;
   using T2 = float2;
+  using G = Tall<QH>;
+  constexpr bool DUAL = (KIND & kFacDual) != 0;
+  using SL = TallSlot<QH>;
   auto clampz = [&](int kp) { return (uint32_t)min(max(kp, 0), d.nz - 1); };
   auto dampz = [&](int kp) {
     const int dz = layer_depth(kp, d.nz, d.damp_cells);
     return (T)(dz * dz) * d.dsc;
   };
-  qfill(d, k + 1 + P, k + P, sN);
-  const T2* cp = (const T2*)(sK + QSlot::kIn);
-  const T2* pp = (const T2*)(sP + QSlot::kIn);
-  const T* kP = (const T*)(sP + QSlot::kKap);
-  const T* kK = (const T*)(sK + QSlot::kKap);
+  qfill<QH>(d, k + 1 + 2, k + 2, sN);
+  const T2* cp = (const T2*)(sK + SL::kIn);
+  const T2* pp = (const T2*)(sP + SL::kIn);
+  const T* kP = (const T*)(sP + SL::kKap);
+  const T* kK = (const T*)(sK + SL::kKap);
   const T dzk = dampz(k), dzm = dampz(k - 1);
   T2 tv[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int c0 = d.c0[h];
     const T2 cen = cc[h], zp = pp[c0], zm = cm[h];
-    const T2 xm = cp[c0 - 1], xp = cp[c0 + 1], ym = cp[c0 - QIX], yp = cp[c0 + QIX];
+    const T2 xm = cp[c0 - 1], xp = cp[c0 + 1], ym = cp[c0 - G::IX], yp = cp[c0 + G::IX];
     const T dre = d.diag0 - kP[d.f[h]];
     const T dim = -(max(d.dampxy[h], dzk) + d.sim);
     const T nbr = ((zm.x + zp.x) + (xm.x + xp.x)) + (ym.x + yp.x);
@@ -1118,7 +1132,7 @@ __device__ __forceinline__ void qstep(const QTile& d, int k, unsigned char* __re
   for (int h = 0; h < 2; ++h) {
     const int fc = d.fc[h];
     const T2 cen2 = t0[h];
-    const T2 xm2 = tq[fc - 1], xp2 = tq[fc + 1], ym2 = tq[fc - QEX], yp2 = tq[fc + QEX];
+    const T2 xm2 = tq[fc - 1], xp2 = tq[fc + 1], ym2 = tq[fc - G::EX], yp2 = tq[fc + G::EX];
     const T2 zm2 = tm[h], zp2 = tv[h];
     const T dre2 = d.diag0 - kK[d.f[h]];
     const T dim2 = -(max(d.dampxy[h], dzm) + d.sim);
@@ -1130,28 +1144,33 @@ __device__ __forceinline__ void qstep(const QTile& d, int k, unsigned char* __re
     T2 o;
     o.x = d.a2r * S2.x - d.a2i * S2.y + d.b2r * cen2.x - d.b2i * cen2.y;
     o.y = d.a2r * S2.y + d.a2i * S2.x + d.b2r * cen2.y + d.b2i * cen2.x;
-    buf_store<T2>(d.rO, zok ? d.ost[h] : kOOB, po, o);
+    const uint32_t voff = zok ? d.ost[h] : kOOB;
+    buf_store<T2>(d.rO, voff, po, o);
+    if constexpr (DUAL) buf_store<T2>(d.rO2, voff, po, o);
     tm[h] = t0[h];
     t0[h] = tv[h];
   }
 }
 
-template <int P>
+template <int KIND, int QH>
 __device__ __forceinline__ void pair_tile_tall(const GridDesc& g, int czlen, int gx, int gy, int s, int b,
                                                const FactorArgs<float2>& a, const float* __restrict__ K) {
   using T = float;
   using T2 = float2;
-  constexpr int R = P + 2;
-  constexpr int V = 2 + 2 + 2;  // memory instructions per plane: input, kappa, the two stores
-  static_assert(P == 2, "prefetch depth 2 (four slots fill the LDS)");
-  constexpr int SB = QSlot::kBytes;
+  using G = Tall<QH>;
+  constexpr bool DUAL = (KIND & kFacDual) != 0, INF = (KIND & kFacInF) != 0;
+  static_assert((KIND & (kFacResid | kFacAdd)) == 0, "the residual and y1 pairs run on 64 x 12 tiles");
+  constexpr int P = 2, R = P + 2;
+  // memory instructions per plane: input (2), kappa (2), the stores
+  constexpr int V = 2 + 2 + 2 * (DUAL ? 2 : 1);
+  constexpr int SB = TallSlot<QH>::kBytes;
   __shared__ __align__(16) unsigned char sl0[SB], sl1[SB], sl2[SB], sl3[SB];
-  __shared__ __align__(16) T2 ts0[QKE], ts1[QKE];
+  __shared__ __align__(16) T2 ts0[G::KE], ts1[G::KE];
   auto slot = [&](int r) -> unsigned char* { return r == 0 ? sl0 : r == 1 ? sl1 : r == 2 ? sl2 : sl3; };
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int bx = b % gx, by = (b / gx) % gy, zc = b / (gx * gy);
-  const int x0 = bx * QX, y0 = by * QY;
+  const int x0 = bx * G::X, y0 = by * G::Y;
   QTile d;
   d.wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   d.nz = g.nz;
@@ -1162,58 +1181,61 @@ __device__ __forceinline__ void pair_tile_tall(const GridDesc& g, int czlen, int
   const size_t n = (size_t)g.nx * g.ny * g.nz;
   const size_t plane = (size_t)g.nx * (size_t)g.ny;
   const int gsys = a.sys0 + s;
-  const int pole = gsys / a.nrhs;
+  const int pole = gsys / a.nrhs, rhs = gsys % a.nrhs;
   const FactorCoef c1 = a.coef[pole * a.cstride + a.k], c2 = a.coef[pole * a.cstride + a.k + 1];
   const PoleDev pd = a.poles[pole];
   d.a1r = (T)c1.a_re, d.a1i = (T)c1.a_im, d.b1r = (T)c1.b_re, d.b1i = (T)c1.b_im;
   d.a2r = (T)c2.a_re, d.a2i = (T)c2.a_im, d.b2r = (T)c2.b_re, d.b2i = (T)c2.b_im;
-  const T2* __restrict__ X = a.win + (size_t)s * n;
+  const T2* __restrict__ X = INF ? a.f + (size_t)rhs * n : a.win + (size_t)s * n;
   T2* __restrict__ O = a.wout + (size_t)s * n;
+  T2* __restrict__ O2 = DUAL ? a.wout2 + (size_t)s * n : O;
   d.sh2 = (T)g.s_h2;
   d.dsc = (T)g.damp_scale;
   d.diag0 = (T)6 * d.sh2 - (T)pd.z0_re;
   d.sim = (T)pd.z0_im;
   d.pb = (uint32_t)(plane * sizeof(T2));
   d.pbk = (uint32_t)(plane * sizeof(T));
-  d.rX = buf_rsrc_n(X, n * sizeof(T2));
+  const size_t vb = n * sizeof(T2);
+  d.rX = buf_rsrc_n(X, vb);
   d.rK = buf_rsrc_n(K, n * sizeof(T));
-  d.rO = buf_rsrc_n(O, n * sizeof(T2));
+  d.rO = buf_rsrc_n(O, vb);
+  d.rO2 = buf_rsrc_n(O2, vb);
 
-  // input duty: pairs p = wave * 68 + lane and p + 34 (lanes < 34) hold entries 2p, 2p + 1
-  // of the 68 x 32 input tile (68 is even and so are x0 and nx: a pair lies in one row,
+  // input duty: pairs p = wave * 2 IPW + lane and p + IPW (lanes < IPW) hold entries 2p,
+  // 2p + 1 of the input tile (IX is even and so are x0 and nx: a pair lies in one row,
   // inside the grid or outside it as a whole)
   auto pair_off = [&](int p) -> uint32_t {
     const int e0 = 2 * p;
-    const int ix = x0 - 2 + e0 % QIX, iy = y0 - 2 + e0 / QIX;
-    return (lane < QIPW && ix >= 0 && ix < g.nx && iy >= 0 && iy < g.ny) ? (uint32_t)((ix + g.nx * iy) * sizeof(T2))
-                                                                          : kOOB;
+    const int ix = x0 - 2 + e0 % G::IX, iy = y0 - 2 + e0 / G::IX;
+    return (lane < G::IPW && ix >= 0 && ix < g.nx && iy >= 0 && iy < g.ny) ? (uint32_t)((ix + g.nx * iy) * sizeof(T2))
+                                                                             : kOOB;
   };
-  d.din0 = pair_off(d.wave * 2 * QIPW + lane);
-  d.din1 = pair_off(d.wave * 2 * QIPW + QIPW + lane);
-  // kappa duty: entries e = wave * 128 + lane and e + 64 of the 66 x 30 first-factor tile
+  d.din0 = pair_off(d.wave * 2 * G::IPW + lane);
+  d.din1 = pair_off(d.wave * 2 * G::IPW + G::IPW + lane);
+  // kappa duty: entries e = wave * 128 + lane and e + 64 of the first-factor tile
   auto kap_off = [&](int e) -> uint32_t {
-    const int kx = x0 - 1 + e % QEX, ky = y0 - 1 + e / QEX;
-    return (e < QEX * QEY && kx >= 0 && kx < g.nx && ky >= 0 && ky < g.ny) ? (uint32_t)((kx + g.nx * ky) * sizeof(T))
-                                                                           : kOOB;
+    const int kx = x0 - 1 + e % G::EX, ky = y0 - 1 + e / G::EX;
+    return (e < G::EX * G::EY && kx >= 0 && kx < g.nx && ky >= 0 && ky < g.ny)
+               ? (uint32_t)((kx + g.nx * ky) * sizeof(T))
+               : kOOB;
   };
   d.dk0 = kap_off(d.wave * 128 + lane);
   d.dk1 = kap_off(d.wave * 128 + 64 + lane);
-  // the thread's two first-factor points: rows ey and ey + QH of column ex (threads past
-  // QUSED compute on clamped points and write their values to pad entries)
-  const bool used = tid < QUSED;
-  const int ex = used ? tid % QEX : (tid - QUSED) % QEX;
-  const int eyb = used ? tid / QEX : QH - 1;
+  // the thread's two first-factor points: rows ey and ey + QH of column ex
+  const bool used = tid < G::USED;
+  const int ex = used ? tid % G::EX : (tid - G::USED) % G::EX;
+  const int eyb = used ? tid / G::EX : QH - 1;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int ey = eyb + h * QH;
     const int xe = x0 - 1 + ex, ye = y0 - 1 + ey;
     const bool in = xe >= 0 && xe < g.nx && ye >= 0 && ye < g.ny;
     d.live[h] = used && in;
-    const bool core = d.live[h] && ex >= 1 && ex <= QX && ey >= 1 && ey <= QY;
+    const bool core = d.live[h] && ex >= 1 && ex <= G::X && ey >= 1 && ey <= G::Y;
     d.ost[h] = core ? (uint32_t)((xe + g.nx * ye) * sizeof(T2)) : kOOB;
-    d.c0[h] = (ey + 1) * QIX + ex + 1;
-    d.f[h] = used ? ey * QEX + ex : QEX * QEY + 2 * (tid - QUSED) + h;
-    d.fc[h] = min(max(ey, 1), QY) * QEX + min(max(ex, 1), QX);
+    d.c0[h] = (ey + 1) * G::IX + ex + 1;
+    d.f[h] = used ? ey * G::EX + ex : G::EX * G::EY + 2 * (tid - G::USED) + h;
+    d.fc[h] = min(max(ey, 1), G::Y) * G::EX + min(max(ex, 1), G::X);
     const int dxy = max(layer_depth(xe, g.nx, g.damp_cells), layer_depth(ye, g.ny, g.damp_cells));
     d.dampxy[h] = (T)(dxy * dxy) * d.dsc;
   }
@@ -1221,7 +1243,7 @@ __device__ __forceinline__ void pair_tile_tall(const GridDesc& g, int czlen, int
   if (zb < ze) {
     // prologue as in pair_tile_dma: slot j gets input plane zb-2+j and kappa plane zb-3+j
 #pragma unroll
-    for (int j = 0; j < R; ++j) qfill(d, zb - 2 + j, zb - 3 + j, slot(j));
+    for (int j = 0; j < R; ++j) qfill<QH>(d, zb - 2 + j, zb - 3 + j, slot(j));
     __builtin_amdgcn_s_waitcnt(0);
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_s_barrier();
@@ -1245,21 +1267,23 @@ __device__ __forceinline__ void pair_tile_tall(const GridDesc& g, int czlen, int
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_barrier();
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        qstep<P>(d, k, slot(u), slot((u + 1) % R), slot((u + 2) % R), odd ? ts1 : ts0, odd ? ts0 : ts1, cm, cc, tm,
-                 t0);
+        qstep<KIND, QH>(d, k, slot(u), slot((u + 1) % R), slot((u + 2) % R), odd ? ts1 : ts0, odd ? ts0 : ts1, cm, cc,
+                        tm, t0);
       }
     }
   }
   __builtin_amdgcn_s_waitcnt(0);
 }
 
-__global__ __launch_bounds__(QNT) __attribute__((amdgpu_waves_per_eu(4))) void zpair_tall_kernel(
+template <int KIND>
+__global__ __launch_bounds__(Tall<kTallQH>::NT) __attribute__((amdgpu_waves_per_eu(Tall<kTallQH>::NW / 4))) void zpair_tall_kernel(
     GridDesc g, int nzc, int czlen, int xcd_slab, int sgrp, FactorArgs<float2> a, const float* __restrict__ K) {
-  const int gx = (g.nx + QX - 1) / QX, gy = (g.ny + QY - 1) / QY;
+  using G = Tall<kTallQH>;
+  const int gx = (g.nx + G::X - 1) / G::X, gy = (g.ny + G::Y - 1) / G::Y;
   const int per_sys = gx * gy * nzc;
   int s, b;
   if (!pair_block(xcd_slab, sgrp, per_sys, a.list, a.count, s, b)) return;  // uniform
-  pair_tile_tall<2>(g, czlen, gx, gy, s, b, a, K);
+  pair_tile_tall<KIND, kTallQH>(g, czlen, gx, gy, s, b, a, K);
 }
 
 // Uneven batches, two factors per pass: as zmulti_kernel, with the pair tile of the
@@ -1641,11 +1665,13 @@ PairShape pair_shape(const GridDesc& g) {
   return p;
 }
 
-// geometry of the tall-tile middle pair (kern 3)
+// geometry of the tall-tile pairs (kern 3) with QH rows per band
+template <int QH>
 PairShape tall_shape(const GridDesc& g, int cz) {
+  using G = Tall<QH>;
   PairShape p;
-  p.gx = (g.nx + QX - 1) / QX;
-  p.gy = (g.ny + QY - 1) / QY;
+  p.gx = (g.nx + G::X - 1) / G::X;
+  p.gy = (g.ny + G::Y - 1) / G::Y;
   if (cz <= 0) {
     cz = 32;
     while (cz > 8 && (long)p.gx * p.gy * ((g.nz + cz - 1) / cz) < 256) cz /= 2;
@@ -1661,20 +1687,24 @@ template <typename T, int KIND, typename T2>
 void run_pair(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a) {
   if (a.count <= 0) return;
   const int sgrp = tune_of<T>(g).sg;
-  if constexpr (sizeof(T) == 4 && KIND == 0) {
-    // kern 3: the middle pair on 64 x 28 tiles (complex64, an even nx, vectors under 2 GiB)
-    if (tune_of<T>(g).kern == 3 && dma_pair_fits(g)) {
-      const PairShape q = tall_shape(g, tune_of<T>(g).cz);
-      hipLaunchKernelGGL(zpair_tall_kernel, dim3((unsigned)q.per_sys * (unsigned)a.count), dim3(QNT), 0, st, g,
-                         q.nzc, q.czlen, q.xcd_slab, sgrp, a, (const float*)kappa);
-      return;
+  if constexpr (sizeof(T) == 4) {
+    // kern 3: the pairs without an extra stream on tall tiles (complex64, an even nx,
+    // vectors under 2 GiB); the residual and y1 pairs as kern 2
+    if constexpr ((KIND & (kFacResid | kFacAdd)) == 0) {
+      if (tune_of<T>(g).kern == 3 && dma_pair_fits(g)) {
+        const PairShape q = tall_shape<kTallQH>(g, tune_of<T>(g).cz);
+        hipLaunchKernelGGL((zpair_tall_kernel<KIND>), dim3((unsigned)q.per_sys * (unsigned)a.count),
+                           dim3(Tall<kTallQH>::NT), 0, st, g, q.nzc, q.czlen, q.xcd_slab, sgrp, a,
+                           (const float*)kappa);
+        return;
+      }
     }
   }
   const PairShape p = pair_shape<T>(g);
   const dim3 grid((unsigned)p.per_sys * (unsigned)a.count);
   if constexpr (sizeof(T) == 4) {
-    // the streams-into-LDS pair kernel: complex64, an even nx, vectors under 2 GiB (kern 3
-    // uses it for the other pair kinds)
+    // the streams-into-LDS pair kernel: complex64, an even nx, vectors under 2 GiB (with
+    // kern 3, the residual and y1 pairs)
     if ((tune_of<T>(g).kern == 2 || tune_of<T>(g).kern == 3) && dma_pair_fits(g)) {
       // prefetch depth P (planes ahead): pd 2 -> 2 (the kinds without an extra stream then
       // fit two blocks per CU), pd 3 -> 4 (one block per CU)

@@ -175,10 +175,10 @@ def tall_tiles(shape, cz):
 @pytest.mark.parametrize("q,steps", KIND_CASES + [(3, 3)])
 @pytest.mark.parametrize("cz,sg", [(8, 3), (0, 1)])
 def test_tall_tiles_match_the_oracle_and_the_register_kernel(ctx, q, steps, cz, sg):
-    # kern 3: the middle pairs on 64 x 28 tiles (the other pair kinds as kern 2), at a
-    # geometry whose tall tiles split into XCD slabs (72 per system with cz 8), groups of
-    # systems taken sg at a time, every kind of pair launch; each result within the FP32
-    # bar of the oracle and within twice it of the register pair kernel
+    # kern 3: the pairs without an extra stream on 64 x 28 tiles (the residual and y1 pairs
+    # as kern 2), at a geometry whose tall tiles split into XCD slabs (72 per system with
+    # cz 8), groups of systems taken sg at a time, every kind of pair launch; each result
+    # within the FP32 bar of the oracle and within twice it of the register pair kernel
     assert tall_tiles(TALL_SHAPE, 8) == 72
     rng = np.random.default_rng(81)
     c = rng.uniform(1.0, 3.0, size=TALL_SHAPE)
