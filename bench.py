@@ -3,9 +3,9 @@
 
 One step = one complete solve of the batched workload: the 256^3 layered medium
 (eight layers, velocities U[1.5, 4.5] times (1 + 0.1 g), 8 points per wavelength,
-8-cell absorbing layer), 8 point sources, 16 contour poles, exponential-Taylor degree
-q = 8, FCI inside FP64 FGMRES(30), all 128 (pole, RHS) shifted systems advanced
-together.  Inputs are resident in HBM before the timed region starts.
+8-cell absorbing layer), 8 point sources, 16 contour poles (eps and the exponential-Taylor
+degree q chosen by the library's rules), FCI inside FP64 FGMRES(30), all 128 (pole, RHS)
+shifted systems advanced together.  Inputs are resident in HBM before the timed region starts.
 
 The run keeps to a wall-clock budget (--budget, counted from process start): the first
 timed solve always runs; the metric's other arms (the oracle CPU baseline, the plain
@@ -68,10 +68,10 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(shape):
-    """Ratio of counter-measured HBM bytes to algorithmic bytes per launch of the stage
+def measured_traffic(shape, kernel):
+    """Ratio of counter-measured HBM bytes to algorithmic bytes per launch of the middle
     kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), if the counters were
-    taken on this source with the same launch shape."""
+    taken on this source with the same launch shape and for this kernel."""
     try:
         with open(traffic_file(shape)) as fh:
             d = json.load(fh)
@@ -79,14 +79,20 @@ def measured_traffic(shape):
         return None
     if d.get("source_hash") != source_hash() or list(d.get("shape", [])) != list(shape):
         return None
+    if d.get("kernel") != kernel:
+        return None
     if not d.get("alg_bytes_per_launch"):
         return None
     return d["bytes_per_launch"] / d["alg_bytes_per_launch"]
 
 
-def middle_kernel_name(t):
-    """The library's kernel for the middle factors of a fixed-point step at launch shape t."""
+def middle_kernel_name(t, triple=False):
+    """The library's kernel for the middle factors of a fixed-point step at launch shape t
+    (triple: the three-factor passes of shapes with fuse 2)."""
     kern, ty, pd, _, fuse = t[:5]
+    if triple:
+        return ("ztrip_kernel (three middle factors of a fixed-point step per pass on 64 x 18 tiles, "
+                "streams loaded straight into LDS)")
     if fuse and kern == 3:
         return ("zpair_tall_kernel (two middle factors of a fixed-point step per pass on 64 x 28 tiles, "
                 "streams loaded straight into LDS)")
@@ -97,6 +103,20 @@ def middle_kernel_name(t):
         return "zpair_kernel<float, 0, %d> (two middle factors of a fixed-point step per pass)" % (2 if pd >= 3 else 1)
     return "%s<float, EpiFactor<float, 0>, %d, %d> (middle factor of a fixed-point step)" % (
         "zlds_kernel" if kern == 1 else "zmarch_kernel", ty, pd)
+
+
+def traffic_kernel(t, triple=False):
+    """Kernel-name key of the counter summary for the middle kernel at launch shape t."""
+    kern, _, pd, _, fuse = t[:5]
+    if triple:
+        return "ztrip_kernel"
+    if fuse and kern == 3:
+        return "zpair_tall_kernel<0>"
+    if fuse and kern == 2:
+        return "zpair_dma_kernel<0, %d>" % (4 if pd >= 3 else 2)
+    if fuse:
+        return "zpair_kernel<float, 0, %d>" % (2 if pd >= 3 else 1)
+    return "zlds_kernel" if kern == 1 else "zmarch_kernel"
 
 
 def host_description():
@@ -156,7 +176,7 @@ def cpu_full_solves(args):
     out = {}
     w1 = W.config_constant_32()
     o1 = OO.Operator(w1.c, w1.omega, w1.damp_cells, w1.damp_rho2)
-    poles = OF.pole_parameters(o1, 8, 1.0, 0.5, args.q)
+    poles = OF.pole_parameters(o1, 8, 1.0, 0.5, 8)  # configuration 1 fixes degree 8
     t0 = time.perf_counter()
     u, info = OF.solve(o1, w1.rhs[0], poles, m=30, tol=1e-8, max_it=400)
     t = time.perf_counter() - t0
@@ -195,10 +215,10 @@ def small_configs_arm(args, ctx):
     from oracle import operator as OO
     from paper_1811_12378_amd import hfci
 
-    def run(wl, J, eps, prec, tol, graphs, reps=3):
+    def run(wl, J, eps, prec, tol, graphs, reps=3, q=None):
         g = hfci.Operator(ctx, torch.from_numpy(wl.c).cuda(), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
         g.autotune(prec, 2)
-        c = hfci.Contour(g, J, 1.0, eps, args.q)
+        c = hfci.Contour(g, J, 1.0, eps, args.q if q is None else q)
         f = torch.from_numpy(np.stack(wl.rhs)).cuda()
         o = hfci.default_opts(precision=prec, tol=tol, max_it=args.max_it, graphs=graphs)
         hfci.solve(g, c, f, opts=o)  # warm-up: workspace, graph instantiation
@@ -220,7 +240,9 @@ def small_configs_arm(args, ctx):
 
     out = {}
     w1 = W.config_constant_32()
-    out["constant_32_fp64_tol1e-8"] = {"direct": run(w1, 8, 0.5, 64, 1e-8, 0), "graphs": run(w1, 8, 0.5, 64, 1e-8, 1)}
+    # configuration 1 fixes degree 8
+    out["constant_32_fp64_tol1e-8"] = {"direct": run(w1, 8, 0.5, 64, 1e-8, 0, q=8),
+                                       "graphs": run(w1, 8, 0.5, 64, 1e-8, 1, q=8)}
     w2 = W.config_grf_96()
     out["grf_96_4rhs_fp64"] = {"direct": run(w2, 12, args.eps, 64, args.tol, 0),
                                "graphs": run(w2, 12, args.eps, 64, args.tol, 1, reps=1)}
@@ -407,7 +429,7 @@ def params_arm(args, ctx, op, f_d, t_mixed, its_mixed):
     headline's q, each a full mixed-precision solve to the headline tolerance."""
     import torch
     from paper_1811_12378_amd import hfci
-    out = {"baseline": {"t": 1.0, "q": args.q, "time_s": round(t_mixed, 4), "its": its_mixed}, "runs": []}
+    out = {"baseline": {"t": 1.0, "q": args.q_used, "time_s": round(t_mixed, 4), "its": its_mixed}, "runs": []}
     for t in (1.0, 0.1):
         c = hfci.Contour(op, args.poles, t, args.eps, 0)
         hfci.solve(op, c, f_d, opts=hfci.default_opts(precision=32, tol=args.tol, max_it=1))
@@ -479,7 +501,7 @@ def case_two_arm(args, ctx, op, cont, wl, solve=True):
     # eq. shifted-2x2's equivalent shifts), so eps / 2 keeps the same modes inside the contour
     eps1 = cont.params()["eps"]
     eps2 = args.case_two_eps if args.case_two_eps > 0 else eps1 / 2
-    c2 = hfci.Contour(g2, args.poles, 1.0, eps2, args.q)
+    c2 = hfci.Contour(g2, args.poles, 1.0, eps2, args.q_used)
     rhs2 = torch.zeros((1, 2, n, n, n), dtype=torch.complex64, device="cuda")
     rhs2[0, 1] = f1[0]
     out = {}
@@ -493,7 +515,7 @@ def case_two_arm(args, ctx, op, cont, wl, solve=True):
         steps = [int(v) for v in st[:, 0]]
         cg = c_.get()
         out[name] = {"time_s": round(t, 4), "eps": round(eps1 if name == "case_one" else eps2, 4),
-                     "steps_per_pole": steps, "stencil_products": int(args.q * sum(steps)),
+                     "steps_per_pole": steps, "stencil_products": int(args.q_used * sum(steps)),
                      "nu_per_pole": [round(float(v), 4) for v in cg["nu"]],
                      "box": [round(o_.info()["b1"], 4), round(o_.info()["b2"], 4), o_.info()["rho2"]]}
         log("%s: %.3f s, steps per pole %s" % (name, t, steps))
@@ -504,7 +526,7 @@ def case_two_arm(args, ctx, op, cont, wl, solve=True):
     # launch reading the right-hand side and the last also writing y; a later step runs
     # ceil(q / 2) launches (pairs, then a single for odd q), the first reading g for the
     # residual, the last reading y1
-    q, nP = args.q, max(args.q - 1, 1)
+    q, nP = args.q_used, max(args.q_used - 1, 1)
     n1 = nP % 2 + nP // 2 if nP > 1 else 1
     nl = (q + 1) // 2
     per = 0.0
@@ -594,7 +616,9 @@ def main():
     ap.add_argument("--poles", type=int, default=16)
     ap.add_argument("--eps", type=float, default=0.0,
                     help="contour eps (default 0: chosen by the library's rule for the operator's box and grid)")
-    ap.add_argument("--q", type=int, default=8)
+    ap.add_argument("--q", type=int, default=0,
+                    help="degree of the exponential-Taylor polynomial (default 0: chosen by the library, Sec. 4.2's "
+                         "rule counted in passes of two factors)")
     ap.add_argument("--ppw", type=float, default=8.0)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-it", type=int, default=1000)
@@ -687,6 +711,7 @@ def main():
     op = hfci.Operator(ctx, c_d, wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
     cont = hfci.Contour(op, args.poles, 1.0, args.eps, args.q)
     eps_used = cont.params()["eps"]  # the library's rule chooses it for --eps 0
+    args.q_used = cont.q  # and the degree for --q 0 (Sec. 4.2's rule, in passes of two factors)
     info = op.info()
     log("operator:", info)
 
@@ -769,7 +794,7 @@ def main():
         if budget.fits(est):
             try:
                 from oracle import fci as OF
-                poles_o = OF.pole_parameters(o, args.poles, 1.0, eps_used, args.q)
+                poles_o = OF.pole_parameters(o, args.poles, 1.0, eps_used, args.q_used)
                 cpu = cpu_baseline(wl, poles_o, st_first["matvecs"])
                 if args.cpu_full:
                     cpu["full_solves"] = cpu_full_solves(args)
@@ -817,11 +842,14 @@ def main():
         timed_solve()
     t_mixed = sum(times) / len(times)
 
-    stage = prof["fp_stage"]
+    # the dominant middle kernel: the three-factor passes where they took more time than the
+    # middle pairs (shapes with fuse 2), else the middle pairs
+    triple = prof["fp_stage_triple"]["total_ms"] > prof["fp_stage"]["total_ms"]
+    stage = prof["fp_stage_triple" if triple else "fp_stage"]
     avg_ms = stage["total_ms"] / max(stage["launches"], 1)
     bytes_per_launch = stage["alg_bytes"] / max(stage["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    traffic_ratio = measured_traffic(tune32)
+    traffic_ratio = measured_traffic(tune32, traffic_kernel(tune32, triple))
     # the counter runs are short solves: their launches cover a different mix of active
     # systems, so the measured bytes are carried over as a ratio to the algorithmic bytes
     traffic = round(traffic_ratio * bytes_per_launch, 0) if traffic_ratio else None
@@ -830,9 +858,10 @@ def main():
         p = prof[cls]
         return round(p["alg_bytes"] / (p["total_ms"] * 1e-3) / 1e9, 1) if p["total_ms"] > 0 else 0.0
 
-    other_gbs = {k: gbs(k) for k in ("fp_stage_first", "fp_stage_last", "fp_stage_init")}
-    launch_ms = {k: round(prof[k]["total_ms"], 1) for k in ("fp_stage", "fp_stage_first", "fp_stage_last",
-                                                             "fp_stage_init")}
+    other_gbs = {k: gbs(k) for k in ("fp_stage", "fp_stage_triple", "fp_stage_first", "fp_stage_last",
+                                      "fp_stage_init") if k != ("fp_stage_triple" if triple else "fp_stage")}
+    launch_ms = {k: round(prof[k]["total_ms"], 1) for k in ("fp_stage", "fp_stage_triple", "fp_stage_first",
+                                                             "fp_stage_last", "fp_stage_init")}
     if fp64 and "time_s" in fp64:
         fp64["speedup_mixed_vs_fp64"] = fp64["time_s"] / t_mixed
 
@@ -854,14 +883,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "layered medium %d^3, %d point sources, %d poles, q=%d, %g ppw, tol %g, "
                                "FP32 shifted sweeps + FP64 FGMRES(30)"
-                               % (args.n, args.nrhs, args.poles, args.q, args.ppw, args.tol),
-                   "grid": args.n, "rhs": args.nrhs, "poles": args.poles, "q": args.q, "eps": round(eps_used, 4),
+                               % (args.n, args.nrhs, args.poles, args.q_used, args.ppw, args.tol),
+                   "grid": args.n, "rhs": args.nrhs, "poles": args.poles, "q": args.q_used, "eps": round(eps_used, 4),
                    "ppw": args.ppw, "tol": args.tol, "stencil_shape_c64": list(tune32),
                    "stencil_shape_c128": list(tune64)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_over_alg": round(traffic_ratio, 4) if traffic_ratio else None,
-                     "kernel": middle_kernel_name(tune32),
+                     "kernel": middle_kernel_name(tune32, triple),
                      "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": bytes_per_launch,
                      "launches": stage["launches"], "timed_every": args.profile_every},
         "cpu_baseline": cpu,

@@ -155,7 +155,8 @@ enum {
   HFCI_PROF_APPLY = 2,     /* hfci_apply                                           */
   HFCI_PROF_FP_LAST = 3,   /* last factor of a step (adds the constant term y1)    */
   HFCI_PROF_FP_INIT = 4,   /* first and last factor of step one (from f, to y1)    */
-  HFCI_PROF_N = 5
+  HFCI_PROF_FP_TRIPLE = 5, /* three middle factors in one pass (launch shape fuse 2)  */
+  HFCI_PROF_N = 6
 };
 
 /* Fill *o with the defaults listed above. */
@@ -204,16 +205,21 @@ hfci_status hfci_op_info(const hfci_op* op, double* out7);
  *           ahead for pd = 2, 4 for pd = 3) without passing through registers, so
  *           more planes are in flight; single factors, and two-factor passes on
  *           grids with an odd nx or vectors of 2 GiB or more, run as kern 1;
- *           3 (HFCI_F32 only, fuse = 1, ty = 8, pd = 2) = as 2, with the middle
+ *           3 (HFCI_F32 only, fuse = 1 or 2, ty = 8, pd = 2) = as 2, with the middle
  *           two-factor passes on 64 x 28 output tiles (the input halo and kappa then
- *           cost less per output point; one 1024-thread block per CU);
+ *           cost less per output point; one 1024-thread block per CU), and with
+ *           fuse = 2 the middle three-factor passes on 64 x 22 tiles;
  *   tune[1] ty:   the thread tile is 64 x ty (4 or 8);
  *   tune[2] pd:   HBM streams are issued pd planes ahead (kern 0: 1 or 2;
  *                 kern 1: 1..3 with ty = 4, 2..3 with ty = 8);
  *   tune[3] cz:   z-chunk length in planes (1..4096, or 0 = chosen from the grid);
  *   tune[4] fuse: 1 = the fixed-point factors run two per pass over HBM (temporal
- *                 blocking on 64 x 12 tiles with z-chunks cz), 0 = one per pass;
- *   tune[5] sg:   1..16; with fuse = 1 on grids whose pair tiles split into 8 XCD
+ *                 blocking on 64 x 12 tiles with z-chunks cz), 0 = one per pass,
+ *                 2 (kern 3 only) = as 1, with the middle factors of a step (those
+ *                 between its first and last pair: q - 4 of them, or of step one's
+ *                 run of pairs) three per pass where they split into threes and at
+ *                 most two pairs (a run of 4 stays 2 + 2);
+ *   tune[5] sg:   1..16; with fuse >= 1 on grids whose pair tiles split into 8 XCD
  *                 slabs, the systems of a launch are taken sg at a time, tile by tile,
  *                 so kappa of a tile is read once per sg systems (1 = one system's
  *                 tiles after another's).
@@ -225,8 +231,8 @@ hfci_status hfci_op_get_tune(const hfci_op* op, int prec, int* tune6);
 
 /* Launch-shape autotuner: times the middle factors of the fixed-point iteration
  * (the dominant launches) over nsys systems (1..64, e.g. the number of shifted
- * systems that usually iterate together) for every valid shape, one and two factors
- * per pass, keeps the fastest per factor for this operator and precision and writes
+ * systems that usually iterate together) for every valid shape, one, two and
+ * (HFCI_F32) three factors per pass, keeps the fastest per factor for this operator and precision and writes
  * it to best6 (HOST, may be NULL).  timings (HOST, may be NULL if cap = 0) receives
  * up to cap rows of {kern, ty, pd, cz, fuse, sg, milliseconds per factor}; *count
  * (may be NULL) the number of shapes timed.  Uses the context's workspace (2 nsys
@@ -282,10 +288,14 @@ hfci_status hfci_op_case_two(const hfci_op* op, hfci_op** out);
  * exponential-Taylor polynomial of degree q (eq. exp-taylor).
  * z, sigma (HOST arrays of J, or NULL) override the computed poles/weights;
  * delta (HOST array of J, or NULL) overrides the delta search.
- * q = 0 chooses the degree by Sec. 4.2's rule: the q in 1..8 minimising nu^(1/q) for
- * the pole closest to the origin (not with given deltas); hfci_contour_q reads it back.
+ * q = 0 chooses the degree by Sec. 4.2's rule for the pole closest to the origin (not
+ * with given deltas): the q in 1..16 minimising the cost of reducing its residual by a
+ * fixed factor, ceil(q/P) / -ln nu_q with P = 2 for the finite-difference operators
+ * (whose fixed-point factors run two per pass over HBM) and P = 1 for the spectral
+ * operator (then it is the smallest nu^(1/q), the rule as written); hfci_contour_q reads
+ * it back.
  * Without given poles, J = 0 takes J = 6 and eps = 0 takes the eps of hfci_contour_rule
- * for this operator's box, J, t, q (8 in its model when q = 0) and fp_reduce 5;
+ * for this operator's box, grid, J, t, q and fp_reduce 5 (with q = 0 also its degree);
  * hfci_contour_params reads J, t and eps back.
  * Errors: HFCI_E_ARG (J < 0 or > 256, J = 0 with given poles or deltas, q < 0 or > 16,
  * t <= 0, eps < 0);
@@ -307,22 +317,26 @@ hfci_status hfci_contour_params(const hfci_contour* c, int* J, double* t, double
 /* Contour parameters by rule, host arithmetic only (no GPU work; b1, b2, rho2 are the
  * box of hfci_op_info, npoints the grid points nx*ny*nz).  Sec. 7.3 sets eps per
  * frequency with a small fixed number of poles (six); here *J_out = J, or 6 for J = 0,
- * and *eps_out is the eps, among 25 geometric steps over [0.04, 0.64], minimising the
+ * and *eps_out is the eps, among 31 geometric steps over [0.01, 0.64], minimising the
  * predicted solve time
- *     T(eps) = eps * (q S + q M * 2e6 / npoints + 100),
+ *     T(eps) = eps * (Q S + Q M * 2e6 / npoints + 100),  Q = per_pass * ceil(q / per_pass),
  *     S = sum_j s_j, M = max_j s_j, s_j = ceil(ln(fp_reduce) / -ln nu_j(eps)),
  * where nu_j is eq. fix-pt-conv's rate for pole j of eq. quad-points (J, t, eps) at the
- * degree q (8 in the model for q = 0), so s_j is the fixed-point steps pole j needs.
- * The FGMRES iteration count grows about in proportion to eps (measured on the
- * finite-difference operators for J from 4 to 16); per iteration the products of all
- * poles cost their bytes, each launch a latency worth about 2e6 grid points of one
- * system's pass, and the Arnoldi step with the combine about 100 products (both fitted
- * to measured solve times on MI355X).  The rates use 200 samples per side of the box and
- * an 80-point delta scan; ties go to the smaller eps.  Outputs HOST (any may be NULL).
- * Errors: HFCI_E_ARG (b1 >= b2, rho2 < 0, npoints < 1, J < 0 or > 256, t <= 0, q < 0 or
- * > 16, fp_reduce <= 1). */
+ * degree q, so s_j is the fixed-point steps pole j needs and Q s_j its products, a pass of
+ * per_pass factors counting per_pass (per_pass = 2 for the finite-difference operators'
+ * two-factor kernels, 1 for the spectral operator).  With q = 0 the degree at each eps is
+ * the one hfci_contour_create would choose for the pole nearest the origin (1..16, in
+ * passes) and *q_out receives the chosen one; else *q_out = q.  The FGMRES iteration count
+ * grows about in proportion to eps (measured on the finite-difference operators for J
+ * from 4 to 16); per iteration the products of all poles cost their bytes, each launch a
+ * latency worth about 2e6 grid points of one system's pass, and the Arnoldi step with the
+ * combine about 100 products (both fitted to measured solve times on MI355X).  The rates
+ * use 200 samples per side of the box and an 80-point delta scan; ties go to the smaller
+ * eps.  Outputs HOST (any may be NULL).  Errors: HFCI_E_ARG (b1 >= b2, rho2 < 0,
+ * npoints < 1, J < 0 or > 256, t <= 0, q < 0 or > 16, per_pass not 1 or 2,
+ * fp_reduce <= 1). */
 hfci_status hfci_contour_rule(double b1, double b2, double rho2, double npoints, int J, double t, int q,
-                              double fp_reduce, int* J_out, double* eps_out);
+                              int per_pass, double fp_reduce, int* J_out, double* eps_out, int* q_out);
 
 /* Copy the contour's parameters into HOST arrays of length J (any may be NULL):
  * poles z, weights sigma, delta, Taylor centres z0, and the rate nu of each. */

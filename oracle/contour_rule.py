@@ -3,21 +3,24 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 Sec. 7.3 uses a small fixed number of poles (six) and sets eps per frequency.  The rule
-written out here chooses eps from the spectrum box [b1, b2] x [-rho2, 0] alone: among 25
-geometric candidates over [0.04, 0.64] it takes the first one minimising the predicted
-solve time
+written out here chooses eps from the spectrum box [b1, b2] x [-rho2, 0] and the grid size
+alone: among 31 geometric candidates over [0.01, 0.64] it takes the first one minimising
+the predicted solve time
 
-    T(eps) = eps * (q * S + q * M * LAUNCH / npoints + ITER),
+    T(eps) = eps * (Q * S + Q * M * LAUNCH / npoints + ITER),  Q = per_pass * ceil(q / per_pass),
     S = sum_j s_j,  M = max_j s_j,  s_j = ceil(ln(reduce) / -ln nu_j),
 
 where nu_j is the rate of eq. fix-pt-conv (Sec. 4.2: the delta search with
-z0 = (b1 + b2)/2 + i Im z) for pole j of eq. quad-points at (J, t, eps).  By Thm 4.2 the
-error of the fixed-point iteration is multiplied by p~(A)/p~(z) each step, whose size on
-the box is at most nu_j (maximum principle), so s_j steps reduce the residual by `reduce`
-for any normal operator with its spectrum in the box.  The iteration count of FGMRES is
-taken proportional to eps, LAUNCH (grid points of one system's pass that a launch's
-latency costs) and ITER (the Arnoldi step's work in products) are measured constants of
-the hardware, not of the paper.  J = 0 means 6 (Sec. 7.3), q = 0 means the model's q = 8.
+z0 = (b1 + b2)/2 + i Im z) for pole j of eq. quad-points at (J, t, eps) and degree q.  By
+Thm 4.2 the error of the fixed-point iteration is multiplied by p~(A)/p~(z) each step,
+whose size on the box is at most nu_j (maximum principle), so s_j steps reduce the residual
+by `reduce` for any normal operator with its spectrum in the box; Q s_j are their products
+when per_pass factors run in one pass (a pass counts per_pass products).  The iteration
+count of FGMRES is taken proportional to eps; LAUNCH (grid points of one system's pass
+that a launch's latency costs) and ITER (the Arnoldi step's work in products) are measured
+constants of the hardware, not of the paper.  J = 0 means 6 (Sec. 7.3).  With q = 0 the
+degree at each candidate is Sec. 4.2's choice for the pole nearest the origin, counted in
+passes (polynomial.choose_q with per_pass, over 1..16).
 
 The rates use the oracle's own delta search on a boundary of `per_side` samples per side.
 
@@ -34,10 +37,10 @@ import math
 import numpy as np
 
 from .contour import poles_and_weights
-from .polynomial import optimise_delta
+from .polynomial import choose_q, optimise_delta
 
-RULE_J, RULE_Q, LAUNCH, ITER = 6, 8, 2.0e6, 100.0
-CANDIDATES = 0.04 * 16.0 ** (np.arange(25) / 24.0)
+RULE_J, QMAX, LAUNCH, ITER = 6, 16, 2.0e6, 100.0
+CANDIDATES = 0.01 * 64.0 ** (np.arange(31) / 30.0)
 
 
 def pole_steps(b1: float, b2: float, rho2: float, J: int, t: float, eps: float, q: int,
@@ -52,19 +55,27 @@ def pole_steps(b1: float, b2: float, rho2: float, J: int, t: float, eps: float, 
     return out
 
 
-def predicted_time(steps, eps: float, q: int, npoints: float, launch: float = LAUNCH, it: float = ITER) -> float:
+def predicted_time(steps, eps: float, q: int, npoints: float, launch: float = LAUNCH, it: float = ITER,
+                   per_pass: int = 2) -> float:
     s = [p[0] for p in steps]
-    return eps * (q * sum(s) + q * max(s) * launch / npoints + it)
+    Q = per_pass * math.ceil(q / per_pass)
+    return eps * (Q * sum(s) + Q * max(s) * launch / npoints + it)
 
 
 def rule_parameters(b1: float, b2: float, rho2: float, npoints: float, J: int = 0, t: float = 1.0, q: int = 0,
-                    reduce: float = 5.0, per_side: int = 200, launch: float = LAUNCH, it: float = ITER):
-    """Returns (J, eps, table) with table[k] = (eps_k, T(eps_k)) over the candidates."""
+                    per_pass: int = 2, reduce: float = 5.0, per_side: int = 200, launch: float = LAUNCH,
+                    it: float = ITER):
+    """Returns (J, eps, q, table) with table[k] = (eps_k, T(eps_k), q_k) over the candidates."""
     J = J if J > 0 else RULE_J
-    qm = q if q > 0 else RULE_Q
     table = []
     for eps in CANDIDATES:
-        st = pole_steps(b1, b2, rho2, J, t, float(eps), qm, reduce, per_side)
-        table.append((float(eps), predicted_time(st, float(eps), qm, npoints, launch, it)))
+        eps = float(eps)
+        qk = q
+        if qk <= 0:
+            z, _, _ = poles_and_weights(J, t, eps, rho2)
+            z1 = z[int(np.argmin(np.abs(z)))]
+            qk = choose_q(z1, b1, b2, rho2, qmax=QMAX, per_pass=per_pass, per_side=per_side)[0]
+        st = pole_steps(b1, b2, rho2, J, t, eps, qk, reduce, per_side)
+        table.append((eps, predicted_time(st, eps, qk, npoints, launch, it, per_pass), qk))
     k = min(range(len(table)), key=lambda i: (table[i][1], i))
-    return J, table[k][0], table
+    return J, table[k][0], table[k][2], table

@@ -95,12 +95,17 @@ def optimise_delta(z: complex, b1: float, b2: float, rho2: float, q: int,
     return sgn * float(d), float(nu), z0
 
 
-def choose_q(z: complex, b1: float, b2: float, rho2: float, qmax: int = 8, **kw):
-    """q in 1..qmax minimising nu^(1/q) (Sec. 4.2); returns (q, delta, nu)."""
+def choose_q(z: complex, b1: float, b2: float, rho2: float, qmax: int = 8, per_pass: int = 1, **kw):
+    """q in 1..qmax minimising nu^(1/q) (Sec. 4.2: products per unit of residual reduction,
+    q / (-ln nu)); with per_pass factors applied per pass over memory, the passes
+    ceil(q / per_pass) / (-ln nu) instead (per_pass = 1 is the rule as written).  Returns
+    (q, delta, nu); ties go to the smaller q."""
     best = None
     for q in range(1, qmax + 1):
         d, nu, _ = optimise_delta(z, b1, b2, rho2, q, **kw)
-        key = nu ** (1.0 / q)
+        if not nu < 1.0:
+            continue
+        key = math.ceil(q / per_pass) / -math.log(nu)
         if best is None or key < best[0]:
             best = (key, q, d, nu)
     return best[1], best[2], best[3]

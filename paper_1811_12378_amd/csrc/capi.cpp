@@ -584,8 +584,14 @@ hfci_status hfci_contour_create(const hfci_op* op, int J, double t, double eps, 
     HFCI_REQUIRE(t > 0 && eps >= 0 && std::isfinite(t) && std::isfinite(eps),
                  "t must be > 0 and eps >= 0 (0: chosen by the rule)");
     if (J == 0) J = kRuleJ;
-    if (eps == 0) eps = rule_eps(op->b1, op->b2, op->rho2, (double)op->g.nx * op->g.ny * op->g.nz, J, t,
-                                 q > 0 ? q : kRuleQ, kRuleReduce);
+    // the finite-difference forms run the fixed-point factors two per pass, the spectral
+    // form one per launch
+    if (eps == 0) {
+      int qr = q;
+      eps = rule_eps(op->b1, op->b2, op->rho2, (double)op->g.nx * op->g.ny * op->g.nz, J, t, q,
+                     op->form == 3 ? 1 : 2, kRuleReduce, &qr);
+      if (q == 0) q = qr;  // chosen with eps
+    }
   }
   DeviceGuard dg(op->ctx->device);
   hfci_contour* c = new hfci_contour();
@@ -616,7 +622,7 @@ hfci_status hfci_contour_create(const hfci_op* op, int J, double t, double eps, 
       int j0 = 0;
       for (int j = 1; j < J; ++j)
         if (std::abs(c->z[j]) < std::abs(c->z[j0])) j0 = j;
-      q = choose_q(c->z[j0], op->b1, op->b2, op->rho2, kAutoQMax);
+      q = choose_q(c->z[j0], op->b1, op->b2, op->rho2, kAutoQMax, op->form == 3 ? 1 : 2);
     }
     c->q = q;
     c->delta.resize(J);
@@ -675,8 +681,9 @@ void hfci_contour_destroy(hfci_contour* c) {
 }
 
 hfci_status hfci_contour_rule(double b1, double b2, double rho2, double npoints, int J, double t, int q,
-                              double fp_reduce, int* J_out, double* eps_out) {
+                              int per_pass, double fp_reduce, int* J_out, double* eps_out, int* q_out) {
   HFCI_API_BEGIN
+  HFCI_REQUIRE(per_pass == 1 || per_pass == 2, "per_pass must be 1 or 2");
   HFCI_REQUIRE(std::isfinite(b1) && std::isfinite(b2) && b1 < b2 && std::isfinite(rho2) && rho2 >= 0,
                "need b1 < b2 and rho2 >= 0");
   HFCI_REQUIRE(npoints >= 1 && std::isfinite(npoints), "npoints must be >= 1");
@@ -685,9 +692,11 @@ hfci_status hfci_contour_rule(double b1, double b2, double rho2, double npoints,
   HFCI_REQUIRE(q >= 0 && q <= 16, "q must be in [0, 16]");
   HFCI_REQUIRE(fp_reduce > 1.0 && std::isfinite(fp_reduce), "fp_reduce must be > 1");
   const int Jr = J > 0 ? J : kRuleJ;
-  const double e = rule_eps(b1, b2, rho2, npoints, Jr, t, q > 0 ? q : kRuleQ, fp_reduce);
+  int qr = q;
+  const double e = rule_eps(b1, b2, rho2, npoints, Jr, t, q, per_pass, fp_reduce, &qr);
   if (J_out) *J_out = Jr;
   if (eps_out) *eps_out = e;
+  if (q_out) *q_out = qr;
   return HFCI_OK;
   HFCI_API_END
 }

@@ -252,16 +252,19 @@ std::vector<cd> rectangle_boundary(double b1, double b2, double rho2, int per_si
 void optimise_delta(cd z, double b1, double b2, double rho2, int q, double& delta, double& nu, cd& z0,
                     int per_side = 2000, int ns = 480);
 // the eps rule (hfci_contour_rule): candidates, the J it assumes by default (Sec. 7.3's six
-// poles), the degree its cost model assumes when q is to be chosen, and its rate resolution
-constexpr int kRuleN = 25, kRuleJ = 6, kRuleQ = 8, kRulePerSide = 200, kRuleScan = 80;
+// poles) and its rate resolution
+constexpr int kRuleN = 31, kRuleJ = 6, kRulePerSide = 200, kRuleScan = 80;
 // kRuleReduce: the stopping factor hfci_contour_create assumes (Table 4's, the default
 // fp_reduce); kRuleLaunch, kRuleIter: the cost model's launch latency (in grid points of one
 // system's pass) and per-iteration work (in products), fitted to solve times on MI355X
-constexpr double kRuleLo = 0.04, kRuleHi = 0.64, kRuleReduce = 5.0, kRuleLaunch = 2.0e6, kRuleIter = 100.0;
-double rule_eps(double b1, double b2, double rho2, double npoints, int J, double t, int q, double reduce);
+constexpr double kRuleLo = 0.01, kRuleHi = 0.64, kRuleReduce = 5.0, kRuleLaunch = 2.0e6, kRuleIter = 100.0;
+// per_pass: factors per pass over HBM; q = 0: the degree is chosen too (written to *q_out)
+double rule_eps(double b1, double b2, double rho2, double npoints, int J, double t, int q, int per_pass,
+                double reduce, int* q_out);
 // largest degree hfci_contour_create considers when it chooses q (q = 0)
-constexpr int kAutoQMax = 8;
-int choose_q(cd z, double b1, double b2, double rho2, int qmax);
+constexpr int kAutoQMax = 16;
+// per_pass: factors applied per pass over HBM (2 for the pair kernels, 1 otherwise)
+int choose_q(cd z, double b1, double b2, double rho2, int qmax, int per_pass);
 std::vector<cd> poly_roots(std::vector<cd> coeffs);
 void factor_coefficients(cd z, cd z0, double delta, int q, FactorCoef* out_L, FactorCoef* out_P, cd& pz);
 

@@ -15,8 +15,10 @@ namespace hfci {
 // fuse 1 applies the fixed-point factors two per pass (64 x 12 tiles, z-chunks cz; loads
 // one plane ahead, two when pd is 3).
 struct KernelTune {
-  // sg: with two factors per pass, the systems of a launch are taken sg at a time, tile
-  // by tile, inside each XCD's slab of tiles (1 = system after system)
+  // fuse: 0 one factor per pass, 1 two (the later steps' first and last factors and the
+  // middle ones in pairs), 2 (kern 3 only) as 1 with the middle factors in threes where
+  // they split so; sg: with several factors per pass, the systems of a launch are taken sg
+  // at a time, tile by tile, inside each XCD's slab of tiles (1 = system after system)
   int kern = 1, ty = 8, pd = 2, cz = 0, fuse = 0, sg = 1;
 };
 
@@ -146,6 +148,12 @@ struct Launch {
   // not alias the input
   static bool factor_pair(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a,
                           int kind);
+  // middle factors a.k, a.k + 1 and a.k + 2 in one pass (no kind bits); false (nothing
+  // launched) unless the complex64 launch shape is kern 3 with fuse 2 and the grid suits
+  // the pair kernels (an even nx, vectors under 2 GiB); the output must not alias the input
+  static bool factor_triple(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a);
+  // whether factor_triple launches on this grid with its current launch shape
+  static bool triple_runs(const GridDesc& g);
   // a kFacInF single factor over systems s = j * nrhs + r (all listed, count a multiple of
   // nrhs, at most 64 poles): each point forms the stencil of f once for all poles; false
   // (nothing launched) when those conditions do not hold

@@ -109,19 +109,22 @@ void optimise_delta(cd z, double b1, double b2, double rho2, int q, double& delt
 }
 
 // Sec. 4.2: the degree q is preferred where nu^(1/q) is smallest (the cost to reduce the
-// residual by a factor F is about q ln F / (-ln nu) products); q in 1..qmax, ties to the
-// smaller q.
-int choose_q(cd z, double b1, double b2, double rho2, int qmax) {
+// residual by a factor F is about q ln F / (-ln nu) products).  Where the products run
+// per_pass at a time in one pass over HBM (the finite-difference operators' two-factor
+// kernels), the cost is ceil(q / per_pass) ln F / (-ln nu) passes, and that is minimised;
+// per_pass = 1 is the rule as written.  q in 1..qmax, ties to the smaller q.
+int choose_q(cd z, double b1, double b2, double rho2, int qmax, int per_pass) {
   int best = 1;
-  double key_best = 0.0;
+  double cost_best = HUGE_VAL;
   for (int q = 1; q <= qmax; ++q) {
     double delta, nu;
     cd z0;
     optimise_delta(z, b1, b2, rho2, q, delta, nu, z0);
-    const double key = std::pow(nu, 1.0 / q);
-    if (q == 1 || key < key_best) {
+    if (!(nu < 1.0)) continue;
+    const double cost = (double)((q + per_pass - 1) / per_pass) / -std::log(nu);
+    if (cost < cost_best) {
       best = q;
-      key_best = key;
+      cost_best = cost;
     }
   }
   return best;
@@ -185,37 +188,61 @@ static double rule_nu(cd z, double b1, double b2, double rho2, int q, const std:
 // Contour parameters by rule.  Sec. 7.3 sets eps per frequency with a small fixed J; here
 // eps is the value, among kRuleN geometric steps over [kRuleLo, kRuleHi], that minimises a
 // predicted solve time
-//   T(eps) = eps * (q sum_j s_j + q max_j s_j * kRuleLaunch / npoints + kRuleIter),
-//   s_j = ceil(ln(reduce) / -ln nu_j),
+//   T(eps) = eps * (Q sum_j s_j + Q max_j s_j * kRuleLaunch / npoints + kRuleIter),
+//   s_j = ceil(ln(reduce) / -ln nu_j),  Q = per_pass * ceil(q / per_pass),
 // nu_j being eq. fix-pt-conv's rate for pole j of eq. quad-points at that eps, so s_j is
-// the fixed-point steps pole j needs.  The FGMRES iteration count grows about in
-// proportion to eps; per iteration the products of all poles cost their bytes, each
-// launch (as many as the slowest pole's products) a latency worth kRuleLaunch grid points
-// of one system's pass, and the Arnoldi step with the combine about kRuleIter products.
-// Ties go to the smaller eps.
-double rule_eps(double b1, double b2, double rho2, double npoints, int J, double t, int q, double reduce) {
+// the fixed-point steps pole j needs and Q s_j their products (a pass of per_pass factors
+// costs per_pass products).  The FGMRES iteration count grows about in proportion to eps;
+// per iteration the products of all poles cost their bytes, each launch (as many as the
+// slowest pole's products) a latency worth kRuleLaunch grid points of one system's pass,
+// and the Arnoldi step with the combine about kRuleIter products.  With q = 0 the degree at
+// each eps is Sec. 4.2's choice for the pole nearest the origin, in passes (choose_q's
+// cost, over 1..kAutoQMax).  Ties go to the smaller eps; *q_out receives the degree.
+double rule_eps(double b1, double b2, double rho2, double npoints, int J, double t, int q, int per_pass,
+                double reduce, int* q_out) {
   const std::vector<cd> bd = rectangle_boundary(b1, b2, rho2, kRulePerSide);
   double best_eps = kRuleLo, best_t = HUGE_VAL;
+  int best_q = q > 0 ? q : 1;
   std::vector<cd> z, sigma;
   for (int k = 0; k < kRuleN; ++k) {
     const double eps = kRuleLo * std::pow(kRuleHi / kRuleLo, (double)k / (kRuleN - 1));
     contour_poles(J, t, eps, rho2, z, sigma);
+    int qk = q;
+    if (qk <= 0) {
+      int j0 = 0;
+      for (int j = 1; j < J; ++j)
+        if (std::abs(z[j]) < std::abs(z[j0])) j0 = j;
+      double cost_best = HUGE_VAL;
+      for (int qq = 1; qq <= kAutoQMax; ++qq) {
+        const double nu = rule_nu(z[j0], b1, b2, rho2, qq, bd);
+        if (!(nu < 1.0)) continue;
+        const double cost = (double)((qq + per_pass - 1) / per_pass) / -std::log(nu);
+        if (cost < cost_best) {
+          cost_best = cost;
+          qk = qq;
+        }
+      }
+      if (qk <= 0) continue;  // no degree contracts at this eps
+    }
     // poles j and J-1-j are mirror images about Im = -rho2/2, as is the box, so they have
     // the same rate: evaluate the first half and count each twice (the middle pole of an
     // odd J once)
     double sum = 0.0, mx = 0.0;
     for (int j = 0; j < (J + 1) / 2 && std::isfinite(sum); ++j) {
-      const double nu = rule_nu(z[j], b1, b2, rho2, q, bd);
+      const double nu = rule_nu(z[j], b1, b2, rho2, qk, bd);
       const double sj = nu < 1.0 ? std::ceil(std::log(reduce) / -std::log(nu)) : HUGE_VAL;
       sum += (2 * j + 1 == J) ? sj : 2.0 * sj;
       mx = std::max(mx, sj);
     }
-    const double tk = eps * (q * sum + q * mx * kRuleLaunch / npoints + kRuleIter);
+    const double Q = (double)(per_pass * ((qk + per_pass - 1) / per_pass));
+    const double tk = eps * (Q * sum + Q * mx * kRuleLaunch / npoints + kRuleIter);
     if (tk < best_t) {
       best_t = tk;
       best_eps = eps;
+      best_q = qk;
     }
   }
+  if (q_out) *q_out = best_q;
   return best_eps;
 }
 

@@ -84,6 +84,7 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
     T2* wB = (q >= 3) ? (T2*)ctx.ws.get("fp_wB", (size_t)nsys * vbytes) : nullptr;
     const KernelTune& tn = (sizeof(T2) == 8) ? op.g.tune32 : op.g.tune64;
     const bool fuse = tn.fuse != 0 && Launch<T2>::pair_fits(op.g);
+    const bool triples = fuse && Launch<T2>::triple_runs(op.g);
     // residual partials come from the first launch of a step: a pair launch when fusing
     const int nblk = (fuse && q >= 3) ? Launch<T2>::pair_blocks(op.g) : Launch<T2>::partial_blocks(op.g);
     double* partial = (double*)ctx.ws.get("fp_partial", (size_t)nsys * nblk * sizeof(double));
@@ -134,22 +135,26 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
       bool reads_f;
     };
     std::vector<Fixup>* fixups = nullptr;
-    // One launch of `width` consecutive factors starting at coefficient k.  kind: kFacInF /
-    // kFacResid on its first factor, kFacAdd / kFacDual on its last.
+    // One launch of `width` (1, 2 or 3) consecutive factors starting at coefficient k.  kind:
+    // kFacInF / kFacResid on its first factor, kFacAdd / kFacDual on its last (none with 3).
     auto launch = [&](int kind, int k, int width, const T2* win, T2* wout, T2* wout2, bool fan = false) {
       a.k = k;
       a.win = win;
       a.wout = wout;
       a.wout2 = wout2;
       const bool inf = kind & kFacInF, resid = kind & kFacResid, add = kind & kFacAdd, dual = kind & kFacDual;
-      const int cls = resid ? HFCI_PROF_FP_FIRST
-                            : (inf || dual) ? HFCI_PROF_FP_INIT : add ? HFCI_PROF_FP_LAST : HFCI_PROF_FP_STAGE;
+      const int cls = resid                  ? HFCI_PROF_FP_FIRST
+                       : (inf || dual)       ? HFCI_PROF_FP_INIT
+                       : add                 ? HFCI_PROF_FP_LAST
+                       : width == 3          ? HFCI_PROF_FP_TRIPLE
+                                             : HFCI_PROF_FP_STAGE;
       const double vecs = (inf ? 0.0 : 1.0) + 1.0 + (add ? 1.0 : 0.0) + (dual ? 1.0 : 0.0);
       const bool timed = pr.sample(cls);
       if (timed) pr.begin(s);
-      const bool ok = width == 2 ? Launch<T2>::factor_pair(s, op.g, kap, a, kind)
-                                 : (fan && Launch<T2>::factor_fanout(s, op.g, kap, a)) ||
-                                       Launch<T2>::factor(s, op.g, kap, a, kind);
+      const bool ok = width == 3   ? kind == 0 && Launch<T2>::factor_triple(s, op.g, kap, a)
+                      : width == 2 ? Launch<T2>::factor_pair(s, op.g, kap, a, kind)
+                                   : (fan && Launch<T2>::factor_fanout(s, op.g, kap, a)) ||
+                                         Launch<T2>::factor(s, op.g, kap, a, kind);
       HFCI_REQUIRE(ok, "internal: unsupported factor kind");
       if (timed) {
         if (fixups) fixups->push_back(Fixup{pr.mark(), vecs, inf || resid});
@@ -160,7 +165,9 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
       int k, width, kind;
     };
     // launches of `count` factors from coefficient k0, two per pass when fusing; an odd
-    // count leaves one single launch, at the end or (single_first) at the start
+    // count leaves one single launch, at the end or (single_first) at the start.  With
+    // triples the run of middle pairs (kind 0), 2L factors, is split again into threes and
+    // the fewest pairs that complete it (none, one or two: 4 = 2 + 2, never 3 + 1).
     auto plan = [&](int k0, int count, int kind_first, int kind_last, bool pairs, bool single_first) {
       std::vector<Part> v;
       for (int j = 0; j < count;) {
@@ -172,7 +179,22 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
         v.push_back(Part{k0 + j, w, kind});
         j += w;
       }
-      return v;
+      if (!triples) return v;
+      std::vector<Part> out;
+      for (size_t i = 0; i < v.size();) {
+        if (v[i].width != 2 || v[i].kind != 0) {
+          out.push_back(v[i++]);
+          continue;
+        }
+        size_t j = i;
+        while (j < v.size() && v[j].width == 2 && v[j].kind == 0) ++j;
+        const int m = 2 * (int)(j - i), np = (m % 3 == 0) ? 0 : (m % 3 == 2) ? 1 : 2;
+        int k = v[i].k;
+        for (int t = 0; t < (m - 2 * np) / 3; ++t, k += 3) out.push_back(Part{k, 3, 0});
+        for (int t = 0; t < np; ++t, k += 2) out.push_back(Part{k, 2, 0});
+        i = j;
+      }
+      return out;
     };
 
     // ---- step one: y1 = prod over the max(q-1, 1) factors of P2, applied to f ----
@@ -380,8 +402,8 @@ void fp_run(const Op& op, const Contour& c, int nrhs, const T2* f, T2* y, int sy
 }  // namespace
 
 // Launch-shape autotuner: times the middle-factor kernel (the dominant launch of the
-// fixed-point iteration) over nsys systems for every valid shape, one factor per pass and
-// two factors per pass, and keeps the fastest per factor for this operator and precision.  Inputs are zeros and the factor is a fixed benign
+// fixed-point iteration) over nsys systems for every valid shape, one, two and (complex64)
+// three factors per pass, and keeps the fastest per factor for this operator and precision.  Inputs are zeros and the factor is a fixed benign
 // one: the kernel's time does not depend on the values.
 template <typename T2>
 KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, double>>& timings) {
@@ -391,10 +413,10 @@ KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, d
   const size_t vbytes = n * sizeof(T2);
   T2* win = (T2*)ctx.ws.get("fp_wA", (size_t)nsys * vbytes);
   T2* wout = (T2*)ctx.ws.get("fp_wB", (size_t)nsys * vbytes);
-  FactorCoef* coef = (FactorCoef*)ctx.ws.get("tune_coef", 2 * sizeof(FactorCoef));
+  FactorCoef* coef = (FactorCoef*)ctx.ws.get("tune_coef", 3 * sizeof(FactorCoef));
   PoleDev* pole = (PoleDev*)ctx.ws.get("tune_pole", sizeof(PoleDev));
   int* list = (int*)ctx.ws.get("tune_list", (size_t)nsys * sizeof(int));
-  const FactorCoef c0[2] = {{1e-3, 0.0, 0.5, 0.0}, {1e-3, 0.0, 0.5, 0.0}};
+  const FactorCoef c0[3] = {{1e-3, 0.0, 0.5, 0.0}, {1e-3, 0.0, 0.5, 0.0}, {1e-3, 0.0, 0.5, 0.0}};
   const PoleDev p0{0.5 * (op.b1 + op.b2), 0.5, 0.0, 0.0};
   std::vector<int> ids(nsys);
   for (int k = 0; k < nsys; ++k) ids[k] = k;
@@ -411,7 +433,7 @@ KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, d
   a.count = nsys;
   a.sys0 = 0;
   a.nrhs = 1;
-  a.cstride = 2;
+  a.cstride = 3;
   a.k = 0;
   KernelTune& cur = (sizeof(T2) == 8) ? op.g.tune32 : op.g.tune64;
   const KernelTune saved = cur;
@@ -435,6 +457,11 @@ KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, d
           for (int sg : {1, 2, 4})
             if ((sg == 1 || sg <= nsys) && !(kern == 3 && pd != 2)) cands.push_back(KernelTune{kern, 8, pd, cz, 1, sg});
     }
+  // three middle factors per pass (kern 3, fuse 2; per-factor time = a third of a launch)
+  if (sizeof(T2) == 8 && Launch<T2>::pair_fits(op.g))
+    for (int cz : {0, 16, 64})
+      for (int sg : {1, 2, 4})
+        if (sg == 1 || sg <= nsys) cands.push_back(KernelTune{3, 8, 2, cz, 2, sg});
   hipEvent_t e0, e1;
   HFCI_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
   HFCI_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
@@ -445,8 +472,10 @@ KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, d
     for (const KernelTune& t : cands) {
       if (t.cz > 0 && t.cz >= op.g.nz) continue;  // same as one chunk per column: covered by cz = 0 or larger
       cur = t;
+      if (t.fuse == 2 && !Launch<T2>::triple_runs(op.g)) continue;  // (an odd nx: the pairs' shape covers it)
       auto one = [&] {
-        if (t.fuse) Launch<T2>::factor_pair(s, op.g, kap, a, 0);
+        if (t.fuse == 2) Launch<T2>::factor_triple(s, op.g, kap, a);
+        else if (t.fuse) Launch<T2>::factor_pair(s, op.g, kap, a, 0);
         else Launch<T2>::factor(s, op.g, kap, a, 0);
       };
       one();  // warm-up
@@ -457,7 +486,7 @@ KernelTune autotune_shapes(Op& op, int nsys, std::vector<std::pair<KernelTune, d
       HFCI_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       HFCI_HIP(hipEventElapsedTime(&ms, e0, e1));
-      const double avg = ms / reps / (t.fuse ? 2.0 : 1.0);  // per factor
+      const double avg = ms / reps / (t.fuse == 2 ? 3.0 : t.fuse ? 2.0 : 1.0);  // per factor
       timings.emplace_back(t, avg);
       if (avg < best_ms) {
         best_ms = avg;

@@ -1286,6 +1286,289 @@ __global__ __launch_bounds__(Tall<kTallQH>::NT) __attribute__((amdgpu_waves_per_
   pair_tile_tall<KIND, kTallQH>(g, czlen, gx, gy, s, b, a, K);
 }
 
+// ---- three factors per pass on tall tiles (kern 3, fuse 2) ----
+// Middle factors k, k + 1 and k + 2 of a later step (the kind without an extra stream) in
+// one pass over HBM: temporal blocking one level deeper than the pairs.  Output tile
+// 64 x (2 QH - 4); the second factor on 66 x (2 QH - 2), the first on 68 x 2 QH (origin
+// x0 - 2, y0 - 2), the input on 72 x (2 QH + 2) from (x0 - 4, y0 - 3) so that rows start at
+// an even x and 16-byte pairs of points never straddle the grid's edge.  Thread t < 68 QH
+// owns column t mod 68 of two row bands of the first-factor tile (rows t / 68 and
+// t / 68 + QH) and computes all three factors at those two points where they lie in the
+// factor's tile.  Per plane k, after one barrier: the first factor at plane k (input
+// planes k - 1 and k from registers and LDS, k + 1 from LDS), the second at plane k - 1
+// (the first factor's plane k - 1 from LDS, planes k - 2 and k from registers), the third
+// at plane k - 2 (likewise from the second factor) to HBM.  The input and kappa ring is
+// that of the pairs (four slots, loads two planes ahead); the first and second factors
+// each keep one plane in a double-buffered LDS tile, so a plane's barrier separates every
+// write of a buffer from the reads of its previous contents.  kappa of plane k - 2 (third
+// factor) is the value the second factor read one plane earlier, kept in a register: its
+// ring slot is being refilled by then.  QH = 11: 64 x 18 outputs, 768 threads (three waves
+// per SIMD, so 128 VGPRs hold the six planes of state per point without spills; with
+// QH = 13 and 896 threads the reloads of two spilled registers waited for every load in
+// flight), 126 KB of LDS (one block per CU).
+template <int QH>
+struct Trip {
+  static constexpr int X = 64, Y = 2 * QH - 4;       // output tile
+  static constexpr int EX = X + 4, EY = Y + 4;       // first-factor tile
+  static constexpr int IX = X + 8, IY = Y + 6;       // input tile
+  static constexpr int USED = EX * QH;               // threads with points
+  static constexpr int NT = (USED + 63) / 64 * 64;   // threads
+  static constexpr int NW = NT / 64;                 // waves
+  static constexpr int IP = IX * IY / 2;             // input pairs per plane
+  static constexpr int IPW = IP / NW / 2;            // per wave and instruction (two of them)
+  static constexpr int KE = NW * 128;                // kappa / factor entries per plane
+  static constexpr int kKap = IP * 16, kSlot = kKap + KE * 4;  // ring slot layout (bytes)
+  static_assert(IPW * 2 * NW == IP, "input pairs split evenly over the waves");
+  static_assert(IPW <= 64, "one input pair per lane and instruction");
+  static_assert(EX * EY + 2 * (NT - USED) <= KE, "the idle threads' pad entries fit");
+  static_assert(4 * kSlot + 4 * KE * 8 <= 160 * 1024, "the ring and the factor tiles fit in LDS");
+};
+constexpr int kTripQH = 11;
+
+struct TTile {
+  BufRsrc rX, rK, rO;
+  uint32_t pb, pbk;
+  uint32_t din0, din1, dk0, dk1;  // this lane's input pairs and kappa entries
+  uint32_t ost[2];                // output points, or kOOB
+  int nz, zb, ze, wave;
+  int c0[2], f[2], f2c[2], f3c[2];  // input centre, own entry, clamped second / third factor entries
+  bool live[2], mid[2];             // point in the grid; inside the second factor's tile
+  float a1r, a1i, b1r, b1i, a2r, a2i, b2r, b2i, a3r, a3i, b3r, b3i, sh2, dsc, diag0, sim, dampxy[2];
+  int damp_cells;
+};
+
+// fill a ring slot: input plane kin and kappa plane kk (zeros outside the grid or past what
+// the chunk reads, from out-of-range offsets)
+template <int QH>
+__device__ __forceinline__ void tfill(const TTile& d, int kin, int kk, unsigned char* sl) {
+  using G = Trip<QH>;
+  auto clampz = [&](int kp) { return (uint32_t)min(max(kp, 0), d.nz - 1); };
+  const bool zin = kin >= 0 && kin < d.nz && kin <= d.ze + 2;
+  const bool zk = kk >= 0 && kk < d.nz && kk <= d.ze + 1;
+  const uint32_t sin = __builtin_amdgcn_readfirstlane(d.pb * clampz(kin));
+  const uint32_t sk = __builtin_amdgcn_readfirstlane(d.pbk * clampz(kk));
+  const int lane = threadIdx.x & 63;
+  if (lane < G::IPW) {
+    unsigned char* b = sl + 16 * (2 * G::IPW) * d.wave;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rX, (lds_void*)b, 16, zin ? d.din0 : kOOB, sin, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rX, (lds_void*)(b + 16 * G::IPW), 16, zin ? d.din1 : kOOB, sin, 0, 0);
+  }
+  unsigned char* kb = sl + G::kKap + 4 * 128 * d.wave;
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rK, (lds_void*)kb, 4, zk ? d.dk0 : kOOB, sk, 0, 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rK, (lds_void*)(kb + 4 * 64), 4, zk ? d.dk1 : kOOB, sk, 0, 0);
+}
+
+// one factor a S x + b x at a point: S x = (diag0 - kap + i dim) x - sh2 (sum of the six
+// neighbours)
+__device__ __forceinline__ float2 tfactor(float ar, float ai, float br, float bi, float sh2, float dre, float dim,
+                                          float2 cen, float2 zm, float2 zp, float2 xm, float2 xp, float2 ym,
+                                          float2 yp) {
+  const float nbr = ((zm.x + zp.x) + (xm.x + xp.x)) + (ym.x + yp.x);
+  const float nbi = ((zm.y + zp.y) + (xm.y + xp.y)) + (ym.y + yp.y);
+  float2 S, o;
+  S.x = dre * cen.x - dim * cen.y - sh2 * nbr;
+  S.y = dre * cen.y + dim * cen.x - sh2 * nbi;
+  o.x = ar * S.x - ai * S.y + br * cen.x - bi * cen.y;
+  o.y = ar * S.y + ai * S.x + br * cen.y + bi * cen.x;
+  return o;
+}
+
+// plane k: refill sN (input k + 3, kappa k + 2); the first factor at plane k from sK (input
+// k; kappa k - 1) and sP (input k + 1; kappa k) into w1; the second at plane k - 1 from r1
+// (first factor, plane k - 1) into w2; the third at plane k - 2 from r2 (second factor,
+// plane k - 2) to HBM.  Registers per point: input planes k - 1, k (cm, cc), first factor
+// k - 2, k - 1 (tm, t0), second factor k - 3, k - 2 (um, u0), kappa k - 2 (kz).
+template <int QH>
+__device__ __forceinline__ void tstep(const TTile& d, int k, unsigned char* __restrict__ sN,
+                                      const unsigned char* __restrict__ sK, const unsigned char* __restrict__ sP,
+                                      float2* __restrict__ w1, const float2* __restrict__ r1, float2* __restrict__ w2,
+                                      const float2* __restrict__ r2, float2 (&cm)[2], float2 (&cc)[2],
+                                      float2 (&tm)[2], float2 (&t0)[2], float2 (&um)[2], float2 (&u0)[2],
+                                      float (&kz)[2]) {
+  using T = float;
+  using T2 = float2;
+  using G = Trip<QH>;
+  auto clampz = [&](int kp) { return (uint32_t)min(max(kp, 0), d.nz - 1); };
+  auto dampz = [&](int kp) {
+    const int dz = layer_depth(kp, d.nz, d.damp_cells);
+    return (T)(dz * dz) * d.dsc;
+  };
+  tfill<QH>(d, k + 3, k + 2, sN);
+  const T2* cp = (const T2*)sK;
+  const T2* pp = (const T2*)sP;
+  const T* kP = (const T*)(sP + G::kKap);
+  const T* kK = (const T*)(sK + G::kKap);
+  const T dz0 = dampz(k), dz1 = dampz(k - 1), dz2 = dampz(k - 2);
+  const bool z0 = k >= 0 && k < d.nz, z1 = k - 1 >= 0 && k - 1 < d.nz;
+  T2 tv[2], uv[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c0 = d.c0[h];
+    const T2 zp = pp[c0];
+    const T2 v = tfactor(d.a1r, d.a1i, d.b1r, d.b1i, d.sh2, d.diag0 - kP[d.f[h]], -(max(d.dampxy[h], dz0) + d.sim),
+                         cc[h], cm[h], zp, cp[c0 - 1], cp[c0 + 1], cp[c0 - G::IX], cp[c0 + G::IX]);
+    tv[h] = (d.live[h] && z0) ? v : T2{(T)0, (T)0};
+    w1[d.f[h]] = tv[h];
+    cm[h] = cc[h];
+    cc[h] = zp;
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = d.f2c[h];
+    const T kap1 = kK[d.f[h]];
+    const T2 v = tfactor(d.a2r, d.a2i, d.b2r, d.b2i, d.sh2, d.diag0 - kap1, -(max(d.dampxy[h], dz1) + d.sim), t0[h],
+                         tm[h], tv[h], r1[e - 1], r1[e + 1], r1[e - G::EX], r1[e + G::EX]);
+    uv[h] = (d.live[h] && d.mid[h] && z1) ? v : T2{(T)0, (T)0};
+    w2[d.f[h]] = uv[h];
+    tm[h] = t0[h];
+    t0[h] = tv[h];
+  }
+  const int km = k - 2;
+  const uint32_t po = __builtin_amdgcn_readfirstlane(d.pb * clampz(km));
+  const bool zok = km >= d.zb && km < d.ze;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = d.f3c[h];
+    const T2 o = tfactor(d.a3r, d.a3i, d.b3r, d.b3i, d.sh2, d.diag0 - kz[h], -(max(d.dampxy[h], dz2) + d.sim), u0[h],
+                         um[h], uv[h], r2[e - 1], r2[e + 1], r2[e - G::EX], r2[e + G::EX]);
+    buf_store<T2>(d.rO, zok ? d.ost[h] : kOOB, po, o);
+    kz[h] = kK[d.f[h]];
+    um[h] = u0[h];
+    u0[h] = uv[h];
+  }
+}
+
+template <int QH>
+__device__ __forceinline__ void trip_tile(const GridDesc& g, int czlen, int gx, int gy, int s, int b,
+                                          const FactorArgs<float2>& a, const float* __restrict__ K) {
+  using T = float;
+  using T2 = float2;
+  using G = Trip<QH>;
+  constexpr int P = 2, R = P + 2;
+  constexpr int V = 2 + 2 + 2;  // memory instructions per plane: input (2), kappa (2), the stores (2)
+  __shared__ __align__(16) unsigned char sl0[G::kSlot], sl1[G::kSlot], sl2[G::kSlot], sl3[G::kSlot];
+  __shared__ __align__(16) T2 f1a[G::KE], f1b[G::KE], f2a[G::KE], f2b[G::KE];
+  auto slot = [&](int r) -> unsigned char* { return r == 0 ? sl0 : r == 1 ? sl1 : r == 2 ? sl2 : sl3; };
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int bx = b % gx, by = (b / gx) % gy, zc = b / (gx * gy);
+  const int x0 = bx * G::X, y0 = by * G::Y;
+  TTile d;
+  d.wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  d.nz = g.nz;
+  d.damp_cells = g.damp_cells;
+  d.zb = zc * czlen;
+  d.ze = min(g.nz, d.zb + czlen);
+  const int zb = d.zb, ze = d.ze;
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  const size_t plane = (size_t)g.nx * (size_t)g.ny;
+  const int pole = (a.sys0 + s) / a.nrhs;
+  const FactorCoef c1 = a.coef[pole * a.cstride + a.k], c2 = a.coef[pole * a.cstride + a.k + 1],
+                   c3 = a.coef[pole * a.cstride + a.k + 2];
+  const PoleDev pd = a.poles[pole];
+  d.a1r = (T)c1.a_re, d.a1i = (T)c1.a_im, d.b1r = (T)c1.b_re, d.b1i = (T)c1.b_im;
+  d.a2r = (T)c2.a_re, d.a2i = (T)c2.a_im, d.b2r = (T)c2.b_re, d.b2i = (T)c2.b_im;
+  d.a3r = (T)c3.a_re, d.a3i = (T)c3.a_im, d.b3r = (T)c3.b_re, d.b3i = (T)c3.b_im;
+  const T2* __restrict__ X = a.win + (size_t)s * n;
+  T2* __restrict__ O = a.wout + (size_t)s * n;
+  d.sh2 = (T)g.s_h2;
+  d.dsc = (T)g.damp_scale;
+  d.diag0 = (T)6 * d.sh2 - (T)pd.z0_re;
+  d.sim = (T)pd.z0_im;
+  d.pb = (uint32_t)(plane * sizeof(T2));
+  d.pbk = (uint32_t)(plane * sizeof(T));
+  d.rX = buf_rsrc_n(X, n * sizeof(T2));
+  d.rK = buf_rsrc_n(K, n * sizeof(T));
+  d.rO = buf_rsrc_n(O, n * sizeof(T2));
+
+  // input duty: pairs p = wave * 2 IPW + lane and p + IPW (lanes < IPW) hold entries 2p,
+  // 2p + 1 of the input tile (IX, x0 - 4 and nx are even: a pair lies in one row, inside
+  // the grid or outside it as a whole)
+  auto pair_off = [&](int p) -> uint32_t {
+    const int e0 = 2 * p;
+    const int ix = x0 - 4 + e0 % G::IX, iy = y0 - 3 + e0 / G::IX;
+    return (lane < G::IPW && ix >= 0 && ix < g.nx && iy >= 0 && iy < g.ny) ? (uint32_t)((ix + g.nx * iy) * sizeof(T2))
+                                                                             : kOOB;
+  };
+  d.din0 = pair_off(d.wave * 2 * G::IPW + lane);
+  d.din1 = pair_off(d.wave * 2 * G::IPW + G::IPW + lane);
+  // kappa duty: entries e = wave * 128 + lane and e + 64 of the first-factor tile
+  auto kap_off = [&](int e) -> uint32_t {
+    const int kx = x0 - 2 + e % G::EX, ky = y0 - 2 + e / G::EX;
+    return (e < G::EX * G::EY && kx >= 0 && kx < g.nx && ky >= 0 && ky < g.ny)
+               ? (uint32_t)((kx + g.nx * ky) * sizeof(T))
+               : kOOB;
+  };
+  d.dk0 = kap_off(d.wave * 128 + lane);
+  d.dk1 = kap_off(d.wave * 128 + 64 + lane);
+  // the thread's two points: rows ey and ey + QH of column ex of the first-factor tile
+  const bool used = tid < G::USED;
+  const int ex = used ? tid % G::EX : (tid - G::USED) % G::EX;
+  const int eyb = used ? tid / G::EX : QH - 1;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int ey = eyb + h * QH;
+    const int xe = x0 - 2 + ex, ye = y0 - 2 + ey;
+    const bool in = xe >= 0 && xe < g.nx && ye >= 0 && ye < g.ny;
+    d.live[h] = used && in;
+    d.mid[h] = ex >= 1 && ex <= G::X + 2 && ey >= 1 && ey <= G::Y + 2;
+    const bool core = d.live[h] && ex >= 2 && ex <= G::X + 1 && ey >= 2 && ey <= G::Y + 1;
+    d.ost[h] = core ? (uint32_t)((xe + g.nx * ye) * sizeof(T2)) : kOOB;
+    d.c0[h] = (ey + 1) * G::IX + ex + 2;
+    d.f[h] = used ? ey * G::EX + ex : G::EX * G::EY + 2 * (tid - G::USED) + h;
+    d.f2c[h] = min(max(ey, 1), G::Y + 2) * G::EX + min(max(ex, 1), G::X + 2);
+    d.f3c[h] = min(max(ey, 2), G::Y + 1) * G::EX + min(max(ex, 2), G::X + 1);
+    const int dxy = max(layer_depth(xe, g.nx, g.damp_cells), layer_depth(ye, g.ny, g.damp_cells));
+    d.dampxy[h] = (T)(dxy * dxy) * d.dsc;
+  }
+
+  if (zb < ze) {
+    // prologue: slot j gets input plane zb-3+j and kappa plane zb-4+j
+#pragma unroll
+    for (int j = 0; j < R; ++j) tfill<QH>(d, zb - 3 + j, zb - 4 + j, slot(j));
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    T2 cm[2], cc[2], tm[2], t0[2], um[2], u0[2];
+    T kz[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      cm[h] = ((const T2*)sl0)[d.c0[h]];
+      cc[h] = ((const T2*)sl1)[d.c0[h]];
+      tm[h] = t0[h] = um[h] = u0[h] = T2{(T)0, (T)0};
+      kz[h] = (T)0;
+    }
+    // planes k = zb-2 .. ze+1: the third factor reaches plane ze-1 at k = ze+1
+    const int len = ze - zb + 4;
+    const int lenp = (len + R - 1) / R * R;
+    for (int r0 = 0; r0 < lenp; r0 += R) {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int k = zb - 2 + r0 + u;
+        const bool odd = (u & 1) != 0;
+        wait_vm_lgkm0<(P - 1) * V>();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        tstep<QH>(d, k, slot(u), slot((u + 1) % R), slot((u + 2) % R), odd ? f1b : f1a, odd ? f1a : f1b,
+                  odd ? f2a : f2b, odd ? f2b : f2a, cm, cc, tm, t0, um, u0, kz);
+      }
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
+__global__ __launch_bounds__(Trip<kTripQH>::NT) __attribute__((amdgpu_waves_per_eu(Trip<kTripQH>::NW / 4))) void ztrip_kernel(
+    GridDesc g, int nzc, int czlen, int xcd_slab, int sgrp, FactorArgs<float2> a, const float* __restrict__ K) {
+  using G = Trip<kTripQH>;
+  const int gx = (g.nx + G::X - 1) / G::X, gy = (g.ny + G::Y - 1) / G::Y;
+  const int per_sys = gx * gy * nzc;
+  int s, b;
+  if (!pair_block(xcd_slab, sgrp, per_sys, a.list, a.count, s, b)) return;  // uniform
+  trip_tile<kTripQH>(g, czlen, gx, gy, s, b, a, K);
+}
+
 // Uneven batches, two factors per pass: as zmulti_kernel, with the pair tile of the
 // block's system on its operator's pair geometry (pgx x pgy x pnzc tiles).
 template <typename T, int KIND>
@@ -1683,6 +1966,24 @@ PairShape tall_shape(const GridDesc& g, int cz) {
   return p;
 }
 
+// geometry of the three-factor passes (kern 3, fuse 2) with QH rows per band
+template <int QH>
+PairShape trip_shape(const GridDesc& g, int cz) {
+  using G = Trip<QH>;
+  PairShape p;
+  p.gx = (g.nx + G::X - 1) / G::X;
+  p.gy = (g.ny + G::Y - 1) / G::Y;
+  if (cz <= 0) {
+    cz = 32;
+    while (cz > 8 && (long)p.gx * p.gy * ((g.nz + cz - 1) / cz) < 256) cz /= 2;
+  }
+  p.czlen = cz;
+  p.nzc = (g.nz + cz - 1) / cz;
+  p.per_sys = p.gx * p.gy * p.nzc;
+  p.xcd_slab = (p.per_sys % 8 == 0 && p.per_sys >= 64) ? p.per_sys / 8 : 0;
+  return p;
+}
+
 template <typename T, int KIND, typename T2>
 void run_pair(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a) {
   if (a.count <= 0) return;
@@ -1728,12 +2029,13 @@ void run_pair(hipStream_t st, const GridDesc& g, const void* kappa, const Factor
 }  // namespace
 
 bool tune_valid(const KernelTune& t) {
-  if (t.cz < 0 || t.cz > 4096 || !(t.ty == 4 || t.ty == 8) || !(t.fuse == 0 || t.fuse == 1)) return false;
+  if (t.cz < 0 || t.cz > 4096 || !(t.ty == 4 || t.ty == 8) || t.fuse < 0 || t.fuse > 2) return false;
+  if (t.fuse == 2 && t.kern != 3) return false;  // three factors per pass: kern 3 only
   if (t.sg < 1 || t.sg > 16) return false;
   if (t.kern == 0) return t.pd == 1 || t.pd == 2;
   if (t.kern == 1) return (t.ty == 4 && t.pd >= 1 && t.pd <= 3) || (t.ty == 8 && (t.pd == 2 || t.pd == 3));
   if (t.kern == 2) return t.fuse == 1 && t.ty == 8 && (t.pd == 2 || t.pd == 3);
-  if (t.kern == 3) return t.fuse == 1 && t.ty == 8 && t.pd == 2;
+  if (t.kern == 3) return (t.fuse == 1 || t.fuse == 2) && t.ty == 8 && t.pd == 2;
   return false;
 }
 
@@ -1808,6 +2110,26 @@ bool Launch<T2>::factor_pair(hipStream_t st, const GridDesc& g, const void* kapp
     default: return false;
   }
   return true;
+}
+
+template <typename T2>
+bool Launch<T2>::triple_runs(const GridDesc& g) {
+  return sizeof(T2) == 8 && g.tune32.kern == 3 && g.tune32.fuse == 2 && dma_pair_fits(g);
+}
+
+template <typename T2>
+bool Launch<T2>::factor_triple(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a) {
+  if constexpr (sizeof(T2) != 8) {
+    return false;
+  } else {
+    const KernelTune& t = g.tune32;
+    if (!triple_runs(g)) return false;
+    if (a.count <= 0) return true;
+    const PairShape q = trip_shape<kTripQH>(g, t.cz);
+    hipLaunchKernelGGL(ztrip_kernel, dim3((unsigned)q.per_sys * (unsigned)a.count), dim3(Trip<kTripQH>::NT), 0, st,
+                       g, q.nzc, q.czlen, q.xcd_slab, t.sg, a, (const float*)kappa);
+    return true;
+  }
 }
 
 template <typename T2>

@@ -36,7 +36,7 @@ EXPORTED = ["hfci_default_opts", "hfci_last_error", "hfci_version", "hfci_ctx_cr
             "hfci_shifted_solve_batch", "hfci_solve_batch", "hfci_op_case_two", "hfci_contour_q",
             "hfci_op_create_spectral", "hfci_shifted_solve_noalloc", "hfci_contour_params",
             "hfci_contour_rule"]
-PROF_CLASSES = ["fp_stage", "fp_stage_first", "apply", "fp_stage_last", "fp_stage_init"]
+PROF_CLASSES = ["fp_stage", "fp_stage_first", "apply", "fp_stage_last", "fp_stage_init", "fp_stage_triple"]
 
 
 class HfciError(RuntimeError):
@@ -123,7 +123,7 @@ def load_library(path: str = LIB_PATH):
         "hfci_contour_get": (ip, [vp, vp, vp, vp, vp, vp]),
         "hfci_contour_q": (ip, [vp, P(ip)]),
         "hfci_contour_params": (ip, [vp, P(ip), P(dp), P(dp)]),
-        "hfci_contour_rule": (ip, [dp, dp, dp, dp, ip, dp, ip, dp, P(ip), P(dp)]),
+        "hfci_contour_rule": (ip, [dp, dp, dp, dp, ip, dp, ip, ip, dp, P(ip), P(dp), P(ip)]),
         "hfci_shifted_solve": (ip, [vp, vp, ip, ip, vp, vp, ip, dp, ip, vp]),
         "hfci_shifted_solve_noalloc": (ip, [vp, vp, ip, ip, vp, vp, ip, dp, ip, vp]),
         "hfci_fci_apply": (ip, [vp, vp, P(SolveOpts), ip, vp, vp, P(Stats)]),
@@ -534,13 +534,13 @@ class Contour(_Handle):
 
 
 def contour_rule(b1: float, b2: float, rho2: float, npoints: float, J: int = 0, t: float = 1.0, q: int = 0,
-                 fp_reduce: float = 5.0):
-    """hfci_contour_rule (host arithmetic only): (J, eps) for the spectrum box [b1, b2] x [-rho2, 0]
-    of an operator on npoints grid points."""
-    Jv, ev = ctypes.c_int(), ctypes.c_double()
-    _check(load_library().hfci_contour_rule(b1, b2, rho2, float(npoints), J, t, q, fp_reduce, ctypes.byref(Jv),
-                                            ctypes.byref(ev)))
-    return Jv.value, ev.value
+                 per_pass: int = 2, fp_reduce: float = 5.0):
+    """hfci_contour_rule (host arithmetic only): (J, eps, q) for the spectrum box [b1, b2] x [-rho2, 0]
+    of an operator on npoints grid points (per_pass = 2 for finite differences, 1 spectral)."""
+    Jv, ev, qv = ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
+    _check(load_library().hfci_contour_rule(b1, b2, rho2, float(npoints), J, t, q, per_pass, fp_reduce,
+                                            ctypes.byref(Jv), ctypes.byref(ev), ctypes.byref(qv)))
+    return Jv.value, ev.value, qv.value
 
 
 def shifted_solve(op, c: Contour, f, steps: int = 0, reduce: float = 5.0, max_steps: int = 200):

@@ -67,25 +67,33 @@ def test_charges_never_grow_with_eps():
 
 
 def test_rule_reduces_to_product_count_without_overheads():
-    J, eps, table = R.rule_parameters(B1, 19.4, RHO2, 1e30, J=6, it=0.0)
-    k = int(np.argmin([t for _, t in table]))
+    J, eps, q, table = R.rule_parameters(B1, 19.4, RHO2, 1e30, J=6, q=8, it=0.0)
+    k = int(np.argmin([t for _, t, _ in table]))
     s = [p[0] for p in R.pole_steps(B1, 19.4, RHO2, 6, 1.0, eps, 8)]
-    assert J == 6 and eps == table[k][0]
+    assert J == 6 and q == 8 and eps == table[k][0]
     assert abs(table[k][1] - eps * 8 * sum(s)) < 1e-9 * table[k][1]
+    # an odd degree costs a whole pass for its lone factor: Q rounds up to even
+    J, eps7, q7, table7 = R.rule_parameters(B1, 19.4, RHO2, 1e30, J=6, q=7, it=0.0)
+    s7 = [p[0] for p in R.pole_steps(B1, 19.4, RHO2, 6, 1.0, eps7, 7)]
+    assert abs(dict((e, t) for e, t, _ in table7)[eps7] - eps7 * 8 * sum(s7)) < 1e-9 * eps7 * 8 * sum(s7)
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libhfci.so not built")
-@pytest.mark.parametrize("b2,npoints", [(19.4, 256 ** 3), (10.9, 128 ** 3)])
-def test_library_rule_matches_oracle(b2, npoints):
+@pytest.mark.parametrize("b2,npoints,q", [(19.4, 256 ** 3, 0), (10.9, 128 ** 3, 8)])
+def test_library_rule_matches_oracle(b2, npoints, q):
     from paper_1811_12378_amd import hfci
-    J, eps = hfci.contour_rule(B1, b2, RHO2, npoints)
-    Jo, eps_o, table = R.rule_parameters(B1, b2, RHO2, npoints)
+    J, eps, qc = hfci.contour_rule(B1, b2, RHO2, npoints, q=q)
+    Jo, eps_o, q_o, table = R.rule_parameters(B1, b2, RHO2, npoints, q=q)
     assert J == Jo == 6
-    assert eps in [e for e, _ in table]
-    # equal, or (the two delta searches differ in resolution, which can move a ceil) within
-    # 2 % of the oracle's minimum predicted time
-    tmin = min(t for _, t in table)
-    assert eps == eps_o or dict(table)[eps] <= 1.02 * tmin, (eps, eps_o)
+    assert q == 0 or qc == q_o == q
+    # a candidate of the geometric grid (the two sides form its powers in their own order)
+    assert min(abs(eps - e) for e, _, _ in table) <= 1e-12 * eps
+    # equal, or (the two delta searches differ in resolution, which can move a ceil or the
+    # degree) within 2 % of the oracle's minimum predicted time at that eps with that degree
+    tmin = min(t for _, t, _ in table)
+    if abs(eps - eps_o) > 1e-12 * eps or qc != q_o:
+        st = R.pole_steps(B1, b2, RHO2, 6, 1.0, eps, qc)
+        assert R.predicted_time(st, eps, qc, npoints) <= 1.02 * tmin, (eps, qc, eps_o, q_o)
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libhfci.so not built")
@@ -96,3 +104,5 @@ def test_library_rule_rejects_bad_boxes():
             hfci.contour_rule(*args)
     with pytest.raises(hfci.HfciError):
         hfci.contour_rule(-1.0, 5.0, 1.0, 8.0, fp_reduce=1.0)
+    with pytest.raises(hfci.HfciError):
+        hfci.contour_rule(-1.0, 5.0, 1.0, 8.0, per_pass=3)

@@ -205,6 +205,95 @@ def test_tall_tiles_match_the_oracle_and_the_register_kernel(ctx, q, steps, cz, 
             assert np.abs(out[3][j, r] - out[1][j, r]).max() <= 2 * bar * np.abs(ref).max(), (j, r)
 
 
+def trip_tiles(shape, cz):
+    nz, ny, nx = shape
+    return -(-nx // 64) * -(-ny // 18) * -(-nz // cz)
+
+
+def launch_plan(count, kind_first, kind_last, pairs, single_first, triples):
+    """(first factor, width, kind bits) of the launches of `count` factors, as the library
+    plans them: pairs (an odd count leaves one single, first or last), then with triples
+    each run of middle pairs (kind 0) split again into threes and at most two pairs."""
+    v, j = [], 0
+    while j < count:
+        lone = single_first and j == 0 and count % 2 == 1
+        w = 2 if (pairs and j + 1 < count and not lone) else 1
+        kind = (kind_first if j == 0 else 0) | (kind_last if j + w == count else 0)
+        v.append((j, w, kind))
+        j += w
+    if not triples:
+        return v
+    out, i = [], 0
+    while i < len(v):
+        if v[i][1] != 2 or v[i][2] != 0:
+            out.append(v[i])
+            i += 1
+            continue
+        j = i
+        while j < len(v) and v[j][1] == 2 and v[j][2] == 0:
+            j += 1
+        m = 2 * (j - i)
+        npair = 0 if m % 3 == 0 else (1 if m % 3 == 2 else 2)
+        k = v[i][0]
+        for _ in range((m - 2 * npair) // 3):
+            out.append((k, 3, 0))
+            k += 3
+        for _ in range(npair):
+            out.append((k, 2, 0))
+            k += 2
+        i = j
+    return out
+
+
+# (q, steps): the run of middle pairs of a later step (q - 4 factors, q - 3 for odd q) and
+# step one's run of pairs are split into threes and at most two pairs (q = 8: later steps
+# 2 + 2 + 2 + 2, step one 1 + 3 + 3; q = 10: later 2 + 3 + 3 + 2); q = 8 with one step ends
+# step one with the dual-output pair, which is not regrouped
+TRIP_CASES = [(8, 3), (8, 1), (9, 3), (10, 3), (11, 2), (12, 2), (13, 2), (7, 2), (6, 3)]
+
+
+@pytest.mark.parametrize("q,steps", TRIP_CASES)
+@pytest.mark.parametrize("cz,sg", [(8, 3), (0, 1)])
+def test_three_factor_passes_match_the_oracle(ctx, q, steps, cz, sg):
+    # kern 3 with fuse 2: the middle factors three per pass on 64 x 18 tiles at a geometry
+    # whose tiles split into XCD slabs (96 per system with cz 8), ragged in x, y and z,
+    # systems taken sg at a time; each result within the FP32 bar of the oracle and within
+    # twice it of the same shape with pairs only (fuse 1)
+    assert trip_tiles(TALL_SHAPE, 8) == 96
+    rng = np.random.default_rng(83)
+    c = rng.uniform(1.0, 3.0, size=TALL_SHAPE)
+    h = 1.0 / 100
+    o, g = OO.Operator(c, 30.0, 3, 1.0, h=h), hf.Operator(ctx, dev(c), h, 30.0, 3, 1.0)
+    poles = OF.pole_parameters(o, 4, 1.0, 0.5, q)
+    cg = hf.Contour(g, 4, 1.0, 0.5, q, z=[p.z for p in poles], sigma=[p.sigma for p in poles],
+                    delta=[p.delta for p in poles])
+    fh = round32(rng.standard_normal((2,) + TALL_SHAPE) + 1j * rng.standard_normal((2,) + TALL_SHAPE))
+    f = dev(fh).to(torch.complex64)
+    out = {}
+    for fuse in (1, 2):
+        g.set_tune(32, 3, 8, 2, cz, fuse, sg)
+        assert g.get_tune(32) == (3, 8, 2, cz, fuse, sg)
+        ctx.profile(True)
+        y, st = hf.shifted_solve(g, cg, f, steps=steps)
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        assert np.all(st == steps)
+        out[fuse] = host(y).astype(np.complex128)
+        # launches of three factors: step one's plan once, a later step's plan per later step
+        # (a fixed count of one step ends step one with the dual-output pair)
+        first = launch_plan(max(q - 1, 1), 8, 4 if steps == 1 else 0, True, True, fuse == 2)
+        later = launch_plan(q, 1, 2, q >= 3, False, fuse == 2)
+        want = sum(w == 3 for _, w, _ in first) + (steps - 1) * sum(w == 3 for _, w, _ in later)
+        assert prof["fp_stage_triple"]["launches"] == want, (fuse, want, prof["fp_stage_triple"])
+    Am = lambda v, sh: o.apply(v, sh)
+    for j, p in enumerate(poles):
+        for r in range(2):
+            ref, _ = OFP.fixed_point_solve(Am, fh[r], p.z, p.z0, p.delta, q, steps=steps)
+            bar = tol_of("f32", o, p, q, steps, fh[r], ref)
+            assert relmax(out[2][j, r], ref) <= bar, (j, r, relmax(out[2][j, r], ref), bar)
+            assert np.abs(out[2][j, r] - out[1][j, r]).max() <= 2 * bar * np.abs(ref).max(), (j, r)
+
+
 @pytest.mark.parametrize("kern", [2, 3])
 def test_streams_into_lds_adaptive(ctx, kern):
     # adaptive stopping in FP32 with kerns 2 and 3: each system stops within one step of the
@@ -259,19 +348,21 @@ def layered(n, nrhs):
     return W.config_layered_256(n=n, nrhs=nrhs)
 
 
-@pytest.mark.parametrize("kern,pd", [(1, 2), (2, 2), (2, 3), (3, 2)])
-def test_headline_shape_lockstep_256(ctx, kern, pd):
+@pytest.mark.parametrize("kern,pd,fuse,q", [(1, 2, 1, 8), (2, 2, 1, 8), (2, 3, 1, 8), (3, 2, 1, 8), (3, 2, 2, 10)])
+def test_headline_shape_lockstep_256(ctx, kern, pd, fuse, q):
     # the benchmark's workload and fused complex64 shapes: 2 of its 16 poles (the one
     # nearest the origin, the slowest, and one across the contour) x 2 of its point
-    # sources, two fixed-point steps (step one, then residual / middle / y1 pairs)
+    # sources, two fixed-point steps (step one, then residual / middle / y1 pairs; with
+    # fuse 2 and q = 10 step one runs 1 + 3 + 3 + 2 factors per pass and the later step
+    # 2 + 3 + 3 + 2)
     wl = layered(256, 2)
     o = OO.Operator(wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
     g = hf.Operator(ctx, dev(wl.c), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
-    g.set_tune(32, kern, 8, pd, 64, 1, 2)
-    assert pair_tiles(o.shape, 64) == 352
-    allp = OF.pole_parameters(o, 16, 1.0, 0.25, 8)
+    g.set_tune(32, kern, 8, pd, 64, fuse, 2)
+    assert pair_tiles(o.shape, 64) == 352 and trip_tiles(o.shape, 64) == 240
+    allp = OF.pole_parameters(o, 16, 1.0, 0.25, q)
     poles = [allp[0], allp[8]]
-    cg = hf.Contour(g, 2, 1.0, 0.25, 8, z=[p.z for p in poles], sigma=[p.sigma for p in poles],
+    cg = hf.Contour(g, 2, 1.0, 0.25, q, z=[p.z for p in poles], sigma=[p.sigma for p in poles],
                     delta=[p.delta for p in poles])
     f = round32(np.stack(wl.rhs))
     y, st = hf.shifted_solve(g, cg, dev(f).to(torch.complex64), steps=2)
@@ -280,8 +371,8 @@ def test_headline_shape_lockstep_256(ctx, kern, pd):
     Am = lambda v, sh: o.apply(v, sh)
     for j, p in enumerate(poles):
         for r in range(2):
-            ref, _ = OFP.fixed_point_solve(Am, f[r], p.z, p.z0, p.delta, 8, steps=2)
-            e, tol = relmax(y[j, r].astype(np.complex128), ref), tol_of("f32", o, p, 8, 2, f[r], ref)
+            ref, _ = OFP.fixed_point_solve(Am, f[r], p.z, p.z0, p.delta, q, steps=2)
+            e, tol = relmax(y[j, r].astype(np.complex128), ref), tol_of("f32", o, p, q, 2, f[r], ref)
             assert e <= tol, (j, r, e, tol)
             del ref
 

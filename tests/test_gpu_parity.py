@@ -232,9 +232,14 @@ def test_profiler_times_every_kth_launch(ctx):
 def test_tune_rejects_invalid(ctx):
     o, g = make_ops(ctx, medium((4, 4, 4), 1), 9.0, 1, 0.5)
     for bad in [(2, 4, 1, 0), (0, 5, 1, 0), (0, 4, 3, 0), (1, 8, 1, 0), (1, 4, 4, 0), (0, 4, 1, -1),
-                (1, 8, 2, 0, 2), (1, 8, 2, 0, 1, 0), (1, 8, 2, 0, 1, 17)]:
+                (1, 8, 2, 0, 2), (2, 8, 2, 0, 2), (3, 8, 2, 0, 3), (3, 8, 3, 0, 2), (1, 8, 2, 0, 1, 0),
+                (1, 8, 2, 0, 1, 17)]:
         with pytest.raises(hf.HfciError):
             g.set_tune(32, *bad)
+    with pytest.raises(hf.HfciError):  # three factors per pass: complex64 only
+        g.set_tune(64, 3, 8, 2, 0, 2)
+    g.set_tune(32, 3, 8, 2, 0, 2, 4)
+    assert g.get_tune(32) == (3, 8, 2, 0, 2, 4)
 
 
 def test_op_info_matches_oracle(ctx):
@@ -624,3 +629,12 @@ def test_graph_replay_equals_direct_launches(ctx, prec, fused, fixed):
     for u1, st1 in res[1]:
         assert st1["its"] == st0["its"] and st1["matvecs"] == st0["matvecs"]
         assert np.array_equal(u1, u0)
+    # and the replayed solve is a solve: the oracle's FP64 residual of every right-hand side
+    # is at most the tolerance, or, if the iteration cap came first, the residual FGMRES
+    # reported (the largest over the right-hand sides)
+    o = OO.Operator(wl.c, wl.omega, wl.damp_cells, wl.damp_rho2)
+    u1, st1 = res[1][-1]
+    for r in range(2):
+        b = o.s * wl.rhs[r]
+        rr = np.linalg.norm(b - o.apply(u1[r])) / np.linalg.norm(b)
+        assert rr <= max(1.01e-8, 1.01 * st1["final_relres"]), (r, rr, st1["final_relres"])

@@ -72,3 +72,31 @@ def test_ptilde_tends_to_exponential():
 def test_choose_q_prefers_smallest_rate_per_matvec():
     q, d, nu = P.choose_q(1j, *RECT1, qmax=5, grid_step=1.0 / 16)
     assert q == 2  # Table 1: nu^(1/q) = 0.733 is the smallest
+
+
+def test_choose_q_in_passes_matches_brute_force():
+    # with two factors per pass the rule minimises ceil(q/2) / (-ln nu): on a normal operator
+    # whose eigenvalue sits at the worst point of the box, the oracle's fixed-point iteration
+    # contracts by exactly nu per step, so the passes it needs to reduce the residual by 5
+    # are ceil(q/2) ceil(ln 5 / -ln nu); the chosen q needs within one step's passes of the
+    # fewest over q = 1..16 (the ceil of the step count is what the rule smooths over)
+    import math
+    from oracle import contour as C
+    from oracle import fixed_point as FP
+    b1, b2, rho2 = -1.0, 19.4, 1.0
+    z, _, _ = C.poles_and_weights(16, 1.0, 0.0635, rho2)
+    z1 = z[np.argmin(np.abs(z))]
+    bd = P.rectangle_boundary(b1, b2, rho2, 400)
+    passes = {}
+    for q in range(1, 17):
+        d, nu, z0 = P.optimise_delta(z1, b1, b2, rho2, q, per_side=400)
+        lam = bd[int(np.argmax(np.abs(P.ptilde(bd, z0, d, q))))]
+        _, hist = FP.fixed_point_solve(lambda x, s: (lam - s) * x, np.ones(1, complex), z1, z0, d, q, reduce=5.0,
+                                       m_max=5000)
+        passes[q] = math.ceil(q / 2) * (len(hist) - 1)
+    q2, _, _ = P.choose_q(z1, b1, b2, rho2, qmax=16, per_pass=2, per_side=400)
+    assert passes[q2] <= min(passes.values()) + math.ceil(q2 / 2), (q2, passes)
+    assert q2 % 2 == 0  # an odd q would leave a lone factor per step
+    q1, _, _ = P.choose_q(z1, b1, b2, rho2, qmax=16, per_pass=1, per_side=400)
+    products = {q: passes[q] // math.ceil(q / 2) * q for q in passes}
+    assert products[q1] <= min(products.values()) + q1
