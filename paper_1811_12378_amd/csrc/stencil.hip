@@ -1300,9 +1300,12 @@ __global__ __launch_bounds__(Tall<kTallQH>::NT) __attribute__((amdgpu_waves_per_
 // at plane k - 2 (likewise from the second factor) to HBM.  The input and kappa ring is
 // that of the pairs (four slots, loads two planes ahead); the first and second factors
 // each keep one plane in a double-buffered LDS tile, so a plane's barrier separates every
-// write of a buffer from the reads of its previous contents.  kappa of plane k - 2 (third
-// factor) is the value the second factor read one plane earlier, kept in a register: its
-// ring slot is being refilled by then.  QH = 11: 64 x 18 outputs, 768 threads (three waves
+// write of a buffer from the reads of its previous contents.  The second and third
+// factors act on the planes the first factor acted on one and two planes earlier, so each
+// point's kappa and damping for them are the first factor's, kept in registers.  Each
+// factor a (A - z0) x + b x is evaluated as m x - (a sh2) nb, nb the sum of the six
+// neighbours and m = a (diag0 - kappa - i (damp + Im z0)) + b = m0 - a kappa - i a damp
+// with m0 fixed per block, which saves the diagonal's own arithmetic.  QH = 11: 64 x 18 outputs, 768 threads (three waves
 // per SIMD, so 128 VGPRs hold the six planes of state per point without spills; with
 // QH = 13 and 896 threads the reloads of two spilled registers waited for every load in
 // flight), 126 KB of LDS (one block per CU).
@@ -1325,6 +1328,12 @@ struct Trip {
 };
 constexpr int kTripQH = 11;
 
+// one factor's constants: x -> m x - c nb with m = (m0r - ar kappa + ai damp) +
+// i (m0i - ai kappa - ar damp), c = a sh2
+struct TFac {
+  float ar, ai, m0r, m0i, cr, ci;
+};
+
 struct TTile {
   BufRsrc rX, rK, rO;
   uint32_t pb, pbk;
@@ -1333,7 +1342,8 @@ struct TTile {
   int nz, zb, ze, wave;
   int c0[2], f[2], f2c[2], f3c[2];  // input centre, own entry, clamped second / third factor entries
   bool live[2], mid[2];             // point in the grid; inside the second factor's tile
-  float a1r, a1i, b1r, b1i, a2r, a2i, b2r, b2i, a3r, a3i, b3r, b3i, sh2, dsc, diag0, sim, dampxy[2];
+  TFac f1, f2, f3;
+  float dsc, dampxy[2];
   int damp_cells;
 };
 
@@ -1358,33 +1368,32 @@ __device__ __forceinline__ void tfill(const TTile& d, int kin, int kk, unsigned 
   __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rK, (lds_void*)(kb + 4 * 64), 4, zk ? d.dk1 : kOOB, sk, 0, 0);
 }
 
-// one factor a S x + b x at a point: S x = (diag0 - kap + i dim) x - sh2 (sum of the six
-// neighbours)
-__device__ __forceinline__ float2 tfactor(float ar, float ai, float br, float bi, float sh2, float dre, float dim,
-                                          float2 cen, float2 zm, float2 zp, float2 xm, float2 xp, float2 ym,
-                                          float2 yp) {
+// one factor at a point, m x - c nb (see TFac), from the point's kappa and damping
+__device__ __forceinline__ float2 tfactor(const TFac& F, float kap, float damp, float2 cen, float2 zm, float2 zp,
+                                          float2 xm, float2 xp, float2 ym, float2 yp) {
   const float nbr = ((zm.x + zp.x) + (xm.x + xp.x)) + (ym.x + yp.x);
   const float nbi = ((zm.y + zp.y) + (xm.y + xp.y)) + (ym.y + yp.y);
-  float2 S, o;
-  S.x = dre * cen.x - dim * cen.y - sh2 * nbr;
-  S.y = dre * cen.y + dim * cen.x - sh2 * nbi;
-  o.x = ar * S.x - ai * S.y + br * cen.x - bi * cen.y;
-  o.y = ar * S.y + ai * S.x + br * cen.y + bi * cen.x;
+  const float mr = F.m0r - F.ar * kap + F.ai * damp;
+  const float mi = F.m0i - F.ai * kap - F.ar * damp;
+  float2 o;
+  o.x = mr * cen.x - mi * cen.y - F.cr * nbr + F.ci * nbi;
+  o.y = mr * cen.y + mi * cen.x - F.cr * nbi - F.ci * nbr;
   return o;
 }
 
 // plane k: refill sN (input k + 3, kappa k + 2); the first factor at plane k from sK (input
-// k; kappa k - 1) and sP (input k + 1; kappa k) into w1; the second at plane k - 1 from r1
-// (first factor, plane k - 1) into w2; the third at plane k - 2 from r2 (second factor,
-// plane k - 2) to HBM.  Registers per point: input planes k - 1, k (cm, cc), first factor
-// k - 2, k - 1 (tm, t0), second factor k - 3, k - 2 (um, u0), kappa k - 2 (kz).
+// k) and sP (input k + 1; kappa k) into w1; the second at plane k - 1 from r1 (first
+// factor, plane k - 1) into w2; the third at plane k - 2 from r2 (second factor, plane
+// k - 2) to HBM.  Registers per point: input planes k - 1, k (cm, cc), first factor k - 2,
+// k - 1 (tm, t0), second factor k - 3, k - 2 (um, u0), kappa and damping of planes k - 1
+// and k - 2 (ka1, ka2, da1, da2).
 template <int QH>
 __device__ __forceinline__ void tstep(const TTile& d, int k, unsigned char* __restrict__ sN,
                                       const unsigned char* __restrict__ sK, const unsigned char* __restrict__ sP,
                                       float2* __restrict__ w1, const float2* __restrict__ r1, float2* __restrict__ w2,
                                       const float2* __restrict__ r2, float2 (&cm)[2], float2 (&cc)[2],
                                       float2 (&tm)[2], float2 (&t0)[2], float2 (&um)[2], float2 (&u0)[2],
-                                      float (&kz)[2]) {
+                                      float (&ka1)[2], float (&ka2)[2], float (&da1)[2], float (&da2)[2]) {
   using T = float;
   using T2 = float2;
   using G = Trip<QH>;
@@ -1397,16 +1406,18 @@ __device__ __forceinline__ void tstep(const TTile& d, int k, unsigned char* __re
   const T2* cp = (const T2*)sK;
   const T2* pp = (const T2*)sP;
   const T* kP = (const T*)(sP + G::kKap);
-  const T* kK = (const T*)(sK + G::kKap);
-  const T dz0 = dampz(k), dz1 = dampz(k - 1), dz2 = dampz(k - 2);
+  const T dz0 = dampz(k);
   const bool z0 = k >= 0 && k < d.nz, z1 = k - 1 >= 0 && k - 1 < d.nz;
   T2 tv[2], uv[2];
+  T ka0[2], da0[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int c0 = d.c0[h];
     const T2 zp = pp[c0];
-    const T2 v = tfactor(d.a1r, d.a1i, d.b1r, d.b1i, d.sh2, d.diag0 - kP[d.f[h]], -(max(d.dampxy[h], dz0) + d.sim),
-                         cc[h], cm[h], zp, cp[c0 - 1], cp[c0 + 1], cp[c0 - G::IX], cp[c0 + G::IX]);
+    ka0[h] = kP[d.f[h]];
+    da0[h] = max(d.dampxy[h], dz0);
+    const T2 v = tfactor(d.f1, ka0[h], da0[h], cc[h], cm[h], zp, cp[c0 - 1], cp[c0 + 1], cp[c0 - G::IX],
+                         cp[c0 + G::IX]);
     tv[h] = (d.live[h] && z0) ? v : T2{(T)0, (T)0};
     w1[d.f[h]] = tv[h];
     cm[h] = cc[h];
@@ -1415,9 +1426,8 @@ __device__ __forceinline__ void tstep(const TTile& d, int k, unsigned char* __re
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int e = d.f2c[h];
-    const T kap1 = kK[d.f[h]];
-    const T2 v = tfactor(d.a2r, d.a2i, d.b2r, d.b2i, d.sh2, d.diag0 - kap1, -(max(d.dampxy[h], dz1) + d.sim), t0[h],
-                         tm[h], tv[h], r1[e - 1], r1[e + 1], r1[e - G::EX], r1[e + G::EX]);
+    const T2 v = tfactor(d.f2, ka1[h], da1[h], t0[h], tm[h], tv[h], r1[e - 1], r1[e + 1], r1[e - G::EX],
+                         r1[e + G::EX]);
     uv[h] = (d.live[h] && d.mid[h] && z1) ? v : T2{(T)0, (T)0};
     w2[d.f[h]] = uv[h];
     tm[h] = t0[h];
@@ -1429,12 +1439,15 @@ __device__ __forceinline__ void tstep(const TTile& d, int k, unsigned char* __re
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int e = d.f3c[h];
-    const T2 o = tfactor(d.a3r, d.a3i, d.b3r, d.b3i, d.sh2, d.diag0 - kz[h], -(max(d.dampxy[h], dz2) + d.sim), u0[h],
-                         um[h], uv[h], r2[e - 1], r2[e + 1], r2[e - G::EX], r2[e + G::EX]);
+    const T2 o = tfactor(d.f3, ka2[h], da2[h], u0[h], um[h], uv[h], r2[e - 1], r2[e + 1], r2[e - G::EX],
+                         r2[e + G::EX]);
     buf_store<T2>(d.rO, zok ? d.ost[h] : kOOB, po, o);
-    kz[h] = kK[d.f[h]];
     um[h] = u0[h];
     u0[h] = uv[h];
+    ka2[h] = ka1[h];
+    ka1[h] = ka0[h];
+    da2[h] = da1[h];
+    da1[h] = da0[h];
   }
 }
 
@@ -1463,18 +1476,25 @@ __device__ __forceinline__ void trip_tile(const GridDesc& g, int czlen, int gx, 
   const size_t n = (size_t)g.nx * g.ny * g.nz;
   const size_t plane = (size_t)g.nx * (size_t)g.ny;
   const int pole = (a.sys0 + s) / a.nrhs;
-  const FactorCoef c1 = a.coef[pole * a.cstride + a.k], c2 = a.coef[pole * a.cstride + a.k + 1],
-                   c3 = a.coef[pole * a.cstride + a.k + 2];
   const PoleDev pd = a.poles[pole];
-  d.a1r = (T)c1.a_re, d.a1i = (T)c1.a_im, d.b1r = (T)c1.b_re, d.b1i = (T)c1.b_im;
-  d.a2r = (T)c2.a_re, d.a2i = (T)c2.a_im, d.b2r = (T)c2.b_re, d.b2i = (T)c2.b_im;
-  d.a3r = (T)c3.a_re, d.a3i = (T)c3.a_im, d.b3r = (T)c3.b_re, d.b3i = (T)c3.b_im;
+  // the factors' constants, formed in FP64: m0 = a (6 sh2 - z0) + b, c = a sh2
+  auto fac = [&](const FactorCoef& c) {
+    const double diag0 = 6.0 * g.s_h2 - pd.z0_re, sim = pd.z0_im;
+    TFac F;
+    F.ar = (T)c.a_re;
+    F.ai = (T)c.a_im;
+    F.m0r = (T)(c.a_re * diag0 + c.a_im * sim + c.b_re);
+    F.m0i = (T)(c.a_im * diag0 - c.a_re * sim + c.b_im);
+    F.cr = (T)(c.a_re * g.s_h2);
+    F.ci = (T)(c.a_im * g.s_h2);
+    return F;
+  };
+  d.f1 = fac(a.coef[pole * a.cstride + a.k]);
+  d.f2 = fac(a.coef[pole * a.cstride + a.k + 1]);
+  d.f3 = fac(a.coef[pole * a.cstride + a.k + 2]);
   const T2* __restrict__ X = a.win + (size_t)s * n;
   T2* __restrict__ O = a.wout + (size_t)s * n;
-  d.sh2 = (T)g.s_h2;
   d.dsc = (T)g.damp_scale;
-  d.diag0 = (T)6 * d.sh2 - (T)pd.z0_re;
-  d.sim = (T)pd.z0_im;
   d.pb = (uint32_t)(plane * sizeof(T2));
   d.pbk = (uint32_t)(plane * sizeof(T));
   d.rX = buf_rsrc_n(X, n * sizeof(T2));
@@ -1531,13 +1551,13 @@ __device__ __forceinline__ void trip_tile(const GridDesc& g, int czlen, int gx, 
     __builtin_amdgcn_s_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     T2 cm[2], cc[2], tm[2], t0[2], um[2], u0[2];
-    T kz[2];
+    T ka1[2], ka2[2], da1[2], da2[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       cm[h] = ((const T2*)sl0)[d.c0[h]];
       cc[h] = ((const T2*)sl1)[d.c0[h]];
       tm[h] = t0[h] = um[h] = u0[h] = T2{(T)0, (T)0};
-      kz[h] = (T)0;
+      ka1[h] = ka2[h] = da1[h] = da2[h] = (T)0;
     }
     // planes k = zb-2 .. ze+1: the third factor reaches plane ze-1 at k = ze+1
     const int len = ze - zb + 4;
@@ -1552,7 +1572,7 @@ __device__ __forceinline__ void trip_tile(const GridDesc& g, int czlen, int gx, 
         __builtin_amdgcn_s_barrier();
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         tstep<QH>(d, k, slot(u), slot((u + 1) % R), slot((u + 2) % R), odd ? f1b : f1a, odd ? f1a : f1b,
-                  odd ? f2a : f2b, odd ? f2b : f2a, cm, cc, tm, t0, um, u0, kz);
+                  odd ? f2a : f2b, odd ? f2b : f2a, cm, cc, tm, t0, um, u0, ka1, ka2, da1, da2);
       }
     }
   }

@@ -23,7 +23,7 @@ import workloads as W
 from oracle import fci as OF
 from oracle import fixed_point as OFP
 from oracle import operator as OO
-from tests.fp32_bounds import fixed_point_bar, relmax, round32, stencil_absrow
+from tests.fp32_bounds import ROUNDINGS, SAFETY, U32, fixed_point_bar, relmax, round32, stencil_absrow
 
 pytestmark = pytest.mark.gpu
 
@@ -294,15 +294,14 @@ def test_three_factor_passes_match_the_oracle(ctx, q, steps, cz, sg):
             assert np.abs(out[2][j, r] - out[1][j, r]).max() <= 2 * bar * np.abs(ref).max(), (j, r)
 
 
-@pytest.mark.parametrize("kern", [2, 3])
-def test_streams_into_lds_adaptive(ctx, kern):
-    # adaptive stopping in FP32 with kerns 2 and 3: each system stops within one step of the
-    # oracle's count (an FP32 residual can land on the other side of the threshold), its
-    # iterate is the oracle's after the steps it took, within the FP32 bar, and it meets the
-    # stopping rule; a zero right-hand side stops at once
+@pytest.mark.parametrize("kern,fuse,q", [(2, 1, 8), (3, 1, 8), (3, 2, 10)])
+def test_streams_into_lds_adaptive(ctx, kern, fuse, q):
+    # adaptive stopping in FP32 with kerns 2 and 3 (and three factors per pass): each system
+    # stops within one step of the oracle's count (an FP32 residual can land on the other
+    # side of the threshold), its iterate is the oracle's after the steps it took, within
+    # the FP32 bar, and it meets the stopping rule; a zero right-hand side stops at once
     o, g, rng = slab_operator(ctx, seed=79)
-    g.set_tune(32, kern, 8, 2, 8, 1, 3)
-    q = 8
+    g.set_tune(32, kern, 8, 2, 8, fuse, 3)
     poles = OF.pole_parameters(o, 4, 1.0, 0.5, q)
     cg = hf.Contour(g, 4, 1.0, 0.5, q, z=[p.z for p in poles], sigma=[p.sigma for p in poles],
                     delta=[p.delta for p in poles])
@@ -320,8 +319,16 @@ def test_streams_into_lds_adaptive(ctx, kern):
             ref, _ = OFP.fixed_point_solve(Am, fh[r], p.z, p.z0, p.delta, q, steps=k)
             e, tol = relmax(y[j, r], ref), tol_of("f32", o, p, q, k, fh[r], ref)
             assert e <= tol, (j, r, e, tol)
-            rn = np.linalg.norm(fh[r] - o.apply(y[j, r], p.z))
-            assert rn <= np.linalg.norm(fh[r]) / 5 * (1 + 1e-4), (j, r)
+            # a system that stopped before the cap of 40 steps met the rule; the test decided
+            # on the FP32 residual the kernel formed, whose error per point is at most
+            # ROUNDINGS u (|f| + |A - z| |y|): in the 2-norm at most that times
+            # (||f|| + absrow ||y||), |A - z| being symmetric with row sums <= absrow (with
+            # q = 10 the pole nearest the origin reaches the cap, in the oracle too)
+            if k < 40:
+                rn = np.linalg.norm(fh[r] - o.apply(y[j, r], p.z))
+                absrow = stencil_absrow(o.s_h2, o.kappa, o.rho2)(p.z)
+                slack = SAFETY * ROUNDINGS * U32 * (np.linalg.norm(fh[r]) + absrow * np.linalg.norm(y[j, r]))
+                assert rn <= np.linalg.norm(fh[r]) / 5 + slack, (j, r, rn, np.linalg.norm(fh[r]) / 5, slack)
 
 
 def test_streams_into_lds_need_an_even_nx(ctx):

@@ -610,15 +610,18 @@ def test_batch_error_paths(ctx):
 
 # ---- fixed-point steps replayed from captured HIP graphs ----
 
-@pytest.mark.parametrize("prec,fused,fixed", [(64, 0, 0), (32, 0, 0), (32, 1, 0), (64, 1, 2), (32, 0, 3)])
-def test_graph_replay_equals_direct_launches(ctx, prec, fused, fixed):
+@pytest.mark.parametrize("prec,kern,fused,fixed,q", [(64, 1, 0, 0, 8), (32, 1, 0, 0, 8), (32, 1, 1, 0, 8),
+                                                    (64, 1, 1, 2, 8), (32, 1, 0, 3, 8), (32, 3, 2, 0, 10),
+                                                    (32, 3, 2, 2, 10)])
+def test_graph_replay_equals_direct_launches(ctx, prec, kern, fused, fixed, q):
     # each FCI application replays the captured step graph many times, with the eager
     # Arnoldi work of FGMRES between replays; every replay must give exactly what direct
-    # launches give, so the whole solve is bitwise identical
+    # launches give, so the whole solve is bitwise identical (kern 3 with fuse 2 and
+    # q = 10: later steps of 2 + 3 + 3 + 2 factors per pass)
     wl = W.config_grf_96(n=20, nrhs=2)
     g = hf.Operator(ctx, dev(wl.c), wl.h, wl.omega, wl.damp_cells, wl.damp_rho2)
-    g.set_tune(prec, 1, 8, 2, 0, fused)
-    c = hf.Contour(g, 8, 1.0, 0.25, 8)
+    g.set_tune(prec, kern, 8, 2, 0, fused)
+    c = hf.Contour(g, 8, 1.0, 0.25, q)
     f = dev(np.stack(wl.rhs))
     res = {}
     for gr in (0, 1, 1):  # the second graph run reuses the cached instantiation
