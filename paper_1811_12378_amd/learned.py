@@ -95,10 +95,10 @@ def harvest_pairs(ctx, n=128, media=42, pairs=48, J=16, eps=0.25, q=8, ppw=10.0,
 
 
 def train(ctx, out, n=128, media=42, pairs=48, steps=4000, crop=64, lr=1e-3, lr_min=1e-5, seed=0, J=16, eps=0.25,
-          target="remainder", loss_kind=2):
+          target="remainder", loss_kind=2, q=8):
     from . import hfci
     t0 = time.perf_counter()
-    x, kch, mop = harvest_pairs(ctx, n=n, media=media, pairs=pairs, J=J, eps=eps, target=target)
+    x, kch, mop = harvest_pairs(ctx, n=n, media=media, pairs=pairs, J=J, eps=eps, q=q, target=target)
     t1 = time.perf_counter()
     net = hfci.Net(ctx, seed=seed)
     # the residual loss reads only the input (e is not used); the other losses need the
