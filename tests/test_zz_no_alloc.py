@@ -46,10 +46,12 @@ def setup(ctx, shape, seed, q, J=4):
     return o, g, cg, poles, rng
 
 
-def test_noalloc_equals_shifted_solve_twice(ctx):
-    # call 1: complex64, two factors per pass, adaptive stopping, 4 poles x 3 sources
-    o, g, cg, poles, rng = setup(ctx, (20, 24, 30), 81, 8)
-    g.set_tune(32, 1, 8, 2, 0, 1)
+@pytest.mark.parametrize("tune,q", [((1, 8, 2, 0, 1), 8), ((3, 8, 2, 0, 2, 1), 10)])
+def test_noalloc_equals_shifted_solve_twice(ctx, tune, q):
+    # call 1: complex64, two factors per pass (and, with kern 3 and fuse 2, the middle
+    # factors three per pass), adaptive stopping, 4 poles x 3 sources
+    o, g, cg, poles, rng = setup(ctx, (20, 24, 30), 81, q)
+    g.set_tune(32, *tune)
     f = rng.standard_normal((3, 20, 24, 30)) + 1j * rng.standard_normal((3, 20, 24, 30))
     f[1] *= 1e-3
     fd = dev(f).to(torch.complex64)
