@@ -275,6 +275,14 @@ def uneven_arm(args, ctx, verbose):
         ops.append(g)
         cons.append(hfci.Contour(g, wl.n_poles, 1.0, args.eps, args.q))
         fs.append(torch.from_numpy(wl.rhs[0]).cuda())
+    # a batch shares one degree: where the rule chose (eps, q) per instance, the instances
+    # whose q differs from the most common one get eps chosen again for that q
+    qs = [c.q for c in cons]
+    q_batch = max(set(qs), key=qs.count)
+    for k, (g, wl) in enumerate(zip(ops, wls)):
+        if cons[k].q != q_batch:
+            cons[k].close()
+            cons[k] = hfci.Contour(g, wl.n_poles, 1.0, args.eps, q_batch)
     # untimed: every instance gets its autotuned complex64 shape, which the one-at-a-time
     # solves use (the batch launches have their own fixed shape)
     for g in ops:
@@ -312,10 +320,12 @@ def uneven_arm(args, ctx, verbose):
     for wl in wls:
         sizes[str(wl.c.shape[0])] = sizes.get(str(wl.c.shape[0]), 0) + 1
     points = sum(int(wl.c.size) for wl in wls)
+    eps_used = [round(c.params()["eps"], 4) for c in cons]
     for g, c in zip(ops, cons):
         c.close()
         g.close()
     return {"instances": len(wls), "grid_sizes": sizes, "points": points, "time_batch_s": round(t_batch, 4),
+            "q": q_batch, "q_chosen_per_instance": qs, "eps_min": min(eps_used), "eps_max": max(eps_used),
             "time_sequential_s": round(t_seq, 4), "speedup_batch_vs_sequential": round(t_seq / t_batch, 3),
             "its_min": min(s["its"] for s in sts), "its_max": max(s["its"] for s in sts),
             "stencil_products": int(sts[0]["matvecs"] + sum(s["matvecs"] for s in sts[1:])),

@@ -320,11 +320,13 @@ hfci_status hfci_contour_params(const hfci_contour* c, int* J, double* t, double
  * and *eps_out is the eps, among 31 geometric steps over [0.01, 0.64], minimising the
  * predicted solve time
  *     T(eps) = eps * (Q S + Q M * 2e6 / npoints + 100),  Q = per_pass * ceil(q / per_pass),
- *     S = sum_j s_j, M = max_j s_j, s_j = ceil(ln(fp_reduce) / -ln nu_j(eps)),
+ *     S = sum_j c_j, M = max_j c_j, c_j = ceil(ln(fp_reduce) / 2 / -ln nu_j(eps)),
  * where nu_j is eq. fix-pt-conv's rate for pole j of eq. quad-points (J, t, eps) at the
- * degree q, so s_j is the fixed-point steps pole j needs and Q s_j its products, a pass of
- * per_pass factors counting per_pass (per_pass = 2 for the finite-difference operators'
- * two-factor kernels, 1 for the spectral operator).  With q = 0 the degree at each eps is
+ * degree q: ceil(ln(fp_reduce) / -ln nu_j) steps reduce pole j's residual by fp_reduce in
+ * the worst case, the adaptive stops measured about half of that, so c_j is the steps the
+ * rule charges and Q c_j their products, a pass of per_pass factors counting per_pass
+ * (per_pass = 2 for the finite-difference operators' multi-factor kernels, 1 for the
+ * spectral operator).  With q = 0 the degree at each eps is
  * the one hfci_contour_create would choose for the pole nearest the origin (1..16, in
  * passes) and *q_out receives the chosen one; else *q_out = q.  The FGMRES iteration count
  * grows about in proportion to eps (measured on the finite-difference operators for J

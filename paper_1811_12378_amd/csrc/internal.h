@@ -258,6 +258,9 @@ constexpr int kRuleN = 31, kRuleJ = 6, kRulePerSide = 200, kRuleScan = 80;
 // fp_reduce); kRuleLaunch, kRuleIter: the cost model's launch latency (in grid points of one
 // system's pass) and per-iteration work (in products), fitted to solve times on MI355X
 constexpr double kRuleLo = 0.01, kRuleHi = 0.64, kRuleReduce = 5.0, kRuleLaunch = 2.0e6, kRuleIter = 100.0;
+// the share of the worst-case step count (in the logarithm of the reduction) the rule
+// charges each pole: the adaptive stops measured 0.45-0.6 of it for eps >= 0.08
+constexpr double kRuleStepFrac = 0.5;
 // per_pass: factors per pass over HBM; q = 0: the degree is chosen too (written to *q_out)
 double rule_eps(double b1, double b2, double rho2, double npoints, int J, double t, int q, int per_pass,
                 double reduce, int* q_out);

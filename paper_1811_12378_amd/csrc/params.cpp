@@ -188,11 +188,13 @@ static double rule_nu(cd z, double b1, double b2, double rho2, int q, const std:
 // Contour parameters by rule.  Sec. 7.3 sets eps per frequency with a small fixed J; here
 // eps is the value, among kRuleN geometric steps over [kRuleLo, kRuleHi], that minimises a
 // predicted solve time
-//   T(eps) = eps * (Q sum_j s_j + Q max_j s_j * kRuleLaunch / npoints + kRuleIter),
-//   s_j = ceil(ln(reduce) / -ln nu_j),  Q = per_pass * ceil(q / per_pass),
-// nu_j being eq. fix-pt-conv's rate for pole j of eq. quad-points at that eps, so s_j is
-// the fixed-point steps pole j needs and Q s_j their products (a pass of per_pass factors
-// costs per_pass products).  The FGMRES iteration count grows about in proportion to eps;
+//   T(eps) = eps * (Q sum_j c_j + Q max_j c_j * kRuleLaunch / npoints + kRuleIter),
+//   c_j = ceil(kRuleStepFrac ln(reduce) / -ln nu_j),  Q = per_pass * ceil(q / per_pass),
+// nu_j being eq. fix-pt-conv's rate for pole j of eq. quad-points at that eps:
+// ceil(ln(reduce) / -ln nu_j) steps reduce the residual by `reduce` in the worst case, and
+// the adaptive stops take about half of it (kRuleStepFrac), so c_j are the fixed-point
+// steps charged to pole j and Q c_j their products (a pass of per_pass factors costs
+// per_pass products).  The FGMRES iteration count grows about in proportion to eps;
 // per iteration the products of all poles cost their bytes, each launch (as many as the
 // slowest pole's products) a latency worth kRuleLaunch grid points of one system's pass,
 // and the Arnoldi step with the combine about kRuleIter products.  With q = 0 the degree at
@@ -230,7 +232,7 @@ double rule_eps(double b1, double b2, double rho2, double npoints, int J, double
     double sum = 0.0, mx = 0.0;
     for (int j = 0; j < (J + 1) / 2 && std::isfinite(sum); ++j) {
       const double nu = rule_nu(z[j], b1, b2, rho2, qk, bd);
-      const double sj = nu < 1.0 ? std::ceil(std::log(reduce) / -std::log(nu)) : HUGE_VAL;
+      const double sj = nu < 1.0 ? std::ceil(kRuleStepFrac * std::log(reduce) / -std::log(nu)) : HUGE_VAL;
       sum += (2 * j + 1 == J) ? sj : 2.0 * sj;
       mx = std::max(mx, sj);
     }

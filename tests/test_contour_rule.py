@@ -1,9 +1,11 @@
 """The contour-parameter rule: its oracle pinned to Thm 4.2 on normal operators, and the
 library's host implementation against the oracle (CPU only: the rule does no GPU work).
 
-The rule charges pole j of a contour s_j = ceil(ln(reduce) / -ln nu_j) fixed-point steps,
-nu_j being eq. fix-pt-conv's rate; by Thm 4.2 the error (and, for a normal operator, the
+Pole j of a contour needs at most s_j = ceil(ln(reduce) / -ln nu_j) fixed-point steps,
+nu_j being eq. fix-pt-conv's rate: by Thm 4.2 the error (and, for a normal operator, the
 residual) is multiplied by p~(A)/p~(z) each step, bounded by nu_j on the spectrum box.
+The rule charges c_j = ceil(ln(reduce) / 2 / -ln nu_j) of them (the adaptive stops'
+measured average is about half the worst case).
 """
 import math
 import os
@@ -66,16 +68,30 @@ def test_charges_never_grow_with_eps():
             prev = cur
 
 
+def charged(st, reduce=5.0):
+    # half the worst case in the logarithm, written out from the rates
+    return [math.ceil(0.5 * math.log(reduce) / -math.log(p[1])) for p in st]
+
+
+def test_charged_steps_are_half_the_worst_case():
+    st = R.pole_steps(B1, 19.4, RHO2, 6, 1.0, 0.1, 8)
+    c = R.charged_steps(st)
+    assert c == charged(st)
+    for cj, p in zip(c, st):
+        # ceil(x / 2) <= ceil(x) <= 2 ceil(x / 2): half the worst case, rounded up
+        assert cj <= p[0] <= 2 * cj
+
+
 def test_rule_reduces_to_product_count_without_overheads():
     J, eps, q, table = R.rule_parameters(B1, 19.4, RHO2, 1e30, J=6, q=8, it=0.0)
     k = int(np.argmin([t for _, t, _ in table]))
-    s = [p[0] for p in R.pole_steps(B1, 19.4, RHO2, 6, 1.0, eps, 8)]
+    c = charged(R.pole_steps(B1, 19.4, RHO2, 6, 1.0, eps, 8))
     assert J == 6 and q == 8 and eps == table[k][0]
-    assert abs(table[k][1] - eps * 8 * sum(s)) < 1e-9 * table[k][1]
+    assert abs(table[k][1] - eps * 8 * sum(c)) < 1e-9 * table[k][1]
     # an odd degree costs a whole pass for its lone factor: Q rounds up to even
     J, eps7, q7, table7 = R.rule_parameters(B1, 19.4, RHO2, 1e30, J=6, q=7, it=0.0)
-    s7 = [p[0] for p in R.pole_steps(B1, 19.4, RHO2, 6, 1.0, eps7, 7)]
-    assert abs(dict((e, t) for e, t, _ in table7)[eps7] - eps7 * 8 * sum(s7)) < 1e-9 * eps7 * 8 * sum(s7)
+    c7 = charged(R.pole_steps(B1, 19.4, RHO2, 6, 1.0, eps7, 7))
+    assert abs(dict((e, t) for e, t, _ in table7)[eps7] - eps7 * 8 * sum(c7)) < 1e-9 * eps7 * 8 * sum(c7)
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libhfci.so not built")
