@@ -218,7 +218,7 @@ hfci_status hfci_op_info(const hfci_op* op, double* out7);
  *                 2 (kern 3 only) = as 1, with the middle factors of a step (those
  *                 between its first and last pair: q - 4 of them, or of step one's
  *                 run of pairs) three per pass where they split into threes and at
- *                 most two pairs (a run of 4 stays 2 + 2);
+ *                 most two pairs (a run of 4 stays 2 + 2), on z-chunks of 2 cz;
  *   tune[5] sg:   1..16; with fuse >= 1 on grids whose pair tiles split into 8 XCD
  *                 slabs, the systems of a launch are taken sg at a time, tile by tile,
  *                 so kappa of a tile is read once per sg systems (1 = one system's

@@ -148,9 +148,10 @@ struct Launch {
   // not alias the input
   static bool factor_pair(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a,
                           int kind);
-  // middle factors a.k, a.k + 1 and a.k + 2 in one pass (no kind bits); false (nothing
-  // launched) unless the complex64 launch shape is kern 3 with fuse 2 and the grid suits
-  // the pair kernels (an even nx, vectors under 2 GiB); the output must not alias the input
+  // middle factors a.k, a.k + 1 and a.k + 2 in one pass (no kind bits), on z-chunks of
+  // 2 cz planes; false (nothing launched) unless the complex64 launch shape is kern 3 with
+  // fuse 2 and the grid suits the pair kernels (an even nx, vectors under 2 GiB); the
+  // output must not alias the input
   static bool factor_triple(hipStream_t st, const GridDesc& g, const void* kappa, const FactorArgs<T2>& a);
   // whether factor_triple launches on this grid with its current launch shape
   static bool triple_runs(const GridDesc& g);

@@ -2145,7 +2145,10 @@ bool Launch<T2>::factor_triple(hipStream_t st, const GridDesc& g, const void* ka
     const KernelTune& t = g.tune32;
     if (!triple_runs(g)) return false;
     if (a.count <= 0) return true;
-    const PairShape q = trip_shape<kTripQH>(g, t.cz);
+    // z-chunks of twice the shape's cz: at 256^3 with 16 systems' worth of launches, 128
+    // planes ran the three-factor pass 6 % faster than 64, while the pairs, which share
+    // cz, ran 5-7 % slower with 128
+    const PairShape q = trip_shape<kTripQH>(g, t.cz > 0 ? 2 * t.cz : 0);
     hipLaunchKernelGGL(ztrip_kernel, dim3((unsigned)q.per_sys * (unsigned)a.count), dim3(Trip<kTripQH>::NT), 0, st,
                        g, q.nzc, q.czlen, q.xcd_slab, t.sg, a, (const float*)kappa);
     return true;
