@@ -27,7 +27,8 @@ scaled residual a preconditioner's output leaves (Ahat = A / (s/h^2) without the
 damping term, built from the input's third channel).  Optimiser: Adam.
 
 Pins (tests/test_oracle_conv.py): the convolution against a brute-force loop
-over every index; every gradient against central finite differences.
+over every index; the whole forward against the same network built from torch's
+CPU primitives; every gradient against central finite differences.
 """
 from __future__ import annotations
 

@@ -158,3 +158,43 @@ def test_residual_loss_pins():
         ep[idx] = h
         fd = (C.loss_residual(out + ep, v, kch)[0] - C.loss_residual(out - ep, v, kch)[0]) / (2 * h)
         assert abs(fd - g[idx]) < 1e-7
+
+
+def test_unet_forward_against_library_primitives():
+    # the network of the module docstring built from torch's CPU primitives (channels-first
+    # cross-correlation conv3d with zero padding, 2x2x2 average pooling, nearest x2
+    # up-sampling, channel concatenation), with the oracle's parameters: pins the skip
+    # order, the pooling and the up-sampling against an implementation that shares nothing
+    # with the oracle's loops
+    torch = pytest.importorskip("torch")
+    import torch.nn.functional as F
+    p = C.init_params(seed=3)
+    rng = np.random.default_rng(11)
+    for name, _, cout in C.LAYERS:
+        p[name + ".b"] = 0.1 * rng.standard_normal(cout)
+    p["out.b"] = 0.1 * rng.standard_normal(2)
+    x = rng.standard_normal((8, 8, 8, 3))
+    out, _ = C.forward(p, x)
+
+    def conv(h, name):
+        w = p[name + ".w"]  # [27, cout, cin], tap t = (dz+1)*9 + (dy+1)*3 + (dx+1)
+        k = torch.from_numpy(w.reshape(3, 3, 3, w.shape[1], w.shape[2])).permute(3, 4, 0, 1, 2).contiguous()
+        return F.relu(F.conv3d(h, k, torch.from_numpy(p[name + ".b"]), padding=1))
+
+    def block(h, a, b):
+        return conv(conv(h, a), b)
+
+    xt = torch.from_numpy(x).permute(3, 0, 1, 2).unsqueeze(0)  # [1, C, Z, Y, X]
+    e1 = block(xt, "c1a", "c1b")
+    e2 = block(F.avg_pool3d(e1, 2), "c2a", "c2b")
+    b3 = block(F.avg_pool3d(e2, 2), "c3a", "c3b")
+    d2 = block(torch.cat([F.interpolate(b3, scale_factor=2, mode="nearest"), e2], dim=1), "d2a", "d2b")
+    d1 = block(torch.cat([F.interpolate(d2, scale_factor=2, mode="nearest"), e1], dim=1), "d1a", "d1b")
+    head = torch.from_numpy(p["out.w"]).reshape(2, 16, 1, 1, 1)
+    ref = F.conv3d(d1, head, torch.from_numpy(p["out.b"]))[0].permute(1, 2, 3, 0).numpy()
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # a swapped skip order is caught: the pin is sensitive to it
+    d2s = block(torch.cat([e2, F.interpolate(b3, scale_factor=2, mode="nearest")], dim=1), "d2a", "d2b")
+    d1s = block(torch.cat([F.interpolate(d2s, scale_factor=2, mode="nearest"), e1], dim=1), "d1a", "d1b")
+    alt = F.conv3d(d1s, head, torch.from_numpy(p["out.b"]))[0].permute(1, 2, 3, 0).numpy()
+    assert np.max(np.abs(out - alt)) > 1e-3 * np.max(np.abs(ref))
