@@ -332,7 +332,8 @@ def test_streams_into_lds_adaptive(ctx, kern, fuse, q):
 
 
 def test_streams_into_lds_need_an_even_nx(ctx):
-    # an odd nx (pairs of x-neighbours would straddle rows) falls back to kern 1's kernel
+    # an odd nx (pairs of x-neighbours would straddle rows) falls back to kern 1's kernel,
+    # for the three-factor shape too (its plan keeps pairs)
     shape = (20, 26, 67)
     rng = np.random.default_rng(77)
     c = rng.uniform(1.0, 3.0, size=shape)
@@ -343,10 +344,11 @@ def test_streams_into_lds_need_an_even_nx(ctx):
                     delta=[p.delta for p in poles])
     f = dev(round32(rng.standard_normal((1,) + shape) + 1j * rng.standard_normal((1,) + shape))).to(torch.complex64)
     res = []
-    for kern in (1, 2):
-        g.set_tune(32, kern, 8, 2, 0, 1)
+    for kern, fuse in ((1, 1), (2, 1), (3, 2)):
+        # kern 2 and kern 3 with three factors per pass both run kern 1's pairs here
+        g.set_tune(32, kern, 8, 2, 0, fuse)
         res.append(host(hf.shifted_solve(g, cg, f, steps=2)[0]))
-    assert np.array_equal(res[0], res[1])
+    assert np.array_equal(res[0], res[1]) and np.array_equal(res[0], res[2])
     with pytest.raises(hf.HfciError):  # a complex64 kernel only
         g.set_tune(64, 2, 8, 2, 0, 1)
 
