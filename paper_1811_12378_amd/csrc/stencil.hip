@@ -1342,6 +1342,7 @@ struct TTile {
   int nz, zb, ze, wave;
   int c0[2], f[2], f2c[2], f3c[2];  // input centre, own entry, clamped second / third factor entries
   bool live[2], mid[2];             // point in the grid; inside the second factor's tile
+  bool skip2[2], skip3[2];          // wave-uniform: no thread of the wave needs the factor
   TFac f1, f2, f3;
   float dsc, dampxy[2];
   int damp_cells;
@@ -1426,9 +1427,12 @@ __device__ __forceinline__ void tstep(const TTile& d, int k, unsigned char* __re
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int e = d.f2c[h];
-    const T2 v = tfactor(d.f2, ka1[h], da1[h], t0[h], tm[h], tv[h], r1[e - 1], r1[e + 1], r1[e - G::EX],
-                         r1[e + G::EX]);
-    uv[h] = (d.live[h] && d.mid[h] && z1) ? v : T2{(T)0, (T)0};
+    uv[h] = T2{(T)0, (T)0};
+    if (!d.skip2[h]) {  // uniform
+      const T2 v = tfactor(d.f2, ka1[h], da1[h], t0[h], tm[h], tv[h], r1[e - 1], r1[e + 1], r1[e - G::EX],
+                           r1[e + G::EX]);
+      uv[h] = (d.live[h] && d.mid[h] && z1) ? v : T2{(T)0, (T)0};
+    }
     w2[d.f[h]] = uv[h];
     tm[h] = t0[h];
     t0[h] = tv[h];
@@ -1439,9 +1443,12 @@ __device__ __forceinline__ void tstep(const TTile& d, int k, unsigned char* __re
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int e = d.f3c[h];
-    const T2 o = tfactor(d.f3, ka2[h], da2[h], u0[h], um[h], uv[h], r2[e - 1], r2[e + 1], r2[e - G::EX],
-                         r2[e + G::EX]);
-    buf_store<T2>(d.rO, zok ? d.ost[h] : kOOB, po, o);
+    T2 o = T2{(T)0, (T)0};
+    if (!d.skip3[h])  // uniform
+      o = tfactor(d.f3, ka2[h], da2[h], u0[h], um[h], uv[h], r2[e - 1], r2[e + 1], r2[e - G::EX], r2[e + G::EX]);
+    // the store is issued by every wave (out of range where skipped or outside the core):
+    // the plane's wait counts V memory instructions per wave
+    buf_store<T2>(d.rO, (zok && !d.skip3[h]) ? d.ost[h] : kOOB, po, o);
     um[h] = u0[h];
     u0[h] = uv[h];
     ka2[h] = ka1[h];
@@ -1525,6 +1532,17 @@ __device__ __forceinline__ void trip_tile(const GridDesc& g, int czlen, int gx, 
   const bool used = tid < G::USED;
   const int ex = used ? tid % G::EX : (tid - G::USED) % G::EX;
   const int eyb = used ? tid / G::EX : QH - 1;
+  // rows of the wave's threads (non-decreasing in the thread index; idle threads take row
+  // QH - 1): a band whose rows all lie outside a factor's tile skips that factor
+  {
+    const int t0w = 64 * d.wave, t1w = t0w + 63;
+    const int rlo = t0w < G::USED ? t0w / G::EX : QH - 1, rhi = t1w < G::USED ? t1w / G::EX : QH - 1;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      d.skip2[h] = rlo + h * QH > G::Y + 2 || rhi + h * QH < 1;
+      d.skip3[h] = rlo + h * QH > G::Y + 1 || rhi + h * QH < 2;
+    }
+  }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int ey = eyb + h * QH;
