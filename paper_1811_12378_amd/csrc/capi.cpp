@@ -637,6 +637,10 @@ hfci_status hfci_contour_create(const hfci_op* op, int J, double t, double eps, 
       const cd zj = c->z[j];
       if (zj.imag() <= 0.0 && zj.imag() >= -op->rho2)
         throw Error(HFCI_E_CONTOUR, "pole inside the imaginary band [-rho2, 0] of the spectrum");
+    }
+    // each pole's delta search is independent: run them on host threads
+    host_parallel_for(J, [&](int j) {
+      const cd zj = c->z[j];
       if (delta) {
         c->delta[j] = delta[j];
         c->z0[j] = cd(0.5 * (op->b1 + op->b2), zj.imag());
@@ -644,6 +648,9 @@ hfci_status hfci_contour_create(const hfci_op* op, int J, double t, double eps, 
       } else {
         optimise_delta(zj, op->b1, op->b2, op->rho2, q, c->delta[j], c->nu[j], c->z0[j]);
       }
+    });
+    for (int j = 0; j < J; ++j) {
+      const cd zj = c->z[j];
       if (!(c->nu[j] < 1.0)) throw Error(HFCI_E_CONTOUR, "no contraction for a pole (nu >= 1)");
       FactorCoef* cj = &c->coef[(size_t)j * c->cstride];
       factor_coefficients(zj, c->z0[j], c->delta[j], q, cj, cj + q, c->pz[j]);

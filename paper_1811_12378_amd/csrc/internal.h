@@ -5,6 +5,7 @@
 
 #include <complex>
 #include <cstdio>
+#include <functional>
 #include <map>
 #include <stdexcept>
 #include <string>
@@ -261,6 +262,8 @@ constexpr double kRuleLo = 0.01, kRuleHi = 0.64, kRuleReduce = 5.0, kRuleLaunch 
 // the share of the worst-case step count (in the logarithm of the reduction) the rule
 // charges each pole: the adaptive stops measured 0.45-0.6 of it for eps >= 0.08
 constexpr double kRuleStepFrac = 0.5;
+// f(0), ..., f(n - 1) on host threads (independent calls; the first exception is rethrown)
+void host_parallel_for(int n, const std::function<void(int)>& f);
 // per_pass: factors per pass over HBM; q = 0: the degree is chosen too (written to *q_out)
 double rule_eps(double b1, double b2, double rho2, double npoints, int J, double t, int q, int per_pass,
                 double reduce, int* q_out);

@@ -2,7 +2,10 @@
 // the delta search of the exponential-Taylor iteration, and the linear-factor
 // coefficients of its product form that the stage kernels consume.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <exception>
+#include <thread>
 
 #include "internal.h"
 
@@ -114,20 +117,54 @@ void optimise_delta(cd z, double b1, double b2, double rho2, int q, double& delt
 // kernels), the cost is ceil(q / per_pass) ln F / (-ln nu) passes, and that is minimised;
 // per_pass = 1 is the rule as written.  q in 1..qmax, ties to the smaller q.
 int choose_q(cd z, double b1, double b2, double rho2, int qmax, int per_pass) {
+  std::vector<double> nu(std::max(qmax, 0) + 1, HUGE_VAL);
+  host_parallel_for(qmax, [&](int i) {
+    double delta;
+    cd z0;
+    optimise_delta(z, b1, b2, rho2, i + 1, delta, nu[i + 1], z0);
+  });
   int best = 1;
   double cost_best = HUGE_VAL;
-  for (int q = 1; q <= qmax; ++q) {
-    double delta, nu;
-    cd z0;
-    optimise_delta(z, b1, b2, rho2, q, delta, nu, z0);
-    if (!(nu < 1.0)) continue;
-    const double cost = (double)((q + per_pass - 1) / per_pass) / -std::log(nu);
+  for (int q = 1; q <= qmax; ++q) {  // in order: ties go to the smaller q
+    if (!(nu[q] < 1.0)) continue;
+    const double cost = (double)((q + per_pass - 1) / per_pass) / -std::log(nu[q]);
     if (cost < cost_best) {
       best = q;
       cost_best = cost;
     }
   }
   return best;
+}
+
+// f(0), ..., f(n - 1) on up to hardware_concurrency host threads (each index once; the
+// calls must be independent); the first exception a call throws is rethrown here
+void host_parallel_for(int n, const std::function<void(int)>& f) {
+  if (n <= 0) return;
+  const int nt = std::max(1, std::min(n, (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
+  if (nt == 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::exception_ptr err;
+  std::atomic<bool> failed{false};
+  auto work = [&] {
+    for (int i; (i = next.fetch_add(1)) < n;) {
+      if (failed.load()) return;
+      try {
+        f(i);
+      } catch (...) {
+        if (!failed.exchange(true)) err = std::current_exception();
+        return;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  th.reserve(nt - 1);
+  for (int k = 1; k < nt; ++k) th.emplace_back(work);
+  work();
+  for (auto& t : th) t.join();
+  if (err) std::rethrow_exception(err);
 }
 
 // max over the boundary of |p~(lambda)| / |p~(z)| with the complex products written out
@@ -203,11 +240,13 @@ static double rule_nu(cd z, double b1, double b2, double rho2, int q, const std:
 double rule_eps(double b1, double b2, double rho2, double npoints, int J, double t, int q, int per_pass,
                 double reduce, int* q_out) {
   const std::vector<cd> bd = rectangle_boundary(b1, b2, rho2, kRulePerSide);
-  double best_eps = kRuleLo, best_t = HUGE_VAL;
-  int best_q = q > 0 ? q : 1;
-  std::vector<cd> z, sigma;
-  for (int k = 0; k < kRuleN; ++k) {
+  // the candidates are independent: evaluate them on host threads, then take the best in
+  // order (ties to the smaller eps)
+  std::vector<double> tks(kRuleN, HUGE_VAL);
+  std::vector<int> qks(kRuleN, 0);
+  host_parallel_for(kRuleN, [&](int k) {
     const double eps = kRuleLo * std::pow(kRuleHi / kRuleLo, (double)k / (kRuleN - 1));
+    std::vector<cd> z, sigma;
     contour_poles(J, t, eps, rho2, z, sigma);
     int qk = q;
     if (qk <= 0) {
@@ -224,7 +263,7 @@ double rule_eps(double b1, double b2, double rho2, double npoints, int J, double
           qk = qq;
         }
       }
-      if (qk <= 0) continue;  // no degree contracts at this eps
+      if (qk <= 0) return;  // no degree contracts at this eps
     }
     // poles j and J-1-j are mirror images about Im = -rho2/2, as is the box, so they have
     // the same rate: evaluate the first half and count each twice (the middle pole of an
@@ -237,13 +276,17 @@ double rule_eps(double b1, double b2, double rho2, double npoints, int J, double
       mx = std::max(mx, sj);
     }
     const double Q = (double)(per_pass * ((qk + per_pass - 1) / per_pass));
-    const double tk = eps * (Q * sum + Q * mx * kRuleLaunch / npoints + kRuleIter);
-    if (tk < best_t) {
-      best_t = tk;
-      best_eps = eps;
-      best_q = qk;
+    tks[k] = eps * (Q * sum + Q * mx * kRuleLaunch / npoints + kRuleIter);
+    qks[k] = qk;
+  });
+  double best_eps = kRuleLo, best_t = HUGE_VAL;
+  int best_q = q > 0 ? q : 1;
+  for (int k = 0; k < kRuleN; ++k)
+    if (tks[k] < best_t) {
+      best_t = tks[k];
+      best_eps = kRuleLo * std::pow(kRuleHi / kRuleLo, (double)k / (kRuleN - 1));
+      best_q = qks[k];
     }
-  }
   if (q_out) *q_out = best_q;
   return best_eps;
 }
