@@ -122,3 +122,14 @@ def test_library_rule_rejects_bad_boxes():
         hfci.contour_rule(-1.0, 5.0, 1.0, 8.0, fp_reduce=1.0)
     with pytest.raises(hfci.HfciError):
         hfci.contour_rule(-1.0, 5.0, 1.0, 8.0, per_pass=3)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhfci.so not built")
+def test_library_rule_is_deterministic():
+    # the candidates, the degree search and the pole rates run on host threads and are
+    # reduced in order: repeated calls agree exactly
+    from paper_1811_12378_amd import hfci
+    for b2, npoints, q in ((19.4, 256.0 ** 3, 0), (10.9, 64.0 ** 3, 0), (43.7, 96.0 ** 3, 8)):
+        first = hfci.contour_rule(B1, b2, RHO2, npoints, q=q)
+        for _ in range(4):
+            assert hfci.contour_rule(B1, b2, RHO2, npoints, q=q) == first
