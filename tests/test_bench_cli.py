@@ -54,3 +54,27 @@ def test_profiles_of_several_timed_solves_add_up():
     q = {"fp_stage": {"launches": 3, "total_ms": 2.0, "alg_bytes": 5.0}}
     assert b.add_prof(None, p) == p
     assert b.add_prof(p, q) == {"fp_stage": {"launches": 5, "total_ms": 3.5, "alg_bytes": 15.0}}
+
+
+def test_traffic_ratio_only_for_its_shape_kernel_and_source(tmp_path, monkeypatch):
+    # the counter ratio of a committed summary is used only for the launch shape, the kernel
+    # and the stencil source it was taken on
+    import json
+    b = _bench_module()
+    shape = [3, 8, 2, 64, 2, 4]
+    assert b.traffic_kernel(shape, triple=True) == "ztrip_kernel"
+    assert b.traffic_kernel(shape, triple=False) == "zpair_tall_kernel<0>"
+    assert b.traffic_kernel([2, 8, 3, 64, 1, 4]) == "zpair_dma_kernel<0, 4>"
+    assert "three middle factors" in b.middle_kernel_name(shape, triple=True)
+    monkeypatch.setattr(b, "PROFILES", str(tmp_path))
+    rec = {"kernel": "ztrip_kernel", "source_hash": b.source_hash(), "shape": shape,
+           "bytes_per_launch": 3.0e9, "alg_bytes_per_launch": 2.5e9}
+    with open(b.traffic_file(shape), "w") as fh:
+        json.dump(rec, fh)
+    assert abs(b.measured_traffic(shape, "ztrip_kernel") - 1.2) < 1e-12
+    assert b.measured_traffic(shape, "zpair_tall_kernel<0>") is None
+    assert b.measured_traffic([3, 8, 2, 64, 2, 1], "ztrip_kernel") is None
+    rec["source_hash"] = "0" * 16
+    with open(b.traffic_file(shape), "w") as fh:
+        json.dump(rec, fh)
+    assert b.measured_traffic(shape, "ztrip_kernel") is None
