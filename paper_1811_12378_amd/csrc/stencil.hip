@@ -1305,10 +1305,13 @@ __global__ __launch_bounds__(Tall<kTallQH>::NT) __attribute__((amdgpu_waves_per_
 // point's kappa and damping for them are the first factor's, kept in registers.  Each
 // factor a (A - z0) x + b x is evaluated as m x - (a sh2) nb, nb the sum of the six
 // neighbours and m = a (diag0 - kappa - i (damp + Im z0)) + b = m0 - a kappa - i a damp
-// with m0 fixed per block, which saves the diagonal's own arithmetic.  QH = 11: 64 x 18 outputs, 768 threads (three waves
-// per SIMD, so 128 VGPRs hold the six planes of state per point without spills; with
-// QH = 13 and 896 threads the reloads of two spilled registers waited for every load in
-// flight), 126 KB of LDS (one block per CU).
+// with m0 fixed per block, which saves the diagonal's own arithmetic.  A wave whose rows
+// all lie outside the second or third factor's tile skips that factor's arithmetic (its
+// store still issues, out of range, so every wave keeps the plane's count of memory
+// instructions that the wait relies on).  QH = 11: 64 x 18 outputs, 768 threads (three
+// waves per SIMD, so up to 168 VGPRs hold the planes of state per point without spills;
+// with 896 or 960 threads the budget is 128 and the reloads of spilled registers waited
+// for every load in flight), 126 KB of LDS (one block per CU).
 template <int QH>
 struct Trip {
   static constexpr int X = 64, Y = 2 * QH - 4;       // output tile
